@@ -1,0 +1,176 @@
+/*
+ * xbar.h - C ABI of the MI355X (gfx950) crossbar nodal solver.
+ *
+ * Problem (Kolinko et al., "XbarSim", Sec. II): an m x n memristive
+ * crossbar with a linear device of conductance G[i][j] at every crosspoint,
+ * a wire resistor between adjacent devices on every word line (WL, row i)
+ * and bit line (BL, column j), a voltage source V_i driving each word line
+ * and an output current through the termination of each bit line.  Nodal
+ * analysis gives 2mn unknown node voltages and a symmetric system G v = I
+ * (Sec. II.A, Eqs. 1-7), which the paper solves by LU decomposition once
+ * per conductance map followed by forward and back substitution for every
+ * input vector of a batch (Sec. II.C, Sec. III.A and III.D).
+ *
+ * This library orders the unknowns by crossbar row, so the system has m
+ * diagonal blocks of 2n unknowns; it eliminates each row's word-line nodes
+ * in closed form and runs a block LU (block-Thomas) over the rows on the
+ * GPU.  The result is the same solution vector; see each call for what it
+ * computes.
+ *
+ * Conventions
+ *  - All pointers named "device" are device (HBM) pointers on the device
+ *    that was current when the plan was created; the caller owns them.
+ *  - All public floating-point data is float64, whatever the precision mode.
+ *  - Node voltages use the paper's interleaved order (Sec. II.B):
+ *      k = 2*(i*n + j) + s, s = 0 for WL(i,j), s = 1 for BL(i,j), 0-based.
+ *  - Calls are asynchronous on the plan's HIP stream unless stated.
+ *  - Errors found on the host are returned at once and touch no device
+ *    state.  Errors found by kernels (bad conductance values, a pivot that
+ *    is not positive, refinement that does not converge) set sticky device
+ *    flags that xbar_get_info() reads (it synchronises the stream).
+ *  - One host thread per plan.  Separate plans may share a device.
+ */
+#ifndef XBAR_H
+#define XBAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xbar_plan_s* xbar_plan;          /* opaque, owned by the library */
+
+typedef enum {
+    XBAR_OK = 0,
+    XBAR_ERR_ARG = 1,            /* invalid argument (host check)                      */
+    XBAR_ERR_ALLOC = 2,          /* device memory allocation failed                    */
+    XBAR_ERR_STATE = 3,          /* call out of order (see xbar_factor / solve_batch) */
+    XBAR_ERR_NOT_SPD = 4,        /* a block pivot was not positive and finite          */
+    XBAR_ERR_NO_CONVERGENCE = 5, /* iterative refinement missed its tolerance          */
+    XBAR_ERR_DEVICE = 6,         /* no usable device, or a HIP runtime error           */
+    XBAR_ERR_INPUT = 7           /* conductances not finite and positive (device check)*/
+} xbar_status;
+
+typedef enum {
+    XBAR_FP64 = 0,      /* factor and substitution in float64 (the paper's method)         */
+    XBAR_FP32_IR = 1,   /* factor and substitution in float32 on MFMA, refined in float64  */
+    XBAR_BF16_IR = 2    /* bfloat16 block inverses (float32 accumulate), refined in float64 */
+} xbar_precision;
+
+typedef struct {
+    int32_t m;          /* word lines (rows),   1 <= m                                  */
+    int32_t n;          /* bit lines (columns), 1 <= n <= XBAR_MAX_N                     */
+    double r_wl;        /* word-line segment resistance, ohm, finite > 0 (Sec. II.A)    */
+    double r_bl;        /* bit-line segment resistance, ohm, finite > 0                 */
+    double r_src;       /* resistance from source V_i to WL(i,0), ohm, finite > 0.
+                           Eq. 5 puts a word-line segment there: the paper's model is
+                           r_src = r_wl.                                                */
+    double r_sense;     /* termination from BL(m-1,j) to 0 V, ohm, finite > 0.  The
+                           paper's model terminates with a bit-line segment,
+                           r_sense = r_bl.                                              */
+} xbar_geometry;
+
+#define XBAR_MAX_N 512
+
+typedef struct {
+    int32_t state;              /* 0 created, 1 assembled, 2 factored, 3 solved               */
+    int32_t last_batch;         /* B of the last xbar_solve_batch                             */
+    int32_t ir_iters;           /* refinement steps taken by the slowest input slab (IR modes)*/
+    int32_t device_error;       /* sticky xbar_status found on the device, 0 if none          */
+    int64_t workspace_bytes;    /* device memory held by the plan                             */
+    int32_t block;              /* padded block size used for the row blocks                  */
+    int32_t reserved;
+} xbar_info;
+
+/*
+ * Create a plan for one crossbar geometry.  Validates the geometry and the
+ * options on the host, then allocates all device workspace for batches of
+ * up to max_batch input vectors (nothing is allocated by later calls).
+ *   p            precision mode.
+ *   max_batch    1 <= max_batch.
+ *   ir_tol       IR modes: stop when, for every input vector, the largest
+ *                correction of the bit-line voltages is <= ir_tol times
+ *                their largest magnitude; 0 selects 1e-13.  Ignored for FP64.
+ *   ir_max_iter  IR modes: refinement steps allowed, 1..100 (0 selects 10).
+ *   hip_stream   hipStream_t the plan's work is queued on (NULL = null stream).
+ * Returns XBAR_ERR_ARG, XBAR_ERR_DEVICE, XBAR_ERR_ALLOC or XBAR_OK.
+ */
+xbar_status xbar_create(const xbar_geometry* geom, xbar_precision p, int32_t max_batch,
+                        double ir_tol, int32_t ir_max_iter, void* hip_stream, xbar_plan* out);
+
+/*
+ * Assemble the nodal equations (Sec. II.A-II.B, Eqs. 1-7) for the device
+ * conductances G: device pointer, [m][n] row-major, siemens, each finite and
+ * > 0 (a value that is not sets XBAR_ERR_INPUT on the device).  The library
+ * copies what it needs; G may be reused after the call is queued and the
+ * stream has passed it.  Invalidates any previous factorization.
+ */
+xbar_status xbar_assemble(xbar_plan plan, const double* G);
+
+/*
+ * LU-decompose the assembled system once per conductance map (Sec. II.C):
+ * a block LU over the m row blocks.  Requires a prior xbar_assemble
+ * (otherwise XBAR_ERR_STATE).  A block pivot that is not positive sets
+ * XBAR_ERR_NOT_SPD on the device.
+ */
+xbar_status xbar_factor(xbar_plan plan);
+
+/*
+ * Forward and back substitution for a batch of input vectors (Sec. II.C,
+ * batch mode of Sec. III.A/III.D), reusing the factorization.
+ *   V       device, [B][m] row-major, volts (input vector b drives WL i with V[b][i]).
+ *   B       1 <= B <= max_batch.
+ *   node_v  device, [B][2mn] node voltages in the paper's order, or NULL to
+ *           skip writing them (the output currents are still produced).
+ * Requires a prior xbar_factor (XBAR_ERR_STATE otherwise).  Any number of
+ * calls may follow one factorization.  IR modes run the refinement inside
+ * this call; failing to converge sets XBAR_ERR_NO_CONVERGENCE on the device.
+ */
+xbar_status xbar_solve_batch(xbar_plan plan, const double* V, int32_t B, double* node_v);
+
+/*
+ * Output currents of the last solved batch: I[b][j] = V_BL(m-1, j) / r_sense,
+ * the current through the termination of bit line j, amperes, positive into
+ * the sense resistor (Sec. II).  I: device, [B][n] row-major.
+ * Requires a prior xbar_solve_batch (XBAR_ERR_STATE otherwise).
+ */
+xbar_status xbar_currents(xbar_plan plan, double* I);
+
+/*
+ * Synchronise the plan's stream and report its state.  Returns the sticky
+ * device error (XBAR_ERR_INPUT, XBAR_ERR_NOT_SPD, XBAR_ERR_NO_CONVERGENCE)
+ * if one was raised, XBAR_ERR_DEVICE on a HIP error, else XBAR_OK.
+ * Reading the flags does not clear them; xbar_assemble does.
+ */
+xbar_status xbar_get_info(xbar_plan plan, xbar_info* info);
+
+/*
+ * Per-kernel timing, measured with HIP events recorded on the plan's stream
+ * around each kernel launch of the calls above (only while enabled).
+ * Times are accumulated milliseconds; *_launches count the kernels timed.
+ */
+typedef struct {
+    double condense_ms;   int64_t condense_launches;   /* xbar_assemble                 */
+    double factor_ms;     int64_t factor_launches;     /* xbar_factor (all its kernels) */
+    double sweep_ms;      int64_t sweep_launches;      /* substitution sweeps           */
+    double recover_ms;    int64_t recover_launches;    /* word-line recovery + output   */
+} xbar_timing;
+
+/* Enable (1) or disable (0) per-kernel timing.  Host-only; never fails on a valid plan. */
+xbar_status xbar_set_timing(xbar_plan plan, int32_t enable);
+
+/* Synchronise, add up all timed launches so far into *out; reset != 0 clears them. */
+xbar_status xbar_get_timing(xbar_plan plan, xbar_timing* out, int32_t reset);
+
+/* Synchronise and free every device buffer of the plan.  NULL is a no-op. */
+xbar_status xbar_destroy(xbar_plan plan);
+
+/* Static, NUL-terminated name of a status code. */
+const char* xbar_status_string(xbar_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XBAR_H */

@@ -1,0 +1,154 @@
+"""ctypes binding of libxbar.so (include/xbar.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; this module
+only converts Python values and torch device tensors into the C ABI's
+plain pointers and sizes.  It raises if the library is missing: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxbar.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "xbar.h")
+
+XBAR_OK = 0
+XBAR_ERR_ARG = 1
+XBAR_ERR_ALLOC = 2
+XBAR_ERR_STATE = 3
+XBAR_ERR_NOT_SPD = 4
+XBAR_ERR_NO_CONVERGENCE = 5
+XBAR_ERR_DEVICE = 6
+XBAR_ERR_INPUT = 7
+
+XBAR_FP64 = 0
+XBAR_FP32_IR = 1
+XBAR_BF16_IR = 2
+PRECISIONS = {"fp64": XBAR_FP64, "fp32_ir": XBAR_FP32_IR, "bf16_ir": XBAR_BF16_IR}
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("r_wl", ctypes.c_double), ("r_bl", ctypes.c_double),
+                ("r_src", ctypes.c_double), ("r_sense", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("last_batch", ctypes.c_int32),
+                ("ir_iters", ctypes.c_int32), ("device_error", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64), ("block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("condense_ms", ctypes.c_double), ("condense_launches", ctypes.c_int64),
+                ("factor_ms", ctypes.c_double), ("factor_launches", ctypes.c_int64),
+                ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
+                ("recover_ms", ctypes.c_double), ("recover_launches", ctypes.c_int64)]
+
+
+class XbarError(RuntimeError):
+    def __init__(self, call: str, status: int):
+        self.status = status
+        super().__init__(f"{call} -> {status_string(status)}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libxbar.so (build it first with paper_2410_19993_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2410_19993_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.xbar_create.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.xbar_assemble.argtypes = [vp, vp]
+        L.xbar_factor.argtypes = [vp]
+        L.xbar_solve_batch.argtypes = [vp, vp, ctypes.c_int32, vp]
+        L.xbar_currents.argtypes = [vp, vp]
+        L.xbar_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.xbar_destroy.argtypes = [vp]
+        L.xbar_set_timing.argtypes = [vp, ctypes.c_int32]
+        L.xbar_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int32]
+        L.xbar_status_string.argtypes = [ctypes.c_int]
+        L.xbar_status_string.restype = ctypes.c_char_p
+        for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
+                  "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
+                  "xbar_get_timing"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of every function the public header declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(xbar_\w+)\s*\(", text, re.M)))
+
+
+def status_string(s: int) -> str:
+    return lib().xbar_status_string(int(s)).decode()
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(call, st):
+    if st != XBAR_OK:
+        raise XbarError(call, st)
+
+
+def xbar_create(geom: Geometry, precision: int, max_batch: int, ir_tol: float = 0.0,
+                ir_max_iter: int = 0, stream: int | None = None) -> ctypes.c_void_p:
+    plan = ctypes.c_void_p()
+    st = lib().xbar_create(ctypes.byref(geom), int(precision), int(max_batch), float(ir_tol),
+                           int(ir_max_iter), ctypes.c_void_p(stream or 0), ctypes.byref(plan))
+    _check("xbar_create", st)
+    return plan
+
+
+def xbar_assemble(plan, G) -> None:
+    _check("xbar_assemble", lib().xbar_assemble(plan, _ptr(G)))
+
+
+def xbar_factor(plan) -> None:
+    _check("xbar_factor", lib().xbar_factor(plan))
+
+
+def xbar_solve_batch(plan, V, B: int, node_v=None) -> None:
+    _check("xbar_solve_batch", lib().xbar_solve_batch(plan, _ptr(V), int(B), _ptr(node_v)))
+
+
+def xbar_currents(plan, I) -> None:
+    _check("xbar_currents", lib().xbar_currents(plan, _ptr(I)))
+
+
+def xbar_get_info(plan) -> tuple[int, Info]:
+    info = Info()
+    st = lib().xbar_get_info(plan, ctypes.byref(info))
+    return st, info
+
+
+def xbar_set_timing(plan, enable: bool) -> None:
+    _check("xbar_set_timing", lib().xbar_set_timing(plan, 1 if enable else 0))
+
+
+def xbar_get_timing(plan, reset: bool = False) -> Timing:
+    t = Timing()
+    _check("xbar_get_timing", lib().xbar_get_timing(plan, ctypes.byref(t), 1 if reset else 0))
+    return t
+
+
+def xbar_destroy(plan) -> None:
+    _check("xbar_destroy", lib().xbar_destroy(plan))

@@ -1,0 +1,117 @@
+// Shared device definitions for the gfx950 crossbar solver kernels.
+//
+// Matrix-core fragments (wave64, 16x16 output tile):
+//   v_mfma_f64_16x16x4f64 : A lane l = A[l%16][l/16], B lane l = B[l/16][l%16],
+//                           D lane l item v = D[l/16 + 4v][l%16]
+//   v_mfma_f32_16x16x4f32 : A, B as above,  D lane l item v = D[4(l/16) + v][l%16]
+// (measured on gfx950 with a one-hot probe).
+//
+// The contraction index K is processed in chunks of 16.  Within a chunk,
+// MFMA step t of lane-group q = l/16 uses k = kidx(q, t), chosen so that
+// the four k values a lane touches are exactly the four output rows the
+// same lane holds in the D layout:
+//   f64: kidx(q, t) = q + 4t     f32: kidx(q, t) = 4q + t
+// A row-major matrix whose columns are permuted inside each 16-chunk by
+// slot(k) = position of k in (q, t) order makes every lane's four A values
+// contiguous (one 32-byte or 16-byte load).  This "chunk-permuted row-major"
+// (CPR) layout is used for every n_p x n_p block the kernels exchange, and
+// for the LDS panels of right-hand sides, stored [column][slot(k)].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+namespace xbk {
+
+constexpr int kWave = 64;
+constexpr int kTile = 64;          // block-inversion tile edge (rows/cols)
+constexpr int kSlabCols = 16;      // input vectors per workgroup in the sweeps
+
+template <typename T> struct Frag;
+template <> struct Frag<double> {
+    using acc_t = d4_t;
+    // k (0..15) of MFMA step t for lane group q
+    __host__ __device__ static constexpr int kidx(int q, int t) { return q + 4 * t; }
+    // slot of k inside its 16-chunk in CPR order (inverse of kidx)
+    __host__ __device__ static constexpr int slot(int k) { return 4 * (k & 3) + (k >> 2); }
+    // row (within the 16-row tile) of output item v for lane group q
+    __host__ __device__ static constexpr int drow(int q, int v) { return q + 4 * v; }
+    __device__ static inline acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Frag<float> {
+    using acc_t = f4_t;
+    __host__ __device__ static constexpr int kidx(int q, int t) { return 4 * q + t; }
+    __host__ __device__ static constexpr int slot(int k) { return k; }
+    __host__ __device__ static constexpr int drow(int q, int v) { return 4 * q + v; }
+    __device__ static inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// CPR offset of (r, k) in a row-major matrix with leading dimension ld.
+template <typename T>
+__host__ __device__ inline int64_t cpr(int64_t r, int k, int ld) {
+    return r * ld + (k & ~15) + Frag<T>::slot(k & 15);
+}
+
+// Device error flags (sticky, cleared by assemble).
+enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNumFlags = 4 };
+
+struct CondenseArgs {
+    const double* G;     // [m][n] user conductances
+    int m, n, n_p;
+    double g_wl, g_bl, g_src, g_sense;
+    void* E;             // [m][n_p][n_p] CPR, element type of the factor
+    double* c;           // [m][n_p]  condensed source coupling c_i
+    double* fr;          // [m][n]    g_wl / p_{j-1} (0 at j = 0): forward Thomas ratios of T_i
+    double* ip;          // [m][n]    1 / p_j
+    double* q;           // [m][n]    bit-line self conductance q_ij
+    double* Gc;          // [m][n]    copy of G
+    int* flags;
+};
+
+struct GJArgs {
+    int m, n, n_p, nb;   // nb = n_p / 64 block steps per inversion
+    double g2;           // g_bl^2 (Schur coupling of consecutive row blocks)
+    void* H;             // [m][n_p][n_p] CPR: E_t on entry, H_t = S_t^{-1} on exit
+    void* S0;            // working copies of S, [n_p][n_p] CPR each
+    void* S1;
+    void* P0;            // inverted pivot tiles, [64][64] row-major each
+    void* P1;
+    int* flags;
+};
+
+struct SweepArgs {
+    int m, n, n_p, B, nslab;
+    double g_bl, g_sense;
+    const void* H;       // [m][n_p][n_p] CPR block inverses H_i
+    const double* c;     // [m][n_p]
+    const double* V;     // [B][m] user inputs
+    void* Z;             // [nslab][m][16][n_p]: forward sweep z_i, then u_i
+    double* Iout;        // [B][n]
+};
+
+struct RecoverArgs {
+    int m, n, n_p, B, nslab;
+    double g_src;
+    const double* V;     // [B][m]
+    const void* Z;       // [nslab][m][16][n_p] u_i (element type of the sweep)
+    const double* fr;
+    const double* ip;
+    const double* Gc;
+    double g_wl;
+    double* node_v;      // [B][2mn]
+};
+
+}  // namespace xbk
+
+// Host-side launchers (defined in the .hip files, called by the C ABI layer).
+hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);

@@ -1,0 +1,390 @@
+// C ABI of the crossbar solver: plan lifetime, host-side validation,
+// workspace sizing and the call-order state machine (include/xbar.h).
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "xbar.h"
+
+namespace {
+
+enum State : int32_t { kCreated = 0, kAssembled = 1, kFactored = 2, kSolved = 3 };
+
+struct Buffers {
+    void* H = nullptr;        // [m][n_p][n_p] E_i, then H_i (factor precision)
+    double* c = nullptr;      // [m][n_p]
+    double* fr = nullptr;     // [m][n]
+    double* ip = nullptr;     // [m][n]
+    double* q = nullptr;      // [m][n]
+    double* Gc = nullptr;     // [m][n]
+    void* S[2] = {nullptr, nullptr};
+    void* P[2] = {nullptr, nullptr};
+    void* Z = nullptr;        // [nslab][m][16][n_p]
+    double* Iout = nullptr;   // [max_batch][n]
+    int* flags = nullptr;     // [kNumFlags]
+};
+
+__global__ void clear_flags_kernel(int* f)
+{
+    if (threadIdx.x < xbk::kNumFlags) f[threadIdx.x] = 0;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+// HIP-event timer of one kernel phase: event pairs recorded around launches and
+// resolved lazily (no synchronisation on the launch path).
+struct PhaseTimer {
+    std::vector<hipEvent_t> ev;     // pairs (start, stop), reused
+    size_t used = 0;                 // events in use
+    double ms = 0.0;
+    int64_t launches = 0;
+    bool begin(hipStream_t s) {
+        if (used + 2 > ev.size()) {
+            if (!flush()) return false;
+            if (ev.size() < 2 * 256) {
+                hipEvent_t a, b;
+                if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return false;
+                ev.push_back(a);
+                ev.push_back(b);
+            }
+        }
+        return hipEventRecord(ev[used], s) == hipSuccess;
+    }
+    bool end(hipStream_t s) {
+        if (hipEventRecord(ev[used + 1], s) != hipSuccess) return false;
+        used += 2;
+        return true;
+    }
+    bool flush() {
+        for (size_t k = 0; k + 1 < used; k += 2) {
+            float t = 0.f;
+            if (hipEventSynchronize(ev[k + 1]) != hipSuccess) return false;
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) return false;
+            ms += t;
+            ++launches;
+        }
+        used = 0;
+        return true;
+    }
+    void destroy() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        used = 0;
+    }
+};
+
+struct xbar_plan_s {
+    xbar_geometry g{};
+    xbar_precision prec = XBAR_FP64;
+    int32_t max_batch = 0;
+    double ir_tol = 0;
+    int32_t ir_max_iter = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int n_p = 0, nb = 0, nslab_max = 0;
+    int64_t bytes = 0;
+    int32_t state = kCreated;
+    int32_t last_B = 0;
+    Buffers d;
+    bool timing = false;
+    PhaseTimer t_condense, t_factor, t_sweep, t_recover;
+    bool fp32() const { return prec != XBAR_FP64; }
+    size_t elem() const { return fp32() ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+xbar_status dev_alloc(xbar_plan p, void** ptr, int64_t bytes)
+{
+    if (bytes <= 0) bytes = 256;
+    if (hipMalloc(ptr, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return XBAR_ERR_ALLOC;
+    }
+    p->bytes += bytes;
+    return XBAR_OK;
+}
+
+void free_all(xbar_plan p)
+{
+    Buffers& d = p->d;
+    void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0], d.S[1], d.P[0], d.P[1], d.Z, d.Iout, d.flags};
+    for (void* x : all)
+        if (x) (void)hipFree(x);
+    d = Buffers{};
+}
+
+bool set_device(xbar_plan p) { return hipSetDevice(p->device) == hipSuccess; }
+
+}  // namespace
+
+extern "C" {
+
+const char* xbar_status_string(xbar_status s)
+{
+    switch (s) {
+        case XBAR_OK: return "XBAR_OK";
+        case XBAR_ERR_ARG: return "XBAR_ERR_ARG";
+        case XBAR_ERR_ALLOC: return "XBAR_ERR_ALLOC";
+        case XBAR_ERR_STATE: return "XBAR_ERR_STATE";
+        case XBAR_ERR_NOT_SPD: return "XBAR_ERR_NOT_SPD";
+        case XBAR_ERR_NO_CONVERGENCE: return "XBAR_ERR_NO_CONVERGENCE";
+        case XBAR_ERR_DEVICE: return "XBAR_ERR_DEVICE";
+        case XBAR_ERR_INPUT: return "XBAR_ERR_INPUT";
+    }
+    return "XBAR_UNKNOWN_STATUS";
+}
+
+xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t max_batch,
+                        double ir_tol, int32_t ir_max_iter, void* hip_stream, xbar_plan* out)
+{
+    if (out == nullptr || geom == nullptr) return XBAR_ERR_ARG;
+    *out = nullptr;
+    const xbar_geometry g = *geom;
+    if (g.m < 1 || g.n < 1 || g.n > XBAR_MAX_N) return XBAR_ERR_ARG;
+    if (!finite_pos(g.r_wl) || !finite_pos(g.r_bl) || !finite_pos(g.r_src) || !finite_pos(g.r_sense))
+        return XBAR_ERR_ARG;
+    if (prec != XBAR_FP64 && prec != XBAR_FP32_IR && prec != XBAR_BF16_IR) return XBAR_ERR_ARG;
+    if (max_batch < 1) return XBAR_ERR_ARG;
+    if (!(std::isfinite(ir_tol) && ir_tol >= 0.0 && ir_tol < 1.0)) return XBAR_ERR_ARG;
+    if (ir_max_iter < 0 || ir_max_iter > 100) return XBAR_ERR_ARG;
+    if (prec != XBAR_FP64) return XBAR_ERR_ARG;   // refinement modes are not built in this library yet
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return XBAR_ERR_DEVICE;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return XBAR_ERR_DEVICE;
+
+    xbar_plan p = new (std::nothrow) xbar_plan_s;
+    if (!p) return XBAR_ERR_ALLOC;
+    p->g = g;
+    p->prec = prec;
+    p->max_batch = max_batch;
+    p->ir_tol = (ir_tol == 0.0) ? 1e-13 : ir_tol;
+    p->ir_max_iter = (ir_max_iter == 0) ? 10 : ir_max_iter;
+    p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    p->device = dev;
+    p->n_p = 64 * ((g.n + 63) / 64);
+    p->nb = p->n_p / 64;
+    p->nslab_max = (max_batch + 15) / 16;
+
+    const int64_t m = g.m, n = g.n, n_p = p->n_p, es = (int64_t)p->elem();
+    Buffers& d = p->d;
+    xbar_status st = XBAR_OK;
+    auto A = [&](void** ptr, int64_t bytes) {
+        if (st == XBAR_OK) st = dev_alloc(p, ptr, bytes);
+    };
+    A(&d.H, m * n_p * n_p * es);
+    A((void**)&d.c, m * n_p * 8);
+    A((void**)&d.fr, m * n * 8);
+    A((void**)&d.ip, m * n * 8);
+    A((void**)&d.q, m * n * 8);
+    A((void**)&d.Gc, m * n * 8);
+    A(&d.S[0], n_p * n_p * es);
+    A(&d.S[1], n_p * n_p * es);
+    A(&d.P[0], 64 * 64 * es);
+    A(&d.P[1], 64 * 64 * es);
+    A(&d.Z, (int64_t)p->nslab_max * m * 16 * n_p * es);
+    A((void**)&d.Iout, (int64_t)max_batch * n * 8);
+    A((void**)&d.flags, xbk::kNumFlags * sizeof(int));
+    if (st != XBAR_OK) {
+        free_all(p);
+        delete p;
+        return st;
+    }
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, p->stream, d.flags);
+    if (hipGetLastError() != hipSuccess) {
+        free_all(p);
+        delete p;
+        return XBAR_ERR_DEVICE;
+    }
+    *out = p;
+    return XBAR_OK;
+}
+
+xbar_status xbar_assemble(xbar_plan p, const double* G)
+{
+    if (p == nullptr || G == nullptr) return XBAR_ERR_ARG;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, p->stream, p->d.flags);
+    xbk::CondenseArgs a{};
+    a.G = G;
+    a.m = p->g.m;
+    a.n = p->g.n;
+    a.n_p = p->n_p;
+    a.g_wl = 1.0 / p->g.r_wl;
+    a.g_bl = 1.0 / p->g.r_bl;
+    a.g_src = 1.0 / p->g.r_src;
+    a.g_sense = 1.0 / p->g.r_sense;
+    a.E = p->d.H;
+    a.c = p->d.c;
+    a.fr = p->d.fr;
+    a.ip = p->d.ip;
+    a.q = p->d.q;
+    a.Gc = p->d.Gc;
+    a.flags = p->d.flags;
+    if (p->timing && !p->t_condense.begin(p->stream)) return XBAR_ERR_DEVICE;
+    if (xbk_launch_condense(a, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (p->timing && !p->t_condense.end(p->stream)) return XBAR_ERR_DEVICE;
+    p->state = kAssembled;
+    return XBAR_OK;
+}
+
+xbar_status xbar_factor(xbar_plan p)
+{
+    if (p == nullptr) return XBAR_ERR_ARG;
+    if (p->state != kAssembled) return XBAR_ERR_STATE;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    xbk::GJArgs a{};
+    a.m = p->g.m;
+    a.n = p->g.n;
+    a.n_p = p->n_p;
+    a.nb = p->nb;
+    const double gb = 1.0 / p->g.r_bl;
+    a.g2 = gb * gb;
+    a.H = p->d.H;
+    a.S0 = p->d.S[0];
+    a.S1 = p->d.S[1];
+    a.P0 = p->d.P[0];
+    a.P1 = p->d.P[1];
+    a.flags = p->d.flags;
+    if (p->timing && !p->t_factor.begin(p->stream)) return XBAR_ERR_DEVICE;
+    if (xbk_launch_factor(a, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (p->timing && !p->t_factor.end(p->stream)) return XBAR_ERR_DEVICE;
+    p->state = kFactored;
+    return XBAR_OK;
+}
+
+xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* node_v)
+{
+    if (p == nullptr || V == nullptr) return XBAR_ERR_ARG;
+    if (B < 1 || B > p->max_batch) return XBAR_ERR_ARG;
+    if (p->state < kFactored) return XBAR_ERR_STATE;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    const int nslab = (B + 15) / 16;
+    xbk::SweepArgs s{};
+    s.m = p->g.m;
+    s.n = p->g.n;
+    s.n_p = p->n_p;
+    s.B = B;
+    s.nslab = nslab;
+    s.g_bl = 1.0 / p->g.r_bl;
+    s.g_sense = 1.0 / p->g.r_sense;
+    s.H = p->d.H;
+    s.c = p->d.c;
+    s.V = V;
+    s.Z = p->d.Z;
+    s.Iout = p->d.Iout;
+    if (p->timing && !p->t_sweep.begin(p->stream)) return XBAR_ERR_DEVICE;
+    if (xbk_launch_sweep(s, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (p->timing && !p->t_sweep.end(p->stream)) return XBAR_ERR_DEVICE;
+    if (node_v != nullptr) {
+        xbk::RecoverArgs r{};
+        r.m = p->g.m;
+        r.n = p->g.n;
+        r.n_p = p->n_p;
+        r.B = B;
+        r.nslab = nslab;
+        r.g_src = 1.0 / p->g.r_src;
+        r.g_wl = 1.0 / p->g.r_wl;
+        r.V = V;
+        r.Z = p->d.Z;
+        r.fr = p->d.fr;
+        r.ip = p->d.ip;
+        r.Gc = p->d.Gc;
+        r.node_v = node_v;
+        if (p->timing && !p->t_recover.begin(p->stream)) return XBAR_ERR_DEVICE;
+        if (xbk_launch_recover(r, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+        if (p->timing && !p->t_recover.end(p->stream)) return XBAR_ERR_DEVICE;
+    }
+    p->state = kSolved;
+    p->last_B = B;
+    return XBAR_OK;
+}
+
+xbar_status xbar_currents(xbar_plan p, double* I)
+{
+    if (p == nullptr || I == nullptr) return XBAR_ERR_ARG;
+    if (p->state != kSolved) return XBAR_ERR_STATE;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    const size_t bytes = (size_t)p->last_B * p->g.n * sizeof(double);
+    if (hipMemcpyAsync(I, p->d.Iout, bytes, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+        return XBAR_ERR_DEVICE;
+    return XBAR_OK;
+}
+
+xbar_status xbar_get_info(xbar_plan p, xbar_info* info)
+{
+    if (p == nullptr || info == nullptr) return XBAR_ERR_ARG;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    int flags[xbk::kNumFlags] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(flags, p->d.flags, sizeof(flags), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
+        return XBAR_ERR_DEVICE;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    std::memset(info, 0, sizeof(*info));
+    info->state = p->state;
+    info->last_batch = p->last_B;
+    info->ir_iters = flags[xbk::kIrIters];
+    info->workspace_bytes = p->bytes;
+    info->block = p->n_p;
+    xbar_status st = XBAR_OK;
+    if (flags[xbk::kErrInput]) st = XBAR_ERR_INPUT;
+    else if (flags[xbk::kErrPivot]) st = XBAR_ERR_NOT_SPD;
+    else if (flags[xbk::kErrConv]) st = XBAR_ERR_NO_CONVERGENCE;
+    info->device_error = (int32_t)st;
+    return st;
+}
+
+xbar_status xbar_set_timing(xbar_plan p, int32_t enable)
+{
+    if (p == nullptr) return XBAR_ERR_ARG;
+    p->timing = enable != 0;
+    return XBAR_OK;
+}
+
+xbar_status xbar_get_timing(xbar_plan p, xbar_timing* out, int32_t reset)
+{
+    if (p == nullptr || out == nullptr) return XBAR_ERR_ARG;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover};
+    for (PhaseTimer* t : all)
+        if (!t->flush()) return XBAR_ERR_DEVICE;
+    out->condense_ms = p->t_condense.ms;
+    out->condense_launches = p->t_condense.launches;
+    out->factor_ms = p->t_factor.ms;
+    out->factor_launches = p->t_factor.launches;
+    out->sweep_ms = p->t_sweep.ms;
+    out->sweep_launches = p->t_sweep.launches;
+    out->recover_ms = p->t_recover.ms;
+    out->recover_launches = p->t_recover.launches;
+    if (reset)
+        for (PhaseTimer* t : all) {
+            t->ms = 0.0;
+            t->launches = 0;
+        }
+    return XBAR_OK;
+}
+
+xbar_status xbar_destroy(xbar_plan p)
+{
+    if (p == nullptr) return XBAR_OK;
+    (void)set_device(p);
+    (void)hipStreamSynchronize(p->stream);
+    PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover};
+    for (PhaseTimer* t : all) t->destroy();
+    free_all(p);
+    delete p;
+    return XBAR_OK;
+}
+
+}  // extern "C"

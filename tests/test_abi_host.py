@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and rejects bad arguments on the host before touching a
+device (include/xbar.h)."""
+import ctypes
+import math
+
+import pytest
+
+from paper_2410_19993_amd import _lib
+
+EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor",
+            "xbar_get_info", "xbar_get_timing", "xbar_set_timing", "xbar_solve_batch",
+            "xbar_status_string"]
+
+
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_header_declares_the_boundary():
+    assert _lib.header_functions() == EXPECTED
+
+
+def test_library_exports_every_header_symbol():
+    L = _lib.lib()
+    for name in _lib.header_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    names = {0: "XBAR_OK", 1: "XBAR_ERR_ARG", 2: "XBAR_ERR_ALLOC", 3: "XBAR_ERR_STATE",
+             4: "XBAR_ERR_NOT_SPD", 5: "XBAR_ERR_NO_CONVERGENCE", 6: "XBAR_ERR_DEVICE",
+             7: "XBAR_ERR_INPUT"}
+    for k, v in names.items():
+        assert _lib.status_string(k) == v
+    assert _lib.status_string(99) == "XBAR_UNKNOWN_STATUS"
+
+
+def _create(geom, prec=0, max_batch=8, tol=0.0, iters=0):
+    plan = ctypes.c_void_p()
+    st = _lib.lib().xbar_create(ctypes.byref(geom), prec, max_batch, tol, iters, None,
+                                ctypes.byref(plan))
+    return st, plan
+
+
+GOOD = dict(m=4, n=4, r_wl=1.0, r_bl=1.0, r_src=50.0, r_sense=50.0)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("m", 0), ("n", 0), ("m", -3), ("n", 513), ("r_wl", 0.0), ("r_bl", -1.0),
+    ("r_src", math.inf), ("r_sense", math.nan), ("r_wl", math.nan)])
+def test_create_rejects_bad_geometry(field, value):
+    kw = dict(GOOD)
+    kw[field] = value
+    st, plan = _create(_lib.Geometry(**kw))
+    assert st == _lib.XBAR_ERR_ARG and not plan.value
+
+
+@pytest.mark.parametrize("prec,max_batch,tol,iters", [
+    (7, 8, 0.0, 0), (-1, 8, 0.0, 0), (0, 0, 0.0, 0), (0, -5, 0.0, 0),
+    (0, 8, -1.0, 0), (0, 8, math.nan, 0), (0, 8, 1.5, 0), (0, 8, 0.0, -1), (0, 8, 0.0, 1000)])
+def test_create_rejects_bad_options(prec, max_batch, tol, iters):
+    st, plan = _create(_lib.Geometry(**GOOD), prec, max_batch, tol, iters)
+    assert st == _lib.XBAR_ERR_ARG and not plan.value
+
+
+def test_create_null_pointers():
+    L = _lib.lib()
+    plan = ctypes.c_void_p()
+    assert L.xbar_create(None, 0, 8, 0.0, 0, None, ctypes.byref(plan)) == _lib.XBAR_ERR_ARG
+    g = _lib.Geometry(**GOOD)
+    assert L.xbar_create(ctypes.byref(g), 0, 8, 0.0, 0, None, None) == _lib.XBAR_ERR_ARG
+
+
+def test_null_plan_calls():
+    L = _lib.lib()
+    assert L.xbar_assemble(None, None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_factor(None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_solve_batch(None, None, 1, None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_currents(None, None) == _lib.XBAR_ERR_ARG
+    info = _lib.Info()
+    assert L.xbar_get_info(None, ctypes.byref(info)) == _lib.XBAR_ERR_ARG
+    assert L.xbar_destroy(None) == _lib.XBAR_OK
+    assert L.xbar_set_timing(None, 1) == _lib.XBAR_ERR_ARG
+    assert L.xbar_get_timing(None, ctypes.byref(_lib.Timing()), 0) == _lib.XBAR_ERR_ARG
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="checks the GPU-less path")
+def test_create_without_device_reports_device_error():
+    st, plan = _create(_lib.Geometry(**GOOD))
+    assert st == _lib.XBAR_ERR_DEVICE and not plan.value

@@ -1,0 +1,119 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Float64 path: per-vector relative error of the output currents <= 1e-10
+(the tolerance of the float64 solver); node voltages <= 1e-10 relative to
+the vector's largest node voltage.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import diagnostics as dg
+from tests.gpu_util import GOLDEN, TOL_FP64, gpu_solve, log, node_rel_err, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_against_oracle(wl, precision="fp64", tol=TOL_FP64, **kw):
+    log(f"case {wl.name} precision={precision}")
+    I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, precision, **kw)
+    assert st == 0, f"device status {st}"
+    ref = oracle.solve_workload(wl)
+    e = rel_err(I, ref.currents)
+    log(f"  max current rel err {e.max():.3e}")
+    assert np.all(np.isfinite(I))
+    assert e.max() <= tol
+    ev = node_rel_err(nv, ref.node_v)
+    log(f"  max node-voltage rel err {ev.max():.3e}")
+    assert ev.max() <= tol
+    return I, nv, ref
+
+
+def test_c1_full():
+    _check_against_oracle(workloads.c1())
+
+
+@pytest.mark.parametrize("m,n,B,seed", [
+    (1, 1, 1, 1), (1, 7, 3, 2), (9, 1, 5, 3), (2, 2, 16, 4), (3, 70, 17, 5), (65, 64, 33, 6),
+    (7, 129, 15, 7), (10, 200, 20, 8), (4, 512, 2, 9), (33, 40, 48, 10)])
+def test_ragged_shapes(m, n, B, seed):
+    """Sizes that are not multiples of the 64-wide blocks or 16-vector slabs."""
+    wl = workloads.random_crossbar(m, n, B, seed, r_wl=1.5, r_bl=3.0, r_src=40.0, r_sense=60.0)
+    _check_against_oracle(wl)
+
+
+@pytest.mark.parametrize("r", [1.0, 2.5, 5.0])
+def test_segment_resistance(r):
+    wl = workloads.random_crossbar(48, 96, 24, 11, r_wl=r, r_bl=r)
+    _check_against_oracle(wl)
+
+
+def test_paper_model_resistances():
+    """The paper's own model: 5-ohm parasitics, source and termination equal to a segment."""
+    wl = workloads.random_crossbar(32, 32, 16, 12, r_wl=5.0, r_bl=5.0, r_src=5.0, r_sense=5.0,
+                                   g_dist="uniform")
+    _check_against_oracle(wl)
+
+
+def test_zero_and_unit_inputs():
+    wl = workloads.random_crossbar(20, 30, 4, 13)
+    wl.V[0] = 0.0
+    wl.V[1] = 0.5
+    I, nv, (st, _) = gpu_solve(wl.G, wl.V, wl.geom)
+    assert st == 0
+    assert np.max(np.abs(I[0])) <= 1e-18 and np.max(np.abs(nv[0])) <= 1e-18
+    ref = oracle.solve_workload(wl)
+    assert rel_err(I[1:], ref.currents[1:]).max() <= TOL_FP64
+
+
+def test_c2_full_golden():
+    path = os.path.join(GOLDEN, "c2_currents.npy")
+    ref = np.load(path)
+    wl = workloads.c2()
+    log(f"case {wl.name}")
+    I, nv, (st, _) = gpu_solve(wl.G, wl.V, wl.geom, node_voltages=True)
+    assert st == 0
+    e = rel_err(I, ref)
+    log(f"  max current rel err {e.max():.3e}")
+    assert e.max() <= TOL_FP64
+    # KCL at every node for a few vectors, from the GPU's node voltages
+    net = oracle.build_netlist(wl.G, wl.geom.r_wl, wl.geom.r_bl, wl.geom.r_src, wl.geom.r_sense)
+    sel = [0, 511, 1023]
+    imb = dg.kcl_imbalance(net, wl.V[sel], nv[sel])
+    src = dg.source_currents(net, wl.V[sel], nv[sel])
+    log(f"  max KCL imbalance {np.abs(imb).max():.3e} A (source scale {np.abs(src).max():.3e})")
+    assert np.abs(imb).max() <= 1e-9 * np.abs(src).max()
+
+
+def test_batch_invariance_and_determinism():
+    """Input vectors are independent: a vector solved alone or inside a batch gives the
+    same bits, and two identical runs are bitwise equal."""
+    wl = workloads.random_crossbar(24, 80, 37, 14)
+    I1, nv1, _ = gpu_solve(wl.G, wl.V, wl.geom)
+    I2, nv2, _ = gpu_solve(wl.G, wl.V, wl.geom)
+    assert np.array_equal(I1, I2) and np.array_equal(nv1, nv2)
+    for k in (0, 17, 36):
+        Ik, nvk, _ = gpu_solve(wl.G, wl.V[k:k + 1], wl.geom)
+        assert np.array_equal(Ik[0], I1[k]) and np.array_equal(nvk[0], nv1[k])
+
+
+def test_plan_reuse_many_batches():
+    """Decompose once, solve many batches (Sec. III.A), including a smaller second batch."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    wl = workloads.random_crossbar(40, 72, 64, 15)
+    ref = oracle.solve_workload(wl)
+    g = wl.geom
+    with xb.Plan(40, 72, g.r_wl, g.r_bl, g.r_src, g.r_sense, "fp64", max_batch=64) as p:
+        p.assemble(torch.from_numpy(wl.G).cuda())
+        p.factor()
+        for lo, hi in ((0, 64), (5, 12), (63, 64)):
+            V = torch.from_numpy(np.ascontiguousarray(wl.V[lo:hi])).cuda()
+            p.solve_batch(V)
+            I = p.currents().cpu().numpy()
+            p.check()
+            assert rel_err(I, ref.currents[lo:hi]).max() <= TOL_FP64
