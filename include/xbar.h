@@ -146,6 +146,20 @@ xbar_status xbar_currents(xbar_plan plan, double* I);
 xbar_status xbar_get_info(xbar_plan plan, xbar_info* info);
 
 /*
+ * How xbar_factor inverts the pivot blocks of the block LU.
+ *   XBAR_FACTOR_AUTO (default): Newton-Schulz iteration on the matrix cores;
+ *       if any block misses its tolerance the factorization is redone with
+ *       Gauss-Jordan elimination.  xbar_factor then waits for the device to
+ *       decide (it synchronises the plan's stream).
+ *   XBAR_FACTOR_GJ: blocked Gauss-Jordan elimination only (asynchronous).
+ *   XBAR_FACTOR_NS: Newton-Schulz only (asynchronous); a block that misses
+ *       its tolerance sets XBAR_ERR_NO_CONVERGENCE on the device.
+ * Host-only; takes effect at the next xbar_factor.
+ */
+typedef enum { XBAR_FACTOR_AUTO = 0, XBAR_FACTOR_GJ = 1, XBAR_FACTOR_NS = 2 } xbar_factor_method;
+xbar_status xbar_set_factor_method(xbar_plan plan, xbar_factor_method method);
+
+/*
  * Per-kernel timing, measured with HIP events recorded on the plan's stream
  * around each kernel launch of the calls above (only while enabled).
  * Times are accumulated milliseconds; *_launches count the kernels timed.

@@ -6,8 +6,8 @@ and the HIP stream.  All arithmetic runs in the library's HIP kernels.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import (PRECISIONS, XBAR_BF16_IR, XBAR_FP32_IR, XBAR_FP64, Geometry,  # noqa: F401
-                   XbarError, status_string)
+from ._lib import (FACTOR_METHODS, PRECISIONS, XBAR_BF16_IR, XBAR_FP32_IR, XBAR_FP64,  # noqa: F401
+                   Geometry, XbarError, status_string)
 
 __all__ = ["Plan", "solve", "Geometry", "XbarError", "PRECISIONS", "status_string"]
 
@@ -32,7 +32,7 @@ class Plan:
 
     def __init__(self, m: int, n: int, r_wl: float, r_bl: float, r_src: float = 50.0,
                  r_sense: float = 50.0, precision: str = "fp64", max_batch: int = 1024,
-                 ir_tol: float = 0.0, ir_max_iter: int = 0, stream=None):
+                 ir_tol: float = 0.0, ir_max_iter: int = 0, stream=None, factor_method: str = "auto"):
         torch = _torch()
         self.m, self.n = int(m), int(n)
         self.max_batch = int(max_batch)
@@ -42,6 +42,7 @@ class Plan:
         self._plan = _lib.xbar_create(self.geom, PRECISIONS[precision], self.max_batch, ir_tol,
                                       ir_max_iter, self.stream.cuda_stream)
         self._B = 0
+        _lib.xbar_set_factor_method(self._plan, FACTOR_METHODS[factor_method])
 
     def assemble(self, G) -> None:
         _check_tensor("G", G, (self.m, self.n))
@@ -98,12 +99,14 @@ class Plan:
         self.close()
 
 
-def solve(G, V, r_wl, r_bl, r_src=50.0, r_sense=50.0, precision="fp64", node_voltages=True):
+def solve(G, V, r_wl, r_bl, r_src=50.0, r_sense=50.0, precision="fp64", node_voltages=True,
+          factor_method="auto"):
     """One-shot solve: returns (currents [B][n], node voltages [B][2mn] or None)."""
     torch = _torch()
     m, n = G.shape
     B = V.shape[0]
-    with Plan(m, n, r_wl, r_bl, r_src, r_sense, precision, max_batch=B) as p:
+    with Plan(m, n, r_wl, r_bl, r_src, r_sense, precision, max_batch=B,
+              factor_method=factor_method) as p:
         p.assemble(G)
         p.factor()
         nv = torch.empty((B, 2 * m * n), dtype=torch.float64, device="cuda") if node_voltages else None

@@ -29,6 +29,11 @@ XBAR_FP32_IR = 1
 XBAR_BF16_IR = 2
 PRECISIONS = {"fp64": XBAR_FP64, "fp32_ir": XBAR_FP32_IR, "bf16_ir": XBAR_BF16_IR}
 
+XBAR_FACTOR_AUTO = 0
+XBAR_FACTOR_GJ = 1
+XBAR_FACTOR_NS = 2
+FACTOR_METHODS = {"auto": XBAR_FACTOR_AUTO, "gj": XBAR_FACTOR_GJ, "ns": XBAR_FACTOR_NS}
+
 
 class Geometry(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32),
@@ -76,12 +81,13 @@ def lib() -> ctypes.CDLL:
         L.xbar_get_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.xbar_destroy.argtypes = [vp]
         L.xbar_set_timing.argtypes = [vp, ctypes.c_int32]
+        L.xbar_set_factor_method.argtypes = [vp, ctypes.c_int]
         L.xbar_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int32]
         L.xbar_status_string.argtypes = [ctypes.c_int]
         L.xbar_status_string.restype = ctypes.c_char_p
         for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
-                  "xbar_get_timing"):
+                  "xbar_get_timing", "xbar_set_factor_method"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -138,6 +144,10 @@ def xbar_get_info(plan) -> tuple[int, Info]:
     info = Info()
     st = lib().xbar_get_info(plan, ctypes.byref(info))
     return st, info
+
+
+def xbar_set_factor_method(plan, method: int) -> None:
+    _check("xbar_set_factor_method", lib().xbar_set_factor_method(plan, int(method)))
 
 
 def xbar_set_timing(plan, enable: bool) -> None:

@@ -59,8 +59,40 @@ __host__ __device__ inline int64_t cpr(int64_t r, int k, int ld) {
     return r * ld + (k & ~15) + Frag<T>::slot(k & 15);
 }
 
-// Device error flags (sticky, cleared by assemble).
-enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNumFlags = 4 };
+// Device error flags (sticky, cleared by assemble).  kNsFail is internal: a
+// Newton-Schulz inverse that missed its tolerance (the factor then reruns
+// with Gauss-Jordan elimination).
+enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNsFail = 4, kNumFlags = 8 };
+
+constexpr int kNsMaxIter = 6;      // Newton-Schulz steps allowed per chain row
+constexpr int kNsMaxIterTwist = 10;
+
+// Newton-Schulz inversion of the pivot blocks: per chain, the formed pivot
+// block S, two iterates X and the residual Q = I - X S.
+struct NSChain {
+    void* S;
+    void* X[2];
+    void* Q;
+    double* dprev;       // [n_p] diagonal of the previous pivot block of this chain
+};
+
+struct NSJob {
+    int row, dep_a, dep_b;   // pivot block E_row - g^2 (H_dep_a + H_dep_b)
+    int warm;                // 1: start from H_dep_a corrected on the diagonal; 0: from diag(S)^{-1}
+    int chain;               // which NSChain buffers
+};
+
+struct NSArgs {
+    int m, n, n_p;
+    double g2;
+    void* H;                 // [m][n_p][n_p] CPR
+    NSChain ch[2];
+    NSJob job[2];
+    unsigned long long* norm;  // [m][kNsMaxIterTwist] max |I - X S| per row and step (bits of a double)
+    int* done;                 // [m] row finished
+    int* flags;
+    int max_iter;
+};
 
 struct CondenseArgs {
     const double* G;     // [m][n] user conductances
@@ -75,14 +107,20 @@ struct CondenseArgs {
     int* flags;
 };
 
+// One inversion in flight: the pivot block of crossbar row `row`.
+struct GJJob {
+    int row;             // row whose pivot block is being inverted
+    int next;            // row whose pivot block this one feeds (-1: none)
+    int dep_a, dep_b;    // rows whose inverses enter the pivot block (-1: none)
+    void* S[2];          // working copies of the pivot block, [n_p][n_p] CPR each
+    void* P[2];          // inverted 64x64 pivot tiles, CPR each
+};
+
 struct GJArgs {
-    int m, n, n_p, nb;   // nb = n_p / 64 block steps per inversion
-    double g2;           // g_bl^2 (Schur coupling of consecutive row blocks)
-    void* H;             // [m][n_p][n_p] CPR: E_t on entry, H_t = S_t^{-1} on exit
-    void* S0;            // working copies of S, [n_p][n_p] CPR each
-    void* S1;
-    void* P0;            // inverted pivot tiles, [64][64] row-major each
-    void* P1;
+    int m, n, n_p, nb;   // nb = n_p / 64 tile rows per block
+    double g2;           // g_bl^2: coupling of neighbouring row blocks
+    void* H;             // [m][n_p][n_p] CPR: E_i on entry, pivot inverse H_i on exit
+    GJJob job[2];        // top and bottom chains (one job for the twist row)
     int* flags;
 };
 
@@ -113,5 +151,6 @@ struct RecoverArgs {
 // Host-side launchers (defined in the .hip files, called by the C ABI layer).
 hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_factor_ns(const xbk::NSArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);

@@ -1,261 +1,366 @@
 // Block LU of the condensed bit-line system (the decomposition of Sec. II.C,
-// done over row blocks).
+// done over row blocks), in twisted ("burn at both ends") order.
 //
 // After condensation the bit-line voltages satisfy the block-tridiagonal
-// system  E_i u_i - g_bl (u_{i-1} + u_{i+1}) = V_i c_i.  Its block LU
-// (block-Thomas) has the pivot blocks
-//     S_0 = E_0,   S_t = E_t - g_bl^2 S_{t-1}^{-1},
-// and the substitution only needs H_t = S_t^{-1}, which this file computes,
-// sequentially in t, overwriting E_t with H_t in place.
+// system  E_i u_i - g_bl (u_{i-1} + u_{i+1}) = V_i c_i.  Its block LU from the
+// top has pivots S_0 = E_0, S_i = E_i - g_bl^2 S_{i-1}^{-1}; from the bottom,
+// S'_{m-1} = E_{m-1}, S'_i = E_i - g_bl^2 S'_{i+1}^{-1}.  Running the top
+// recurrence on rows 0..kt-1 and the bottom one on rows m-1..kt+1 at the same
+// time, with kt = m/2, leaves the twist block
+//     K = E_kt - g_bl^2 S_{kt-1}^{-1} - g_bl^2 S'_{kt+1}^{-1}
+// and halves the sequential chain.  This file stores H_i = (pivot of row i)^{-1}
+// over E_i: S_i^{-1} above kt, S'_i^{-1} below, K^{-1} at kt.
 //
 // Each inverse is an in-place blocked Gauss-Jordan elimination on 64 x 64
-// tiles (no row exchanges: every S_t is symmetric positive definite, a
-// Schur complement of the SPD nodal matrix).  For pivot block k with
-// P = S[k][k]:
+// tiles (no row exchanges: every pivot block is symmetric positive definite,
+// a Schur complement of the SPD nodal matrix).  For pivot block k, P = S[k][k]:
 //     S[I][J] -= S[I][k] (P^{-1} S[k][J])      I != k, J != k
 //     S[k][J]  = P^{-1} S[k][J]                J != k
 //     S[I][k]  = -S[I][k] P^{-1}                I != k
 //     S[k][k]  = P^{-1}
-// One kernel launch per pivot block (the launch boundary is the only
-// grid-wide synchronisation); workgroup (I, J) updates tile (I, J) with two
-// 64^3 MFMA products.  The workgroup that owns the next pivot tile inverts
-// it before exiting, so P^{-1} is ready when the next launch starts; the
-// last launch of step t also forms S_{t+1} = E_{t+1} - g_bl^2 H_t tile by
-// tile and inverts its first pivot tile.
+// One launch per pivot block serves both chains (the launch boundary is the
+// grid-wide synchronisation); workgroup (chain, I, J) updates tile (I, J).
+// The workgroup owning the next pivot tile inverts it before exiting, and
+// the last launch of a row forms the chain's next pivot block tile by tile.
+#include <type_traits>
+
 #include "common.h"
 
 namespace xbk {
 
-constexpr int kLd = kTile + 4;          // LDS row pitch (elements) for operand tiles
-constexpr int kLdP = kTile + 1;         // LDS row pitch for the pivot inversion
+constexpr int kLd = kTile + 4;          // LDS pitch (elements) of operand tiles
+constexpr int kTT = kTile * kTile;
 
-// acc[C] += A(16w.. rows, 64) * B(64, 16C.. cols); sA row-major CPR, sB = B^T, CPR on k.
+template <typename T>
+__device__ inline int out_row(int w, int l, int v)
+{
+    return 16 * w + Frag<T>::drow(l >> 4, v);
+}
+
+// acc[C] += A(rows 16w.., 64) * B(64, cols 16C..); sA row-major CPR, sB = B^T (CPR on k).
 template <typename T>
 __device__ inline void tile_mma(typename Frag<T>::acc_t (&acc)[4], const T* sA, const T* sB, int w, int l)
 {
     const int q = l >> 4, r = l & 15;
 #pragma unroll
     for (int K = 0; K < 4; ++K) {
-        T av[4];
+        T av[4], bv[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) av[t] = sA[(16 * w + r) * kLd + 16 * K + 4 * q + t];
 #pragma unroll
-        for (int C = 0; C < 4; ++C) {
+        for (int C = 0; C < 4; ++C)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[C] = Frag<T>::mma(av[t], sB[(16 * C + r) * kLd + 16 * K + 4 * q + t], acc[C]);
-        }
+            for (int t = 0; t < 4; ++t) bv[C][t] = sB[(16 * C + r) * kLd + 16 * K + 4 * q + t];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int C = 0; C < 4; ++C) acc[C] = Frag<T>::mma(av[t], bv[C][t], acc[C]);
     }
 }
 
-// Stage a 64x64 tile of a CPR matrix as an A operand (same CPR order), scaled by s.
+// Operand staging is split into a fetch (global -> registers, 16 values per
+// thread, row-contiguous across a wave) and a put (registers -> LDS), so that a
+// workgroup can issue every global load of a launch before waiting on any.
+constexpr int kPer = kTT / 256;
+
 template <typename T>
-__device__ inline void stage_A(T* sA, const T* M, int ld, int r0, int c0, T s)
+__device__ inline void fetch_tile(T (&v)[kPer], const T* __restrict__ M, int ld, int r0, int c0)
 {
-    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-        const int r = e / kTile, p = e % kTile;
-        sA[r * kLd + p] = s * M[(int64_t)(r0 + r) * ld + c0 + p];
+    const int p = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) v[it] = M[(int64_t)(r0 + rb + 4 * it) * ld + c0 + p];
+}
+
+// A operand: same CPR order as in memory, scaled by s.
+template <typename T>
+__device__ inline void put_A(T* sA, const T (&v)[kPer], T s)
+{
+    const int p = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) sA[(rb + 4 * it) * kLd + p] = s * v[it];
+}
+
+// B operand: sB[col][slot(k)] = M[k][col] (memory position p holds column 16(p/16)+slot(p%16)).
+template <typename T>
+__device__ inline void put_B(T* sB, const T (&v)[kPer])
+{
+    const int p = threadIdx.x & 63, rb = threadIdx.x >> 6;
+    const int cc = (p & ~15) + Frag<T>::slot(p & 15);
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+        const int kk = rb + 4 * it;
+        sB[cc * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = v[it];
     }
 }
 
-// Stage a 64x64 tile of a CPR matrix as a B operand: sB[col][slot(k)] = M[k][col].
 template <typename T>
-__device__ inline void stage_B(T* sB, const T* M, int ld, int r0, int c0)
+__device__ inline void load_acc(typename Frag<T>::acc_t (&acc)[4], const T* __restrict__ M, int ld,
+                                int r0, int c0, int w, int l)
 {
-    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-        const int kk = e / kTile, p = e % kTile;       // global position p holds column 16(p/16)+slot(p%16)
-        const int cc = (p & ~15) + Frag<T>::slot(p & 15);
-        sB[cc * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = M[(int64_t)(r0 + kk) * ld + c0 + p];
-    }
-}
-
-// Element (row, col) of the output sub-tile held by lane l, item v, of wave w.
-__device__ inline int out_row(int w, int l, int v, bool f64) { return 16 * w + (f64 ? ((l >> 4) + 4 * v) : (4 * (l >> 4) + v)); }
-
-template <typename T>
-__device__ inline void load_acc(typename Frag<T>::acc_t (&acc)[4], const T* M, int ld, int r0, int c0, int w, int l)
-{
-    constexpr bool f64 = sizeof(T) == 8;
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            acc[C][v] = M[cpr<T>(r0 + out_row(w, l, v, f64), c0 + 16 * C + (l & 15), ld)];
+            acc[C][v] = M[cpr<T>(r0 + out_row<T>(w, l, v), c0 + 16 * C + (l & 15), ld)];
 }
 
 template <typename T>
-__device__ inline void store_acc(const typename Frag<T>::acc_t (&acc)[4], T* M, int ld, int r0, int c0, int w, int l)
+__device__ inline void store_acc(const typename Frag<T>::acc_t (&acc)[4], T* M, int ld, int r0, int c0,
+                                 int w, int l)
 {
-    constexpr bool f64 = sizeof(T) == 8;
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            M[cpr<T>(r0 + out_row(w, l, v, f64), c0 + 16 * C + (l & 15), ld)] = acc[C][v];
+            M[cpr<T>(r0 + out_row<T>(w, l, v), c0 + 16 * C + (l & 15), ld)] = acc[C][v];
 }
 
-// In-place Gauss-Jordan inverse of the 64x64 SPD tile held in acc (C layout);
-// result written row-major CPR to Pout.  Raises kErrPivot on a bad pivot.
+// Gauss-Jordan inverse of the 64x64 SPD tile held in acc (MFMA output layout),
+// written row-major CPR to Pout.  Thread t keeps row t/4, columns 16(t%4)..+15
+// in registers; the pivot row (with the pivot's reciprocal) and the pivot
+// column go through double-buffered LDS, one barrier per pivot, and every
+// thread updates its 16 entries without branches.  A pivot that is not
+// positive and finite raises kErrPivot.
 template <typename T>
-__device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* sP, T* Pout, int* flags, int w, int l)
+__device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* Pout, int* flags,
+                            int w, int l)
 {
-    constexpr bool f64 = sizeof(T) == 8;
+    using v4 = typename std::conditional<sizeof(T) == 8, d4_t, f4_t>::type;
+    T* sP = lds;                         // [64][kLd] staging of the tile
+    T* rowb = lds + kTile * kLd;         // [2][64]
+    T* colb = rowb + 2 * kTile;          // [2][64]
     __syncthreads();
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sP[out_row(w, l, v, f64) * kLdP + 16 * C + (l & 15)] = acc[C][v];
+        for (int v = 0; v < 4; ++v) sP[out_row<T>(w, l, v) * kLd + 16 * C + (l & 15)] = acc[C][v];
     __syncthreads();
-    const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 16;
+    const int r = threadIdx.x >> 2, cbk = threadIdx.x & 3, c0 = cbk * 16;
+    T a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = sP[r * kLd + c0 + c];
     bool bad = false;
     for (int p = 0; p < kTile; ++p) {
-        const T d = sP[p * kLdP + p];
-        const T arp = sP[r * kLdP + p];
-        T prow[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) prow[c] = sP[p * kLdP + c0 + c];
-        __syncthreads();
-        bad |= !(d > (T)0) || !isfinite(d);
-        const T inv = (T)1 / d;
+        T* rb = rowb + (p & 1) * kTile;
+        T* cb = colb + (p & 1) * kTile;
         if (r == p) {
 #pragma unroll
-            for (int c = 0; c < 16; ++c) sP[p * kLdP + c0 + c] = (c0 + c == p) ? inv : prow[c] * inv;
-        } else {
-            const T f = arp * inv;
+            for (int c = 0; c < 16; ++c) rb[c0 + c] = a[c];
+        }
+        if ((p >> 4) == cbk) {
+            T v = a[0];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                T* x = &sP[r * kLdP + c0 + c];
-                *x = (c0 + c == p) ? -f : *x - f * prow[c];
-            }
+            for (int c = 1; c < 16; ++c) v = ((p & 15) == c) ? a[c] : v;
+            cb[r] = v;
         }
         __syncthreads();
+        T pr[16];
+#pragma unroll
+        for (int c = 0; c < 16; c += 4) {
+            const v4 x = *reinterpret_cast<const v4*>(rb + c0 + c);
+            pr[c] = x[0]; pr[c + 1] = x[1]; pr[c + 2] = x[2]; pr[c + 3] = x[3];
+        }
+        const T d = rb[p];
+        const T cr = cb[r];
+        bad |= !(d > (T)0) || !isfinite(d);
+        const T inv = (T)1 / d;
+        const bool is_p = (r == p);
+        const T f = cr * inv;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const T upd = a[c] - f * pr[c];
+            const T scl = a[c] * inv;
+            T x = is_p ? scl : upd;
+            if (c0 + c == p) x = is_p ? inv : -f;
+            a[c] = x;
+        }
     }
     if (bad) atomicOr(flags + kErrPivot, 1);
-    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-        const int rr = e / kTile, cc = e % kTile;
-        Pout[cpr<T>(rr, cc, kTile)] = sP[rr * kLdP + cc];
-    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Pout[cpr<T>(r, c0 + c, kTile)] = a[c];
 }
 
-// S_t(r, c) for block t: E_t - g^2 H_{t-1} on the n x n part, identity on the padding.
+// Pivot block of a row: E_row - g^2 (H_a + H_b) on the n x n part (a, b < 0: absent),
+// identity on the padding.
 template <typename T>
-__device__ inline T form_S(T e, T h, double g2, int r, int c, int n)
+__device__ inline T form_elem(const T* E, const T* Ha, const T* Hb, int64_t off, double g2, int r, int c, int n)
 {
-    if (r < n && c < n) return e - (T)g2 * h;
-    return (r == c) ? (T)1 : (T)0;
+    if (r >= n || c >= n) return (r == c) ? (T)1 : (T)0;
+    T s = E[off];
+    if (Ha) s -= (T)g2 * Ha[off];
+    if (Hb) s -= (T)g2 * Hb[off];
+    return s;
 }
 
-// Chain step 0: S_0 = E_0 (identity padding) into S[0]; pivot tile (0,0) inverted into P[0].
 template <typename T>
-__global__ __launch_bounds__(256) void gj_init_kernel(GJArgs a)
+__device__ inline const T* slot_ptr(const GJArgs& a, int row)
 {
-    __shared__ T sP[kTile * kLdP];
-    const int I = blockIdx.x / a.nb, J = blockIdx.x % a.nb;
+    return row < 0 ? nullptr : reinterpret_cast<const T*>(a.H) + (int64_t)row * a.n_p * a.n_p;
+}
+
+// Form the first pivot block of each job (chain start or twist) into its S[0] and
+// invert its pivot tile (0,0) into its P[0].
+template <typename T>
+__global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
+{
+    __shared__ __align__(32) T lds[kTile * kLd + 4 * kTile];
+    const int tiles = a.nb * a.nb;
+    const GJJob& job = a.job[blockIdx.x / tiles];
+    const int I = (blockIdx.x % tiles) / a.nb, J = blockIdx.x % a.nb;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const T* E0 = reinterpret_cast<const T*>(a.H);
-    T* S = reinterpret_cast<T*>(a.S0);
+    const T* E = slot_ptr<T>(a, job.row);
+    const T* Ha = slot_ptr<T>(a, job.dep_a);
+    const T* Hb = slot_ptr<T>(a, job.dep_b);
     typename Frag<T>::acc_t acc[4];
-    load_acc<T>(acc, E0, a.n_p, 64 * I, 64 * J, w, l);
-    constexpr bool f64 = sizeof(T) == 8;
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            acc[C][v] = form_S<T>(acc[C][v], (T)0, 0.0, 64 * I + out_row(w, l, v, f64),
-                                  64 * J + 16 * C + (l & 15), a.n);
-    store_acc<T>(acc, S, a.n_p, 64 * I, 64 * J, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, sP, reinterpret_cast<T*>(a.P0), a.flags, w, l);
+        for (int v = 0; v < 4; ++v) {
+            const int rr = 64 * I + out_row<T>(w, l, v), cc = 64 * J + 16 * C + (l & 15);
+            acc[C][v] = form_elem<T>(E, Ha, Hb, cpr<T>(rr, cc, a.n_p), a.g2, rr, cc, a.n);
+        }
+    store_acc<T>(acc, reinterpret_cast<T*>(job.S[0]), a.n_p, 64 * I, 64 * J, w, l);
+    if (I == 0 && J == 0) invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, w, l);
 }
 
-// Pivot block k of chain step t.  g = t*nb + k selects the ping-pong buffers.
+// Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
 template <typename T>
-__global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int t, int k)
+__global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
 {
-    __shared__ T sA[kTile * kLd];
-    __shared__ T sB[kTile * kLd];
-    const int nb = a.nb, n_p = a.n_p;
-    const int I = blockIdx.x / nb, J = blockIdx.x % nb;
+    __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
+    __shared__ __align__(32) T sB[kTile * kLd];
+    const int nb = a.nb, n_p = a.n_p, tiles = nb * nb;
+    const GJJob& job = a.job[blockIdx.x / tiles];
+    const int I = (blockIdx.x % tiles) / nb, J = blockIdx.x % nb;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int64_t g = (int64_t)t * nb + k;
-    const T* Sin = reinterpret_cast<const T*>((g & 1) ? a.S1 : a.S0);
-    T* Sout = reinterpret_cast<T*>((g & 1) ? a.S0 : a.S1);
-    const T* Pin = reinterpret_cast<const T*>((g & 1) ? a.P1 : a.P0);
-    T* Pout = reinterpret_cast<T*>((g & 1) ? a.P0 : a.P1);
-    const bool last = (k == nb - 1);
+    const int par = (int)(((int64_t)step * nb + k) & 1);
+    const T* Sin = reinterpret_cast<const T*>(job.S[par]);
+    T* Sout = reinterpret_cast<T*>(job.S[par ^ 1]);
+    const T* Pin = reinterpret_cast<const T*>(job.P[par]);
+    T* Pout = reinterpret_cast<T*>(job.P[par ^ 1]);
     using acc_t = typename Frag<T>::acc_t;
     acc_t acc[4];
 #pragma unroll
     for (int C = 0; C < 4; ++C) acc[C] = acc_t{0, 0, 0, 0};
 
     const int r0 = 64 * I, c0 = 64 * J, pk = 64 * k;
+    T v0[kPer], v1[kPer], v2[kPer];
     if (I != k && J != k) {
-        stage_A<T>(sA, Pin, kTile, 0, 0, (T)1);
-        stage_B<T>(sB, Sin, n_p, pk, c0);
+        fetch_tile<T>(v0, Pin, kTile, 0, 0);
+        fetch_tile<T>(v1, Sin, n_p, pk, c0);
+        fetch_tile<T>(v2, Sin, n_p, r0, pk);
+        load_acc<T>(acc, Sin, n_p, r0, c0, w, l);
+        put_A<T>(sA, v0, (T)1);
+        put_B<T>(sB, v1);
         __syncthreads();
-        tile_mma<T>(acc, sA, sB, w, l);                 // X = P^{-1} S[k][J]
+        acc_t x[4];
+#pragma unroll
+        for (int C = 0; C < 4; ++C) x[C] = acc_t{0, 0, 0, 0};
+        tile_mma<T>(x, sA, sB, w, l);                   // X = P^{-1} S[k][J]
         __syncthreads();
-        constexpr bool f64 = sizeof(T) == 8;
 #pragma unroll
         for (int C = 0; C < 4; ++C)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {               // X as the next B operand: sB[col][slot(k)]
-                const int kk = out_row(w, l, v, f64);
-                sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = acc[C][v];
+            for (int v = 0; v < 4; ++v) {               // X becomes the next B operand
+                const int kk = out_row<T>(w, l, v);
+                sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = x[C][v];
             }
-        stage_A<T>(sA, Sin, n_p, r0, pk, (T)-1);
-        load_acc<T>(acc, Sin, n_p, r0, c0, w, l);
+        put_A<T>(sA, v2, (T)-1);
         __syncthreads();
         tile_mma<T>(acc, sA, sB, w, l);                 // S[I][J] - S[I][k] X
     } else if (I == k && J != k) {
-        stage_A<T>(sA, Pin, kTile, 0, 0, (T)1);
-        stage_B<T>(sB, Sin, n_p, pk, c0);
+        fetch_tile<T>(v0, Pin, kTile, 0, 0);
+        fetch_tile<T>(v1, Sin, n_p, pk, c0);
+        put_A<T>(sA, v0, (T)1);
+        put_B<T>(sB, v1);
         __syncthreads();
         tile_mma<T>(acc, sA, sB, w, l);                 // P^{-1} S[k][J]
     } else if (I != k && J == k) {
-        stage_A<T>(sA, Sin, n_p, r0, pk, (T)-1);
-        stage_B<T>(sB, Pin, kTile, 0, 0);
+        fetch_tile<T>(v2, Sin, n_p, r0, pk);
+        fetch_tile<T>(v0, Pin, kTile, 0, 0);
+        put_A<T>(sA, v2, (T)-1);
+        put_B<T>(sB, v0);
         __syncthreads();
         tile_mma<T>(acc, sA, sB, w, l);                 // -S[I][k] P^{-1}
     } else {
         load_acc<T>(acc, Pin, kTile, 0, 0, w, l);       // P^{-1}
     }
 
-    T* sP = sA;   // operand tiles are dead from here on; reuse for the pivot inversion
-    if (!last) {
+    if (k != nb - 1) {
         store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-        if (I == k + 1 && J == k + 1) invert_tile<T>(acc, sP, Pout, a.flags, w, l);
+        if (I == k + 1 && J == k + 1) invert_tile<T>(acc, sA, Pout, a.flags, w, l);
         return;
     }
-    // Last pivot block: acc holds H_t[I][J].  Store it over E_t, then form S_{t+1}.
-    T* Ht = reinterpret_cast<T*>(a.H) + (int64_t)t * n_p * n_p;
-    store_acc<T>(acc, Ht, n_p, r0, c0, w, l);
-    if (t + 1 >= a.m) return;
-    const T* En = Ht + (int64_t)n_p * n_p;
-    constexpr bool f64 = sizeof(T) == 8;
+    // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
+    // chain's next pivot block E_next - g^2 H_row.
+    T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
+    store_acc<T>(acc, Hr, n_p, r0, c0, w, l);
+    if (job.next < 0) return;
+    const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)job.next * n_p * n_p;
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rr = r0 + out_row(w, l, v, f64), cc = c0 + 16 * C + (l & 15);
-            acc[C][v] = form_S<T>(En[cpr<T>(rr, cc, n_p)], acc[C][v], a.g2, rr, cc, a.n);
+            const int rr = r0 + out_row<T>(w, l, v), cc = c0 + 16 * C + (l & 15);
+            const T e = En[cpr<T>(rr, cc, n_p)];
+            acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
         }
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, sP, Pout, a.flags, w, l);
+    if (I == 0 && J == 0) invert_tile<T>(acc, sA, Pout, a.flags, w, l);
 }
 
 template <typename T>
-hipError_t launch_factor(const GJArgs& a, hipStream_t s)
+hipError_t launch_factor(GJArgs a, hipStream_t s)
 {
-    const int tiles = a.nb * a.nb;
-    hipLaunchKernelGGL(gj_init_kernel<T>, dim3(tiles), dim3(256), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    for (int t = 0; t < a.m; ++t)
-        for (int k = 0; k < a.nb; ++k) {
-            hipLaunchKernelGGL(gj_step_kernel<T>, dim3(tiles), dim3(256), 0, s, a, t, k);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
+    const int m = a.m, kt = m / 2, nb = a.nb, tiles = nb * nb;
+    const int top_len = kt, bot_len = m - 1 - kt;
+    GJJob top = a.job[0], bot = a.job[1];    // buffers provided by the caller
+    hipError_t e;
+    // chain starts: S_0 = E_0 (top), S'_{m-1} = E_{m-1} (bottom)
+    {
+        GJArgs f = a;
+        int nj = 0;
+        if (top_len > 0) { f.job[nj] = top; f.job[nj].row = 0; f.job[nj].dep_a = f.job[nj].dep_b = -1; ++nj; }
+        if (bot_len > 0) { f.job[nj] = bot; f.job[nj].row = m - 1; f.job[nj].dep_a = f.job[nj].dep_b = -1; ++nj; }
+        if (nj > 0) {
+            hipLaunchKernelGGL(gj_form_kernel<T>, dim3(nj * tiles), dim3(256), 0, s, f);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
         }
+    }
+    const int steps = top_len > bot_len ? top_len : bot_len;
+    for (int st = 0; st < steps; ++st) {
+        GJArgs f = a;
+        int nj = 0;
+        if (st < top_len) {
+            f.job[nj] = top;
+            f.job[nj].row = st;
+            f.job[nj].next = (st + 1 < kt) ? st + 1 : -1;
+            ++nj;
+        }
+        if (st < bot_len) {
+            f.job[nj] = bot;
+            f.job[nj].row = m - 1 - st;
+            f.job[nj].next = (m - 2 - st > kt) ? m - 2 - st : -1;
+            ++nj;
+        }
+        for (int k = 0; k < nb; ++k) {
+            hipLaunchKernelGGL(gj_step_kernel<T>, dim3(nj * tiles), dim3(256), 0, s, f, st, k);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    // twist block K = E_kt - g^2 (H_{kt-1} + H'_{kt+1})
+    GJArgs f = a;
+    f.job[0] = top;
+    f.job[0].row = kt;
+    f.job[0].dep_a = (kt >= 1) ? kt - 1 : -1;
+    f.job[0].dep_b = (kt + 1 <= m - 1) ? kt + 1 : -1;
+    f.job[0].next = -1;
+    hipLaunchKernelGGL(gj_form_kernel<T>, dim3(tiles), dim3(256), 0, s, f);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int k = 0; k < nb; ++k) {
+        hipLaunchKernelGGL(gj_step_kernel<T>, dim3(tiles), dim3(256), 0, s, f, 0, k);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 

@@ -1,13 +1,13 @@
 // Forward and back substitution over the row blocks (Sec. II.C: L y = I then
-// U v = y, for every input vector of a batch, Sec. III.A/III.D), and the
-// recovery of the word-line voltages and output currents.
-//
-// With H_i = S_i^{-1} from the block LU, the condensed bit-line voltages are
-//   forward:  y_0 = V_0 c_0,  z_i = H_i y_i,  y_{i+1} = V_{i+1} c_{i+1} + g_bl z_i
-//   back:     u_{m-1} = z_{m-1},  u_i = z_i + g_bl H_i u_{i+1}
-// and the word-line voltages of row i follow from its tridiagonal block:
-//   T_i w_i = g_src V_i e_0 + Gam_i u_i.
-// Output currents are I_j = g_sense u_{m-1, j} (current into the termination).
+// U v = y, for every input vector of a batch, Sec. III.A/III.D), in the
+// twisted order of the factorization (top chain rows 0..kt-1, bottom chain
+// rows m-1..kt+1, twist row kt = m/2), with H_i the stored pivot inverses:
+//   forward, top:    y_0 = f_0,        z_i = H_i y_i,  y_{i+1} = f_{i+1} + g_bl z_i
+//   forward, bottom: y_{m-1} = f_{m-1}, z_i = H_i y_i,  y_{i-1} = f_{i-1} + g_bl z_i
+//   twist:           u_kt = H_kt (f_kt + g_bl z_{kt-1} + g_bl z_{kt+1})
+//   back, up:        u_i = z_i + g_bl H_i u_{i+1}   (i = kt-1 .. 0)
+//   back, down:      u_i = z_i + g_bl H_i u_{i-1}   (i = kt+1 .. m-1)
+// with f_i = V_i c_i.  Output currents are I_j = g_sense u_{m-1, j}.
 //
 // Input vectors are independent, so each workgroup owns a slab of 16 of
 // them for the whole sweep: no grid synchronisation at all.  Per row block
@@ -32,9 +32,12 @@ __device__ inline void panel_product(typename Frag<T>::acc_t (&acc)[NT], const T
                                      const T* ybuf, int ldy, int w, int l)
 {
     using v4 = typename Vec4<T>::type;
+    using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT;
     constexpr int KC = n_p / 16;
     const int q = l >> 4, r = l & 15;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
     const T* rowp[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) rowp[t] = Hi + (int64_t)(16 * (NT * w + t) + r) * n_p + 4 * q;
@@ -48,10 +51,9 @@ __device__ inline void panel_product(typename Frag<T>::acc_t (&acc)[NT], const T
         }
         const v4 bv = *reinterpret_cast<const v4*>(ybuf + r * ldy + 16 * K + 4 * q);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc[t] = Frag<T>::mma(cur[t][s], bv[s], acc[t]);
-        }
+            for (int t = 0; t < NT; ++t) acc[t] = Frag<T>::mma(cur[t][s], bv[s], acc[t]);
         if (K + 1 < KC) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
@@ -60,94 +62,142 @@ __device__ inline void panel_product(typename Frag<T>::acc_t (&acc)[NT], const T
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void sweep_kernel(SweepArgs a)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* ybuf = reinterpret_cast<T*>(smem_raw);
-    constexpr int n_p = 64 * NT;
-    constexpr int ldy = n_p + 4;
-    constexpr bool f64 = sizeof(T) == 8;
+struct SweepCtx {
     using acc_t = typename Frag<T>::acc_t;
-    const int m = a.m, n = a.n;
-    const int slab = blockIdx.x;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, col = l & 15;
-    const int b = 16 * slab + col;
-    const bool bval = b < a.B;
-    const T g = (T)a.g_bl;
-    T* Zs = reinterpret_cast<T*>(a.Z) + (int64_t)slab * m * 16 * n_p;
-    const T* H = reinterpret_cast<const T*>(a.H);
+    static constexpr int n_p = 64 * NT;
+    static constexpr int ldy = n_p + 4;
+    const SweepArgs& a;
+    T* ybuf;
+    T* Zs;
+    const T* H;
+    int w, l, q, col, b;
+    bool bval;
+    T g;
 
-    auto row_of = [&](int t, int v) { return 16 * (NT * w + t) + (f64 ? (q + 4 * v) : (4 * q + v)); };
+    __device__ int row_of(int t, int v) const { return 16 * (NT * w + t) + Frag<T>::drow(q, v); }
+    __device__ T* zrow(int i) const { return Zs + (int64_t)i * 16 * n_p + col * n_p; }
+    __device__ double vin(int i) const { return bval ? a.V[(int64_t)b * a.m + i] : 0.0; }
 
-    acc_t acc[NT];
-    // y_0 = V_0 c_0
-    {
-        const double vb = bval ? a.V[(int64_t)b * m] : 0.0;
+    // panel <- f_i + g * (sum of the given z rows); every lane fills the entries it owns
+    __device__ void set_panel(int i, const acc_t (&zacc)[NT], bool with_acc, int zrow_a, int zrow_b) {
+        const double vb = vin(i);
+        const double* ci = a.c + (int64_t)i * n_p;
+        __syncthreads();
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int k = row_of(t, v);
-                ybuf[col * ldy + pos<T>(k)] = (T)(a.c[k] * vb);
+                T y = (T)(ci[k] * vb);
+                if (with_acc) y += g * zacc[t][v];
+                if (zrow_a >= 0) y += g * zrow(zrow_a)[pos<T>(k)];
+                if (zrow_b >= 0) y += g * zrow(zrow_b)[pos<T>(k)];
+                ybuf[col * ldy + pos<T>(k)] = y;
             }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = 0; i < m; ++i) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
-        panel_product<T, NT>(acc, H + (int64_t)i * n_p * n_p, ybuf, ldy, w, l);
-        T* Zi = Zs + (int64_t)i * 16 * n_p + col * n_p;
+    __device__ void put_panel(const acc_t (&u)[NT]) {
+        __syncthreads();
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Zi[pos<T>(row_of(t, v))] = acc[t][v];
-        if (i + 1 < m) {
-            const double vb = bval ? a.V[(int64_t)b * m + i + 1] : 0.0;
-            const double* ci = a.c + (int64_t)(i + 1) * n_p;
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int k = row_of(t, v);
-                    ybuf[col * ldy + pos<T>(k)] = (T)(ci[k] * vb) + g * acc[t][v];
-                }
-            __syncthreads();
-        }
+            for (int v = 0; v < 4; ++v) ybuf[col * ldy + pos<T>(row_of(t, v))] = u[t][v];
+        __syncthreads();
     }
-    // u_{m-1} = z_{m-1}: output currents
+    __device__ void store_z(int i, const acc_t (&z)[NT]) {
+        T* zr = zrow(i);
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int k = row_of(t, v);
-            if (bval && k < n) a.Iout[(int64_t)b * n + k] = a.g_sense * (double)acc[t][v];
-        }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) ybuf[col * ldy + pos<T>(row_of(t, v))] = acc[t][v];
-    __syncthreads();
-    for (int i = m - 2; i >= 0; --i) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
-        panel_product<T, NT>(acc, H + (int64_t)i * n_p * n_p, ybuf, ldy, w, l);
-        T* Zi = Zs + (int64_t)i * 16 * n_p + col * n_p;
+            for (int v = 0; v < 4; ++v) zr[pos<T>(row_of(t, v))] = z[t][v];
+    }
+    // acc <- z_i + g * acc, written back over z_i
+    __device__ void finish_back(int i, acc_t (&acc)[NT]) {
+        T* zr = zrow(i);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int p = pos<T>(row_of(t, v));
-                acc[t][v] = Zi[p] + g * acc[t][v];       // u_i = z_i + g H_i u_{i+1}
-                Zi[p] = acc[t][v];
+                acc[t][v] = zr[p] + g * acc[t][v];
+                zr[p] = acc[t][v];
             }
-        __syncthreads();
+    }
+    __device__ void currents(const acc_t (&u)[NT]) {
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ybuf[col * ldy + pos<T>(row_of(t, v))] = acc[t][v];
-        __syncthreads();
+            for (int v = 0; v < 4; ++v) {
+                const int k = row_of(t, v);
+                if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * (double)u[t][v];
+            }
+    }
+};
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void sweep_kernel(SweepArgs a)
+{
+    extern __shared__ __align__(32) unsigned char smem_raw[];
+    using acc_t = typename Frag<T>::acc_t;
+    using Ctx = SweepCtx<T, NT>;
+    const int m = a.m, kt = m / 2;
+    const int l = threadIdx.x & 63;
+    Ctx x{a, reinterpret_cast<T*>(smem_raw),
+          reinterpret_cast<T*>(a.Z) + (int64_t)blockIdx.x * m * 16 * Ctx::n_p,
+          reinterpret_cast<const T*>(a.H), (int)(threadIdx.x >> 6), l, l >> 4, l & 15,
+          16 * (int)blockIdx.x + (l & 15), false, (T)a.g_bl};
+    x.bval = x.b < a.B;
+    const int64_t blk = (int64_t)Ctx::n_p * Ctx::n_p;
+    acc_t acc[NT];
+    // forward, top chain
+    if (kt > 0) {
+        x.set_panel(0, acc, false, -1, -1);
+        for (int i = 0; i < kt; ++i) {
+            panel_product<T, NT>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
+            x.store_z(i, acc);
+            if (i + 1 < kt) x.set_panel(i + 1, acc, true, -1, -1);
+        }
+    }
+    // forward, bottom chain
+    if (m - 1 > kt) {
+        x.set_panel(m - 1, acc, false, -1, -1);
+        for (int i = m - 1; i > kt; --i) {
+            panel_product<T, NT>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
+            x.store_z(i, acc);
+            if (i - 1 > kt) x.set_panel(i - 1, acc, true, -1, -1);
+        }
+    }
+    // twist row
+    x.set_panel(kt, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
+    panel_product<T, NT>(acc, x.H + kt * blk, x.ybuf, Ctx::ldy, x.w, l);
+    x.store_z(kt, acc);
+    if (kt == m - 1) x.currents(acc);
+    // back, upward
+    if (kt > 0) {
+        x.put_panel(acc);
+        for (int i = kt - 1; i >= 0; --i) {
+            acc_t u[NT];
+            panel_product<T, NT>(u, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
+            x.finish_back(i, u);
+            if (i > 0) x.put_panel(u);
+        }
+    }
+    // back, downward
+    if (kt + 1 < m) {
+        {
+            const T* zr = x.zrow(kt);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[t][v] = zr[pos<T>(x.row_of(t, v))];
+        }
+        x.put_panel(acc);
+        for (int i = kt + 1; i < m; ++i) {
+            panel_product<T, NT>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
+            x.finish_back(i, acc);
+            if (i == m - 1) x.currents(acc);
+            else x.put_panel(acc);
+        }
     }
 }
 

@@ -21,11 +21,18 @@ struct Buffers {
     double* ip = nullptr;     // [m][n]
     double* q = nullptr;      // [m][n]
     double* Gc = nullptr;     // [m][n]
-    void* S[2] = {nullptr, nullptr};
-    void* P[2] = {nullptr, nullptr};
+    void* S[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [chain][parity]
+    void* P[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* Z = nullptr;        // [nslab][m][16][n_p]
     double* Iout = nullptr;   // [max_batch][n]
     int* flags = nullptr;     // [kNumFlags]
+    // Newton-Schulz factor: per chain S, X[2], Q ([n_p][n_p]) and dprev ([n_p])
+    void* ns_S[2] = {nullptr, nullptr};
+    void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    void* ns_Q[2] = {nullptr, nullptr};
+    double* ns_dprev[2] = {nullptr, nullptr};
+    unsigned long long* ns_norm = nullptr;   // [m][kNsMaxIterTwist]
+    int* ns_done = nullptr;                  // [m]
 };
 
 __global__ void clear_flags_kernel(int* f)
@@ -93,6 +100,8 @@ struct xbar_plan_s {
     int32_t last_B = 0;
     Buffers d;
     bool timing = false;
+    int32_t factor_method = XBAR_FACTOR_AUTO;
+    int64_t gj_fallbacks = 0;
     PhaseTimer t_condense, t_factor, t_sweep, t_recover;
     bool fp32() const { return prec != XBAR_FP64; }
     size_t elem() const { return fp32() ? sizeof(float) : sizeof(double); }
@@ -115,13 +124,18 @@ xbar_status dev_alloc(xbar_plan p, void** ptr, int64_t bytes)
 void free_all(xbar_plan p)
 {
     Buffers& d = p->d;
-    void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0], d.S[1], d.P[0], d.P[1], d.Z, d.Iout, d.flags};
+    void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
+                   d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags,
+                   d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
+                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_norm, d.ns_done};
     for (void* x : all)
         if (x) (void)hipFree(x);
     d = Buffers{};
 }
 
 bool set_device(xbar_plan p) { return hipSetDevice(p->device) == hipSuccess; }
+
+xbk::CondenseArgs condense_args(xbar_plan p, const double* G);
 
 }  // namespace
 
@@ -190,13 +204,23 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     A((void**)&d.ip, m * n * 8);
     A((void**)&d.q, m * n * 8);
     A((void**)&d.Gc, m * n * 8);
-    A(&d.S[0], n_p * n_p * es);
-    A(&d.S[1], n_p * n_p * es);
-    A(&d.P[0], 64 * 64 * es);
-    A(&d.P[1], 64 * 64 * es);
+    for (int c = 0; c < 2; ++c)
+        for (int k = 0; k < 2; ++k) {
+            A(&d.S[c][k], n_p * n_p * es);
+            A(&d.P[c][k], 64 * 64 * es);
+        }
     A(&d.Z, (int64_t)p->nslab_max * m * 16 * n_p * es);
     A((void**)&d.Iout, (int64_t)max_batch * n * 8);
     A((void**)&d.flags, xbk::kNumFlags * sizeof(int));
+    for (int c = 0; c < 2; ++c) {
+        A(&d.ns_S[c], n_p * n_p * es);
+        A(&d.ns_X[c][0], n_p * n_p * es);
+        A(&d.ns_X[c][1], n_p * n_p * es);
+        A(&d.ns_Q[c], n_p * n_p * es);
+        A((void**)&d.ns_dprev[c], n_p * 8);
+    }
+    A((void**)&d.ns_norm, m * xbk::kNsMaxIterTwist * 8);
+    A((void**)&d.ns_done, m * 4);
     if (st != XBAR_OK) {
         free_all(p);
         delete p;
@@ -217,6 +241,20 @@ xbar_status xbar_assemble(xbar_plan p, const double* G)
     if (p == nullptr || G == nullptr) return XBAR_ERR_ARG;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
     hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, p->stream, p->d.flags);
+    const xbk::CondenseArgs a = condense_args(p, G);
+    if (p->timing && !p->t_condense.begin(p->stream)) return XBAR_ERR_DEVICE;
+    if (xbk_launch_condense(a, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (p->timing && !p->t_condense.end(p->stream)) return XBAR_ERR_DEVICE;
+    p->state = kAssembled;
+    return XBAR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+xbk::CondenseArgs condense_args(xbar_plan p, const double* G)
+{
     xbk::CondenseArgs a{};
     a.G = G;
     a.m = p->g.m;
@@ -233,18 +271,11 @@ xbar_status xbar_assemble(xbar_plan p, const double* G)
     a.q = p->d.q;
     a.Gc = p->d.Gc;
     a.flags = p->d.flags;
-    if (p->timing && !p->t_condense.begin(p->stream)) return XBAR_ERR_DEVICE;
-    if (xbk_launch_condense(a, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
-    if (p->timing && !p->t_condense.end(p->stream)) return XBAR_ERR_DEVICE;
-    p->state = kAssembled;
-    return XBAR_OK;
+    return a;
 }
 
-xbar_status xbar_factor(xbar_plan p)
+hipError_t launch_gj(xbar_plan p)
 {
-    if (p == nullptr) return XBAR_ERR_ARG;
-    if (p->state != kAssembled) return XBAR_ERR_STATE;
-    if (!set_device(p)) return XBAR_ERR_DEVICE;
     xbk::GJArgs a{};
     a.m = p->g.m;
     a.n = p->g.n;
@@ -253,13 +284,83 @@ xbar_status xbar_factor(xbar_plan p)
     const double gb = 1.0 / p->g.r_bl;
     a.g2 = gb * gb;
     a.H = p->d.H;
-    a.S0 = p->d.S[0];
-    a.S1 = p->d.S[1];
-    a.P0 = p->d.P[0];
-    a.P1 = p->d.P[1];
+    for (int c = 0; c < 2; ++c) {
+        a.job[c].row = a.job[c].next = a.job[c].dep_a = a.job[c].dep_b = -1;
+        for (int k = 0; k < 2; ++k) {
+            a.job[c].S[k] = p->d.S[c][k];
+            a.job[c].P[k] = p->d.P[c][k];
+        }
+    }
     a.flags = p->d.flags;
+    return xbk_launch_factor(a, p->fp32(), p->stream);
+}
+
+hipError_t launch_ns(xbar_plan p)
+{
+    xbk::NSArgs a{};
+    a.m = p->g.m;
+    a.n = p->g.n;
+    a.n_p = p->n_p;
+    const double gb = 1.0 / p->g.r_bl;
+    a.g2 = gb * gb;
+    a.H = p->d.H;
+    for (int c = 0; c < 2; ++c) {
+        a.ch[c].S = p->d.ns_S[c];
+        a.ch[c].X[0] = p->d.ns_X[c][0];
+        a.ch[c].X[1] = p->d.ns_X[c][1];
+        a.ch[c].Q = p->d.ns_Q[c];
+        a.ch[c].dprev = p->d.ns_dprev[c];
+    }
+    a.norm = p->d.ns_norm;
+    a.done = p->d.ns_done;
+    a.flags = p->d.flags;
+    a.max_iter = xbk::kNsMaxIter;
+    return xbk_launch_factor_ns(a, p->fp32(), p->stream);
+}
+
+__global__ void clear_flag_kernel(int* f, int which) { f[which] = 0; }
+
+}  // namespace
+
+extern "C" {
+
+xbar_status xbar_set_factor_method(xbar_plan p, xbar_factor_method method)
+{
+    if (p == nullptr) return XBAR_ERR_ARG;
+    if (method != XBAR_FACTOR_AUTO && method != XBAR_FACTOR_GJ && method != XBAR_FACTOR_NS)
+        return XBAR_ERR_ARG;
+    p->factor_method = method;
+    return XBAR_OK;
+}
+
+xbar_status xbar_factor(xbar_plan p)
+{
+    if (p == nullptr) return XBAR_ERR_ARG;
+    if (p->state != kAssembled) return XBAR_ERR_STATE;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
     if (p->timing && !p->t_factor.begin(p->stream)) return XBAR_ERR_DEVICE;
-    if (xbk_launch_factor(a, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (p->factor_method == XBAR_FACTOR_GJ) {
+        if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
+    } else {
+        if (launch_ns(p) != hipSuccess) return XBAR_ERR_DEVICE;
+        if (p->factor_method == XBAR_FACTOR_AUTO) {
+            int failed = 0;
+            if (hipMemcpyAsync(&failed, p->d.flags + xbk::kNsFail, sizeof(int), hipMemcpyDeviceToHost,
+                               p->stream) != hipSuccess ||
+                hipStreamSynchronize(p->stream) != hipSuccess)
+                return XBAR_ERR_DEVICE;
+            if (failed) {
+                // Redo the factorization by Gauss-Jordan elimination: rebuild E from the
+                // plan's copy of G (the Newton-Schulz pass consumed part of it).
+                hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
+                                   (int)xbk::kNsFail);
+                if (xbk_launch_condense(condense_args(p, p->d.Gc), p->fp32(), p->stream) != hipSuccess)
+                    return XBAR_ERR_DEVICE;
+                if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
+                p->gj_fallbacks++;
+            }
+        }
+    }
     if (p->timing && !p->t_factor.end(p->stream)) return XBAR_ERR_DEVICE;
     p->state = kFactored;
     return XBAR_OK;

@@ -9,8 +9,8 @@ import pytest
 from paper_2410_19993_amd import _lib
 
 EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor",
-            "xbar_get_info", "xbar_get_timing", "xbar_set_timing", "xbar_solve_batch",
-            "xbar_status_string"]
+            "xbar_get_info", "xbar_get_timing", "xbar_set_factor_method", "xbar_set_timing",
+            "xbar_solve_batch", "xbar_status_string"]
 
 
 def _gpu_visible():
@@ -86,6 +86,7 @@ def test_null_plan_calls():
     assert L.xbar_get_info(None, ctypes.byref(info)) == _lib.XBAR_ERR_ARG
     assert L.xbar_destroy(None) == _lib.XBAR_OK
     assert L.xbar_set_timing(None, 1) == _lib.XBAR_ERR_ARG
+    assert L.xbar_set_factor_method(None, 0) == _lib.XBAR_ERR_ARG
     assert L.xbar_get_timing(None, ctypes.byref(_lib.Timing()), 0) == _lib.XBAR_ERR_ARG
 
 

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _check_against_oracle(wl, precision="fp64", tol=TOL_FP64, **kw):
-    log(f"case {wl.name} precision={precision}")
+    log(f"case {wl.name} precision={precision} {kw}")
     I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, precision, **kw)
     assert st == 0, f"device status {st}"
     ref = oracle.solve_workload(wl)
@@ -32,17 +32,30 @@ def _check_against_oracle(wl, precision="fp64", tol=TOL_FP64, **kw):
     return I, nv, ref
 
 
-def test_c1_full():
-    _check_against_oracle(workloads.c1())
+@pytest.mark.parametrize("method", ["auto", "gj", "ns"])
+def test_c1_full(method):
+    _check_against_oracle(workloads.c1(), factor_method=method)
 
 
+@pytest.mark.parametrize("method", ["gj", "ns"])
 @pytest.mark.parametrize("m,n,B,seed", [
     (1, 1, 1, 1), (1, 7, 3, 2), (9, 1, 5, 3), (2, 2, 16, 4), (3, 70, 17, 5), (65, 64, 33, 6),
     (7, 129, 15, 7), (10, 200, 20, 8), (4, 512, 2, 9), (33, 40, 48, 10)])
-def test_ragged_shapes(m, n, B, seed):
-    """Sizes that are not multiples of the 64-wide blocks or 16-vector slabs."""
+def test_ragged_shapes(m, n, B, seed, method):
+    """Sizes that are not multiples of the 64-wide blocks or 16-vector slabs, with either
+    way of inverting the pivot blocks (Gauss-Jordan, Newton-Schulz)."""
     wl = workloads.random_crossbar(m, n, B, seed, r_wl=1.5, r_bl=3.0, r_src=40.0, r_sense=60.0)
-    _check_against_oracle(wl)
+    _check_against_oracle(wl, factor_method=method)
+
+
+def test_strong_devices_fall_back_or_converge():
+    """Devices far stronger than the wires (1 kOhm cells, 20-ohm segments) make the pivot
+    blocks far from diagonal; the default factor must still match the oracle."""
+    rng = np.random.default_rng(77)
+    wl = workloads.random_crossbar(24, 96, 8, 16, r_wl=20.0, r_bl=20.0)
+    wl.G[:] = rng.uniform(5e-4, 1e-3, wl.G.shape)
+    _check_against_oracle(wl, factor_method="auto")
+    _check_against_oracle(wl, factor_method="gj")
 
 
 @pytest.mark.parametrize("r", [1.0, 2.5, 5.0])
