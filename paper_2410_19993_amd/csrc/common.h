@@ -130,8 +130,33 @@ struct SweepArgs {
     const void* H;       // [m][n_p][n_p] CPR block inverses H_i
     const double* c;     // [m][n_p]
     const double* V;     // [B][m] user inputs
-    void* Z;             // [nslab][m][16][n_p]: forward sweep z_i, then u_i
+    void* Z;             // [nslab][m][16][n_p]: forward sweep z_i, then u_i (or the correction d_i)
     double* Iout;        // [B][n]
+    // iterative refinement (float sweeps): correction of the float64 solution U
+    int iter;            // 0: right-hand side V c; > 0: right-hand side R
+    int max_iter;        // sweeps allowed in total
+    double tol;
+    const void* R;       // [nslab][m][16][n_p] float residual panels (iter > 0)
+    const double* Uin;   // [nslab][m][16][n_p] solution before this sweep (iter > 0)
+    double* Uout;        // solution after it
+    double* dnorm;       // [nslab][16] largest correction of the previous sweep, per vector
+    int* slab_done;      // [nslab]
+    int* slab_final;     // [nslab] which U buffer holds the final solution
+    int* flags;
+};
+
+struct ResidualArgs {
+    int m, n, n_p, B, nslab;
+    double g_bl, g_wl;
+    const double* V;     // [B][m]
+    const double* c;     // [m][n_p]
+    const double* fr;
+    const double* ip;
+    const double* q;
+    const double* Gc;
+    const double* U;     // [nslab][m][16][n_p] current solution (float positions)
+    void* R;             // [nslab][m][16][n_p] float residual
+    const int* slab_done;
 };
 
 struct RecoverArgs {
@@ -139,6 +164,8 @@ struct RecoverArgs {
     double g_src;
     const double* V;     // [B][m]
     const void* Z;       // [nslab][m][16][n_p] u_i (element type of the sweep)
+    const double* U[2];  // refinement: float64 solutions, U[slab_final[slab]] is final
+    const int* slab_final;
     const double* fr;
     const double* ip;
     const double* Gc;
@@ -154,3 +181,5 @@ hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_factor_ns(const xbk::NSArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);
+hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s);

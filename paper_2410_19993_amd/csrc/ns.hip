@@ -13,7 +13,8 @@
 // workgroups; no small serial inversion sits on the critical path.
 //
 // The largest |Q_k| entry is reduced on the device.  When it is <= 1e-10 the
-// update just applied leaves an error <= 1e-20 (plus rounding), the result is
+// update just applied leaves an error <= 1e-20 (plus rounding; 1e-4 and 1e-8
+// for the float32 factor of the refinement mode), the result is
 // written over E_i and later launches for the row exit at once.  A row still
 // above the threshold after its last step raises kNsFail, and the host then
 // refactors with Gauss-Jordan elimination (factor.hip).
@@ -26,7 +27,8 @@
 
 namespace xbk {
 
-constexpr double kNsDone = 1e-10;
+constexpr double kNsDone = 1e-10;      // float64: update leaves <= 1e-20 + rounding
+constexpr double kNsDoneF32 = 1e-4;    // float32: update leaves <= 1e-8, at float rounding
 
 template <typename T> struct V4;
 template <> struct V4<double> { using type = d4_t; };
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
         }
     } else {
         const double nu = __longlong_as_double((long long)*nrm);
-        const bool fin = nu <= kNsDone;                      // false for NaN
+        const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
         T* Xout = reinterpret_cast<T*>(ch.X[(it + 1) & 1]);
         T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
 #pragma unroll

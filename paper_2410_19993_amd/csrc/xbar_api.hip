@@ -33,7 +33,20 @@ struct Buffers {
     double* ns_dprev[2] = {nullptr, nullptr};
     unsigned long long* ns_norm = nullptr;   // [m][kNsMaxIterTwist]
     int* ns_done = nullptr;                  // [m]
+    // refinement (IR modes): float64 solutions, float residual panels, per-slab state
+    double* U[2] = {nullptr, nullptr};       // [nslab][m][16][n_p]
+    void* R = nullptr;                       // [nslab][m][16][n_p] float
+    double* dnorm = nullptr;                 // [nslab][16]
+    int* slab_done = nullptr;                // [nslab]
+    int* slab_final = nullptr;               // [nslab]
 };
+
+__global__ void clear_slabs_kernel(int* done, double* dnorm, int nslab)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nslab) done[i] = 0;
+    if (i < 16 * nslab) dnorm[i] = 0.0;
+}
 
 __global__ void clear_flags_kernel(int* f)
 {
@@ -127,7 +140,8 @@ void free_all(xbar_plan p)
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
                    d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
-                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_norm, d.ns_done};
+                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_norm, d.ns_done,
+                   d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final};
     for (void* x : all)
         if (x) (void)hipFree(x);
     d = Buffers{};
@@ -169,7 +183,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     if (max_batch < 1) return XBAR_ERR_ARG;
     if (!(std::isfinite(ir_tol) && ir_tol >= 0.0 && ir_tol < 1.0)) return XBAR_ERR_ARG;
     if (ir_max_iter < 0 || ir_max_iter > 100) return XBAR_ERR_ARG;
-    if (prec != XBAR_FP64) return XBAR_ERR_ARG;   // refinement modes are not built in this library yet
+    if (prec == XBAR_BF16_IR) return XBAR_ERR_ARG;   // bfloat16 factor: not built in this library
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -184,7 +198,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     p->g = g;
     p->prec = prec;
     p->max_batch = max_batch;
-    p->ir_tol = (ir_tol == 0.0) ? 1e-13 : ir_tol;
+    p->ir_tol = (ir_tol == 0.0) ? 1e-12 : ir_tol;
     p->ir_max_iter = (ir_max_iter == 0) ? 10 : ir_max_iter;
     p->stream = reinterpret_cast<hipStream_t>(hip_stream);
     p->device = dev;
@@ -221,6 +235,15 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     }
     A((void**)&d.ns_norm, m * xbk::kNsMaxIterTwist * 8);
     A((void**)&d.ns_done, m * 4);
+    if (prec != XBAR_FP64) {
+        const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
+        A((void**)&d.U[0], panel * 8);
+        A((void**)&d.U[1], panel * 8);
+        A(&d.R, panel * 4);
+        A((void**)&d.dnorm, (int64_t)p->nslab_max * 16 * 8);
+        A((void**)&d.slab_done, (int64_t)p->nslab_max * 4);
+        A((void**)&d.slab_final, (int64_t)p->nslab_max * 4);
+    }
     if (st != XBAR_OK) {
         free_all(p);
         delete p;
@@ -386,8 +409,49 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
     s.V = V;
     s.Z = p->d.Z;
     s.Iout = p->d.Iout;
+    s.flags = p->d.flags;
+    const bool ir = p->prec != XBAR_FP64;
     if (p->timing && !p->t_sweep.begin(p->stream)) return XBAR_ERR_DEVICE;
-    if (xbk_launch_sweep(s, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (!ir) {
+        if (xbk_launch_sweep(s, false, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    } else {
+        // float sweeps refined in float64: sweep 0 solves with V c, each later sweep
+        // corrects U by the solution for the float64 residual of the previous U.
+        hipLaunchKernelGGL(clear_slabs_kernel, dim3((16 * nslab + 255) / 256), dim3(256), 0, p->stream,
+                           p->d.slab_done, p->d.dnorm, nslab);
+        s.max_iter = 1 + p->ir_max_iter;
+        s.tol = p->ir_tol;
+        s.R = p->d.R;
+        s.dnorm = p->d.dnorm;
+        s.slab_done = p->d.slab_done;
+        s.slab_final = p->d.slab_final;
+        xbk::ResidualArgs r{};
+        r.m = p->g.m;
+        r.n = p->g.n;
+        r.n_p = p->n_p;
+        r.B = B;
+        r.nslab = nslab;
+        r.g_bl = 1.0 / p->g.r_bl;
+        r.g_wl = 1.0 / p->g.r_wl;
+        r.V = V;
+        r.c = p->d.c;
+        r.fr = p->d.fr;
+        r.ip = p->d.ip;
+        r.q = p->d.q;
+        r.Gc = p->d.Gc;
+        r.R = p->d.R;
+        r.slab_done = p->d.slab_done;
+        for (int it = 0; it < s.max_iter; ++it) {
+            s.iter = it;
+            s.Uin = p->d.U[it & 1];
+            s.Uout = p->d.U[(it + 1) & 1];
+            if (it > 0) {
+                r.U = p->d.U[it & 1];
+                if (xbk_launch_residual(r, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+            }
+            if (xbk_launch_sweep_ir(s, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+        }
+    }
     if (p->timing && !p->t_sweep.end(p->stream)) return XBAR_ERR_DEVICE;
     if (node_v != nullptr) {
         xbk::RecoverArgs r{};
@@ -400,6 +464,9 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         r.g_wl = 1.0 / p->g.r_wl;
         r.V = V;
         r.Z = p->d.Z;
+        r.U[0] = p->d.U[0];
+        r.U[1] = p->d.U[1];
+        r.slab_final = ir ? p->d.slab_final : nullptr;
         r.fr = p->d.fr;
         r.ip = p->d.ip;
         r.Gc = p->d.Gc;
