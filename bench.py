@@ -6,7 +6,7 @@ source and sense resistors, segment resistance --r): assemble, factor,
 forward/back substitution with every node voltage written to HBM, and the
 output currents.  Inputs are resident in HBM before timing starts.
 
-    python bench.py [--steps K] [--warmup W] [--r 2.5] [--precision fp64]
+    python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--r", type=float, default=2.5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-fp32-ir", action="store_true", help="skip the float32+refinement leg")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
@@ -98,82 +98,90 @@ def main():
     node_v = torch.empty((B, 2 * m * n), dtype=torch.float64, device="cuda")
     I = torch.empty((B, n), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
-    plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, args.precision, max_batch=B,
-                   stream=stream)
+    gold = os.path.join(ROOT, "tests", "golden", f"c3_r{g.r_wl:g}_currents.npy")
 
-    def step():
-        plan.assemble(G)
-        plan.factor()
-        plan.solve_batch(V, node_v)
-        plan.currents(I)
+    def verify():
+        if args.no_verify or not os.path.exists(gold) or B != 4096:
+            return None
+        ref = np.load(gold)
+        Ih = I.cpu().numpy()[workloads.c3_subset()]
+        return float((np.max(np.abs(Ih - ref), axis=1) / np.max(np.abs(ref), axis=1)).max())
 
-    for w in range(args.warmup):
-        step()
+    def run(precision, steps, warmup):
+        plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B,
+                       stream=stream)
+
+        def step():
+            plan.assemble(G)
+            plan.factor()
+            plan.solve_batch(V, node_v)
+            plan.currents(I)
+
+        for w in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"{precision}: warmup step {w} done")
+        plan.check()
+        plan.set_timing(True)
+        plan.timing(reset=True)
         torch.cuda.synchronize()
-        log(f"warmup step {w} done")
-    plan.check()
-    plan.set_timing(True)
-    plan.timing(reset=True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for s in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    tm = plan.timing()
-    plan.check()
-    ms_per_step = 1e3 * wall / args.steps
-    log(f"timed {args.steps} steps: wall {wall:.3f} s, events {gpu_ms:.1f} ms")
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm = plan.timing()
+        st, info = plan.info()
+        plan.check()
+        err = verify()
+        plan.close()
+        log(f"{precision}: {steps} steps in {wall:.3f} s")
+        return wall * 1e3 / steps, tm, info, err
 
+    ms64, tm, info64, err64 = run("fp64", args.steps, args.warmup)
     # kernels: algorithmic work per launch
     sweep_flops = 2.0 * n * n * B * (2 * m - 1)          # forward m products + back (m-1)
     factor_flops = float(m) * n ** 3                     # m SPD inverses of n x n
-    k_sweep = tm.sweep_ms / max(tm.sweep_launches, 1)
-    k_factor = tm.factor_ms / max(tm.factor_launches, 1)
-    k_recover = tm.recover_ms / max(tm.recover_launches, 1)
-    k_condense = tm.condense_ms / max(tm.condense_launches, 1)
+    per = lambda ms, k: ms / max(k, 1)
+    k_sweep = per(tm.sweep_ms, tm.sweep_launches)
+    k_factor = per(tm.factor_ms, tm.factor_launches)
+    k_recover = per(tm.recover_ms, tm.recover_launches)
+    k_condense = per(tm.condense_ms, tm.condense_launches)
     recover_bytes = 8.0 * B * m * n * (1 + 2) + 8.0 * 3 * m * n     # read u, write w and u
-    phases = {"condense_ms": k_condense, "factor_ms": k_factor, "sweep_ms": k_sweep,
-              "recover_ms": k_recover}
     achieved = sweep_flops / (k_sweep * 1e-3)
     roof = {"bound": "mfma", "kernel": "sweep_kernel<double,8>", "achieved": achieved / 1e12,
             "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA,
             "traffic": None, "flops_per_launch": sweep_flops, "avg_launch_ms": k_sweep}
-
     result = {
-        "metric": METRIC, "value": B / (ms_per_step * 1e-3), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": B / (ms64 * 1e-3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms64,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "m": m, "n": n, "batch": B, "r_segment_ohm": g.r_wl,
-                   "r_src_ohm": g.r_src, "r_sense_ohm": g.r_sense, "precision": args.precision,
+                   "r_src_ohm": g.r_src, "r_sense_ohm": g.r_sense, "precision": "fp64",
                    "node_voltages": True, "parallelism": "single-gpu"},
-        "phases_ms": phases,
+        "phases_ms": {"condense": k_condense, "factor": k_factor, "sweep": k_sweep,
+                      "recover": k_recover},
         "factor": {"algorithmic_flops": factor_flops, "ms": k_factor,
-                   "tflops": factor_flops / (k_factor * 1e-3) / 1e12,
-                   "kernel_launches": int(tm.factor_launches)},
+                   "tflops": factor_flops / (k_factor * 1e-3) / 1e12},
         "recover": {"ms": k_recover, "bytes": recover_bytes,
                     "gbps": recover_bytes / (k_recover * 1e-3) / 1e9 if k_recover > 0 else None},
         "roofline": roof,
+        "max_rel_err_vs_oracle": err64,
     }
-    if not args.no_verify:
-        gold = os.path.join(ROOT, "tests", "golden", f"c3_r{g.r_wl:g}_currents.npy")
-        if os.path.exists(gold) and B == 4096:
-            ref = np.load(gold)
-            sub = workloads.c3_subset()
-            Ih = I.cpu().numpy()[sub]
-            err = np.max(np.abs(Ih - ref), axis=1) / np.max(np.abs(ref), axis=1)
-            result["max_rel_err_vs_oracle"] = float(err.max())
-            result["verified_vectors"] = int(len(sub))
+    if not args.no_fp32_ir:
+        ms32, tm32, info32, err32 = run("fp32_ir", args.steps, args.warmup)
+        result["fp32_ir"] = {
+            "value": B / (ms32 * 1e-3), "unit": "solves/s", "ms_per_step": ms32, "dtype": "f32+f64",
+            "sweeps": int(info32.ir_iters), "max_rel_err_vs_oracle": err32,
+            "phases_ms": {"condense": per(tm32.condense_ms, tm32.condense_launches),
+                          "factor": per(tm32.factor_ms, tm32.factor_launches),
+                          "refined_solve": per(tm32.sweep_ms, tm32.sweep_launches),
+                          "recover": per(tm32.recover_ms, tm32.recover_launches)},
+            "speedup_vs_fp64": ms64 / ms32}
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(wl)
-    plan.close()
     print(json.dumps(result))
 
 

@@ -88,7 +88,7 @@ struct NSArgs {
     void* H;                 // [m][n_p][n_p] CPR
     NSChain ch[2];
     NSJob job[2];
-    unsigned long long* norm;  // [m][kNsMaxIterTwist] max |I - X S| per row and step (bits of a double)
+    double* part;              // [2][n_p/32]^2 per-workgroup max |I - X P| of the current step
     int* done;                 // [m] row finished
     int* flags;
     int max_iter;
@@ -130,8 +130,14 @@ struct SweepArgs {
     const void* H;       // [m][n_p][n_p] CPR block inverses H_i
     const double* c;     // [m][n_p]
     const double* V;     // [B][m] user inputs
-    void* Z;             // [nslab][m][16][n_p]: forward sweep z_i, then u_i (or the correction d_i)
+    void* Z;             // [nslab][m][16][n_p]: forward sweep z_i (or the correction d_i)
     double* Iout;        // [B][n]
+    // word-line recovery fused into the float64 back sweep (node_v == nullptr: skipped)
+    double* node_v;      // [B][2mn]
+    const double* Gc;    // [m][n]
+    const double* fr;    // [m][n]
+    const double* ip;    // [m][n]
+    double g_src, g_wl;
     // iterative refinement (float sweeps): correction of the float64 solution U
     int iter;            // 0: right-hand side V c; > 0: right-hand side R
     int max_iter;        // sweeps allowed in total

@@ -12,7 +12,8 @@
 // is two n_p^3 products on the matrix cores, spread over all the GPU's
 // workgroups; no small serial inversion sits on the critical path.
 //
-// The largest |Q_k| entry is reduced on the device.  When it is <= 1e-10 the
+// The largest |Q_k| entry is reduced on the device (per-workgroup partials,
+// combined by every workgroup of the following update).  When it is <= 1e-10 the
 // update just applied leaves an error <= 1e-20 (plus rounding; 1e-4 and 1e-8
 // for the float32 factor of the refinement mode), the result is
 // written over E_i and later launches for the row exit at once.  A row still
@@ -54,7 +55,6 @@ __global__ __launch_bounds__(256) void ns_form_kernel(NSArgs a)
     T* S = reinterpret_cast<T*>(ch.S);
     T* X = reinterpret_cast<T*>(ch.X[0]);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.done[job.row] = 0;
-    if (blockIdx.x == 0 && threadIdx.x < kNsMaxIterTwist) a.norm[(int64_t)job.row * kNsMaxIterTwist + threadIdx.x] = 0ull;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / n_p), p = (int)(e % n_p);
         const int c = (p & ~15) + Frag<T>::slot(p & 15);         // CPR position p holds column c
@@ -102,22 +102,38 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
     const T* ap = A + (int64_t)(R0 + r) * n_p + 4 * q;
     const T* bp = Bm + (int64_t)(C0 + r) * n_p + 4 * q;
     acc_t acc = acc_t{0, 0, 0, 0};
-    const int KC = n_p / 16;
-    v4 ac = *reinterpret_cast<const v4*>(ap), bc = *reinterpret_cast<const v4*>(bp);
-    for (int K = 0; K < KC; ++K) {
-        v4 an, bn;
-        if (K + 1 < KC) {
-            an = *reinterpret_cast<const v4*>(ap + 16 * (K + 1));
-            bn = *reinterpret_cast<const v4*>(bp + 16 * (K + 1));
+    // K in chunks of 16, four chunks in flight ahead of the matrix cores
+    constexpr int D = 4;
+    const int KC = n_p / 16;                 // a multiple of 4 (n_p is a multiple of 64)
+    v4 ac[D], bc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        ac[j] = *reinterpret_cast<const v4*>(ap + 16 * j);
+        bc[j] = *reinterpret_cast<const v4*>(bp + 16 * j);
+    }
+    for (int K = 0; K < KC; K += D) {
+        v4 an[D], bn[D];
+        const bool more = K + D < KC;
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                an[j] = *reinterpret_cast<const v4*>(ap + 16 * (K + D + j));
+                bn[j] = *reinterpret_cast<const v4*>(bp + 16 * (K + D + j));
+            }
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc = Frag<T>::mma(ac[t], bc[t], acc);
-        if (K + 1 < KC) {
-            ac = an;
-            bc = bn;
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = Frag<T>::mma(ac[j][t], bc[j][t], acc);
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                ac[j] = an[j];
+                bc[j] = bn[j];
+            }
         }
     }
-    unsigned long long* nrm = a.norm + (int64_t)job.row * kNsMaxIterTwist + it;
+    double* part = a.part + (int64_t)(blockIdx.x / tiles) * tiles;    // this job's partials
     if (MODE == 0) {
         T* Q = reinterpret_cast<T*>(ch.Q);
         double mx = 0.0;
@@ -133,12 +149,32 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
             const double o = __shfl_xor(mx, off);
             mx = (o > mx || o != o) ? o : mx;
         }
-        if (l == 0) {
-            const unsigned long long bits = (mx != mx) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(mx);
-            atomicMax(nrm, bits);
+        __shared__ double wmax[4];
+        if (l == 0) wmax[w] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = wmax[0];
+            for (int k = 1; k < 4; ++k) t = (wmax[k] > t || wmax[k] != wmax[k]) ? wmax[k] : t;
+            part[tile] = t;
         }
     } else {
-        const double nu = __longlong_as_double((long long)*nrm);
+        // max over the job's workgroup partials of Q's step
+        __shared__ double red[256];
+        double mx = 0.0;
+        for (int k = threadIdx.x; k < tiles; k += 256) {
+            const double o = part[k];
+            mx = (o > mx || o != o) ? o : mx;
+        }
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                const double o = red[threadIdx.x + h];
+                red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
+            }
+            __syncthreads();
+        }
+        const double nu = red[0];
         const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
         T* Xout = reinterpret_cast<T*>(ch.X[(it + 1) & 1]);
         T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
@@ -151,7 +187,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
         }
         if (fin) {
             if (threadIdx.x == 0) a.done[job.row] = 1;
-        } else if (it == maxit - 1 && threadIdx.x == 0 && blockIdx.x % tiles == 0) {
+        } else if (it == maxit - 1 && threadIdx.x == 0 && tile == 0) {
             atomicOr(a.flags + kNsFail, 1);
         }
     }

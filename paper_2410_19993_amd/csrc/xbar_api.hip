@@ -31,7 +31,7 @@ struct Buffers {
     void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* ns_Q[2] = {nullptr, nullptr};
     double* ns_dprev[2] = {nullptr, nullptr};
-    unsigned long long* ns_norm = nullptr;   // [m][kNsMaxIterTwist]
+    double* ns_part = nullptr;               // [2][(n_p/32)^2]
     int* ns_done = nullptr;                  // [m]
     // refinement (IR modes): float64 solutions, float residual panels, per-slab state
     double* U[2] = {nullptr, nullptr};       // [nslab][m][16][n_p]
@@ -140,7 +140,7 @@ void free_all(xbar_plan p)
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
                    d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
-                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_norm, d.ns_done,
+                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_done,
                    d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final};
     for (void* x : all)
         if (x) (void)hipFree(x);
@@ -233,7 +233,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         A(&d.ns_Q[c], n_p * n_p * es);
         A((void**)&d.ns_dprev[c], n_p * 8);
     }
-    A((void**)&d.ns_norm, m * xbk::kNsMaxIterTwist * 8);
+    A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
     A((void**)&d.ns_done, m * 4);
     if (prec != XBAR_FP64) {
         const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
@@ -334,7 +334,7 @@ hipError_t launch_ns(xbar_plan p)
         a.ch[c].Q = p->d.ns_Q[c];
         a.ch[c].dprev = p->d.ns_dprev[c];
     }
-    a.norm = p->d.ns_norm;
+    a.part = p->d.ns_part;
     a.done = p->d.ns_done;
     a.flags = p->d.flags;
     a.max_iter = xbk::kNsMaxIter;
@@ -411,6 +411,12 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
     s.Iout = p->d.Iout;
     s.flags = p->d.flags;
     const bool ir = p->prec != XBAR_FP64;
+    s.node_v = ir ? nullptr : node_v;     // float64: recovery fused into the back sweep
+    s.Gc = p->d.Gc;
+    s.fr = p->d.fr;
+    s.ip = p->d.ip;
+    s.g_src = 1.0 / p->g.r_src;
+    s.g_wl = 1.0 / p->g.r_wl;
     if (p->timing && !p->t_sweep.begin(p->stream)) return XBAR_ERR_DEVICE;
     if (!ir) {
         if (xbk_launch_sweep(s, false, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
@@ -453,7 +459,7 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         }
     }
     if (p->timing && !p->t_sweep.end(p->stream)) return XBAR_ERR_DEVICE;
-    if (node_v != nullptr) {
+    if (node_v != nullptr && ir) {
         xbk::RecoverArgs r{};
         r.m = p->g.m;
         r.n = p->g.n;
