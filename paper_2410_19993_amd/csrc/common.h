@@ -14,8 +14,19 @@
 // A row-major matrix whose columns are permuted inside each 16-chunk by
 // slot(k) = position of k in (q, t) order makes every lane's four A values
 // contiguous (one 32-byte or 16-byte load).  This "chunk-permuted row-major"
-// (CPR) layout is used for every n_p x n_p block the kernels exchange, and
-// for the LDS panels of right-hand sides, stored [column][slot(k)].
+// (CPR) layout is used for the Gauss-Jordan working blocks and for the
+// panels of right-hand sides, stored [column][slot(k)].
+//
+// Blocks that stream through the matrix cores (E_i, then H_i, and the
+// Newton-Schulz iterates) use a fragment-tiled (FRG) layout instead: 16x16
+// tiles in row-major tile order, each tile stored in A-operand lane order, so
+// that a wave reads one tile with fully contiguous 16-byte loads (1 KB per
+// load instruction) rather than 16 short row segments:
+//   f64: lane l = 16q + r holds (r, kidx(q, t)), t = 0..3, at 128 (t >> 1) + 2 l + (t & 1)
+//   f32: lane l holds (r, kidx(q, t)) at 4 l + t
+// The same slots hold the D tile of an MFMA transposed: with the A slot fed
+// from tile rows of B and the B slot from tile rows of A, lane l item v of D
+// is element (r, kidx(q, v)) of the matching tile of A B^T, stored in place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,6 +70,40 @@ __host__ __device__ inline int64_t cpr(int64_t r, int k, int ld) {
     return r * ld + (k & ~15) + Frag<T>::slot(k & 15);
 }
 
+// FRG slot of item t of lane l inside a 256-element tile.
+template <typename T>
+__host__ __device__ constexpr int frg_slot(int l, int t) {
+    return sizeof(T) == 8 ? 128 * (t >> 1) + 2 * l + (t & 1) : 4 * l + t;
+}
+
+// FRG offset of (r, c) in an n_p x n_p block.
+template <typename T>
+__host__ __device__ inline int64_t frg(int r, int c, int n_p) {
+    const int k = c & 15;
+    const int q = sizeof(T) == 8 ? (k & 3) : (k >> 2);     // inverse of kidx
+    const int t = sizeof(T) == 8 ? (k >> 2) : (k & 3);
+    const int64_t tile = (int64_t)(r >> 4) * (n_p >> 4) + (c >> 4);
+    return tile * 256 + frg_slot<T>(16 * q + (r & 15), t);
+}
+
+// (row, column) held at FRG offset e of an n_p x n_p block.
+template <typename T>
+__host__ __device__ inline void frg_rc(int64_t e, int n_p, int& r, int& c) {
+    const int64_t tile = e >> 8;
+    const int s = (int)(e & 255);
+    int l, t;
+    if (sizeof(T) == 8) {
+        l = (s & 127) >> 1;
+        t = 2 * (s >> 7) + (s & 1);
+    } else {
+        l = s >> 2;
+        t = s & 3;
+    }
+    const int kt = n_p >> 4;
+    r = 16 * (int)(tile / kt) + (l & 15);
+    c = 16 * (int)(tile % kt) + Frag<T>::kidx(l >> 4, t);
+}
+
 // Device error flags (sticky, cleared by assemble).  kNsFail is internal: a
 // Newton-Schulz inverse that missed its tolerance (the factor then reruns
 // with Gauss-Jordan elimination).
@@ -85,7 +130,7 @@ struct NSJob {
 struct NSArgs {
     int m, n, n_p;
     double g2;
-    void* H;                 // [m][n_p][n_p] CPR
+    void* H;                 // [m][n_p][n_p] FRG: E_i on entry, H_i on exit
     NSChain ch[2];
     NSJob job[2];
     double* part;              // [2][n_p/32]^2 per-workgroup max |I - X P| of the current step
@@ -98,7 +143,7 @@ struct CondenseArgs {
     const double* G;     // [m][n] user conductances
     int m, n, n_p;
     double g_wl, g_bl, g_src, g_sense;
-    void* E;             // [m][n_p][n_p] CPR, element type of the factor
+    void* E;             // [m][n_p][n_p] FRG, element type of the factor
     double* c;           // [m][n_p]  condensed source coupling c_i
     double* fr;          // [m][n]    g_wl / p_{j-1} (0 at j = 0): forward Thomas ratios of T_i
     double* ip;          // [m][n]    1 / p_j
@@ -119,7 +164,7 @@ struct GJJob {
 struct GJArgs {
     int m, n, n_p, nb;   // nb = n_p / 64 tile rows per block
     double g2;           // g_bl^2: coupling of neighbouring row blocks
-    void* H;             // [m][n_p][n_p] CPR: E_i on entry, pivot inverse H_i on exit
+    void* H;             // [m][n_p][n_p] FRG: E_i on entry, pivot inverse H_i on exit
     GJJob job[2];        // top and bottom chains (one job for the twist row)
     int* flags;
 };
@@ -127,7 +172,7 @@ struct GJArgs {
 struct SweepArgs {
     int m, n, n_p, B, nslab;
     double g_bl, g_sense;
-    const void* H;       // [m][n_p][n_p] CPR block inverses H_i
+    const void* H;       // [m][n_p][n_p] FRG block inverses H_i
     const double* c;     // [m][n_p]
     const double* V;     // [B][m] user inputs
     void* Z;             // [nslab][m][16][n_p]: forward sweep z_i (or the correction d_i)

@@ -79,25 +79,25 @@ __global__ __launch_bounds__(256) void condense_kernel(CondenseArgs a)
     T* E = reinterpret_cast<T*>(a.E) + (int64_t)i * n_p * n_p;
     for (int k = threadIdx.x; k < n_p; k += blockDim.x) {
         if (k >= n) {
-            for (int j = 0; j < n_p; ++j) E[cpr<T>(j, k, n_p)] = (T)0;
+            for (int j = 0; j < n_p; ++j) E[frg<T>(j, k, n_p)] = (T)0;
             a.c[(int64_t)i * n_p + k] = 0.0;
             continue;
         }
         const double Gk = Gs[k];
         const double qk = Gk + qb_up + qb_dn;
         double x = dg[k];
-        E[cpr<T>(k, k, n_p)] = (T)(qk - Gk * x * Gk);
+        E[frg<T>(k, k, n_p)] = (T)(qk - Gk * x * Gk);
         for (int j = k - 1; j >= 0; --j) {          // up column k: x_j = x_{j+1} g_wl / p_j
             x *= rf[j];
-            E[cpr<T>(j, k, n_p)] = (T)(-(Gs[j] * x * Gk));
+            E[frg<T>(j, k, n_p)] = (T)(-(Gs[j] * x * Gk));
         }
         a.c[(int64_t)i * n_p + k] = a.g_src * Gk * x;   // x = (T^{-1})_{0k} = (T^{-1})_{k0}
         x = dg[k];
         for (int j = k + 1; j < n; ++j) {           // down column k: x_j = x_{j-1} g_wl / pb_j
             x *= rb[j];
-            E[cpr<T>(j, k, n_p)] = (T)(-(Gs[j] * x * Gk));
+            E[frg<T>(j, k, n_p)] = (T)(-(Gs[j] * x * Gk));
         }
-        for (int j = n; j < n_p; ++j) E[cpr<T>(j, k, n_p)] = (T)0;
+        for (int j = n; j < n_p; ++j) E[frg<T>(j, k, n_p)] = (T)0;
         a.q[(int64_t)i * n + k] = qk;
         a.fr[(int64_t)i * n + k] = (k == 0) ? 0.0 : rf[k - 1];
         a.ip[(int64_t)i * n + k] = 1.0 / fp[k];

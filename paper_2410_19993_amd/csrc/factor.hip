@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = 64 * I + out_row<T>(w, l, v), cc = 64 * J + 16 * C + (l & 15);
-            acc[C][v] = form_elem<T>(E, Ha, Hb, cpr<T>(rr, cc, a.n_p), a.g2, rr, cc, a.n);
+            acc[C][v] = form_elem<T>(E, Ha, Hb, frg<T>(rr, cc, a.n_p), a.g2, rr, cc, a.n);
         }
     store_acc<T>(acc, reinterpret_cast<T*>(job.S[0]), a.n_p, 64 * I, 64 * J, w, l);
     if (I == 0 && J == 0) invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, w, l);
@@ -294,7 +294,11 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
     // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
     // chain's next pivot block E_next - g^2 H_row.
     T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
-    store_acc<T>(acc, Hr, n_p, r0, c0, w, l);
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            Hr[frg<T>(r0 + out_row<T>(w, l, v), c0 + 16 * C + (l & 15), n_p)] = acc[C][v];
     if (job.next < 0) return;
     const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)job.next * n_p * n_p;
 #pragma unroll
@@ -302,7 +306,7 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = r0 + out_row<T>(w, l, v), cc = c0 + 16 * C + (l & 15);
-            const T e = En[cpr<T>(rr, cc, n_p)];
+            const T e = En[frg<T>(rr, cc, n_p)];
             acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
         }
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);

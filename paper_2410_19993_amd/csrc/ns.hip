@@ -20,8 +20,12 @@
 // above the threshold after its last step raises kNsFail, and the host then
 // refactors with Gauss-Jordan elimination (factor.hip).
 //
-// Products read both operands row-wise: the right operand (P or X) is
-// symmetric, so its column k is its row k.
+// Every block here (E_i, H_i, S, X, Q) is stored fragment-tiled (FRG), and
+// a product C = A B^T is formed with the A slot of the matrix cores fed from
+// tile rows of B and the B slot from tile rows of A, so that operand loads and
+// output stores are all contiguous 16-byte accesses.  Since S is symmetric,
+// X S^T = X S; the update uses Q X^T, which equals Q X up to rounding because
+// the iteration keeps X symmetric (2X - X S X is symmetric when X is).
 #include <algorithm>
 
 #include "common.h"
@@ -56,8 +60,8 @@ __global__ __launch_bounds__(256) void ns_form_kernel(NSArgs a)
     T* X = reinterpret_cast<T*>(ch.X[0]);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.done[job.row] = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / n_p), p = (int)(e % n_p);
-        const int c = (p & ~15) + Frag<T>::slot(p & 15);         // CPR position p holds column c
+        int r, c;
+        frg_rc<T>(e, n_p, r, c);
         T s, x;
         if (r >= n || c >= n) {
             s = x = (r == c) ? (T)1 : (T)0;
@@ -78,70 +82,106 @@ __global__ __launch_bounds__(256) void ns_form_kernel(NSArgs a)
     }
 }
 
-// One product of a Newton-Schulz step on a 32x32 output tile per workgroup
-// (four waves, one 16x16 MFMA tile each, K = n_p).
-//   MODE 0:  Q = I - X_k P       (and the row's max |Q|)
-//   MODE 1:  X_{k+1} = X_k + Q X_k   (and H_row when the step converged)
-template <typename T, int MODE>
+// A-operand fragment of FRG tile (tr, tk) of an n_p x n_p block (kt = n_p / 16).
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type load_frag(const T* __restrict__ M, int kt, int tr, int tk, int l)
+{
+    using v4 = typename V4<T>::type;
+    const T* p = M + ((int64_t)tr * kt + tk) * 256;
+    if constexpr (sizeof(T) == 8) {
+        typedef double d2_t __attribute__((ext_vector_type(2)));
+        const d2_t lo = *reinterpret_cast<const d2_t*>(p + 2 * l);
+        const d2_t hi = *reinterpret_cast<const d2_t*>(p + 128 + 2 * l);
+        return v4{lo[0], lo[1], hi[0], hi[1]};
+    } else {
+        return *reinterpret_cast<const v4*>(p + 4 * l);
+    }
+}
+
+// One product of a Newton-Schulz step on a 32x32 output tile per workgroup.
+// The four waves split K = n_p into quarters (NT = n_p / 64 chunks of 16
+// each), every wave accumulating all four 16x16 output tiles; the partial
+// sums meet in LDS and wave w finishes output tile w.
+//   MODE 0:  Q = I - X_k S          (and the row's max |Q|)
+//   MODE 1:  X_{k+1} = X_k + Q X_k  (and H_row when the step converged)
+template <typename T, int MODE, int NT>
 __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
 {
     using v4 = typename V4<T>::type;
     using acc_t = typename Frag<T>::acc_t;
-    const int n_p = a.n_p, tdim = n_p / 32, tiles = tdim * tdim;
+    constexpr int n_p = 64 * NT, kt = n_p / 16, tdim = n_p / 32, tiles = tdim * tdim;
+    __shared__ __align__(16) T red[4 * 4 * 4 * 64];       // [wave][output tile][item][lane]
+    __shared__ double wmax[256];
     const NSJob& job = a.job[blockIdx.x / tiles];
     if (a.done[job.row]) return;
     const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
     if (it >= maxit) return;
     const NSChain& ch = a.ch[job.chain];
     const int tile = blockIdx.x % tiles;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, r = l & 15;
-    const int R0 = 32 * (tile / tdim) + 16 * (w >> 1), C0 = 32 * (tile % tdim) + 16 * (w & 1);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
     const T* Xin = reinterpret_cast<const T*>(ch.X[it & 1]);
-    const T* A = MODE == 0 ? Xin : reinterpret_cast<const T*>(ch.Q);
+    // C = Am Bm^T
+    const T* Am = MODE == 0 ? Xin : reinterpret_cast<const T*>(ch.Q);
     const T* Bm = MODE == 0 ? reinterpret_cast<const T*>(ch.S) : Xin;
-    const T* ap = A + (int64_t)(R0 + r) * n_p + 4 * q;
-    const T* bp = Bm + (int64_t)(C0 + r) * n_p + 4 * q;
-    acc_t acc = acc_t{0, 0, 0, 0};
-    // K in chunks of 16, four chunks in flight ahead of the matrix cores
-    constexpr int D = 4;
-    const int KC = n_p / 16;                 // a multiple of 4 (n_p is a multiple of 64)
-    v4 ac[D], bc[D];
+    acc_t acc[2][2];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        ac[j] = *reinterpret_cast<const v4*>(ap + 16 * j);
-        bc[j] = *reinterpret_cast<const v4*>(bp + 16 * j);
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    const int K0 = w * NT;
+    v4 ac[2], bc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        ac[i] = load_frag<T>(Am, kt, TR + i, K0, l);
+        bc[i] = load_frag<T>(Bm, kt, TC + i, K0, l);
     }
-    for (int K = 0; K < KC; K += D) {
-        v4 an[D], bn[D];
-        const bool more = K + D < KC;
-        if (more) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                an[j] = *reinterpret_cast<const v4*>(ap + 16 * (K + D + j));
-                bn[j] = *reinterpret_cast<const v4*>(bp + 16 * (K + D + j));
+    for (int K = 0; K < NT; ++K) {
+        v4 an[2], bn[2];
+        if (K + 1 < NT) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                an[i] = load_frag<T>(Am, kt, TR + i, K0 + K + 1, l);
+                bn[i] = load_frag<T>(Bm, kt, TC + i, K0 + K + 1, l);
             }
         }
 #pragma unroll
-        for (int j = 0; j < D; ++j)
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc = Frag<T>::mma(ac[j][t], bc[j][t], acc);
-        if (more) {
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                ac[j] = an[j];
-                bc[j] = bn[j];
+                for (int j = 0; j < 2; ++j) acc[i][j] = Frag<T>::mma(bc[j][t], ac[i][t], acc[i][j]);
+        if (K + 1 < NT) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ac[i] = an[i];
+                bc[i] = bn[i];
             }
         }
     }
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((w * 4 + o) * 4 + v) * 64 + l] = acc[o >> 1][o & 1][v];
+    __syncthreads();
+    acc_t sum = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum[v] += red[((k * 4 + w) * 4 + v) * 64 + l];
+    // wave w owns output tile (TR + w/2, TC + w%2); lane l item v is (row, col) of C
+    const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
+    const int row = 16 * (TR + (w >> 1)) + (l & 15);
     double* part = a.part + (int64_t)(blockIdx.x / tiles) * tiles;    // this job's partials
     if (MODE == 0) {
         T* Q = reinterpret_cast<T*>(ch.Q);
         double mx = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = R0 + Frag<T>::drow(q, v), col = C0 + r;
-            const T val = (T)(row == col ? 1 : 0) - acc[v];
-            Q[cpr<T>(row, col, n_p)] = val;
+            const int col = 16 * (TC + (w & 1)) + Frag<T>::kidx(l >> 4, v);
+            const T val = (T)(row == col ? 1 : 0) - sum[v];
+            Q[base + frg_slot<T>(l, v)] = val;
             const double av = fabs((double)val);
             mx = (av > mx || av != av) ? av : mx;          // keep NaN
         }
@@ -149,7 +189,6 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
             const double o = __shfl_xor(mx, off);
             mx = (o > mx || o != o) ? o : mx;
         }
-        __shared__ double wmax[4];
         if (l == 0) wmax[w] = mx;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -159,29 +198,28 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
         }
     } else {
         // max over the job's workgroup partials of Q's step
-        __shared__ double red[256];
         double mx = 0.0;
         for (int k = threadIdx.x; k < tiles; k += 256) {
             const double o = part[k];
             mx = (o > mx || o != o) ? o : mx;
         }
-        red[threadIdx.x] = mx;
+        wmax[threadIdx.x] = mx;
         __syncthreads();
         for (int h = 128; h > 0; h >>= 1) {
             if (threadIdx.x < h) {
-                const double o = red[threadIdx.x + h];
-                red[threadIdx.x] = (o > red[threadIdx.x] || o != o) ? o : red[threadIdx.x];
+                const double o = wmax[threadIdx.x + h];
+                wmax[threadIdx.x] = (o > wmax[threadIdx.x] || o != o) ? o : wmax[threadIdx.x];
             }
             __syncthreads();
         }
-        const double nu = red[0];
+        const double nu = wmax[0];
         const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
         T* Xout = reinterpret_cast<T*>(ch.X[(it + 1) & 1]);
         T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t o = cpr<T>(R0 + Frag<T>::drow(q, v), C0 + r, n_p);
-            const T x = Xin[o] + acc[v];
+            const int64_t o = base + frg_slot<T>(l, v);
+            const T x = Xin[o] + sum[v];
             Xout[o] = x;
             if (fin) Hr[o] = x;
         }
@@ -193,11 +231,34 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
     }
 }
 
+template <typename T, int MODE, int NT>
+hipError_t launch_gemm_nt(const NSArgs& f, int njobs, int it, hipStream_t s)
+{
+    constexpr int tiles = (2 * NT) * (2 * NT);
+    hipLaunchKernelGGL((ns_gemm_kernel<T, MODE, NT>), dim3(njobs * tiles), dim3(256), 0, s, f, it);
+    return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t launch_gemm(const NSArgs& f, int njobs, int it, hipStream_t s)
+{
+    switch (f.n_p / 64) {
+        case 1: return launch_gemm_nt<T, MODE, 1>(f, njobs, it, s);
+        case 2: return launch_gemm_nt<T, MODE, 2>(f, njobs, it, s);
+        case 3: return launch_gemm_nt<T, MODE, 3>(f, njobs, it, s);
+        case 4: return launch_gemm_nt<T, MODE, 4>(f, njobs, it, s);
+        case 5: return launch_gemm_nt<T, MODE, 5>(f, njobs, it, s);
+        case 6: return launch_gemm_nt<T, MODE, 6>(f, njobs, it, s);
+        case 7: return launch_gemm_nt<T, MODE, 7>(f, njobs, it, s);
+        case 8: return launch_gemm_nt<T, MODE, 8>(f, njobs, it, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_ns(NSArgs a, hipStream_t s)
 {
     const int m = a.m, kt = m / 2, n_p = a.n_p;
-    const int tiles = (n_p / 32) * (n_p / 32);
     const int top_len = kt, bot_len = m - 1 - kt;
     const int form_blocks = (int)std::min<int64_t>(((int64_t)n_p * n_p + 255) / 256, 1024);
     hipError_t e;
@@ -205,9 +266,8 @@ hipError_t launch_ns(NSArgs a, hipStream_t s)
         hipLaunchKernelGGL(ns_form_kernel<T>, dim3(form_blocks, njobs), dim3(256), 0, s, f);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int it = 0; it < iters; ++it) {
-            hipLaunchKernelGGL((ns_gemm_kernel<T, 0>), dim3(njobs * tiles), dim3(256), 0, s, f, it);
-            hipLaunchKernelGGL((ns_gemm_kernel<T, 1>), dim3(njobs * tiles), dim3(256), 0, s, f, it);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = launch_gemm<T, 0>(f, njobs, it, s)) != hipSuccess) return e;
+            if ((e = launch_gemm<T, 1>(f, njobs, it, s)) != hipSuccess) return e;
         }
         return hipSuccess;
     };

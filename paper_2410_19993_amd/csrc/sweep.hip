@@ -15,7 +15,8 @@
 // them for the whole sweep: no grid synchronisation at all.  Per row block
 // it computes an (n_p x n_p) x (n_p x 16) product on the matrix cores: H_i
 // streams from L2/HBM straight into registers as MFMA A fragments, and the
-// 16-column right-hand-side panel sits in LDS.  W waves (8 when n_p/64 is
+// 16-column right-hand-side panel sits in LDS (H_i fragment-tiled, so each
+// load instruction of a wave reads 1 KB of contiguous memory).  W waves (8 when n_p/64 is
 // even, else 4) each own a band of TW = 4 n_p / (64 W) tiles of 16 rows, so
 // that the accumulators and one chunk of prefetched H stay in registers.
 #include "common.h"
@@ -30,7 +31,25 @@ template <> struct Vec4<float> { using type = f4_t; };
 template <typename T>
 __device__ __host__ inline int pos(int k) { return (k & ~15) + Frag<T>::slot(k & 15); }
 
-// acc[t] = (rows of tile t of this wave) x panel, K = n_p in chunks of 16.
+// A-operand fragment of FRG tile (tr, tk) of an n_p x n_p block (kt = n_p / 16):
+// one contiguous 1 KB region per 16-byte load instruction.
+template <typename T>
+__device__ __forceinline__ typename Vec4<T>::type load_frag(const T* __restrict__ M, int kt, int tr, int tk, int l)
+{
+    using v4 = typename Vec4<T>::type;
+    const T* p = M + ((int64_t)tr * kt + tk) * 256;
+    if constexpr (sizeof(T) == 8) {
+        typedef double d2_t __attribute__((ext_vector_type(2)));
+        const d2_t lo = *reinterpret_cast<const d2_t*>(p + 2 * l);
+        const d2_t hi = *reinterpret_cast<const d2_t*>(p + 128 + 2 * l);
+        return v4{lo[0], lo[1], hi[0], hi[1]};
+    } else {
+        return *reinterpret_cast<const v4*>(p + 4 * l);
+    }
+}
+
+// acc[t] = (rows of tile t of this wave) x panel, K = n_p in chunks of 16;
+// H_i is FRG, the panel is [column][CPR position].
 template <typename T, int NT, int TW>
 __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW], const T* __restrict__ Hi,
                                               const T* ybuf, int ldy, int w, int l)
@@ -44,21 +63,18 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
     const int q = l >> 4, r = l & 15;
 #pragma unroll
     for (int t = 0; t < TW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    const T* rowp[TW];
-#pragma unroll
-    for (int t = 0; t < TW; ++t) rowp[t] = Hi + (int64_t)(16 * (TW * w + t) + r) * n_p + 4 * q;
     v4 cur[D][TW], nxt[D][TW];
 #pragma unroll
     for (int d = 0; d < D; ++d)
 #pragma unroll
-        for (int t = 0; t < TW; ++t) cur[d][t] = *reinterpret_cast<const v4*>(rowp[t] + 16 * d);
+        for (int t = 0; t < TW; ++t) cur[d][t] = load_frag<T>(Hi, KC, TW * w + t, d, l);
     for (int K = 0; K < KC; K += D) {
         const bool more = K + D < KC;
         if (more) {
 #pragma unroll
             for (int d = 0; d < D; ++d)
 #pragma unroll
-                for (int t = 0; t < TW; ++t) nxt[d][t] = *reinterpret_cast<const v4*>(rowp[t] + 16 * (K + D + d));
+                for (int t = 0; t < TW; ++t) nxt[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + D + d, l);
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
