@@ -104,6 +104,18 @@ __host__ __device__ inline void frg_rc(int64_t e, int n_p, int& r, int& c) {
     c = 16 * (int)(tile % kt) + Frag<T>::kidx(l >> 4, t);
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store of the wave; kernels whose threads
+// never read each other's global writes within a launch use this instead, so
+// that stores (node voltages, forward-sweep panels) drain while the next
+// row's products run.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Device error flags (sticky, cleared by assemble).  kNsFail is internal: a
 // Newton-Schulz inverse that missed its tolerance (the factor then reruns
 // with Gauss-Jordan elimination).
@@ -179,6 +191,7 @@ struct SweepArgs {
     double* Iout;        // [B][n]
     // word-line recovery fused into the float64 back sweep (node_v == nullptr: skipped)
     double* node_v;      // [B][2mn]
+    double* sink;        // [128] scratch target of masked-off node-voltage stores
     const double* Gc;    // [m][n]
     const double* fr;    // [m][n]
     const double* ip;    // [m][n]
@@ -230,7 +243,7 @@ struct RecoverArgs {
 hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_factor_ns(const xbk::NSArgs& a, bool fp32, hipStream_t s);
-hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s);

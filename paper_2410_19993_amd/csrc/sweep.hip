@@ -12,7 +12,8 @@
 //   T_i w_i = g_src V_i e_0 + Gam_i u_i.
 //
 // Input vectors are independent, so each workgroup owns a slab of 16 of
-// them for the whole sweep: no grid synchronisation at all.  Per row block
+// them for the whole sweep: no grid synchronisation at all, and no thread
+// reads another's global writes, so barriers order LDS only.  Per row block
 // it computes an (n_p x n_p) x (n_p x 16) product on the matrix cores: H_i
 // streams from L2/HBM straight into registers as MFMA A fragments, and the
 // 16-column right-hand-side panel sits in LDS (H_i fragment-tiled, so each
@@ -49,46 +50,52 @@ __device__ __forceinline__ typename Vec4<T>::type load_frag(const T* __restrict_
 }
 
 // acc[t] = (rows of tile t of this wave) x panel, K = n_p in chunks of 16;
-// H_i is FRG, the panel is [column][CPR position].
-template <typename T, int NT, int TW>
+// H_i is FRG, the panel is [column][CPR position].  The chunks of H stream
+// through a ring of DP register sets: chunk K + DP is requested as soon as
+// chunk K has been issued to the matrix cores, so DP chunks are always in
+// flight (the loop is unrolled by DP to keep the ring indices static).
+template <typename T> struct SweepRing { static constexpr int value = sizeof(T) == 8 ? 2 : 4; };
+
+struct NoHook {
+    __device__ __forceinline__ void operator()(int) const {}
+};
+
+// hook(K) runs after the products of chunk K have been issued (K is a
+// compile-time constant once the loop is unrolled), so that independent
+// work can fill the matrix-core loop.
+template <typename T, int NT, int TW, typename Hook>
 __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW], const T* __restrict__ Hi,
-                                              const T* ybuf, int ldy, int w, int l)
+                                              const T* ybuf, int ldy, int w, int l, const Hook& hook)
 {
     using v4 = typename Vec4<T>::type;
     using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT;
-    constexpr int KC = n_p / 16;             // even
-    // float fragments are half the size: keep two chunks of H in flight instead of one
-    constexpr int D = sizeof(T) == 4 ? 2 : 1;
+    constexpr int KC = n_p / 16;
+    constexpr int DP = SweepRing<T>::value;
+    static_assert(KC % DP == 0, "chunk count must be a multiple of the ring depth");
     const int q = l >> 4, r = l & 15;
 #pragma unroll
     for (int t = 0; t < TW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    v4 cur[D][TW], nxt[D][TW];
+    v4 ring[DP][TW];
 #pragma unroll
-    for (int d = 0; d < D; ++d)
+    for (int d = 0; d < DP; ++d)
 #pragma unroll
-        for (int t = 0; t < TW; ++t) cur[d][t] = load_frag<T>(Hi, KC, TW * w + t, d, l);
-    for (int K = 0; K < KC; K += D) {
-        const bool more = K + D < KC;
-        if (more) {
+        for (int t = 0; t < TW; ++t) ring[d][t] = load_frag<T>(Hi, KC, TW * w + t, d, l);
 #pragma unroll
-            for (int d = 0; d < D; ++d)
+    for (int K0 = 0; K0 < KC; K0 += DP) {
 #pragma unroll
-                for (int t = 0; t < TW; ++t) nxt[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + D + d, l);
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const v4 bv = *reinterpret_cast<const v4*>(ybuf + r * ldy + 16 * (K + d) + 4 * q);
+        for (int d = 0; d < DP; ++d) {
+            const int K = K0 + d;
+            const v4 bv = *reinterpret_cast<const v4*>(ybuf + r * ldy + 16 * K + 4 * q);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(cur[d][t][s], bv[s], acc[t]);
-        }
-        if (more) {
+                for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(ring[d][t][s], bv[s], acc[t]);
+            if (K + DP < KC) {
 #pragma unroll
-            for (int d = 0; d < D; ++d)
-#pragma unroll
-                for (int t = 0; t < TW; ++t) cur[d][t] = nxt[d][t];
+                for (int t = 0; t < TW; ++t) ring[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + DP, l);
+            }
+            hook(K);
         }
     }
 }
@@ -167,7 +174,29 @@ __device__ __forceinline__ void stage_row_coeffs(double* sfr, double* sip, const
     }
 }
 
+// Order this wave's LDS writes before later LDS reads of other lanes of the
+// same wave (no workgroup barrier needed: the data is private to the wave).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------
+// Per-workgroup state of a sweep.  Global inputs of a step (right-hand-side
+// rows, forward results z_i, row coefficients of the word-line recovery) are
+// requested before the step's product and consumed after it, so their latency
+// hides behind the matrix cores.
+//
+// Word-line recovery (float64 sweep with node voltages): wave w recovers the
+// VW input vectors w*VW.. of the slab, LR lanes each, in a buffer private to
+// the wave; only the staging of the row coefficients is shared.  The node
+// voltages of a recovered row are written during the next row's product, one
+// 16-byte store per lane every few K chunks, so the stores spread over the
+// whole sweep instead of bursting between products.
 template <typename T, int NT, bool IR, int W>
 struct SweepCtx {
     using acc_t = typename Frag<T>::acc_t;
@@ -175,105 +204,142 @@ struct SweepCtx {
     static constexpr int ldy = n_p + 4;
     static constexpr int TW = 4 * NT / W;    // row tiles per wave
     static constexpr int NTHR = 64 * W;
-    static constexpr int LR = NTHR / 16;     // recovery lanes per input vector
+    static constexpr int VW = 16 / W;        // input vectors a wave recovers
+    static constexpr int LR = 64 / VW;       // lanes per input vector in the recovery
+    static constexpr int CPT = (n_p + NTHR - 1) / NTHR;   // row coefficients per thread
+    static constexpr int NST = VW * NT;      // node-voltage stores per lane and row
     const SweepArgs& a;
-    T* ybuf;
+    T* ybuf;          // [16][ldy] right-hand side / solution panel
+    double* wv;       // [VW][PL] this wave's word-line buffers
+    double* coef;     // [3][PL] fr, ip, G of the row being recovered
     T* Zs;
     const T* H;
     int w, l, q, col, b;
     bool bval;
     T g;
-    double dmax = 0.0, umax = 0.0;   // refinement: largest correction and solution entry seen
+    int lg = 0, PL = 0;                      // recovery segment width (log2), padded row length
+    double dmax = 0.0, umax = 0.0;           // refinement: largest correction and solution entry
+    double pf_fr[CPT], pf_ip[CPT], pf_g[CPT], pf_v = 0.0;
 
+    // Lane (q, col) of wave w holds rows row_of(t, v) of tile t, item v.  In panel
+    // (CPR) order those rows sit at poff + 16 t + v, so every panel access is a
+    // wave-uniform base, one per-lane offset and a small constant.
     __device__ __forceinline__ int row_of(int t, int v) const { return 16 * (TW * w + t) + Frag<T>::drow(q, v); }
-    __device__ __forceinline__ int64_t rowoff(int i) const { return ((int64_t)blockIdx.x * a.m + i) * 16 * n_p + col * n_p; }
-    __device__ __forceinline__ T* zrow(int i) const { return Zs + (int64_t)i * 16 * n_p + col * n_p; }
+    __device__ __forceinline__ uint32_t poff() const { return (uint32_t)(16 * TW * w + 4 * q); }
+    __device__ __forceinline__ uint32_t lane_off() const { return (uint32_t)(col * n_p) + poff(); }
+    __device__ __forceinline__ int64_t slab_row(int i) const { return ((int64_t)blockIdx.x * a.m + i) * 16 * n_p; }
+    __device__ __forceinline__ T* zbase(int i) const { return Zs + (int64_t)i * 16 * n_p; }
+    __device__ __forceinline__ T* zrow(int i) const { return zbase(i) + col * n_p; }
     __device__ __forceinline__ double vin(int i) const { return bval ? a.V[(int64_t)b * a.m + i] : 0.0; }
 
-    // panel <- f_i + g * (z terms); f_i = V_i c_i, or the residual panel R_i when refining
-    __device__ __forceinline__ void set_panel(int i, const acc_t (&zacc)[TW], bool with_acc, int zrow_a, int zrow_b) {
-        const bool from_r = IR && a.iter > 0;
-        const double vb = from_r ? 0.0 : vin(i);
-        const double* ci = a.c + (int64_t)i * n_p;
-        const T* Ri = from_r ? reinterpret_cast<const T*>(a.R) + rowoff(i) : nullptr;
-        __syncthreads();
+    // ---- forward sweep
+    // this lane's rows of the right-hand side of row block i: V_i c_i, or the residual R_i
+    __device__ __forceinline__ void load_rhs(int i, T (&f)[TW][4]) const {
+        if (IR && a.iter > 0) {
+            const T* Ri = reinterpret_cast<const T*>(a.R) + slab_row(i);
+            const uint32_t o = lane_off();
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) f[t][v] = row_of(t, v) < a.n ? Ri[o + 16 * t + v] : (T)0;
+        } else {
+            const double vb = vin(i);
+            const double* ci = a.c + (int64_t)i * n_p;         // zero on the padding
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) f[t][v] = (T)(ci[row_of(t, v)] * vb);
+        }
+    }
+    // panel <- f + g * zacc (+ g * the forward results of rows zrow_a, zrow_b: the twist)
+    __device__ __forceinline__ void set_panel(const T (&f)[TW][4], const acc_t (&zacc)[TW], bool with_acc,
+                                              int zrow_a, int zrow_b) {
+        lds_barrier();
+        const uint32_t o = lane_off(), lo = (uint32_t)(col * ldy) + poff();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int k = row_of(t, v);
-                T y = from_r ? (k < a.n ? Ri[pos<T>(k)] : (T)0) : (T)(ci[k] * vb);
+                T y = f[t][v];
                 if (with_acc) y += g * zacc[t][v];
-                if (zrow_a >= 0) y += g * zrow(zrow_a)[pos<T>(k)];
-                if (zrow_b >= 0) y += g * zrow(zrow_b)[pos<T>(k)];
-                ybuf[col * ldy + pos<T>(k)] = y;
+                if (zrow_a >= 0) y += g * zbase(zrow_a)[o + 16 * t + v];
+                if (zrow_b >= 0) y += g * zbase(zrow_b)[o + 16 * t + v];
+                ybuf[lo + 16 * t + v] = y;
             }
-        __syncthreads();
-    }
-    __device__ __forceinline__ void put_panel(const acc_t (&u)[TW]) {
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < TW; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) ybuf[col * ldy + pos<T>(row_of(t, v))] = u[t][v];
-        __syncthreads();
+        lds_barrier();
     }
     __device__ __forceinline__ void store_z(int i, const acc_t (&z)[TW]) {
-        T* zr = zrow(i);
+        T* zr = zbase(i);
+        const uint32_t o = lane_off();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) zr[pos<T>(row_of(t, v))] = z[t][v];
+            for (int v = 0; v < 4; ++v) zr[o + 16 * t + v] = z[t][v];
     }
-    // Word lines of row i from the bit-line voltages in the panel (LR lanes per
-    // input vector), then both node voltages of the row go out in the paper's
-    // interleaved order, coalesced.  wb: [16][padded n] + 2 padded coefficient rows.
-    __device__ __forceinline__ void recover_row(int i, double* wb) {
-        if (a.node_v == nullptr) return;
-        const int n = a.n, cc = threadIdx.x / LR, s = threadIdx.x % LR;
-        const int lg = seg_lg(n, LR), PL = padded_len(n, LR);
-        double* sfr = wb + 16 * PL;
-        double* sip = sfr + PL;
-        stage_row_coeffs(sfr, sip, a.fr, a.ip, i, n, lg, NTHR);
-        const int bb = 16 * (int)blockIdx.x + cc;
-        const double* Gi = a.Gc + (int64_t)i * n;
-        const double vb = (bb < a.B) ? a.V[(int64_t)bb * a.m + i] : 0.0;
-        double* wv = wb + cc * PL;
-        for (int j = s; j < n; j += LR)
-            wv[padj(j, lg)] = Gi[j] * (double)ybuf[cc * ldy + pos<T>(j)] + (j == 0 ? a.g_src * vb : 0.0);
-        __syncthreads();
-        tridiag_solve_lanes<LR>(wv, sfr, sip, a.g_wl, n, s, lg);
-        __syncthreads();
-        const int two_n = 2 * n;
-        const int64_t mn2 = (int64_t)2 * a.m * n;
-        for (int c2 = 0; c2 < 16; ++c2) {          // one input vector at a time, coalesced
-            const int b2 = 16 * (int)blockIdx.x + c2;
-            if (b2 >= a.B) break;
-            double* out = a.node_v + (int64_t)b2 * mn2 + (int64_t)i * two_n;
-            for (int k = threadIdx.x; k < two_n; k += NTHR) {
-                const int j = k >> 1;
-                out[k] = (k & 1) ? (double)ybuf[c2 * ldy + pos<T>(j)] : wb[c2 * PL + padj(j, lg)];
+
+    // ---- back sweep
+    __device__ __forceinline__ void load_z(int i, T (&zp)[TW][4]) const {
+        const T* zr = zbase(i);
+        const uint32_t o = lane_off();
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zp[t][v] = zr[o + 16 * t + v];
+    }
+    // refinement: the float64 solution before this sweep (zero at the first sweep)
+    __device__ __forceinline__ void load_u(int i, double (&up)[TW][4]) const {
+        const double* ui = a.Uin + slab_row(i);
+        const uint32_t o = lane_off();
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) up[t][v] = (IR && a.iter > 0) ? ui[o + 16 * t + v] : 0.0;
+    }
+    // acc <- z_i + g * acc
+    __device__ __forceinline__ void back_step(const T (&zp)[TW][4], acc_t (&acc)[TW]) const {
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][v] = zp[t][v] + g * acc[t][v];
+    }
+    // panel <- u (and, when recovering, the staged coefficients of the row)
+    __device__ __forceinline__ void put_panel(const acc_t (&u)[TW], bool commit) {
+        lds_barrier();
+        const uint32_t lo = (uint32_t)(col * ldy) + poff();
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ybuf[lo + 16 * t + v] = u[t][v];
+        if (commit) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int j = (int)threadIdx.x + c * NTHR;
+                if (j < a.n) {
+                    const int p = padj(j, lg);
+                    coef[p] = pf_fr[c];
+                    coef[PL + p] = pf_ip[c];
+                    coef[2 * PL + p] = pf_g[c];
+                }
             }
         }
+        lds_barrier();
     }
-    // Row i of the back sweep is final in acc: emit the currents of row m-1, or (when
+    // Row i of the back sweep is final in u: emit the currents of row m-1, or (when
     // refining) add the correction to the float64 solution.
-    __device__ __forceinline__ void settle(int i, const acc_t (&u)[TW]) {
+    __device__ __forceinline__ void settle(int i, const acc_t (&u)[TW], const double (&up)[TW][4]) {
         if (!IR) {
             if (i == a.m - 1) currents(u);
             return;
         }
-        const int64_t ro = rowoff(i);
-        const double* ui = a.Uin + ro;
-        double* uo = a.Uout + ro;
+        double* uo = a.Uout + slab_row(i);
+        const uint32_t o = lane_off();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int p = pos<T>(row_of(t, v));
                 const double d = (double)u[t][v];
-                const double x = (a.iter > 0 ? ui[p] : 0.0) + d;
-                uo[p] = x;
+                const double x = up[t][v] + d;
+                uo[o + 16 * t + v] = x;
                 dmax = fmax(dmax, fabs(d));
                 umax = fmax(umax, fabs(x));
                 if (i == a.m - 1) {
@@ -281,14 +347,6 @@ struct SweepCtx {
                     if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * x;
                 }
             }
-    }
-    // acc <- z_i + g * acc (back-sweep step)
-    __device__ __forceinline__ void back_step(int i, acc_t (&acc)[TW]) {
-        const T* zr = zrow(i);
-#pragma unroll
-        for (int t = 0; t < TW; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[t][v] = zr[pos<T>(row_of(t, v))] + g * acc[t][v];
     }
     __device__ __forceinline__ void currents(const acc_t (&u)[TW]) {
 #pragma unroll
@@ -299,6 +357,54 @@ struct SweepCtx {
                 if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * (double)u[t][v];
             }
     }
+
+    // ---- word-line recovery: T_i w_i = g_src V_i e_0 + Gam_i u_i
+    // request row i's coefficients and this lane's input (staged by put_panel)
+    __device__ __forceinline__ void prefetch_row(int i) {
+        const int64_t o = (int64_t)i * a.n;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int jj = min((int)threadIdx.x + c * NTHR, a.n - 1);
+            pf_fr[c] = a.fr[o + jj];
+            pf_ip[c] = a.ip[o + jj];
+            pf_g[c] = a.Gc[o + jj];
+        }
+        const int bb = 16 * (int)blockIdx.x + w * VW + l / LR;
+        pf_v = (bb < a.B) ? a.V[(int64_t)bb * a.m + i] : 0.0;
+    }
+    // word lines of the row whose bit-line voltages are in the panel, for this wave's vectors
+    __device__ __forceinline__ void solve_row() {
+        const int n = a.n, v = l / LR, s = l % LR, cc = w * VW + v;
+        double* wr = wv + v * PL;
+        for (int j = s; j < n; j += LR)
+            wr[padj(j, lg)] = coef[2 * PL + padj(j, lg)] * (double)ybuf[cc * ldy + pos<T>(j)] +
+                              (j == 0 ? a.g_src * pf_v : 0.0);
+        wave_lds_fence();
+        tridiag_solve_lanes<LR>(wr, coef, coef + PL, a.g_wl, n, s, lg);
+        wave_lds_fence();
+    }
+    // k-th node-voltage store of recovered row i (i < 0: none): the pair (w_j, u_j) of
+    // this wave's vector k / NT, j = 64 (k % NT) + lane, in the interleaved node order.
+    // The lane-dependent addresses are rebuilt from an opaque copy of the lane index,
+    // so the compiler cannot hoist all NST of them out of the row loop into registers.
+    __device__ __forceinline__ void out_store(int i, int k) const {
+        const int v = k / NT, cc = w * VW + v;
+        const int bb = 16 * (int)blockIdx.x + cc;              // wave-uniform
+        if (i < 0 || bb >= a.B) return;
+        int lane = l;
+        asm volatile("" : "+v"(lane));
+        const int j = 64 * (k % NT) + lane;
+        if (j >= a.n) return;
+        const double wj = wv[v * PL + padj(j, lg)];
+        const double uj = (double)ybuf[cc * ldy + pos<T>(j)];
+        double* base = a.node_v + ((int64_t)bb * a.m + i) * 2 * a.n;
+        *reinterpret_cast<d2_t*>(base + 2 * j) = d2_t{wj, uj};
+    }
+    __device__ __forceinline__ void out_row(int i) const {
+#pragma unroll
+        for (int k = 0; k < NST; ++k) out_store(i, k);
+    }
+
     // Refinement bookkeeping for the slab: per input vector, stop when the error left after
     // this correction, estimated as |d| * min(1, |d| / |d_prev|), is <= tol * |u|.
     __device__ __forceinline__ void decide(double* red) {
@@ -307,12 +413,12 @@ struct SweepCtx {
             dm = fmax(dm, __shfl_xor(dm, off));
             um = fmax(um, __shfl_xor(um, off));
         }
-        __syncthreads();
+        lds_barrier();
         if (l < 16) {
             red[w * 16 + l] = dm;
             red[16 * W + w * 16 + l] = um;
         }
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x < 16) {
             double D = 0.0, U = 0.0;
             for (int k = 0; k < W; ++k) {
@@ -337,9 +443,38 @@ struct SweepCtx {
     }
 };
 
+// Node-voltage stores of a recovered row, spread over the K chunks of a product.
+template <typename Ctx>
+struct OutHook {
+    const Ctx& x;
+    int row;
+    __device__ __forceinline__ void operator()(int K) const {
+        constexpr int STEP = Ctx::n_p / 16 / Ctx::NST;
+        if ((K + 1) % STEP == 0) {
+            // keep each store's loads in place: hoisted together they would
+            // hold every pending store's data in registers during the product
+            __builtin_amdgcn_sched_barrier(0);
+            x.out_store(row, K / STEP);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+};
+
 template <int NT> struct SweepWaves { static constexpr int value = (NT % 2 == 0) ? 8 : 4; };
 
+// LDS bytes of a sweep: panel, then either the word-line buffers and row coefficients
+// (recovery) or the refinement's reduction scratch.
 template <typename T, int NT, bool IR>
+__host__ __device__ inline size_t sweep_lds_bytes(int n)
+{
+    constexpr int W = SweepWaves<NT>::value;
+    const size_t panel = 16 * (size_t)(64 * NT + 4) * sizeof(T);
+    const size_t extra = IR ? 2 * 16 * W * sizeof(double)
+                            : (16 + 3) * (size_t)padded_len(n, 64 / (16 / W)) * sizeof(double);
+    return panel + extra;
+}
+
+template <typename T, int NT, bool IR, bool REC>
 __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(SweepArgs a)
 {
     constexpr int W = SweepWaves<NT>::value;
@@ -350,73 +485,120 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
     if (IR && a.iter > 0 && a.slab_done[blockIdx.x]) return;
     const int m = a.m, kt = m / 2;
     const int l = threadIdx.x & 63;
-    Ctx x{a, reinterpret_cast<T*>(smem_raw),
+    Ctx x{a, reinterpret_cast<T*>(smem_raw), nullptr, nullptr,
           reinterpret_cast<T*>(a.Z) + (int64_t)blockIdx.x * m * 16 * Ctx::n_p,
-          reinterpret_cast<const T*>(a.H), (int)(threadIdx.x >> 6), l, l >> 4, l & 15,
+          reinterpret_cast<const T*>(a.H), __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l, l >> 4, l & 15,
           16 * (int)blockIdx.x + (l & 15), false, (T)a.g_bl};
     x.bval = x.b < a.B;
+    x.lg = seg_lg(a.n, Ctx::LR);
+    x.PL = padded_len(a.n, Ctx::LR);
+    double* extra = reinterpret_cast<double*>(smem_raw + 16 * Ctx::ldy * sizeof(T));
+    x.wv = extra + x.w * Ctx::VW * x.PL;
+    x.coef = extra + 16 * x.PL;
     const int64_t blk = (int64_t)Ctx::n_p * Ctx::n_p;
-    double* wb = reinterpret_cast<double*>(smem_raw + 16 * Ctx::ldy * sizeof(T));
     acc_t acc[TW];
+    T f[TW][4];
+    const NoHook none{};
     // forward, top chain
     if (kt > 0) {
-        x.set_panel(0, acc, false, -1, -1);
+        x.load_rhs(0, f);
+        x.set_panel(f, acc, false, -1, -1);
         for (int i = 0; i < kt; ++i) {
-            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
+            if (i + 1 < kt) x.load_rhs(i + 1, f);
+            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
             x.store_z(i, acc);
-            if (i + 1 < kt) x.set_panel(i + 1, acc, true, -1, -1);
+            if (i + 1 < kt) x.set_panel(f, acc, true, -1, -1);
         }
     }
     // forward, bottom chain
     if (m - 1 > kt) {
-        x.set_panel(m - 1, acc, false, -1, -1);
+        x.load_rhs(m - 1, f);
+        x.set_panel(f, acc, false, -1, -1);
         for (int i = m - 1; i > kt; --i) {
-            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
+            if (i - 1 > kt) x.load_rhs(i - 1, f);
+            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
             x.store_z(i, acc);
-            if (i - 1 > kt) x.set_panel(i - 1, acc, true, -1, -1);
+            if (i - 1 > kt) x.set_panel(f, acc, true, -1, -1);
         }
     }
     // twist row
-    x.set_panel(kt, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
-    panel_product<T, NT, TW>(acc, x.H + kt * blk, x.ybuf, Ctx::ldy, x.w, l);
+    double up[TW][4];
+    x.load_rhs(kt, f);
+    x.set_panel(f, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
+    x.load_u(kt, up);
+    if (REC) x.prefetch_row(kt);
+    panel_product<T, NT, TW>(acc, x.H + kt * blk, x.ybuf, Ctx::ldy, x.w, l, none);
     x.store_z(kt, acc);             // the downward back sweep restarts from this row
-    x.settle(kt, acc);
-    const bool fused = !IR && a.node_v != nullptr;
-    if (fused) {
-        x.put_panel(acc);
-        x.recover_row(kt, wb);
+    x.settle(kt, acc, up);
+    int pend = -1;                  // recovered row whose node voltages are not yet written
+    if (REC) {
+        x.put_panel(acc, true);
+        x.solve_row();
+        pend = kt;
     }
     // back, upward
     if (kt > 0) {
-        if (!fused) x.put_panel(acc);
+        if (!REC) x.put_panel(acc, false);
         for (int i = kt - 1; i >= 0; --i) {
+            T zp[TW][4];
+            x.load_z(i, zp);
+            x.load_u(i, up);
             acc_t u[TW];
-            panel_product<T, NT, TW>(u, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
-            x.back_step(i, u);
-            x.settle(i, u);
-            if (i > 0 || fused) x.put_panel(u);
-            if (fused) x.recover_row(i, wb);
+            if (REC) {
+                x.prefetch_row(i);
+                panel_product<T, NT, TW>(u, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
+            } else {
+                panel_product<T, NT, TW>(u, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+            }
+            x.back_step(zp, u);
+            x.settle(i, u, up);
+            if (REC) {
+                x.put_panel(u, true);
+                x.solve_row();
+                pend = i;
+            } else if (i > 0) {
+                x.put_panel(u, false);
+            }
         }
     }
     // back, downward
     if (kt + 1 < m) {
+        if (REC && pend >= 0) {
+            x.out_row(pend);        // the panel is about to be reset to u_kt
+            pend = -1;
+        }
         {
-            const T* zr = x.zrow(kt);
+            T zp[TW][4];
+            x.load_z(kt, zp);
 #pragma unroll
             for (int t = 0; t < TW; ++t)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[t][v] = zr[pos<T>(x.row_of(t, v))];
+                for (int v = 0; v < 4; ++v) acc[t][v] = zp[t][v];
         }
-        x.put_panel(acc);
+        x.put_panel(acc, false);
         for (int i = kt + 1; i < m; ++i) {
-            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l);
-            x.back_step(i, acc);
-            x.settle(i, acc);
-            if (i < m - 1 || fused) x.put_panel(acc);
-            if (fused) x.recover_row(i, wb);
+            T zp[TW][4];
+            x.load_z(i, zp);
+            x.load_u(i, up);
+            if (REC) {
+                x.prefetch_row(i);
+                panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
+            } else {
+                panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+            }
+            x.back_step(zp, acc);
+            x.settle(i, acc, up);
+            if (REC) {
+                x.put_panel(acc, true);
+                x.solve_row();
+                pend = i;
+            } else if (i < m - 1) {
+                x.put_panel(acc, false);
+            }
         }
     }
-    if (IR) x.decide(wb);
+    if (REC && pend >= 0) x.out_row(pend);
+    if (IR) x.decide(extra);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,9 +630,9 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
     const double* Ui = a.U + (((int64_t)slab * m + i) * 16 + colg) * n_p;
     double* w = wb + c * PL;
     for (int j = s; j < n; j += kResLanes) w[padj(j, lg)] = Gi[j] * Ui[j];
-    __syncthreads();
+    lds_barrier();
     tridiag_solve_lanes<kResLanes>(w, sfr, sip, a.g_wl, n, s, lg);
-    __syncthreads();
+    lds_barrier();
     const double vb = (b < a.B) ? a.V[(int64_t)b * m + i] : 0.0;
     const double* ci = a.c + (int64_t)i * n_p;
     const double* qi = a.q + (int64_t)i * n;
@@ -498,15 +680,15 @@ __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
             ub[e] = (double)Zi[(half * kRecCols + cc) * n_p + pos<T>(j)];
         }
     }
-    __syncthreads();
+    lds_barrier();
     const double* Gi = a.Gc + (int64_t)i * n;
     const double vin = (b < a.B) ? a.V[(int64_t)b * m + i] : 0.0;
     const double* u = ub + c * n;
     double* wv = wb + c * PL;
     for (int j = s; j < n; j += kResLanes) wv[padj(j, lg)] = Gi[j] * u[j] + (j == 0 ? a.g_src * vin : 0.0);
-    __syncthreads();
+    lds_barrier();
     tridiag_solve_lanes<kResLanes>(wv, sfr, sip, a.g_wl, n, s, lg);
-    __syncthreads();
+    lds_barrier();
     if (a.node_v == nullptr) return;
     for (int cc = 0; cc < kRecCols; ++cc) {
         const int bb = 16 * slab + half * kRecCols + cc;
@@ -524,10 +706,14 @@ template <typename T, int NT, bool IR>
 hipError_t launch_sweep_nt(const SweepArgs& a, hipStream_t s)
 {
     constexpr int W = SweepWaves<NT>::value;
-    const size_t panel = 16 * (size_t)(64 * NT + 4) * sizeof(T);
-    const size_t extra = IR ? 2 * 16 * W * sizeof(double)
-                            : (16 + 2) * (size_t)padded_len(a.n, 4 * W) * sizeof(double);
-    hipLaunchKernelGGL((sweep_kernel<T, NT, IR>), dim3(a.nslab), dim3(64 * W), panel + extra, s, a);
+    const size_t lds = sweep_lds_bytes<T, NT, IR>(a.n);
+    if constexpr (!IR) {
+        if (a.node_v != nullptr) {
+            hipLaunchKernelGGL((sweep_kernel<T, NT, IR, true>), dim3(a.nslab), dim3(64 * W), lds, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((sweep_kernel<T, NT, IR, false>), dim3(a.nslab), dim3(64 * W), lds, s, a);
     return hipGetLastError();
 }
 
@@ -549,9 +735,9 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t s)
 
 }  // namespace xbk
 
-hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, bool fp32, hipStream_t s)
+hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s)
 {
-    return fp32 ? xbk::launch_sweep<float, false>(a, s) : xbk::launch_sweep<double, false>(a, s);
+    return xbk::launch_sweep<double, false>(a, s);
 }
 
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s)

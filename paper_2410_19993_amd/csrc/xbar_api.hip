@@ -26,6 +26,7 @@ struct Buffers {
     void* Z = nullptr;        // [nslab][m][16][n_p]
     double* Iout = nullptr;   // [max_batch][n]
     int* flags = nullptr;     // [kNumFlags]
+    double* sink = nullptr;   // [128]: target of the sweep's masked-off node-voltage stores
     // Newton-Schulz factor: per chain S, X[2], Q ([n_p][n_p]) and dprev ([n_p])
     void* ns_S[2] = {nullptr, nullptr};
     void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -138,7 +139,7 @@ void free_all(xbar_plan p)
 {
     Buffers& d = p->d;
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
-                   d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags,
+                   d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags, d.sink,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
                    d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_done,
                    d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final};
@@ -226,6 +227,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     A(&d.Z, (int64_t)p->nslab_max * m * 16 * n_p * es);
     A((void**)&d.Iout, (int64_t)max_batch * n * 8);
     A((void**)&d.flags, xbk::kNumFlags * sizeof(int));
+    A((void**)&d.sink, 128 * sizeof(double));
     for (int c = 0; c < 2; ++c) {
         A(&d.ns_S[c], n_p * n_p * es);
         A(&d.ns_X[c][0], n_p * n_p * es);
@@ -410,6 +412,7 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
     s.Z = p->d.Z;
     s.Iout = p->d.Iout;
     s.flags = p->d.flags;
+    s.sink = p->d.sink;
     const bool ir = p->prec != XBAR_FP64;
     s.node_v = ir ? nullptr : node_v;     // float64: recovery fused into the back sweep
     s.Gc = p->d.Gc;
@@ -419,7 +422,7 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
     s.g_wl = 1.0 / p->g.r_wl;
     if (p->timing && !p->t_sweep.begin(p->stream)) return XBAR_ERR_DEVICE;
     if (!ir) {
-        if (xbk_launch_sweep(s, false, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+        if (xbk_launch_sweep(s, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
     } else {
         // float sweeps refined in float64: sweep 0 solves with V c, each later sweep
         // corrects U by the solution for the float64 residual of the previous U.
