@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA = 78.6e12     # MI355X dense FP64 matrix, FLOP/s
 PEAK_FP32_MFMA = 157.3e12
 PEAK_HBM = 8.0e12            # B/s
+# HBM traffic of the dominant kernel per launch, from two counter runs (FETCH_SIZE,
+# WRITE_SIZE) scaled by what the same counters read for a plain copy; valid only
+# while the kernel's sources are unchanged since the counters were taken.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_c3_512x512_b4096_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_19993_amd", "csrc", f) for f in ("sweep.hip", "common.h")]
 METRIC = ("input-vector solves/s, 512×512 xbar: FP64 LU vs FP32+IR at 1e-9 rel err")
 
 
@@ -33,7 +38,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, rows=16, vectors=64):
+def cpu_baseline(wl, rows=64, vectors=128):
     """Time the oracle on a bounded slice of the same workload and scale it.
 
     The oracle's banded LU costs rows x (half-bandwidth)^2 and its substitution
@@ -63,6 +68,27 @@ def cpu_baseline(wl, rows=16, vectors=64):
                        f"x{scale:g} in rows and to {wl.B} vectors (banded LU and substitution "
                        f"cost are linear in rows)"),
             "seconds_measured": t_all + t_fact, "extrapolated_seconds": t_full}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """Bytes per launch of the sweep kernel from the committed counter summary, or None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.loads(fh.read().split("JSON:", 1)[1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -151,7 +177,8 @@ def main():
     achieved = sweep_flops / (k_sweep * 1e-3)
     roof = {"bound": "mfma", "kernel": "sweep_kernel<double,8>", "achieved": achieved / 1e12,
             "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA,
-            "traffic": None, "flops_per_launch": sweep_flops, "avg_launch_ms": k_sweep}
+            "traffic": measured_traffic(wl.name), "flops_per_launch": sweep_flops,
+            "avg_launch_ms": k_sweep}
     result = {
         "metric": METRIC, "value": B / (ms64 * 1e-3), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms64,
