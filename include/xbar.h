@@ -55,7 +55,8 @@ typedef enum {
 typedef enum {
     XBAR_FP64 = 0,      /* factor and substitution in float64 (the paper's method)         */
     XBAR_FP32_IR = 1,   /* factor and substitution in float32 on MFMA, refined in float64  */
-    XBAR_BF16_IR = 2    /* bfloat16 block inverses (float32 accumulate), refined in float64 */
+    XBAR_BF16_IR = 2    /* reserved (bfloat16 block inverses): not built, xbar_create
+                           returns XBAR_ERR_ARG                                          */
 } xbar_precision;
 
 typedef struct {
@@ -89,9 +90,11 @@ typedef struct {
  * up to max_batch input vectors (nothing is allocated by later calls).
  *   p            precision mode.
  *   max_batch    1 <= max_batch.
- *   ir_tol       IR modes: stop when, for every input vector, the largest
- *                correction of the bit-line voltages is <= ir_tol times
- *                their largest magnitude; 0 selects 1e-13.  Ignored for FP64.
+ *   ir_tol       IR modes: a slab of input vectors stops refining when, for each
+ *                of its vectors, the error estimate |d| min(1, |d| / |d_prev|)
+ *                (d: the latest correction of the bit-line voltages, max norm)
+ *                is <= ir_tol times the largest bit-line voltage; 0 selects
+ *                1e-12.  Must be finite, 0 <= ir_tol < 1.  Ignored for FP64.
  *   ir_max_iter  IR modes: refinement steps allowed, 1..100 (0 selects 10).
  *   hip_stream   hipStream_t the plan's work is queued on (NULL = null stream).
  * Returns XBAR_ERR_ARG, XBAR_ERR_DEVICE, XBAR_ERR_ALLOC or XBAR_OK.
@@ -160,9 +163,13 @@ typedef enum { XBAR_FACTOR_AUTO = 0, XBAR_FACTOR_GJ = 1, XBAR_FACTOR_NS = 2 } xb
 xbar_status xbar_set_factor_method(xbar_plan plan, xbar_factor_method method);
 
 /*
- * Per-kernel timing, measured with HIP events recorded on the plan's stream
- * around each kernel launch of the calls above (only while enabled).
- * Times are accumulated milliseconds; *_launches count the kernels timed.
+ * Phase timing, measured with HIP events recorded on the plan's stream
+ * around each phase of the calls above (only while enabled): one interval
+ * per xbar_assemble (condense), per xbar_factor (all its kernels), per
+ * xbar_solve_batch (its substitution sweeps; in FP64 mode that is exactly
+ * one kernel, the sweep with the word-line recovery fused) and per
+ * word-line recovery launch of the IR modes.  Times are accumulated
+ * milliseconds; *_launches count the intervals.
  */
 typedef struct {
     double condense_ms;   int64_t condense_launches;   /* xbar_assemble                 */
