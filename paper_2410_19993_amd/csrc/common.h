@@ -139,14 +139,26 @@ struct NSJob {
     int chain;               // which NSChain buffers
 };
 
+// Device-driven schedule of the Newton-Schulz factor.  Each launch ("slot") reads
+// every chain's state, does that chain's phase (form the pivot block and the
+// first iterate, a residual product, or an update product) and writes the
+// chain's next state into the other parity, so no launch is spent on a row
+// that has already converged.
+enum : int { kNsForm = 0, kNsResid = 1, kNsUpdate = 2, kNsWait = 3, kNsFinished = 4 };
+struct NSState {
+    int row;      // crossbar row being inverted
+    int phase;    // kNs*
+    int it;       // Newton-Schulz step of the row
+    int slots;    // slot count at which the chain finished (kNsFinished), else 0
+};
+
 struct NSArgs {
     int m, n, n_p;
     double g2;
     void* H;                 // [m][n_p][n_p] FRG: E_i on entry, H_i on exit
-    NSChain ch[2];
-    NSJob job[2];
-    double* part;              // [2][n_p/32]^2 per-workgroup max |I - X P| of the current step
-    int* done;                 // [m] row finished
+    NSChain ch[2];           // top chain (and the twist row), bottom chain
+    NSState* state;          // [2 parities][2 chains]
+    double* part;            // [2 chains][(n_p/32)^2] per-workgroup max |I - X P| of the current step
     int* flags;
     int max_iter;
 };
@@ -242,7 +254,8 @@ struct RecoverArgs {
 // Host-side launchers (defined in the .hip files, called by the C ABI layer).
 hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
-hipError_t xbk_launch_factor_ns(const xbk::NSArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s);
+hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int first, int count, hipStream_t s);
 hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);

@@ -13,12 +13,21 @@
 // workgroups; no small serial inversion sits on the critical path.
 //
 // The largest |Q_k| entry is reduced on the device (per-workgroup partials,
-// combined by every workgroup of the following update).  When it is <= 1e-10 the
-// update just applied leaves an error <= 1e-20 (plus rounding; 1e-4 and 1e-8
-// for the float32 factor of the refinement mode), the result is
-// written over E_i and later launches for the row exit at once.  A row still
+// combined by every workgroup of the following update).  When it is <= 1e-9,
+// ||Q_k||_inf <= n_p 1e-9 and the update just applied leaves
+// ||I - X_{k+1} P||_inf <= (n_p 1e-9)^2 <= 2.7e-13 for n_p <= 512 (in practice
+// float64 rounding: consecutive pivots of a chain start the iteration at about
+// 4e-6, then 3e-10, then 3e-15).  The float32 factor of the refinement mode
+// stops at 1e-4 and relies on the refinement.  The result is written over E_i
+// and later launches for the row exit at once.  A row still
 // above the threshold after its last step raises kNsFail, and the host then
 // refactors with Gauss-Jordan elimination (factor.hip).
+//
+// The schedule is driven by the device: each launch (slot) does one phase per
+// chain (form, residual product, update product) and hands the chain's next
+// state to the following launch, so a converged row costs no further launches.
+// The host launches an estimate of the slots needed, reads the two states
+// back, and launches more until both chains have finished.
 //
 // Every block here (E_i, H_i, S, X, Q) is stored fragment-tiled (FRG), and
 // a product C = A B^T is formed with the A slot of the matrix cores fed from
@@ -32,8 +41,8 @@
 
 namespace xbk {
 
-constexpr double kNsDone = 1e-10;      // float64: update leaves <= 1e-20 + rounding
-constexpr double kNsDoneF32 = 1e-4;    // float32: update leaves <= 1e-8, at float rounding
+constexpr double kNsDone = 1e-9;       // float64: see the bound above
+constexpr double kNsDoneF32 = 1e-4;    // float32: at float rounding after the update
 
 template <typename T> struct V4;
 template <> struct V4<double> { using type = d4_t; };
@@ -45,21 +54,42 @@ __device__ inline const T* hslot(const NSArgs& a, int row)
     return row < 0 ? nullptr : reinterpret_cast<const T*>(a.H) + (int64_t)row * a.n_p * a.n_p;
 }
 
-// Form P = E_row - g^2 (H_a + H_b) and the starting iterate X_0 (identity on the padding).
+// Pivot block of row `row` in chain `chain` (twisted order): the top chain takes rows
+// 0..kt-1 and then the twist row kt = m/2, the bottom chain rows m-1..kt+1.
+__device__ inline NSJob ns_job(int m, int chain, int row)
+{
+    const int kt = m / 2;
+    if (row == kt) return NSJob{kt, kt >= 1 ? kt - 1 : -1, kt + 1 <= m - 1 ? kt + 1 : -1, 0, 0};
+    if (chain == 0) return NSJob{row, row > 0 ? row - 1 : -1, -1, row > 0 ? 1 : 0, 0};
+    return NSJob{row, row < m - 1 ? row + 1 : -1, -1, row < m - 1 ? 1 : 0, 1};
+}
+
+// State of a chain once `row` is inverted.
+__device__ inline NSState ns_advance(int m, int chain, int row, int slot)
+{
+    const int kt = m / 2;
+    if (chain == 0) {
+        if (row == kt) return NSState{row, kNsFinished, 0, slot + 1};
+        if (row + 1 < kt) return NSState{row + 1, kNsForm, 0, 0};
+        return NSState{kt, kNsWait, 0, 0};           // the twist needs the bottom chain's last inverse
+    }
+    if (row - 1 > kt) return NSState{row - 1, kNsForm, 0, 0};
+    return NSState{-1, kNsFinished, 0, slot + 1};
+}
+
+// Form P = E_row - g^2 (H_a + H_b) and the starting iterate X_0 (identity on the
+// padding); element e0, e0 + stride, ... of the FRG block.
 template <typename T>
-__global__ __launch_bounds__(256) void ns_form_kernel(NSArgs a)
+__device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const NSChain& ch, int64_t e0, int64_t stride)
 {
     const int n_p = a.n_p, n = a.n;
     const int64_t nn = (int64_t)n_p * n_p;
-    const NSJob& job = a.job[blockIdx.y];
-    const NSChain& ch = a.ch[job.chain];
     const T* E = hslot<T>(a, job.row);
     const T* Ha = hslot<T>(a, job.dep_a);
     const T* Hb = hslot<T>(a, job.dep_b);
     T* S = reinterpret_cast<T*>(ch.S);
     T* X = reinterpret_cast<T*>(ch.X[0]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.done[job.row] = 0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = e0; e < nn; e += stride) {
         int r, c;
         frg_rc<T>(e, n_p, r, c);
         T s, x;
@@ -102,22 +132,16 @@ __device__ __forceinline__ typename V4<T>::type load_frag(const T* __restrict__ 
 // The four waves split K = n_p into quarters (NT = n_p / 64 chunks of 16
 // each), every wave accumulating all four 16x16 output tiles; the partial
 // sums meet in LDS and wave w finishes output tile w.
-//   MODE 0:  Q = I - X_k S          (and the row's max |Q|)
-//   MODE 1:  X_{k+1} = X_k + Q X_k  (and H_row when the step converged)
+//   MODE 0:  Q = I - X_k S          (and the workgroup's max |Q|)
+//   MODE 1:  X_{k+1} = X_k + Q X_k  (and H_row when the step converged or was the last)
+// MODE 1 returns whether the step converged (the same answer in every workgroup).
 template <typename T, int MODE, int NT>
-__global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
+__device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, const NSChain& ch, int it,
+                                           int chain, int tile, bool last, T* red, double* wmax)
 {
     using v4 = typename V4<T>::type;
     using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT, kt = n_p / 16, tdim = n_p / 32, tiles = tdim * tdim;
-    __shared__ __align__(16) T red[4 * 4 * 4 * 64];       // [wave][output tile][item][lane]
-    __shared__ double wmax[256];
-    const NSJob& job = a.job[blockIdx.x / tiles];
-    if (a.done[job.row]) return;
-    const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
-    if (it >= maxit) return;
-    const NSChain& ch = a.ch[job.chain];
-    const int tile = blockIdx.x % tiles;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
     const T* Xin = reinterpret_cast<const T*>(ch.X[it & 1]);
@@ -173,7 +197,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
     // wave w owns output tile (TR + w/2, TC + w%2); lane l item v is (row, col) of C
     const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
     const int row = 16 * (TR + (w >> 1)) + (l & 15);
-    double* part = a.part + (int64_t)(blockIdx.x / tiles) * tiles;    // this job's partials
+    double* part = a.part + (int64_t)chain * tiles;    // this chain's partials
     if (MODE == 0) {
         T* Q = reinterpret_cast<T*>(ch.Q);
         double mx = 0.0;
@@ -196,8 +220,9 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
             for (int k = 1; k < 4; ++k) t = (wmax[k] > t || wmax[k] != wmax[k]) ? wmax[k] : t;
             part[tile] = t;
         }
+        return false;
     } else {
-        // max over the job's workgroup partials of Q's step
+        // max over the chain's workgroup partials of Q's step
         double mx = 0.0;
         for (int k = threadIdx.x; k < tiles; k += 256) {
             const double o = part[k];
@@ -221,79 +246,98 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(NSArgs a, int it)
             const int64_t o = base + frg_slot<T>(l, v);
             const T x = Xin[o] + sum[v];
             Xout[o] = x;
-            if (fin) Hr[o] = x;
+            if (fin || last) Hr[o] = x;
         }
-        if (fin) {
-            if (threadIdx.x == 0) a.done[job.row] = 1;
-        } else if (it == maxit - 1 && threadIdx.x == 0 && tile == 0) {
-            atomicOr(a.flags + kNsFail, 1);
-        }
+        return fin;
     }
 }
 
-template <typename T, int MODE, int NT>
-hipError_t launch_gemm_nt(const NSArgs& f, int njobs, int it, hipStream_t s)
+// One slot of the schedule: every chain does its current phase with its share of
+// the grid ((n_p/32)^2 workgroups per chain), and workgroup 0 of the chain writes
+// the chain's next state.  A chain that waits or has finished only carries its
+// state over.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int slot)
 {
     constexpr int tiles = (2 * NT) * (2 * NT);
-    hipLaunchKernelGGL((ns_gemm_kernel<T, MODE, NT>), dim3(njobs * tiles), dim3(256), 0, s, f, it);
-    return hipGetLastError();
+    __shared__ __align__(16) T red[4 * 4 * 4 * 64];       // product partials [wave][output tile][item][lane]
+    __shared__ double wmax[256];
+    const int chain = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const NSState* cur = a.state + 2 * (slot & 1);
+    NSState* nxt = a.state + 2 * ((slot + 1) & 1);
+    const int m = a.m;
+    NSState s = cur[chain];
+    if (s.phase == kNsWait && cur[1].phase == kNsFinished) s = NSState{m / 2, kNsForm, 0, 0};
+    NSState ns = s;
+    if (s.phase == kNsForm || s.phase == kNsResid || s.phase == kNsUpdate) {
+        const NSJob job = ns_job(m, chain, s.row);
+        const NSChain& ch = a.ch[job.chain];
+        const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
+        if (s.phase == kNsForm) {
+            ns_form<T>(a, job, ch, (int64_t)tile * 256 + threadIdx.x, (int64_t)tiles * 256);
+            ns = NSState{s.row, kNsResid, 0, 0};
+        } else if (s.phase == kNsResid) {
+            ns_product<T, 0, NT>(a, job, ch, s.it, chain, tile, false, red, wmax);
+            ns = NSState{s.row, kNsUpdate, s.it, 0};
+        } else {
+            const bool last = s.it + 1 >= maxit;
+            const bool fin = ns_product<T, 1, NT>(a, job, ch, s.it, chain, tile, last, red, wmax);
+            if (fin || last) {
+                if (!fin && tile == 0 && threadIdx.x == 0) atomicOr(a.flags + kNsFail, 1);
+                ns = ns_advance(m, chain, s.row, slot);
+            } else {
+                ns = NSState{s.row, kNsResid, s.it + 1, 0};
+            }
+        }
+    }
+    if (tile == 0 && threadIdx.x == 0) nxt[chain] = ns;
 }
 
-template <typename T, int MODE>
-hipError_t launch_gemm(const NSArgs& f, int njobs, int it, hipStream_t s)
+__global__ void ns_init_kernel(NSArgs a)
 {
-    switch (f.n_p / 64) {
-        case 1: return launch_gemm_nt<T, MODE, 1>(f, njobs, it, s);
-        case 2: return launch_gemm_nt<T, MODE, 2>(f, njobs, it, s);
-        case 3: return launch_gemm_nt<T, MODE, 3>(f, njobs, it, s);
-        case 4: return launch_gemm_nt<T, MODE, 4>(f, njobs, it, s);
-        case 5: return launch_gemm_nt<T, MODE, 5>(f, njobs, it, s);
-        case 6: return launch_gemm_nt<T, MODE, 6>(f, njobs, it, s);
-        case 7: return launch_gemm_nt<T, MODE, 7>(f, njobs, it, s);
-        case 8: return launch_gemm_nt<T, MODE, 8>(f, njobs, it, s);
+    if (threadIdx.x != 0) return;
+    const int m = a.m, kt = m / 2;
+    a.state[0] = kt > 0 ? NSState{0, kNsForm, 0, 0} : NSState{kt, kNsWait, 0, 0};
+    a.state[1] = m - 1 > kt ? NSState{m - 1, kNsForm, 0, 0} : NSState{-1, kNsFinished, 0, 0};
+}
+
+template <typename T, int NT>
+hipError_t launch_slots_nt(const NSArgs& a, int first, int count, hipStream_t s)
+{
+    constexpr int tiles = (2 * NT) * (2 * NT);
+    for (int k = 0; k < count; ++k) {
+        hipLaunchKernelGGL((ns_slot_kernel<T, NT>), dim3(2 * tiles), dim3(256), 0, s, a, first + k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_slots(const NSArgs& a, int first, int count, hipStream_t s)
+{
+    switch (a.n_p / 64) {
+        case 1: return launch_slots_nt<T, 1>(a, first, count, s);
+        case 2: return launch_slots_nt<T, 2>(a, first, count, s);
+        case 3: return launch_slots_nt<T, 3>(a, first, count, s);
+        case 4: return launch_slots_nt<T, 4>(a, first, count, s);
+        case 5: return launch_slots_nt<T, 5>(a, first, count, s);
+        case 6: return launch_slots_nt<T, 6>(a, first, count, s);
+        case 7: return launch_slots_nt<T, 7>(a, first, count, s);
+        case 8: return launch_slots_nt<T, 8>(a, first, count, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
-hipError_t launch_ns(NSArgs a, hipStream_t s)
-{
-    const int m = a.m, kt = m / 2, n_p = a.n_p;
-    const int top_len = kt, bot_len = m - 1 - kt;
-    const int form_blocks = (int)std::min<int64_t>(((int64_t)n_p * n_p + 255) / 256, 1024);
-    hipError_t e;
-    auto run = [&](const NSArgs& f, int njobs, int iters) -> hipError_t {
-        hipLaunchKernelGGL(ns_form_kernel<T>, dim3(form_blocks, njobs), dim3(256), 0, s, f);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        for (int it = 0; it < iters; ++it) {
-            if ((e = launch_gemm<T, 0>(f, njobs, it, s)) != hipSuccess) return e;
-            if ((e = launch_gemm<T, 1>(f, njobs, it, s)) != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
-    const int steps = top_len > bot_len ? top_len : bot_len;
-    for (int st = 0; st < steps; ++st) {
-        NSArgs f = a;
-        int nj = 0;
-        if (st < top_len) {
-            f.job[nj] = NSJob{st, st > 0 ? st - 1 : -1, -1, st > 0 ? 1 : 0, 0};
-            ++nj;
-        }
-        if (st < bot_len) {
-            const int row = m - 1 - st;
-            f.job[nj] = NSJob{row, st > 0 ? row + 1 : -1, -1, st > 0 ? 1 : 0, 1};
-            ++nj;
-        }
-        if ((e = run(f, nj, st > 0 ? a.max_iter : a.max_iter + 4)) != hipSuccess) return e;
-    }
-    NSArgs f = a;
-    f.job[0] = NSJob{kt, kt >= 1 ? kt - 1 : -1, kt + 1 <= m - 1 ? kt + 1 : -1, 0, 0};
-    return run(f, 1, a.max_iter + 4);
-}
-
 }  // namespace xbk
 
-hipError_t xbk_launch_factor_ns(const xbk::NSArgs& a, bool fp32, hipStream_t s)
+hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s)
 {
-    return fp32 ? xbk::launch_ns<float>(a, s) : xbk::launch_ns<double>(a, s);
+    hipLaunchKernelGGL(xbk::ns_init_kernel, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int first, int count, hipStream_t s)
+{
+    return fp32 ? xbk::launch_slots<float>(a, first, count, s) : xbk::launch_slots<double>(a, first, count, s);
 }

@@ -33,7 +33,7 @@ struct Buffers {
     void* ns_Q[2] = {nullptr, nullptr};
     double* ns_dprev[2] = {nullptr, nullptr};
     double* ns_part = nullptr;               // [2][(n_p/32)^2]
-    int* ns_done = nullptr;                  // [m]
+    xbk::NSState* ns_state = nullptr;        // [2 parities][2 chains] schedule state
     // refinement (IR modes): float64 solutions, float residual panels, per-slab state
     double* U[2] = {nullptr, nullptr};       // [nslab][m][16][n_p]
     void* R = nullptr;                       // [nslab][m][16][n_p] float
@@ -116,6 +116,7 @@ struct xbar_plan_s {
     bool timing = false;
     int32_t factor_method = XBAR_FACTOR_AUTO;
     int64_t gj_fallbacks = 0;
+    int ns_slots_hint = 0;      // slots the last Newton-Schulz factor needed
     PhaseTimer t_condense, t_factor, t_sweep, t_recover;
     bool fp32() const { return prec != XBAR_FP64; }
     size_t elem() const { return fp32() ? sizeof(float) : sizeof(double); }
@@ -141,7 +142,7 @@ void free_all(xbar_plan p)
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
                    d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags, d.sink,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
-                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_done,
+                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
                    d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final};
     for (void* x : all)
         if (x) (void)hipFree(x);
@@ -236,7 +237,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         A((void**)&d.ns_dprev[c], n_p * 8);
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
-    A((void**)&d.ns_done, m * 4);
+    A((void**)&d.ns_state, 4 * sizeof(xbk::NSState));
     if (prec != XBAR_FP64) {
         const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
         A((void**)&d.U[0], panel * 8);
@@ -320,7 +321,11 @@ hipError_t launch_gj(xbar_plan p)
     return xbk_launch_factor(a, p->fp32(), p->stream);
 }
 
-hipError_t launch_ns(xbar_plan p)
+// Newton-Schulz factor on its device-driven schedule: launch the slots the last
+// factorization needed (or an estimate), read the two chain states back, and
+// launch more until both chains have finished.  *failed: a block missed its
+// tolerance, or the schedule hit its cap.
+hipError_t run_ns(xbar_plan p, bool* failed)
 {
     xbk::NSArgs a{};
     a.m = p->g.m;
@@ -336,14 +341,45 @@ hipError_t launch_ns(xbar_plan p)
         a.ch[c].Q = p->d.ns_Q[c];
         a.ch[c].dprev = p->d.ns_dprev[c];
     }
+    a.state = p->d.ns_state;
     a.part = p->d.ns_part;
-    a.done = p->d.ns_done;
     a.flags = p->d.flags;
     a.max_iter = xbk::kNsMaxIter;
-    return xbk_launch_factor_ns(a, p->fp32(), p->stream);
+    hipError_t e = xbk_launch_ns_init(a, p->stream);
+    if (e != hipSuccess) return e;
+    const int kt = p->g.m / 2;
+    const int rows = kt + 1;                       // top chain and the twist row
+    const int cap = rows * (1 + 2 * (xbk::kNsMaxIter + 4)) + 4;
+    int launched = 0;
+    int batch = p->ns_slots_hint > 0 ? p->ns_slots_hint : rows * 5 + 8;
+    for (;;) {
+        batch = std::min(batch, cap - launched);
+        if ((e = xbk_launch_ns_slots(a, p->fp32(), launched, batch, p->stream)) != hipSuccess) return e;
+        launched += batch;
+        xbk::NSState st[2];
+        int fail = 0;
+        if ((e = hipMemcpyAsync(st, p->d.ns_state + 2 * (launched & 1), sizeof(st), hipMemcpyDeviceToHost,
+                                p->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(&fail, p->d.flags + xbk::kNsFail, sizeof(int), hipMemcpyDeviceToHost,
+                                p->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+            return e;
+        if (st[0].phase == xbk::kNsFinished && st[1].phase == xbk::kNsFinished) {
+            p->ns_slots_hint = std::max(st[0].slots, st[1].slots);
+            *failed = fail != 0;
+            return hipSuccess;
+        }
+        if (launched >= cap) {
+            *failed = true;
+            return hipSuccess;
+        }
+        const int left = (st[0].phase == xbk::kNsWait || st[0].row < 0) ? 1 : kt - st[0].row + 1;
+        batch = std::max(8, 5 * left + 4);
+    }
 }
 
 __global__ void clear_flag_kernel(int* f, int which) { f[which] = 0; }
+__global__ void set_flag_kernel(int* f, int which) { f[which] = 1; }
 
 }  // namespace
 
@@ -367,23 +403,22 @@ xbar_status xbar_factor(xbar_plan p)
     if (p->factor_method == XBAR_FACTOR_GJ) {
         if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
     } else {
-        if (launch_ns(p) != hipSuccess) return XBAR_ERR_DEVICE;
-        if (p->factor_method == XBAR_FACTOR_AUTO) {
-            int failed = 0;
-            if (hipMemcpyAsync(&failed, p->d.flags + xbk::kNsFail, sizeof(int), hipMemcpyDeviceToHost,
-                               p->stream) != hipSuccess ||
-                hipStreamSynchronize(p->stream) != hipSuccess)
+        bool failed = false;
+        if (run_ns(p, &failed) != hipSuccess) return XBAR_ERR_DEVICE;
+        if (failed && p->factor_method == XBAR_FACTOR_AUTO) {
+            // Redo the factorization by Gauss-Jordan elimination: rebuild E from the
+            // plan's copy of G (the Newton-Schulz pass consumed part of it).
+            hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
+                               (int)xbk::kNsFail);
+            if (xbk_launch_condense(condense_args(p, p->d.Gc), p->fp32(), p->stream) != hipSuccess)
                 return XBAR_ERR_DEVICE;
-            if (failed) {
-                // Redo the factorization by Gauss-Jordan elimination: rebuild E from the
-                // plan's copy of G (the Newton-Schulz pass consumed part of it).
-                hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
-                                   (int)xbk::kNsFail);
-                if (xbk_launch_condense(condense_args(p, p->d.Gc), p->fp32(), p->stream) != hipSuccess)
-                    return XBAR_ERR_DEVICE;
-                if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
-                p->gj_fallbacks++;
-            }
+            if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
+            p->gj_fallbacks++;
+            p->ns_slots_hint = 0;
+        } else if (failed) {
+            // Newton-Schulz only: report the miss through the sticky flags
+            hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
+                               (int)xbk::kErrConv);
         }
     }
     if (p->timing && !p->t_factor.end(p->stream)) return XBAR_ERR_DEVICE;
