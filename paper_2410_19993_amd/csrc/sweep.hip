@@ -53,8 +53,25 @@ __device__ __forceinline__ typename Vec4<T>::type load_frag(const T* __restrict_
 // H_i is FRG, the panel is [column][CPR position].  The chunks of H stream
 // through a ring of DP register sets: chunk K + DP is requested as soon as
 // chunk K has been issued to the matrix cores, so DP chunks are always in
-// flight (the loop is unrolled by DP to keep the ring indices static).
+// flight (the loop is unrolled by DP to keep the ring indices static).  The
+// ring runs on across row blocks: on entry it holds the first DP chunks of Hi,
+// and the last DP chunks of Hi are followed by the first DP of Hnext, so the
+// next row's loads are in flight during the barriers and bookkeeping between
+// products.
 template <typename T> struct SweepRing { static constexpr int value = sizeof(T) == 8 ? 2 : 4; };
+
+template <typename T, int NT, int TW>
+struct HRing {
+    using v4 = typename Vec4<T>::type;
+    static constexpr int DP = SweepRing<T>::value;
+    v4 r[DP][TW];
+    __device__ __forceinline__ void prime(const T* __restrict__ Hi, int w, int l) {
+#pragma unroll
+        for (int d = 0; d < DP; ++d)
+#pragma unroll
+            for (int t = 0; t < TW; ++t) r[d][t] = load_frag<T>(Hi, 4 * NT, TW * w + t, d, l);
+    }
+};
 
 struct NoHook {
     __device__ __forceinline__ void operator()(int) const {}
@@ -64,7 +81,8 @@ struct NoHook {
 // compile-time constant once the loop is unrolled), so that independent
 // work can fill the matrix-core loop.
 template <typename T, int NT, int TW, typename Hook>
-__device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW], const T* __restrict__ Hi,
+__device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW], HRing<T, NT, TW>& ring,
+                                              const T* __restrict__ Hi, const T* __restrict__ Hnext,
                                               const T* ybuf, int ldy, int w, int l, const Hook& hook)
 {
     using v4 = typename Vec4<T>::type;
@@ -76,11 +94,6 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
     const int q = l >> 4, r = l & 15;
 #pragma unroll
     for (int t = 0; t < TW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    v4 ring[DP][TW];
-#pragma unroll
-    for (int d = 0; d < DP; ++d)
-#pragma unroll
-        for (int t = 0; t < TW; ++t) ring[d][t] = load_frag<T>(Hi, KC, TW * w + t, d, l);
 #pragma unroll
     for (int K0 = 0; K0 < KC; K0 += DP) {
 #pragma unroll
@@ -90,10 +103,13 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(ring[d][t][s], bv[s], acc[t]);
+                for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(ring.r[d][t][s], bv[s], acc[t]);
             if (K + DP < KC) {
 #pragma unroll
-                for (int t = 0; t < TW; ++t) ring[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + DP, l);
+                for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + DP, l);
+            } else {
+#pragma unroll
+                for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hnext, KC, TW * w + t, K + DP - KC, l);
             }
             hook(K);
         }
@@ -496,16 +512,21 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
     x.wv = extra + x.w * Ctx::VW * x.PL;
     x.coef = extra + 16 * x.PL;
     const int64_t blk = (int64_t)Ctx::n_p * Ctx::n_p;
+    auto Hb = [&](int i) { return x.H + i * blk; };
     acc_t acc[TW];
     T f[TW][4];
     const NoHook none{};
+    // H blocks in sweep order: 0..kt-1, m-1..kt+1, kt, kt-1..0, kt+1..m-1
+    HRing<T, NT, TW> ring;
+    ring.prime(Hb(kt > 0 ? 0 : (m - 1 > kt ? m - 1 : kt)), x.w, l);
     // forward, top chain
     if (kt > 0) {
         x.load_rhs(0, f);
         x.set_panel(f, acc, false, -1, -1);
         for (int i = 0; i < kt; ++i) {
             if (i + 1 < kt) x.load_rhs(i + 1, f);
-            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+            const int nx = i + 1 < kt ? i + 1 : (m - 1 > kt ? m - 1 : kt);
+            panel_product<T, NT, TW>(acc, ring, Hb(i), Hb(nx), x.ybuf, Ctx::ldy, x.w, l, none);
             x.store_z(i, acc);
             if (i + 1 < kt) x.set_panel(f, acc, true, -1, -1);
         }
@@ -516,7 +537,7 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
         x.set_panel(f, acc, false, -1, -1);
         for (int i = m - 1; i > kt; --i) {
             if (i - 1 > kt) x.load_rhs(i - 1, f);
-            panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+            panel_product<T, NT, TW>(acc, ring, Hb(i), Hb(i - 1 > kt ? i - 1 : kt), x.ybuf, Ctx::ldy, x.w, l, none);
             x.store_z(i, acc);
             if (i - 1 > kt) x.set_panel(f, acc, true, -1, -1);
         }
@@ -527,7 +548,8 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
     x.set_panel(f, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
     x.load_u(kt, up);
     if (REC) x.prefetch_row(kt);
-    panel_product<T, NT, TW>(acc, x.H + kt * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+    panel_product<T, NT, TW>(acc, ring, Hb(kt), Hb(kt > 0 ? kt - 1 : (kt + 1 < m ? kt + 1 : kt)), x.ybuf, Ctx::ldy,
+                             x.w, l, none);
     x.store_z(kt, acc);             // the downward back sweep restarts from this row
     x.settle(kt, acc, up);
     int pend = -1;                  // recovered row whose node voltages are not yet written
@@ -544,11 +566,12 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
             x.load_z(i, zp);
             x.load_u(i, up);
             acc_t u[TW];
+            const T* Hn = Hb(i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i));
             if (REC) {
                 x.prefetch_row(i);
-                panel_product<T, NT, TW>(u, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
+                panel_product<T, NT, TW>(u, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
             } else {
-                panel_product<T, NT, TW>(u, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+                panel_product<T, NT, TW>(u, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, none);
             }
             x.back_step(zp, u);
             x.settle(i, u, up);
@@ -580,11 +603,12 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
             T zp[TW][4];
             x.load_z(i, zp);
             x.load_u(i, up);
+            const T* Hn = Hb(i + 1 < m ? i + 1 : i);
             if (REC) {
                 x.prefetch_row(i);
-                panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
+                panel_product<T, NT, TW>(acc, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
             } else {
-                panel_product<T, NT, TW>(acc, x.H + i * blk, x.ybuf, Ctx::ldy, x.w, l, none);
+                panel_product<T, NT, TW>(acc, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, none);
             }
             x.back_step(zp, acc);
             x.settle(i, acc, up);
