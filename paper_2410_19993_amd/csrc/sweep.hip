@@ -131,6 +131,8 @@ __host__ __device__ inline int seg_lg(int n, int lanes)
 }
 __device__ __forceinline__ int padj(int j, int lg) { return j + (j >> lg); }
 __host__ __device__ inline int padded_len(int n, int lanes) { return n + (n >> seg_lg(n, lanes)) + 1; }
+// smallest power of two >= x
+constexpr int seg_cap(int x) { return x <= 1 ? 1 : 2 * seg_cap((x + 1) / 2); }
 
 __device__ __forceinline__ void affine_compose(double& P, double& Q, double Pp, double Qp)
 {
@@ -202,40 +204,25 @@ __device__ __forceinline__ void wave_lds_fence()
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
-// Per-workgroup state of a sweep.  Global inputs of a step (right-hand-side
-// rows, forward results z_i, row coefficients of the word-line recovery) are
-// requested before the step's product and consumed after it, so their latency
-// hides behind the matrix cores.
-//
-// Word-line recovery (float64 sweep with node voltages): wave w recovers the
-// VW input vectors w*VW.. of the slab, LR lanes each, in a buffer private to
-// the wave; only the staging of the row coefficients is shared.  The node
-// voltages of a recovered row are written during the next row's product, one
-// 16-byte store per lane every few K chunks, so the stores spread over the
-// whole sweep instead of bursting between products.
+// Per-workgroup state of a sweep, as seen by the matrix-core waves.  Global
+// inputs of a step (right-hand-side rows, and in the refinement sweeps the
+// forward results z_i and the float64 solution) are requested before the
+// step's product and consumed after it, so their latency hides behind the
+// matrix cores.
 template <typename T, int NT, bool IR, int W>
 struct SweepCtx {
     using acc_t = typename Frag<T>::acc_t;
     static constexpr int n_p = 64 * NT;
     static constexpr int ldy = n_p + 4;
     static constexpr int TW = 4 * NT / W;    // row tiles per wave
-    static constexpr int NTHR = 64 * W;
-    static constexpr int VW = 16 / W;        // input vectors a wave recovers
-    static constexpr int LR = 64 / VW;       // lanes per input vector in the recovery
-    static constexpr int CPT = (n_p + NTHR - 1) / NTHR;   // row coefficients per thread
-    static constexpr int NST = VW * NT;      // node-voltage stores per lane and row
     const SweepArgs& a;
     T* ybuf;          // [16][ldy] right-hand side / solution panel
-    double* wv;       // [VW][PL] this wave's word-line buffers
-    double* coef;     // [3][PL] fr, ip, G of the row being recovered
     T* Zs;
     const T* H;
     int w, l, q, col, b;
     bool bval;
     T g;
-    int lg = 0, PL = 0;                      // recovery segment width (log2), padded row length
     double dmax = 0.0, umax = 0.0;           // refinement: largest correction and solution entry
-    double pf_fr[CPT], pf_ip[CPT], pf_g[CPT], pf_v = 0.0;
 
     // Lane (q, col) of wave w holds rows row_of(t, v) of tile t, item v.  In panel
     // (CPR) order those rows sit at poff + 16 t + v, so every panel access is a
@@ -245,7 +232,6 @@ struct SweepCtx {
     __device__ __forceinline__ uint32_t lane_off() const { return (uint32_t)(col * n_p) + poff(); }
     __device__ __forceinline__ int64_t slab_row(int i) const { return ((int64_t)blockIdx.x * a.m + i) * 16 * n_p; }
     __device__ __forceinline__ T* zbase(int i) const { return Zs + (int64_t)i * 16 * n_p; }
-    __device__ __forceinline__ T* zrow(int i) const { return zbase(i) + col * n_p; }
     __device__ __forceinline__ double vin(int i) const { return bval ? a.V[(int64_t)b * a.m + i] : 0.0; }
 
     // ---- forward sweep
@@ -318,26 +304,14 @@ struct SweepCtx {
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[t][v] = zp[t][v] + g * acc[t][v];
     }
-    // panel <- u (and, when recovering, the staged coefficients of the row)
-    __device__ __forceinline__ void put_panel(const acc_t (&u)[TW], bool commit) {
+    // panel <- u
+    __device__ __forceinline__ void put_panel(const acc_t (&u)[TW]) {
         lds_barrier();
         const uint32_t lo = (uint32_t)(col * ldy) + poff();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) ybuf[lo + 16 * t + v] = u[t][v];
-        if (commit) {
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int j = (int)threadIdx.x + c * NTHR;
-                if (j < a.n) {
-                    const int p = padj(j, lg);
-                    coef[p] = pf_fr[c];
-                    coef[PL + p] = pf_ip[c];
-                    coef[2 * PL + p] = pf_g[c];
-                }
-            }
-        }
         lds_barrier();
     }
     // Row i of the back sweep is final in u: emit the currents of row m-1, or (when
@@ -372,53 +346,6 @@ struct SweepCtx {
                 const int k = row_of(t, v);
                 if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * (double)u[t][v];
             }
-    }
-
-    // ---- word-line recovery: T_i w_i = g_src V_i e_0 + Gam_i u_i
-    // request row i's coefficients and this lane's input (staged by put_panel)
-    __device__ __forceinline__ void prefetch_row(int i) {
-        const int64_t o = (int64_t)i * a.n;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int jj = min((int)threadIdx.x + c * NTHR, a.n - 1);
-            pf_fr[c] = a.fr[o + jj];
-            pf_ip[c] = a.ip[o + jj];
-            pf_g[c] = a.Gc[o + jj];
-        }
-        const int bb = 16 * (int)blockIdx.x + w * VW + l / LR;
-        pf_v = (bb < a.B) ? a.V[(int64_t)bb * a.m + i] : 0.0;
-    }
-    // word lines of the row whose bit-line voltages are in the panel, for this wave's vectors
-    __device__ __forceinline__ void solve_row() {
-        const int n = a.n, v = l / LR, s = l % LR, cc = w * VW + v;
-        double* wr = wv + v * PL;
-        for (int j = s; j < n; j += LR)
-            wr[padj(j, lg)] = coef[2 * PL + padj(j, lg)] * (double)ybuf[cc * ldy + pos<T>(j)] +
-                              (j == 0 ? a.g_src * pf_v : 0.0);
-        wave_lds_fence();
-        tridiag_solve_lanes<LR>(wr, coef, coef + PL, a.g_wl, n, s, lg);
-        wave_lds_fence();
-    }
-    // k-th node-voltage store of recovered row i (i < 0: none): the pair (w_j, u_j) of
-    // this wave's vector k / NT, j = 64 (k % NT) + lane, in the interleaved node order.
-    // The lane-dependent addresses are rebuilt from an opaque copy of the lane index,
-    // so the compiler cannot hoist all NST of them out of the row loop into registers.
-    __device__ __forceinline__ void out_store(int i, int k) const {
-        const int v = k / NT, cc = w * VW + v;
-        const int bb = 16 * (int)blockIdx.x + cc;              // wave-uniform
-        if (i < 0 || bb >= a.B) return;
-        int lane = l;
-        asm volatile("" : "+v"(lane));
-        const int j = 64 * (k % NT) + lane;
-        if (j >= a.n) return;
-        const double wj = wv[v * PL + padj(j, lg)];
-        const double uj = (double)ybuf[cc * ldy + pos<T>(j)];
-        double* base = a.node_v + ((int64_t)bb * a.m + i) * 2 * a.n;
-        *reinterpret_cast<d2_t*>(base + 2 * j) = d2_t{wj, uj};
-    }
-    __device__ __forceinline__ void out_row(int i) const {
-#pragma unroll
-        for (int k = 0; k < NST; ++k) out_store(i, k);
     }
 
     // Refinement bookkeeping for the slab: per input vector, stop when the error left after
@@ -459,39 +386,274 @@ struct SweepCtx {
     }
 };
 
-// Node-voltage stores of a recovered row, spread over the K chunks of a product.
-template <typename Ctx>
-struct OutHook {
-    const Ctx& x;
-    int row;
-    __device__ __forceinline__ void operator()(int K) const {
-        constexpr int STEP = Ctx::n_p / 16 / Ctx::NST;
-        if ((K + 1) % STEP == 0) {
-            // keep each store's loads in place: hoisted together they would
-            // hold every pending store's data in registers during the product
-            __builtin_amdgcn_sched_barrier(0);
-            x.out_store(row, K / STEP);
-            __builtin_amdgcn_sched_barrier(0);
+// Matrix-core waves per workgroup: 8 for even n_p / 64 (n_p / 128 row tiles each);
+// for odd n_p / 64 either n_p / 64 waves of 4 tiles or (n_p = 320) 4 waves of 5
+// tiles, whichever keeps the accumulators and the H ring without spills next to
+// the helper waves.
+template <int NT> struct SweepWaves { static constexpr int value = (NT % 2 == 0) ? 8 : (NT == 5 ? 4 : NT); };
+constexpr int kHelpers = 4;      // helper waves of the float64 sweep (one per SIMD)
+
+// ---------------------------------------------------------------------------
+// Schedule of the float64 sweep as pairs of workgroup barriers (a panel update
+// each).  The matrix-core waves pass them as set_panel / put_panel calls; the
+// helper waves count them off with the same enumeration:
+//   pairs 0 .. kt-1          forward, top chain: product of row p follows
+//   pairs kt .. F-1          forward, bottom chain: rows m-1 .. kt+1
+//   pair  F                  twist: row kt
+//   pair  F+1                panel <- u_kt; then rows kt-1 .. 0 (one pair after each)
+//   pair  F+2+kt             (kt+1 < m) panel <- z_kt, restart; then rows kt+1 .. m-1
+// with F = kt + max(0, m-1-kt).
+struct SweepPlan {
+    int m, kt, F;
+    __device__ __forceinline__ explicit SweepPlan(int m_) : m(m_), kt(m_ / 2), F(m_ / 2 + max(0, m_ - 1 - m_ / 2)) {}
+    __device__ __forceinline__ int pairs() const { return F + 2 + kt + (kt + 1 < m ? 1 + (m - 1 - kt) : 0); }
+    // row whose product follows pair p (-1: none)
+    __device__ __forceinline__ int product_after(int p) const {
+        if (p < kt) return p;
+        if (p < F) return m - 1 - (p - kt);
+        if (p == F) return kt;
+        int q = p - (F + 1);                       // 0: panel <- u_kt, then u_{kt-1}, ...
+        if (q <= kt) {
+            const int i = kt - q;                  // panel holds u_i
+            return i > 0 ? i - 1 : -1;
         }
+        q -= kt + 1;
+        if (kt + 1 < m) return q == 0 ? kt + 1 : (kt + q + 1 < m ? kt + q + 1 : -1);
+        return -1;
+    }
+    // row whose bit-line voltages are in the panel after pair p, to recover (-1: none)
+    __device__ __forceinline__ int recover_after(int p) const {
+        if (p <= F) return -1;
+        int q = p - (F + 1);
+        if (q <= kt) return kt - q;
+        q -= kt + 1;
+        return (kt + 1 < m && q > 0) ? kt + q : -1;
     }
 };
 
-template <int NT> struct SweepWaves { static constexpr int value = (NT % 2 == 0) ? 8 : 4; };
+// Helper waves of the float64 sweep.  While the matrix-core waves run the product
+// that follows a barrier pair, the helpers
+//  * pull this workgroup's share of the next row's H block into L2 (workgroups b,
+//    b+8, ... share an L2; each takes 1/32 of the block), so that the products
+//    find H in L2 instead of missing all together at the same addresses;
+//  * in the back sweep, pull the z row the next back step reads into L2, and
+//    recover the word lines of the row whose bit lines are in the panel,
+//        T_i w_i = g_src V_i e_0 + Gam_i u_i,
+//    writing that row's node voltages in the paper's interleaved order.  Helper
+//    wave h takes input vectors 4h .. 4h+3, 16 lanes each, every lane a contiguous
+//    segment of the row; the T_i coefficients are read from L2.
+template <typename T, int NT>
+struct SweepHelper {
+    static constexpr int n_p = 64 * NT;
+    static constexpr int ldy = n_p + 4;
+    static constexpr int LR = 16;             // lanes per input vector
+    static constexpr int VPW = 64 / LR;       // input vectors per helper wave
+    const SweepArgs& a;
+    const T* ybuf;
+    double* wv;                               // [16][PL] word-line buffers
+    int h, l, lg, PL;
+    uint32_t keep = 0;                        // xor of the prefetched words (kept live)
 
-// LDS bytes of a sweep: panel, then either the word-line buffers and row coefficients
-// (recovery) or the refinement's reduction scratch.
+    // Pull this workgroup's 1/32 share of an H block, and this slab's z row, into L2:
+    // one 4-byte load per 128-byte line.  The loads are issued before the task's
+    // recovery and their values consumed after it, so the helper never waits on them.
+    static constexpr size_t LINE = 128;
+    static constexpr size_t STEP = (size_t)kHelpers * 64 * LINE;
+    static constexpr size_t BLK = (size_t)n_p * n_p * sizeof(T);
+    static constexpr size_t SHARE = ((BLK / 32) + LINE - 1) & ~(LINE - 1);
+    static constexpr int PULL_IT = (int)((SHARE + STEP - 1) / STEP);
+    static constexpr size_t ZROW = (size_t)16 * n_p * sizeof(T);
+    static constexpr int ZPULL_IT = (int)((ZROW + STEP - 1) / STEP);
+    uint32_t pv[PULL_IT + ZPULL_IT];
+    __device__ __forceinline__ void pull_issue(const T* blk, int zrow) {
+        const char* p = reinterpret_cast<const char*>(blk);
+        const size_t lo = SHARE * (((size_t)blockIdx.x >> 3) & 31);
+        const size_t hi = min(BLK, lo + SHARE);
+#pragma unroll
+        for (int it = 0; it < PULL_IT; ++it) {
+            const size_t off = lo + ((size_t)it * kHelpers + h) * 64 * LINE + LINE * (size_t)l;
+            pv[it] = (blk != nullptr && off < hi) ? *reinterpret_cast<const uint32_t*>(p + off) : 0u;
+        }
+        const char* z = reinterpret_cast<const char*>(reinterpret_cast<const T*>(a.Z) +
+                                                      ((int64_t)blockIdx.x * a.m + max(zrow, 0)) * 16 * n_p);
+#pragma unroll
+        for (int it = 0; it < ZPULL_IT; ++it) {
+            const size_t off = ((size_t)it * kHelpers + h) * 64 * LINE + LINE * (size_t)l;
+            pv[PULL_IT + it] = (zrow >= 0 && off < ZROW) ? *reinterpret_cast<const uint32_t*>(z + off) : 0u;
+        }
+    }
+    __device__ __forceinline__ void pull_consume() {
+#pragma unroll
+        for (int it = 0; it < PULL_IT + ZPULL_IT; ++it) keep ^= pv[it];
+    }
+    // Row coefficients of T_i (fr, ip) and the devices G of the row recovered after the
+    // next barrier pair: requested at the start of a task, written to the free half of
+    // the double-buffered LDS copy at its end, published by the next barrier pair.
+    static constexpr int HT = kHelpers * 64;                 // helper threads
+    static constexpr int CPT = (n_p + HT - 1) / HT;          // coefficients per thread
+    double* coef;                                            // [2][3][PL]
+    double cf[CPT], ci[CPT], cg[CPT];
+    double vnext = 0.0, vcur = 0.0;                          // input V of this lane's vector
+    __device__ __forceinline__ void stage_load(int i) {
+        const int64_t o = (int64_t)i * a.n;
+        const int bb = 16 * (int)blockIdx.x + h * VPW + l / LR;
+        vnext = (bb < a.B) ? a.V[(int64_t)bb * a.m + i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int jj = min(h * 64 + l + c * HT, a.n - 1);
+            cf[c] = a.fr[o + jj];
+            ci[c] = a.ip[o + jj];
+            cg[c] = a.Gc[o + jj];
+        }
+    }
+    __device__ __forceinline__ void stage_store(int buf) {
+        vcur = vnext;
+        double* cb = coef + buf * 3 * PL;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int j = h * 64 + l + c * HT;
+            if (j < a.n) {
+                const int pj = padj(j, lg);
+                cb[pj] = cf[c];
+                cb[PL + pj] = ci[c];
+                cb[2 * PL + pj] = cg[c];
+            }
+        }
+    }
+    // Word lines and node voltages of row i for this wave's vectors, from the staged
+    // coefficients in buffer buf.  Loops run to compile-time bounds with masked lanes.
+    static constexpr int KJ = (n_p + LR - 1) / LR;          // j's per lane in the first pass
+    static constexpr int SEG = seg_cap(KJ);                  // longest lane segment
+    __device__ __forceinline__ void recover(int i, int buf) {
+        const int n = a.n, v = l / LR, s = l % LR, cc = h * VPW + v;
+        const int bb = 16 * (int)blockIdx.x + cc;
+        const double* fr = coef + buf * 3 * PL;              // padded like d
+        const double* ip = fr + PL;
+        const double* Gi = fr + 2 * PL;
+        const double vb = vcur;
+        double* d = wv + cc * PL;
+        const int spare = PL - 1;                              // never a padded index of j < n
+#pragma unroll 8
+        for (int k = 0; k < KJ; ++k) {
+            const int j = s + LR * k;
+            const bool ok = j < n;
+            const int pj = padj(ok ? j : n - 1, lg);
+            const double val = Gi[pj] * (double)ybuf[cc * ldy + pos<T>(ok ? j : n - 1)] +
+                               (j == 0 ? a.g_src * vb : 0.0);
+            d[ok ? pj : spare] = val;
+        }
+        wave_lds_fence();
+        // T_i w = d by forward and backward affine scans over the LR lanes of a vector
+        const int j0 = s << lg, len = max(0, min(n - j0, 1 << lg)), base = j0 + s;
+        const double gw = a.g_wl;
+        double P = 1.0, Q = 0.0;
+#pragma unroll 8
+        for (int e = 0; e < SEG; ++e) {
+            const bool ok = e < len;
+            const int p = ok ? base + e : spare;
+            const double f = ok ? fr[p] : 0.0;               // fr at j = 0 is zero
+            const double Qn = d[p] + f * Q, Pn = f * P;
+            Q = ok ? Qn : Q;
+            P = ok ? Pn : P;
+        }
+        for (int off = 1; off < LR; off <<= 1) {
+            const double Pp = __shfl_up(P, off, LR), Qp = __shfl_up(Q, off, LR);
+            if (s >= off) affine_compose(P, Q, Pp, Qp);
+        }
+        double x = __shfl_up(Q, 1, LR);
+        if (s == 0) x = 0.0;
+#pragma unroll 8
+        for (int e = 0; e < SEG; ++e) {
+            const bool ok = e < len;
+            const int p = ok ? base + e : spare;
+            const double f = ok ? fr[p] : 0.0;
+            const double xn = d[p] + f * x;
+            x = ok ? xn : x;
+            d[p] = x;
+        }
+        P = 1.0;
+        Q = 0.0;
+#pragma unroll 8
+        for (int e = SEG - 1; e >= 0; --e) {
+            const bool ok = e < len;
+            const int p = ok ? base + e : spare;
+            const double ipj = ok ? ip[p] : 0.0;
+            const double f = (j0 + e >= n - 1) ? 0.0 : ipj * gw;
+            const double Qn = ipj * d[p] + f * Q, Pn = f * P;
+            Q = ok ? Qn : Q;
+            P = ok ? Pn : P;
+        }
+        for (int off = 1; off < LR; off <<= 1) {
+            const double Pp = __shfl_down(P, off, LR), Qp = __shfl_down(Q, off, LR);
+            if (s + off < LR) affine_compose(P, Q, Pp, Qp);
+        }
+        x = __shfl_down(Q, 1, LR);
+        if (s == LR - 1) x = 0.0;
+#pragma unroll 8
+        for (int e = SEG - 1; e >= 0; --e) {
+            const bool ok = e < len;
+            const int p = ok ? base + e : spare;
+            const double ipj = ok ? ip[p] : 0.0;
+            const double f = (j0 + e >= n - 1) ? 0.0 : ipj * gw;
+            const double xn = ipj * d[p] + f * x;
+            x = ok ? xn : x;
+            d[p] = x;
+        }
+        wave_lds_fence();
+        // node voltages (w_j, u_j) of the wave's vectors, 1 KB per store instruction
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        for (int vv = 0; vv < VPW; ++vv) {
+            const int c2 = h * VPW + vv, b2 = 16 * (int)blockIdx.x + c2;
+            if (b2 >= a.B) break;
+            double* out = a.node_v + ((int64_t)b2 * a.m + i) * 2 * n;
+#pragma unroll 4
+            for (int k = 0; k < NT; ++k) {
+                const int j = 64 * k + l;
+                if (j < n)
+                    *reinterpret_cast<d2v*>(out + 2 * j) =
+                        d2v{wv[c2 * PL + padj(j, lg)], (double)ybuf[c2 * ldy + pos<T>(j)]};
+            }
+        }
+    }
+    // the whole schedule, one barrier pair at a time
+    __device__ void run(bool rec) {
+        const SweepPlan sp(a.m);
+        const int np = sp.pairs();
+        const T* H = reinterpret_cast<const T*>(a.H);
+        for (int p = 0; p < np; ++p) {
+            lds_barrier();
+            lds_barrier();
+            const int rn = rec && p + 1 < np ? sp.recover_after(p + 1) : -1;
+            if (rn >= 0) stage_load(rn);
+            // during the product after pair p: the block of the next product, and the z
+            // row the back step after this product reads
+            int nb = sp.product_after(p + 1);
+            if (nb < 0 && p + 2 < np) nb = sp.product_after(p + 2);
+            const int cur = sp.product_after(p);
+            pull_issue(nb >= 0 ? H + (int64_t)nb * n_p * n_p : nullptr, p > sp.F ? cur : -1);
+            const int r = sp.recover_after(p);
+            if (rec && r >= 0) recover(r, p & 1);
+            pull_consume();
+            if (rn >= 0) stage_store((p + 1) & 1);
+        }
+        if (keep == 0x9e3779b9u) a.sink[l] = (double)keep;   // keeps the prefetch loads
+    }
+};
+
+// LDS bytes of a sweep: the panel, then the word-line buffers and two copies of
+// the row coefficients (float64 sweep) or the refinement's reduction scratch.
 template <typename T, int NT, bool IR>
 __host__ __device__ inline size_t sweep_lds_bytes(int n)
 {
     constexpr int W = SweepWaves<NT>::value;
     const size_t panel = 16 * (size_t)(64 * NT + 4) * sizeof(T);
     const size_t extra = IR ? 2 * 16 * W * sizeof(double)
-                            : (16 + 3) * (size_t)padded_len(n, 64 / (16 / W)) * sizeof(double);
+                            : (16 + 2 * 3) * (size_t)padded_len(n, SweepHelper<T, NT>::LR) * sizeof(double);
     return panel + extra;
 }
 
 template <typename T, int NT, bool IR, bool REC>
-__global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(64 * (SweepWaves<NT>::value + (IR ? 0 : kHelpers))) void sweep_kernel(SweepArgs a)
 {
     constexpr int W = SweepWaves<NT>::value;
     extern __shared__ __align__(32) unsigned char smem_raw[];
@@ -501,16 +663,26 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
     if (IR && a.iter > 0 && a.slab_done[blockIdx.x]) return;
     const int m = a.m, kt = m / 2;
     const int l = threadIdx.x & 63;
-    Ctx x{a, reinterpret_cast<T*>(smem_raw), nullptr, nullptr,
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    double* extra = reinterpret_cast<double*>(smem_raw + 16 * Ctx::ldy * sizeof(T));
+    if constexpr (!IR) {
+        if (wave >= W) {
+            const int PL = padded_len(a.n, SweepHelper<T, NT>::LR);
+            SweepHelper<T, NT> hp{a, reinterpret_cast<const T*>(smem_raw), extra, wave - W, l,
+                                   seg_lg(a.n, SweepHelper<T, NT>::LR), PL};
+            hp.coef = extra + 16 * PL;
+            // the helpers' latency-bound work gets issue priority over the matrix-core
+            // waves, which have independent work queued behind every instruction
+            __builtin_amdgcn_s_setprio(3);
+            hp.run(REC);
+            return;
+        }
+    }
+    Ctx x{a, reinterpret_cast<T*>(smem_raw),
           reinterpret_cast<T*>(a.Z) + (int64_t)blockIdx.x * m * 16 * Ctx::n_p,
-          reinterpret_cast<const T*>(a.H), __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l, l >> 4, l & 15,
+          reinterpret_cast<const T*>(a.H), wave, l, l >> 4, l & 15,
           16 * (int)blockIdx.x + (l & 15), false, (T)a.g_bl};
     x.bval = x.b < a.B;
-    x.lg = seg_lg(a.n, Ctx::LR);
-    x.PL = padded_len(a.n, Ctx::LR);
-    double* extra = reinterpret_cast<double*>(smem_raw + 16 * Ctx::ldy * sizeof(T));
-    x.wv = extra + x.w * Ctx::VW * x.PL;
-    x.coef = extra + 16 * x.PL;
     const int64_t blk = (int64_t)Ctx::n_p * Ctx::n_p;
     auto Hb = [&](int i) { return x.H + i * blk; };
     acc_t acc[TW];
@@ -547,49 +719,26 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
     x.load_rhs(kt, f);
     x.set_panel(f, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
     x.load_u(kt, up);
-    if (REC) x.prefetch_row(kt);
     panel_product<T, NT, TW>(acc, ring, Hb(kt), Hb(kt > 0 ? kt - 1 : (kt + 1 < m ? kt + 1 : kt)), x.ybuf, Ctx::ldy,
                              x.w, l, none);
     x.store_z(kt, acc);             // the downward back sweep restarts from this row
     x.settle(kt, acc, up);
-    int pend = -1;                  // recovered row whose node voltages are not yet written
-    if (REC) {
-        x.put_panel(acc, true);
-        x.solve_row();
-        pend = kt;
-    }
+    x.put_panel(acc);
     // back, upward
-    if (kt > 0) {
-        if (!REC) x.put_panel(acc, false);
-        for (int i = kt - 1; i >= 0; --i) {
-            T zp[TW][4];
-            x.load_z(i, zp);
-            x.load_u(i, up);
-            acc_t u[TW];
-            const T* Hn = Hb(i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i));
-            if (REC) {
-                x.prefetch_row(i);
-                panel_product<T, NT, TW>(u, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
-            } else {
-                panel_product<T, NT, TW>(u, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, none);
-            }
-            x.back_step(zp, u);
-            x.settle(i, u, up);
-            if (REC) {
-                x.put_panel(u, true);
-                x.solve_row();
-                pend = i;
-            } else if (i > 0) {
-                x.put_panel(u, false);
-            }
-        }
+    for (int i = kt - 1; i >= 0; --i) {
+        T zp[TW][4];
+        if (IR) x.load_z(i, zp);    // refinement sweeps: no helpers, request z before the product
+        x.load_u(i, up);
+        acc_t u[TW];
+        panel_product<T, NT, TW>(u, ring, Hb(i), Hb(i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i)), x.ybuf, Ctx::ldy,
+                                 x.w, l, none);
+        if (!IR) x.load_z(i, zp);   // float64 sweep: the helpers have pulled z_i into L2
+        x.back_step(zp, u);
+        x.settle(i, u, up);
+        x.put_panel(u);
     }
     // back, downward
     if (kt + 1 < m) {
-        if (REC && pend >= 0) {
-            x.out_row(pend);        // the panel is about to be reset to u_kt
-            pend = -1;
-        }
         {
             T zp[TW][4];
             x.load_z(kt, zp);
@@ -598,30 +747,18 @@ __global__ __launch_bounds__(64 * SweepWaves<NT>::value) void sweep_kernel(Sweep
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[t][v] = zp[t][v];
         }
-        x.put_panel(acc, false);
+        x.put_panel(acc);
         for (int i = kt + 1; i < m; ++i) {
             T zp[TW][4];
-            x.load_z(i, zp);
+            if (IR) x.load_z(i, zp);
             x.load_u(i, up);
-            const T* Hn = Hb(i + 1 < m ? i + 1 : i);
-            if (REC) {
-                x.prefetch_row(i);
-                panel_product<T, NT, TW>(acc, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, OutHook<Ctx>{x, pend});
-            } else {
-                panel_product<T, NT, TW>(acc, ring, Hb(i), Hn, x.ybuf, Ctx::ldy, x.w, l, none);
-            }
+            panel_product<T, NT, TW>(acc, ring, Hb(i), Hb(i + 1 < m ? i + 1 : i), x.ybuf, Ctx::ldy, x.w, l, none);
+            if (!IR) x.load_z(i, zp);
             x.back_step(zp, acc);
             x.settle(i, acc, up);
-            if (REC) {
-                x.put_panel(acc, true);
-                x.solve_row();
-                pend = i;
-            } else if (i < m - 1) {
-                x.put_panel(acc, false);
-            }
+            x.put_panel(acc);
         }
     }
-    if (REC && pend >= 0) x.out_row(pend);
     if (IR) x.decide(extra);
 }
 
@@ -729,15 +866,15 @@ __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
 template <typename T, int NT, bool IR>
 hipError_t launch_sweep_nt(const SweepArgs& a, hipStream_t s)
 {
-    constexpr int W = SweepWaves<NT>::value;
+    constexpr int threads = 64 * (SweepWaves<NT>::value + (IR ? 0 : kHelpers));
     const size_t lds = sweep_lds_bytes<T, NT, IR>(a.n);
     if constexpr (!IR) {
         if (a.node_v != nullptr) {
-            hipLaunchKernelGGL((sweep_kernel<T, NT, IR, true>), dim3(a.nslab), dim3(64 * W), lds, s, a);
+            hipLaunchKernelGGL((sweep_kernel<T, NT, IR, true>), dim3(a.nslab), dim3(threads), lds, s, a);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((sweep_kernel<T, NT, IR, false>), dim3(a.nslab), dim3(64 * W), lds, s, a);
+    hipLaunchKernelGGL((sweep_kernel<T, NT, IR, false>), dim3(a.nslab), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
