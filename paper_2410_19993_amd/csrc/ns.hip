@@ -259,10 +259,17 @@ __device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, co
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int slot)
 {
-    constexpr int tiles = (2 * NT) * (2 * NT);
+    constexpr int tdim = 2 * NT, tiles = tdim * tdim, half = tdim / 2;
     __shared__ __align__(16) T red[4 * 4 * 4 * 64];       // product partials [wave][output tile][item][lane]
     __shared__ double wmax[256];
-    const int chain = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    // XCD-aware tile map: workgroups are dispatched round-robin over the 8 XCDs
+    // (each with its own L2), so workgroup b runs on XCD b % 8.  XCDs 0-3 take the
+    // top chain and 4-7 the bottom one; within a chain each XCD owns a quadrant of
+    // the output tile grid, so its L2 holds half the rows of each operand instead
+    // of all of them.
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int chain = xcd >> 2, quad = xcd & 3;
+    const int tile = ((quad >> 1) * half + local / half) * tdim + (quad & 1) * half + local % half;
     const NSState* cur = a.state + 2 * (slot & 1);
     NSState* nxt = a.state + 2 * ((slot + 1) & 1);
     const int m = a.m;
