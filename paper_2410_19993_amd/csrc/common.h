@@ -149,6 +149,7 @@ struct NSState {
     int row;      // crossbar row being inverted
     int phase;    // kNs*
     int it;       // Newton-Schulz step of the row
+    int xb;       // which of the chain's two X buffers holds the current iterate
     int slots;    // slot count at which the chain finished (kNsFinished), else 0
 };
 

@@ -26,6 +26,9 @@
 // The schedule is driven by the device: each launch (slot) does one phase per
 // chain (form, residual product, update product) and hands the chain's next
 // state to the following launch, so a converged row costs no further launches.
+// The update that finishes a row also forms the chain's next pivot block and
+// first iterate, element by element from the tile of H it has just computed, so
+// only the chain starts and the twist need a form launch of their own.
 // The host launches an estimate of the slots needed, reads the two states
 // back, and launches more until both chains have finished.
 //
@@ -64,23 +67,35 @@ __device__ inline NSJob ns_job(int m, int chain, int row)
     return NSJob{row, row < m - 1 ? row + 1 : -1, -1, row < m - 1 ? 1 : 0, 1};
 }
 
-// State of a chain once `row` is inverted.
-__device__ inline NSState ns_advance(int m, int chain, int row, int slot)
+// State of a chain once `row` is inverted (xb: buffer of the next iterate).  A next
+// row of the same chain starts at its first residual product: its pivot block and
+// first iterate are formed by the update that finished this row.
+__device__ inline NSState ns_advance(int m, int chain, int row, int slot, int xb)
 {
     const int kt = m / 2;
     if (chain == 0) {
-        if (row == kt) return NSState{row, kNsFinished, 0, slot + 1};
-        if (row + 1 < kt) return NSState{row + 1, kNsForm, 0, 0};
-        return NSState{kt, kNsWait, 0, 0};           // the twist needs the bottom chain's last inverse
+        if (row == kt) return NSState{row, kNsFinished, 0, 0, slot + 1};
+        if (row + 1 < kt) return NSState{row + 1, kNsResid, 0, xb, 0};
+        return NSState{kt, kNsWait, 0, 0, 0};        // the twist needs the bottom chain's last inverse
     }
-    if (row - 1 > kt) return NSState{row - 1, kNsForm, 0, 0};
-    return NSState{-1, kNsFinished, 0, slot + 1};
+    if (row - 1 > kt) return NSState{row - 1, kNsResid, 0, xb, 0};
+    return NSState{-1, kNsFinished, 0, 0, slot + 1};
+}
+
+// Next row of a chain whose pivot block an update can form in place (-1: none).
+__device__ inline int ns_fused_next(int m, int chain, int row)
+{
+    const int kt = m / 2;
+    if (row == kt) return -1;
+    if (chain == 0) return row + 1 < kt ? row + 1 : -1;
+    return row - 1 > kt ? row - 1 : -1;
 }
 
 // Form P = E_row - g^2 (H_a + H_b) and the starting iterate X_0 (identity on the
 // padding); element e0, e0 + stride, ... of the FRG block.
 template <typename T>
-__device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const NSChain& ch, int64_t e0, int64_t stride)
+__device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const NSChain& ch, int xb, int64_t e0,
+                                        int64_t stride)
 {
     const int n_p = a.n_p, n = a.n;
     const int64_t nn = (int64_t)n_p * n_p;
@@ -88,7 +103,7 @@ __device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const
     const T* Ha = hslot<T>(a, job.dep_a);
     const T* Hb = hslot<T>(a, job.dep_b);
     T* S = reinterpret_cast<T*>(ch.S);
-    T* X = reinterpret_cast<T*>(ch.X[0]);
+    T* X = reinterpret_cast<T*>(ch.X[xb]);
     for (int64_t e = e0; e < nn; e += stride) {
         int r, c;
         frg_rc<T>(e, n_p, r, c);
@@ -136,15 +151,15 @@ __device__ __forceinline__ typename V4<T>::type load_frag(const T* __restrict__ 
 //   MODE 1:  X_{k+1} = X_k + Q X_k  (and H_row when the step converged or was the last)
 // MODE 1 returns whether the step converged (the same answer in every workgroup).
 template <typename T, int MODE, int NT>
-__device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, const NSChain& ch, int it,
-                                           int chain, int tile, bool last, T* red, double* wmax)
+__device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, const NSChain& ch, int xb,
+                                           int chain, int tile, bool last, int next_row, T* red, double* wmax)
 {
     using v4 = typename V4<T>::type;
     using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT, kt = n_p / 16, tdim = n_p / 32, tiles = tdim * tdim;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
-    const T* Xin = reinterpret_cast<const T*>(ch.X[it & 1]);
+    const T* Xin = reinterpret_cast<const T*>(ch.X[xb]);
     // C = Am Bm^T
     const T* Am = MODE == 0 ? Xin : reinterpret_cast<const T*>(ch.Q);
     const T* Bm = MODE == 0 ? reinterpret_cast<const T*>(ch.S) : Xin;
@@ -239,14 +254,37 @@ __device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, co
         }
         const double nu = wmax[0];
         const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
-        T* Xout = reinterpret_cast<T*>(ch.X[(it + 1) & 1]);
+        T* Xout = reinterpret_cast<T*>(ch.X[xb ^ 1]);
         T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
+        const bool form = (fin || last) && next_row >= 0;
+        // the next row's pivot block E_next - g^2 H and first iterate H + diag(S)^-1 - diag(S_prev)^-1,
+        // element by element from this tile of H (E_next is read before being overwritten
+        // by H_next, many launches later)
+        const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)max(next_row, 0) * n_p * n_p;
+        T* S = reinterpret_cast<T*>(ch.S);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t o = base + frg_slot<T>(l, v);
             const T x = Xin[o] + sum[v];
-            Xout[o] = x;
             if (fin || last) Hr[o] = x;
+            if (form) {
+                const int col = 16 * (TC + (w & 1)) + Frag<T>::kidx(l >> 4, v);
+                T sv, xv;
+                if (row >= a.n || col >= a.n) {
+                    sv = xv = (row == col) ? (T)1 : (T)0;
+                } else {
+                    sv = En[o] - (T)a.g2 * x;
+                    xv = x;
+                    if (row == col) {
+                        xv += (T)1 / sv - (T)(1.0 / ch.dprev[row]);
+                        ch.dprev[row] = (double)sv;
+                    }
+                }
+                S[o] = sv;
+                Xout[o] = xv;
+            } else {
+                Xout[o] = x;
+            }
         }
         return fin;
     }
@@ -274,26 +312,27 @@ __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int slot)
     NSState* nxt = a.state + 2 * ((slot + 1) & 1);
     const int m = a.m;
     NSState s = cur[chain];
-    if (s.phase == kNsWait && cur[1].phase == kNsFinished) s = NSState{m / 2, kNsForm, 0, 0};
+    if (s.phase == kNsWait && cur[1].phase == kNsFinished) s = NSState{m / 2, kNsForm, 0, 0, 0};
     NSState ns = s;
     if (s.phase == kNsForm || s.phase == kNsResid || s.phase == kNsUpdate) {
         const NSJob job = ns_job(m, chain, s.row);
         const NSChain& ch = a.ch[job.chain];
         const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
         if (s.phase == kNsForm) {
-            ns_form<T>(a, job, ch, (int64_t)tile * 256 + threadIdx.x, (int64_t)tiles * 256);
-            ns = NSState{s.row, kNsResid, 0, 0};
+            ns_form<T>(a, job, ch, s.xb, (int64_t)tile * 256 + threadIdx.x, (int64_t)tiles * 256);
+            ns = NSState{s.row, kNsResid, 0, s.xb, 0};
         } else if (s.phase == kNsResid) {
-            ns_product<T, 0, NT>(a, job, ch, s.it, chain, tile, false, red, wmax);
-            ns = NSState{s.row, kNsUpdate, s.it, 0};
+            ns_product<T, 0, NT>(a, job, ch, s.xb, chain, tile, false, -1, red, wmax);
+            ns = NSState{s.row, kNsUpdate, s.it, s.xb, 0};
         } else {
             const bool last = s.it + 1 >= maxit;
-            const bool fin = ns_product<T, 1, NT>(a, job, ch, s.it, chain, tile, last, red, wmax);
+            const int next_row = ns_fused_next(m, chain, s.row);
+            const bool fin = ns_product<T, 1, NT>(a, job, ch, s.xb, chain, tile, last, next_row, red, wmax);
             if (fin || last) {
                 if (!fin && tile == 0 && threadIdx.x == 0) atomicOr(a.flags + kNsFail, 1);
-                ns = ns_advance(m, chain, s.row, slot);
+                ns = ns_advance(m, chain, s.row, slot, s.xb ^ 1);
             } else {
-                ns = NSState{s.row, kNsResid, s.it + 1, 0};
+                ns = NSState{s.row, kNsResid, s.it + 1, s.xb ^ 1, 0};
             }
         }
     }
@@ -304,8 +343,8 @@ __global__ void ns_init_kernel(NSArgs a)
 {
     if (threadIdx.x != 0) return;
     const int m = a.m, kt = m / 2;
-    a.state[0] = kt > 0 ? NSState{0, kNsForm, 0, 0} : NSState{kt, kNsWait, 0, 0};
-    a.state[1] = m - 1 > kt ? NSState{m - 1, kNsForm, 0, 0} : NSState{-1, kNsFinished, 0, 0};
+    a.state[0] = kt > 0 ? NSState{0, kNsForm, 0, 0, 0} : NSState{kt, kNsWait, 0, 0, 0};
+    a.state[1] = m - 1 > kt ? NSState{m - 1, kNsForm, 0, 0, 0} : NSState{-1, kNsFinished, 0, 0, 0};
 }
 
 template <typename T, int NT>
