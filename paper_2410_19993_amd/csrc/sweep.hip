@@ -270,13 +270,15 @@ struct SweepCtx {
             }
         lds_barrier();
     }
+    // z_i is read back only in the back sweep: streamed past L2 so that it does not
+    // displace the H blocks the workgroups share
     __device__ __forceinline__ void store_z(int i, const acc_t (&z)[TW]) {
         T* zr = zbase(i);
         const uint32_t o = lane_off();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) zr[o + 16 * t + v] = z[t][v];
+            for (int v = 0; v < 4; ++v) __builtin_nontemporal_store(z[t][v], zr + o + 16 * t + v);
     }
 
     // ---- back sweep
@@ -436,8 +438,8 @@ struct SweepPlan {
 //  * pull this workgroup's share of the next row's H block into L2 (workgroups b,
 //    b+8, ... share an L2; each takes 1/32 of the block), so that the products
 //    find H in L2 instead of missing all together at the same addresses;
-//  * in the back sweep, pull the z row the next back step reads into L2, and
-//    recover the word lines of the row whose bit lines are in the panel,
+//  * in the back sweep, recover the word lines of the row whose bit lines are in
+//    the panel,
 //        T_i w_i = g_src V_i e_0 + Gam_i u_i,
 //    writing that row's node voltages in the paper's interleaved order.  Helper
 //    wave h takes input vectors 4h .. 4h+3, 16 lanes each, every lane a contiguous
@@ -454,18 +456,16 @@ struct SweepHelper {
     int h, l, lg, PL;
     uint32_t keep = 0;                        // xor of the prefetched words (kept live)
 
-    // Pull this workgroup's 1/32 share of an H block, and this slab's z row, into L2:
-    // one 4-byte load per 128-byte line.  The loads are issued before the task's
-    // recovery and their values consumed after it, so the helper never waits on them.
+    // Pull this workgroup's 1/32 share of an H block into L2: one 4-byte load per
+    // 128-byte line.  The loads are issued before the task's recovery and their
+    // values consumed after it, so the helper never waits on them.
     static constexpr size_t LINE = 128;
     static constexpr size_t STEP = (size_t)kHelpers * 64 * LINE;
     static constexpr size_t BLK = (size_t)n_p * n_p * sizeof(T);
     static constexpr size_t SHARE = ((BLK / 32) + LINE - 1) & ~(LINE - 1);
     static constexpr int PULL_IT = (int)((SHARE + STEP - 1) / STEP);
-    static constexpr size_t ZROW = (size_t)16 * n_p * sizeof(T);
-    static constexpr int ZPULL_IT = (int)((ZROW + STEP - 1) / STEP);
-    uint32_t pv[PULL_IT + ZPULL_IT];
-    __device__ __forceinline__ void pull_issue(const T* blk, int zrow) {
+    uint32_t pv[PULL_IT];
+    __device__ __forceinline__ void pull_issue(const T* blk) {
         const char* p = reinterpret_cast<const char*>(blk);
         const size_t lo = SHARE * (((size_t)blockIdx.x >> 3) & 31);
         const size_t hi = min(BLK, lo + SHARE);
@@ -474,17 +474,10 @@ struct SweepHelper {
             const size_t off = lo + ((size_t)it * kHelpers + h) * 64 * LINE + LINE * (size_t)l;
             pv[it] = (blk != nullptr && off < hi) ? *reinterpret_cast<const uint32_t*>(p + off) : 0u;
         }
-        const char* z = reinterpret_cast<const char*>(reinterpret_cast<const T*>(a.Z) +
-                                                      ((int64_t)blockIdx.x * a.m + max(zrow, 0)) * 16 * n_p);
-#pragma unroll
-        for (int it = 0; it < ZPULL_IT; ++it) {
-            const size_t off = ((size_t)it * kHelpers + h) * 64 * LINE + LINE * (size_t)l;
-            pv[PULL_IT + it] = (zrow >= 0 && off < ZROW) ? *reinterpret_cast<const uint32_t*>(z + off) : 0u;
-        }
     }
     __device__ __forceinline__ void pull_consume() {
 #pragma unroll
-        for (int it = 0; it < PULL_IT + ZPULL_IT; ++it) keep ^= pv[it];
+        for (int it = 0; it < PULL_IT; ++it) keep ^= pv[it];
     }
     // Row coefficients of T_i (fr, ip) and the devices G of the row recovered after the
     // next barrier pair: requested at the start of a task, written to the free half of
@@ -610,8 +603,8 @@ struct SweepHelper {
             for (int k = 0; k < NT; ++k) {
                 const int j = 64 * k + l;
                 if (j < n)
-                    *reinterpret_cast<d2v*>(out + 2 * j) =
-                        d2v{wv[c2 * PL + padj(j, lg)], (double)ybuf[c2 * ldy + pos<T>(j)]};
+                    __builtin_nontemporal_store(d2v{wv[c2 * PL + padj(j, lg)], (double)ybuf[c2 * ldy + pos<T>(j)]},
+                                                reinterpret_cast<d2v*>(out + 2 * j));
             }
         }
     }
@@ -625,12 +618,10 @@ struct SweepHelper {
             lds_barrier();
             const int rn = rec && p + 1 < np ? sp.recover_after(p + 1) : -1;
             if (rn >= 0) stage_load(rn);
-            // during the product after pair p: the block of the next product, and the z
-            // row the back step after this product reads
+            // during the product after pair p: the block of the next product
             int nb = sp.product_after(p + 1);
             if (nb < 0 && p + 2 < np) nb = sp.product_after(p + 2);
-            const int cur = sp.product_after(p);
-            pull_issue(nb >= 0 ? H + (int64_t)nb * n_p * n_p : nullptr, p > sp.F ? cur : -1);
+            pull_issue(nb >= 0 ? H + (int64_t)nb * n_p * n_p : nullptr);
             const int r = sp.recover_after(p);
             if (rec && r >= 0) recover(r, p & 1);
             pull_consume();
