@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA = 78.6e12     # MI355X dense FP64 matrix, FLOP/s
 PEAK_FP32_MFMA = 157.3e12
 PEAK_HBM = 8.0e12            # B/s
+IR_TOL = 1e-10               # refinement stop of the float32 leg (its target is 1e-9 rel err)
 # HBM traffic of the dominant kernel per launch, from two counter runs (FETCH_SIZE,
 # WRITE_SIZE) scaled by what the same counters read for a plain copy; valid only
 # while the kernel's sources are unchanged since the counters were taken.
@@ -133,9 +134,9 @@ def main():
         Ih = I.cpu().numpy()[workloads.c3_subset()]
         return float((np.max(np.abs(Ih - ref), axis=1) / np.max(np.abs(ref), axis=1)).max())
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, ir_tol=0.0):
         plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B,
-                       stream=stream)
+                       ir_tol=ir_tol, stream=stream)
 
         def step():
             plan.assemble(G)
@@ -197,10 +198,13 @@ def main():
         "max_rel_err_vs_oracle": err64,
     }
     if not args.no_fp32_ir:
-        ms32, tm32, info32, err32 = run("fp32_ir", args.steps, args.warmup)
+        # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
+        # refinement stops once its error estimate is below 1e-10 (the error actually
+        # reached, measured against the oracle, is reported beside it).
+        ms32, tm32, info32, err32 = run("fp32_ir", args.steps, args.warmup, ir_tol=IR_TOL)
         result["fp32_ir"] = {
             "value": B / (ms32 * 1e-3), "unit": "solves/s", "ms_per_step": ms32, "dtype": "f32+f64",
-            "sweeps": int(info32.ir_iters), "max_rel_err_vs_oracle": err32,
+            "sweeps": int(info32.ir_iters), "ir_tol": IR_TOL, "max_rel_err_vs_oracle": err32,
             "phases_ms": {"condense": per(tm32.condense_ms, tm32.condense_launches),
                           "factor": per(tm32.factor_ms, tm32.factor_launches),
                           "refined_solve": per(tm32.sweep_ms, tm32.sweep_launches),
