@@ -125,11 +125,13 @@ constexpr int kNsMaxIter = 6;      // Newton-Schulz steps allowed per chain row
 constexpr int kNsMaxIterTwist = 10;
 
 // Newton-Schulz inversion of the pivot blocks: per chain, the formed pivot
-// block S, two iterates X and the residual Q = I - X S.
+// block S, two iterates X, the residual Q = I - X S, its transpose and its square.
 struct NSChain {
     void* S;
     void* X[2];
     void* Q;
+    void* Qt;
+    void* P2;
     double* dprev;       // [n_p] diagonal of the previous pivot block of this chain
 };
 
@@ -139,26 +141,26 @@ struct NSJob {
     int chain;               // which NSChain buffers
 };
 
-// Device-driven schedule of the Newton-Schulz factor.  Each launch ("slot") reads
-// every chain's state, does that chain's phase (form the pivot block and the
-// first iterate, a residual product, or an update product) and writes the
-// chain's next state into the other parity, so no launch is spent on a row
-// that has already converged.
-enum : int { kNsForm = 0, kNsResid = 1, kNsUpdate = 2, kNsWait = 3, kNsFinished = 4 };
+// Device-driven schedules of the Newton-Schulz factor (top chain, bottom chain,
+// twist).  Each launch ("slot") of a schedule reads its state, does its phase
+// (form the pivot block and the first iterate, or one of the three launches of
+// a two-step round) and writes the next state into the other parity, so no
+// launch is spent on a row that has already converged.
+enum : int { kNsForm = 0, kNsResid = 1, kNsDouble = 2, kNsUpdate = 3, kNsFinished = 4 };
 struct NSState {
     int row;      // crossbar row being inverted
     int phase;    // kNs*
     int it;       // Newton-Schulz step of the row
     int xb;       // which of the chain's two X buffers holds the current iterate
-    int slots;    // slot count at which the chain finished (kNsFinished), else 0
+    int slots;    // slot count at which the schedule finished (kNsFinished), else 0
 };
 
 struct NSArgs {
     int m, n, n_p;
     double g2;
     void* H;                 // [m][n_p][n_p] FRG: E_i on entry, H_i on exit
-    NSChain ch[2];           // top chain (and the twist row), bottom chain
-    NSState* state;          // [2 parities][2 chains]
+    NSChain ch[2];           // buffers of the top chain (and the twist row), bottom chain
+    NSState* state;          // [2 parities][3 schedules: top chain, bottom chain, twist]
     double* part;            // [2 chains][(n_p/32)^2] per-workgroup max |I - X P| of the current step
     int* flags;
     int max_iter;
@@ -256,7 +258,7 @@ struct RecoverArgs {
 hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s);
-hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int first, int count, hipStream_t s);
+hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int chain, int first, int count, hipStream_t s);
 hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);

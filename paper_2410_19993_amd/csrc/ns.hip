@@ -4,40 +4,50 @@
 // H_i = P_i^{-1} for every pivot block P_i = E_i - g_bl^2 (H_a + H_b).  The
 // pivot blocks are symmetric positive definite and close to diagonal, and
 // consecutive pivots of a chain differ little, so the inverse is reached in a
-// few steps of the quadratically convergent iteration
+// few steps of the quadratically convergent Newton-Schulz iteration
 //     Q_k = I - X_k P,      X_{k+1} = X_k + Q_k X_k      (I - X_{k+1} P = Q_k^2)
 // started from the previous row's inverse with its diagonal corrected,
 //     X_0 = H_prev + diag(P)^{-1} - diag(P_prev)^{-1},
-// or from diag(P)^{-1} at a chain start and for the twist block.  Every step
-// is two n_p^3 products on the matrix cores, spread over all the GPU's
-// workgroups; no small serial inversion sits on the critical path.
+// or from diag(P)^{-1} at a chain start and for the twist block.  Two steps are
+// taken together as a round of three launches,
+//     Q = I - X P;    Q^2 and Y = X + Q X;    X'' = Y + Q^2 Y = (I + Q^2)(I + Q) X,
+// whose residual is I - X'' P = Q^4 (the middle launch holds two products that
+// share their first operand), so a round costs four n_p^3 products and three
+// launches instead of four.  All products run on the matrix cores, spread over
+// all the GPU's workgroups; no small serial inversion sits on the critical path.
 //
-// The largest |Q_k| entry is reduced on the device (per-workgroup partials,
-// combined by every workgroup of the following update).  When it is <= 1e-9,
-// ||Q_k||_inf <= n_p 1e-9 and the update just applied leaves
-// ||I - X_{k+1} P||_inf <= (n_p 1e-9)^2 <= 2.7e-13 for n_p <= 512 (in practice
+// The largest |Q^2| entry of a round is reduced on the device (per-workgroup
+// partials, combined by every workgroup of the round's last launch).  When it is
+// <= 1e-9, ||Q^2||_inf <= n_p 1e-9 and the round leaves
+// ||I - X'' P||_inf <= (n_p 1e-9)^2 <= 2.7e-13 for n_p <= 512 (in practice
 // float64 rounding: consecutive pivots of a chain start the iteration at about
-// 4e-6, then 3e-10, then 3e-15).  The float32 factor of the refinement mode
-// stops at 1e-4 and relies on the refinement.  The result is written over E_i
-// and later launches for the row exit at once.  A row still
-// above the threshold after its last step raises kNsFail, and the host then
-// refactors with Gauss-Jordan elimination (factor.hip).
+// |Q| = 4e-6, so one round ends at rounding level).  The float32 factor of the
+// refinement mode stops at 1e-4 and relies on the refinement.  The result is
+// written over E_i.  A row still above the threshold after its last round raises
+// kNsFail, and the host then refactors with Gauss-Jordan elimination
+// (factor.hip).
 //
-// The schedule is driven by the device: each launch (slot) does one phase per
-// chain (form, residual product, update product) and hands the chain's next
-// state to the following launch, so a converged row costs no further launches.
-// The update that finishes a row also forms the chain's next pivot block and
-// first iterate, element by element from the tile of H it has just computed, so
-// only the chain starts and the twist need a form launch of their own.
-// The host launches an estimate of the slots needed, reads the two states
-// back, and launches more until both chains have finished.
+// The schedule is driven by the device.  The two chains are independent until
+// the twist, so each runs on a stream of its own, and a third schedule inverts
+// the twist block once both have finished; the launches of one chain then fill
+// the matrix cores while the other's are starting up or writing out.  Each
+// launch (slot) does one phase of its schedule (the form, or one launch of a
+// round) and hands the next state to the following launch, so a converged row
+// costs no further launches.  The launch that finishes a row also
+// forms the chain's next pivot block and first iterate, element by element from
+// the tile of H it has just computed, so only the chain starts and the twist
+// need a form launch of their own.  The host launches the slot count the last
+// factorization needed, reads the states back, and launches more until every
+// schedule has finished.
 //
-// Every block here (E_i, H_i, S, X, Q) is stored fragment-tiled (FRG), and
-// a product C = A B^T is formed with the A slot of the matrix cores fed from
+// Every block here (E_i, H_i, S, X, Q, Q^T, Q^2) is stored fragment-tiled (FRG),
+// and a product C = A B^T is formed with the A slot of the matrix cores fed from
 // tile rows of B and the B slot from tile rows of A, so that operand loads and
 // output stores are all contiguous 16-byte accesses.  Since S is symmetric,
-// X S^T = X S; the update uses Q X^T, which equals Q X up to rounding because
-// the iteration keeps X symmetric (2X - X S X is symmetric when X is).
+// X S^T = X S; Q X and Q^2 Y are formed as Q X^T and Q^2 Y^T, equal up to
+// rounding because the iteration keeps X and Y symmetric (X Q^T = Q X when X and
+// P are symmetric, so (I + Q) X and every iterate are); Q Q is formed from the
+// transpose that the residual launch stores next to Q.
 #include <algorithm>
 
 #include "common.h"
@@ -46,6 +56,12 @@ namespace xbk {
 
 constexpr double kNsDone = 1e-9;       // float64: see the bound above
 constexpr double kNsDoneF32 = 1e-4;    // float32: at float rounding after the update
+
+// float64 rows take rounds of two steps (three launches); the float32 factor of
+// the refinement mode, whose loose tolerance a warm-started row meets after one
+// step, takes single steps (residual launch, update launch).
+template <typename T>
+constexpr bool ns_rounds() { return sizeof(T) == 8; }
 
 template <typename T> struct V4;
 template <> struct V4<double> { using type = d4_t; };
@@ -57,28 +73,25 @@ __device__ inline const T* hslot(const NSArgs& a, int row)
     return row < 0 ? nullptr : reinterpret_cast<const T*>(a.H) + (int64_t)row * a.n_p * a.n_p;
 }
 
-// Pivot block of row `row` in chain `chain` (twisted order): the top chain takes rows
-// 0..kt-1 and then the twist row kt = m/2, the bottom chain rows m-1..kt+1.
+// Pivot block of row `row` in schedule `chain` (twisted order): the top chain
+// takes rows 0..kt-1, the bottom chain rows m-1..kt+1, and schedule 2 the twist
+// row kt = m/2 (with the top chain's buffers, once both chains have finished).
 __device__ inline NSJob ns_job(int m, int chain, int row)
 {
     const int kt = m / 2;
-    if (row == kt) return NSJob{kt, kt >= 1 ? kt - 1 : -1, kt + 1 <= m - 1 ? kt + 1 : -1, 0, 0};
+    if (chain == 2) return NSJob{kt, kt >= 1 ? kt - 1 : -1, kt + 1 <= m - 1 ? kt + 1 : -1, 0, 0};
     if (chain == 0) return NSJob{row, row > 0 ? row - 1 : -1, -1, row > 0 ? 1 : 0, 0};
     return NSJob{row, row < m - 1 ? row + 1 : -1, -1, row < m - 1 ? 1 : 0, 1};
 }
 
-// State of a chain once `row` is inverted (xb: buffer of the next iterate).  A next
-// row of the same chain starts at its first residual product: its pivot block and
-// first iterate are formed by the update that finished this row.
+// State of a schedule once `row` is inverted (xb: buffer of the next iterate).  A
+// next row of the same chain starts at its first residual product: its pivot block
+// and first iterate are formed by the update that finished this row.
 __device__ inline NSState ns_advance(int m, int chain, int row, int slot, int xb)
 {
     const int kt = m / 2;
-    if (chain == 0) {
-        if (row == kt) return NSState{row, kNsFinished, 0, 0, slot + 1};
-        if (row + 1 < kt) return NSState{row + 1, kNsResid, 0, xb, 0};
-        return NSState{kt, kNsWait, 0, 0, 0};        // the twist needs the bottom chain's last inverse
-    }
-    if (row - 1 > kt) return NSState{row - 1, kNsResid, 0, xb, 0};
+    if (chain == 0 && row + 1 < kt) return NSState{row + 1, kNsResid, 0, xb, 0};
+    if (chain == 1 && row - 1 > kt) return NSState{row - 1, kNsResid, 0, xb, 0};
     return NSState{-1, kNsFinished, 0, 0, slot + 1};
 }
 
@@ -86,9 +99,9 @@ __device__ inline NSState ns_advance(int m, int chain, int row, int slot, int xb
 __device__ inline int ns_fused_next(int m, int chain, int row)
 {
     const int kt = m / 2;
-    if (row == kt) return -1;
     if (chain == 0) return row + 1 < kt ? row + 1 : -1;
-    return row - 1 > kt ? row - 1 : -1;
+    if (chain == 1) return row - 1 > kt ? row - 1 : -1;
+    return -1;
 }
 
 // Form P = E_row - g^2 (H_a + H_b) and the starting iterate X_0 (identity on the
@@ -143,62 +156,69 @@ __device__ __forceinline__ typename V4<T>::type load_frag(const T* __restrict__ 
     }
 }
 
-// One product of a Newton-Schulz step on a 32x32 output tile per workgroup.
+// Products of a Newton-Schulz round on a 32x32 output tile per workgroup.
 // The four waves split K = n_p into quarters (NT = n_p / 64 chunks of 16
-// each), every wave accumulating all four 16x16 output tiles; the partial
-// sums meet in LDS and wave w finishes output tile w.
-//   MODE 0:  Q = I - X_k S          (and the workgroup's max |Q|)
-//   MODE 1:  X_{k+1} = X_k + Q X_k  (and H_row when the step converged or was the last)
-// MODE 1 returns whether the step converged (the same answer in every workgroup).
-template <typename T, int MODE, int NT>
-__device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, const NSChain& ch, int xb,
-                                           int chain, int tile, bool last, int next_row, T* red, double* wmax)
+// each), every wave accumulating all four 16x16 output tiles (of one or two
+// products that share the A operand); the partial sums meet in LDS and wave w
+// finishes output tile w.  C = A B^T throughout, so tile row TR of A and tile
+// row TC of B are read.
+template <typename T, int NT, int NB>
+__device__ __forceinline__ void ns_core(const T* __restrict__ Am, const T* const (&Bm)[NB], int TR, int TC, int w,
+                                        int l, typename Frag<T>::acc_t (&acc)[NB][2][2])
 {
     using v4 = typename V4<T>::type;
     using acc_t = typename Frag<T>::acc_t;
-    constexpr int n_p = 64 * NT, kt = n_p / 16, tdim = n_p / 32, tiles = tdim * tdim;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
-    const T* Xin = reinterpret_cast<const T*>(ch.X[xb]);
-    // C = Am Bm^T
-    const T* Am = MODE == 0 ? Xin : reinterpret_cast<const T*>(ch.Q);
-    const T* Bm = MODE == 0 ? reinterpret_cast<const T*>(ch.S) : Xin;
-    acc_t acc[2][2];
+    constexpr int kt = 4 * NT;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int p = 0; p < NB; ++p)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[p][i][j] = acc_t{0, 0, 0, 0};
     const int K0 = w * NT;
-    v4 ac[2], bc[2];
+    v4 ac[2], bc[NB][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         ac[i] = load_frag<T>(Am, kt, TR + i, K0, l);
-        bc[i] = load_frag<T>(Bm, kt, TC + i, K0, l);
+#pragma unroll
+        for (int p = 0; p < NB; ++p) bc[p][i] = load_frag<T>(Bm[p], kt, TC + i, K0, l);
     }
 #pragma unroll
     for (int K = 0; K < NT; ++K) {
-        v4 an[2], bn[2];
+        v4 an[2], bn[NB][2];
         if (K + 1 < NT) {
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 an[i] = load_frag<T>(Am, kt, TR + i, K0 + K + 1, l);
-                bn[i] = load_frag<T>(Bm, kt, TC + i, K0 + K + 1, l);
+#pragma unroll
+                for (int p = 0; p < NB; ++p) bn[p][i] = load_frag<T>(Bm[p], kt, TC + i, K0 + K + 1, l);
             }
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int p = 0; p < NB; ++p)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = Frag<T>::mma(bc[j][t], ac[i][t], acc[i][j]);
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[p][i][j] = Frag<T>::mma(bc[p][j][t], ac[i][t], acc[p][i][j]);
         if (K + 1 < NT) {
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 ac[i] = an[i];
-                bc[i] = bn[i];
+#pragma unroll
+                for (int p = 0; p < NB; ++p) bc[p][i] = bn[p][i];
             }
         }
     }
+}
+
+// Sum of the four waves' partial tiles: wave w receives output tile w.
+template <typename T>
+__device__ __forceinline__ typename Frag<T>::acc_t ns_reduce(const typename Frag<T>::acc_t (&acc)[2][2], T* red,
+                                                              int w, int l)
+{
+    using acc_t = typename Frag<T>::acc_t;
 #pragma unroll
     for (int o = 0; o < 4; ++o)
 #pragma unroll
@@ -209,130 +229,241 @@ __device__ __forceinline__ bool ns_product(const NSArgs& a, const NSJob& job, co
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int v = 0; v < 4; ++v) sum[v] += red[((k * 4 + w) * 4 + v) * 64 + l];
-    // wave w owns output tile (TR + w/2, TC + w%2); lane l item v is (row, col) of C
-    const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
-    const int row = 16 * (TR + (w >> 1)) + (l & 15);
-    double* part = a.part + (int64_t)chain * tiles;    // this chain's partials
-    if (MODE == 0) {
-        T* Q = reinterpret_cast<T*>(ch.Q);
-        double mx = 0.0;
+    return sum;
+}
+
+// Largest |entry| of this workgroup's output tiles -> the chain's partial of `tile`.
+template <typename T>
+__device__ __forceinline__ void ns_tile_max(const NSArgs& a, int chain, int tile, int tiles, const T (&val)[4],
+                                            double* wmax, int w, int l)
+{
+    double mx = 0.0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int col = 16 * (TC + (w & 1)) + Frag<T>::kidx(l >> 4, v);
-            const T val = (T)(row == col ? 1 : 0) - sum[v];
-            Q[base + frg_slot<T>(l, v)] = val;
-            const double av = fabs((double)val);
-            mx = (av > mx || av != av) ? av : mx;          // keep NaN
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_xor(mx, off);
-            mx = (o > mx || o != o) ? o : mx;
-        }
-        if (l == 0) wmax[w] = mx;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = wmax[0];
-            for (int k = 1; k < 4; ++k) t = (wmax[k] > t || wmax[k] != wmax[k]) ? wmax[k] : t;
-            part[tile] = t;
-        }
-        return false;
-    } else {
-        // max over the chain's workgroup partials of Q's step
-        double mx = 0.0;
-        for (int k = threadIdx.x; k < tiles; k += 256) {
-            const double o = part[k];
-            mx = (o > mx || o != o) ? o : mx;
-        }
-        wmax[threadIdx.x] = mx;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                const double o = wmax[threadIdx.x + h];
-                wmax[threadIdx.x] = (o > wmax[threadIdx.x] || o != o) ? o : wmax[threadIdx.x];
-            }
-            __syncthreads();
-        }
-        const double nu = wmax[0];
-        const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
-        T* Xout = reinterpret_cast<T*>(ch.X[xb ^ 1]);
-        T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
-        const bool form = (fin || last) && next_row >= 0;
-        // the next row's pivot block E_next - g^2 H and first iterate H + diag(S)^-1 - diag(S_prev)^-1,
-        // element by element from this tile of H (E_next is read before being overwritten
-        // by H_next, many launches later)
-        const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)max(next_row, 0) * n_p * n_p;
-        T* S = reinterpret_cast<T*>(ch.S);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t o = base + frg_slot<T>(l, v);
-            const T x = Xin[o] + sum[v];
-            if (fin || last) Hr[o] = x;
-            if (form) {
-                const int col = 16 * (TC + (w & 1)) + Frag<T>::kidx(l >> 4, v);
-                T sv, xv;
-                if (row >= a.n || col >= a.n) {
-                    sv = xv = (row == col) ? (T)1 : (T)0;
-                } else {
-                    sv = En[o] - (T)a.g2 * x;
-                    xv = x;
-                    if (row == col) {
-                        xv += (T)1 / sv - (T)(1.0 / ch.dprev[row]);
-                        ch.dprev[row] = (double)sv;
-                    }
-                }
-                S[o] = sv;
-                Xout[o] = xv;
-            } else {
-                Xout[o] = x;
-            }
-        }
-        return fin;
+    for (int v = 0; v < 4; ++v) {
+        const double av = fabs((double)val[v]);
+        mx = (av > mx || av != av) ? av : mx;          // keep NaN
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mx, off);
+        mx = (o > mx || o != o) ? o : mx;
+    }
+    if (l == 0) wmax[w] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = wmax[0];
+        for (int k = 1; k < 4; ++k) t = (wmax[k] > t || wmax[k] != wmax[k]) ? wmax[k] : t;
+        a.part[(int64_t)chain * tiles + tile] = t;
     }
 }
 
-// One slot of the schedule: every chain does its current phase with its share of
-// the grid ((n_p/32)^2 workgroups per chain), and workgroup 0 of the chain writes
-// the chain's next state.  A chain that waits or has finished only carries its
-// state over.
+// Residual launch of a round:  Q = I - X S, its transpose, and the workgroup's max |Q|.
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int slot)
+__device__ __forceinline__ void ns_resid(const NSArgs& a, const NSChain& ch, int xb, int chain, int tile, T* red,
+                                         T* trn, double* wmax)
 {
-    constexpr int tdim = 2 * NT, tiles = tdim * tdim, half = tdim / 2;
+    using acc_t = typename Frag<T>::acc_t;
+    constexpr int kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4, r = l & 15;
+    const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
+    const T* const Bm[1] = {reinterpret_cast<const T*>(ch.S)};
+    acc_t acc[1][2][2];
+    ns_core<T, NT, 1>(reinterpret_cast<const T*>(ch.X[xb]), Bm, TR, TC, w, l, acc);
+    const acc_t sum = ns_reduce<T>(acc[0], red, w, l);
+    const int tr = TR + (w >> 1), tc = TC + (w & 1);
+    T* Q = reinterpret_cast<T*>(ch.Q);
+    T* Qt = reinterpret_cast<T*>(ch.Qt);
+    T val[4];
+    T* tw = trn + w * 16 * 17;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int c = Frag<T>::kidx(q, v);
+        val[v] = (T)(tr == tc && r == c ? 1 : 0) - sum[v];
+        Q[((int64_t)tr * kt + tc) * 256 + frg_slot<T>(l, v)] = val[v];
+        tw[r * 17 + c] = val[v];
+    }
+    if constexpr (!ns_rounds<T>()) {
+        ns_tile_max<T>(a, chain, tile, tiles, val, wmax, w, l);
+        return;
+    }
+    // the transposed tile through the wave's LDS scratch
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        Qt[((int64_t)tc * kt + tr) * 256 + frg_slot<T>(l, v)] = tw[Frag<T>::kidx(q, v) * 17 + r];
+    ns_tile_max<T>(a, chain, tile, tiles, val, wmax, w, l);
+}
+
+// Middle launch of a round:  P2 = Q Q and Y = X + Q X (into the other iterate
+// buffer), and the workgroup's max |P2|.
+template <typename T, int NT>
+__device__ __forceinline__ void ns_double(const NSArgs& a, const NSChain& ch, int xb, int chain, int tile, T* red,
+                                          double* wmax)
+{
+    using acc_t = typename Frag<T>::acc_t;
+    constexpr int kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
+    const T* X = reinterpret_cast<const T*>(ch.X[xb]);
+    const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
+    T xin[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xin[v] = X[base + frg_slot<T>(l, v)];
+    // Q Q = Q (Q^T)^T and Q X = Q X^T (X is symmetric)
+    const T* const Bm[2] = {reinterpret_cast<const T*>(ch.Qt), X};
+    acc_t acc[2][2][2];
+    ns_core<T, NT, 2>(reinterpret_cast<const T*>(ch.Q), Bm, TR, TC, w, l, acc);
+    const acc_t p2 = ns_reduce<T>(acc[0], red, w, l);
+    __syncthreads();
+    const acc_t qx = ns_reduce<T>(acc[1], red, w, l);
+    T* P2 = reinterpret_cast<T*>(ch.P2);
+    T* Y = reinterpret_cast<T*>(ch.X[xb ^ 1]);
+    T val[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t o = base + frg_slot<T>(l, v);
+        val[v] = p2[v];
+        P2[o] = p2[v];
+        Y[o] = xin[v] + qx[v];
+    }
+    ns_tile_max<T>(a, chain, tile, tiles, val, wmax, w, l);
+}
+
+// Last launch of a round:  X'' = Y + P2 Y, whose residual is Q^4 (or, for single
+// steps, X' = X + Q X with residual Q^2: Am = Q, Y = X).  When the round converged
+// (the largest |entry| of P2, or of Q, read from the previous launch's partials,
+// is <= the tolerance) or was the last allowed, the result is H_row; the launch
+// that finishes a row also forms the chain's next pivot block E_next - g^2 H and
+// first iterate H + diag(S)^-1 - diag(S_prev)^-1, element by element from its
+// tile of H (E_next is read before being overwritten by H_next, many launches
+// later).  Returns whether the round converged (the same answer in every
+// workgroup).
+template <typename T, int NT>
+__device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, const NSChain& ch, const T* Am,
+                                          const T* Y, T* Xout, int chain, int tile, bool last, int next_row, T* red,
+                                          double* wmax)
+{
+    using acc_t = typename Frag<T>::acc_t;
+    constexpr int n_p = 64 * NT, kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
+    const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
+    const int row = 16 * (TR + (w >> 1)) + (l & 15);
+    // the epilogue's operands (this tile of Y, of the next row's E block and the
+    // previous pivot diagonal) and the round's max |P2| partials are requested
+    // before the product, so that their latency hides behind it
+    T yin[4], en[4];
+    double dp = 1.0;
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < tiles; k += 256) {
+        const double o = a.part[(int64_t)chain * tiles + k];
+        mx = (o > mx || o != o) ? o : mx;
+    }
+    const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)max(next_row, 0) * n_p * n_p;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        yin[v] = Y[base + frg_slot<T>(l, v)];
+        en[v] = next_row >= 0 ? En[base + frg_slot<T>(l, v)] : (T)0;
+    }
+    if (next_row >= 0 && row < a.n) dp = ch.dprev[row];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(mx, off);
+        mx = (o > mx || o != o) ? o : mx;
+    }
+    if (l == 0) wmax[w] = mx;
+    const T* const Bm[1] = {Y};
+    acc_t acc[1][2][2];
+    ns_core<T, NT, 1>(Am, Bm, TR, TC, w, l, acc);
+    const acc_t sum = ns_reduce<T>(acc[0], red, w, l);      // its barrier also publishes wmax
+    double nu = wmax[0];
+    for (int k = 1; k < 4; ++k) nu = (wmax[k] > nu || wmax[k] != wmax[k]) ? wmax[k] : nu;
+    const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
+    T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
+    const bool form = (fin || last) && next_row >= 0;
+    T* S = reinterpret_cast<T*>(ch.S);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t o = base + frg_slot<T>(l, v);
+        const T x = yin[v] + sum[v];
+        if (fin || last) Hr[o] = x;
+        if (form) {
+            const int col = 16 * (TC + (w & 1)) + Frag<T>::kidx(l >> 4, v);
+            T sv, xv;
+            if (row >= a.n || col >= a.n) {
+                sv = xv = (row == col) ? (T)1 : (T)0;
+            } else {
+                sv = en[v] - (T)a.g2 * x;
+                xv = x;
+                if (row == col) {
+                    xv += (T)1 / sv - (T)(1.0 / dp);
+                    ch.dprev[row] = (double)sv;
+                }
+            }
+            S[o] = sv;
+            Xout[o] = xv;
+        } else if (!(fin || last)) {
+            Xout[o] = x;
+        }
+    }
+    return fin;
+}
+
+// One slot of schedule `chain`: its current phase, spread over (n_p/32)^2
+// workgroups (a 32x32 output tile each); workgroup 0 writes the next state.  A
+// finished schedule only carries its state over.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int chain, int slot)
+{
+    constexpr int tdim = 2 * NT;
     __shared__ __align__(16) T red[4 * 4 * 4 * 64];       // product partials [wave][output tile][item][lane]
-    __shared__ double wmax[256];
+    __shared__ __align__(16) T trn[4 * 16 * 17];          // per-wave transpose scratch
+    __shared__ double wmax[4];
     // XCD-aware tile map: workgroups are dispatched round-robin over the 8 XCDs
-    // (each with its own L2), so workgroup b runs on XCD b % 8.  XCDs 0-3 take the
-    // top chain and 4-7 the bottom one; within a chain each XCD owns a quadrant of
-    // the output tile grid, so its L2 holds half the rows of each operand instead
-    // of all of them.
-    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
-    const int chain = xcd >> 2, quad = xcd & 3;
-    const int tile = ((quad >> 1) * half + local / half) * tdim + (quad & 1) * half + local % half;
-    const NSState* cur = a.state + 2 * (slot & 1);
-    NSState* nxt = a.state + 2 * ((slot + 1) & 1);
+    // (each with its own L2), so workgroup b runs on XCD b % 8.  Each XCD owns a
+    // block of a quarter of the tile rows and half of the tile columns, so its L2
+    // holds a quarter of the rows of one operand and half of the other's.
+    int tile = blockIdx.x;
+    if constexpr (tdim % 4 == 0) {
+        constexpr int rpx = tdim / 4, cpx = tdim / 2;
+        const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+        tile = ((xcd >> 1) * rpx + local / cpx) * tdim + (xcd & 1) * cpx + local % cpx;
+    }
+    const NSState* cur = a.state + 3 * (slot & 1);
+    NSState* nxt = a.state + 3 * ((slot + 1) & 1);
     const int m = a.m;
-    NSState s = cur[chain];
-    if (s.phase == kNsWait && cur[1].phase == kNsFinished) s = NSState{m / 2, kNsForm, 0, 0, 0};
+    const NSState s = cur[chain];
     NSState ns = s;
-    if (s.phase == kNsForm || s.phase == kNsResid || s.phase == kNsUpdate) {
+    if (s.phase != kNsFinished) {
         const NSJob job = ns_job(m, chain, s.row);
         const NSChain& ch = a.ch[job.chain];
-        const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
         if (s.phase == kNsForm) {
+            constexpr int tiles = tdim * tdim;
             ns_form<T>(a, job, ch, s.xb, (int64_t)tile * 256 + threadIdx.x, (int64_t)tiles * 256);
             ns = NSState{s.row, kNsResid, 0, s.xb, 0};
         } else if (s.phase == kNsResid) {
-            ns_product<T, 0, NT>(a, job, ch, s.xb, chain, tile, false, -1, red, wmax);
+            ns_resid<T, NT>(a, ch, s.xb, job.chain, tile, red, trn, wmax);
+            ns = NSState{s.row, ns_rounds<T>() ? kNsDouble : kNsUpdate, s.it, s.xb, 0};
+        } else if (s.phase == kNsDouble) {
+            ns_double<T, NT>(a, ch, s.xb, job.chain, tile, red, wmax);
             ns = NSState{s.row, kNsUpdate, s.it, s.xb, 0};
         } else {
-            const bool last = s.it + 1 >= maxit;
+            // a round: X[xb] <- Y + P2 Y with Y in X[xb^1]; a single step: X[xb^1] <- X + Q X
+            constexpr int steps = ns_rounds<T>() ? 2 : 1;
+            T* const X0 = reinterpret_cast<T*>(ch.X[s.xb]);
+            T* const X1 = reinterpret_cast<T*>(ch.X[s.xb ^ 1]);
+            const T* Am = reinterpret_cast<const T*>(ns_rounds<T>() ? ch.P2 : ch.Q);
+            const int xo = ns_rounds<T>() ? s.xb : s.xb ^ 1;
+            const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
+            const bool last = s.it + steps >= maxit;
             const int next_row = ns_fused_next(m, chain, s.row);
-            const bool fin = ns_product<T, 1, NT>(a, job, ch, s.xb, chain, tile, last, next_row, red, wmax);
+            const bool fin = ns_update<T, NT>(a, job, ch, Am, ns_rounds<T>() ? X1 : X0, ns_rounds<T>() ? X0 : X1,
+                                              job.chain, tile, last, next_row, red, wmax);
             if (fin || last) {
                 if (!fin && tile == 0 && threadIdx.x == 0) atomicOr(a.flags + kNsFail, 1);
-                ns = ns_advance(m, chain, s.row, slot, s.xb ^ 1);
+                ns = ns_advance(m, chain, s.row, slot, xo);
             } else {
-                ns = NSState{s.row, kNsResid, s.it + 1, s.xb ^ 1, 0};
+                ns = NSState{s.row, kNsResid, s.it + steps, xo, 0};
             }
         }
     }
@@ -343,16 +474,17 @@ __global__ void ns_init_kernel(NSArgs a)
 {
     if (threadIdx.x != 0) return;
     const int m = a.m, kt = m / 2;
-    a.state[0] = kt > 0 ? NSState{0, kNsForm, 0, 0, 0} : NSState{kt, kNsWait, 0, 0, 0};
+    a.state[0] = kt > 0 ? NSState{0, kNsForm, 0, 0, 0} : NSState{-1, kNsFinished, 0, 0, 0};
     a.state[1] = m - 1 > kt ? NSState{m - 1, kNsForm, 0, 0, 0} : NSState{-1, kNsFinished, 0, 0, 0};
+    a.state[2] = NSState{kt, kNsForm, 0, 0, 0};
 }
 
 template <typename T, int NT>
-hipError_t launch_slots_nt(const NSArgs& a, int first, int count, hipStream_t s)
+hipError_t launch_slots_nt(const NSArgs& a, int chain, int first, int count, hipStream_t s)
 {
     constexpr int tiles = (2 * NT) * (2 * NT);
     for (int k = 0; k < count; ++k) {
-        hipLaunchKernelGGL((ns_slot_kernel<T, NT>), dim3(2 * tiles), dim3(256), 0, s, a, first + k);
+        hipLaunchKernelGGL((ns_slot_kernel<T, NT>), dim3(tiles), dim3(256), 0, s, a, chain, first + k);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -360,17 +492,17 @@ hipError_t launch_slots_nt(const NSArgs& a, int first, int count, hipStream_t s)
 }
 
 template <typename T>
-hipError_t launch_slots(const NSArgs& a, int first, int count, hipStream_t s)
+hipError_t launch_slots(const NSArgs& a, int chain, int first, int count, hipStream_t s)
 {
     switch (a.n_p / 64) {
-        case 1: return launch_slots_nt<T, 1>(a, first, count, s);
-        case 2: return launch_slots_nt<T, 2>(a, first, count, s);
-        case 3: return launch_slots_nt<T, 3>(a, first, count, s);
-        case 4: return launch_slots_nt<T, 4>(a, first, count, s);
-        case 5: return launch_slots_nt<T, 5>(a, first, count, s);
-        case 6: return launch_slots_nt<T, 6>(a, first, count, s);
-        case 7: return launch_slots_nt<T, 7>(a, first, count, s);
-        case 8: return launch_slots_nt<T, 8>(a, first, count, s);
+        case 1: return launch_slots_nt<T, 1>(a, chain, first, count, s);
+        case 2: return launch_slots_nt<T, 2>(a, chain, first, count, s);
+        case 3: return launch_slots_nt<T, 3>(a, chain, first, count, s);
+        case 4: return launch_slots_nt<T, 4>(a, chain, first, count, s);
+        case 5: return launch_slots_nt<T, 5>(a, chain, first, count, s);
+        case 6: return launch_slots_nt<T, 6>(a, chain, first, count, s);
+        case 7: return launch_slots_nt<T, 7>(a, chain, first, count, s);
+        case 8: return launch_slots_nt<T, 8>(a, chain, first, count, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -383,7 +515,9 @@ hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int first, int count, hipStream_t s)
+hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int chain, int first, int count, hipStream_t s)
 {
-    return fp32 ? xbk::launch_slots<float>(a, first, count, s) : xbk::launch_slots<double>(a, first, count, s);
+    if (chain < 0 || chain > 2) return hipErrorInvalidValue;
+    return fp32 ? xbk::launch_slots<float>(a, chain, first, count, s)
+                : xbk::launch_slots<double>(a, chain, first, count, s);
 }

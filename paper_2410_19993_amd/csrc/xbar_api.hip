@@ -31,9 +31,11 @@ struct Buffers {
     void* ns_S[2] = {nullptr, nullptr};
     void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* ns_Q[2] = {nullptr, nullptr};
+    void* ns_Qt[2] = {nullptr, nullptr};
+    void* ns_P2[2] = {nullptr, nullptr};
     double* ns_dprev[2] = {nullptr, nullptr};
     double* ns_part = nullptr;               // [2][(n_p/32)^2]
-    xbk::NSState* ns_state = nullptr;        // [2 parities][2 chains] schedule state
+    xbk::NSState* ns_state = nullptr;        // [2 parities][3 schedules] schedule state
     // refinement (IR modes): float64 solutions, float residual panels, per-slab state
     double* U[2] = {nullptr, nullptr};       // [nslab][m][16][n_p]
     void* R = nullptr;                       // [nslab][m][16][n_p] float
@@ -116,7 +118,9 @@ struct xbar_plan_s {
     bool timing = false;
     int32_t factor_method = XBAR_FACTOR_AUTO;
     int64_t gj_fallbacks = 0;
-    int ns_slots_hint = 0;      // slots the last Newton-Schulz factor needed
+    int ns_slots_hint[3] = {0, 0, 0};   // slots each Newton-Schulz schedule last needed
+    hipStream_t side = nullptr;         // second stream: the bottom chain of the factor
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     PhaseTimer t_condense, t_factor, t_sweep, t_recover;
     bool fp32() const { return prec != XBAR_FP64; }
     size_t elem() const { return fp32() ? sizeof(float) : sizeof(double); }
@@ -142,7 +146,8 @@ void free_all(xbar_plan p)
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
                    d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags, d.sink,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
-                   d.ns_Q[0], d.ns_Q[1], d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
+                   d.ns_Q[0], d.ns_Q[1], d.ns_Qt[0], d.ns_Qt[1], d.ns_P2[0], d.ns_P2[1],
+                   d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
                    d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final};
     for (void* x : all)
         if (x) (void)hipFree(x);
@@ -150,6 +155,15 @@ void free_all(xbar_plan p)
 }
 
 bool set_device(xbar_plan p) { return hipSetDevice(p->device) == hipSuccess; }
+
+void destroy_side(xbar_plan p)
+{
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    p->ev_join = p->ev_fork = nullptr;
+    p->side = nullptr;
+}
 
 xbk::CondenseArgs condense_args(xbar_plan p, const double* G);
 
@@ -234,10 +248,12 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         A(&d.ns_X[c][0], n_p * n_p * es);
         A(&d.ns_X[c][1], n_p * n_p * es);
         A(&d.ns_Q[c], n_p * n_p * es);
+        A(&d.ns_Qt[c], n_p * n_p * es);
+        A(&d.ns_P2[c], n_p * n_p * es);
         A((void**)&d.ns_dprev[c], n_p * 8);
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
-    A((void**)&d.ns_state, 4 * sizeof(xbk::NSState));
+    A((void**)&d.ns_state, 6 * sizeof(xbk::NSState));
     if (prec != XBAR_FP64) {
         const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
         A((void**)&d.U[0], panel * 8);
@@ -253,7 +269,12 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         return st;
     }
     hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, p->stream, d.flags);
-    if (hipGetLastError() != hipSuccess) {
+    if (hipGetLastError() != hipSuccess ||
+        hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy_side(p);
         free_all(p);
         delete p;
         return XBAR_ERR_DEVICE;
@@ -339,6 +360,8 @@ hipError_t run_ns(xbar_plan p, bool* failed)
         a.ch[c].X[0] = p->d.ns_X[c][0];
         a.ch[c].X[1] = p->d.ns_X[c][1];
         a.ch[c].Q = p->d.ns_Q[c];
+        a.ch[c].Qt = p->d.ns_Qt[c];
+        a.ch[c].P2 = p->d.ns_P2[c];
         a.ch[c].dprev = p->d.ns_dprev[c];
     }
     a.state = p->d.ns_state;
@@ -347,35 +370,76 @@ hipError_t run_ns(xbar_plan p, bool* failed)
     a.max_iter = xbk::kNsMaxIter;
     hipError_t e = xbk_launch_ns_init(a, p->stream);
     if (e != hipSuccess) return e;
-    const int kt = p->g.m / 2;
-    const int rows = kt + 1;                       // top chain and the twist row
-    const int cap = rows * (1 + 2 * (xbk::kNsMaxIter + 4)) + 4;
-    int launched = 0;
-    int batch = p->ns_slots_hint > 0 ? p->ns_slots_hint : rows * 5 + 8;
-    for (;;) {
-        batch = std::min(batch, cap - launched);
-        if ((e = xbk_launch_ns_slots(a, p->fp32(), launched, batch, p->stream)) != hipSuccess) return e;
-        launched += batch;
-        xbk::NSState st[2];
-        int fail = 0;
-        if ((e = hipMemcpyAsync(st, p->d.ns_state + 2 * (launched & 1), sizeof(st), hipMemcpyDeviceToHost,
-                                p->stream)) != hipSuccess ||
-            (e = hipMemcpyAsync(&fail, p->d.flags + xbk::kNsFail, sizeof(int), hipMemcpyDeviceToHost,
-                                p->stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(p->stream)) != hipSuccess)
-            return e;
-        if (st[0].phase == xbk::kNsFinished && st[1].phase == xbk::kNsFinished) {
-            p->ns_slots_hint = std::max(st[0].slots, st[1].slots);
-            *failed = fail != 0;
-            return hipSuccess;
-        }
-        if (launched >= cap) {
-            *failed = true;
-            return hipSuccess;
-        }
-        const int left = (st[0].phase == xbk::kNsWait || st[0].row < 0) ? 1 : kt - st[0].row + 1;
-        batch = std::max(8, 5 * left + 4);
+    // Schedules 0 and 1 (the two chains) run on the plan stream and the side stream,
+    // so that one chain's launches fill the matrix cores while the other's start up
+    // or write out; schedule 2 (the twist) runs on the plan stream once both have
+    // finished.
+    const int m = p->g.m, kt = m / 2;
+    const int rows[3] = {kt, std::max(0, m - 1 - kt), 1};
+    hipStream_t on[3] = {p->stream, p->side, p->stream};
+    int launched[3] = {0, 0, 0}, batch[3];
+    int cap[3];
+    for (int c = 0; c < 3; ++c) {
+        const int steps = (c == 0 || c == 1) ? xbk::kNsMaxIter : xbk::kNsMaxIter + 4;
+        cap[c] = rows[c] * (1 + 2 * (steps + 4)) + 4;
+        batch[c] = rows[c] == 0                ? 0
+                   : p->ns_slots_hint[c] > 0 ? p->ns_slots_hint[c]
+                   : c == 2                  ? 2 * steps + 2
+                                             : rows[c] * 5 + 8;
     }
+    xbk::NSState st[6];
+    int fail = 0;
+    // read every state back (through the plan stream, after the side stream's work)
+    auto sync_states = [&]() -> hipError_t {
+        hipError_t r;
+        if ((r = hipEventRecord(p->ev_join, p->side)) != hipSuccess ||
+            (r = hipStreamWaitEvent(p->stream, p->ev_join, 0)) != hipSuccess ||
+            (r = hipMemcpyAsync(st, p->d.ns_state, sizeof(st), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+            (r = hipMemcpyAsync(&fail, p->d.flags + xbk::kNsFail, sizeof(int), hipMemcpyDeviceToHost,
+                                p->stream)) != hipSuccess)
+            return r;
+        return hipStreamSynchronize(p->stream);
+    };
+    auto state_of = [&](int c) -> const xbk::NSState& { return st[3 * (launched[c] & 1) + c]; };
+    // the side stream starts after the plan stream's work so far (E blocks, initial states)
+    if ((e = hipEventRecord(p->ev_fork, p->stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(p->side, p->ev_fork, 0)) != hipSuccess)
+        return e;
+    for (int phase = 0; phase < 2; ++phase) {
+        const int c0 = phase == 0 ? 0 : 2, c1 = phase == 0 ? 1 : 2;
+        for (;;) {
+            // interleave the two chains' launches so that both streams stay fed
+            const int most = std::max(batch[c0], batch[c1]);
+            for (int k = 0; k < most; ++k)
+                for (int c = c0; c <= c1; ++c)
+                    if (k < batch[c] && (e = xbk_launch_ns_slots(a, p->fp32(), c, launched[c] + k, 1, on[c])) !=
+                                            hipSuccess)
+                        return e;
+            for (int c = c0; c <= c1; ++c) launched[c] += batch[c];
+            if ((e = sync_states()) != hipSuccess) return e;
+            bool done = true, over = false;
+            for (int c = c0; c <= c1; ++c) {
+                const xbk::NSState& s = state_of(c);
+                batch[c] = 0;
+                if (s.phase == xbk::kNsFinished) continue;
+                done = false;
+                if (launched[c] >= cap[c]) {
+                    over = true;
+                    continue;
+                }
+                const int left = c == 0 ? kt - s.row : c == 1 ? s.row - kt : 1;
+                batch[c] = std::min(std::max(8, 5 * left + 4), cap[c] - launched[c]);
+            }
+            if (over) {
+                *failed = true;
+                return hipSuccess;
+            }
+            if (done) break;
+        }
+    }
+    for (int c = 0; c < 3; ++c) p->ns_slots_hint[c] = state_of(c).slots;
+    *failed = fail != 0;
+    return hipSuccess;
 }
 
 __global__ void clear_flag_kernel(int* f, int which) { f[which] = 0; }
@@ -414,7 +478,7 @@ xbar_status xbar_factor(xbar_plan p)
                 return XBAR_ERR_DEVICE;
             if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
             p->gj_fallbacks++;
-            p->ns_slots_hint = 0;
+            for (int& h : p->ns_slots_hint) h = 0;
         } else if (failed) {
             // Newton-Schulz only: report the miss through the sticky flags
             hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
@@ -594,6 +658,8 @@ xbar_status xbar_destroy(xbar_plan p)
     (void)hipStreamSynchronize(p->stream);
     PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover};
     for (PhaseTimer* t : all) t->destroy();
+    if (p->side) (void)hipStreamSynchronize(p->side);
+    destroy_side(p);
     free_all(p);
     delete p;
     return XBAR_OK;
