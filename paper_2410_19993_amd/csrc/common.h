@@ -242,8 +242,7 @@ struct RecoverArgs {
     int m, n, n_p, B, nslab;
     double g_src;
     const double* V;     // [B][m]
-    const void* Z;       // [nslab][m][16][n_p] u_i (element type of the sweep)
-    const double* U[2];  // refinement: float64 solutions, U[slab_final[slab]] is final
+    const double* U[2];  // float64 solutions of the refinement, U[slab_final[slab]] is final
     const int* slab_final;
     const double* fr;
     const double* ip;
@@ -260,6 +259,6 @@ hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s);
 hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int chain, int first, int count, hipStream_t s);
 hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
-hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s);

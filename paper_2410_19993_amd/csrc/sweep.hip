@@ -21,6 +21,7 @@
 // even, else 4) each own a band of TW = 4 n_p / (64 W) tiles of 16 rows, so
 // that the accumulators and one chunk of prefetched H stay in registers.
 #include "common.h"
+#include "xbar.h"
 
 namespace xbk {
 
@@ -58,7 +59,7 @@ __device__ __forceinline__ typename Vec4<T>::type load_frag(const T* __restrict_
 // and the last DP chunks of Hi are followed by the first DP of Hnext, so the
 // next row's loads are in flight during the barriers and bookkeeping between
 // products.
-template <typename T> struct SweepRing { static constexpr int value = sizeof(T) == 8 ? 2 : 4; };
+template <typename T> struct SweepRing { static constexpr int value = 2; };
 
 template <typename T, int NT, int TW>
 struct HRing {
@@ -138,58 +139,6 @@ __device__ __forceinline__ void affine_compose(double& P, double& Q, double Pp, 
 {
     Q = P * Qp + Q;          // x -> P (Pp x + Qp) + Q
     P = P * Pp;
-}
-
-template <int LANES>
-__device__ __forceinline__ void tridiag_solve_lanes(double* __restrict__ d, const double* __restrict__ fr,
-                                                    const double* __restrict__ ip, double gw, int n, int s,
-                                                    int lg)
-{
-    const int j0 = s << lg, j1 = min(n, (s + 1) << lg);
-    const int base = j0 + s;                 // padded index of j0
-    double P = 1.0, Q = 0.0;
-    for (int j = j0, p = base; j < j1; ++j, ++p) {
-        Q = d[p] + fr[p] * Q;
-        P = fr[p] * P;
-    }
-    for (int off = 1; off < LANES; off <<= 1) {
-        const double Pp = __shfl_up(P, off, LANES), Qp = __shfl_up(Q, off, LANES);
-        if (s >= off) affine_compose(P, Q, Pp, Qp);
-    }
-    double x = __shfl_up(Q, 1, LANES);
-    if (s == 0) x = 0.0;
-    for (int j = j0, p = base; j < j1; ++j, ++p) {
-        x = d[p] + fr[p] * x;
-        d[p] = x;
-    }
-    P = 1.0;
-    Q = 0.0;
-    for (int j = j1 - 1, p = base + (j1 - 1 - j0); j >= j0; --j, --p) {
-        const double f = (j == n - 1) ? 0.0 : ip[p] * gw;
-        Q = ip[p] * d[p] + f * Q;
-        P = f * P;
-    }
-    for (int off = 1; off < LANES; off <<= 1) {
-        const double Pp = __shfl_down(P, off, LANES), Qp = __shfl_down(Q, off, LANES);
-        if (s + off < LANES) affine_compose(P, Q, Pp, Qp);
-    }
-    x = __shfl_down(Q, 1, LANES);
-    if (s == LANES - 1) x = 0.0;
-    for (int j = j1 - 1, p = base + (j1 - 1 - j0); j >= j0; --j, --p) {
-        const double f = (j == n - 1) ? 0.0 : ip[p] * gw;
-        x = ip[p] * d[p] + f * x;
-        d[p] = x;
-    }
-}
-
-// Stage the T_i coefficients of row i in padded LDS order.
-__device__ __forceinline__ void stage_row_coeffs(double* sfr, double* sip, const double* fr,
-                                                 const double* ip, int i, int n, int lg, int nthreads)
-{
-    for (int j = threadIdx.x; j < n; j += nthreads) {
-        sfr[padj(j, lg)] = fr[(int64_t)i * n + j];
-        sip[padj(j, lg)] = ip[(int64_t)i * n + j];
-    }
 }
 
 // Order this wave's LDS writes before later LDS reads of other lanes of the
@@ -644,7 +593,7 @@ __host__ __device__ inline size_t sweep_lds_bytes(int n)
 }
 
 template <typename T, int NT, bool IR, bool REC>
-__global__ __launch_bounds__(64 * (SweepWaves<NT>::value + (IR ? 0 : kHelpers))) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep_kernel(SweepArgs a)
 {
     constexpr int W = SweepWaves<NT>::value;
     extern __shared__ __align__(32) unsigned char smem_raw[];
@@ -656,18 +605,18 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + (IR ? 0 : kHelpers)))
     const int l = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     double* extra = reinterpret_cast<double*>(smem_raw + 16 * Ctx::ldy * sizeof(T));
-    if constexpr (!IR) {
-        if (wave >= W) {
-            const int PL = padded_len(a.n, SweepHelper<T, NT>::LR);
-            SweepHelper<T, NT> hp{a, reinterpret_cast<const T*>(smem_raw), extra, wave - W, l,
-                                   seg_lg(a.n, SweepHelper<T, NT>::LR), PL};
-            hp.coef = extra + 16 * PL;
-            // the helpers' latency-bound work gets issue priority over the matrix-core
-            // waves, which have independent work queued behind every instruction
-            __builtin_amdgcn_s_setprio(3);
-            hp.run(REC);
-            return;
-        }
+    if (wave >= W) {
+        // helper waves; in the refinement sweeps (no word-line recovery here) they only
+        // pull the H blocks into L2, and own no LDS
+        const int PL = padded_len(a.n, SweepHelper<T, NT>::LR);
+        SweepHelper<T, NT> hp{a, reinterpret_cast<const T*>(smem_raw), extra, wave - W, l,
+                               seg_lg(a.n, SweepHelper<T, NT>::LR), PL};
+        hp.coef = extra + 16 * PL;
+        // the helpers' latency-bound work gets issue priority over the matrix-core
+        // waves, which have independent work queued behind every instruction
+        __builtin_amdgcn_s_setprio(3);
+        hp.run(REC && !IR);
+        return;
     }
     Ctx x{a, reinterpret_cast<T*>(smem_raw),
           reinterpret_cast<T*>(a.Z) + (int64_t)blockIdx.x * m * 16 * Ctx::n_p,
@@ -754,102 +703,247 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + (IR ? 0 : kHelpers)))
 }
 
 // ---------------------------------------------------------------------------
+// T_i w = d for one input vector over LANES lanes (padded LDS vectors d, fr, ip as
+// above), with loops run to the compile-time bound SEG >= 1 << lg and masked lanes
+// (they touch only the spare slot), so that each pass's LDS loads issue ahead of
+// its recurrence.
+template <int LANES, int SEG>
+__device__ __forceinline__ void tridiag_solve_masked(double* __restrict__ d, const double* __restrict__ fr,
+                                                     const double* __restrict__ ip, double gw, int n, int s,
+                                                     int lg, int spare)
+{
+    const int j0 = s << lg, len = max(0, min(n - j0, 1 << lg)), base = j0 + s;
+    double P = 1.0, Q = 0.0;
+#pragma unroll 8
+    for (int e = 0; e < SEG; ++e) {
+        const bool ok = e < len;
+        const int p = ok ? base + e : spare;
+        const double f = ok ? fr[p] : 0.0;                   // fr at j = 0 is zero
+        const double Qn = d[p] + f * Q, Pn = f * P;
+        Q = ok ? Qn : Q;
+        P = ok ? Pn : P;
+    }
+    for (int off = 1; off < LANES; off <<= 1) {
+        const double Pp = __shfl_up(P, off, LANES), Qp = __shfl_up(Q, off, LANES);
+        if (s >= off) affine_compose(P, Q, Pp, Qp);
+    }
+    double x = __shfl_up(Q, 1, LANES);
+    if (s == 0) x = 0.0;
+#pragma unroll 8
+    for (int e = 0; e < SEG; ++e) {
+        const bool ok = e < len;
+        const int p = ok ? base + e : spare;
+        const double f = ok ? fr[p] : 0.0;
+        const double xn = d[p] + f * x;
+        x = ok ? xn : x;
+        d[p] = x;
+    }
+    P = 1.0;
+    Q = 0.0;
+#pragma unroll 8
+    for (int e = SEG - 1; e >= 0; --e) {
+        const bool ok = e < len;
+        const int p = ok ? base + e : spare;
+        const double ipj = ok ? ip[p] : 0.0;
+        const double f = (j0 + e >= n - 1) ? 0.0 : ipj * gw;
+        const double Qn = ipj * d[p] + f * Q, Pn = f * P;
+        Q = ok ? Qn : Q;
+        P = ok ? Pn : P;
+    }
+    for (int off = 1; off < LANES; off <<= 1) {
+        const double Pp = __shfl_down(P, off, LANES), Qp = __shfl_down(Q, off, LANES);
+        if (s + off < LANES) affine_compose(P, Q, Pp, Qp);
+    }
+    x = __shfl_down(Q, 1, LANES);
+    if (s == LANES - 1) x = 0.0;
+#pragma unroll 8
+    for (int e = SEG - 1; e >= 0; --e) {
+        const bool ok = e < len;
+        const int p = ok ? base + e : spare;
+        const double ipj = ok ? ip[p] : 0.0;
+        const double f = (j0 + e >= n - 1) ? 0.0 : ipj * gw;
+        const double xn = ipj * d[p] + f * x;
+        x = ok ? xn : x;
+        d[p] = x;
+    }
+}
+
+// Row walkers of the refinement: one workgroup per half slab (8 input vectors,
+// 32 lanes each) walks the rows i = 0..m-1, so that every row of the float64
+// solution is read from memory once (a lane keeps elements j = s + 32k of the
+// rows it still needs in registers).  The next row of the solution and of the
+// coefficients is requested before a row's tridiagonal solve, so that its
+// latency hides behind it; the coefficients pass through double-buffered LDS.  One workgroup barrier per
+// row publishes the next row's coefficients.
+constexpr int kRwCols = 8;                                  // input vectors per workgroup
+constexpr int kRwLanes = 32;                                // lanes per input vector
+constexpr int kRwJ = (XBAR_MAX_N + kRwLanes - 1) / kRwLanes;   // elements per lane
+constexpr int kRwSeg = seg_cap(kRwJ);                       // longest lane segment of a solve
+constexpr int kRwCoef = (XBAR_MAX_N + 255) / 256;           // staged coefficients per thread and array
+
+template <int NC>
+struct RowCoeffs {
+    double r[NC][kRwCoef];
+    // arrays [m][ld] of row i, element j of thread t at j = t + 256 k
+    __device__ __forceinline__ void load(const double* const (&src)[NC], const int (&ld)[NC], int i, int n) {
+#pragma unroll
+        for (int k = 0; k < kRwCoef; ++k) {
+            const int jj = min((int)threadIdx.x + 256 * k, n - 1);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) r[q][k] = src[q][(int64_t)i * ld[q] + jj];
+        }
+    }
+    __device__ __forceinline__ void store(double* cb, int PL, int n, int lg) const {
+#pragma unroll
+        for (int k = 0; k < kRwCoef; ++k) {
+            const int j = threadIdx.x + 256 * k;
+            if (j < n) {
+                const int pj = padj(j, lg);
+#pragma unroll
+                for (int q = 0; q < NC; ++q) cb[q * PL + pj] = r[q][k];
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ void rw_load_row(const double* __restrict__ Ui, int n, int s, double (&u)[kRwJ])
+{
+#pragma unroll
+    for (int k = 0; k < kRwJ; ++k) {
+        const int j = s + kRwLanes * k;
+        u[k] = j < n ? Ui[j] : 0.0;
+    }
+}
+
 // Residual of the condensed system for the refinement, in float64:
 //   r_i = V_i c_i - (E_i u_i - g_bl (u_{i-1} + u_{i+1})),
 //   E_i u_i = Q_i u_i - Gam_i T_i^{-1} (Gam_i u_i)
 // with T_i^{-1} applied by the same Thomas recurrences as the word-line
-// recovery; rounded to float for the correction sweep.  One workgroup per
-// (row, 8 input vectors), 32 lanes per vector.
-constexpr int kResCols = 8;
-constexpr int kResLanes = 32;
-
+// recovery; rounded to float for the correction sweep.
 __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.n, m = a.m, n_p = a.n_p;
-    const int i = blockIdx.y;
-    const int slab = blockIdx.x / 2, half = blockIdx.x % 2;
+    const int slab = blockIdx.x >> 1, half = blockIdx.x & 1;
     if (a.slab_done[slab]) return;
-    const int lg = seg_lg(n, kResLanes), PL = padded_len(n, kResLanes);
-    double* wb = reinterpret_cast<double*>(smem_raw);             // [kResCols][PL]
-    double* sfr = wb + kResCols * PL;
-    double* sip = sfr + PL;
-    stage_row_coeffs(sfr, sip, a.fr, a.ip, i, n, lg, 256);
-    const int c = threadIdx.x / kResLanes, s = threadIdx.x % kResLanes;
-    const int colg = half * kResCols + c;
-    const int b = 16 * slab + colg;
-    const double* Gi = a.Gc + (int64_t)i * n;
-    const double* Ui = a.U + (((int64_t)slab * m + i) * 16 + colg) * n_p;
+    const int lg = seg_lg(n, kRwLanes), PL = padded_len(n, kRwLanes), spare = PL - 1;
+    double* wb = reinterpret_cast<double*>(smem_raw);        // [8][PL] right-hand sides / solutions
+    double* cb = wb + kRwCols * PL;                           // [2][5][PL] fr, ip, G, c, q of a row
+    const int c = threadIdx.x / kRwLanes, s = threadIdx.x % kRwLanes;
+    const int colg = half * kRwCols + c, b = 16 * slab + colg;
+    const int64_t rs = 16 * (int64_t)n_p;
+    const double* U = a.U + ((int64_t)slab * m * 16 + colg) * n_p;
+    float* R = reinterpret_cast<float*>(a.R) + ((int64_t)slab * m * 16 + colg) * n_p;
     double* w = wb + c * PL;
-    for (int j = s; j < n; j += kResLanes) w[padj(j, lg)] = Gi[j] * Ui[j];
-    lds_barrier();
-    tridiag_solve_lanes<kResLanes>(w, sfr, sip, a.g_wl, n, s, lg);
-    lds_barrier();
-    const double vb = (b < a.B) ? a.V[(int64_t)b * m + i] : 0.0;
-    const double* ci = a.c + (int64_t)i * n_p;
-    const double* qi = a.q + (int64_t)i * n;
-    const double* Uup = (i > 0) ? Ui - 16 * (int64_t)n_p : nullptr;
-    const double* Udn = (i + 1 < m) ? Ui + 16 * (int64_t)n_p : nullptr;
-    float* Ri = reinterpret_cast<float*>(a.R) + (((int64_t)slab * m + i) * 16 + colg) * n_p;
-    for (int j = s; j < n; j += kResLanes) {
-        double r = ci[j] * vb - (qi[j] * Ui[j] - Gi[j] * w[padj(j, lg)]);
-        if (Uup) r += a.g_bl * Uup[j];
-        if (Udn) r += a.g_bl * Udn[j];
-        Ri[j] = (float)r;
+    const double* const src[5] = {a.fr, a.ip, a.Gc, a.c, a.q};
+    const int ld[5] = {n, n, n, n_p, n};
+    RowCoeffs<5> rc;
+    double up[kRwJ], uc[kRwJ];
+#pragma unroll
+    for (int k = 0; k < kRwJ; ++k) up[k] = 0.0;
+    rw_load_row(U, n, s, uc);
+    rc.load(src, ld, 0, n);
+    rc.store(cb, PL, n, lg);
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+        const double* cf = cb + (i & 1) * 5 * PL;
+        // the next row of the solution and of the coefficients, requested before
+        // this row's solve and used after it
+        double un[kRwJ];
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) un[k] = 0.0;
+        if (i + 1 < m) {
+            rw_load_row(U + (i + 1) * rs, n, s, un);
+            rc.load(src, ld, i + 1, n);
+        }
+        const double vb = b < a.B ? a.V[(int64_t)b * m + i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) {
+            const int j = s + kRwLanes * k;
+            if (j < n) w[padj(j, lg)] = cf[2 * PL + padj(j, lg)] * uc[k];
+        }
+        wave_lds_fence();
+        tridiag_solve_masked<kRwLanes, kRwSeg>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
+        wave_lds_fence();
+        float* Ri = R + i * rs;
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) {
+            const int j = s + kRwLanes * k;
+            if (j < n) {
+                const int pj = padj(j, lg);
+                const double r = cf[3 * PL + pj] * vb - (cf[4 * PL + pj] * uc[k] - cf[2 * PL + pj] * w[pj]) +
+                                 a.g_bl * (up[k] + un[k]);
+                Ri[j] = (float)r;
+            }
+        }
+        for (int j = n + s; j < n_p; j += kRwLanes) Ri[j] = 0.0f;      // padding stays zero
+        if (i + 1 < m) rc.store(cb + ((i + 1) & 1) * 5 * PL, PL, n, lg);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) {
+            up[k] = uc[k];
+            uc[k] = un[k];
+        }
     }
-    for (int j = n + s; j < n_p; j += kResLanes) Ri[j] = 0.0f;      // padding stays zero
 }
 
-// Word-line recovery and node-voltage output from the float64 solution of the
-// refinement (one workgroup per (row, 8 input vectors), 32 lanes per vector).
-constexpr int kRecCols = kResCols;
-
-template <typename T>
+// Word-line recovery and node-voltage output from the final float64 solution of
+// the refinement: T_i w_i = g_src V_i e_0 + Gam_i u_i, then (w_ij, u_ij) in the
+// paper's interleaved order, 16 bytes per lane and 512 contiguous bytes per vector
+// and store instruction.
 __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.n, m = a.m, n_p = a.n_p;
-    const int lg = seg_lg(n, kResLanes), PL = padded_len(n, kResLanes);
-    double* ub = reinterpret_cast<double*>(smem_raw);       // [kRecCols][n]
-    double* wb = ub + kRecCols * n;                           // [kRecCols][PL]
-    double* sfr = wb + kRecCols * PL;
-    double* sip = sfr + PL;
-    const int i = blockIdx.y;
-    const int slab = blockIdx.x / 2, half = blockIdx.x % 2;
-    stage_row_coeffs(sfr, sip, a.fr, a.ip, i, n, lg, 256);
-    const int c = threadIdx.x / kResLanes, s = threadIdx.x % kResLanes;
-    const int b = 16 * slab + half * kRecCols + c;
-    if (a.slab_final != nullptr) {
-        const double* Ui = a.U[a.slab_final[slab]] + ((int64_t)slab * m + i) * 16 * n_p;
-        for (int e = threadIdx.x; e < kRecCols * n; e += blockDim.x) {
-            const int cc = e / n, j = e % n;
-            ub[e] = Ui[(half * kRecCols + cc) * n_p + pos<T>(j)];
+    const int slab = blockIdx.x >> 1, half = blockIdx.x & 1;
+    const int lg = seg_lg(n, kRwLanes), PL = padded_len(n, kRwLanes), spare = PL - 1;
+    double* wb = reinterpret_cast<double*>(smem_raw);        // [8][PL]
+    double* cb = wb + kRwCols * PL;                           // [2][3][PL] fr, ip, G of a row
+    const int c = threadIdx.x / kRwLanes, s = threadIdx.x % kRwLanes;
+    const int colg = half * kRwCols + c, b = 16 * slab + colg;
+    const bool bval = b < a.B;
+    const int64_t rs = 16 * (int64_t)n_p;
+    const double* U = a.U[a.slab_final[slab]] + ((int64_t)slab * m * 16 + colg) * n_p;
+    double* w = wb + c * PL;
+    const double* const src[3] = {a.fr, a.ip, a.Gc};
+    const int ld[3] = {n, n, n};
+    RowCoeffs<3> rc;
+    double uc[kRwJ];
+    rw_load_row(U, n, s, uc);
+    rc.load(src, ld, 0, n);
+    rc.store(cb, PL, n, lg);
+    __syncthreads();
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    for (int i = 0; i < m; ++i) {
+        const double* cf = cb + (i & 1) * 3 * PL;
+        double un[kRwJ];
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) un[k] = 0.0;
+        if (i + 1 < m) {
+            rw_load_row(U + (i + 1) * rs, n, s, un);
+            rc.load(src, ld, i + 1, n);
         }
-    } else {
-        const T* Zi = reinterpret_cast<const T*>(a.Z) + ((int64_t)slab * m + i) * 16 * n_p;
-        for (int e = threadIdx.x; e < kRecCols * n; e += blockDim.x) {
-            const int cc = e / n, j = e % n;
-            ub[e] = (double)Zi[(half * kRecCols + cc) * n_p + pos<T>(j)];
+        const double vb = bval ? a.V[(int64_t)b * m + i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) {
+            const int j = s + kRwLanes * k;
+            if (j < n) w[padj(j, lg)] = cf[2 * PL + padj(j, lg)] * uc[k] + (j == 0 ? a.g_src * vb : 0.0);
         }
-    }
-    lds_barrier();
-    const double* Gi = a.Gc + (int64_t)i * n;
-    const double vin = (b < a.B) ? a.V[(int64_t)b * m + i] : 0.0;
-    const double* u = ub + c * n;
-    double* wv = wb + c * PL;
-    for (int j = s; j < n; j += kResLanes) wv[padj(j, lg)] = Gi[j] * u[j] + (j == 0 ? a.g_src * vin : 0.0);
-    lds_barrier();
-    tridiag_solve_lanes<kResLanes>(wv, sfr, sip, a.g_wl, n, s, lg);
-    lds_barrier();
-    if (a.node_v == nullptr) return;
-    for (int cc = 0; cc < kRecCols; ++cc) {
-        const int bb = 16 * slab + half * kRecCols + cc;
-        if (bb >= a.B) break;
-        double* out = a.node_v + (int64_t)bb * 2 * m * n + (int64_t)2 * i * n;
-        for (int k = threadIdx.x; k < 2 * n; k += blockDim.x) {
-            const int j = k >> 1;
-            out[k] = (k & 1) ? ub[cc * n + j] : wb[cc * PL + padj(j, lg)];
+        wave_lds_fence();
+        tridiag_solve_masked<kRwLanes, kRwSeg>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
+        wave_lds_fence();
+        if (bval) {
+            double* out = a.node_v + ((int64_t)b * m + i) * 2 * n;
+#pragma unroll
+            for (int k = 0; k < kRwJ; ++k) {
+                const int j = s + kRwLanes * k;
+                if (j < n) __builtin_nontemporal_store(d2v{w[padj(j, lg)], uc[k]}, reinterpret_cast<d2v*>(out + 2 * j));
+            }
         }
+        if (i + 1 < m) rc.store(cb + ((i + 1) & 1) * 3 * PL, PL, n, lg);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRwJ; ++k) uc[k] = un[k];
     }
 }
 
@@ -857,7 +951,7 @@ __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
 template <typename T, int NT, bool IR>
 hipError_t launch_sweep_nt(const SweepArgs& a, hipStream_t s)
 {
-    constexpr int threads = 64 * (SweepWaves<NT>::value + (IR ? 0 : kHelpers));
+    constexpr int threads = 64 * (SweepWaves<NT>::value + kHelpers);
     const size_t lds = sweep_lds_bytes<T, NT, IR>(a.n);
     if constexpr (!IR) {
         if (a.node_v != nullptr) {
@@ -899,19 +993,15 @@ hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s)
 
 hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s)
 {
-    const size_t lds = ((size_t)xbk::kResCols + 2) * xbk::padded_len(a.n, xbk::kResLanes) * sizeof(double);
-    hipLaunchKernelGGL(xbk::residual_kernel, dim3(2 * a.nslab, a.m), dim3(256), lds, s, a);
+    const size_t lds = ((size_t)xbk::kRwCols + 2 * 5) * xbk::padded_len(a.n, xbk::kRwLanes) * sizeof(double);
+    hipLaunchKernelGGL(xbk::residual_kernel, dim3(2 * a.nslab), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, bool fp32, hipStream_t s)
+hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, hipStream_t s)
 {
-    const size_t lds = (xbk::kRecCols * (size_t)a.n +
-                        (xbk::kRecCols + 2) * (size_t)xbk::padded_len(a.n, xbk::kResLanes)) * sizeof(double);
-    dim3 grid(2 * a.nslab, a.m);
-    if (fp32)
-        hipLaunchKernelGGL(xbk::recover_kernel<float>, grid, dim3(256), lds, s, a);
-    else
-        hipLaunchKernelGGL(xbk::recover_kernel<double>, grid, dim3(256), lds, s, a);
+    if (a.slab_final == nullptr) return hipErrorInvalidValue;
+    const size_t lds = ((size_t)xbk::kRwCols + 2 * 3) * xbk::padded_len(a.n, xbk::kRwLanes) * sizeof(double);
+    hipLaunchKernelGGL(xbk::recover_kernel, dim3(2 * a.nslab), dim3(256), lds, s, a);
     return hipGetLastError();
 }

@@ -571,16 +571,15 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         r.g_src = 1.0 / p->g.r_src;
         r.g_wl = 1.0 / p->g.r_wl;
         r.V = V;
-        r.Z = p->d.Z;
         r.U[0] = p->d.U[0];
         r.U[1] = p->d.U[1];
-        r.slab_final = ir ? p->d.slab_final : nullptr;
+        r.slab_final = p->d.slab_final;
         r.fr = p->d.fr;
         r.ip = p->d.ip;
         r.Gc = p->d.Gc;
         r.node_v = node_v;
         if (p->timing && !p->t_recover.begin(p->stream)) return XBAR_ERR_DEVICE;
-        if (xbk_launch_recover(r, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+        if (xbk_launch_recover(r, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
         if (p->timing && !p->t_recover.end(p->stream)) return XBAR_ERR_DEVICE;
     }
     p->state = kSolved;
