@@ -23,6 +23,28 @@
 
 namespace xbk {
 
+// Row k of FRG tile (k >> 4, c) of an n_p x n_p block: the tile's 16 values v[e]
+// (e = column within the tile), as 16-byte stores (two values per lane for
+// float64: columns q and q+4, q+8 and q+12 of lane 16q + r; four for float32).
+template <typename T>
+__device__ __forceinline__ void store_tile_row(T* E, int n_p, int k, int c, const double (&v)[16])
+{
+    T* tile = E + ((int64_t)(k >> 4) * (n_p >> 4) + c) * 256;
+    const int r = k & 15;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int l = 16 * q + r;
+        if constexpr (sizeof(T) == 8) {
+            typedef double d2v __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<d2v*>(tile + frg_slot<T>(l, 0)) = d2v{v[q], v[q + 4]};
+            *reinterpret_cast<d2v*>(tile + frg_slot<T>(l, 2)) = d2v{v[q + 8], v[q + 12]};
+        } else {
+            *reinterpret_cast<f4_t*>(tile + frg_slot<T>(l, 0)) =
+                f4_t{(float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]};
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void condense_kernel(CondenseArgs a)
 {
@@ -77,27 +99,71 @@ __global__ __launch_bounds__(256) void condense_kernel(CondenseArgs a)
     const double qb_up = (i > 0) ? a.g_bl : 0.0;
     const double qb_dn = (i < a.m - 1) ? a.g_bl : a.g_sense;
     T* E = reinterpret_cast<T*>(a.E) + (int64_t)i * n_p * n_p;
+    const int ct = n_p >> 4;
+    // E is symmetric, so thread k produces row k of E as it walks column k of
+    // T^{-1}; a tile's 16 values of the row are kept in registers and written
+    // with 16-byte stores, so the 16 threads of a tile row fill whole lines.
     for (int k = threadIdx.x; k < n_p; k += blockDim.x) {
+        double v[16];
         if (k >= n) {
-            for (int j = 0; j < n_p; ++j) E[frg<T>(j, k, n_p)] = (T)0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = 0.0;
+            for (int c = 0; c < ct; ++c) store_tile_row<T>(E, n_p, k, c, v);
             a.c[(int64_t)i * n_p + k] = 0.0;
             continue;
         }
+        const int ck = k >> 4, kk = k & 15;
         const double Gk = Gs[k];
         const double qk = Gk + qb_up + qb_dn;
+        double home[16];
+        // up column k within the home tile: x_j = x_{j+1} g_wl / p_j, j = k-1 .. 16 ck
         double x = dg[k];
-        E[frg<T>(k, k, n_p)] = (T)(qk - Gk * x * Gk);
-        for (int j = k - 1; j >= 0; --j) {          // up column k: x_j = x_{j+1} g_wl / p_j
-            x *= rf[j];
-            E[frg<T>(j, k, n_p)] = (T)(-(Gs[j] * x * Gk));
+#pragma unroll
+        for (int e = 15; e >= 0; --e) {
+            const int j = 16 * ck + e;
+            if (e < kk) {
+                x *= rf[j];
+                home[e] = -(Gs[j] * x * Gk);
+            } else {
+                home[e] = 0.0;
+            }
+        }
+        home[kk] = qk - Gk * dg[k] * Gk;
+        // the tiles to the left, right to left
+        for (int c = ck - 1; c >= 0; --c) {
+#pragma unroll
+            for (int e = 15; e >= 0; --e) {
+                const int j = 16 * c + e;
+                x *= rf[j];
+                v[e] = -(Gs[j] * x * Gk);
+            }
+            store_tile_row<T>(E, n_p, k, c, v);
         }
         a.c[(int64_t)i * n_p + k] = a.g_src * Gk * x;   // x = (T^{-1})_{0k} = (T^{-1})_{k0}
+        // down column k: x_j = x_{j-1} g_wl / pb_j, j = k+1 .. n-1 (zero on the padding)
         x = dg[k];
-        for (int j = k + 1; j < n; ++j) {           // down column k: x_j = x_{j-1} g_wl / pb_j
-            x *= rb[j];
-            E[frg<T>(j, k, n_p)] = (T)(-(Gs[j] * x * Gk));
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int j = 16 * ck + e;
+            if (e > kk && j < n) {
+                x *= rb[j];
+                home[e] = -(Gs[j] * x * Gk);
+            }
         }
-        for (int j = n; j < n_p; ++j) E[frg<T>(j, k, n_p)] = (T)0;
+        store_tile_row<T>(E, n_p, k, ck, home);
+        for (int c = ck + 1; c < ct; ++c) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int j = 16 * c + e;
+                if (j < n) {
+                    x *= rb[j];
+                    v[e] = -(Gs[j] * x * Gk);
+                } else {
+                    v[e] = 0.0;
+                }
+            }
+            store_tile_row<T>(E, n_p, k, c, v);
+        }
         a.q[(int64_t)i * n + k] = qk;
         a.fr[(int64_t)i * n + k] = (k == 0) ? 0.0 : rf[k - 1];
         a.ip[(int64_t)i * n + k] = 1.0 / fp[k];
