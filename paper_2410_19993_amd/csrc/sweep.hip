@@ -101,16 +101,31 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
         for (int d = 0; d < DP; ++d) {
             const int K = K0 + d;
             const v4 bv = *reinterpret_cast<const v4*>(ybuf + r * ldy + 16 * K + 4 * q);
+            if constexpr (sizeof(T) == 4) {
+                // float32: tile by tile, the tile's products and then the load of its
+                // chunk K + DP, with a scheduling fence after every second tile, so that
+                // the loads stay spread between the products (the float64 waves have no
+                // registers to spare for this ordering)
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+                for (int t = 0; t < TW; ++t) {
 #pragma unroll
-                for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(ring.r[d][t][s], bv[s], acc[t]);
-            if (K + DP < KC) {
-#pragma unroll
-                for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + DP, l);
+                    for (int s = 0; s < 4; ++s) acc[t] = Frag<T>::mma(ring.r[d][t][s], bv[s], acc[t]);
+                    ring.r[d][t] = K + DP < KC ? load_frag<T>(Hi, KC, TW * w + t, K + DP, l)
+                                               : load_frag<T>(Hnext, KC, TW * w + t, K + DP - KC, l);
+                    if (t & 1) __builtin_amdgcn_sched_barrier(0);
+                }
             } else {
 #pragma unroll
-                for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hnext, KC, TW * w + t, K + DP - KC, l);
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(ring.r[d][t][s], bv[s], acc[t]);
+                if (K + DP < KC) {
+#pragma unroll
+                    for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + DP, l);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hnext, KC, TW * w + t, K + DP - KC, l);
+                }
             }
             hook(K);
         }
