@@ -97,6 +97,9 @@ typedef struct {
  *                1e-12.  Must be finite, 0 <= ir_tol < 1.  Ignored for FP64.
  *   ir_max_iter  IR modes: refinement steps allowed, 1..100 (0 selects 10).
  *   hip_stream   hipStream_t the plan's work is queued on (NULL = null stream).
+ *                The plan also creates one stream of its own (default priority,
+ *                non-blocking), used only inside xbar_factor and joined back to
+ *                hip_stream before that call returns; xbar_destroy releases it.
  * Returns XBAR_ERR_ARG, XBAR_ERR_DEVICE, XBAR_ERR_ALLOC or XBAR_OK.
  */
 xbar_status xbar_create(const xbar_geometry* geom, xbar_precision p, int32_t max_batch,
@@ -115,7 +118,10 @@ xbar_status xbar_assemble(xbar_plan plan, const double* G);
  * LU-decompose the assembled system once per conductance map (Sec. II.C):
  * a block LU over the m row blocks.  Requires a prior xbar_assemble
  * (otherwise XBAR_ERR_STATE).  A block pivot that is not positive sets
- * XBAR_ERR_NOT_SPD on the device.
+ * XBAR_ERR_NOT_SPD on the device.  The Newton-Schulz inversion of the pivot
+ * blocks runs its two independent chains on the plan stream and the plan's
+ * own second stream, and reads its schedule state back to the host, so the
+ * call synchronises the plan stream (it cannot be captured into a graph).
  */
 xbar_status xbar_factor(xbar_plan plan);
 
