@@ -131,3 +131,36 @@ def test_plan_reuse_many_batches():
             I = p.currents().cpu().numpy()
             p.check()
             assert rel_err(I, ref.currents[lo:hi]).max() <= TOL_FP64
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_user_stream_and_refactor(precision):
+    """A plan queued on a non-default stream gives the bits of the default stream: the
+    factor runs its second chain on the plan's own stream, forked from and joined back
+    to the caller's.  Factoring the same map again on the same plan (the schedule then
+    launches the slot counts the first factorization needed) gives the same bits too."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    wl = workloads.random_crossbar(33, 96, 21, 16)
+    log(f"case user stream {precision}: m=33 n=96 B=21")
+    I0, nv0, (st0, _) = gpu_solve(wl.G, wl.V, wl.geom, precision)
+    assert st0 == 0
+    g = wl.geom
+    s = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(s):
+        Gd = torch.from_numpy(wl.G).cuda()
+        Vd = torch.from_numpy(np.ascontiguousarray(wl.V)).cuda()
+        with xb.Plan(33, 96, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=21, stream=s) as p:
+            for _ in range(2):
+                p.assemble(Gd)
+                p.factor()
+                nv = torch.empty((21, 2 * 33 * 96), dtype=torch.float64, device="cuda")
+                p.solve_batch(Vd, nv)
+                outs.append((p.currents(), nv))
+            st, _ = p.info()
+    s.synchronize()
+    assert st == 0
+    for I, nv in outs:
+        assert np.array_equal(I.cpu().numpy(), I0) and np.array_equal(nv.cpu().numpy(), nv0)
