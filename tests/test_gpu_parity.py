@@ -12,7 +12,7 @@ import pytest
 import oracle
 import workloads
 from oracle import diagnostics as dg
-from tests.gpu_util import GOLDEN, TOL_FP64, gpu_solve, log, node_rel_err, rel_err
+from tests.gpu_util import GOLDEN, TOL_FP64, TOL_IR, gpu_solve, log, node_rel_err, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -164,3 +164,11 @@ def test_user_stream_and_refactor(precision):
     assert st == 0
     for I, nv in outs:
         assert np.array_equal(I.cpu().numpy(), I0) and np.array_equal(nv.cpu().numpy(), nv0)
+
+
+@pytest.mark.parametrize("m,n,B,seed", [(1024, 64, 24, 17), (513, 37, 9, 18)])
+def test_long_chains(m, n, B, seed):
+    """Tall crossbars: factor chains of 512 and 256 rows, and an odd row count."""
+    wl = workloads.random_crossbar(m, n, B, seed)
+    _check_against_oracle(wl)
+    _check_against_oracle(wl, precision="fp32_ir", tol=TOL_IR)
