@@ -8,7 +8,7 @@ output currents.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the solver runs on one GPU.
 """
 from __future__ import annotations
 
@@ -105,7 +105,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the solver has no multi-GPU path in this build.", file=sys.stderr)
+              "the solver has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
