@@ -721,17 +721,18 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
 // T_i w = d for one input vector over LANES lanes (padded LDS vectors d, fr, ip as
 // above), with loops run to the compile-time bound SEG >= 1 << lg and masked lanes
 // (they touch only the spare slot), so that each pass's LDS loads issue ahead of
-// its recurrence.
-template <int LANES, int SEG>
+// its recurrence.  FULL: every lane owns exactly SEG elements (n = LANES * SEG),
+// so no lane is masked and the LDS offsets are immediates.
+template <int LANES, int SEG, bool FULL>
 __device__ __forceinline__ void tridiag_solve_masked(double* __restrict__ d, const double* __restrict__ fr,
                                                      const double* __restrict__ ip, double gw, int n, int s,
                                                      int lg, int spare)
 {
-    const int j0 = s << lg, len = max(0, min(n - j0, 1 << lg)), base = j0 + s;
+    const int j0 = s << lg, len = FULL ? SEG : max(0, min(n - j0, 1 << lg)), base = j0 + s;
     double P = 1.0, Q = 0.0;
 #pragma unroll 8
     for (int e = 0; e < SEG; ++e) {
-        const bool ok = e < len;
+        const bool ok = FULL || e < len;
         const int p = ok ? base + e : spare;
         const double f = ok ? fr[p] : 0.0;                   // fr at j = 0 is zero
         const double Qn = d[p] + f * Q, Pn = f * P;
@@ -746,7 +747,7 @@ __device__ __forceinline__ void tridiag_solve_masked(double* __restrict__ d, con
     if (s == 0) x = 0.0;
 #pragma unroll 8
     for (int e = 0; e < SEG; ++e) {
-        const bool ok = e < len;
+        const bool ok = FULL || e < len;
         const int p = ok ? base + e : spare;
         const double f = ok ? fr[p] : 0.0;
         const double xn = d[p] + f * x;
@@ -757,7 +758,7 @@ __device__ __forceinline__ void tridiag_solve_masked(double* __restrict__ d, con
     Q = 0.0;
 #pragma unroll 8
     for (int e = SEG - 1; e >= 0; --e) {
-        const bool ok = e < len;
+        const bool ok = FULL || e < len;
         const int p = ok ? base + e : spare;
         const double ipj = ok ? ip[p] : 0.0;
         const double f = (j0 + e >= n - 1) ? 0.0 : ipj * gw;
@@ -773,7 +774,7 @@ __device__ __forceinline__ void tridiag_solve_masked(double* __restrict__ d, con
     if (s == LANES - 1) x = 0.0;
 #pragma unroll 8
     for (int e = SEG - 1; e >= 0; --e) {
-        const bool ok = e < len;
+        const bool ok = FULL || e < len;
         const int p = ok ? base + e : spare;
         const double ipj = ok ? ip[p] : 0.0;
         const double f = (j0 + e >= n - 1) ? 0.0 : ipj * gw;
@@ -835,12 +836,11 @@ __device__ __forceinline__ void rw_load_row(const double* __restrict__ Ui, int n
 //   E_i u_i = Q_i u_i - Gam_i T_i^{-1} (Gam_i u_i)
 // with T_i^{-1} applied by the same Thomas recurrences as the word-line
 // recovery; rounded to float for the correction sweep.
-__global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
+template <bool FULL>
+__device__ __forceinline__ void residual_walk(const ResidualArgs& a, unsigned char* smem_raw)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.n, m = a.m, n_p = a.n_p;
     const int slab = blockIdx.x >> 1, half = blockIdx.x & 1;
-    if (a.slab_done[slab]) return;
     const int lg = seg_lg(n, kRwLanes), PL = padded_len(n, kRwLanes), spare = PL - 1;
     double* wb = reinterpret_cast<double*>(smem_raw);        // [8][PL] right-hand sides / solutions
     double* cb = wb + kRwCols * PL;                           // [2][5][PL] fr, ip, G, c, q of a row
@@ -875,16 +875,16 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;
-            if (j < n) w[padj(j, lg)] = cf[2 * PL + padj(j, lg)] * uc[k];
+            if (FULL || j < n) w[padj(j, lg)] = cf[2 * PL + padj(j, lg)] * uc[k];
         }
         wave_lds_fence();
-        tridiag_solve_masked<kRwLanes, kRwSeg>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
+        tridiag_solve_masked<kRwLanes, kRwSeg, FULL>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
         wave_lds_fence();
         float* Ri = R + i * rs;
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;
-            if (j < n) {
+            if (FULL || j < n) {
                 const int pj = padj(j, lg);
                 const double r = cf[3 * PL + pj] * vb - (cf[4 * PL + pj] * uc[k] - cf[2 * PL + pj] * w[pj]) +
                                  a.g_bl * (up[k] + un[k]);
@@ -902,13 +902,23 @@ __global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void residual_kernel(ResidualArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (a.slab_done[blockIdx.x >> 1]) return;
+    if (a.n == kRwLanes * kRwSeg)
+        residual_walk<true>(a, smem_raw);
+    else
+        residual_walk<false>(a, smem_raw);
+}
+
 // Word-line recovery and node-voltage output from the final float64 solution of
 // the refinement: T_i w_i = g_src V_i e_0 + Gam_i u_i, then (w_ij, u_ij) in the
 // paper's interleaved order, 16 bytes per lane and 512 contiguous bytes per vector
 // and store instruction.
-__global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
+template <bool FULL>
+__device__ __forceinline__ void recover_walk(const RecoverArgs& a, unsigned char* smem_raw)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.n, m = a.m, n_p = a.n_p;
     const int slab = blockIdx.x >> 1, half = blockIdx.x & 1;
     const int lg = seg_lg(n, kRwLanes), PL = padded_len(n, kRwLanes), spare = PL - 1;
@@ -942,17 +952,17 @@ __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;
-            if (j < n) w[padj(j, lg)] = cf[2 * PL + padj(j, lg)] * uc[k] + (j == 0 ? a.g_src * vb : 0.0);
+            if (FULL || j < n) w[padj(j, lg)] = cf[2 * PL + padj(j, lg)] * uc[k] + (j == 0 ? a.g_src * vb : 0.0);
         }
         wave_lds_fence();
-        tridiag_solve_masked<kRwLanes, kRwSeg>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
+        tridiag_solve_masked<kRwLanes, kRwSeg, FULL>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
         wave_lds_fence();
         if (bval) {
             double* out = a.node_v + ((int64_t)b * m + i) * 2 * n;
 #pragma unroll
             for (int k = 0; k < kRwJ; ++k) {
                 const int j = s + kRwLanes * k;
-                if (j < n) __builtin_nontemporal_store(d2v{w[padj(j, lg)], uc[k]}, reinterpret_cast<d2v*>(out + 2 * j));
+                if (FULL || j < n) __builtin_nontemporal_store(d2v{w[padj(j, lg)], uc[k]}, reinterpret_cast<d2v*>(out + 2 * j));
             }
         }
         if (i + 1 < m) rc.store(cb + ((i + 1) & 1) * 3 * PL, PL, n, lg);
@@ -960,6 +970,14 @@ __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) uc[k] = un[k];
     }
+}
+
+// (the unmasked solve measured 5% slower here: this walk is bound by its node-voltage
+// writes, and the unmasked path holds more registers)
+__global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    recover_walk<false>(a, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
