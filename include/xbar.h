@@ -55,8 +55,10 @@ typedef enum {
 typedef enum {
     XBAR_FP64 = 0,      /* factor and substitution in float64 (the paper's method)         */
     XBAR_FP32_IR = 1,   /* factor and substitution in float32 on MFMA, refined in float64  */
-    XBAR_BF16_IR = 2    /* reserved (bfloat16 block inverses): not built, xbar_create
-                           returns XBAR_ERR_ARG                                          */
+    XBAR_BF16_IR = 2    /* trial: as XBAR_FP32_IR, with the factor's inverse blocks rounded
+                           to bfloat16 values (8-bit significand, ties to even) before the
+                           float32 sweeps; measures whether a bfloat16-accurate factor still
+                           drives the float64 refinement (else XBAR_ERR_NO_CONVERGENCE) */
 } xbar_precision;
 
 typedef struct {

@@ -199,7 +199,6 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     if (max_batch < 1) return XBAR_ERR_ARG;
     if (!(std::isfinite(ir_tol) && ir_tol >= 0.0 && ir_tol < 1.0)) return XBAR_ERR_ARG;
     if (ir_max_iter < 0 || ir_max_iter > 100) return XBAR_ERR_ARG;
-    if (prec == XBAR_BF16_IR) return XBAR_ERR_ARG;   // bfloat16 factor: not built in this library
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -443,6 +442,19 @@ hipError_t run_ns(xbar_plan p, bool* failed)
 }
 
 __global__ void clear_flag_kernel(int* f, int which) { f[which] = 0; }
+
+// The bfloat16 trial: round every stored inverse block to the nearest bfloat16
+// value (8-bit significand, ties to even), kept in float32 storage.  NaN stays NaN.
+__global__ void round_bf16_kernel(float* x, int64_t count)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        const float v = x[e];
+        if (v != v) continue;
+        uint32_t u = __float_as_uint(v);
+        u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+        x[e] = __uint_as_float(u);
+    }
+}
 __global__ void set_flag_kernel(int* f, int which) { f[which] = 1; }
 
 }  // namespace
@@ -484,6 +496,13 @@ xbar_status xbar_factor(xbar_plan p)
             hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
                                (int)xbk::kErrConv);
         }
+    }
+    if (p->prec == XBAR_BF16_IR) {
+        // the trial's factor: the float32 inverse blocks at bfloat16 precision
+        const int64_t count = (int64_t)p->g.m * p->n_p * p->n_p;
+        hipLaunchKernelGGL(round_bf16_kernel, dim3(2048), dim3(256), 0, p->stream, reinterpret_cast<float*>(p->d.H),
+                           count);
+        if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
     }
     if (p->timing && !p->t_factor.end(p->stream)) return XBAR_ERR_DEVICE;
     p->state = kFactored;
