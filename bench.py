@@ -7,6 +7,12 @@ forward/back substitution with every node voltage written to HBM, and the
 output currents.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
+                    [--no-shortcuts]
+
+Besides the metric (float64, node voltages written) the line reports the
+float32 + float64-refinement leg and exact shortcuts that skip work the metric
+does: the same path without node voltages, the sweeps alone, and the output
+currents through the transfer matrix (one product per batch once T is built).
 
 Prints one JSON line.  --gpus N > 1 is refused: the solver runs on one GPU.
 """
@@ -102,6 +108,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-shortcuts", action="store_true",
+                    help="skip the currents-only and transfer-matrix legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -134,14 +142,14 @@ def main():
         Ih = I.cpu().numpy()[workloads.c3_subset()]
         return float((np.max(np.abs(Ih - ref), axis=1) / np.max(np.abs(ref), axis=1)).max())
 
-    def run(precision, steps, warmup, ir_tol=0.0):
+    def run(precision, steps, warmup, ir_tol=0.0, nodes=True):
         plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B,
                        ir_tol=ir_tol, stream=stream)
 
         def step():
             plan.assemble(G)
             plan.factor()
-            plan.solve_batch(V, node_v)
+            plan.solve_batch(V, node_v if nodes else None)
             plan.currents(I)
 
         for w in range(warmup):
@@ -162,8 +170,57 @@ def main():
         plan.check()
         err = verify()
         plan.close()
-        log(f"{precision}: {steps} steps in {wall:.3f} s")
+        log(f"{precision}{'' if nodes else ' currents only'}: {steps} steps in {wall:.3f} s")
         return wall * 1e3 / steps, tm, info, err
+
+    def run_transfer(steps, reps=50):
+        """Currents through the transfer matrix: per conductance map assemble, factor and
+        T (m unit-input solves); per batch one float64 matrix-core product I = V T."""
+        plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, "fp64", max_batch=B, stream=stream)
+        T = torch.empty((m, n), dtype=torch.float64, device="cuda")
+
+        def per_map():
+            plan.assemble(G)
+            plan.factor()
+            plan.transfer(T)
+
+        per_map()
+        plan.transfer_apply(T, V, I)
+        torch.cuda.synchronize()
+        plan.check()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            per_map()
+            plan.transfer_apply(T, V, I)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            per_map()
+        torch.cuda.synchronize()
+        map_ms = (time.perf_counter() - t0) * 1e3 / steps
+        # the product alone, timed with events on the stream it is launched on
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.transfer_apply(T, V, I)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        apply_ms = e0.elapsed_time(e1) / reps
+        plan.check()
+        err = verify()
+        plan.close()
+        flops = 2.0 * B * m * n
+        log(f"transfer: per map {map_ms:.2f} ms, product {apply_ms * 1e3:.1f} us")
+        return {"value": B / (step_ms * 1e-3), "unit": "solves/s", "ms_per_step": step_ms,
+                "per_map_ms": map_ms, "apply_ms": apply_ms,
+                "apply_solves_per_s": B / (apply_ms * 1e-3),
+                "apply_roofline": {"bound": "mfma", "kernel": "transfer_apply_kernel<true>",
+                                   "achieved": flops / (apply_ms * 1e-3) / 1e12,
+                                   "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
+                                   "frac": flops / (apply_ms * 1e-3) / PEAK_FP64_MFMA,
+                                   "flops_per_launch": flops},
+                "max_rel_err_vs_oracle": err}
 
     ms64, tm, info64, err64 = run("fp64", args.steps, args.warmup)
     # kernels: algorithmic work per launch
@@ -197,6 +254,18 @@ def main():
         "roofline": roof,
         "max_rel_err_vs_oracle": err64,
     }
+    # Exact shortcuts, outside the metric: the same fp64 path without node voltages, the
+    # substitution sweeps alone, and currents through the transfer matrix.
+    if not args.no_shortcuts:
+        msc, tmc, _, errc = run("fp64", args.steps, args.warmup, nodes=False)
+        result["currents_only"] = {
+            "value": B / (msc * 1e-3), "unit": "solves/s", "ms_per_step": msc,
+            "sweep_ms": per(tmc.sweep_ms, tmc.sweep_launches),
+            "solve_only_solves_per_s": B / (per(tmc.sweep_ms, tmc.sweep_launches) * 1e-3),
+            "max_rel_err_vs_oracle": errc}
+        result["solve_only"] = {"value": B / (k_sweep * 1e-3), "unit": "solves/s",
+                                "note": "fp64 sweeps with node voltages, factor excluded"}
+        result["transfer"] = run_transfer(args.steps)
     if not args.no_fp32_ir:
         # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
         # refinement stops once its error estimate is below 1e-10 (the error actually

@@ -149,6 +149,39 @@ xbar_status xbar_solve_batch(xbar_plan plan, const double* V, int32_t B, double*
 xbar_status xbar_currents(xbar_plan plan, double* I);
 
 /*
+ * Transfer matrix of the factored crossbar: T[i][j] = the output current of bit
+ * line j (as xbar_currents reports it) when word line i is driven with 1 V and
+ * every other source with 0 V.  The nodal system G v = I has a right-hand side
+ * that is linear in the source voltages (Sec. II.A, Eqs. 5-7), so the currents
+ * of any input vector are I[b][j] = sum_i V[b][i] T[i][j]: see
+ * xbar_transfer_apply.  T is computed by solving the m unit inputs with the
+ * plan's factorization and precision mode, min(max_batch, m) of them per
+ * xbar_solve_batch, without node voltages.
+ *   T  device, [m][n] row-major, amperes per volt; caller-owned.
+ * Requires a prior xbar_factor (XBAR_ERR_STATE otherwise).  Uses the plan's
+ * batch workspace: the result of an earlier xbar_solve_batch is dropped and
+ * xbar_currents returns XBAR_ERR_STATE until the next xbar_solve_batch.  The
+ * unit solves are not counted by the phase timers.  Device errors (e.g. IR
+ * modes not converging) set the sticky flags as xbar_solve_batch does.
+ */
+xbar_status xbar_transfer(xbar_plan plan, double* T);
+
+/*
+ * Output currents through the transfer matrix: I[b][j] = sum_i V[b][i] T[i][j],
+ * a float64 matrix-core product queued on the plan's stream.  Exact up to
+ * rounding for the linear network of Sec. II.A, and the same result as
+ * xbar_solve_batch + xbar_currents for the conductances T was computed from.
+ *   T  device, [m][n] row-major, from xbar_transfer (of this plan or another
+ *      with the same m and n).
+ *   V  device, [B][m] row-major, volts.
+ *   B  1 <= B; not bounded by max_batch (the call uses no plan workspace).
+ *   I  device, [B][n] row-major, amperes; must not overlap V or T.
+ * Independent of the plan's state.  XBAR_ERR_ARG on NULL pointers, B < 1 or
+ * overlapping I; XBAR_ERR_DEVICE on a launch error.
+ */
+xbar_status xbar_transfer_apply(xbar_plan plan, const double* T, const double* V, int32_t B, double* I);
+
+/*
  * Synchronise the plan's stream and report its state.  Returns the sticky
  * device error (XBAR_ERR_INPUT, XBAR_ERR_NOT_SPD, XBAR_ERR_NO_CONVERGENCE)
  * if one was raised, XBAR_ERR_DEVICE on a HIP error, else XBAR_OK.

@@ -67,6 +67,28 @@ class Plan:
         _lib.xbar_currents(self._plan, out)
         return out
 
+    def transfer(self, out=None):
+        """T [m][n]: output currents per unit volt on each word line (xbar_transfer)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.m, self.n), dtype=torch.float64, device="cuda")
+        _check_tensor("T", out, (self.m, self.n))
+        _lib.xbar_transfer(self._plan, out)
+        self._B = 0
+        return out
+
+    def transfer_apply(self, T, V, out=None):
+        """I = V T for any batch V [B][m] (xbar_transfer_apply)."""
+        torch = _torch()
+        B = int(V.shape[0])
+        _check_tensor("T", T, (self.m, self.n))
+        _check_tensor("V", V, (B, self.m))
+        if out is None:
+            out = torch.empty((B, self.n), dtype=torch.float64, device="cuda")
+        _check_tensor("I", out, (B, self.n))
+        _lib.xbar_transfer_apply(self._plan, T, V, B, out)
+        return out
+
     def set_timing(self, enable: bool = True) -> None:
         _lib.xbar_set_timing(self._plan, enable)
 

@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.xbar_factor.argtypes = [vp]
         L.xbar_solve_batch.argtypes = [vp, vp, ctypes.c_int32, vp]
         L.xbar_currents.argtypes = [vp, vp]
+        L.xbar_transfer.argtypes = [vp, vp]
+        L.xbar_transfer_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
         L.xbar_get_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.xbar_destroy.argtypes = [vp]
         L.xbar_set_timing.argtypes = [vp, ctypes.c_int32]
@@ -87,7 +89,8 @@ def lib() -> ctypes.CDLL:
         L.xbar_status_string.restype = ctypes.c_char_p
         for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
-                  "xbar_get_timing", "xbar_set_factor_method"):
+                  "xbar_get_timing", "xbar_set_factor_method", "xbar_transfer",
+                  "xbar_transfer_apply"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -138,6 +141,14 @@ def xbar_solve_batch(plan, V, B: int, node_v=None) -> None:
 
 def xbar_currents(plan, I) -> None:
     _check("xbar_currents", lib().xbar_currents(plan, _ptr(I)))
+
+
+def xbar_transfer(plan, T) -> None:
+    _check("xbar_transfer", lib().xbar_transfer(plan, _ptr(T)))
+
+
+def xbar_transfer_apply(plan, T, V, B: int, I) -> None:
+    _check("xbar_transfer_apply", lib().xbar_transfer_apply(plan, _ptr(T), _ptr(V), int(B), _ptr(I)))
 
 
 def xbar_get_info(plan) -> tuple[int, Info]:

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.h"
+#include "transfer.h"
 #include "xbar.h"
 
 namespace {
@@ -42,6 +43,7 @@ struct Buffers {
     double* dnorm = nullptr;                 // [nslab][16]
     int* slab_done = nullptr;                // [nslab]
     int* slab_final = nullptr;               // [nslab]
+    double* Vunit = nullptr;                 // [tr_rows][m]: unit inputs of xbar_transfer
 };
 
 __global__ void clear_slabs_kernel(int* done, double* dnorm, int nslab)
@@ -111,6 +113,7 @@ struct xbar_plan_s {
     hipStream_t stream = nullptr;
     int device = 0;
     int n_p = 0, nb = 0, nslab_max = 0;
+    int tr_rows = 0;                    // unit inputs per xbar_transfer solve: min(max_batch, m)
     int64_t bytes = 0;
     int32_t state = kCreated;
     int32_t last_B = 0;
@@ -148,7 +151,7 @@ void free_all(xbar_plan p)
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
                    d.ns_Q[0], d.ns_Q[1], d.ns_Qt[0], d.ns_Qt[1], d.ns_P2[0], d.ns_P2[1],
                    d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
-                   d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final};
+                   d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final, d.Vunit};
     for (void* x : all)
         if (x) (void)hipFree(x);
     d = Buffers{};
@@ -220,6 +223,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     p->n_p = 64 * ((g.n + 63) / 64);
     p->nb = p->n_p / 64;
     p->nslab_max = (max_batch + 15) / 16;
+    p->tr_rows = max_batch < g.m ? max_batch : g.m;
 
     const int64_t m = g.m, n = g.n, n_p = p->n_p, es = (int64_t)p->elem();
     Buffers& d = p->d;
@@ -253,6 +257,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
     A((void**)&d.ns_state, 6 * sizeof(xbk::NSState));
+    A((void**)&d.Vunit, (int64_t)p->tr_rows * m * 8);
     if (prec != XBAR_FP64) {
         const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
         A((void**)&d.U[0], panel * 8);
@@ -457,6 +462,23 @@ __global__ void round_bf16_kernel(float* x, int64_t count)
 }
 __global__ void set_flag_kernel(int* f, int which) { f[which] = 1; }
 
+// rows unit input vectors: V[b][i] = 1 if i == i0 + b else 0, b < rows
+__global__ void unit_inputs_kernel(double* V, int rows, int m, int i0)
+{
+    const int64_t total = (int64_t)rows * m;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / m, i = e - b * m;
+        V[e] = (i == i0 + b) ? 1.0 : 0.0;
+    }
+}
+
+bool overlaps(const void* a, int64_t a_bytes, const void* b, int64_t b_bytes)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + (uintptr_t)b_bytes && y < x + (uintptr_t)a_bytes;
+}
+
 }  // namespace
 
 extern "C" {
@@ -614,6 +636,49 @@ xbar_status xbar_currents(xbar_plan p, double* I)
     const size_t bytes = (size_t)p->last_B * p->g.n * sizeof(double);
     if (hipMemcpyAsync(I, p->d.Iout, bytes, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
         return XBAR_ERR_DEVICE;
+    return XBAR_OK;
+}
+
+xbar_status xbar_transfer(xbar_plan p, double* T)
+{
+    if (p == nullptr || T == nullptr) return XBAR_ERR_ARG;
+    if (p->state < kFactored) return XBAR_ERR_STATE;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    const int m = p->g.m, n = p->g.n;
+    const bool timing = p->timing;
+    p->timing = false;                     // the unit solves are not counted as sweeps
+    xbar_status st = XBAR_OK;
+    for (int i0 = 0; i0 < m && st == XBAR_OK; i0 += p->tr_rows) {
+        const int rows = p->tr_rows < m - i0 ? p->tr_rows : m - i0;
+        const int64_t total = (int64_t)rows * m;
+        const int grid = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+        hipLaunchKernelGGL(unit_inputs_kernel, dim3(grid), dim3(256), 0, p->stream, p->d.Vunit, rows, m, i0);
+        if (hipGetLastError() != hipSuccess) {
+            st = XBAR_ERR_DEVICE;
+            break;
+        }
+        st = xbar_solve_batch(p, p->d.Vunit, rows, nullptr);
+        if (st == XBAR_OK &&
+            hipMemcpyAsync(T + (int64_t)i0 * n, p->d.Iout, (size_t)rows * n * sizeof(double),
+                           hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            st = XBAR_ERR_DEVICE;
+    }
+    p->timing = timing;
+    // the batch workspace now holds unit solves, not a caller's batch
+    p->state = kFactored;
+    p->last_B = 0;
+    return st;
+}
+
+xbar_status xbar_transfer_apply(xbar_plan p, const double* T, const double* V, int32_t B, double* I)
+{
+    if (p == nullptr || T == nullptr || V == nullptr || I == nullptr || B < 1) return XBAR_ERR_ARG;
+    const int64_t m = p->g.m, n = p->g.n;
+    const int64_t i_bytes = (int64_t)B * n * 8;
+    if (overlaps(I, i_bytes, V, (int64_t)B * m * 8) || overlaps(I, i_bytes, T, m * n * 8))
+        return XBAR_ERR_ARG;
+    if (!set_device(p)) return XBAR_ERR_DEVICE;
+    if (xbk_launch_transfer_apply(B, (int)m, (int)n, V, T, I, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
     return XBAR_OK;
 }
 

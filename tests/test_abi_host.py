@@ -10,7 +10,7 @@ from paper_2410_19993_amd import _lib
 
 EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor",
             "xbar_get_info", "xbar_get_timing", "xbar_set_factor_method", "xbar_set_timing",
-            "xbar_solve_batch", "xbar_status_string"]
+            "xbar_solve_batch", "xbar_status_string", "xbar_transfer", "xbar_transfer_apply"]
 
 
 def _gpu_visible():
@@ -82,6 +82,8 @@ def test_null_plan_calls():
     assert L.xbar_factor(None) == _lib.XBAR_ERR_ARG
     assert L.xbar_solve_batch(None, None, 1, None) == _lib.XBAR_ERR_ARG
     assert L.xbar_currents(None, None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_transfer(None, None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_transfer_apply(None, None, None, 1, None) == _lib.XBAR_ERR_ARG
     info = _lib.Info()
     assert L.xbar_get_info(None, ctypes.byref(info)) == _lib.XBAR_ERR_ARG
     assert L.xbar_destroy(None) == _lib.XBAR_OK

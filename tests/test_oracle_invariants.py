@@ -89,3 +89,14 @@ def test_reciprocity():
     N = net.num_nodes
     E = oracle.lu_solve(lu, w, np.eye(N))
     np.testing.assert_allclose(E, E.T, rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("m,n,r", CASES)
+def test_transfer_matrix_superposition(m, n, r):
+    """Linear network: each vector's currents are its voltages times the currents per unit
+    volt on each word line (I = V T), and every entry of T is positive (passive network with
+    every conductance > 0)."""
+    G, V, net, res = _case(m, n, r, B=6)
+    T = oracle.solve(G, np.eye(m), r, r, 50.0, 50.0).currents      # row i: 1 V on word line i
+    assert T.shape == (m, n) and np.all(T > 0)
+    np.testing.assert_allclose(V @ T, res.currents, rtol=1e-12)
