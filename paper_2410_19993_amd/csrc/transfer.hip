@@ -3,15 +3,17 @@
 // is linear in the word-line sources, so the output currents of any batch are
 // the input voltages times the m x n matrix of output currents per unit input.
 //
-// Tiling (gfx950, wave64): a workgroup of 4 waves owns a 128 x 64 block of I
-// and walks the contraction index k in chunks of 16.  Each chunk of V
-// (128 x 16) and of T (16 x 64) is staged in LDS in matrix-core operand order:
+// Tiling (gfx950, wave64): a workgroup of 8 waves owns a 128 x 64 block of I
+// and walks the contraction index k in chunks of 32.  Each chunk of V
+// (128 x 32) and of T (32 x 64) is staged in LDS in matrix-core operand order:
 // 16 x 16 tiles, lane l = 16q + r holding the four values k = 4q + t,
 // t = 0..3, so every lane fetches its operands for four v_mfma_f64_16x16x4f64
-// steps with two 16-byte LDS loads.  Wave w computes rows 32w..32w+31 against
-// all 64 columns (2 x 4 output tiles, 32 float64 accumulators per lane).  The
-// next chunk is loaded from global memory into registers while the matrix
-// cores run and written to the other LDS buffer: one barrier per chunk.
+// steps with two 16-byte LDS loads.  Thread g fills operand slot g, so a wave
+// writes LDS contiguously (a row-major thread mapping is 8-way bank-conflicted
+// here and costs about 30% of the kernel's time).  The waves form a 4 x 2
+// grid, each computing a 32 x 32 block (2 x 2 output tiles).  Chunks are loaded
+// from global memory into registers two ahead of the one the matrix cores are
+// working on and written to the other of two LDS buffers: one barrier per chunk.
 //
 // XCD-aware launch: workgroups are dealt to the 8 XCDs round-robin.  When the
 // row panels divide by 8, each XCD gets a contiguous range of row panels with
@@ -19,17 +21,13 @@
 // which every workgroup reads, stays in each XCD's L2.
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "transfer.h"
 
 namespace {
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
-
-constexpr int kBM = 128;     // rows of I per workgroup
-constexpr int kBN = 64;      // columns of I per workgroup
-constexpr int kBK = 16;      // contraction chunk
-constexpr int kThreads = 256;
 
 // p[0..valid-1] into x, zeros beyond; one pair of 16-byte loads when allowed
 template <bool VEC>
@@ -50,16 +48,35 @@ __device__ inline void load4(const double* p, int valid, double (&x)[4])
 
 __device__ inline int clamp4(int v) { return v < 0 ? 0 : (v > 4 ? 4 : v); }
 
-// VEC: m and n even and V, T 16-byte aligned, so every 4-wide piece starts 16-byte aligned
-template <bool VEC>
-__global__ __launch_bounds__(kThreads) void transfer_apply_kernel(
+// Block shape: BM x BN outputs, contraction chunks of BK, WM x WN waves each owning
+// (BM / WM) x (BN / WN) outputs.
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int DEPTH_ = 1>
+struct Tiling {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int DEPTH = DEPTH_;                          // chunks loaded ahead (1 or 2)
+    static constexpr int kThreads = 64 * WM * WN;
+    static constexpr int TI = BM / WM / 16, TJ = BN / WN / 16;   // output tiles per wave
+    static constexpr int KS = BK / 16;                            // 16-deep sub-chunks per chunk
+    static constexpr int GA = BM * BK / 4 / kThreads;             // 4-wide V pieces per thread
+    static constexpr int GB = BN * BK / 4 / kThreads;             // 4-wide T pieces per thread
+    static constexpr int LA = BM * BK, LB = BN * BK;              // doubles per LDS stage
+    static_assert(TI >= 1 && TJ >= 1 && BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tiles");
+    static_assert(BK % 16 == 0 && GA >= 1 && GB >= 1 && (DEPTH == 1 || DEPTH == 2), "chunk");
+    static_assert(GA * kThreads * 4 == BM * BK && GB * kThreads * 4 == BN * BK, "pieces");
+};
+
+// VEC: m even and V 16-byte aligned, so every 4-wide piece of a V row starts 16-byte aligned.
+// LDS stage layout (both operands): [16-row tile][16-deep sub-chunk][lane][t].
+template <class C, bool VEC>
+__global__ __launch_bounds__(C::kThreads) void transfer_apply_kernel(
     const double* __restrict__ V, const double* __restrict__ T, double* __restrict__ I,
     int B, int m, int n, int col_tiles, int xcd_rows)
 {
-    __shared__ __align__(16) double la[2][8 * 256];   // V chunk: [row tile][lane][t]
-    __shared__ __align__(16) double lb[2][4 * 256];   // T chunk: [column tile][lane][t]
+    __shared__ __align__(16) double la[2][C::LA];
+    __shared__ __align__(16) double lb[2][C::LB];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wi = w / C::WN, wj = w % C::WN;
     const int bid = blockIdx.x;
     int rp, ct;
     if (xcd_rows > 0) {
@@ -70,110 +87,165 @@ __global__ __launch_bounds__(kThreads) void transfer_apply_kernel(
         rp = bid / col_tiles;
         ct = bid % col_tiles;
     }
-    const int64_t r0 = (int64_t)rp * kBM;
-    const int c0 = ct * kBN;
+    const int64_t r0 = (int64_t)rp * C::BM;
+    const int c0 = ct * C::BN;
 
-    // this thread's share of a chunk: two 4-wide pieces of V rows, one 4-wide piece of a T row
-    int a_row[2], a_q[2];
-    bool a_ok[2];
-    const double* a_src[2];
+    // Thread g fills LDS slot g of each operand (4 doubles at 32 g bytes, so the stores are
+    // contiguous across a wave).  Slot g is lane l = g % 64 (l = 16q + r) of 16 x 16 operand
+    // tile g / 64 = (tile, sub-chunk ks): V row 16 tile + r, k = 16 ks + 4q + t; T column
+    // 16 tile + r, the same k.  A V slot is four consecutive doubles of one row; a T slot is
+    // four doubles of one column.
+    int a_k[C::GA];
+    bool a_ok[C::GA];
+    const double* a_src[C::GA];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int g = tid + kThreads * e;
-        a_row[e] = g >> 2;
-        a_q[e] = g & 3;
-        a_ok[e] = r0 + a_row[e] < B;
-        a_src[e] = V + (a_ok[e] ? (r0 + a_row[e]) * (int64_t)m : 0) + 4 * a_q[e];
+    for (int e = 0; e < C::GA; ++e) {
+        const int g = tid + C::kThreads * e, rest = g >> 6;
+        const int row = 16 * (rest / C::KS) + (g & 15);
+        a_k[e] = 16 * (rest % C::KS) + 4 * ((g >> 4) & 3);
+        a_ok[e] = r0 + row < B;
+        a_src[e] = V + (a_ok[e] ? (r0 + row) * (int64_t)m : 0) + a_k[e];
     }
-    const int b_kk = tid >> 4, b_c = (tid & 15) * 4;
-    const int b_cols = clamp4(n - (c0 + b_c));
-    const double* b_src = T + c0 + b_c;
+    int b_k[C::GB];
+    bool b_ok[C::GB];
+    const double* b_src[C::GB];
+#pragma unroll
+    for (int e = 0; e < C::GB; ++e) {
+        const int g = tid + C::kThreads * e, rest = g >> 6;
+        const int col = c0 + 16 * (rest / C::KS) + (g & 15);
+        b_k[e] = 16 * (rest % C::KS) + 4 * ((g >> 4) & 3);
+        b_ok[e] = col < n;
+        b_src[e] = T + (b_ok[e] ? col : 0);
+    }
 
-    double ra[2][4], rb[4];
-    auto fetch = [&](int k0) {
+    double ra[C::DEPTH][C::GA][4], rb[C::DEPTH][C::GB][4];
+    auto fetch = [&](int k0, auto set) {
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
-            load4<VEC>(a_src[e] + k0, a_ok[e] ? clamp4(m - (k0 + 4 * a_q[e])) : 0, ra[e]);
-        const int k = k0 + b_kk;
-        load4<VEC>(b_src + (k < m ? (int64_t)k * n : 0), k < m ? b_cols : 0, rb);
-    };
-    auto stash = [&](int buf) {
+        for (int e = 0; e < C::GA; ++e)
+            load4<VEC>(a_src[e] + k0, a_ok[e] ? clamp4(m - (k0 + a_k[e])) : 0, ra[set][e]);
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int rt = a_row[e] >> 4, rr = a_row[e] & 15;
-            double* d = &la[buf][rt * 256 + (16 * a_q[e] + rr) * 4];
-            *reinterpret_cast<double2*>(d) = double2{ra[e][0], ra[e][1]};
-            *reinterpret_cast<double2*>(d + 2) = double2{ra[e][2], ra[e][3]};
-        }
-        const int q = b_kk >> 2, t = b_kk & 3;
+        for (int e = 0; e < C::GB; ++e) {
+            const int k = k0 + b_k[e];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = b_c + e;
-            lb[buf][(c >> 4) * 256 + (16 * q + (c & 15)) * 4 + t] = rb[e];
+            for (int t = 0; t < 4; ++t)
+                rb[set][e][t] = (b_ok[e] && k + t < m) ? b_src[e][(int64_t)(k + t) * n] : 0.0;
         }
     };
+    auto put = [](double* d, const double (&x)[4]) {
+        *reinterpret_cast<double2*>(d) = double2{x[0], x[1]};
+        *reinterpret_cast<double2*>(d + 2) = double2{x[2], x[3]};
+    };
+    auto stash = [&](int buf, auto set) {
+#pragma unroll
+        for (int e = 0; e < C::GA; ++e) put(&la[buf][(tid + C::kThreads * e) * 4], ra[set][e]);
+#pragma unroll
+        for (int e = 0; e < C::GB; ++e) put(&lb[buf][(tid + C::kThreads * e) * 4], rb[set][e]);
+    };
 
-    dv4 acc[2][4];
+    dv4 acc[C::TI][C::TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < C::TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < C::TJ; ++j) acc[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
 
-    const int nk = (m + kBK - 1) / kBK;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-        const int buf = kc & 1;
-        if (kc + 1 < nk) fetch((kc + 1) * kBK);
-        double fa[2][4], fb[4][4];
+    auto compute = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const double* s = &la[buf][(2 * w + i) * 256 + lane * 4];
-            const double2 x = *reinterpret_cast<const double2*>(s);
-            const double2 y = *reinterpret_cast<const double2*>(s + 2);
-            fa[i][0] = x.x;
-            fa[i][1] = x.y;
-            fa[i][2] = y.x;
-            fa[i][3] = y.y;
+        for (int ks = 0; ks < C::KS; ++ks) {
+            double fa[C::TI][4], fb[C::TJ][4];
+#pragma unroll
+            for (int i = 0; i < C::TI; ++i) {
+                const double* s = &la[buf][((wi * C::TI + i) * C::KS + ks) * 256 + lane * 4];
+                const double2 x = *reinterpret_cast<const double2*>(s);
+                const double2 y = *reinterpret_cast<const double2*>(s + 2);
+                fa[i][0] = x.x;
+                fa[i][1] = x.y;
+                fa[i][2] = y.x;
+                fa[i][3] = y.y;
+            }
+#pragma unroll
+            for (int j = 0; j < C::TJ; ++j) {
+                const double* s = &lb[buf][((wj * C::TJ + j) * C::KS + ks) * 256 + lane * 4];
+                const double2 x = *reinterpret_cast<const double2*>(s);
+                const double2 y = *reinterpret_cast<const double2*>(s + 2);
+                fb[j][0] = x.x;
+                fb[j][1] = x.y;
+                fb[j][2] = y.x;
+                fb[j][3] = y.y;
+            }
+            // step t contracts k = 4q + t over the lane groups q
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < C::TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][t], fb[j][t], acc[i][j], 0, 0, 0);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double* s = &lb[buf][j * 256 + lane * 4];
-            const double2 x = *reinterpret_cast<const double2*>(s);
-            const double2 y = *reinterpret_cast<const double2*>(s + 2);
-            fb[j][0] = x.x;
-            fb[j][1] = x.y;
-            fb[j][2] = y.x;
-            fb[j][3] = y.y;
-        }
-        // step t contracts k = 4q + t over the lane groups q
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i][t], fb[j][t], acc[i][j], 0, 0, 0);
-        if (kc + 1 < nk) stash(buf ^ 1);
+    };
+
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, C::DEPTH - 1>;
+    const int nk = (m + C::BK - 1) / C::BK;
+    fetch(0, S0{});
+    stash(0, S0{});
+    if constexpr (C::DEPTH == 1) {
         __syncthreads();
+        for (int kc = 0; kc < nk; ++kc) {
+            if (kc + 1 < nk) fetch((kc + 1) * C::BK, S0{});
+            compute(kc & 1);
+            if (kc + 1 < nk) stash((kc & 1) ^ 1, S0{});
+            __syncthreads();
+        }
+    } else {
+        // register set s holds the chunk kc + 1 while the chunk kc + 2 loads into the other
+        if (nk > 1) fetch(C::BK, S1{});
+        __syncthreads();
+        auto step = [&](int kc, auto cur, auto nxt) {
+            if (kc + 2 < nk) fetch((kc + 2) * C::BK, cur);
+            compute(kc & 1);
+            if (kc + 1 < nk) stash((kc & 1) ^ 1, nxt);
+            __syncthreads();
+        };
+        for (int kc = 0; kc < nk; kc += 2) {
+            step(kc, S0{}, S1{});
+            if (kc + 1 < nk) step(kc + 1, S1{}, S0{});
+        }
     }
 
     // item v of lane l = 16q + c is row q + 4v, column c of its 16 x 16 output tile
     const int q = lane >> 4, c = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < C::TI; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t row = r0 + (2 * w + i) * 16 + q + 4 * v;
+            const int64_t row = r0 + (wi * C::TI + i) * 16 + q + 4 * v;
             if (row >= B) continue;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = c0 + j * 16 + c;
+            for (int j = 0; j < C::TJ; ++j) {
+                const int col = c0 + (wj * C::TJ + j) * 16 + c;
                 if (col < n) I[row * n + col] = acc[i][j][v];
             }
         }
 }
+
+template <class C>
+hipError_t launch_tiling(int B, int m, int n, const double* V, const double* T, double* I, hipStream_t s)
+{
+    const int64_t rp = ((int64_t)B + C::BM - 1) / C::BM, ct = ((int64_t)n + C::BN - 1) / C::BN;
+    if (rp * ct > INT_MAX) return hipErrorInvalidValue;
+    const int xcd_rows = rp % 8 == 0 ? (int)(rp / 8) : 0;
+    const bool vec = m % 2 == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0;
+    const dim3 grid((unsigned)(rp * ct)), block(C::kThreads);
+    if (vec)
+        hipLaunchKernelGGL((transfer_apply_kernel<C, true>), grid, block, 0, s, V, T, I, B, m, n, (int)ct,
+                           xcd_rows);
+    else
+        hipLaunchKernelGGL((transfer_apply_kernel<C, false>), grid, block, 0, s, V, T, I, B, m, n, (int)ct,
+                           xcd_rows);
+    return hipGetLastError();
+}
+
+using ApplyTiling = Tiling<128, 64, 32, 4, 2, 2>;
 
 }  // namespace
 
@@ -181,17 +253,5 @@ hipError_t xbk_launch_transfer_apply(int B, int m, int n, const double* V, const
                                      hipStream_t s)
 {
     if (B < 1 || m < 1 || n < 1 || !V || !T || !I) return hipErrorInvalidValue;
-    const int64_t rp = ((int64_t)B + kBM - 1) / kBM, ct = ((int64_t)n + kBN - 1) / kBN;
-    if (rp * ct > INT_MAX) return hipErrorInvalidValue;
-    const int xcd_rows = rp % 8 == 0 ? (int)(rp / 8) : 0;
-    const bool vec = m % 2 == 0 && n % 2 == 0 && reinterpret_cast<uintptr_t>(V) % 16 == 0 &&
-                     reinterpret_cast<uintptr_t>(T) % 16 == 0;
-    const dim3 grid((unsigned)(rp * ct)), block(kThreads);
-    if (vec)
-        hipLaunchKernelGGL(transfer_apply_kernel<true>, grid, block, 0, s, V, T, I, B, m, n, (int)ct,
-                           xcd_rows);
-    else
-        hipLaunchKernelGGL(transfer_apply_kernel<false>, grid, block, 0, s, V, T, I, B, m, n, (int)ct,
-                           xcd_rows);
-    return hipGetLastError();
+    return launch_tiling<ApplyTiling>(B, m, n, V, T, I, s);
 }
