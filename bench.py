@@ -36,8 +36,11 @@ IR_TOL = 1e-10               # refinement stop of the float32 leg (its target is
 # HBM traffic of the dominant kernel per launch, from two counter runs (FETCH_SIZE,
 # WRITE_SIZE) scaled by what the same counters read for a plain copy; valid only
 # while the kernel's sources are unchanged since the counters were taken.
+CSRC = os.path.join(ROOT, "paper_2410_19993_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_c3_512x512_b4096_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_19993_amd", "csrc", f) for f in ("sweep.hip", "common.h")]
+KERNEL_SOURCES = [os.path.join(CSRC, f) for f in ("sweep.hip", "common.h")]
+APPLY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "transfer_apply_kernel_c3_512x512_b4096.md")
+APPLY_SOURCES = [os.path.join(CSRC, "transfer.hip")]
 METRIC = ("input-vector solves/s, 512×512 xbar: FP64 LU vs FP32+IR at 1e-9 rel err")
 
 
@@ -77,23 +80,23 @@ def cpu_baseline(wl, rows=64, vectors=128):
             "seconds_measured": t_all + t_fact, "extrapolated_seconds": t_full}
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """Bytes per launch of the sweep kernel from the committed counter summary, or None."""
+def measured_traffic(workload, record=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """Bytes per launch of a kernel from its committed counter summary, or None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(record) as fh:
             rec = json.loads(fh.read().split("JSON:", 1)[1])
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("source_sha256") != kernel_source_hash() or rec.get("workload") != workload:
+    if rec.get("source_sha256") != kernel_source_hash(sources) or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
 
@@ -219,6 +222,7 @@ def main():
                                    "achieved": flops / (apply_ms * 1e-3) / 1e12,
                                    "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                                    "frac": flops / (apply_ms * 1e-3) / PEAK_FP64_MFMA,
+                                   "traffic": measured_traffic(wl.name, APPLY_TRAFFIC_FILE, APPLY_SOURCES),
                                    "flops_per_launch": flops},
                 "max_rel_err_vs_oracle": err}
 

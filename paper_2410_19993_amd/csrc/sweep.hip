@@ -368,17 +368,25 @@ constexpr int kHelpers = 4;      // helper waves of the float64 sweep (one per S
 //   pair  F                  twist: row kt
 //   pair  F+1                panel <- u_kt; then rows kt-1 .. 0 (one pair after each)
 //   pair  F+2+kt             (kt+1 < m) panel <- z_kt, restart; then rows kt+1 .. m-1
-// with F = kt + max(0, m-1-kt).
+// with F = kt + max(0, m-1-kt).  Without the upward back sweep (up = false: only
+// the output currents, which depend on u_{m-1} alone, are wanted) rows kt+1 .. m-1
+// follow pair F+1 directly: the panel already holds u_kt.
 struct SweepPlan {
     int m, kt, F;
-    __device__ __forceinline__ explicit SweepPlan(int m_) : m(m_), kt(m_ / 2), F(m_ / 2 + max(0, m_ - 1 - m_ / 2)) {}
-    __device__ __forceinline__ int pairs() const { return F + 2 + kt + (kt + 1 < m ? 1 + (m - 1 - kt) : 0); }
+    bool up;
+    __device__ __forceinline__ SweepPlan(int m_, bool up_)
+        : m(m_), kt(m_ / 2), F(m_ / 2 + max(0, m_ - 1 - m_ / 2)), up(up_) {}
+    __device__ __forceinline__ int pairs() const {
+        const int down = m - 1 - kt;               // rows kt+1 .. m-1
+        return up ? F + 2 + kt + (down > 0 ? 1 + down : 0) : F + 2 + down;
+    }
     // row whose product follows pair p (-1: none)
     __device__ __forceinline__ int product_after(int p) const {
         if (p < kt) return p;
         if (p < F) return m - 1 - (p - kt);
         if (p == F) return kt;
         int q = p - (F + 1);                       // 0: panel <- u_kt, then u_{kt-1}, ...
+        if (!up) return kt + 1 + q < m ? kt + 1 + q : -1;
         if (q <= kt) {
             const int i = kt - q;                  // panel holds u_i
             return i > 0 ? i - 1 : -1;
@@ -389,7 +397,7 @@ struct SweepPlan {
     }
     // row whose bit-line voltages are in the panel after pair p, to recover (-1: none)
     __device__ __forceinline__ int recover_after(int p) const {
-        if (p <= F) return -1;
+        if (p <= F || !up) return -1;
         int q = p - (F + 1);
         if (q <= kt) return kt - q;
         q -= kt + 1;
@@ -573,8 +581,8 @@ struct SweepHelper {
         }
     }
     // the whole schedule, one barrier pair at a time
-    __device__ void run(bool rec) {
-        const SweepPlan sp(a.m);
+    __device__ void run(bool rec, bool up) {
+        const SweepPlan sp(a.m, up);
         const int np = sp.pairs();
         const T* H = reinterpret_cast<const T*>(a.H);
         for (int p = 0; p < np; ++p) {
@@ -630,7 +638,7 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
         // the helpers' latency-bound work gets issue priority over the matrix-core
         // waves, which have independent work queued behind every instruction
         __builtin_amdgcn_s_setprio(3);
-        hp.run(REC && !IR);
+        hp.run(REC && !IR, IR || REC);
         return;
     }
     Ctx x{a, reinterpret_cast<T*>(smem_raw),
@@ -669,40 +677,44 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
             if (i - 1 > kt) x.set_panel(f, acc, true, -1, -1);
         }
     }
-    // twist row
+    // twist row.  Only the output currents wanted (float64, no node voltages): they
+    // depend on u_{m-1} alone, so the upward back sweep is skipped.
+    constexpr bool UP = IR || REC;
     double up[TW][4];
     x.load_rhs(kt, f);
     x.set_panel(f, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
     x.load_u(kt, up);
-    panel_product<T, NT, TW>(acc, ring, Hb(kt), Hb(kt > 0 ? kt - 1 : (kt + 1 < m ? kt + 1 : kt)), x.ybuf, Ctx::ldy,
-                             x.w, l, none);
-    x.store_z(kt, acc);             // the downward back sweep restarts from this row
+    const int after_twist = (UP && kt > 0) ? kt - 1 : (kt + 1 < m ? kt + 1 : kt);
+    panel_product<T, NT, TW>(acc, ring, Hb(kt), Hb(after_twist), x.ybuf, Ctx::ldy, x.w, l, none);
+    if (UP) x.store_z(kt, acc);     // the downward back sweep restarts from this row
     x.settle(kt, acc, up);
     x.put_panel(acc);
     // back, upward
-    for (int i = kt - 1; i >= 0; --i) {
-        T zp[TW][4];
-        if (IR) x.load_z(i, zp);    // refinement sweeps: no helpers, request z before the product
-        x.load_u(i, up);
-        acc_t u[TW];
-        panel_product<T, NT, TW>(u, ring, Hb(i), Hb(i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i)), x.ybuf, Ctx::ldy,
-                                 x.w, l, none);
-        if (!IR) x.load_z(i, zp);   // float64 sweep: the helpers have pulled z_i into L2
-        x.back_step(zp, u);
-        x.settle(i, u, up);
-        x.put_panel(u);
+    if (UP) {
+        for (int i = kt - 1; i >= 0; --i) {
+            T zp[TW][4];
+            if (IR) x.load_z(i, zp);    // refinement sweeps: no helpers, request z before the product
+            x.load_u(i, up);
+            acc_t u[TW];
+            panel_product<T, NT, TW>(u, ring, Hb(i), Hb(i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i)), x.ybuf,
+                                     Ctx::ldy, x.w, l, none);
+            if (!IR) x.load_z(i, zp);   // float64 sweep: the helpers have pulled z_i into L2
+            x.back_step(zp, u);
+            x.settle(i, u, up);
+            x.put_panel(u);
+        }
     }
     // back, downward
     if (kt + 1 < m) {
-        {
+        if (UP) {
             T zp[TW][4];
             x.load_z(kt, zp);
 #pragma unroll
             for (int t = 0; t < TW; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[t][v] = zp[t][v];
+            x.put_panel(acc);
         }
-        x.put_panel(acc);
         for (int i = kt + 1; i < m; ++i) {
             T zp[TW][4];
             if (IR) x.load_z(i, zp);

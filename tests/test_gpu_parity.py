@@ -172,3 +172,21 @@ def test_long_chains(m, n, B, seed):
     wl = workloads.random_crossbar(m, n, B, seed)
     _check_against_oracle(wl)
     _check_against_oracle(wl, precision="fp32_ir", tol=TOL_IR)
+
+
+@pytest.mark.parametrize("m,n,B,seed", [
+    (1, 5, 3, 51), (2, 9, 4, 52), (3, 16, 17, 53), (5, 64, 16, 54), (64, 70, 33, 55),
+    (65, 128, 20, 56), (200, 512, 40, 57), (513, 40, 9, 58)])
+def test_currents_only_same_bits(m, n, B, seed):
+    """Without node voltages the float64 sweep skips the upward back sweep (the currents
+    depend only on the bottom row).  The currents must be the same bits as with node
+    voltages, and within the float64 tolerance of the oracle."""
+    wl = workloads.random_crossbar(m, n, B, seed)
+    log(f"case currents only m={m} n={n} B={B}")
+    I_full, _, (st0, _) = gpu_solve(wl.G, wl.V, wl.geom, "fp64")
+    I_only, nv, (st1, _) = gpu_solve(wl.G, wl.V, wl.geom, "fp64", node_voltages=False)
+    assert st0 == 0 and st1 == 0 and nv is None
+    assert np.array_equal(I_full, I_only)
+    e = rel_err(I_only, oracle.solve_workload(wl).currents)
+    log(f"  max current rel err {e.max():.3e}")
+    assert e.max() <= TOL_FP64
