@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "common.h"
 #include "transfer.h"
 
 namespace {
@@ -247,7 +248,140 @@ hipError_t launch_tiling(int B, int m, int n, const double* V, const double* T, 
 
 using ApplyTiling = Tiling<128, 64, 32, 4, 2, 2>;
 
+// ---------------------------------------------------------------------------
+// Products of FRG blocks for building T from the factorization.  A workgroup of 4
+// waves owns a 32 x 32 output block (2 x 2 tiles); wave w covers a quarter of the
+// contraction for all four tiles (so each operand tile is read once per workgroup),
+// and the partial tiles are summed through LDS.  With the A slot of the matrix core
+// fed from the tile of B and the B slot from the tile of A, item v of lane l is
+// element (l % 16, kidx(l / 16, v)) of the tile of A B^T: partials and output are in
+// FRG order with no shuffle.
+struct FrgProductArgs {
+    XbkFrgJob job[2];
+    int n_p;
+    double alpha;
+};
+
+__global__ __launch_bounds__(256) void frg_product_kernel(FrgProductArgs a)
+{
+    using F = xbk::Frag<double>;
+    __shared__ __align__(16) double part[4][4][256];      // [wave][output tile][slot]
+    const int TP = a.n_p / 32, T2 = TP * TP, KT = a.n_p / 16, KQ = KT / 4;
+    const int jb = blockIdx.x / T2, t2 = blockIdx.x % T2;
+    const XbkFrgJob J = a.job[jb];
+    int tr2, tc2;
+    if (TP % 4 == 0) {
+        // XCD b % 8 owns a quarter of the block rows and half of the block columns
+        const int xcd = t2 & 7, local = t2 >> 3;
+        tr2 = (xcd >> 1) * (TP / 4) + local / (TP / 2);
+        tc2 = (xcd & 1) * (TP / 2) + local % (TP / 2);
+    } else {
+        tr2 = t2 / TP;
+        tc2 = t2 % TP;
+    }
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // tiles (2 tr2 + i, k) of A and (2 tc2 + j, k) of B for k in this wave's quarter
+    const double* pa = J.A + ((int64_t)(2 * tr2) * KT + w * KQ) * 256;
+    const double* pb = J.B + ((int64_t)(2 * tc2) * KT + w * KQ) * 256;
+    const int64_t row_step = (int64_t)KT * 256;
+    auto frag = [&](const double* t, double (&x)[4]) {
+        const double2 lo = *reinterpret_cast<const double2*>(t + 2 * l);
+        const double2 hi = *reinterpret_cast<const double2*>(t + 128 + 2 * l);
+        x[0] = lo.x;
+        x[1] = lo.y;
+        x[2] = hi.x;
+        x[3] = hi.y;
+    };
+    F::acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = F::acc_t{0.0, 0.0, 0.0, 0.0};
+    double fa[2][2][4], fb[2][2][4];                        // [buffer][tile][t]
+    auto load = [&](int k, int buf) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            frag(pa + i * row_step + k * 256, fa[buf][i]);
+            frag(pb + i * row_step + k * 256, fb[buf][i]);
+        }
+    };
+    auto step = [&](int buf) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = F::mma(fb[buf][j][t], fa[buf][i][t], acc[i][j]);
+    };
+    load(0, 0);
+    for (int k = 0; k < KQ; k += 2) {
+        if (k + 1 < KQ) load(k + 1, 1);
+        step(0);
+        if (k + 1 < KQ) {
+            if (k + 2 < KQ) load(k + 2, 0);
+            step(1);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[w][2 * i + j][xbk::frg_slot<double>(l, v)] = acc[i][j][v];
+    __syncthreads();
+    // wave w sums output tile (i, j) = (w >> 1, w & 1) over the four quarters
+    const int tr = 2 * tr2 + (w >> 1), tc = 2 * tc2 + (w & 1);
+    const int64_t o = ((int64_t)tr * KT + tc) * 256;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int e = xbk::frg_slot<double>(l, v);
+        const double sum = ((part[0][w][e] + part[1][w][e]) + part[2][w][e]) + part[3][w][e];
+        const double c = J.C ? J.C[o + e] : 0.0;
+        J.out[o + e] = a.alpha * sum + c;
+    }
+}
+
+// T[i][j] = g_sense sum_{k < n} W_i[j][k] c_i[k]: workgroup (i, 64-row group), lane j,
+// the k sum in order over the FRG positions of row j
+__global__ __launch_bounds__(64) void transfer_rows_kernel(int m, int n, int n_p, const double* __restrict__ W,
+                                                           const double* __restrict__ c, double g_sense,
+                                                           double* __restrict__ T)
+{
+    const int i = blockIdx.x / (n_p / 64), j = (blockIdx.x % (n_p / 64)) * 64 + threadIdx.x;
+    if (i >= m || j >= n) return;
+    const double* Wi = W + (int64_t)i * n_p * n_p;
+    const double* ci = c + (int64_t)i * n_p;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += Wi[xbk::frg<double>(j, k, n_p)] * ci[k];
+    T[(int64_t)i * n + j] = g_sense * s;
+}
+
 }  // namespace
+
+hipError_t xbk_launch_frg_products(const XbkFrgJob* jobs, int njobs, int n_p, double alpha, hipStream_t s)
+{
+    if (njobs < 1 || njobs > 2 || n_p < 64 || n_p % 64 != 0) return hipErrorInvalidValue;
+    FrgProductArgs a{};
+    for (int k = 0; k < njobs; ++k) {
+        if (!jobs[k].A || !jobs[k].B || !jobs[k].out) return hipErrorInvalidValue;
+        a.job[k] = jobs[k];
+    }
+    a.n_p = n_p;
+    a.alpha = alpha;
+    const int TP = n_p / 32;
+    hipLaunchKernelGGL(frg_product_kernel, dim3(njobs * TP * TP), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t xbk_launch_transfer_rows(int m, int n, int n_p, const double* W, const double* c, double g_sense,
+                                    double* T, hipStream_t s)
+{
+    if (m < 1 || n < 1 || n > n_p || n_p % 64 != 0 || !W || !c || !T) return hipErrorInvalidValue;
+    const int64_t grid = (int64_t)m * (n_p / 64);
+    if (grid > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(transfer_rows_kernel, dim3((unsigned)grid), dim3(64), 0, s, m, n, n_p, W, c, g_sense, T);
+    return hipGetLastError();
+}
 
 hipError_t xbk_launch_transfer_apply(int B, int m, int n, const double* V, const double* T, double* I,
                                      hipStream_t s)

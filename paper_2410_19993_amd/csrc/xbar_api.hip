@@ -479,6 +479,86 @@ bool overlaps(const void* a, int64_t a_bytes, const void* b, int64_t b_bytes)
     return x < y + (uintptr_t)b_bytes && y < x + (uintptr_t)a_bytes;
 }
 
+// The block form of xbar_transfer keeps m FRG blocks of n_p x n_p in the sweep workspace
+// (float64 plans whose max_batch, rounded up to 16, is at least n_p).
+bool transfer_blocks_fit(xbar_plan p)
+{
+    return p->prec == XBAR_FP64 && (int64_t)p->nslab_max * 16 >= p->n_p;
+}
+
+// T from the m unit input vectors, solved with the plan's factorization (any plan).
+xbar_status transfer_by_unit_solves(xbar_plan p, double* T)
+{
+    const int m = p->g.m, n = p->g.n;
+    const bool timing = p->timing;
+    p->timing = false;                     // the unit solves are not counted as sweeps
+    xbar_status st = XBAR_OK;
+    for (int i0 = 0; i0 < m && st == XBAR_OK; i0 += p->tr_rows) {
+        const int rows = p->tr_rows < m - i0 ? p->tr_rows : m - i0;
+        const int64_t total = (int64_t)rows * m;
+        const int grid = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+        hipLaunchKernelGGL(unit_inputs_kernel, dim3(grid), dim3(256), 0, p->stream, p->d.Vunit, rows, m, i0);
+        if (hipGetLastError() != hipSuccess) {
+            st = XBAR_ERR_DEVICE;
+            break;
+        }
+        st = xbar_solve_batch(p, p->d.Vunit, rows, nullptr);
+        if (st == XBAR_OK &&
+            hipMemcpyAsync(T + (int64_t)i0 * n, p->d.Iout, (size_t)rows * n * sizeof(double),
+                           hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            st = XBAR_ERR_DEVICE;
+    }
+    p->timing = timing;
+    return st;
+}
+
+// T from the factorization by block recurrences.  The condensed system A is
+// symmetric, so row i of T is g_sense W_i c_i with W_i the transpose of block row i
+// of Y = A^-1 E (E: identity blocks at the last row; c_i: the condensed source
+// coupling of row i, whose input vector is V_i c_i).  Y follows from the twisted
+// factorization exactly as a sweep would with right-hand side E, on whole n_p x n_p
+// blocks: the top chain's forward results are zero, so
+//   bottom chain:  W_{m-1} = H_{m-1},  W_i = g W_{i+1} H_i       (i = m-2 .. kt+1)
+//   twist:         W_kt = g W_{kt+1} H_kt                       (H_kt if kt = m-1)
+//   back, up:      W_i = g W_{i+1} H_i                           (i = kt-1 .. 0)
+//   back, down:    W_i = W_i + g W_{i-1} H_i                     (i = kt+1 .. m-1)
+// (H_i symmetric, g = g_bl).  The two back chains share launches.
+xbar_status transfer_by_blocks(xbar_plan p, double* T)
+{
+    const int m = p->g.m, n = p->g.n, n_p = p->n_p, kt = m / 2;
+    const int64_t blk = (int64_t)n_p * n_p;
+    double* W = reinterpret_cast<double*>(p->d.Z);
+    const double* H = reinterpret_cast<const double*>(p->d.H);
+    const double g = 1.0 / p->g.r_bl;
+    auto Wb = [&](int i) { return W + i * blk; };
+    auto Hb = [&](int i) { return H + i * blk; };
+    auto one = [&](const double* A, const double* B, const double* C, double* out) {
+        const XbkFrgJob j{A, B, C, out};
+        return xbk_launch_frg_products(&j, 1, n_p, g, p->stream) == hipSuccess;
+    };
+    const size_t bytes = (size_t)blk * sizeof(double);
+    if (kt + 1 < m) {
+        if (hipMemcpyAsync(Wb(m - 1), Hb(m - 1), bytes, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            return XBAR_ERR_DEVICE;
+        for (int i = m - 2; i >= kt; --i)
+            if (!one(Wb(i + 1), Hb(i), nullptr, Wb(i))) return XBAR_ERR_DEVICE;
+    } else if (hipMemcpyAsync(Wb(kt), Hb(kt), bytes, hipMemcpyDeviceToDevice, p->stream) != hipSuccess) {
+        return XBAR_ERR_DEVICE;
+    }
+    for (int s = 0;; ++s) {
+        const int up = kt - 1 - s, down = kt + 1 + s;
+        XbkFrgJob jobs[2];
+        int nj = 0;
+        if (up >= 0) jobs[nj++] = XbkFrgJob{Wb(up + 1), Hb(up), nullptr, Wb(up)};
+        if (down < m) jobs[nj++] = XbkFrgJob{Wb(down - 1), Hb(down), Wb(down), Wb(down)};
+        if (nj == 0) break;
+        if (xbk_launch_frg_products(jobs, nj, n_p, g, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    }
+    if (xbk_launch_transfer_rows(m, n, n_p, W, p->d.c, 1.0 / p->g.r_sense, T, p->stream) != hipSuccess)
+        return XBAR_ERR_DEVICE;
+    return XBAR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -644,27 +724,8 @@ xbar_status xbar_transfer(xbar_plan p, double* T)
     if (p == nullptr || T == nullptr) return XBAR_ERR_ARG;
     if (p->state < kFactored) return XBAR_ERR_STATE;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
-    const int m = p->g.m, n = p->g.n;
-    const bool timing = p->timing;
-    p->timing = false;                     // the unit solves are not counted as sweeps
-    xbar_status st = XBAR_OK;
-    for (int i0 = 0; i0 < m && st == XBAR_OK; i0 += p->tr_rows) {
-        const int rows = p->tr_rows < m - i0 ? p->tr_rows : m - i0;
-        const int64_t total = (int64_t)rows * m;
-        const int grid = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-        hipLaunchKernelGGL(unit_inputs_kernel, dim3(grid), dim3(256), 0, p->stream, p->d.Vunit, rows, m, i0);
-        if (hipGetLastError() != hipSuccess) {
-            st = XBAR_ERR_DEVICE;
-            break;
-        }
-        st = xbar_solve_batch(p, p->d.Vunit, rows, nullptr);
-        if (st == XBAR_OK &&
-            hipMemcpyAsync(T + (int64_t)i0 * n, p->d.Iout, (size_t)rows * n * sizeof(double),
-                           hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
-            st = XBAR_ERR_DEVICE;
-    }
-    p->timing = timing;
-    // the batch workspace now holds unit solves, not a caller's batch
+    const xbar_status st = transfer_blocks_fit(p) ? transfer_by_blocks(p, T) : transfer_by_unit_solves(p, T);
+    // the batch workspace no longer holds a caller's batch
     p->state = kFactored;
     p->last_B = 0;
     return st;

@@ -37,16 +37,24 @@ def _oracle_T(wl):
 
 @pytest.mark.parametrize("name,precision,max_batch", [
     ("c1", "fp64", None), ("ragged", "fp64", None), ("ragged", "fp64", 7),
-    ("tall", "fp64", 64), ("c1", "fp32_ir", None), ("ragged", "fp32_ir", 5)])
+    ("tall", "fp64", 64), ("c1", "fp32_ir", None), ("ragged", "fp32_ir", 5),
+    ("c1", "fp64", 64), ("ragged", "fp64", 64), ("tall", "fp64", 128), ("m1", "fp64", 64),
+    ("m2", "fp64", 64), ("m3", "fp64", 70), ("wide", "fp64", 256), ("ragged", "fp32_ir", 64)])
 def test_transfer_matches_oracle(name, precision, max_batch):
     """T against the oracle's unit-input currents; V T against the oracle's currents.
-    max_batch below m makes xbar_transfer solve the unit inputs in several batches,
-    the last one ragged."""
+    Float64 plans whose max_batch (rounded up to 16) reaches the padded block size n_p
+    build T by block recurrences on the factorization; the others, and the refinement
+    mode, solve the unit inputs, in several batches when max_batch < m (the last one
+    ragged)."""
     import torch
     wl = {"c1": workloads.c1,
           "ragged": lambda: workloads.random_crossbar(37, 45, 19, 41, r_wl=1.5, r_bl=3.0,
                                                       r_src=40.0, r_sense=60.0),
-          "tall": lambda: workloads.random_crossbar(150, 70, 33, 42)}[name]()
+          "tall": lambda: workloads.random_crossbar(150, 70, 33, 42),
+          "m1": lambda: workloads.random_crossbar(1, 20, 4, 61),
+          "m2": lambda: workloads.random_crossbar(2, 33, 4, 62),
+          "m3": lambda: workloads.random_crossbar(3, 64, 4, 63),
+          "wide": lambda: workloads.random_crossbar(21, 200, 9, 64, r_wl=1.0, r_bl=4.0)}[name]()
     m, n = wl.G.shape
     tol = TOL_FP64 if precision == "fp64" else TOL_IR
     log(f"case transfer {name} m={m} n={n} {precision} max_batch={max_batch}")
