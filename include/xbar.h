@@ -154,15 +154,21 @@ xbar_status xbar_currents(xbar_plan plan, double* I);
  * every other source with 0 V.  The nodal system G v = I has a right-hand side
  * that is linear in the source voltages (Sec. II.A, Eqs. 5-7), so the currents
  * of any input vector are I[b][j] = sum_i V[b][i] T[i][j]: see
- * xbar_transfer_apply.  T is computed by solving the m unit inputs with the
- * plan's factorization and precision mode, min(max_batch, m) of them per
- * xbar_solve_batch, without node voltages.
+ * xbar_transfer_apply.  How T is computed from the plan's factorization:
+ *  - XBAR_FP64 plans whose max_batch, rounded up to 16, is at least the padded
+ *    block size (n rounded up to 64): by block recurrences.  The condensed
+ *    system is symmetric, so row i of T is g_sense W_i c_i, with W_i the
+ *    transposed block row i of the inverse applied to identity blocks at the
+ *    last row; the W_i follow from the factorization by the substitution
+ *    recurrences on whole blocks (about m dependent block products);
+ *  - otherwise: by solving the m unit inputs, min(max_batch, m) of them per
+ *    xbar_solve_batch, without node voltages, in the plan's precision mode.
  *   T  device, [m][n] row-major, amperes per volt; caller-owned.
  * Requires a prior xbar_factor (XBAR_ERR_STATE otherwise).  Uses the plan's
  * batch workspace: the result of an earlier xbar_solve_batch is dropped and
- * xbar_currents returns XBAR_ERR_STATE until the next xbar_solve_batch.  The
- * unit solves are not counted by the phase timers.  Device errors (e.g. IR
- * modes not converging) set the sticky flags as xbar_solve_batch does.
+ * xbar_currents returns XBAR_ERR_STATE until the next xbar_solve_batch.  Not
+ * counted by the phase timers.  Device errors (e.g. IR modes not converging)
+ * set the sticky flags as xbar_solve_batch does.
  */
 xbar_status xbar_transfer(xbar_plan plan, double* T);
 
