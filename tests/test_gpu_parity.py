@@ -190,3 +190,28 @@ def test_currents_only_same_bits(m, n, B, seed):
     e = rel_err(I_only, oracle.solve_workload(wl).currents)
     log(f"  max current rel err {e.max():.3e}")
     assert e.max() <= TOL_FP64
+
+
+def test_partitioned_crossbar():
+    """The partition experiment's reading: a 64 x 64 crossbar split into 32 x 32 tiles, each
+    solved as a crossbar of its own (the paper's model, 5-ohm segments), column currents of a
+    tile column summed.  Library tiles against oracle tiles."""
+    rng = np.random.default_rng(2562)
+    M, s, B, r = 64, 32, 3, 5.0
+    G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (M, M)))
+    V = rng.uniform(0.0, 0.5, (B, M))
+    geom = workloads.Geometry(s, s, r, r, r, r)
+    log(f"case partition {M}x{M} into {s}x{s}")
+    I = np.zeros((B, M))
+    I_ref = np.zeros((B, M))
+    for a in range(M // s):
+        for b in range(M // s):
+            Gt = np.ascontiguousarray(G[a * s:(a + 1) * s, b * s:(b + 1) * s])
+            Vt = np.ascontiguousarray(V[:, a * s:(a + 1) * s])
+            It, _, (st, _) = gpu_solve(Gt, Vt, geom, "fp64", node_voltages=False)
+            assert st == 0
+            I[:, b * s:(b + 1) * s] += It
+            I_ref[:, b * s:(b + 1) * s] += oracle.solve(Gt, Vt, r, r, r, r).currents
+    e = rel_err(I, I_ref)
+    log(f"  max rel err {e.max():.3e}")
+    assert e.max() <= TOL_FP64
