@@ -178,7 +178,8 @@ def main():
 
     def run_transfer(steps, reps=50):
         """Currents through the transfer matrix: per conductance map assemble, factor and
-        T (m unit-input solves); per batch one float64 matrix-core product I = V T."""
+        T (block recurrences on the factorization); per batch one float64 matrix-core
+        product I = V T."""
         plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, "fp64", max_batch=B, stream=stream)
         T = torch.empty((m, n), dtype=torch.float64, device="cuda")
 

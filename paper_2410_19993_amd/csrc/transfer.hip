@@ -1,7 +1,9 @@
-// Float64 matrix-core product for the transfer-matrix shortcut.  The crossbar
-// is a linear network: the nodal system of Sec. II.A has a right-hand side that
-// is linear in the word-line sources, so the output currents of any batch are
-// the input voltages times the m x n matrix of output currents per unit input.
+// Float64 matrix-core kernels of the transfer-matrix shortcut.  The crossbar is
+// a linear network: the nodal system of Sec. II.A has a right-hand side that is
+// linear in the word-line sources, so the output currents of any batch are the
+// input voltages times the m x n matrix T of output currents per unit input.
+// This file holds the product I = V T (below) and, further down, the block
+// products and row reduction that build T from the factorization.
 //
 // Tiling (gfx950, wave64): a workgroup of 8 waves owns a 128 x 64 block of I
 // and walks the contraction index k in chunks of 32.  Each chunk of V
@@ -51,10 +53,9 @@ __device__ inline int clamp4(int v) { return v < 0 ? 0 : (v > 4 ? 4 : v); }
 
 // Block shape: BM x BN outputs, contraction chunks of BK, WM x WN waves each owning
 // (BM / WM) x (BN / WN) outputs.
-template <int BM_, int BN_, int BK_, int WM_, int WN_, int DEPTH_ = 1>
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
 struct Tiling {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
-    static constexpr int DEPTH = DEPTH_;                          // chunks loaded ahead (1 or 2)
     static constexpr int kThreads = 64 * WM * WN;
     static constexpr int TI = BM / WM / 16, TJ = BN / WN / 16;   // output tiles per wave
     static constexpr int KS = BK / 16;                            // 16-deep sub-chunks per chunk
@@ -62,7 +63,7 @@ struct Tiling {
     static constexpr int GB = BN * BK / 4 / kThreads;             // 4-wide T pieces per thread
     static constexpr int LA = BM * BK, LB = BN * BK;              // doubles per LDS stage
     static_assert(TI >= 1 && TJ >= 1 && BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tiles");
-    static_assert(BK % 16 == 0 && GA >= 1 && GB >= 1 && (DEPTH == 1 || DEPTH == 2), "chunk");
+    static_assert(BK % 16 == 0 && GA >= 1 && GB >= 1, "chunk");
     static_assert(GA * kThreads * 4 == BM * BK && GB * kThreads * 4 == BN * BK, "pieces");
 };
 
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(C::kThreads) void transfer_apply_kernel(
         b_src[e] = T + (b_ok[e] ? col : 0);
     }
 
-    double ra[C::DEPTH][C::GA][4], rb[C::DEPTH][C::GB][4];
+    double ra[2][C::GA][4], rb[2][C::GB][4];                  // two chunks in flight
     auto fetch = [&](int k0, auto set) {
 #pragma unroll
         for (int e = 0; e < C::GA; ++e)
@@ -184,33 +185,23 @@ __global__ __launch_bounds__(C::kThreads) void transfer_apply_kernel(
         }
     };
 
+    // register set s holds the chunk kc + 1 while the chunk kc + 2 loads into the other
     using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, C::DEPTH - 1>;
+    using S1 = std::integral_constant<int, 1>;
     const int nk = (m + C::BK - 1) / C::BK;
     fetch(0, S0{});
     stash(0, S0{});
-    if constexpr (C::DEPTH == 1) {
+    if (nk > 1) fetch(C::BK, S1{});
+    __syncthreads();
+    auto step = [&](int kc, auto cur, auto nxt) {
+        if (kc + 2 < nk) fetch((kc + 2) * C::BK, cur);
+        compute(kc & 1);
+        if (kc + 1 < nk) stash((kc & 1) ^ 1, nxt);
         __syncthreads();
-        for (int kc = 0; kc < nk; ++kc) {
-            if (kc + 1 < nk) fetch((kc + 1) * C::BK, S0{});
-            compute(kc & 1);
-            if (kc + 1 < nk) stash((kc & 1) ^ 1, S0{});
-            __syncthreads();
-        }
-    } else {
-        // register set s holds the chunk kc + 1 while the chunk kc + 2 loads into the other
-        if (nk > 1) fetch(C::BK, S1{});
-        __syncthreads();
-        auto step = [&](int kc, auto cur, auto nxt) {
-            if (kc + 2 < nk) fetch((kc + 2) * C::BK, cur);
-            compute(kc & 1);
-            if (kc + 1 < nk) stash((kc & 1) ^ 1, nxt);
-            __syncthreads();
-        };
-        for (int kc = 0; kc < nk; kc += 2) {
-            step(kc, S0{}, S1{});
-            if (kc + 1 < nk) step(kc + 1, S1{}, S0{});
-        }
+    };
+    for (int kc = 0; kc < nk; kc += 2) {
+        step(kc, S0{}, S1{});
+        if (kc + 1 < nk) step(kc + 1, S1{}, S0{});
     }
 
     // item v of lane l = 16q + c is row q + 4v, column c of its 16 x 16 output tile
@@ -246,7 +237,7 @@ hipError_t launch_tiling(int B, int m, int n, const double* V, const double* T, 
     return hipGetLastError();
 }
 
-using ApplyTiling = Tiling<128, 64, 32, 4, 2, 2>;
+using ApplyTiling = Tiling<128, 64, 32, 4, 2>;
 
 // ---------------------------------------------------------------------------
 // Products of FRG blocks for building T from the factorization.  A workgroup of 4

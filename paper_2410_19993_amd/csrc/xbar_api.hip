@@ -43,7 +43,8 @@ struct Buffers {
     double* dnorm = nullptr;                 // [nslab][16]
     int* slab_done = nullptr;                // [nslab]
     int* slab_final = nullptr;               // [nslab]
-    double* Vunit = nullptr;                 // [tr_rows][m]: unit inputs of xbar_transfer
+    double* Vunit = nullptr;                 // [tr_rows][m]: unit inputs of xbar_transfer (plans
+                                             // without the block form only)
 };
 
 __global__ void clear_slabs_kernel(int* done, double* dnorm, int nslab)
@@ -159,6 +160,14 @@ void free_all(xbar_plan p)
 
 bool set_device(xbar_plan p) { return hipSetDevice(p->device) == hipSuccess; }
 
+// The block form of xbar_transfer keeps m FRG blocks of n_p x n_p in the sweep workspace
+// (float64 plans whose max_batch, rounded up to 16, is at least n_p); other plans solve
+// unit inputs and hold a staging buffer for them.
+bool transfer_blocks_fit(xbar_plan p)
+{
+    return p->prec == XBAR_FP64 && (int64_t)p->nslab_max * 16 >= p->n_p;
+}
+
 void destroy_side(xbar_plan p)
 {
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
@@ -257,7 +266,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
     A((void**)&d.ns_state, 6 * sizeof(xbk::NSState));
-    A((void**)&d.Vunit, (int64_t)p->tr_rows * m * 8);
+    if (!transfer_blocks_fit(p)) A((void**)&d.Vunit, (int64_t)p->tr_rows * m * 8);
     if (prec != XBAR_FP64) {
         const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
         A((void**)&d.U[0], panel * 8);
@@ -477,13 +486,6 @@ bool overlaps(const void* a, int64_t a_bytes, const void* b, int64_t b_bytes)
 {
     const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
     return x < y + (uintptr_t)b_bytes && y < x + (uintptr_t)a_bytes;
-}
-
-// The block form of xbar_transfer keeps m FRG blocks of n_p x n_p in the sweep workspace
-// (float64 plans whose max_batch, rounded up to 16, is at least n_p).
-bool transfer_blocks_fit(xbar_plan p)
-{
-    return p->prec == XBAR_FP64 && (int64_t)p->nslab_max * 16 >= p->n_p;
 }
 
 // T from the m unit input vectors, solved with the plan's factorization (any plan).
