@@ -188,6 +188,29 @@ xbar_status xbar_transfer(xbar_plan plan, double* T);
 xbar_status xbar_transfer_apply(xbar_plan plan, const double* T, const double* V, int32_t B, double* I);
 
 /*
+ * Output currents of T small crossbars of one shape, each with its own
+ * conductances and input vectors, in one launch with one workgroup per
+ * crossbar (the partitioned crossbars of Sec. III.C, solved by the method of
+ * Sec. II.A-II.C: word-line elimination per row, block LU over the rows
+ * top-down, forward substitution; the bottom row's forward result gives the
+ * currents, so no back substitution is needed).  Needs no plan and allocates
+ * nothing.
+ *   geom   1 <= m, 1 <= n <= XBAR_TILE_MAX_N; resistances as for xbar_create.
+ *   T      number of crossbars, >= 1.
+ *   B      input vectors per crossbar, 1 <= B <= XBAR_TILE_MAX_B.
+ *   G      device, [T][m][n] siemens.   V  device, [T][B][m] volts.
+ *   I      device, [T][B][n] amperes, as xbar_currents; must not overlap G or V.
+ *   hip_stream  hipStream_t the launch is queued on (NULL = null stream).
+ * Asynchronous.  A crossbar with a conductance that is not finite and
+ * positive gets NaN currents (the others are unaffected).  Returns
+ * XBAR_ERR_ARG (host checks), XBAR_ERR_DEVICE (launch error) or XBAR_OK.
+ */
+#define XBAR_TILE_MAX_N 64
+#define XBAR_TILE_MAX_B 256
+xbar_status xbar_tiles_currents(const xbar_geometry* geom, int32_t T, int32_t B, const double* G, const double* V,
+                                double* I, void* hip_stream);
+
+/*
  * Synchronise the plan's stream and report its state.  Returns the sticky
  * device error (XBAR_ERR_INPUT, XBAR_ERR_NOT_SPD, XBAR_ERR_NO_CONVERGENCE)
  * if one was raised, XBAR_ERR_DEVICE on a HIP error, else XBAR_OK.

@@ -9,7 +9,7 @@ from . import _lib
 from ._lib import (FACTOR_METHODS, PRECISIONS, XBAR_BF16_IR, XBAR_FP32_IR, XBAR_FP64,  # noqa: F401
                    Geometry, XbarError, status_string)
 
-__all__ = ["Plan", "solve", "Geometry", "XbarError", "PRECISIONS", "status_string"]
+__all__ = ["Plan", "solve", "tiles_currents", "Geometry", "XbarError", "PRECISIONS", "status_string"]
 
 
 def _torch():
@@ -119,6 +119,23 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def tiles_currents(G, V, r_wl, r_bl, r_src=50.0, r_sense=50.0, out=None, stream=None):
+    """Output currents of T crossbars of one shape in one launch (xbar_tiles_currents):
+    G [T][m][n], V [T][B][m] float64 CUDA/HIP tensors; returns I [T][B][n]."""
+    torch = _torch()
+    T, m, n = (int(x) for x in G.shape)
+    B = int(V.shape[1])
+    _check_tensor("G", G, (T, m, n))
+    _check_tensor("V", V, (T, B, m))
+    if out is None:
+        out = torch.empty((T, B, n), dtype=torch.float64, device="cuda")
+    _check_tensor("I", out, (T, B, n))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    geom = Geometry(m, n, float(r_wl), float(r_bl), float(r_src), float(r_sense))
+    _lib.xbar_tiles_currents(geom, T, B, G, V, out, s.cuda_stream)
+    return out
 
 
 def solve(G, V, r_wl, r_bl, r_src=50.0, r_sense=50.0, precision="fp64", node_voltages=True,

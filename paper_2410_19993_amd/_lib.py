@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         L.xbar_currents.argtypes = [vp, vp]
         L.xbar_transfer.argtypes = [vp, vp]
         L.xbar_transfer_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+        L.xbar_tiles_currents.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         L.xbar_get_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.xbar_destroy.argtypes = [vp]
         L.xbar_set_timing.argtypes = [vp, ctypes.c_int32]
@@ -90,7 +91,7 @@ def lib() -> ctypes.CDLL:
         for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
                   "xbar_get_timing", "xbar_set_factor_method", "xbar_transfer",
-                  "xbar_transfer_apply"):
+                  "xbar_transfer_apply", "xbar_tiles_currents"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -149,6 +150,11 @@ def xbar_transfer(plan, T) -> None:
 
 def xbar_transfer_apply(plan, T, V, B: int, I) -> None:
     _check("xbar_transfer_apply", lib().xbar_transfer_apply(plan, _ptr(T), _ptr(V), int(B), _ptr(I)))
+
+
+def xbar_tiles_currents(geom: Geometry, T: int, B: int, G, V, I, stream: int | None = None) -> None:
+    _check("xbar_tiles_currents", lib().xbar_tiles_currents(ctypes.byref(geom), int(T), int(B), _ptr(G), _ptr(V),
+                                                            _ptr(I), ctypes.c_void_p(stream or 0)))
 
 
 def xbar_get_info(plan) -> tuple[int, Info]:

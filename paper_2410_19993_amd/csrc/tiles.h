@@ -1,0 +1,9 @@
+// Batched small crossbars: output currents, one workgroup per crossbar.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+// T crossbars of m x n (n <= 64), B <= 256 input vectors each: G [T][m][n],
+// V [T][B][m], I [T][B][n], float64 device arrays, I not overlapping G or V.
+hipError_t xbk_launch_tile_currents(int T, int m, int n, int B, double g_wl, double g_bl, double g_src,
+                                    double g_sense, const double* G, const double* V, double* I, hipStream_t s);

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.h"
+#include "tiles.h"
 #include "transfer.h"
 #include "xbar.h"
 
@@ -742,6 +743,25 @@ xbar_status xbar_transfer_apply(xbar_plan p, const double* T, const double* V, i
         return XBAR_ERR_ARG;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
     if (xbk_launch_transfer_apply(B, (int)m, (int)n, V, T, I, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    return XBAR_OK;
+}
+
+xbar_status xbar_tiles_currents(const xbar_geometry* geom, int32_t T, int32_t B, const double* G, const double* V,
+                                double* I, void* hip_stream)
+{
+    if (geom == nullptr || G == nullptr || V == nullptr || I == nullptr) return XBAR_ERR_ARG;
+    const xbar_geometry g = *geom;
+    if (g.m < 1 || g.n < 1 || g.n > XBAR_TILE_MAX_N || T < 1 || B < 1 || B > XBAR_TILE_MAX_B) return XBAR_ERR_ARG;
+    if (!finite_pos(g.r_wl) || !finite_pos(g.r_bl) || !finite_pos(g.r_src) || !finite_pos(g.r_sense))
+        return XBAR_ERR_ARG;
+    const int64_t i_bytes = (int64_t)T * B * g.n * 8;
+    if (overlaps(I, i_bytes, G, (int64_t)T * g.m * g.n * 8) || overlaps(I, i_bytes, V, (int64_t)T * B * g.m * 8))
+        return XBAR_ERR_ARG;
+    if (xbk_launch_tile_currents(T, g.m, g.n, B, 1.0 / g.r_wl, 1.0 / g.r_bl, 1.0 / g.r_src, 1.0 / g.r_sense, G, V, I,
+                                 reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return XBAR_ERR_DEVICE;
+    }
     return XBAR_OK;
 }
 

@@ -10,7 +10,7 @@ from paper_2410_19993_amd import _lib
 
 EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor",
             "xbar_get_info", "xbar_get_timing", "xbar_set_factor_method", "xbar_set_timing",
-            "xbar_solve_batch", "xbar_status_string", "xbar_transfer", "xbar_transfer_apply"]
+            "xbar_solve_batch", "xbar_status_string", "xbar_tiles_currents", "xbar_transfer", "xbar_transfer_apply"]
 
 
 def _gpu_visible():
@@ -96,3 +96,29 @@ def test_null_plan_calls():
 def test_create_without_device_reports_device_error():
     st, plan = _create(_lib.Geometry(**GOOD))
     assert st == _lib.XBAR_ERR_DEVICE and not plan.value
+
+
+@pytest.mark.parametrize("field,value,T,B", [
+    ("n", 65, 2, 4), ("n", 0, 2, 4), ("m", 0, 2, 4), ("r_wl", 0.0, 2, 4), ("r_sense", math.inf, 2, 4),
+    ("n", 8, 0, 4), ("n", 8, 2, 0), ("n", 8, 2, 257)])
+def test_tiles_rejects_bad_arguments(field, value, T, B):
+    """Host checks of xbar_tiles_currents come before any device call (no GPU needed)."""
+    kw = dict(GOOD)
+    kw[field] = value
+    g = _lib.Geometry(**kw)
+    buf = (ctypes.c_double * 4096)()
+    L = _lib.lib()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.xbar_tiles_currents(ctypes.byref(g), T, B, p, p, None, None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_tiles_currents(None, 1, 1, p, p, p, None) == _lib.XBAR_ERR_ARG
+
+
+def test_tiles_rejects_overlapping_output():
+    g = _lib.Geometry(**GOOD)                      # 4 x 4
+    buf = (ctypes.c_double * 4096)()
+    base = ctypes.addressof(buf)
+    G, V = ctypes.c_void_p(base), ctypes.c_void_p(base + 8 * 1024)
+    L = _lib.lib()
+    # I over G, then over V: rejected before any device call
+    assert L.xbar_tiles_currents(ctypes.byref(g), 2, 3, G, V, ctypes.c_void_p(base + 8 * 16), None) == _lib.XBAR_ERR_ARG
+    assert L.xbar_tiles_currents(ctypes.byref(g), 2, 3, G, V, ctypes.c_void_p(base + 8 * 1030), None) == _lib.XBAR_ERR_ARG
