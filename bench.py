@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-shortcuts", action="store_true",
                     help="skip the currents-only and transfer-matrix legs")
+    ap.add_argument("--no-tiles", action="store_true", help="skip the batched small-tile leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -227,6 +228,45 @@ def main():
                                    "flops_per_launch": flops},
                 "max_rel_err_vs_oracle": err}
 
+    def run_tiles(steps):
+        """The heterogeneous tiles workload's crossbars with n_t <= 64 (its other half needs
+        blocks larger than one workgroup's LDS), one xbar_tiles_currents launch per
+        (m_t, n_t) class, currents of all 256 input vectors of every tile."""
+        tl = workloads.c4(max_n=64)
+        classes = {}
+        for t in tl:
+            classes.setdefault(t.G.shape, []).append(t)
+        dev = []
+        flops = 0.0
+        for (tm_, tn_), ts in sorted(classes.items()):
+            Gs = torch.from_numpy(np.stack([t.G for t in ts])).cuda()
+            Vs = torch.from_numpy(np.stack([t.V for t in ts])).cuda()
+            Is = torch.empty((len(ts), 256, tn_), dtype=torch.float64, device="cuda")
+            dev.append((Gs, Vs, Is))
+            flops += len(ts) * (tm_ * tn_ ** 3 + 2.0 * tm_ * tn_ ** 2 * 256)
+        g4 = workloads.C4_GEOM
+
+        def one_pass():
+            for Gs, Vs, Is in dev:
+                xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is,
+                                  stream=stream)
+
+        one_pass()
+        torch.cuda.synchronize()
+        assert all(bool(torch.isfinite(Is).all()) for _, _, Is in dev), "tile currents not finite"
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one_pass()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        vecs = 256 * len(tl)
+        log(f"tiles: {len(tl)} crossbars in {len(dev)} classes, {ms:.2f} ms per pass")
+        return {"value": vecs / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms, "tiles": len(tl),
+                "classes": len(dev), "tiles_per_s": len(tl) / (ms * 1e-3),
+                "workload": "c4 tiles with n_t <= 64 (seed 1004), 256 vectors each, currents only",
+                "algorithmic_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
+                "frac_of_fp64_peak": flops / (ms * 1e-3) / PEAK_FP64_MFMA}
+
     ms64, tm, info64, err64 = run("fp64", args.steps, args.warmup)
     # kernels: algorithmic work per launch
     sweep_flops = 2.0 * n * n * B * (2 * m - 1)          # forward m products + back (m-1)
@@ -278,6 +318,8 @@ def main():
         result["solve_only"] = {"value": B / (k_sweep * 1e-3), "unit": "solves/s",
                                 "note": "fp64 sweeps with node voltages, factor excluded"}
         result["transfer"] = run_transfer(args.steps)
+    if not args.no_tiles:
+        result["tiles"] = run_tiles(args.steps)
     if not args.no_fp32_ir:
         # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
         # refinement stops once its error estimate is below 1e-10 (the error actually

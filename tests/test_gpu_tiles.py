@@ -70,3 +70,31 @@ def test_tiles_agree_with_the_plan_path():
     Ip, _, (st, _) = gpu_solve(G[0], V[0], workloads.Geometry(40, 64, *r), "fp64", node_voltages=False)
     assert st == 0
     assert rel_err(I, Ip).max() <= 1e-11
+
+
+def test_c4_tiles_in_bench_configuration():
+    """The heterogeneous tiles workload as the benchmark runs it: every (m_t, n_t) class with
+    n_t <= 64 in one launch; the first two tiles of each class against the oracle (all 256
+    input vectors for m_t <= 64, the first 32 otherwise)."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    import workloads
+    g = workloads.C4_GEOM
+    r = (g["r_wl"], g["r_bl"], g["r_src"], g["r_sense"])
+    classes = {}
+    for t in workloads.c4(max_n=64):
+        classes.setdefault(t.G.shape, []).append(t)
+    worst = 0.0
+    for (m, n), ts in sorted(classes.items()):
+        log(f"case c4 class m={m} n={n}: {len(ts)} tiles")
+        Gs = torch.from_numpy(np.stack([t.G for t in ts])).cuda()
+        Vs = torch.from_numpy(np.stack([t.V for t in ts])).cuda()
+        I = xb.tiles_currents(Gs, Vs, *r).cpu().numpy()
+        assert np.all(np.isfinite(I))
+        for k in range(2):
+            rows = slice(None) if m <= 64 else slice(0, 32)
+            ref = oracle.solve(ts[k].G, ts[k].V[rows], *r).currents
+            worst = max(worst, float(rel_err(I[k][rows], ref).max()))
+    log(f"  max current rel err {worst:.3e}")
+    assert worst <= TOL_FP64

@@ -14,6 +14,9 @@ for those random crossbars with stated distributions:
   50/50 ohm, 1024 input vectors ~ U[0, 0.5] V.
 * ``c3``: 512x512, G log-uniform, segment resistance in {1, 2.5, 5} ohm
   (one G and V shared by the three), 50/50 ohm, 4096 input vectors.
+* ``c4``: 2048 heterogeneous tiles (the partitioned crossbars of Sec. III.C at
+  scale): m_t, n_t in {32, 64, 128, 256}, signed weights mapped to
+  differential column pairs, 256 input vectors each, binarized or uniform.
 
 All arrays are float64, drawn with ``numpy.random.default_rng(seed)`` (PCG64)
 in the order listed in each function.  ``G`` is [m][n] (row = word line,
@@ -103,3 +106,42 @@ def random_crossbar(m: int, n: int, B: int, seed: int, r_wl: float = 2.5,
     V = rng.uniform(0.0, 0.5, (B, m))
     rb = r_wl if r_bl is None else r_bl
     return Workload(f"rand_{m}x{n}_b{B}_s{seed}", Geometry(m, n, r_wl, rb, r_src, r_sense), G, V)
+
+
+C4_SIZES = (32, 64, 128, 256)
+
+
+@dataclass
+class Tile:
+    index: int
+    G: np.ndarray          # [m_t][n_t] siemens, columns (2k, 2k+1) = (G+, G-) of weight column k
+    V: np.ndarray          # [256][m_t] volts
+
+
+def c4(seed: int = 1004, tiles: int = 2048, max_n: int | None = None) -> list:
+    """Heterogeneous tiles, drawn in this order for each tile t: m_t and n_t, each
+    C4_SIZES[integers(4)]; W ~ N(0, 0.05) of shape m_t x (n_t / 2), clipped to
+    +-0.15; G+ = G_MIN + (G_MAX - G_MIN) max(W, 0) / 0.15 and G- the same for -W,
+    interleaved as columns (2k, 2k+1); V of shape 256 x m_t, in {0, 0.5} with
+    probability 1/2 each for even t, U[0, 0.5] for odd t.  Wires: r = 2.5 ohm,
+    50-ohm source and sense resistors (``C4_GEOM``).  Every tile's draws are
+    made; with ``max_n`` only the tiles with n_t <= max_n are returned."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(tiles):
+        m = C4_SIZES[int(rng.integers(4))]
+        n = C4_SIZES[int(rng.integers(4))]
+        W = np.clip(rng.normal(0.0, 0.05, (m, n // 2)), -0.15, 0.15)
+        G = np.empty((m, n))
+        G[:, 0::2] = G_MIN + (G_MAX - G_MIN) * np.maximum(W, 0.0) / 0.15
+        G[:, 1::2] = G_MIN + (G_MAX - G_MIN) * np.maximum(-W, 0.0) / 0.15
+        if t % 2 == 0:
+            V = rng.integers(0, 2, (256, m)).astype(np.float64) * 0.5
+        else:
+            V = rng.uniform(0.0, 0.5, (256, m))
+        if max_n is None or n <= max_n:
+            out.append(Tile(t, G, V))
+    return out
+
+
+C4_GEOM = dict(r_wl=2.5, r_bl=2.5, r_src=50.0, r_sense=50.0)
