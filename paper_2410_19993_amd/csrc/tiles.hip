@@ -10,20 +10,23 @@
 // back substitution leaves the last row unchanged), so the output currents
 // g_sense z_{m-1} need no back substitution and no row block is stored.
 //
-// Workgroup layout (256 threads, NP x NP blocks padded with identity to NP in
-// {16, 32, 64}):
+// Workgroup layout (256 threads = 4 waves, blocks padded with identity to NP in
+// {16, 32, 64}, BS = NP / 16):
 //  * thread k < n walks column k of T_i^-1 with the Thomas recurrences of the
-//    word-line chain and writes column k of S_i into LDS;
-//  * S_i is inverted in place by Gauss-Jordan elimination without pivoting (S_i
-//    is symmetric positive definite); thread t owns the elements e = t + 256 s
-//    (two barriers per pivot step: read, then write);
-//  * thread b < B keeps z for input vector b in registers and forms the next z
-//    from H_i in LDS (every lane reads the same H element: LDS broadcast).
-// Two LDS blocks alternate: S_i is built in one while H_{i-1} sits in the other.
-// A tile with a conductance that is not finite and positive, or a pivot that is
-// not positive, gets NaN currents.
-// float64 throughout.  The float64 vector units of this part run at the
-// float64 matrix-core rate, so the n x n x B product per row stays on them.
+//    word-line chain (reciprocal pivots, so only multiplications) into LDS;
+//  * thread t = 16 br + bc holds the BS x BS block (br, bc) of S_i in registers
+//    and inverts S_i in place with the others by Gauss-Jordan elimination
+//    without pivoting (S_i is SPD): per pivot step only row k and column k go
+//    through LDS (double-buffered, one barrier per step);
+//  * the product H_i Y runs on the float64 matrix cores: wave w owns input
+//    vectors 64 w .. 64 w + 63 as four groups of 16, and keeps their forward
+//    results in the accumulator layout (item v of lane l = 16 q + c is row
+//    q + 4v of a 16-row tile, vector c of a group).  That is also the B-operand
+//    layout of the next row's product, so the forward results never move.  The
+//    A operand, H_i, is read from LDS along rows (H_i is symmetric).
+// Two LDS blocks alternate: T_i^-1, then H_i, in one, while H_{i-1} sits in the
+// other.  A tile with a conductance that is not finite and positive, or a pivot
+// that is not positive, gets NaN currents.  float64 throughout.
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -33,6 +36,8 @@
 namespace {
 
 constexpr int kTileThreads = 256;
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
 
 struct TileArgs {
     int m, n, B;
@@ -45,13 +50,17 @@ struct TileArgs {
 template <int NP>
 __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
 {
-    constexpr int LD = NP;     // row stride: every cross-lane LDS access is a row or a broadcast
-    constexpr int PER = NP * NP / kTileThreads > 0 ? NP * NP / kTileThreads : 1;
-    __shared__ double blk[2][NP * LD];
-    __shared__ double gr[NP], cr[NP], piv[NP];
+    constexpr int LD = NP;                             // row stride of the LDS blocks
+    constexpr int BS = NP / 16;                        // register block edge of the elimination
+    constexpr int NT = NP / 16;                        // 16-row tiles of the product
+    __shared__ __align__(16) double blk[2][NP * LD];
+    __shared__ __align__(16) double rowb[2][NP], colb[2][NP];
+    __shared__ double gr[NP], cr[NP], piv[NP], rpiv[NP];
     __shared__ int bad;
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int q = lane >> 4, l16 = lane & 15;
+    const int br = tid >> 4, bc = tid & 15;
     const int m = a.m, n = a.n, B = a.B;
     const int64_t t = blockIdx.x;
     const double* G = a.G + t * m * n;
@@ -61,14 +70,17 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
     if (tid == 0) bad = 0;
     __syncthreads();
 
-    double z[NP];
+    // forward results of vectors 64 w + 16 g + l16: z[tile][g] item v = row 16 tile + q + 4 v
+    dv4 z[NT][4];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) z[k] = 0.0;
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) z[tt][g] = dv4{0.0, 0.0, 0.0, 0.0};
 
     for (int i = 0; i < m; ++i) {
-        double* S = blk[i & 1];
-        const double* Hp = blk[(i & 1) ^ 1];
-        // ---- row data and the pivots of the word-line chain (excess form, no subtraction):
+        double* Tb = blk[i & 1];                       // T_i^-1, then H_i
+        const double* Hp = blk[(i & 1) ^ 1];           // H_{i-1}
+        // ---- row data; pivots of the word-line chain (excess form, no subtraction):
         // e_0 = G_0 + g_src, e_j = G_j + g_wl e_{j-1} / p_{j-1}, p_j = e_j + g_wl [j < n-1]
         if (tid < n) {
             const double g = G[(int64_t)i * n + tid];
@@ -79,105 +91,148 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
         if (tid == 0) {
             double e = gr[0] + a.g_src;
             piv[0] = e + (n > 1 ? gw : 0.0);
+            rpiv[0] = 1.0 / piv[0];
             for (int j = 1; j < n; ++j) {
-                e = gr[j] + gw * e / piv[j - 1];
+                e = gr[j] + gw * e * rpiv[j - 1];
                 piv[j] = e + (j < n - 1 ? gw : 0.0);
+                rpiv[j] = 1.0 / piv[j];
             }
         }
         __syncthreads();
-        // ---- column k of T_i^-1 (thread k): forward y_j = [j = k] + (g_wl / p_{j-1}) y_{j-1},
-        // back x_j = (y_j + g_wl x_{j+1}) / p_j, kept in column k of S
+        // ---- column k of T_i^-1 (thread k): y_j = [j = k] + g_wl y_{j-1} / p_{j-1},
+        // x_j = (y_j + g_wl x_{j+1}) / p_j
         if (tid < n) {
             const int k = tid;
             double y = 0.0;
             for (int j = k; j < n; ++j) {
-                y = (j == k ? 1.0 : 0.0) + (j > k ? gw / piv[j - 1] * y : 0.0);
-                S[j * LD + k] = y;
+                y = (j == k) ? 1.0 : gw * rpiv[j - 1] * y;
+                Tb[j * LD + k] = y;
             }
-            for (int j = 0; j < k; ++j) S[j * LD + k] = 0.0;
+            for (int j = 0; j < k; ++j) Tb[j * LD + k] = 0.0;
             double x = 0.0;
             for (int j = n - 1; j >= 0; --j) {
-                x = (S[j * LD + k] + (j < n - 1 ? gw * x : 0.0)) / piv[j];
-                S[j * LD + k] = x;
+                x = (Tb[j * LD + k] + (j < n - 1 ? gw * x : 0.0)) * rpiv[j];
+                Tb[j * LD + k] = x;
             }
         }
         __syncthreads();
-        // ---- S_i = diag(q_i) - Gam T^-1 Gam - g_bl^2 H_{i-1}, identity on the padding;
-        // c_i = g_src Gam T^-1 e_0
+        // ---- S_i = diag(q_i) - Gam T^-1 Gam - g_bl^2 H_{i-1} (identity on the padding) into
+        // this thread's register block; c_i = g_src Gam T^-1 e_0 (zero on the padding)
+        double s[BS][BS];
         {
             const double below = (i < m - 1) ? gb : a.g_sense;
             const double above = (i > 0) ? gb : 0.0;
             const double g2 = gb * gb;
 #pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const int e = tid + kTileThreads * s;
-                if (e < NP * NP) {
-                    const int r = e / NP, c = e % NP;
-                    double v;
+            for (int ii = 0; ii < BS; ++ii) {
+                const int r = BS * br + ii;
+#pragma unroll
+                for (int jj = 0; jj < BS; ++jj) {
+                    const int c = BS * bc + jj;
+                    double v = (r == c) ? 1.0 : 0.0;
                     if (r < n && c < n) {
-                        v = -gr[r] * S[r * LD + c] * gr[c];
+                        v = -gr[r] * Tb[r * LD + c] * gr[c];
                         if (r == c) v += gr[r] + above + below;
                         if (i > 0) v -= g2 * Hp[r * LD + c];
-                    } else {
-                        v = (r == c) ? 1.0 : 0.0;
                     }
-                    if (c == 0 && r < n) cr[r] = a.g_src * gr[r] * S[r * LD];
-                    // all reads of column c above were this thread's own column-0 or (r, c) entry
-                    // except S[r][0] for c == 0, which is the same element: safe in place
-                    S[r * LD + c] = v;
+                    s[ii][jj] = v;
                 }
+                if (bc == 0) cr[r] = (r < n) ? a.g_src * gr[r] * Tb[r * LD] : 0.0;
+            }
+        }
+        // ---- H_i = S_i^-1 (Gauss-Jordan, no pivoting) on the register blocks
+        for (int k = 0; k < n; ++k) {
+            const int kb = k & 1, kr = k / BS, ko = k % BS;
+            if (br == kr) {
+#pragma unroll
+                for (int jj = 0; jj < BS; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < BS; ++ii)
+                        if (ii == ko) rowb[kb][BS * bc + jj] = s[ii][jj];
+            }
+            if (bc == kr) {
+#pragma unroll
+                for (int ii = 0; ii < BS; ++ii)
+#pragma unroll
+                    for (int jj = 0; jj < BS; ++jj)
+                        if (jj == ko) colb[kb][BS * br + ii] = s[ii][jj];
+            }
+            __syncthreads();
+            const double p = rowb[kb][k];
+            if (tid == 0 && !(p > 0.0 && p <= 1e300)) bad = 1;
+            const double pinv = 1.0 / p;
+            double f[BS], nk[BS];
+#pragma unroll
+            for (int ii = 0; ii < BS; ++ii) f[ii] = colb[kb][BS * br + ii];
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj) {
+                const int c = BS * bc + jj;
+                nk[jj] = (c == k ? 1.0 : rowb[kb][c]) * pinv;        // new row k
+            }
+#pragma unroll
+            for (int ii = 0; ii < BS; ++ii) {
+                const int r = BS * br + ii;
+#pragma unroll
+                for (int jj = 0; jj < BS; ++jj) {
+                    const int c = BS * bc + jj;
+                    s[ii][jj] = (r == k) ? nk[jj] : ((c == k ? 0.0 : s[ii][jj]) - f[ii] * nk[jj]);
+                }
+            }
+        }
+        // ---- H_i into LDS (T_i^-1 there is no longer needed)
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < BS; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj) Tb[(BS * br + ii) * LD + BS * bc + jj] = s[ii][jj];
+        __syncthreads();
+        // ---- z <- H_i (V_i c_i + g_bl z) on the matrix cores
+        {
+            double vi[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int b = 64 * w + 16 * g + l16;
+                vi[g] = (b < B) ? V[(int64_t)b * m + i] : 0.0;
+            }
+            dv4 y[NT][4];
+#pragma unroll
+            for (int kc = 0; kc < NT; ++kc)
+#pragma unroll
+                for (int tq = 0; tq < 4; ++tq) {
+                    const double ck = cr[16 * kc + q + 4 * tq];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) y[kc][g][tq] = vi[g] * ck + gb * z[kc][g][tq];
+                }
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) z[tt][g] = dv4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kc = 0; kc < NT; ++kc)
+#pragma unroll
+                    for (int tq = 0; tq < 4; ++tq) {
+                        // A operand H[16 tt + l16][16 kc + q + 4 tq], read as its mirror H[k][a]
+                        const double h = Tb[(16 * kc + q + 4 * tq) * LD + 16 * tt + l16];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g)
+                            z[tt][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, y[kc][g][tq], z[tt][g], 0, 0, 0);
+                    }
             }
         }
         __syncthreads();
-        // ---- H_i = S_i^-1 in place (Gauss-Jordan, no pivoting)
-        for (int k = 0; k < n; ++k) {
-            const double p = S[k * LD + k];
-            double f[PER], rk[PER];
-#pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const int e = tid + kTileThreads * s;
-                const int r = e / NP, c = e % NP;
-                f[s] = (e < NP * NP) ? S[r * LD + k] : 0.0;
-                rk[s] = (e < NP * NP) ? S[k * LD + c] : 0.0;
-            }
-            if (tid == 0 && !(p > 0.0 && p <= 1e300)) bad = 1;
-            __syncthreads();
-            const double pinv = 1.0 / p;
-#pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const int e = tid + kTileThreads * s;
-                if (e < NP * NP) {
-                    const int r = e / NP, c = e % NP;
-                    const double nk = (c == k ? 1.0 : rk[s]) * pinv;     // new row k, column c
-                    S[r * LD + c] = (r == k) ? nk : ((c == k ? 0.0 : S[r * LD + c]) - f[s] * nk);
-                }
-            }
-            __syncthreads();
-        }
-        // ---- z <- H_i (V_i c_i + g_bl z) for this thread's input vector
-        if (tid < B) {
-            const double vi = V[(int64_t)tid * m + i];
-            double y[NP];
-#pragma unroll
-            for (int k = 0; k < NP; ++k) y[k] = (k < n ? vi * cr[k] : 0.0) + gb * z[k];
-#pragma unroll
-            for (int r = 0; r < NP; ++r) {
-                double acc = 0.0;
-#pragma unroll
-                for (int k = 0; k < NP; k += 2) {
-                    const double2 h = *reinterpret_cast<const double2*>(&S[r * LD + k]);
-                    acc += h.x * y[k] + h.y * y[k + 1];
-                }
-                z[r] = acc;
-            }
-        }
-        __syncthreads();          // H_i stays in this block for the next row's S_{i+1}
     }
-    if (tid < B) {
-        const bool fail = bad != 0;
+    const bool fail = bad != 0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j)           // unrolled: z stays in registers
-            if (j < n) I[(int64_t)tid * n + j] = fail ? NAN : a.g_sense * z[j];
+    for (int g = 0; g < 4; ++g) {
+        const int b = 64 * w + 16 * g + l16;
+        if (b >= B) continue;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * tt + q + 4 * v;
+                if (j < n) I[(int64_t)b * n + j] = fail ? NAN : a.g_sense * z[tt][g][v];
+            }
     }
 }
 
