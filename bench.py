@@ -231,7 +231,8 @@ def main():
     def run_tiles(steps):
         """The heterogeneous tiles workload's crossbars with n_t <= 64 (its other half needs
         blocks larger than one workgroup's LDS), one xbar_tiles_currents launch per
-        (m_t, n_t) class, currents of all 256 input vectors of every tile."""
+        (m_t, n_t) class, longest classes first, over four streams; currents of all 256
+        input vectors of every tile."""
         tl = workloads.c4(max_n=64)
         classes = {}
         for t in tl:
@@ -245,11 +246,23 @@ def main():
             dev.append((Gs, Vs, Is))
             flops += len(ts) * (tm_ * tn_ ** 3 + 2.0 * tm_ * tn_ ** 2 * 256)
         g4 = workloads.C4_GEOM
+        # classes side by side: each launch covers fewer tiles than there are CUs, so the
+        # launches go round-robin over four streams (default priority) joined to the main one
+        side = [torch.cuda.Stream() for _ in range(4)]
 
         def one_pass():
-            for Gs, Vs, Is in dev:
-                xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is,
-                                  stream=stream)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            order = sorted(range(len(dev)), key=lambda k: -dev[k][0].shape[1] * dev[k][0].shape[2] ** 2)
+            for j, k in enumerate(order):
+                Gs, Vs, Is = dev[k]
+                st = side[j % 4]
+                st.wait_event(ev)
+                xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is, stream=st)
+            for st in side:
+                done = torch.cuda.Event()
+                done.record(st)
+                stream.wait_event(done)
 
         one_pass()
         torch.cuda.synchronize()
