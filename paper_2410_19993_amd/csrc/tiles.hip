@@ -16,8 +16,8 @@
 //    word-line chain (reciprocal pivots, so only multiplications) into LDS;
 //  * thread t = 16 br + bc holds the BS x BS block (br, bc) of S_i in registers
 //    and inverts S_i in place with the others by Gauss-Jordan elimination
-//    without pivoting (S_i is SPD): per pivot step only row k and column k go
-//    through LDS (double-buffered, one barrier per step);
+//    without pivoting (S_i is SPD), two pivots per step: only the two pivot rows
+//    and columns go through LDS (double-buffered, one barrier per step);
 //  * the product H_i Y runs on the float64 matrix cores: wave w owns input
 //    vectors 64 w .. 64 w + 63 as four groups of 16, and keeps their forward
 //    results in the accumulator layout (item v of lane l = 16 q + c is row
@@ -39,6 +39,16 @@ constexpr int kTileThreads = 256;
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
+// 1 / x for the positive normal pivots here: the hardware reciprocal estimate
+// refined by two Newton-Raphson steps r <- r + r (1 - x r), each of which squares
+// the relative error (full double precision after the second)
+__device__ inline double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 struct TileArgs {
     int m, n, B;
     double g_wl, g_bl, g_src, g_sense;
@@ -54,7 +64,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
     constexpr int BS = NP / 16;                        // register block edge of the elimination
     constexpr int NT = NP / 16;                        // 16-row tiles of the product
     __shared__ __align__(16) double blk[2][NP * LD];
-    __shared__ __align__(16) double rowb[2][NP], colb[2][NP];
+    __shared__ __align__(16) double rowb[2][2][NP], colb[2][2][NP];   // [buffer][pivot][index]
     __shared__ double gr[NP], cr[NP], piv[NP], rpiv[NP];
     __shared__ int bad;
 
@@ -91,11 +101,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
         if (tid == 0) {
             double e = gr[0] + a.g_src;
             piv[0] = e + (n > 1 ? gw : 0.0);
-            rpiv[0] = 1.0 / piv[0];
+            rpiv[0] = recip(piv[0]);
             for (int j = 1; j < n; ++j) {
                 e = gr[j] + gw * e * rpiv[j - 1];
                 piv[j] = e + (j < n - 1 ? gw : 0.0);
-                rpiv[j] = 1.0 / piv[j];
+                rpiv[j] = recip(piv[j]);
             }
         }
         __syncthreads();
@@ -140,34 +150,62 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
                 if (bc == 0) cr[r] = (r < n) ? a.g_src * gr[r] * Tb[r * LD] : 0.0;
             }
         }
-        // ---- H_i = S_i^-1 (Gauss-Jordan, no pivoting) on the register blocks
-        for (int k = 0; k < n; ++k) {
-            const int kb = k & 1, kr = k / BS, ko = k % BS;
-            if (br == kr) {
+        // ---- H_i = S_i^-1 (Gauss-Jordan, no pivoting) on the register blocks, two pivots
+        // k, k+1 per step: P = S[K][K] (K = {k, k+1}) is inverted in closed form and
+        //   S[K][c] <- P^-1 S'[K][c],  S[r][c] <- S'[r][c] - S[r][K] P^-1 S'[K][c]  (r not in K)
+        // where S' is S with S[.][K] replaced by the identity columns; an odd n ends
+        // with one single pivot
+        for (int k = 0, step = 0; k < n; ++step) {
+            const int kb = step & 1, np2 = (k + 1 < n) ? 2 : 1;
 #pragma unroll
-                for (int jj = 0; jj < BS; ++jj)
+            for (int ii = 0; ii < BS; ++ii) {
+                const int r = BS * br + ii;
+                if (r == k || (np2 == 2 && r == k + 1)) {
 #pragma unroll
-                    for (int ii = 0; ii < BS; ++ii)
-                        if (ii == ko) rowb[kb][BS * bc + jj] = s[ii][jj];
+                    for (int jj = 0; jj < BS; ++jj) rowb[kb][r - k][BS * bc + jj] = s[ii][jj];
+                }
             }
-            if (bc == kr) {
-#pragma unroll
-                for (int ii = 0; ii < BS; ++ii)
-#pragma unroll
-                    for (int jj = 0; jj < BS; ++jj)
-                        if (jj == ko) colb[kb][BS * br + ii] = s[ii][jj];
-            }
-            __syncthreads();
-            const double p = rowb[kb][k];
-            if (tid == 0 && !(p > 0.0 && p <= 1e300)) bad = 1;
-            const double pinv = 1.0 / p;
-            double f[BS], nk[BS];
-#pragma unroll
-            for (int ii = 0; ii < BS; ++ii) f[ii] = colb[kb][BS * br + ii];
 #pragma unroll
             for (int jj = 0; jj < BS; ++jj) {
                 const int c = BS * bc + jj;
-                nk[jj] = (c == k ? 1.0 : rowb[kb][c]) * pinv;        // new row k
+                if (c == k || (np2 == 2 && c == k + 1)) {
+#pragma unroll
+                    for (int ii = 0; ii < BS; ++ii) colb[kb][c - k][BS * br + ii] = s[ii][jj];
+                }
+            }
+            __syncthreads();
+            // P^-1 = [[p00, p01], [p10, p11]]
+            double p00, p01, p10, p11;
+            if (np2 == 2) {
+                const double pa = rowb[kb][0][k], pb = rowb[kb][0][k + 1];
+                const double pc = rowb[kb][1][k], pd = rowb[kb][1][k + 1];
+                const double det = pa * pd - pb * pc;
+                if (tid == 0 && !(pa > 0.0 && det > 0.0 && det <= 1e300)) bad = 1;
+                const double rdet = recip(det);
+                p00 = pd * rdet;
+                p01 = -pb * rdet;
+                p10 = -pc * rdet;
+                p11 = pa * rdet;
+            } else {
+                const double pa = rowb[kb][0][k];
+                if (tid == 0 && !(pa > 0.0 && pa <= 1e300)) bad = 1;
+                p00 = recip(pa);
+                p01 = p10 = p11 = 0.0;
+            }
+            double f0[BS], f1[BS], n0[BS], n1[BS];
+#pragma unroll
+            for (int ii = 0; ii < BS; ++ii) {
+                f0[ii] = colb[kb][0][BS * br + ii];
+                f1[ii] = (np2 == 2) ? colb[kb][1][BS * br + ii] : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj) {
+                const int c = BS * bc + jj;
+                // column c of S'[K][.]: the identity inside K
+                const double u0 = (c == k) ? 1.0 : ((np2 == 2 && c == k + 1) ? 0.0 : rowb[kb][0][c]);
+                const double u1 = (np2 == 2) ? ((c == k) ? 0.0 : ((c == k + 1) ? 1.0 : rowb[kb][1][c])) : 0.0;
+                n0[jj] = p00 * u0 + p01 * u1;
+                n1[jj] = p10 * u0 + p11 * u1;
             }
 #pragma unroll
             for (int ii = 0; ii < BS; ++ii) {
@@ -175,9 +213,13 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
 #pragma unroll
                 for (int jj = 0; jj < BS; ++jj) {
                     const int c = BS * bc + jj;
-                    s[ii][jj] = (r == k) ? nk[jj] : ((c == k ? 0.0 : s[ii][jj]) - f[ii] * nk[jj]);
+                    const bool inK = (c == k) || (np2 == 2 && c == k + 1);
+                    s[ii][jj] = (r == k) ? n0[jj]
+                              : (np2 == 2 && r == k + 1) ? n1[jj]
+                              : ((inK ? 0.0 : s[ii][jj]) - f0[ii] * n0[jj] - f1[ii] * n1[jj]);
                 }
             }
+            k += np2;
         }
         // ---- H_i into LDS (T_i^-1 there is no longer needed)
         __syncthreads();
