@@ -98,3 +98,43 @@ def test_c4_tiles_in_bench_configuration():
             worst = max(worst, float(rel_err(I[k][rows], ref).max()))
     log(f"  max current rel err {worst:.3e}")
     assert worst <= TOL_FP64
+
+
+def test_tiles_in_a_captured_graph():
+    """Launches of several classes on forked streams, captured into one HIP graph and replayed
+    three times with eager work between the replays: every replay gives the eager bits."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    r = (2.5, 2.5, 50.0, 50.0)
+    shapes = [(3, 20, 16, 8), (2, 37, 40, 4), (4, 12, 64, 32)]
+    data = []
+    for k, (T, m, n, B) in enumerate(shapes):
+        G, V = _inputs(T, m, n, B, 90 + k)
+        data.append((torch.from_numpy(G).cuda(), torch.from_numpy(V).cuda(),
+                     torch.empty((T, B, n), dtype=torch.float64, device="cuda")))
+    eager = [xb.tiles_currents(Gd, Vd, *r).cpu().numpy() for Gd, Vd, _ in data]
+    log("case tiles graph capture: 3 classes on 2 forked streams")
+    side = [torch.cuda.Stream() for _ in range(2)]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        main = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(main)
+        for k, (Gd, Vd, Id) in enumerate(data):
+            st = side[k % 2]
+            st.wait_event(fork)
+            xb.tiles_currents(Gd, Vd, *r, out=Id, stream=st)
+        for st in side:
+            done = torch.cuda.Event()
+            done.record(st)
+            main.wait_event(done)
+    for rep in range(3):
+        for _, _, Id in data:
+            Id.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (_, _, Id) in enumerate(data):
+            assert np.array_equal(Id.cpu().numpy(), eager[k]), f"replay {rep}, class {k}"
+        _ = torch.ones(1000, device="cuda").sum().item()        # eager work between replays
