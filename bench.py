@@ -295,10 +295,19 @@ def main():
             graph.replay()
         torch.cuda.synchronize()
         ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+        # each class alone, HIP events on the launch stream
+        per_class = {}
+        for Gs, Vs, Is in dev:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            per_class[f"{Gs.shape[1]}x{Gs.shape[2]}"] = {"tiles": int(Gs.shape[0]), "ms": e0.elapsed_time(e1)}
         vecs = 256 * len(tl)
         log(f"tiles: {len(tl)} crossbars in {len(dev)} classes, {ms:.2f} ms per pass")
         return {"value": vecs / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms,
-                "ms_per_pass_graph_replay": ms_graph, "tiles": len(tl),
+                "ms_per_pass_graph_replay": ms_graph, "per_class": per_class, "tiles": len(tl),
                 "classes": len(dev), "tiles_per_s": len(tl) / (ms * 1e-3),
                 "workload": "c4 tiles with n_t <= 64 (seed 1004), 256 vectors each, currents only",
                 "algorithmic_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
