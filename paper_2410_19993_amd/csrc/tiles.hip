@@ -16,8 +16,8 @@
 //    word-line chain (reciprocal pivots, so only multiplications) into LDS;
 //  * thread t = 16 br + bc holds the BS x BS block (br, bc) of S_i in registers
 //    and inverts S_i in place with the others by Gauss-Jordan elimination
-//    without pivoting (S_i is SPD), two pivots per step: only the two pivot rows
-//    and columns go through LDS (double-buffered, one barrier per step);
+//    without pivoting (S_i is SPD), four pivots per step: only the four pivot
+//    rows and columns go through LDS (double-buffered, one barrier per step);
 //  * the product H_i Y runs on the float64 matrix cores: wave w owns input
 //    vectors 64 w .. 64 w + 63 as four groups of 16, and keeps their forward
 //    results in the accumulator layout (item v of lane l = 16 q + c is row
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
     constexpr int BS = NP / 16;                        // register block edge of the elimination
     constexpr int NT = NP / 16;                        // 16-row tiles of the product
     __shared__ __align__(16) double blk[2][NP * LD];
-    __shared__ __align__(16) double rowb[2][2][NP], colb[2][2][NP];   // [buffer][pivot][index]
+    __shared__ __align__(16) double rowb[2][4][NP], colb[2][4][NP];   // [buffer][pivot][index]
     __shared__ double gr[NP], cr[NP], piv[NP], rpiv[NP];
     __shared__ int bad;
 
@@ -150,17 +150,18 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
                 if (bc == 0) cr[r] = (r < n) ? a.g_src * gr[r] * Tb[r * LD] : 0.0;
             }
         }
-        // ---- H_i = S_i^-1 (Gauss-Jordan, no pivoting) on the register blocks, two pivots
-        // k, k+1 per step: P = S[K][K] (K = {k, k+1}) is inverted in closed form and
+        // ---- H_i = S_i^-1 (Gauss-Jordan, no pivoting) on the register blocks, four pivots
+        // K = {k .. k+3} per step: the 4 x 4 pivot block P = S[K][K] is inverted in
+        // registers by every thread, and
         //   S[K][c] <- P^-1 S'[K][c],  S[r][c] <- S'[r][c] - S[r][K] P^-1 S'[K][c]  (r not in K)
-        // where S' is S with S[.][K] replaced by the identity columns; an odd n ends
-        // with one single pivot
-        for (int k = 0, step = 0; k < n; ++step) {
-            const int kb = step & 1, np2 = (k + 1 < n) ? 2 : 1;
+        // where S' is S with S[.][K] replaced by the identity columns.  The padding is
+        // the identity, so blocks that reach past n stay exact.
+        for (int k = 0, step = 0; k < n; k += 4, ++step) {
+            const int kb = step & 1;
 #pragma unroll
             for (int ii = 0; ii < BS; ++ii) {
                 const int r = BS * br + ii;
-                if (r == k || (np2 == 2 && r == k + 1)) {
+                if (r >= k && r < k + 4) {
 #pragma unroll
                     for (int jj = 0; jj < BS; ++jj) rowb[kb][r - k][BS * bc + jj] = s[ii][jj];
                 }
@@ -168,58 +169,63 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
 #pragma unroll
             for (int jj = 0; jj < BS; ++jj) {
                 const int c = BS * bc + jj;
-                if (c == k || (np2 == 2 && c == k + 1)) {
+                if (c >= k && c < k + 4) {
 #pragma unroll
                     for (int ii = 0; ii < BS; ++ii) colb[kb][c - k][BS * br + ii] = s[ii][jj];
                 }
             }
             __syncthreads();
-            // P^-1 = [[p00, p01], [p10, p11]]
-            double p00, p01, p10, p11;
-            if (np2 == 2) {
-                const double pa = rowb[kb][0][k], pb = rowb[kb][0][k + 1];
-                const double pc = rowb[kb][1][k], pd = rowb[kb][1][k + 1];
-                const double det = pa * pd - pb * pc;
-                if (tid == 0 && !(pa > 0.0 && det > 0.0 && det <= 1e300)) bad = 1;
-                const double rdet = recip(det);
-                p00 = pd * rdet;
-                p01 = -pb * rdet;
-                p10 = -pc * rdet;
-                p11 = pa * rdet;
-            } else {
-                const double pa = rowb[kb][0][k];
-                if (tid == 0 && !(pa > 0.0 && pa <= 1e300)) bad = 1;
-                p00 = recip(pa);
-                p01 = p10 = p11 = 0.0;
-            }
-            double f0[BS], f1[BS], n0[BS], n1[BS];
+            double P[4][4];
 #pragma unroll
-            for (int ii = 0; ii < BS; ++ii) {
-                f0[ii] = colb[kb][0][BS * br + ii];
-                f1[ii] = (np2 == 2) ? colb[kb][1][BS * br + ii] : 0.0;
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) P[u][v] = rowb[kb][u][k + v];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double pv = P[t][t];
+                if (tid == 0 && !(pv > 0.0 && pv <= 1e300)) bad = 1;
+                const double rp = recip(pv);
+                double row[4], col[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    row[v] = (v == t ? 1.0 : P[t][v]) * rp;
+                    col[v] = P[v][t];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) P[u][v] = (u == t) ? row[v] : ((v == t ? 0.0 : P[u][v]) - col[u] * row[v]);
             }
+            double f[4][BS], nn[4][BS], keep[BS];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int ii = 0; ii < BS; ++ii) f[t][ii] = colb[kb][t][BS * br + ii];
 #pragma unroll
             for (int jj = 0; jj < BS; ++jj) {
-                const int c = BS * bc + jj;
-                // column c of S'[K][.]: the identity inside K
-                const double u0 = (c == k) ? 1.0 : ((np2 == 2 && c == k + 1) ? 0.0 : rowb[kb][0][c]);
-                const double u1 = (np2 == 2) ? ((c == k) ? 0.0 : ((c == k + 1) ? 1.0 : rowb[kb][1][c])) : 0.0;
-                n0[jj] = p00 * u0 + p01 * u1;
-                n1[jj] = p10 * u0 + p11 * u1;
+                const int c = BS * bc + jj, ck = c - k;
+                const bool inK = ck >= 0 && ck < 4;
+                double u[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) u[t] = inK ? (ck == t ? 1.0 : 0.0) : rowb[kb][t][c];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) nn[t][jj] = P[t][0] * u[0] + P[t][1] * u[1] + P[t][2] * u[2] + P[t][3] * u[3];
+                keep[jj] = inK ? 0.0 : 1.0;
             }
 #pragma unroll
             for (int ii = 0; ii < BS; ++ii) {
-                const int r = BS * br + ii;
+                const int rk = BS * br + ii - k;
+                const bool inK = rk >= 0 && rk < 4;
 #pragma unroll
                 for (int jj = 0; jj < BS; ++jj) {
-                    const int c = BS * bc + jj;
-                    const bool inK = (c == k) || (np2 == 2 && c == k + 1);
-                    s[ii][jj] = (r == k) ? n0[jj]
-                              : (np2 == 2 && r == k + 1) ? n1[jj]
-                              : ((inK ? 0.0 : s[ii][jj]) - f0[ii] * n0[jj] - f1[ii] * n1[jj]);
+                    double own = nn[0][jj];
+#pragma unroll
+                    for (int t = 1; t < 4; ++t) own = (rk == t) ? nn[t][jj] : own;
+                    const double upd = s[ii][jj] * keep[jj] - f[0][ii] * nn[0][jj] - f[1][ii] * nn[1][jj] -
+                                       f[2][ii] * nn[2][jj] - f[3][ii] * nn[3][jj];
+                    s[ii][jj] = inK ? own : upd;
                 }
             }
-            k += np2;
         }
         // ---- H_i into LDS (T_i^-1 there is no longer needed)
         __syncthreads();
