@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-tiles", action="store_true", help="skip the batched small-tile leg")
     ap.add_argument("--tiles-large", action="store_true",
                     help="also time the tiles workload's n_t >= 128 half through plans (several seconds)")
+    ap.add_argument("--tile-lanes", type=int, default=3,
+                    help="concurrent plans (stream + host thread each) for the n_t >= 128 tiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -313,41 +315,26 @@ def main():
                 "algorithmic_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
                 "frac_of_fp64_peak": flops / (ms * 1e-3) / PEAK_FP64_MFMA}
 
-    def run_tiles_large():
-        """The tiles workload's crossbars with n_t >= 128, each through a plan of its
-        class (float64, currents only, all 256 vectors), one after another."""
+    def run_tiles_large(lanes):
+        """The tiles workload's crossbars with n_t >= 128 through plans (float64, currents
+        only, all 256 vectors): `lanes` plans at a time, each on a stream and host thread
+        of its own (PlanLanes), one plan per shape and lane."""
         tl = [t for t in workloads.c4() if t.G.shape[1] >= 128]
         g4 = workloads.C4_GEOM
-        plans, Vd, Id = {}, {}, {}
-        for t in tl:
-            shp = t.G.shape
-            if shp not in plans:
-                plans[shp] = xb.Plan(shp[0], shp[1], g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], "fp64",
-                                     max_batch=256, stream=stream)
-                Id[shp] = torch.empty((256, shp[1]), dtype=torch.float64, device="cuda")
         Gd = [torch.from_numpy(t.G).cuda() for t in tl]
         Vd = [torch.from_numpy(np.ascontiguousarray(t.V)).cuda() for t in tl]
-
-        def solve(k):
-            p = plans[tl[k].G.shape]
-            p.assemble(Gd[k])
-            p.factor()
-            p.solve_batch(Vd[k], None)
-            p.currents(Id[tl[k].G.shape])
-
-        for shp in plans:                               # warm every class once
-            solve(next(k for k in range(len(tl)) if tl[k].G.shape == shp))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(len(tl)):
-            solve(k)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
-        for p in plans.values():
-            p.check()
-            p.close()
-        log(f"tiles (n >= 128): {len(tl)} crossbars through plans in {ms:.0f} ms")
+        Id = [torch.empty((256, t.G.shape[1]), dtype=torch.float64, device="cuda") for t in tl]
+        with xb.PlanLanes(g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], lanes=lanes, max_batch=256) as pl:
+            pl.currents(Gd, Vd, Id)                     # creates and warms every plan
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl.currents(Gd, Vd, Id)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            pl.check()
+        log(f"tiles (n >= 128): {len(tl)} crossbars through {lanes} plan lanes in {ms:.0f} ms")
         return {"value": 256 * len(tl) / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms, "tiles": len(tl),
+                "lanes": lanes,
                 "workload": "c4 tiles with n_t >= 128 (seed 1004), 256 vectors each, currents only, plan path"}
 
     ms64, tm, info64, err64 = run("fp64", args.steps, args.warmup)
@@ -404,7 +391,7 @@ def main():
     if not args.no_tiles:
         result["tiles"] = run_tiles(args.steps)
     if args.tiles_large:
-        result["tiles_large"] = run_tiles_large()
+        result["tiles_large"] = run_tiles_large(args.tile_lanes)
     if not args.no_fp32_ir:
         # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
         # refinement stops once its error estimate is below 1e-10 (the error actually
