@@ -257,6 +257,69 @@ xbar_status xbar_get_timing(xbar_plan plan, xbar_timing* out, int32_t reset);
 /* Synchronise and free every device buffer of the plan.  NULL is a no-op. */
 xbar_status xbar_destroy(xbar_plan plan);
 
+/*
+ * ---- Learned current surrogate ------------------------------------------
+ *
+ * A small convolutional network (an extension: the paper has no learned
+ * part) predicts the relative parasitic correction of each bit-line current,
+ * delta_j = (I_j - I0_j) / I0_j with I0 = G^T V, the currents of the same
+ * crossbar without wire resistance (the zero-resistance limit of the nodal
+ * equations of Sec. II.A).  Its training targets come from the exact solver
+ * above, which stays the reference for its error.  These calls are the
+ * network's steps; the caller owns every buffer (device memory, float32
+ * activations [B][C][H][W] with H = m rows and W = n columns, weights
+ * [O][C][3][3], biases [O]).  All convolutions are 3 x 3 cross-correlations
+ * with zero padding of one crosspoint.  Each call checks its arguments on the
+ * host (XBAR_ERR_ARG: a size out of range, a NULL pointer, an output that
+ * overlaps an input), queues its kernels on `stream` and returns without
+ * waiting; XBAR_ERR_DEVICE reports a failed launch.  Sizes: 1 <= B <= 65535,
+ * H, W >= 1, 1 <= C, O <= XBAR_SG_MAX_CHANNELS.
+ */
+#define XBAR_SG_MAX_CHANNELS 32
+
+/* X [B][5][m][n] float32 from G [B][m][n] (S, > 0), V [B][m] (V), r [B] (ohm,
+ * the segment resistance): log10(G) + 5, 2 V_i, (r - 3) / 2, and the column
+ * and row positions 2 j / (n - 1) - 1 and 2 i / (m - 1) - 1 (0 for n or m = 1). */
+xbar_status xbar_sg_features(int32_t B, int32_t m, int32_t n, const double* G, const double* V, const double* r,
+                             float* X, void* stream);
+
+/* y[b][o][p][q] = bias[o] + sum_{c,dy,dx} w[o][c][dy][dx] x[b][c][p+dy-1][q+dx-1],
+ * then max(y, 0) if relu != 0.  x [B][C][H][W], y [B][O][H][W]. */
+xbar_status xbar_sg_conv_forward(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, int32_t relu,
+                                 const float* x, const float* w, const float* bias, float* y, void* stream);
+
+/* Input gradient of a convolution: with g = gy, multiplied by [ymask > 0] when
+ * ymask (the layer's ReLU output, same shape as gy) is not NULL,
+ * gx[b][c][p][q] = sum_{o,dy,dx} w[o][c][dy][dx] g[b][o][p-dy+1][q-dx+1]. */
+xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* gy,
+                                       const float* ymask, const float* w, float* gx, void* stream);
+
+/* Weight and bias gradients, g masked as above: gw[o][c][dy][dx] = sum_{b,p,q}
+ * g[b][o][p][q] x[b][c][p+dy-1][q+dx-1], gb[o] = sum g[b][o][p][q].  work:
+ * at least xbar_sg_workspace_floats(C, O) floats (partial sums, summed in a
+ * fixed order, so the result is deterministic). */
+xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
+                                         const float* gy, const float* ymask, float* gw, float* gb, float* work,
+                                         int64_t work_floats, void* stream);
+
+/* Floats of workspace xbar_sg_conv_backward_weight needs (-1 for bad C, O). */
+int64_t xbar_sg_workspace_floats(int32_t C, int32_t O);
+
+/* Column readout and squared-error loss of the last map Y [B][m][n]:
+ * yhat_j = mean_i Y[b][i][j], e = yhat - delta (delta [B][n] float64),
+ * gY[b][i][j] = 2 e_j / (B n m) (the gradient of mean(e^2)), err2[b] = sum_j e_j^2. */
+xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, float* gY,
+                                 double* err2, void* stream);
+
+/* One Adam step (bias-corrected, step t >= 1) over count float32 parameters p
+ * with gradients g and moments m1, m2, all updated in place. */
+xbar_status xbar_sg_adam(int64_t count, float* p, const float* g, float* m1, float* m2, double lr, double b1,
+                         double b2, double eps, int32_t t, void* stream);
+
+/* Surrogate currents I [B][n] float64 = (G^T V)_j (1 + mean_i Y[b][i][j]). */
+xbar_status xbar_sg_predict(int32_t B, int32_t m, int32_t n, const float* Y, const double* G, const double* V,
+                            double* I, void* stream);
+
 /* Static, NUL-terminated name of a status code. */
 const char* xbar_status_string(xbar_status s);
 

@@ -87,11 +87,23 @@ def lib() -> ctypes.CDLL:
         L.xbar_set_factor_method.argtypes = [vp, ctypes.c_int]
         L.xbar_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int32]
         L.xbar_status_string.argtypes = [ctypes.c_int]
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.xbar_sg_features.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_forward.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_backward_data.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_backward_weight.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.xbar_sg_workspace_floats.argtypes = [i32, i32]
+        L.xbar_sg_workspace_floats.restype = i64
+        L.xbar_sg_readout_loss.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_adam.argtypes = [i64, vp, vp, vp, vp, f64, f64, f64, f64, i32, vp]
+        L.xbar_sg_predict.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
         L.xbar_status_string.restype = ctypes.c_char_p
         for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
                   "xbar_get_timing", "xbar_set_factor_method", "xbar_transfer",
-                  "xbar_transfer_apply", "xbar_tiles_currents"):
+                  "xbar_transfer_apply", "xbar_tiles_currents", "xbar_sg_features", "xbar_sg_conv_forward",
+                  "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_readout_loss",
+                  "xbar_sg_adam", "xbar_sg_predict"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,3 +191,47 @@ def xbar_get_timing(plan, reset: bool = False) -> Timing:
 
 def xbar_destroy(plan) -> None:
     _check("xbar_destroy", lib().xbar_destroy(plan))
+
+
+# ---- learned current surrogate (argument marshalling only) -------------------------
+
+def _s(stream):
+    return ctypes.c_void_p(stream or 0)
+
+
+def xbar_sg_features(B, m, n, G, V, r, X, stream=None) -> None:
+    _check("xbar_sg_features", lib().xbar_sg_features(B, m, n, _ptr(G), _ptr(V), _ptr(r), _ptr(X), _s(stream)))
+
+
+def xbar_sg_conv_forward(B, H, W, C, O, relu, x, w, b, y, stream=None) -> None:
+    _check("xbar_sg_conv_forward", lib().xbar_sg_conv_forward(B, H, W, C, O, int(bool(relu)), _ptr(x), _ptr(w),
+                                                              _ptr(b), _ptr(y), _s(stream)))
+
+
+def xbar_sg_conv_backward_data(B, H, W, C, O, gy, ymask, w, gx, stream=None) -> None:
+    _check("xbar_sg_conv_backward_data", lib().xbar_sg_conv_backward_data(B, H, W, C, O, _ptr(gy), _ptr(ymask),
+                                                                          _ptr(w), _ptr(gx), _s(stream)))
+
+
+def xbar_sg_conv_backward_weight(B, H, W, C, O, x, gy, ymask, gw, gb, work, stream=None) -> None:
+    _check("xbar_sg_conv_backward_weight",
+           lib().xbar_sg_conv_backward_weight(B, H, W, C, O, _ptr(x), _ptr(gy), _ptr(ymask), _ptr(gw), _ptr(gb),
+                                              _ptr(work), int(work.numel()), _s(stream)))
+
+
+def xbar_sg_workspace_floats(C, O) -> int:
+    return int(lib().xbar_sg_workspace_floats(C, O))
+
+
+def xbar_sg_readout_loss(B, m, n, Y, delta, gY, err2, stream=None) -> None:
+    _check("xbar_sg_readout_loss", lib().xbar_sg_readout_loss(B, m, n, _ptr(Y), _ptr(delta), _ptr(gY), _ptr(err2),
+                                                              _s(stream)))
+
+
+def xbar_sg_adam(p, g, m1, m2, lr, b1, b2, eps, t, stream=None) -> None:
+    _check("xbar_sg_adam", lib().xbar_sg_adam(int(p.numel()), _ptr(p), _ptr(g), _ptr(m1), _ptr(m2), float(lr),
+                                              float(b1), float(b2), float(eps), int(t), _s(stream)))
+
+
+def xbar_sg_predict(B, m, n, Y, G, V, I, stream=None) -> None:
+    _check("xbar_sg_predict", lib().xbar_sg_predict(B, m, n, _ptr(Y), _ptr(G), _ptr(V), _ptr(I), _s(stream)))

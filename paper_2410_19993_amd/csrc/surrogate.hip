@@ -1,0 +1,420 @@
+// Learned current surrogate: features, 3x3 convolutions (forward, input
+// gradient, weight gradient), column readout and loss, Adam, prediction.
+//
+// A small convolutional network over one crossbar's conductance map and inputs
+// predicts the relative parasitic correction of each bit-line current,
+// delta_j = (I_j - I0_j) / I0_j with I0 = G^T V, the currents without wire
+// resistance (the zero-resistance limit of the nodal equations of Sec. II.A).
+// The exact solver supplies the training targets and remains the reference.
+//
+// Layout: activations are float32 [B][C][H][W] (H = m rows, W = n columns);
+// weights [O][C][3][3], biases [O].  All convolutions use zero padding of one
+// crosspoint, so H and W are kept.  Every kernel handles any H, W >= 1 and
+// C, O <= 32; a workgroup covers a 16 x 16 tile of crosspoints.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "xbar.h"
+
+namespace {
+
+constexpr int kMaxCh = XBAR_SG_MAX_CHANNELS;
+constexpr int kParts = 256;            // workgroups of the weight-gradient pass (partial sums)
+constexpr int kPer = (kMaxCh * kMaxCh * 9 + 255) / 256;
+
+__device__ __forceinline__ bool in_grid(int p, int q, int H, int W) { return p >= 0 && p < H && q >= 0 && q < W; }
+
+// X[b][0..4][i][j] = log10(G) + 5, 2 V_i, (r - 3) / 2, column and row position in [-1, 1].
+__global__ void sg_features_kernel(int B, int m, int n, const double* __restrict__ G, const double* __restrict__ V,
+                                   const double* __restrict__ r, float* __restrict__ X)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)m * n;
+    if (e >= (int64_t)B * mn) return;
+    const int b = (int)(e / mn);
+    const int i = (int)((e % mn) / n), j = (int)(e % n);
+    float* xb = X + (int64_t)b * 5 * mn + (int64_t)i * n + j;
+    xb[0] = (float)(log10(G[e]) + 5.0);
+    xb[mn] = (float)(2.0 * V[(int64_t)b * m + i]);
+    xb[2 * mn] = (float)((r[b] - 3.0) * 0.5);
+    xb[3 * mn] = n > 1 ? (float)(2.0 * j / (n - 1) - 1.0) : 0.0f;
+    xb[4 * mn] = m > 1 ? (float)(2.0 * i / (m - 1) - 1.0) : 0.0f;
+}
+
+// y[b][o] = bias[o] + sum_{c, dy, dx} w[o][c][dy][dx] x[b][c][p + dy - 1][q + dx - 1]  (ReLU optional).
+// One thread per output crosspoint holds all O sums; the weights sit in LDS.
+template <bool RELU>
+__global__ __launch_bounds__(256) void sg_conv_fwd_kernel(int H, int W, int C, int O, const float* __restrict__ x,
+                                                          const float* __restrict__ w,
+                                                          const float* __restrict__ bias, float* __restrict__ y)
+{
+    __shared__ float ws[kMaxCh * kMaxCh * 9];
+    __shared__ float bs[kMaxCh];
+    for (int e = threadIdx.x; e < O * C * 9; e += 256) ws[e] = w[e];
+    if (threadIdx.x < O) bs[threadIdx.x] = bias[threadIdx.x];
+    __syncthreads();
+    const int tw = (W + 15) / 16;
+    const int p = (blockIdx.x / tw) * 16 + (threadIdx.x >> 4);
+    const int q = (blockIdx.x % tw) * 16 + (threadIdx.x & 15);
+    if (p >= H || q >= W) return;
+    const int64_t hw = (int64_t)H * W;
+    const float* xb = x + (int64_t)blockIdx.y * C * hw;
+    float acc[kMaxCh];
+#pragma unroll
+    for (int o = 0; o < kMaxCh; ++o) acc[o] = 0.0f;
+    for (int c = 0; c < C; ++c) {
+        const float* xc = xb + c * hw;
+        float v[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = p + t / 3 - 1, xx = q + t % 3 - 1;
+            v[t] = in_grid(yy, xx, H, W) ? xc[(int64_t)yy * W + xx] : 0.0f;
+        }
+        const float* wc = ws + c * 9;
+#pragma unroll
+        for (int o = 0; o < kMaxCh; ++o) {
+            if (o < O) {
+                float s = acc[o];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) s = fmaf(wc[o * C * 9 + t], v[t], s);
+                acc[o] = s;
+            }
+        }
+    }
+    float* yb = y + (int64_t)blockIdx.y * O * hw + (int64_t)p * W + q;
+#pragma unroll
+    for (int o = 0; o < kMaxCh; ++o) {
+        if (o < O) {
+            float s = acc[o] + bs[o];
+            if (RELU) s = s > 0.0f ? s : 0.0f;
+            yb[o * hw] = s;
+        }
+    }
+}
+
+// Gradient of the layer's output g = gy (times [ymask > 0] when the layer has a
+// ReLU) with respect to its input:
+//     gx[b][c][p][q] = sum_{o, dy, dx} w[o][c][dy][dx] g[b][o][p - dy + 1][q - dx + 1].
+__global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int C, int O,
+                                                               const float* __restrict__ gy,
+                                                               const float* __restrict__ ymask,
+                                                               const float* __restrict__ w, float* __restrict__ gx)
+{
+    __shared__ float ws[kMaxCh * kMaxCh * 9];
+    for (int e = threadIdx.x; e < O * C * 9; e += 256) ws[e] = w[e];
+    __syncthreads();
+    const int tw = (W + 15) / 16;
+    const int p = (blockIdx.x / tw) * 16 + (threadIdx.x >> 4);
+    const int q = (blockIdx.x % tw) * 16 + (threadIdx.x & 15);
+    if (p >= H || q >= W) return;
+    const int64_t hw = (int64_t)H * W;
+    const int64_t base = (int64_t)blockIdx.y * O * hw;
+    float acc[kMaxCh];
+#pragma unroll
+    for (int c = 0; c < kMaxCh; ++c) acc[c] = 0.0f;
+    for (int o = 0; o < O; ++o) {
+        const float* go = gy + base + o * hw;
+        const float* mo = ymask ? ymask + base + o * hw : nullptr;
+        float v[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = p - t / 3 + 1, xx = q - t % 3 + 1;
+            float g = 0.0f;
+            if (in_grid(yy, xx, H, W)) {
+                const int64_t off = (int64_t)yy * W + xx;
+                g = go[off];
+                if (mo && !(mo[off] > 0.0f)) g = 0.0f;
+            }
+            v[t] = g;
+        }
+        const float* wo = ws + o * C * 9;
+#pragma unroll
+        for (int c = 0; c < kMaxCh; ++c) {
+            if (c < C) {
+                float s = acc[c];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) s = fmaf(wo[c * 9 + t], v[t], s);
+                acc[c] = s;
+            }
+        }
+    }
+    float* gb = gx + (int64_t)blockIdx.y * C * hw + (int64_t)p * W + q;
+#pragma unroll
+    for (int c = 0; c < kMaxCh; ++c)
+        if (c < C) gb[c * hw] = acc[c];
+}
+
+// Partial weight and bias gradients: workgroup k sums, over the 16 x 16 tiles
+// k, k + kParts, ..., gw[o][c][dy][dx] = sum g[b][o][p][q] x[b][c][p + dy - 1][q + dx - 1]
+// and gb[o] = sum g[b][o][p][q] into part[k][0 .. O C 9 + O).  The tile of g and
+// the tile of x with its one-crosspoint halo are staged in LDS; thread t owns
+// entries t, t + 256, ... of gw.
+__global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, int W, int C, int O,
+                                                                 const float* __restrict__ x,
+                                                                 const float* __restrict__ gy,
+                                                                 const float* __restrict__ ymask,
+                                                                 float* __restrict__ part)
+{
+    __shared__ float gs[kMaxCh * 256];          // [o][16 x 16]
+    __shared__ float xs[kMaxCh * 18 * 18];      // [c][18 x 18]
+    const int ne = O * C * 9;
+    const int tw = (W + 15) / 16, th = (H + 15) / 16;
+    const int tiles = B * th * tw;
+    const int64_t hw = (int64_t)H * W;
+    float acc[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) acc[k] = 0.0f;
+    float accb = 0.0f;
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int b = t / (th * tw), r = t % (th * tw);
+        const int p0 = (r / tw) * 16, q0 = (r % tw) * 16;
+        __syncthreads();                        // the previous tile's LDS reads are done
+        for (int e = threadIdx.x; e < O * 256; e += 256) {
+            const int o = e >> 8, p = p0 + ((e & 255) >> 4), q = q0 + (e & 15);
+            float g = 0.0f;
+            if (p < H && q < W) {
+                const int64_t off = ((int64_t)b * O + o) * hw + (int64_t)p * W + q;
+                g = gy[off];
+                if (ymask && !(ymask[off] > 0.0f)) g = 0.0f;
+            }
+            gs[e] = g;
+        }
+        for (int e = threadIdx.x; e < C * 324; e += 256) {
+            const int c = e / 324, k = e % 324;
+            const int p = p0 + k / 18 - 1, q = q0 + k % 18 - 1;
+            xs[e] = in_grid(p, q, H, W) ? x[((int64_t)b * C + c) * hw + (int64_t)p * W + q] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            if (e < ne) {
+                const int o = e / (C * 9), c = (e / 9) % C, tap = e % 9;
+                const float* go = gs + o * 256;
+                const float* xc = xs + c * 324 + (tap / 3) * 18 + tap % 3;
+                float s = 0.0f;
+                for (int pr = 0; pr < 16; ++pr)
+#pragma unroll
+                    for (int pc = 0; pc < 16; ++pc) s = fmaf(go[pr * 16 + pc], xc[pr * 18 + pc], s);
+                acc[k] += s;
+            }
+        }
+        if (threadIdx.x < O) {
+            float s = 0.0f;
+            for (int e = 0; e < 256; ++e) s += gs[threadIdx.x * 256 + e];
+            accb += s;
+        }
+    }
+    float* pw = part + (int64_t)blockIdx.x * (ne + O);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < ne) pw[e] = acc[k];
+    }
+    if (threadIdx.x < O) pw[ne + threadIdx.x] = accb;
+}
+
+// gw[e] = sum over the partials in workgroup order (deterministic); e >= ne: gb.
+__global__ void sg_reduce_parts_kernel(int nparts, int ne, int O, const float* __restrict__ part,
+                                       float* __restrict__ gw, float* __restrict__ gb)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne + O) return;
+    float s = 0.0f;
+    for (int k = 0; k < nparts; ++k) s += part[(int64_t)k * (ne + O) + e];
+    if (e < ne) gw[e] = s;
+    else gb[e - ne] = s;
+}
+
+// yhat_j = mean_i Y[b][i][j]; e_j = yhat_j - delta_j; gY[b][i][j] = 2 e_j / (B n m);
+// err2[b] = sum_j e_j^2.  One workgroup per sample.
+__global__ __launch_bounds__(256) void sg_readout_loss_kernel(int B, int m, int n, const float* __restrict__ Y,
+                                                              const double* __restrict__ delta,
+                                                              float* __restrict__ gY, double* __restrict__ err2)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const float* yb = Y + (int64_t)b * m * n;
+    float* gb = gY + (int64_t)b * m * n;
+    const double scale = 2.0 / ((double)B * n * m);
+    double e2 = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += yb[(int64_t)i * n + j];
+        const double e = s / m - delta[(int64_t)b * n + j];
+        e2 += e * e;
+        const float g = (float)(scale * e);
+        for (int i = 0; i < m; ++i) gb[(int64_t)i * n + j] = g;
+    }
+    red[threadIdx.x] = e2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) err2[b] = red[0];
+}
+
+// Adam with bias correction; c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ void sg_adam_kernel(int64_t count, float* __restrict__ p, const float* __restrict__ g,
+                               float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float b2,
+                               float eps, float c1, float c2)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const float ge = g[e];
+    const float a = b1 * m1[e] + (1.0f - b1) * ge;
+    const float v = b2 * m2[e] + (1.0f - b2) * ge * ge;
+    m1[e] = a;
+    m2[e] = v;
+    p[e] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// I[b][j] = (sum_i G[b][i][j] V[b][i]) (1 + mean_i Y[b][i][j]).
+__global__ void sg_predict_kernel(int B, int m, int n, const float* __restrict__ Y, const double* __restrict__ G,
+                                  const double* __restrict__ V, double* __restrict__ I)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (j >= n) return;
+    const double* gb = G + (int64_t)b * m * n;
+    const float* yb = Y + (int64_t)b * m * n;
+    const double* vb = V + (int64_t)b * m;
+    double i0 = 0.0, s = 0.0;
+    for (int i = 0; i < m; ++i) {
+        i0 += gb[(int64_t)i * n + j] * vb[i];
+        s += yb[(int64_t)i * n + j];
+    }
+    I[(int64_t)b * n + j] = i0 * (1.0 + s / m);
+}
+
+bool shape_ok(int32_t B, int32_t H, int32_t W) { return B >= 1 && B <= 65535 && H >= 1 && W >= 1; }
+bool ch_ok(int32_t C, int32_t O) { return C >= 1 && C <= kMaxCh && O >= 1 && O <= kMaxCh; }
+
+// [a, a + na) and [b, b + nb) share a byte
+bool overlap(const void* a, int64_t na, const void* b, int64_t nb)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + (uintptr_t)nb && y < x + (uintptr_t)na;
+}
+
+xbar_status launched()
+{
+    if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
+    return XBAR_OK;
+}
+
+dim3 tile_grid(int B, int H, int W) { return dim3(((H + 15) / 16) * ((W + 15) / 16), B); }
+
+}  // namespace
+
+extern "C" {
+
+int64_t xbar_sg_workspace_floats(int32_t C, int32_t O)
+{
+    if (!ch_ok(C, O)) return -1;
+    return (int64_t)kParts * (O * C * 9 + O);
+}
+
+xbar_status xbar_sg_features(int32_t B, int32_t m, int32_t n, const double* G, const double* V, const double* r,
+                             float* X, void* hip_stream)
+{
+    if (!shape_ok(B, m, n) || !G || !V || !r || !X) return XBAR_ERR_ARG;
+    const int64_t total = (int64_t)B * m * n;
+    if (overlap(X, total * 5 * 4, G, total * 8) || overlap(X, total * 5 * 4, V, (int64_t)B * m * 8) ||
+        overlap(X, total * 5 * 4, r, (int64_t)B * 8))
+        return XBAR_ERR_ARG;
+    hipLaunchKernelGGL(sg_features_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(hip_stream), B, m, n, G, V, r, X);
+    return launched();
+}
+
+xbar_status xbar_sg_conv_forward(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, int32_t relu, const float* x,
+                                 const float* w, const float* bias, float* y, void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !x || !w || !bias || !y) return XBAR_ERR_ARG;
+    const int64_t hw = (int64_t)H * W;
+    if (overlap(y, (int64_t)B * O * hw * 4, x, (int64_t)B * C * hw * 4) ||
+        overlap(y, (int64_t)B * O * hw * 4, w, (int64_t)O * C * 36) || overlap(y, (int64_t)B * O * hw * 4, bias, O * 4))
+        return XBAR_ERR_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (relu)
+        hipLaunchKernelGGL(sg_conv_fwd_kernel<true>, tile_grid(B, H, W), dim3(256), 0, s, H, W, C, O, x, w, bias, y);
+    else
+        hipLaunchKernelGGL(sg_conv_fwd_kernel<false>, tile_grid(B, H, W), dim3(256), 0, s, H, W, C, O, x, w, bias, y);
+    return launched();
+}
+
+xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* gy,
+                                       const float* ymask, const float* w, float* gx, void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !gy || !w || !gx) return XBAR_ERR_ARG;
+    const int64_t hw = (int64_t)H * W, nx = (int64_t)B * C * hw * 4, ny = (int64_t)B * O * hw * 4;
+    if (overlap(gx, nx, gy, ny) || (ymask && overlap(gx, nx, ymask, ny)) || overlap(gx, nx, w, (int64_t)O * C * 36))
+        return XBAR_ERR_ARG;
+    hipLaunchKernelGGL(sg_conv_bwd_data_kernel, tile_grid(B, H, W), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(hip_stream), H, W, C, O, gy, ymask, w, gx);
+    return launched();
+}
+
+xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
+                                         const float* gy, const float* ymask, float* gw, float* gb, float* work,
+                                         int64_t work_floats, void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !x || !gy || !gw || !gb || !work) return XBAR_ERR_ARG;
+    const int ne = O * C * 9;
+    const int64_t tiles = (int64_t)B * ((H + 15) / 16) * ((W + 15) / 16);
+    const int nparts = (int)(tiles < kParts ? tiles : kParts);
+    if (work_floats < (int64_t)nparts * (ne + O)) return XBAR_ERR_ARG;
+    const int64_t nw = (int64_t)nparts * (ne + O) * 4;
+    if (overlap(work, nw, gw, ne * 4) || overlap(work, nw, gb, O * 4) || overlap(gw, ne * 4, gb, O * 4))
+        return XBAR_ERR_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(256), 0, s, B, H, W, C, O, x, gy, ymask, work);
+    if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
+    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 255) / 256), dim3(256), 0, s, nparts, ne, O, work, gw,
+                       gb);
+    return launched();
+}
+
+xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, float* gY,
+                                 double* err2, void* hip_stream)
+{
+    if (!shape_ok(B, m, n) || !Y || !delta || !gY || !err2) return XBAR_ERR_ARG;
+    const int64_t ny = (int64_t)B * m * n * 4;
+    if (overlap(gY, ny, Y, ny) || overlap(gY, ny, delta, (int64_t)B * n * 8) || overlap(err2, (int64_t)B * 8, gY, ny))
+        return XBAR_ERR_ARG;
+    hipLaunchKernelGGL(sg_readout_loss_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream), B, m,
+                       n, Y, delta, gY, err2);
+    return launched();
+}
+
+xbar_status xbar_sg_adam(int64_t count, float* p, const float* g, float* m1, float* m2, double lr, double b1,
+                         double b2, double eps, int32_t t, void* hip_stream)
+{
+    if (count < 1 || !p || !g || !m1 || !m2 || t < 1 || !(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) ||
+        !(eps > 0))
+        return XBAR_ERR_ARG;
+    const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+    hipLaunchKernelGGL(sg_adam_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(hip_stream), count, p, g, m1, m2, (float)lr, (float)b1,
+                       (float)b2, (float)eps, (float)c1, (float)c2);
+    return launched();
+}
+
+xbar_status xbar_sg_predict(int32_t B, int32_t m, int32_t n, const float* Y, const double* G, const double* V,
+                            double* I, void* hip_stream)
+{
+    if (!shape_ok(B, m, n) || !Y || !G || !V || !I) return XBAR_ERR_ARG;
+    const int64_t ni = (int64_t)B * n * 8;
+    if (overlap(I, ni, Y, (int64_t)B * m * n * 4) || overlap(I, ni, G, (int64_t)B * m * n * 8) ||
+        overlap(I, ni, V, (int64_t)B * m * 8))
+        return XBAR_ERR_ARG;
+    hipLaunchKernelGGL(sg_predict_kernel, dim3((n + 255) / 256, B), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(hip_stream), B, m, n, Y, G, V, I);
+    return launched();
+}
+
+}  // extern "C"

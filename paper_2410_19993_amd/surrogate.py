@@ -1,0 +1,221 @@
+"""Learned current surrogate: a small convolutional network, trained on solver output.
+
+The network predicts the relative parasitic correction of each bit-line current,
+delta_j = (I_j - I0_j) / I0_j, where I0 = G^T V are the currents without wire
+resistance (the zero-resistance limit of the nodal equations of Sec. II.A), so
+that the surrogate's currents are I0 (1 + yhat).  The exact solver (Plan,
+PlanLanes) produces the training targets and stays the reference for the error.
+
+Network: 5 features per crosspoint (log10 G + 5, 2 V_i, (r - 3) / 2, column and
+row position), four 3 x 3 convolutions 5 -> C -> C -> C -> 1 with ReLU after the
+first three, and the mean over rows of the last map as yhat_j.  Loss: mean
+squared error of yhat against delta; optimizer: Adam.  Every step (features,
+convolutions, their gradients, readout, loss, update, prediction) runs in the
+library's kernels (xbar_sg_*); torch only holds the device buffers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from .lanes import PlanLanes
+
+N_FEATURES = 5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Surrogate:
+    """Weights, Adam state and activation buffers of the surrogate on the current device.
+
+    channels: width C of the hidden layers (<= 32).  seed: weight initialisation
+    (He-normal weights, zero biases).  zero_last: start the last layer at zero, so
+    that the untrained network predicts the ideal currents G^T V exactly."""
+
+    def __init__(self, channels: int = 32, seed: int = 0, lr: float = 1e-3, betas=(0.9, 0.999),
+                 eps: float = 1e-8, zero_last: bool = True):
+        torch = _torch()
+        if not 1 <= channels <= 32:
+            raise ValueError("channels must be in [1, 32]")
+        self.C = int(channels)
+        self.dims = [N_FEATURES, self.C, self.C, self.C, 1]
+        self.lr, self.betas, self.eps = float(lr), tuple(betas), float(eps)
+        self.t = 0
+        sizes = []
+        for k in range(4):
+            sizes += [self.dims[k + 1] * self.dims[k] * 9, self.dims[k + 1]]
+        self._sizes = sizes
+        total = sum(sizes)
+        rng = np.random.default_rng(seed)
+        host = np.zeros(total, dtype=np.float32)
+        off = 0
+        for k in range(4):
+            nw = sizes[2 * k]
+            w = rng.normal(0.0, np.sqrt(2.0 / (self.dims[k] * 9)), nw)
+            host[off:off + nw] = 0.0 if (zero_last and k == 3) else w
+            off += nw + sizes[2 * k + 1]
+        self.params = torch.from_numpy(host).cuda()
+        self.grads = torch.zeros_like(self.params)
+        self.m1 = torch.zeros_like(self.params)
+        self.m2 = torch.zeros_like(self.params)
+        self.work = torch.empty(_lib.xbar_sg_workspace_floats(self.C, self.C), dtype=torch.float32, device="cuda")
+        self._buf_shape = None
+
+    # -- parameter views -----------------------------------------------------------------
+    def _views(self, flat):
+        out, off = [], 0
+        for k in range(4):
+            nw, nb = self._sizes[2 * k], self._sizes[2 * k + 1]
+            out.append((flat[off:off + nw], flat[off + nw:off + nw + nb]))
+            off += nw + nb
+        return out
+
+    def layers(self):
+        """[(w [O][C][3][3], b [O])] views of the weights."""
+        return [(w.view(self.dims[k + 1], self.dims[k], 3, 3), b) for k, (w, b) in enumerate(self._views(self.params))]
+
+    def state(self) -> dict:
+        """Host copies of the weights and optimizer state (for checkpoints)."""
+        return {"params": self.params.cpu().numpy(), "m1": self.m1.cpu().numpy(), "m2": self.m2.cpu().numpy(),
+                "t": self.t, "channels": self.C}
+
+    def load(self, state: dict) -> None:
+        torch = _torch()
+        if int(state["channels"]) != self.C:
+            raise ValueError("checkpoint has a different width")
+        for name in ("params", "m1", "m2"):
+            getattr(self, name).copy_(torch.from_numpy(np.asarray(state[name], dtype=np.float32)))
+        self.t = int(state["t"])
+
+    # -- buffers -------------------------------------------------------------------------
+    def _buffers(self, B, m, n):
+        torch = _torch()
+        if self._buf_shape is not None and self._buf_shape[0] >= B and self._buf_shape[1:] == (m, n):
+            return
+        f = dict(dtype=torch.float32, device="cuda")
+        self.X = torch.empty((B, N_FEATURES, m, n), **f)
+        self.acts = [torch.empty((B, self.C, m, n), **f) for _ in range(3)]
+        self.Y = torch.empty((B, 1, m, n), **f)
+        self.gY = torch.empty((B, 1, m, n), **f)
+        self.ga = [torch.empty((B, self.C, m, n), **f) for _ in range(2)]
+        self.err2 = torch.empty(B, dtype=torch.float64, device="cuda")
+        self._buf_shape = (B, m, n)
+
+    @staticmethod
+    def _stream():
+        return _torch().cuda.current_stream().cuda_stream
+
+    # -- steps ---------------------------------------------------------------------------
+    def forward(self, G, V, r):
+        """Last map Y [B][1][m][n] for G [B][m][n], V [B][m], r [B] (float64 device tensors)."""
+        B, m, n = (int(x) for x in G.shape)
+        self._buffers(B, m, n)
+        s = self._stream()
+        _lib.xbar_sg_features(B, m, n, G, V, r, self.X, s)
+        x = self.X
+        outs = self.acts + [self.Y]
+        for k, (w, b) in enumerate(self._views(self.params)):
+            _lib.xbar_sg_conv_forward(B, m, n, self.dims[k], self.dims[k + 1], k < 3, x, w, b, outs[k], s)
+            x = outs[k]
+        return self.Y[:B]
+
+    def train_step(self, G, V, r, delta, want_loss: bool = True):
+        """One forward, backward and Adam step on a batch (delta [B][n] float64 device
+        tensor).  Returns the batch loss mean((yhat - delta)^2), which waits for the
+        step to finish, or None when want_loss is false."""
+        B, m, n = (int(x) for x in G.shape)
+        self.forward(G, V, r)
+        s = self._stream()
+        _lib.xbar_sg_readout_loss(B, m, n, self.Y, delta, self.gY, self.err2, s)
+        ins = [self.X] + self.acts                  # input of layer k
+        gv = self._views(self.grads)
+        wv = self._views(self.params)
+        g_out = self.gY                             # dLoss / d(output of layer k)
+        for k in range(3, -1, -1):
+            mask = self.acts[k] if k < 3 else None   # ReLU output of layer k
+            C, O = self.dims[k], self.dims[k + 1]
+            _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, mask, gv[k][0], gv[k][1], self.work, s)
+            if k > 0:
+                g_in = self.ga[k % 2]
+                _lib.xbar_sg_conv_backward_data(B, m, n, C, O, g_out, mask, wv[k][0], g_in, s)
+                g_out = g_in
+        self.t += 1
+        _lib.xbar_sg_adam(self.params, self.grads, self.m1, self.m2, self.lr, self.betas[0], self.betas[1],
+                          self.eps, self.t, s)
+        if not want_loss:
+            return None
+        return float(self.err2[:B].cpu().numpy().sum()) / (B * n)
+
+    def predict(self, G, V, r, out=None):
+        """Surrogate currents I [B][n] float64 = (G^T V)_j (1 + yhat_j)."""
+        torch = _torch()
+        B, m, n = (int(x) for x in G.shape)
+        self.forward(G, V, r)
+        if out is None:
+            out = torch.empty((B, n), dtype=torch.float64, device="cuda")
+        _lib.xbar_sg_predict(B, m, n, self.Y, G, V, out, self._stream())
+        return out
+
+
+class Dataset:
+    """Solver-labelled samples: maps G [M][m][n] with segment resistances r [M], and
+    `vectors` input vectors per map, V [M * vectors][m], with their exact currents
+    I [M * vectors][n] and targets delta (all float64 device tensors).  Sample s uses
+    map s // vectors."""
+
+    def __init__(self, G, r, V, I, vectors):
+        self.G, self.r, self.V, self.I, self.vectors = G, r, V, I, int(vectors)
+        self.delta, self.I0 = targets_of(self)
+
+    def __len__(self):
+        return int(self.V.shape[0])
+
+    def batch(self, idx):
+        """(G, V, r, delta, I) of the samples idx (a device int64 tensor), gathered."""
+        maps = idx // self.vectors
+        return (self.G[maps].contiguous(), self.V[idx].contiguous(), self.r[maps].contiguous(),
+                self.delta[idx].contiguous(), self.I[idx].contiguous())
+
+
+def solver_dataset(maps: int, vectors: int, m: int, n: int, seed: int, r_levels=None, r_src: float = 50.0,
+                   r_sense: float = 50.0, lanes: int = 3) -> Dataset:
+    """Training data from the exact solver: `maps` conductance maps (log-uniform on
+    [1e-6, 1e-4] S), each with `vectors` input vectors (uniform on [0, 0.5] V) and one
+    segment resistance r = r_wl = r_bl drawn from r_levels (default 1.0, 1.25, ..., 5.0
+    ohm), solved with PlanLanes (one plan set per resistance level)."""
+    torch = _torch()
+    levels = np.arange(1.0, 5.0001, 0.25) if r_levels is None else np.asarray(r_levels, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    Gm = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (maps, m, n)))
+    Vm = rng.uniform(0.0, 0.5, (maps, vectors, m))
+    rm = levels[rng.integers(0, len(levels), maps)]
+    Gd = torch.from_numpy(Gm).cuda()
+    Vd = torch.from_numpy(Vm).cuda()
+    Id = torch.empty((maps, vectors, n), dtype=torch.float64, device="cuda")
+    for lv in np.unique(rm):
+        idx = np.nonzero(rm == lv)[0]
+        with PlanLanes(lv, lv, r_src, r_sense, lanes=lanes, max_batch=vectors) as pl:
+            pl.currents([Gd[k] for k in idx], [Vd[k] for k in idx], [Id[k] for k in idx])
+            pl.check()
+    return Dataset(Gd, torch.from_numpy(rm).cuda(), Vd.reshape(maps * vectors, m), Id.reshape(maps * vectors, n),
+                   vectors)
+
+
+def targets_of(ds: Dataset):
+    """delta = (I - I0) / I0 with I0 = G^T V formed by the library's prediction kernel
+    (a zero correction map), chunked over samples."""
+    torch = _torch()
+    S, n = (int(x) for x in ds.I.shape)
+    m = int(ds.G.shape[1])
+    I0 = torch.empty((S, n), dtype=torch.float64, device="cuda")
+    step = 4096
+    zero = torch.zeros((min(step, S), 1, m, n), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    for a in range(0, S, step):
+        idx = torch.arange(a, min(S, a + step), device="cuda")
+        Gb = ds.G[idx // ds.vectors].contiguous()
+        _lib.xbar_sg_predict(len(idx), m, n, zero, Gb, ds.V[idx].contiguous(), I0[a:a + len(idx)], st)
+    return (ds.I - I0) / I0, I0

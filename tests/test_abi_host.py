@@ -8,9 +8,12 @@ import pytest
 
 from paper_2410_19993_amd import _lib
 
-EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor",
-            "xbar_get_info", "xbar_get_timing", "xbar_set_factor_method", "xbar_set_timing",
-            "xbar_solve_batch", "xbar_status_string", "xbar_tiles_currents", "xbar_transfer", "xbar_transfer_apply"]
+EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor", "xbar_get_info",
+            "xbar_get_timing", "xbar_set_factor_method", "xbar_set_timing", "xbar_sg_adam",
+            "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_conv_forward",
+            "xbar_sg_features", "xbar_sg_predict", "xbar_sg_readout_loss", "xbar_sg_workspace_floats",
+            "xbar_solve_batch", "xbar_status_string", "xbar_tiles_currents", "xbar_transfer",
+            "xbar_transfer_apply"]
 
 
 def _gpu_visible():
@@ -122,3 +125,38 @@ def test_tiles_rejects_overlapping_output():
     # I over G, then over V: rejected before any device call
     assert L.xbar_tiles_currents(ctypes.byref(g), 2, 3, G, V, ctypes.c_void_p(base + 8 * 16), None) == _lib.XBAR_ERR_ARG
     assert L.xbar_tiles_currents(ctypes.byref(g), 2, 3, G, V, ctypes.c_void_p(base + 8 * 1030), None) == _lib.XBAR_ERR_ARG
+
+
+def test_surrogate_calls_reject_bad_arguments():
+    """Host checks of the surrogate calls come before any device call (no GPU needed)."""
+    L = _lib.lib()
+    buf = (ctypes.c_float * 65536)()
+    base = ctypes.addressof(buf)
+    a, b, c, d = (ctypes.c_void_p(base + k * 65536) for k in range(4))
+    E = _lib.XBAR_ERR_ARG
+    assert L.xbar_sg_workspace_floats(32, 32) == 256 * (32 * 32 * 9 + 32)
+    assert L.xbar_sg_workspace_floats(33, 1) == -1 and L.xbar_sg_workspace_floats(1, 0) == -1
+    # channels out of range, empty shapes, NULL pointers
+    assert L.xbar_sg_conv_forward(1, 4, 4, 33, 2, 1, a, b, c, d, None) == E
+    assert L.xbar_sg_conv_forward(1, 4, 4, 2, 0, 1, a, b, c, d, None) == E
+    assert L.xbar_sg_conv_forward(0, 4, 4, 2, 2, 1, a, b, c, d, None) == E
+    assert L.xbar_sg_conv_forward(1, 4, 0, 2, 2, 1, a, b, c, d, None) == E
+    assert L.xbar_sg_conv_forward(1, 4, 4, 2, 2, 1, None, b, c, d, None) == E
+    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, None, None) == E
+    assert L.xbar_sg_features(1, 0, 4, a, b, c, d, None) == E
+    assert L.xbar_sg_readout_loss(1, 4, 4, a, b, None, d, None) == E
+    assert L.xbar_sg_predict(1, 4, 4, a, b, c, None, None) == E
+    # outputs overlapping inputs: y over x, gx over gy, I over Y
+    assert L.xbar_sg_conv_forward(1, 4, 4, 2, 2, 1, a, b, c, ctypes.c_void_p(base + 16), None) == E
+    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, ctypes.c_void_p(base + 64), None) == E
+    assert L.xbar_sg_predict(1, 4, 4, a, b, c, ctypes.c_void_p(base + 8), None) == E
+    # weight gradient: workspace too small, gw over gb
+    ws = L.xbar_sg_workspace_floats(2, 2)
+    assert L.xbar_sg_conv_backward_weight(1, 4, 4, 2, 2, a, b, None, c, d, ctypes.c_void_p(base + 4 * 65536 * 8),
+                                          1, None) == E
+    assert L.xbar_sg_conv_backward_weight(1, 4, 4, 2, 2, a, b, None, c, ctypes.c_void_p(base + 2 * 65536 + 8),
+                                          ctypes.c_void_p(base + 4 * 65536 * 8), ws, None) == E
+    # Adam: step 0, lr <= 0, beta outside [0, 1)
+    assert L.xbar_sg_adam(4, a, b, c, d, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E
+    assert L.xbar_sg_adam(4, a, b, c, d, 0.0, 0.9, 0.999, 1e-8, 1, None) == E
+    assert L.xbar_sg_adam(4, a, b, c, d, 1e-3, 1.0, 0.999, 1e-8, 1, None) == E

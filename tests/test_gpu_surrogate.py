@@ -1,0 +1,223 @@
+"""GPU parity of the surrogate's kernels (xbar_sg_*) against the float64 oracle
+(oracle/surrogate.py), and a training run that must beat the ideal currents G^T V.
+
+Tolerance of a float32 kernel: an output that sums K products is compared with the
+oracle within 2 K u (sum of |terms|), u = 2^-24, the float32 unit roundoff times the
+accumulation length; sum of |terms| is the oracle applied to absolute values."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate as osg
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _rand(rng, *shape):
+    return _f32(rng.normal(size=shape))
+
+
+def _lib():
+    from paper_2410_19993_amd import _lib
+    return _lib
+
+
+def _assert_within(got, ref, absref, K, what):
+    bound = 2.0 * K * U32 * absref + 1e-30
+    err = np.abs(got - ref)
+    worst = float((err / bound).max())
+    log(f"  {what}: max error / bound {worst:.3f}")
+    assert np.all(err <= bound), what
+
+
+CONV_CASES = [(2, 13, 17, 5, 7), (1, 20, 33, 32, 32), (3, 1, 1, 1, 1), (2, 16, 16, 32, 1), (1, 5, 40, 3, 32)]
+
+
+@pytest.mark.parametrize("B,H,W,C,O", CONV_CASES)
+@pytest.mark.parametrize("relu", [False, True])
+def test_conv_forward(B, H, W, C, O, relu):
+    import torch
+    rng = np.random.default_rng(B * 1000 + H * 10 + C + O + relu)
+    x, w, b = _rand(rng, B, C, H, W), _rand(rng, O, C, 3, 3), _rand(rng, O)
+    log(f"case conv forward B={B} H={H} W={W} C={C} O={O} relu={relu}")
+    y = torch.empty((B, O, H, W), dtype=torch.float32, device="cuda")
+    _lib().xbar_sg_conv_forward(B, H, W, C, O, relu, _t(x, torch.float32), _t(w, torch.float32),
+                                _t(b, torch.float32), y)
+    got = y.cpu().numpy().astype(np.float64)
+    ref = osg.conv2d(x, w, b)
+    absref = osg.conv2d(np.abs(x), np.abs(w), np.abs(b))
+    if relu:
+        ref = np.maximum(ref, 0.0)
+        got_neg = got[ref == 0.0]
+        assert np.all(got_neg >= 0.0)
+    _assert_within(got, ref, absref, C * 9 + 1, "conv forward")
+
+
+@pytest.mark.parametrize("B,H,W,C,O", CONV_CASES)
+@pytest.mark.parametrize("masked", [False, True])
+def test_conv_backward_data(B, H, W, C, O, masked):
+    import torch
+    rng = np.random.default_rng(7 + B * 1000 + H * 10 + C + O + masked)
+    g, w = _rand(rng, B, O, H, W), _rand(rng, O, C, 3, 3)
+    ymask = _f32(np.maximum(rng.normal(size=(B, O, H, W)), 0.0)) if masked else None
+    log(f"case conv backward data B={B} H={H} W={W} C={C} O={O} masked={masked}")
+    gx = torch.empty((B, C, H, W), dtype=torch.float32, device="cuda")
+    _lib().xbar_sg_conv_backward_data(B, H, W, C, O, _t(g, torch.float32),
+                                      None if ymask is None else _t(ymask, torch.float32), _t(w, torch.float32), gx)
+    gm = g * (ymask > 0) if masked else g
+    ref = osg.conv2d_grad_input(gm, w)
+    absref = osg.conv2d_grad_input(np.abs(gm), np.abs(w))
+    _assert_within(gx.cpu().numpy().astype(np.float64), ref, absref, O * 9, "conv backward data")
+
+
+@pytest.mark.parametrize("B,H,W,C,O", CONV_CASES + [(20, 64, 64, 3, 4), (3, 50, 37, 2, 5)])
+@pytest.mark.parametrize("masked", [False, True])
+def test_conv_backward_weight(B, H, W, C, O, masked):
+    """Includes shapes with more 16 x 16 tiles than partial-sum workgroups (256)."""
+    import torch
+    rng = np.random.default_rng(11 + B * 1000 + H * 10 + C + O + masked)
+    x, g = _rand(rng, B, C, H, W), _rand(rng, B, O, H, W)
+    ymask = _f32(np.maximum(rng.normal(size=(B, O, H, W)), 0.0)) if masked else None
+    log(f"case conv backward weight B={B} H={H} W={W} C={C} O={O} masked={masked}")
+    L = _lib()
+    work = torch.empty(L.xbar_sg_workspace_floats(C, O), dtype=torch.float32, device="cuda")
+    gw = torch.empty((O, C, 3, 3), dtype=torch.float32, device="cuda")
+    gb = torch.empty(O, dtype=torch.float32, device="cuda")
+    L.xbar_sg_conv_backward_weight(B, H, W, C, O, _t(x, torch.float32), _t(g, torch.float32),
+                                   None if ymask is None else _t(ymask, torch.float32), gw, gb, work)
+    gm = g * (ymask > 0) if masked else g
+    rw, rb = osg.conv2d_grad_weight(x, gm)
+    aw, ab = osg.conv2d_grad_weight(np.abs(x), np.abs(gm))
+    K = B * H * W
+    _assert_within(gw.cpu().numpy().astype(np.float64), rw, aw, K, "weight gradient")
+    _assert_within(gb.cpu().numpy().astype(np.float64), rb, ab, K, "bias gradient")
+
+
+def test_features_readout_predict_adam():
+    import torch
+    rng = np.random.default_rng(21)
+    B, m, n = 3, 9, 14
+    G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (B, m, n)))
+    V = rng.uniform(0, 0.5, (B, m))
+    r = np.array([1.0, 2.75, 5.0])
+    L = _lib()
+    log("case features, readout + loss, prediction, Adam")
+    X = torch.empty((B, 5, m, n), dtype=torch.float32, device="cuda")
+    L.xbar_sg_features(B, m, n, _t(G), _t(V), _t(r), X)
+    ref = osg.features(G, V, r)
+    assert np.allclose(X.cpu().numpy(), ref, rtol=2 * U32, atol=2 * U32 * 4)
+
+    Y = _rand(rng, B, 1, m, n)
+    delta = rng.normal(scale=0.1, size=(B, n))
+    gY = torch.empty((B, 1, m, n), dtype=torch.float32, device="cuda")
+    err2 = torch.empty(B, dtype=torch.float64, device="cuda")
+    L.xbar_sg_readout_loss(B, m, n, _t(Y, torch.float32), _t(delta), gY, err2)
+    loss, dY = osg.loss_and_grad(Y, delta)
+    assert float(err2.cpu().numpy().sum()) / (B * n) == pytest.approx(loss, rel=1e-12)
+    assert np.allclose(gY.cpu().numpy(), dY, rtol=2 * U32, atol=0)
+
+    I = torch.empty((B, n), dtype=torch.float64, device="cuda")
+    L.xbar_sg_predict(B, m, n, _t(Y, torch.float32), _t(G), _t(V), I)
+    refI = osg.ideal_currents(G, V) * (1.0 + osg.readout(Y))
+    assert np.allclose(I.cpu().numpy(), refI, rtol=1e-12, atol=0)
+
+    p, g = _rand(rng, 1000), _rand(rng, 1000)
+    m1, m2 = np.zeros(1000), np.zeros(1000)
+    pd, gd = _t(p, torch.float32), _t(g, torch.float32)
+    m1d, m2d = torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    for t in range(1, 4):
+        L.xbar_sg_adam(pd, gd, m1d, m2d, 1e-2, 0.9, 0.999, 1e-8, t)
+        p, m1, m2 = osg.adam_step(p, g, m1, m2, t, 1e-2)
+    assert np.allclose(pd.cpu().numpy(), p, rtol=0, atol=1e-6)
+
+
+def test_network_gradients_and_update_match_oracle():
+    """Surrogate.train_step: its gradients equal the oracle's backward pass at the
+    pre-step weights (norm-wise within 1e-3 per tensor: four float32 layers of at most
+    288-term sums, about 4 * 288 u = 7e-5, with a margin), and the new weights equal
+    the oracle's Adam step."""
+    import torch
+
+    import paper_2410_19993_amd.surrogate as sgm
+    rng = np.random.default_rng(31)
+    B, m, n = 4, 12, 19
+    G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (B, m, n)))
+    V = rng.uniform(0, 0.5, (B, m))
+    r = rng.uniform(1, 5, B)
+    delta = rng.normal(scale=0.05, size=(B, n))
+    net = sgm.Surrogate(channels=8, seed=3, lr=1e-3, zero_last=False)
+    params = [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for w, b in net.layers()]
+    log("case network gradients, channels 8, B=4 12x19")
+    loss = net.train_step(_t(G), _t(V), _t(r), _t(delta))
+    X = osg.features(G, V, r)
+    acts = osg.forward(params, _f32(X))
+    ref_loss, dY = osg.loss_and_grad(acts[-1], delta)
+    assert loss == pytest.approx(ref_loss, rel=1e-3)
+    grads = osg.backward(params, acts, dY)
+    gv = net._views(net.grads)
+    for k in range(4):
+        for part in range(2):
+            got = gv[k][part].cpu().numpy().astype(np.float64).reshape(grads[k][part].shape)
+            ref = grads[k][part]
+            assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref) + 1e-30, (k, part)
+    new = [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for w, b in net.layers()]
+    for k in range(4):
+        for part in range(2):
+            g = gv[k][part].cpu().numpy().astype(np.float64).reshape(params[k][part].shape)
+            p1, _, _ = osg.adam_step(params[k][part], g, 0.0, 0.0, 1, 1e-3)
+            assert np.allclose(new[k][part], p1, rtol=0, atol=2e-6), (k, part)
+
+
+def test_training_beats_ideal_currents():
+    """Trained on oracle-labelled 16 x 16 crossbars, the surrogate's currents on held-out
+    maps are closer to the exact currents than G^T V is (by at least a factor 2 in mean
+    relative error)."""
+    import torch
+
+    import paper_2410_19993_amd.surrogate as sgm
+    rng = np.random.default_rng(41)
+    m = n = 16
+    vectors = 8
+
+    def data(maps):
+        G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (maps, m, n)))
+        r = rng.choice(np.arange(1.0, 5.01, 0.5), maps)
+        V = rng.uniform(0, 0.5, (maps, vectors, m))
+        I = np.stack([oracle.solve(G[k], V[k], r[k], r[k], 50.0, 50.0).currents for k in range(maps)])
+        S = maps * vectors
+        Gs = np.repeat(G, vectors, axis=0)
+        return Gs, V.reshape(S, m), np.repeat(r, vectors), I.reshape(S, n)
+
+    Gt, Vt, rt, It = data(48)
+    Gh, Vh, rh, Ih = data(16)
+    dt = osg.targets(It, Gt, Vt)
+    net = sgm.Surrogate(channels=16, seed=1, lr=3e-3)
+    Gd, Vd, rd, dd = _t(Gt), _t(Vt), _t(rt), _t(dt)
+    log("case surrogate training: 384 samples of 16 x 16, 400 steps of 32")
+    g = torch.Generator().manual_seed(5)
+    for step in range(400):
+        idx = torch.randint(0, len(Gt), (32,), generator=g).cuda()
+        net.train_step(Gd[idx].contiguous(), Vd[idx].contiguous(), rd[idx].contiguous(), dd[idx].contiguous(),
+                       want_loss=False)
+    I_sg = net.predict(_t(Gh), _t(Vh), _t(rh)).cpu().numpy()
+    I0 = osg.ideal_currents(Gh, Vh)
+    e_sg = float(np.mean(np.abs(I_sg - Ih) / np.abs(Ih)))
+    e_0 = float(np.mean(np.abs(I0 - Ih) / np.abs(Ih)))
+    log(f"  held-out mean relative error: surrogate {e_sg:.4f}, G^T V {e_0:.4f}")
+    assert np.all(np.isfinite(I_sg))
+    assert e_sg < 0.5 * e_0
