@@ -1,0 +1,151 @@
+"""Learned current surrogate on 128 x 128 crossbars: data, training, accuracy, speed.
+
+    python bench_surrogate.py [--maps 12500] [--held-out-maps 1250] [--vectors 16]
+                              [--epochs 3] [--batch 32] [--lr 1e-3] [--channels 32]
+
+Workload (seeded, synthetic): conductance maps log-uniform on [1e-6, 1e-4] S, the
+segment resistance r = r_wl = r_bl drawn from {1.0, 1.25, ..., 5.0} ohm per map,
+r_src = r_sense = 50 ohm, input vectors uniform on [0, 0.5] V; `vectors` input vectors
+per map.  The defaults give 200,000 training and 20,000 held-out samples.
+
+Steps, all on the GPU through the library:
+1. labels: exact float64 currents of every sample from the solver (PlanLanes, three
+   plans at a time), timed: that is the solver's throughput on new maps;
+2. training: Adam on the mean squared error of the predicted correction, timed per
+   step (features, 4 convolutions, readout and loss, 7 gradient kernels, update);
+3. held-out accuracy: relative current error of the surrogate and of G^T V against the
+   exact currents, mean, 99th percentile and maximum, and the share of samples whose
+   worst column is within 1%;
+4. inference: surrogate currents for batches of held-out samples, timed.
+One JSON line goes to stdout at the end; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--maps", type=int, default=12500)
+    ap.add_argument("--held-out-maps", type=int, default=1250)
+    ap.add_argument("--vectors", type=int, default=16)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=1005)
+    ap.add_argument("--infer-batch", type=int, default=256)
+    args = ap.parse_args()
+
+    import torch
+
+    import paper_2410_19993_amd.surrogate as sgm
+    from paper_2410_19993_amd import _lib
+    _lib.lib()
+    assert torch.cuda.is_available(), "no GPU visible"
+    m = n = args.size
+
+    # 1. labels from the exact solver
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    train = sgm.solver_dataset(args.maps, args.vectors, m, n, seed=args.seed)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    held = sgm.solver_dataset(args.held_out_maps, args.vectors, m, n, seed=args.seed + 1)
+    torch.cuda.synchronize()
+    log(f"labels: {args.maps} maps x {args.vectors} vectors in {t_label:.1f} s "
+        f"({args.maps / t_label:.0f} maps/s, {len(train) / t_label:.0f} solves/s)")
+
+    # 2. training
+    net = sgm.Surrogate(channels=args.channels, seed=args.seed, lr=args.lr)
+    S = len(train)
+    steps_per_epoch = S // args.batch
+    total = steps_per_epoch * args.epochs
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed)
+    losses = []
+    step = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(args.epochs):
+        perm = torch.randperm(S, device="cuda", generator=g)
+        run = 0.0
+        for k in range(steps_per_epoch):
+            net.lr = args.lr * (0.1 + 0.9 * 0.5 * (1.0 + math.cos(math.pi * step / total)))
+            G, V, r, d, _ = train.batch(perm[k * args.batch:(k + 1) * args.batch])
+            want = (k % 200 == 199) or k == steps_per_epoch - 1
+            loss = net.train_step(G, V, r, d, want_loss=want)
+            if want:
+                run = loss
+                losses.append((step + 1, loss))
+            step += 1
+        log(f"epoch {ep + 1}/{args.epochs}: loss {run:.3e} after {step} steps, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # 3. held-out accuracy
+    rel_sg, rel_0 = [], []
+    for a in range(0, len(held), args.infer_batch):
+        idx = torch.arange(a, min(len(held), a + args.infer_batch), device="cuda")
+        G, V, r, _, I = held.batch(idx)
+        Ip = net.predict(G, V, r)
+        I0 = held.I0[idx]
+        rel_sg.append(((Ip - I).abs() / I.abs()).cpu().numpy())
+        rel_0.append(((I0 - I).abs() / I.abs()).cpu().numpy())
+    rel_sg, rel_0 = np.concatenate(rel_sg), np.concatenate(rel_0)
+
+    def stats(e):
+        worst = e.max(axis=1)
+        return {"mean": float(e.mean()), "p99": float(np.percentile(e, 99)), "max": float(e.max()),
+                "samples_within_1pct": float(np.mean(worst <= 0.01))}
+
+    acc_sg, acc_0 = stats(rel_sg), stats(rel_0)
+    log(f"held-out relative current error: surrogate mean {acc_sg['mean']:.2e} p99 {acc_sg['p99']:.2e} "
+        f"max {acc_sg['max']:.2e}; G^T V mean {acc_0['mean']:.2e} max {acc_0['max']:.2e}")
+
+    # 4. inference speed on held-out samples (inputs resident)
+    B = min(args.infer_batch, len(held))
+    idx = torch.arange(0, B, device="cuda")
+    G, V, r, _, _ = held.batch(idx)
+    out = torch.empty((B, n), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        net.predict(G, V, r, out)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.predict(G, V, r, out)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / reps
+    result = {
+        "metric": "surrogate_samples_per_s", "value": B / t_inf, "unit": "samples/s",
+        "workload": f"{m}x{n} crossbars, r_wl = r_bl in [1, 5] ohm, r_src = r_sense = 50 ohm, synthetic",
+        "train_samples": S, "held_out_samples": len(held), "channels": args.channels, "epochs": args.epochs,
+        "batch": args.batch, "steps": total, "dtype": "f32 (network), f64 (labels, readout)",
+        "label_solves_per_s": len(train) / t_label, "label_maps_per_s": args.maps / t_label,
+        "train_s": t_train, "train_ms_per_step": 1e3 * t_train / max(total, 1),
+        "train_samples_per_s": total * args.batch / t_train,
+        "infer_ms_per_batch": 1e3 * t_inf, "infer_batch": B,
+        "speedup_vs_solver_new_maps": (B / t_inf) / (args.maps / t_label),
+        "error_surrogate": acc_sg, "error_ideal_GtV": acc_0, "loss_curve": losses[-10:],
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

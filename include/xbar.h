@@ -276,10 +276,15 @@ xbar_status xbar_destroy(xbar_plan plan);
  * H, W >= 1, 1 <= C, O <= XBAR_SG_MAX_CHANNELS.
  */
 #define XBAR_SG_MAX_CHANNELS 32
+#define XBAR_SG_FEATURES 7
+#define XBAR_SG_MAX_LINE 2048
 
-/* X [B][5][m][n] float32 from G [B][m][n] (S, > 0), V [B][m] (V), r [B] (ohm,
- * the segment resistance): log10(G) + 5, 2 V_i, (r - 3) / 2, and the column
- * and row positions 2 j / (n - 1) - 1 and 2 i / (m - 1) - 1 (0 for n or m = 1). */
+/* X [B][7][m][n] float32 from G [B][m][n] (S, > 0), V [B][m] (V), r [B] (ohm,
+ * the segment resistance), m, n <= XBAR_SG_MAX_LINE: log10(G) + 5, 2 V_i,
+ * (r - 3) / 2, the column and row positions 2 j / (n - 1) - 1 and
+ * 2 i / (m - 1) - 1 (0 for n or m = 1), and the line totals that set the drops
+ * at the line ends, 1e4 mean_j' G[i][j'] (row i) and 1e4 mean_i' G[i'][j] 2 V_i'
+ * (column j). */
 xbar_status xbar_sg_features(int32_t B, int32_t m, int32_t n, const double* G, const double* V, const double* r,
                              float* X, void* stream);
 

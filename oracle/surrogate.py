@@ -10,12 +10,15 @@ module; it shares nothing with the GPU library.  Arithmetic is float64.
 
 Definitions (the GPU library implements the same definitions in float32):
 
-* Features, 5 channels per crosspoint (i, j) of an m x n crossbar:
+* Features, 7 channels per crosspoint (i, j) of an m x n crossbar:
   log10(G_ij) + 5 (so [1e-6, 1e-4] S maps to [-1, 1]), 2 V_i, (r - 3) / 2
-  for the segment resistance r (ohm), and the column and row positions
-  2 j / (n - 1) - 1 and 2 i / (m - 1) - 1 (0 for a single column or row).
+  for the segment resistance r (ohm), the column and row positions
+  2 j / (n - 1) - 1 and 2 i / (m - 1) - 1 (0 for a single column or row), and
+  two line totals that set the drops at the line ends: 1e4 times the mean
+  conductance of row i, and 1e4 times the column mean of G_i'j 2 V_i' (the
+  ideal current of column j over 0.5 m V).
 * Network: four 3 x 3 convolutions with zero padding of one crosspoint,
-  5 -> C -> C -> C -> 1 channels, a bias per output channel, ReLU after the
+  7 -> C -> C -> C -> 1 channels, a bias per output channel, ReLU after the
   first three.  conv(x)[o, y, x] = b[o] + sum_{c, dy, dx} w[o, c, dy, dx]
   x[c, y + dy - 1, x + dx - 1] (cross-correlation, as deep-learning
   convolutions are defined).
@@ -28,11 +31,11 @@ from __future__ import annotations
 
 import numpy as np
 
-N_FEATURES = 5
+N_FEATURES = 7
 
 
 def features(G: np.ndarray, V: np.ndarray, r: np.ndarray) -> np.ndarray:
-    """G [B][m][n] (S), V [B][m] (V), r [B] (ohm) -> X [B][5][m][n]."""
+    """G [B][m][n] (S), V [B][m] (V), r [B] (ohm) -> X [B][7][m][n]."""
     G = np.asarray(G, dtype=np.float64)
     B, m, n = G.shape
     X = np.empty((B, N_FEATURES, m, n))
@@ -41,6 +44,8 @@ def features(G: np.ndarray, V: np.ndarray, r: np.ndarray) -> np.ndarray:
     X[:, 2] = ((np.asarray(r, dtype=np.float64) - 3.0) / 2.0)[:, None, None]
     X[:, 3] = (2.0 * np.arange(n) / (n - 1) - 1.0)[None, None, :] if n > 1 else 0.0
     X[:, 4] = (2.0 * np.arange(m) / (m - 1) - 1.0)[None, :, None] if m > 1 else 0.0
+    X[:, 5] = 1e4 * G.mean(axis=2)[:, :, None]
+    X[:, 6] = 1e4 * (G * 2.0 * np.asarray(V, dtype=np.float64)[:, :, None]).mean(axis=1)[:, None, :]
     return X
 
 

@@ -21,26 +21,48 @@
 namespace {
 
 constexpr int kMaxCh = XBAR_SG_MAX_CHANNELS;
+constexpr int kMaxLine = XBAR_SG_MAX_LINE;
+constexpr int kFeatures = XBAR_SG_FEATURES;
 constexpr int kParts = 256;            // workgroups of the weight-gradient pass (partial sums)
 constexpr int kPer = (kMaxCh * kMaxCh * 9 + 255) / 256;
 
 __device__ __forceinline__ bool in_grid(int p, int q, int H, int W) { return p >= 0 && p < H && q >= 0 && q < W; }
 
-// X[b][0..4][i][j] = log10(G) + 5, 2 V_i, (r - 3) / 2, column and row position in [-1, 1].
-__global__ void sg_features_kernel(int B, int m, int n, const double* __restrict__ G, const double* __restrict__ V,
-                                   const double* __restrict__ r, float* __restrict__ X)
+// X[b][0..6][i][j] = log10(G) + 5, 2 V_i, (r - 3) / 2, column and row position in
+// [-1, 1], and the line totals 1e4 mean_j' G[i][j'] (row i) and 1e4 mean_i' G[i'][j] 2 V_i'
+// (column j).  One workgroup per sample; the line totals go through LDS.
+__global__ __launch_bounds__(256) void sg_features_kernel(int m, int n, const double* __restrict__ G,
+                                                          const double* __restrict__ V, const double* __restrict__ r,
+                                                          float* __restrict__ X)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double rows[kMaxLine], cols[kMaxLine];
+    const int b = blockIdx.x;
     const int64_t mn = (int64_t)m * n;
-    if (e >= (int64_t)B * mn) return;
-    const int b = (int)(e / mn);
-    const int i = (int)((e % mn) / n), j = (int)(e % n);
-    float* xb = X + (int64_t)b * 5 * mn + (int64_t)i * n + j;
-    xb[0] = (float)(log10(G[e]) + 5.0);
-    xb[mn] = (float)(2.0 * V[(int64_t)b * m + i]);
-    xb[2 * mn] = (float)((r[b] - 3.0) * 0.5);
-    xb[3 * mn] = n > 1 ? (float)(2.0 * j / (n - 1) - 1.0) : 0.0f;
-    xb[4 * mn] = m > 1 ? (float)(2.0 * i / (m - 1) - 1.0) : 0.0f;
+    const double* gb = G + (int64_t)b * mn;
+    const double* vb = V + (int64_t)b * m;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += gb[(int64_t)i * n + j];
+        rows[i] = 1e4 * s / n;
+    }
+    for (int j = threadIdx.x; j < n; j += 256) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += gb[(int64_t)i * n + j] * 2.0 * vb[i];
+        cols[j] = 1e4 * s / m;
+    }
+    __syncthreads();
+    float* xb = X + (int64_t)b * kFeatures * mn;
+    const float rr = (float)((r[b] - 3.0) * 0.5);
+    for (int64_t e = threadIdx.x; e < mn; e += 256) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        xb[e] = (float)(log10(gb[e]) + 5.0);
+        xb[mn + e] = (float)(2.0 * vb[i]);
+        xb[2 * mn + e] = rr;
+        xb[3 * mn + e] = n > 1 ? (float)(2.0 * j / (n - 1) - 1.0) : 0.0f;
+        xb[4 * mn + e] = m > 1 ? (float)(2.0 * i / (m - 1) - 1.0) : 0.0f;
+        xb[5 * mn + e] = (float)rows[i];
+        xb[6 * mn + e] = (float)cols[j];
+    }
 }
 
 // y[b][o] = bias[o] + sum_{c, dy, dx} w[o][c][dy][dx] x[b][c][p + dy - 1][q + dx - 1]  (ReLU optional).
@@ -321,13 +343,12 @@ int64_t xbar_sg_workspace_floats(int32_t C, int32_t O)
 xbar_status xbar_sg_features(int32_t B, int32_t m, int32_t n, const double* G, const double* V, const double* r,
                              float* X, void* hip_stream)
 {
-    if (!shape_ok(B, m, n) || !G || !V || !r || !X) return XBAR_ERR_ARG;
-    const int64_t total = (int64_t)B * m * n;
-    if (overlap(X, total * 5 * 4, G, total * 8) || overlap(X, total * 5 * 4, V, (int64_t)B * m * 8) ||
-        overlap(X, total * 5 * 4, r, (int64_t)B * 8))
+    if (!shape_ok(B, m, n) || m > kMaxLine || n > kMaxLine || !G || !V || !r || !X) return XBAR_ERR_ARG;
+    const int64_t total = (int64_t)B * m * n, nx = total * kFeatures * 4;
+    if (overlap(X, nx, G, total * 8) || overlap(X, nx, V, (int64_t)B * m * 8) || overlap(X, nx, r, (int64_t)B * 8))
         return XBAR_ERR_ARG;
-    hipLaunchKernelGGL(sg_features_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(hip_stream), B, m, n, G, V, r, X);
+    hipLaunchKernelGGL(sg_features_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream), m, n,
+                       G, V, r, X);
     return launched();
 }
 

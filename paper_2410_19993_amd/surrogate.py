@@ -6,9 +6,10 @@ resistance (the zero-resistance limit of the nodal equations of Sec. II.A), so
 that the surrogate's currents are I0 (1 + yhat).  The exact solver (Plan,
 PlanLanes) produces the training targets and stays the reference for the error.
 
-Network: 5 features per crosspoint (log10 G + 5, 2 V_i, (r - 3) / 2, column and
-row position), four 3 x 3 convolutions 5 -> C -> C -> C -> 1 with ReLU after the
-first three, and the mean over rows of the last map as yhat_j.  Loss: mean
+Network: 7 features per crosspoint (log10 G + 5, 2 V_i, (r - 3) / 2, column and
+row position, and the row's mean conductance and the column's mean G 2 V, which set
+the drops across the source and sense resistors at the line ends), four 3 x 3
+convolutions 7 -> C -> C -> C -> 1 with ReLU after the first three, and the mean over rows of the last map as yhat_j.  Loss: mean
 squared error of yhat against delta; optimizer: Adam.  Every step (features,
 convolutions, their gradients, readout, loss, update, prediction) runs in the
 library's kernels (xbar_sg_*); torch only holds the device buffers.
@@ -20,7 +21,7 @@ import numpy as np
 from . import _lib
 from .lanes import PlanLanes
 
-N_FEATURES = 5
+N_FEATURES = 7
 
 
 def _torch():

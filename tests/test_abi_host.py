@@ -144,6 +144,7 @@ def test_surrogate_calls_reject_bad_arguments():
     assert L.xbar_sg_conv_forward(1, 4, 4, 2, 2, 1, None, b, c, d, None) == E
     assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, None, None) == E
     assert L.xbar_sg_features(1, 0, 4, a, b, c, d, None) == E
+    assert L.xbar_sg_features(1, 4, 2049, a, b, c, d, None) == E
     assert L.xbar_sg_readout_loss(1, 4, 4, a, b, None, d, None) == E
     assert L.xbar_sg_predict(1, 4, 4, a, b, c, None, None) == E
     # outputs overlapping inputs: y over x, gx over gy, I over Y

@@ -117,7 +117,7 @@ def test_features_readout_predict_adam():
     r = np.array([1.0, 2.75, 5.0])
     L = _lib()
     log("case features, readout + loss, prediction, Adam")
-    X = torch.empty((B, 5, m, n), dtype=torch.float32, device="cuda")
+    X = torch.empty((B, 7, m, n), dtype=torch.float32, device="cuda")
     L.xbar_sg_features(B, m, n, _t(G), _t(V), _t(r), X)
     ref = osg.features(G, V, r)
     assert np.allclose(X.cpu().numpy(), ref, rtol=2 * U32, atol=2 * U32 * 4)

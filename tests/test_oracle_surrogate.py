@@ -106,7 +106,12 @@ def test_features_definition_values():
     assert X[0, 0, 0, 0] == pytest.approx(0.0, abs=1e-15) and X[0, 0, 1, 2] == pytest.approx(1.0)
     assert np.allclose(X[0, 1, :, 0], [0.0, 0.5, 1.0]) and np.allclose(X[0, 2], 1.0)
     assert np.allclose(X[0, 3, 0], [-1, -1 / 3, 1 / 3, 1]) and np.allclose(X[0, 4, :, 0], [-1, 0, 1])
-    assert np.all(sg.features(G[:, :1, :1], np.array([[0.1]]), np.array([1.0]))[0, 3:] == 0.0)
+    assert np.all(sg.features(G[:, :1, :1], np.array([[0.1]]), np.array([1.0]))[0, 3:5] == 0.0)
+    # line totals: row 1 holds one 1e-4 among four columns; column 2 sees 2 V_i G_i2 summed
+    assert np.allclose(X[0, 5, :, 3], [0.1, (3e-5 + 1e-4) / 4 * 1e4, 0.1])
+    assert np.allclose(X[0, 6, 0], [1e4 * (1e-5 * 0.5 + 1e-5 * 1.0) / 3] * 2
+                       + [1e4 * (1e-4 * 0.5 + 1e-5 * 1.0) / 3] + [1e4 * (1e-5 * 0.5 + 1e-5 * 1.0) / 3])
+    assert np.allclose(X[0, 6, 0], 1e4 * sg.ideal_currents(G, np.array([[0.0, 0.25, 0.5]]))[0] * 2 / 3)
 
 
 def test_targets_vanish_without_wire_resistance():
