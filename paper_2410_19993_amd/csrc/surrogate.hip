@@ -171,8 +171,14 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int
 // Partial weight and bias gradients: workgroup k sums, over the 16 x 16 tiles
 // k, k + kParts, ..., gw[o][c][dy][dx] = sum g[b][o][p][q] x[b][c][p + dy - 1][q + dx - 1]
 // and gb[o] = sum g[b][o][p][q] into part[k][0 .. O C 9 + O).  The tile of g and
-// the tile of x with its one-crosspoint halo are staged in LDS; thread t owns
-// entries t, t + 256, ... of gw.
+// the tile of x with its one-crosspoint halo are staged in LDS.  With G = 256 / C
+// groups, thread t < G C owns input channel c = t % C and output channels
+// o = t / C + G k (k < 4), all nine taps of each: it walks the tile row by row with
+// the 3 x 3 window of x in registers, so each crosspoint costs three LDS reads of x
+// and one of g per output channel for 9 multiply-adds per output channel.
+constexpr int kXs = 18 * 18 + 1;        // LDS stride of a staged x channel (odd: spreads banks)
+constexpr int kOk = 4;                  // output channels per thread (256 / 32 groups of 8)
+
 __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, int W, int C, int O,
                                                                  const float* __restrict__ x,
                                                                  const float* __restrict__ gy,
@@ -180,14 +186,28 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
                                                                  float* __restrict__ part)
 {
     __shared__ float gs[kMaxCh * 256];          // [o][16 x 16]
-    __shared__ float xs[kMaxCh * 18 * 18];      // [c][18 x 18]
+    __shared__ float xs[kMaxCh * kXs];          // [c][18 x 18]
     const int ne = O * C * 9;
     const int tw = (W + 15) / 16, th = (H + 15) / 16;
     const int tiles = B * th * tw;
     const int64_t hw = (int64_t)H * W;
-    float acc[kPer];
+    const int groups = 256 / C;
+    const int c = threadIdx.x % C, og = threadIdx.x / C;
+    const bool active = og < groups;
+    int orow[kOk];
+    float on[kOk];                              // 1 for an output channel this thread owns, else 0
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) acc[k] = 0.0f;
+    for (int k = 0; k < kOk; ++k) {
+        const int o = og + groups * k;
+        const bool own = active && o < O;
+        on[k] = own ? 1.0f : 0.0f;
+        orow[k] = (own ? o : 0) * 256;          // a valid row of gs either way
+    }
+    float acc[kOk][9];
+#pragma unroll
+    for (int k = 0; k < kOk; ++k)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[k][t] = 0.0f;
     float accb = 0.0f;
     for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
         const int b = t / (th * tw), r = t % (th * tw);
@@ -204,50 +224,77 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
             gs[e] = g;
         }
         for (int e = threadIdx.x; e < C * 324; e += 256) {
-            const int c = e / 324, k = e % 324;
+            const int cc = e / 324, k = e % 324;
             const int p = p0 + k / 18 - 1, q = q0 + k % 18 - 1;
-            xs[e] = in_grid(p, q, H, W) ? x[((int64_t)b * C + c) * hw + (int64_t)p * W + q] : 0.0f;
+            xs[cc * kXs + k] = in_grid(p, q, H, W) ? x[((int64_t)b * C + cc) * hw + (int64_t)p * W + q] : 0.0f;
         }
         __syncthreads();
+        if (active) {
+            const float* xc = xs + c * kXs;
+            for (int pr = 0; pr < 16; ++pr) {
+                const float* xr = xc + pr * 18;
+                float a0 = xr[0], a1 = xr[18], a2 = xr[36];
+                float b0 = xr[1], b1 = xr[19], b2 = xr[37];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            if (e < ne) {
-                const int o = e / (C * 9), c = (e / 9) % C, tap = e % 9;
-                const float* go = gs + o * 256;
-                const float* xc = xs + c * 324 + (tap / 3) * 18 + tap % 3;
-                float s = 0.0f;
-                for (int pr = 0; pr < 16; ++pr)
+                for (int pc = 0; pc < 16; ++pc) {
+                    const float c0 = xr[pc + 2], c1 = xr[pc + 20], c2 = xr[pc + 38];
 #pragma unroll
-                    for (int pc = 0; pc < 16; ++pc) s = fmaf(go[pr * 16 + pc], xc[pr * 18 + pc], s);
-                acc[k] += s;
+                    for (int k = 0; k < kOk; ++k) {
+                        const float g = on[k] * gs[orow[k] + pr * 16 + pc];
+                        acc[k][0] = fmaf(g, a0, acc[k][0]);
+                        acc[k][1] = fmaf(g, b0, acc[k][1]);
+                        acc[k][2] = fmaf(g, c0, acc[k][2]);
+                        acc[k][3] = fmaf(g, a1, acc[k][3]);
+                        acc[k][4] = fmaf(g, b1, acc[k][4]);
+                        acc[k][5] = fmaf(g, c1, acc[k][5]);
+                        acc[k][6] = fmaf(g, a2, acc[k][6]);
+                        acc[k][7] = fmaf(g, b2, acc[k][7]);
+                        acc[k][8] = fmaf(g, c2, acc[k][8]);
+                    }
+                    a0 = b0; b0 = c0;
+                    a1 = b1; b1 = c1;
+                    a2 = b2; b2 = c2;
+                }
             }
         }
         if (threadIdx.x < O) {
-            float s = 0.0f;
-            for (int e = 0; e < 256; ++e) s += gs[threadIdx.x * 256 + e];
-            accb += s;
+            float sb = 0.0f;
+            for (int e = 0; e < 256; ++e) sb += gs[threadIdx.x * 256 + e];
+            accb += sb;
         }
     }
     float* pw = part + (int64_t)blockIdx.x * (ne + O);
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int e = threadIdx.x + 256 * k;
-        if (e < ne) pw[e] = acc[k];
+    for (int k = 0; k < kOk; ++k) {
+        const int o = og + groups * k;
+        if (active && o < O)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) pw[(o * C + c) * 9 + t] = acc[k][t];
     }
     if (threadIdx.x < O) pw[ne + threadIdx.x] = accb;
 }
 
-// gw[e] = sum over the partials in workgroup order (deterministic); e >= ne: gb.
-__global__ void sg_reduce_parts_kernel(int nparts, int ne, int O, const float* __restrict__ part,
-                                       float* __restrict__ gw, float* __restrict__ gb)
+// gw[e] = sum over the partials; e >= ne: gb.  Each workgroup takes 32 entries; lane
+// l of an entry adds the partials l, l + 8, ... in order, and the eight sums are then
+// added in lane order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void sg_reduce_parts_kernel(int nparts, int ne, int O,
+                                                              const float* __restrict__ part,
+                                                              float* __restrict__ gw, float* __restrict__ gb)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ne + O) return;
+    __shared__ float red[8][32];
+    const int le = threadIdx.x & 31, lp = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + le;
     float s = 0.0f;
-    for (int k = 0; k < nparts; ++k) s += part[(int64_t)k * (ne + O) + e];
-    if (e < ne) gw[e] = s;
-    else gb[e - ne] = s;
+    if (e < ne + O)
+        for (int k = lp; k < nparts; k += 8) s += part[(int64_t)k * (ne + O) + e];
+    red[lp][le] = s;
+    __syncthreads();
+    if (lp == 0 && e < ne + O) {
+        float t = red[0][le];
+        for (int k = 1; k < 8; ++k) t += red[k][le];
+        if (e < ne) gw[e] = t;
+        else gb[e - ne] = t;
+    }
 }
 
 // yhat_j = mean_i Y[b][i][j]; e_j = yhat_j - delta_j; gY[b][i][j] = 2 e_j / (B n m);
@@ -395,7 +442,7 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(256), 0, s, B, H, W, C, O, x, gy, ymask, work);
     if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
-    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 255) / 256), dim3(256), 0, s, nparts, ne, O, work, gw,
+    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 31) / 32), dim3(256), 0, s, nparts, ne, O, work, gw,
                        gb);
     return launched();
 }
