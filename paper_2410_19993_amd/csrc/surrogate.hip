@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void sg_features_kernel(int m, int n, const do
 }
 
 // y[b][o] = bias[o] + sum_{c, dy, dx} w[o][c][dy][dx] x[b][c][p + dy - 1][q + dx - 1]  (ReLU optional).
-// One thread per output crosspoint holds all O sums; the weights sit in LDS.
+// A workgroup covers 32 rows x 16 columns; each thread holds all O sums of two
+// crosspoints 16 rows apart, so every weight read from LDS feeds two multiply-adds.
 template <bool RELU>
 __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(int H, int W, int C, int O, const float* __restrict__ x,
                                                           const float* __restrict__ w,
@@ -78,30 +79,37 @@ __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(int H, int W, int C, i
     if (threadIdx.x < O) bs[threadIdx.x] = bias[threadIdx.x];
     __syncthreads();
     const int tw = (W + 15) / 16;
-    const int p = (blockIdx.x / tw) * 16 + (threadIdx.x >> 4);
+    const int p = (blockIdx.x / tw) * 32 + (threadIdx.x >> 4);
     const int q = (blockIdx.x % tw) * 16 + (threadIdx.x & 15);
     if (p >= H || q >= W) return;
+    const bool two = p + 16 < H;
     const int64_t hw = (int64_t)H * W;
     const float* xb = x + (int64_t)blockIdx.y * C * hw;
-    float acc[kMaxCh];
+    float acc[kMaxCh], acc2[kMaxCh];
 #pragma unroll
-    for (int o = 0; o < kMaxCh; ++o) acc[o] = 0.0f;
+    for (int o = 0; o < kMaxCh; ++o) acc[o] = acc2[o] = 0.0f;
     for (int c = 0; c < C; ++c) {
         const float* xc = xb + c * hw;
-        float v[9];
+        float v[9], v2[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int yy = p + t / 3 - 1, xx = q + t % 3 - 1;
             v[t] = in_grid(yy, xx, H, W) ? xc[(int64_t)yy * W + xx] : 0.0f;
+            v2[t] = (two && in_grid(yy + 16, xx, H, W)) ? xc[(int64_t)(yy + 16) * W + xx] : 0.0f;
         }
         const float* wc = ws + c * 9;
 #pragma unroll
         for (int o = 0; o < kMaxCh; ++o) {
             if (o < O) {
-                float s = acc[o];
+                float s = acc[o], s2 = acc2[o];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) s = fmaf(wc[o * C * 9 + t], v[t], s);
+                for (int t = 0; t < 9; ++t) {
+                    const float wv = wc[o * C * 9 + t];
+                    s = fmaf(wv, v[t], s);
+                    s2 = fmaf(wv, v2[t], s2);
+                }
                 acc[o] = s;
+                acc2[o] = s2;
             }
         }
     }
@@ -109,9 +117,13 @@ __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(int H, int W, int C, i
 #pragma unroll
     for (int o = 0; o < kMaxCh; ++o) {
         if (o < O) {
-            float s = acc[o] + bs[o];
-            if (RELU) s = s > 0.0f ? s : 0.0f;
+            float s = acc[o] + bs[o], s2 = acc2[o] + bs[o];
+            if (RELU) {
+                s = s > 0.0f ? s : 0.0f;
+                s2 = s2 > 0.0f ? s2 : 0.0f;
+            }
             yb[o * hw] = s;
+            if (two) yb[o * hw + 16 * (int64_t)W] = s2;
         }
     }
 }
@@ -119,6 +131,7 @@ __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(int H, int W, int C, i
 // Gradient of the layer's output g = gy (times [ymask > 0] when the layer has a
 // ReLU) with respect to its input:
 //     gx[b][c][p][q] = sum_{o, dy, dx} w[o][c][dy][dx] g[b][o][p - dy + 1][q - dx + 1].
+// As in the forward kernel, each thread takes two crosspoints 16 rows apart.
 __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int C, int O,
                                                                const float* __restrict__ gy,
                                                                const float* __restrict__ ymask,
@@ -128,44 +141,60 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int
     for (int e = threadIdx.x; e < O * C * 9; e += 256) ws[e] = w[e];
     __syncthreads();
     const int tw = (W + 15) / 16;
-    const int p = (blockIdx.x / tw) * 16 + (threadIdx.x >> 4);
+    const int p = (blockIdx.x / tw) * 32 + (threadIdx.x >> 4);
     const int q = (blockIdx.x % tw) * 16 + (threadIdx.x & 15);
     if (p >= H || q >= W) return;
+    const bool two = p + 16 < H;
     const int64_t hw = (int64_t)H * W;
     const int64_t base = (int64_t)blockIdx.y * O * hw;
-    float acc[kMaxCh];
+    float acc[kMaxCh], acc2[kMaxCh];
 #pragma unroll
-    for (int c = 0; c < kMaxCh; ++c) acc[c] = 0.0f;
+    for (int c = 0; c < kMaxCh; ++c) acc[c] = acc2[c] = 0.0f;
     for (int o = 0; o < O; ++o) {
         const float* go = gy + base + o * hw;
         const float* mo = ymask ? ymask + base + o * hw : nullptr;
-        float v[9];
+        float v[9], v2[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int yy = p - t / 3 + 1, xx = q - t % 3 + 1;
-            float g = 0.0f;
+            float g = 0.0f, g2 = 0.0f;
             if (in_grid(yy, xx, H, W)) {
                 const int64_t off = (int64_t)yy * W + xx;
                 g = go[off];
                 if (mo && !(mo[off] > 0.0f)) g = 0.0f;
             }
+            if (two && in_grid(yy + 16, xx, H, W)) {
+                const int64_t off = (int64_t)(yy + 16) * W + xx;
+                g2 = go[off];
+                if (mo && !(mo[off] > 0.0f)) g2 = 0.0f;
+            }
             v[t] = g;
+            v2[t] = g2;
         }
         const float* wo = ws + o * C * 9;
 #pragma unroll
         for (int c = 0; c < kMaxCh; ++c) {
             if (c < C) {
-                float s = acc[c];
+                float s = acc[c], s2 = acc2[c];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) s = fmaf(wo[c * 9 + t], v[t], s);
+                for (int t = 0; t < 9; ++t) {
+                    const float wv = wo[c * 9 + t];
+                    s = fmaf(wv, v[t], s);
+                    s2 = fmaf(wv, v2[t], s2);
+                }
                 acc[c] = s;
+                acc2[c] = s2;
             }
         }
     }
     float* gb = gx + (int64_t)blockIdx.y * C * hw + (int64_t)p * W + q;
 #pragma unroll
-    for (int c = 0; c < kMaxCh; ++c)
-        if (c < C) gb[c * hw] = acc[c];
+    for (int c = 0; c < kMaxCh; ++c) {
+        if (c < C) {
+            gb[c * hw] = acc[c];
+            if (two) gb[c * hw + 16 * (int64_t)W] = acc2[c];
+        }
+    }
 }
 
 // Partial weight and bias gradients: workgroup k sums, over the 16 x 16 tiles
@@ -376,6 +405,7 @@ xbar_status launched()
 }
 
 dim3 tile_grid(int B, int H, int W) { return dim3(((H + 15) / 16) * ((W + 15) / 16), B); }
+dim3 tall_grid(int B, int H, int W) { return dim3(((H + 31) / 32) * ((W + 15) / 16), B); }
 
 }  // namespace
 
@@ -409,9 +439,9 @@ xbar_status xbar_sg_conv_forward(int32_t B, int32_t H, int32_t W, int32_t C, int
         return XBAR_ERR_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     if (relu)
-        hipLaunchKernelGGL(sg_conv_fwd_kernel<true>, tile_grid(B, H, W), dim3(256), 0, s, H, W, C, O, x, w, bias, y);
+        hipLaunchKernelGGL(sg_conv_fwd_kernel<true>, tall_grid(B, H, W), dim3(256), 0, s, H, W, C, O, x, w, bias, y);
     else
-        hipLaunchKernelGGL(sg_conv_fwd_kernel<false>, tile_grid(B, H, W), dim3(256), 0, s, H, W, C, O, x, w, bias, y);
+        hipLaunchKernelGGL(sg_conv_fwd_kernel<false>, tall_grid(B, H, W), dim3(256), 0, s, H, W, C, O, x, w, bias, y);
     return launched();
 }
 
@@ -422,7 +452,7 @@ xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t 
     const int64_t hw = (int64_t)H * W, nx = (int64_t)B * C * hw * 4, ny = (int64_t)B * O * hw * 4;
     if (overlap(gx, nx, gy, ny) || (ymask && overlap(gx, nx, ymask, ny)) || overlap(gx, nx, w, (int64_t)O * C * 36))
         return XBAR_ERR_ARG;
-    hipLaunchKernelGGL(sg_conv_bwd_data_kernel, tile_grid(B, H, W), dim3(256), 0,
+    hipLaunchKernelGGL(sg_conv_bwd_data_kernel, tall_grid(B, H, W), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(hip_stream), H, W, C, O, gy, ymask, w, gx);
     return launched();
 }
