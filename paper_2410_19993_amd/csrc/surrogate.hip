@@ -23,7 +23,7 @@ namespace {
 constexpr int kMaxCh = XBAR_SG_MAX_CHANNELS;
 constexpr int kMaxLine = XBAR_SG_MAX_LINE;
 constexpr int kFeatures = XBAR_SG_FEATURES;
-constexpr int kParts = 256;            // workgroups of the weight-gradient pass (partial sums)
+constexpr int kParts = 512;            // workgroups of the weight-gradient pass (partial sums; two fit a CU)
 constexpr int kPer = (kMaxCh * kMaxCh * 9 + 255) / 256;
 
 __device__ __forceinline__ bool in_grid(int p, int q, int H, int W) { return p >= 0 && p < H && q >= 0 && q < W; }

@@ -134,7 +134,7 @@ def test_surrogate_calls_reject_bad_arguments():
     base = ctypes.addressof(buf)
     a, b, c, d = (ctypes.c_void_p(base + k * 65536) for k in range(4))
     E = _lib.XBAR_ERR_ARG
-    assert L.xbar_sg_workspace_floats(32, 32) == 256 * (32 * 32 * 9 + 32)
+    assert L.xbar_sg_workspace_floats(32, 32) == 512 * (32 * 32 * 9 + 32)
     assert L.xbar_sg_workspace_floats(33, 1) == -1 and L.xbar_sg_workspace_floats(1, 0) == -1
     # channels out of range, empty shapes, NULL pointers
     assert L.xbar_sg_conv_forward(1, 4, 4, 33, 2, 1, a, b, c, d, None) == E

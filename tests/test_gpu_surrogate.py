@@ -85,10 +85,10 @@ def test_conv_backward_data(B, H, W, C, O, masked):
     _assert_within(gx.cpu().numpy().astype(np.float64), ref, absref, O * 9, "conv backward data")
 
 
-@pytest.mark.parametrize("B,H,W,C,O", CONV_CASES + [(20, 64, 64, 3, 4), (3, 50, 37, 2, 5)])
+@pytest.mark.parametrize("B,H,W,C,O", CONV_CASES + [(40, 64, 64, 3, 4), (3, 50, 37, 2, 5)])
 @pytest.mark.parametrize("masked", [False, True])
 def test_conv_backward_weight(B, H, W, C, O, masked):
-    """Includes shapes with more 16 x 16 tiles than partial-sum workgroups (256)."""
+    """Includes a shape with more 16 x 16 tiles (640) than partial-sum workgroups (512)."""
     import torch
     rng = np.random.default_rng(11 + B * 1000 + H * 10 + C + O + masked)
     x, g = _rand(rng, B, C, H, W), _rand(rng, B, O, H, W)
