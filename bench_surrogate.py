@@ -15,8 +15,13 @@ Steps, all on the GPU through the library:
    step (features, 4 convolutions, readout and loss, 7 gradient kernels, update);
 3. held-out accuracy: relative current error of the surrogate and of G^T V against the
    exact currents, mean, 99th percentile and maximum, and the share of samples whose
-   worst column is within 1%;
-4. inference: surrogate currents for batches of held-out samples, timed.
+   worst column is within 1%; how well the error estimate ranks the errors; after
+   calibrating its scale kappa on a third set (--cal-maps maps, 99% coverage), the
+   held-out coverage, and at the tolerance (--tol) the share of samples it flags and
+   the errors of the rest;
+4. inference: surrogate currents for batches of held-out samples, timed;
+5. checked predictions: the surrogate, with every flagged sample re-solved exactly,
+   over the first 2048 held-out samples, timed.
 One JSON line goes to stdout at the end; progress goes to stderr.
 """
 from __future__ import annotations
@@ -50,6 +55,8 @@ def main():
     ap.add_argument("--channels", type=int, default=32)
     ap.add_argument("--seed", type=int, default=1005)
     ap.add_argument("--infer-batch", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=0.01, help="error-estimate threshold of the checked predictions")
+    ap.add_argument("--cal-maps", type=int, default=256, help="maps of the calibration set of the error estimate")
     args = ap.parse_args()
 
     import torch
@@ -67,6 +74,7 @@ def main():
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     held = sgm.solver_dataset(args.held_out_maps, args.vectors, m, n, seed=args.seed + 1)
+    cal = sgm.solver_dataset(args.cal_maps, args.vectors, m, n, seed=args.seed + 2)
     torch.cuda.synchronize()
     log(f"labels: {args.maps} maps x {args.vectors} vectors in {t_label:.1f} s "
         f"({args.maps / t_label:.0f} maps/s, {len(train) / t_label:.0f} solves/s)")
@@ -91,23 +99,46 @@ def main():
             want = (k % 200 == 199) or k == steps_per_epoch - 1
             loss = net.train_step(G, V, r, d, want_loss=want)
             if want:
-                run = loss
-                losses.append((step + 1, loss))
+                run = loss[0]
+                losses.append((step + 1, loss[0], loss[1]))
             step += 1
         log(f"epoch {ep + 1}/{args.epochs}: loss {run:.3e} after {step} steps, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
-    # 3. held-out accuracy
-    rel_sg, rel_0 = [], []
+    kappa = net.calibrate(cal, quantile=0.99)
+    log(f"error estimate calibrated on {len(cal)} samples: kappa {kappa:.2f}")
+
+    # 3. held-out accuracy and the error estimate
+    rel_sg, rel_0, ests = [], [], []
     for a in range(0, len(held), args.infer_batch):
         idx = torch.arange(a, min(len(held), a + args.infer_batch), device="cuda")
         G, V, r, _, I = held.batch(idx)
-        Ip = net.predict(G, V, r)
+        est = torch.empty((len(idx), n), dtype=torch.float64, device="cuda")
+        Ip = net.predict(G, V, r, est=est)
         I0 = held.I0[idx]
         rel_sg.append(((Ip - I).abs() / I.abs()).cpu().numpy())
         rel_0.append(((I0 - I).abs() / I.abs()).cpu().numpy())
-    rel_sg, rel_0 = np.concatenate(rel_sg), np.concatenate(rel_0)
+        ests.append(est.cpu().numpy())
+    rel_sg, rel_0, ests = np.concatenate(rel_sg), np.concatenate(rel_0), np.concatenate(ests)
+    worst_err, worst_est = rel_sg.max(axis=1), ests.max(axis=1)
+    rank = lambda x: np.argsort(np.argsort(x))
+    spearman = float(np.corrcoef(rank(worst_est), rank(worst_err))[0, 1])
+    flag = kappa * worst_est > args.tol
+    covered = float(np.mean(worst_err <= kappa * worst_est))
+    estimate = {"spearman_worst_column": spearman, "kappa": kappa, "calibration_samples": len(cal),
+                "held_out_covered": covered, "tol": args.tol, "flagged_share": float(flag.mean()),
+                "max_error_not_flagged": float(worst_err[~flag].max()) if (~flag).any() else None,
+                "mean_worst_error_not_flagged": float(worst_err[~flag].mean()) if (~flag).any() else None,
+                "share_not_flagged_within_tol": float(np.mean(worst_err[~flag] <= args.tol)) if (~flag).any()
+                else None}
+    for t in (0.01, 0.02, 0.05):
+        f = kappa * worst_est > t
+        estimate[f"at_{t:g}"] = {"flagged_share": float(f.mean()),
+                                 "max_error_not_flagged": float(worst_err[~f].max()) if (~f).any() else None}
+    log(f"error estimate: rank correlation {spearman:.2f}, kappa x estimate covers {100 * covered:.1f}% of held-out "
+        f"samples; at tol {args.tol}: {100 * flag.mean():.1f}% flagged, "
+        f"unflagged worst-column error max {estimate['max_error_not_flagged']}")
 
     def stats(e):
         worst = e.max(axis=1)
@@ -132,6 +163,24 @@ def main():
         net.predict(G, V, r, out)
     torch.cuda.synchronize()
     t_inf = (time.perf_counter() - t0) / reps
+    # 5. checked predictions: the surrogate, with the solver for every flagged sample
+    Bc = min(args.infer_batch, len(held))
+    G, V, r, _, I = held.batch(torch.arange(0, Bc, device="cuda"))
+    net.predict_checked(G, V, r, tol=args.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nflag = 0
+    chk_n = min(len(held), 2048)
+    for a in range(0, chk_n, Bc):
+        idx = torch.arange(a, min(chk_n, a + Bc), device="cuda")
+        G, V, r, _, I = held.batch(idx)
+        out, flagged = net.predict_checked(G, V, r, tol=args.tol)
+        nflag += int(flagged.sum())
+    torch.cuda.synchronize()
+    t_chk = time.perf_counter() - t0
+    estimate["checked_samples_per_s"] = chk_n / t_chk
+    estimate["checked_samples"] = chk_n
+    log(f"checked predictions: {chk_n} samples ({nflag} re-solved exactly) in {t_chk:.1f} s")
     result = {
         "metric": "surrogate_samples_per_s", "value": B / t_inf, "unit": "samples/s",
         "workload": f"{m}x{n} crossbars, r_wl = r_bl in [1, 5] ohm, r_src = r_sense = 50 ohm, synthetic",
@@ -142,9 +191,10 @@ def main():
         "train_samples_per_s": total * args.batch / t_train,
         "infer_ms_per_batch": 1e3 * t_inf, "infer_batch": B,
         "speedup_vs_solver_new_maps": (B / t_inf) / (args.maps / t_label),
-        "error_surrogate": acc_sg, "error_ideal_GtV": acc_0, "loss_curve": losses[-10:],
+        "error_surrogate": acc_sg, "error_ideal_GtV": acc_0, "error_estimate": estimate, "loss_curve": losses[-10:],
     }
     print(json.dumps(result), flush=True)
+    net.close()
 
 
 if __name__ == "__main__":

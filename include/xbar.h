@@ -310,20 +310,31 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
 /* Floats of workspace xbar_sg_conv_backward_weight needs (-1 for bad C, O). */
 int64_t xbar_sg_workspace_floats(int32_t C, int32_t O);
 
-/* Column readout and squared-error loss of the last map Y [B][m][n]:
- * yhat_j = mean_i Y[b][i][j], e = yhat - delta (delta [B][n] float64),
- * gY[b][i][j] = 2 e_j / (B n m) (the gradient of mean(e^2)), err2[b] = sum_j e_j^2. */
-xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, float* gY,
-                                 double* err2, void* stream);
+/* Column readouts and loss of the last map Y [B][2][m][n] (float32):
+ * yhat_j = mean_i Y[b][0][i][j] (the correction), s_j = mean_i Y[b][1][i][j] (the
+ * error estimate), e = yhat - delta (delta [B][n] float64), and the normalised log
+ * squared error t = (log(e^2 + eps) - mu) / sigma (eps, mu, sigma = XBAR_SG_EST_EPS,
+ * XBAR_SG_EST_MU, XBAR_SG_EST_SIGMA), held constant.  Loss mean(e^2) + lam
+ * mean((s - t)^2): gY[b][0][i][j] = 2 e_j / (B n m), gY[b][1][i][j] = lam 2 (s_j - t_j)
+ * / (B n m); err2 [B][2] = {sum_j e_j^2, sum_j (s_j - t_j)^2}.  lam >= 0.  (A caller
+ * that keeps the estimate out of the shared layers zeroes gY[b][1] after the last
+ * layer's weight gradient and before its input gradient.) */
+#define XBAR_SG_EST_EPS 1e-8
+#define XBAR_SG_EST_MU (-12.0)
+#define XBAR_SG_EST_SIGMA 4.0
+xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, double lam,
+                                 float* gY, double* err2, void* stream);
 
 /* One Adam step (bias-corrected, step t >= 1) over count float32 parameters p
  * with gradients g and moments m1, m2, all updated in place. */
 xbar_status xbar_sg_adam(int64_t count, float* p, const float* g, float* m1, float* m2, double lr, double b1,
                          double b2, double eps, int32_t t, void* stream);
 
-/* Surrogate currents I [B][n] float64 = (G^T V)_j (1 + mean_i Y[b][i][j]). */
+/* Surrogate currents I [B][n] float64 = (G^T V)_j (1 + yhat_j), yhat_j = mean_i Y[b][0][i][j],
+ * and, when est is not NULL, the predicted relative current error
+ * est [B][n] = exp((sigma s_j + mu) / 2) / |1 + yhat_j|, s_j = mean_i Y[b][1][i][j]. */
 xbar_status xbar_sg_predict(int32_t B, int32_t m, int32_t n, const float* Y, const double* G, const double* V,
-                            double* I, void* stream);
+                            double* I, double* est, void* stream);
 
 /* Static, NUL-terminated name of a status code. */
 const char* xbar_status_string(xbar_status s);

@@ -18,13 +18,21 @@ Definitions (the GPU library implements the same definitions in float32):
   conductance of row i, and 1e4 times the column mean of G_i'j 2 V_i' (the
   ideal current of column j over 0.5 m V).
 * Network: four 3 x 3 convolutions with zero padding of one crosspoint,
-  7 -> C -> C -> C -> 1 channels, a bias per output channel, ReLU after the
+  7 -> C -> C -> C -> 2 channels, a bias per output channel, ReLU after the
   first three.  conv(x)[o, y, x] = b[o] + sum_{c, dy, dx} w[o, c, dy, dx]
   x[c, y + dy - 1, x + dx - 1] (cross-correlation, as deep-learning
   convolutions are defined).
-* Column readout: yhat_j = mean over rows i of the last layer's map.
-* Loss: mean over samples and columns of (yhat_j - delta_j)^2.
-* Prediction: I_j = I0_j (1 + yhat_j).
+* Column readouts: yhat_j = mean over rows i of the last layer's channel 0
+  (the correction), s_j = mean over rows of channel 1 (the error estimate).
+* Loss: mean over samples and columns of e_j^2 with e = yhat - delta, plus
+  lam times the mean of (s_j - t_j)^2 with t_j = (log(e_j^2 + eps) - MU) / SIG,
+  the normalised log of the squared error, held constant (no gradient through
+  e).  The estimate term trains only the last layer's channel-1 weights: its
+  gradient does not flow into the shared layers, whose gradients are those of
+  the first term alone.
+* Prediction: I_j = I0_j (1 + yhat_j); relative current error estimate
+  exp((SIG s_j + MU) / 2) / |1 + yhat_j| (the current error I0 |yhat - delta|
+  over I).
 * Optimizer: Adam with bias correction (Kingma and Ba, 2015).
 """
 from __future__ import annotations
@@ -100,7 +108,7 @@ def conv2d_grad_weight(x: np.ndarray, g: np.ndarray):
 def init_params(channels: int = 32, seed: int = 0):
     """He-initialised weights [(w, b)] of the four layers, float64."""
     rng = np.random.default_rng(seed)
-    dims = [N_FEATURES, channels, channels, channels, 1]
+    dims = [N_FEATURES, channels, channels, channels, 2]
     out = []
     for k in range(4):
         fan_in = dims[k] * 9
@@ -122,22 +130,39 @@ def readout(Y: np.ndarray) -> np.ndarray:
     return Y[:, 0].mean(axis=1)
 
 
-def loss_and_grad(Y: np.ndarray, delta: np.ndarray):
-    """Loss and dLoss/dY for the column readout."""
+LAM, EPS, MU, SIG = 0.1, 1e-8, -12.0, 4.0
+
+
+def estimate(Y: np.ndarray) -> np.ndarray:
+    """Relative current error estimate [B][n] = exp((SIG s + MU) / 2) / |1 + yhat|, s =
+    mean over rows of Y[:, 1]: the error of the correction, |yhat - delta|, divided by
+    the predicted current over the ideal one, I / I0 = 1 + yhat."""
+    return np.exp(0.5 * (SIG * Y[:, 1].mean(axis=1) + MU)) / np.abs(1.0 + readout(Y))
+
+
+def loss_and_grad(Y: np.ndarray, delta: np.ndarray, lam: float = LAM, eps: float = EPS):
+    """(main loss, estimate loss, dLoss/dY) for the two column readouts."""
     B, _, m, n = Y.shape
     e = readout(Y) - delta
-    loss = float(np.mean(e * e))
-    dY = np.broadcast_to((2.0 * e / (B * n * m))[:, None, None, :], (B, 1, m, n)).copy()
-    return loss, dY
+    s = Y[:, 1].mean(axis=1)
+    t = (np.log(e * e + eps) - MU) / SIG
+    dY = np.empty_like(Y)
+    dY[:, 0] = (2.0 * e / (B * n * m))[:, None, :]
+    dY[:, 1] = (lam * 2.0 * (s - t) / (B * n * m))[:, None, :]
+    return float(np.mean(e * e)), float(np.mean((s - t) ** 2)), dY
 
 
 def backward(params, acts, dY):
-    """Gradients [(dw, db)] of every layer given dLoss/dY."""
+    """Gradients [(dw, db)] of every layer given dLoss/dY; the estimate channel's
+    gradient stops at the last layer (its input gradient uses channel 0 only)."""
     grads = [None] * 4
     g = dY
     for k in range(3, -1, -1):
         w, _ = params[k]
         grads[k] = conv2d_grad_weight(acts[k], g)
+        if k == 3:
+            g = g.copy()
+            g[:, 1] = 0.0
         if k > 0:
             g = conv2d_grad_input(g, w) * (acts[k] > 0.0)
     return grads
@@ -153,6 +178,6 @@ def adam_step(p, g, m1, m2, t, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def predict(params, G, V, r):
-    """Surrogate currents [B][n]."""
-    yhat = readout(forward(params, features(G, V, r))[-1])
-    return ideal_currents(G, V) * (1.0 + yhat)
+    """Surrogate currents [B][n] and their relative error estimates [B][n]."""
+    Y = forward(params, features(G, V, r))[-1]
+    return ideal_currents(G, V) * (1.0 + readout(Y)), estimate(Y)

@@ -94,9 +94,9 @@ def lib() -> ctypes.CDLL:
         L.xbar_sg_conv_backward_weight.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i64, vp]
         L.xbar_sg_workspace_floats.argtypes = [i32, i32]
         L.xbar_sg_workspace_floats.restype = i64
-        L.xbar_sg_readout_loss.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_readout_loss.argtypes = [i32, i32, i32, vp, vp, f64, vp, vp, vp]
         L.xbar_sg_adam.argtypes = [i64, vp, vp, vp, vp, f64, f64, f64, f64, i32, vp]
-        L.xbar_sg_predict.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_predict.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.xbar_status_string.restype = ctypes.c_char_p
         for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
@@ -223,9 +223,9 @@ def xbar_sg_workspace_floats(C, O) -> int:
     return int(lib().xbar_sg_workspace_floats(C, O))
 
 
-def xbar_sg_readout_loss(B, m, n, Y, delta, gY, err2, stream=None) -> None:
-    _check("xbar_sg_readout_loss", lib().xbar_sg_readout_loss(B, m, n, _ptr(Y), _ptr(delta), _ptr(gY), _ptr(err2),
-                                                              _s(stream)))
+def xbar_sg_readout_loss(B, m, n, Y, delta, lam, gY, err2, stream=None) -> None:
+    _check("xbar_sg_readout_loss", lib().xbar_sg_readout_loss(B, m, n, _ptr(Y), _ptr(delta), float(lam), _ptr(gY),
+                                                              _ptr(err2), _s(stream)))
 
 
 def xbar_sg_adam(p, g, m1, m2, lr, b1, b2, eps, t, stream=None) -> None:
@@ -233,5 +233,6 @@ def xbar_sg_adam(p, g, m1, m2, lr, b1, b2, eps, t, stream=None) -> None:
                                               float(b1), float(b2), float(eps), int(t), _s(stream)))
 
 
-def xbar_sg_predict(B, m, n, Y, G, V, I, stream=None) -> None:
-    _check("xbar_sg_predict", lib().xbar_sg_predict(B, m, n, _ptr(Y), _ptr(G), _ptr(V), _ptr(I), _s(stream)))
+def xbar_sg_predict(B, m, n, Y, G, V, I, est=None, stream=None) -> None:
+    _check("xbar_sg_predict", lib().xbar_sg_predict(B, m, n, _ptr(Y), _ptr(G), _ptr(V), _ptr(I), _ptr(est),
+                                                    _s(stream)))

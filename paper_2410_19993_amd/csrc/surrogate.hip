@@ -23,6 +23,9 @@ namespace {
 constexpr int kMaxCh = XBAR_SG_MAX_CHANNELS;
 constexpr int kMaxLine = XBAR_SG_MAX_LINE;
 constexpr int kFeatures = XBAR_SG_FEATURES;
+constexpr double kEstEps = XBAR_SG_EST_EPS;
+constexpr double kEstMu = XBAR_SG_EST_MU;
+constexpr double kEstSig = XBAR_SG_EST_SIGMA;
 constexpr int kParts = 512;            // workgroups of the weight-gradient pass (partial sums; two fit a CU)
 constexpr int kPer = (kMaxCh * kMaxCh * 9 + 255) / 256;
 
@@ -326,33 +329,54 @@ __global__ __launch_bounds__(256) void sg_reduce_parts_kernel(int nparts, int ne
     }
 }
 
-// yhat_j = mean_i Y[b][i][j]; e_j = yhat_j - delta_j; gY[b][i][j] = 2 e_j / (B n m);
-// err2[b] = sum_j e_j^2.  One workgroup per sample.
+// Column readouts of the last map Y[b][0..1] and the loss gradient:
+// yhat_j = mean_i Y[b][0][i][j], s_j = mean_i Y[b][1][i][j], e_j = yhat_j - delta_j,
+// t_j = (log(e_j^2 + eps) - mu) / sigma (held constant);  gY[b][0][i][j] = 2 e_j / (B n m),
+// gY[b][1][i][j] = lam 2 (s_j - t_j) / (B n m);  err2[b] = {sum_j e_j^2, sum_j (s_j - t_j)^2}.
+// One workgroup per sample.
 __global__ __launch_bounds__(256) void sg_readout_loss_kernel(int B, int m, int n, const float* __restrict__ Y,
-                                                              const double* __restrict__ delta,
+                                                              const double* __restrict__ delta, double lam,
                                                               float* __restrict__ gY, double* __restrict__ err2)
 {
-    __shared__ double red[256];
+    __shared__ double red[2][256];
     const int b = blockIdx.x;
-    const float* yb = Y + (int64_t)b * m * n;
-    float* gb = gY + (int64_t)b * m * n;
+    const int64_t mn = (int64_t)m * n;
+    const float* y0 = Y + (int64_t)b * 2 * mn;
+    const float* y1 = y0 + mn;
+    float* g0 = gY + (int64_t)b * 2 * mn;
+    float* g1 = g0 + mn;
     const double scale = 2.0 / ((double)B * n * m);
-    double e2 = 0.0;
+    double e2 = 0.0, d2 = 0.0;
     for (int j = threadIdx.x; j < n; j += 256) {
-        double s = 0.0;
-        for (int i = 0; i < m; ++i) s += yb[(int64_t)i * n + j];
-        const double e = s / m - delta[(int64_t)b * n + j];
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < m; ++i) {
+            s0 += y0[(int64_t)i * n + j];
+            s1 += y1[(int64_t)i * n + j];
+        }
+        const double e = s0 / m - delta[(int64_t)b * n + j];
+        const double d = s1 / m - (log(e * e + kEstEps) - kEstMu) / kEstSig;
         e2 += e * e;
-        const float g = (float)(scale * e);
-        for (int i = 0; i < m; ++i) gb[(int64_t)i * n + j] = g;
+        d2 += d * d;
+        const float ga = (float)(scale * e), gb = (float)(lam * scale * d);
+        for (int i = 0; i < m; ++i) {
+            g0[(int64_t)i * n + j] = ga;
+            g1[(int64_t)i * n + j] = gb;
+        }
     }
-    red[threadIdx.x] = e2;
+    red[0][threadIdx.x] = e2;
+    red[1][threadIdx.x] = d2;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) err2[b] = red[0];
+    if (threadIdx.x == 0) {
+        err2[2 * b] = red[0][0];
+        err2[2 * b + 1] = red[1][0];
+    }
 }
 
 // Adam with bias correction; c1 = 1 - b1^t, c2 = 1 - b2^t.
@@ -370,22 +394,28 @@ __global__ void sg_adam_kernel(int64_t count, float* __restrict__ p, const float
     p[e] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
-// I[b][j] = (sum_i G[b][i][j] V[b][i]) (1 + mean_i Y[b][i][j]).
+// I[b][j] = (sum_i G[b][i][j] V[b][i]) (1 + yhat_j), yhat_j = mean_i Y[b][0][i][j];
+// est[b][j] = exp((sigma mean_i Y[b][1][i][j] + mu) / 2) / |1 + yhat_j|, the predicted
+// relative current error (skipped when est is null).
 __global__ void sg_predict_kernel(int B, int m, int n, const float* __restrict__ Y, const double* __restrict__ G,
-                                  const double* __restrict__ V, double* __restrict__ I)
+                                  const double* __restrict__ V, double* __restrict__ I, double* __restrict__ est)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (j >= n) return;
-    const double* gb = G + (int64_t)b * m * n;
-    const float* yb = Y + (int64_t)b * m * n;
+    const int64_t mn = (int64_t)m * n;
+    const double* gb = G + (int64_t)b * mn;
+    const float* y0 = Y + (int64_t)b * 2 * mn;
+    const float* y1 = y0 + mn;
     const double* vb = V + (int64_t)b * m;
-    double i0 = 0.0, s = 0.0;
+    double i0 = 0.0, s0 = 0.0, s1 = 0.0;
     for (int i = 0; i < m; ++i) {
         i0 += gb[(int64_t)i * n + j] * vb[i];
-        s += yb[(int64_t)i * n + j];
+        s0 += y0[(int64_t)i * n + j];
+        s1 += y1[(int64_t)i * n + j];
     }
-    I[(int64_t)b * n + j] = i0 * (1.0 + s / m);
+    I[(int64_t)b * n + j] = i0 * (1.0 + s0 / m);
+    if (est) est[(int64_t)b * n + j] = exp(0.5 * (kEstSig * s1 / m + kEstMu)) / fabs(1.0 + s0 / m);
 }
 
 bool shape_ok(int32_t B, int32_t H, int32_t W) { return B >= 1 && B <= 65535 && H >= 1 && W >= 1; }
@@ -477,15 +507,16 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
     return launched();
 }
 
-xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, float* gY,
-                                 double* err2, void* hip_stream)
+xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, double lam,
+                                 float* gY, double* err2, void* hip_stream)
 {
-    if (!shape_ok(B, m, n) || !Y || !delta || !gY || !err2) return XBAR_ERR_ARG;
-    const int64_t ny = (int64_t)B * m * n * 4;
-    if (overlap(gY, ny, Y, ny) || overlap(gY, ny, delta, (int64_t)B * n * 8) || overlap(err2, (int64_t)B * 8, gY, ny))
+    if (!shape_ok(B, m, n) || !Y || !delta || !gY || !err2 || !(lam >= 0.0)) return XBAR_ERR_ARG;
+    const int64_t ny = (int64_t)B * 2 * m * n * 4;
+    if (overlap(gY, ny, Y, ny) || overlap(gY, ny, delta, (int64_t)B * n * 8) ||
+        overlap(err2, (int64_t)B * 16, gY, ny) || overlap(err2, (int64_t)B * 16, Y, ny))
         return XBAR_ERR_ARG;
     hipLaunchKernelGGL(sg_readout_loss_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream), B, m,
-                       n, Y, delta, gY, err2);
+                       n, Y, delta, lam, gY, err2);
     return launched();
 }
 
@@ -503,15 +534,16 @@ xbar_status xbar_sg_adam(int64_t count, float* p, const float* g, float* m1, flo
 }
 
 xbar_status xbar_sg_predict(int32_t B, int32_t m, int32_t n, const float* Y, const double* G, const double* V,
-                            double* I, void* hip_stream)
+                            double* I, double* est, void* hip_stream)
 {
     if (!shape_ok(B, m, n) || !Y || !G || !V || !I) return XBAR_ERR_ARG;
     const int64_t ni = (int64_t)B * n * 8;
-    if (overlap(I, ni, Y, (int64_t)B * m * n * 4) || overlap(I, ni, G, (int64_t)B * m * n * 8) ||
-        overlap(I, ni, V, (int64_t)B * m * 8))
+    if (overlap(I, ni, Y, (int64_t)B * 2 * m * n * 4) || overlap(I, ni, G, (int64_t)B * m * n * 8) ||
+        overlap(I, ni, V, (int64_t)B * m * 8) || (est && overlap(est, ni, I, ni)) ||
+        (est && overlap(est, ni, Y, (int64_t)B * 2 * m * n * 4)))
         return XBAR_ERR_ARG;
     hipLaunchKernelGGL(sg_predict_kernel, dim3((n + 255) / 256, B), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(hip_stream), B, m, n, Y, G, V, I);
+                       reinterpret_cast<hipStream_t>(hip_stream), B, m, n, Y, G, V, I, est);
     return launched();
 }
 

@@ -9,10 +9,16 @@ PlanLanes) produces the training targets and stays the reference for the error.
 Network: 7 features per crosspoint (log10 G + 5, 2 V_i, (r - 3) / 2, column and
 row position, and the row's mean conductance and the column's mean G 2 V, which set
 the drops across the source and sense resistors at the line ends), four 3 x 3
-convolutions 7 -> C -> C -> C -> 1 with ReLU after the first three, and the mean over rows of the last map as yhat_j.  Loss: mean
-squared error of yhat against delta; optimizer: Adam.  Every step (features,
-convolutions, their gradients, readout, loss, update, prediction) runs in the
+convolutions 7 -> C -> C -> C -> 2 with ReLU after the first three.  The row means of
+the last map's two channels are the correction yhat_j and the error estimate s_j.
+Loss: mean squared error of yhat against delta, plus lam times the squared error of
+s against the normalised log((yhat - delta)^2 + eps), that target held constant; the
+second term trains the last layer's estimate channel only, so the correction keeps
+the shared layers to itself.  Optimizer: Adam.  Every step (features,
+convolutions, their gradients, readouts, loss, update, prediction) runs in the
 library's kernels (xbar_sg_*); torch only holds the device buffers.
+predict_checked() re-solves with the exact solver every sample whose estimate
+exceeds a tolerance.
 """
 from __future__ import annotations
 
@@ -37,13 +43,13 @@ class Surrogate:
     that the untrained network predicts the ideal currents G^T V exactly."""
 
     def __init__(self, channels: int = 32, seed: int = 0, lr: float = 1e-3, betas=(0.9, 0.999),
-                 eps: float = 1e-8, zero_last: bool = True):
+                 eps: float = 1e-8, zero_last: bool = True, lam: float = 0.1):
         torch = _torch()
         if not 1 <= channels <= 32:
             raise ValueError("channels must be in [1, 32]")
         self.C = int(channels)
-        self.dims = [N_FEATURES, self.C, self.C, self.C, 1]
-        self.lr, self.betas, self.eps = float(lr), tuple(betas), float(eps)
+        self.dims = [N_FEATURES, self.C, self.C, self.C, 2]
+        self.lr, self.betas, self.eps, self.lam = float(lr), tuple(betas), float(eps), float(lam)
         self.t = 0
         sizes = []
         for k in range(4):
@@ -64,6 +70,8 @@ class Surrogate:
         self.m2 = torch.zeros_like(self.params)
         self.work = torch.empty(_lib.xbar_sg_workspace_floats(self.C, self.C), dtype=torch.float32, device="cuda")
         self._buf_shape = None
+        self._solvers = {}
+        self.kappa = 1.0
 
     # -- parameter views -----------------------------------------------------------------
     def _views(self, flat):
@@ -99,10 +107,10 @@ class Surrogate:
         f = dict(dtype=torch.float32, device="cuda")
         self.X = torch.empty((B, N_FEATURES, m, n), **f)
         self.acts = [torch.empty((B, self.C, m, n), **f) for _ in range(3)]
-        self.Y = torch.empty((B, 1, m, n), **f)
-        self.gY = torch.empty((B, 1, m, n), **f)
+        self.Y = torch.empty((B, 2, m, n), **f)
+        self.gY = torch.empty((B, 2, m, n), **f)
         self.ga = [torch.empty((B, self.C, m, n), **f) for _ in range(2)]
-        self.err2 = torch.empty(B, dtype=torch.float64, device="cuda")
+        self.err2 = torch.empty((B, 2), dtype=torch.float64, device="cuda")
         self._buf_shape = (B, m, n)
 
     @staticmethod
@@ -111,7 +119,7 @@ class Surrogate:
 
     # -- steps ---------------------------------------------------------------------------
     def forward(self, G, V, r):
-        """Last map Y [B][1][m][n] for G [B][m][n], V [B][m], r [B] (float64 device tensors)."""
+        """Last map Y [B][2][m][n] for G [B][m][n], V [B][m], r [B] (float64 device tensors)."""
         B, m, n = (int(x) for x in G.shape)
         self._buffers(B, m, n)
         s = self._stream()
@@ -125,12 +133,12 @@ class Surrogate:
 
     def train_step(self, G, V, r, delta, want_loss: bool = True):
         """One forward, backward and Adam step on a batch (delta [B][n] float64 device
-        tensor).  Returns the batch loss mean((yhat - delta)^2), which waits for the
-        step to finish, or None when want_loss is false."""
+        tensor).  Returns (mean (yhat - delta)^2, mean (s - log(e^2 + eps))^2), which
+        waits for the step to finish, or None when want_loss is false."""
         B, m, n = (int(x) for x in G.shape)
         self.forward(G, V, r)
         s = self._stream()
-        _lib.xbar_sg_readout_loss(B, m, n, self.Y, delta, self.gY, self.err2, s)
+        _lib.xbar_sg_readout_loss(B, m, n, self.Y, delta, self.lam, self.gY, self.err2, s)
         ins = [self.X] + self.acts                  # input of layer k
         gv = self._views(self.grads)
         wv = self._views(self.params)
@@ -139,6 +147,8 @@ class Surrogate:
             mask = self.acts[k] if k < 3 else None   # ReLU output of layer k
             C, O = self.dims[k], self.dims[k + 1]
             _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, mask, gv[k][0], gv[k][1], self.work, s)
+            if k == 3:
+                self.gY[:B, 1].zero_()              # the estimate trains the last layer only
             if k > 0:
                 g_in = self.ga[k % 2]
                 _lib.xbar_sg_conv_backward_data(B, m, n, C, O, g_out, mask, wv[k][0], g_in, s)
@@ -148,17 +158,69 @@ class Surrogate:
                           self.eps, self.t, s)
         if not want_loss:
             return None
-        return float(self.err2[:B].cpu().numpy().sum()) / (B * n)
+        e = self.err2[:B].cpu().numpy().sum(axis=0) / (B * n)
+        return float(e[0]), float(e[1])
 
-    def predict(self, G, V, r, out=None):
-        """Surrogate currents I [B][n] float64 = (G^T V)_j (1 + yhat_j)."""
+    def predict(self, G, V, r, out=None, est=None):
+        """Surrogate currents I [B][n] float64 = (G^T V)_j (1 + yhat_j); when est (a
+        [B][n] float64 tensor) is given, it receives the predicted relative errors."""
         torch = _torch()
         B, m, n = (int(x) for x in G.shape)
         self.forward(G, V, r)
         if out is None:
             out = torch.empty((B, n), dtype=torch.float64, device="cuda")
-        _lib.xbar_sg_predict(B, m, n, self.Y, G, V, out, self._stream())
+        _lib.xbar_sg_predict(B, m, n, self.Y, G, V, out, est, self._stream())
         return out
+
+    def calibrate(self, data: "Dataset", quantile: float = 0.99, batch: int = 256) -> float:
+        """Set kappa so that kappa times the largest estimated error of a sample covers its
+        largest actual relative current error on `quantile` of the samples of `data`
+        (solver-labelled samples the network was not trained on: a split-conformal
+        calibration).  Returns kappa."""
+        torch = _torch()
+        n = int(data.G.shape[2])
+        ratios = []
+        for a in range(0, len(data), batch):
+            idx = torch.arange(a, min(len(data), a + batch), device="cuda")
+            G, V, r, _, I = data.batch(idx)
+            est = torch.empty((len(idx), n), dtype=torch.float64, device="cuda")
+            Ip = self.predict(G, V, r, est=est)
+            worst = ((Ip - I).abs() / I.abs()).max(dim=1).values
+            ratios.append((worst / est.max(dim=1).values).cpu().numpy())
+        self.kappa = float(np.quantile(np.concatenate(ratios), quantile))
+        return self.kappa
+
+    def predict_checked(self, G, V, r, tol: float = 0.01, r_src: float = 50.0, r_sense: float = 50.0,
+                        lanes: int = 3):
+        """Currents for every sample, from the surrogate where kappa times its error
+        estimate is at most tol in every column (kappa = 1 until calibrate()), and from
+        the exact solver (float64, through PlanLanes, one plan set per segment resistance)
+        for the others.  Returns (I, flagged),
+        flagged a host bool array of the samples that were solved exactly.  The plans are
+        kept for later calls until close()."""
+        torch = _torch()
+        B, m, n = (int(x) for x in G.shape)
+        est = torch.empty((B, n), dtype=torch.float64, device="cuda")
+        out = self.predict(G, V, r, est=est)
+        flagged = (self.kappa * est.max(dim=1).values > tol).cpu().numpy()
+        idx = np.nonzero(flagged)[0]
+        if len(idx):
+            rs = r.cpu().numpy()
+            for lv in np.unique(rs[idx]):
+                sel = idx[rs[idx] == lv]
+                key = (float(lv), float(r_src), float(r_sense), int(lanes))
+                pl = self._solvers.get(key)
+                if pl is None:
+                    pl = self._solvers[key] = PlanLanes(key[0], key[0], key[1], key[2], lanes=key[3], max_batch=1)
+                pl.currents([G[k] for k in sel], [V[k:k + 1] for k in sel], [out[k:k + 1] for k in sel])
+                pl.check()
+        return out, flagged
+
+    def close(self) -> None:
+        """Free the plans predict_checked keeps (one PlanLanes per segment resistance)."""
+        for pl in self._solvers.values():
+            pl.close()
+        self._solvers.clear()
 
 
 class Dataset:
@@ -213,10 +275,10 @@ def targets_of(ds: Dataset):
     m = int(ds.G.shape[1])
     I0 = torch.empty((S, n), dtype=torch.float64, device="cuda")
     step = 4096
-    zero = torch.zeros((min(step, S), 1, m, n), dtype=torch.float32, device="cuda")
+    zero = torch.zeros((min(step, S), 2, m, n), dtype=torch.float32, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
     for a in range(0, S, step):
         idx = torch.arange(a, min(S, a + step), device="cuda")
         Gb = ds.G[idx // ds.vectors].contiguous()
-        _lib.xbar_sg_predict(len(idx), m, n, zero, Gb, ds.V[idx].contiguous(), I0[a:a + len(idx)], st)
+        _lib.xbar_sg_predict(len(idx), m, n, zero, Gb, ds.V[idx].contiguous(), I0[a:a + len(idx)], None, st)
     return (ds.I - I0) / I0, I0

@@ -122,19 +122,22 @@ def test_features_readout_predict_adam():
     ref = osg.features(G, V, r)
     assert np.allclose(X.cpu().numpy(), ref, rtol=2 * U32, atol=2 * U32 * 4)
 
-    Y = _rand(rng, B, 1, m, n)
+    Y = _rand(rng, B, 2, m, n)
     delta = rng.normal(scale=0.1, size=(B, n))
-    gY = torch.empty((B, 1, m, n), dtype=torch.float32, device="cuda")
-    err2 = torch.empty(B, dtype=torch.float64, device="cuda")
-    L.xbar_sg_readout_loss(B, m, n, _t(Y, torch.float32), _t(delta), gY, err2)
-    loss, dY = osg.loss_and_grad(Y, delta)
-    assert float(err2.cpu().numpy().sum()) / (B * n) == pytest.approx(loss, rel=1e-12)
+    gY = torch.empty((B, 2, m, n), dtype=torch.float32, device="cuda")
+    err2 = torch.empty((B, 2), dtype=torch.float64, device="cuda")
+    L.xbar_sg_readout_loss(B, m, n, _t(Y, torch.float32), _t(delta), osg.LAM, gY, err2)
+    loss, est_loss, dY = osg.loss_and_grad(Y, delta)
+    e2 = err2.cpu().numpy().sum(axis=0) / (B * n)
+    assert e2[0] == pytest.approx(loss, rel=1e-12) and e2[1] == pytest.approx(est_loss, rel=1e-12)
     assert np.allclose(gY.cpu().numpy(), dY, rtol=2 * U32, atol=0)
 
     I = torch.empty((B, n), dtype=torch.float64, device="cuda")
-    L.xbar_sg_predict(B, m, n, _t(Y, torch.float32), _t(G), _t(V), I)
+    est = torch.empty((B, n), dtype=torch.float64, device="cuda")
+    L.xbar_sg_predict(B, m, n, _t(Y, torch.float32), _t(G), _t(V), I, est)
     refI = osg.ideal_currents(G, V) * (1.0 + osg.readout(Y))
     assert np.allclose(I.cpu().numpy(), refI, rtol=1e-12, atol=0)
+    assert np.allclose(est.cpu().numpy(), osg.estimate(Y), rtol=1e-12, atol=0)
 
     p, g = _rand(rng, 1000), _rand(rng, 1000)
     m1, m2 = np.zeros(1000), np.zeros(1000)
@@ -166,8 +169,8 @@ def test_network_gradients_and_update_match_oracle():
     loss = net.train_step(_t(G), _t(V), _t(r), _t(delta))
     X = osg.features(G, V, r)
     acts = osg.forward(params, _f32(X))
-    ref_loss, dY = osg.loss_and_grad(acts[-1], delta)
-    assert loss == pytest.approx(ref_loss, rel=1e-3)
+    ref_loss, ref_est, dY = osg.loss_and_grad(acts[-1], delta)
+    assert loss[0] == pytest.approx(ref_loss, rel=1e-3) and loss[1] == pytest.approx(ref_est, rel=1e-3)
     grads = osg.backward(params, acts, dY)
     gv = net._views(net.grads)
     for k in range(4):
@@ -183,10 +186,12 @@ def test_network_gradients_and_update_match_oracle():
             assert np.allclose(new[k][part], p1, rtol=0, atol=2e-6), (k, part)
 
 
-def test_training_beats_ideal_currents():
+def test_training_beats_ideal_currents_and_flags_its_errors():
     """Trained on oracle-labelled 16 x 16 crossbars, the surrogate's currents on held-out
     maps are closer to the exact currents than G^T V is (by at least a factor 2 in mean
-    relative error)."""
+    relative error).  Its error estimate ranks its errors: the samples it flags (the
+    largest fifth of the estimates) have larger actual errors on average than the rest,
+    and predict_checked returns the exact currents for them."""
     import torch
 
     import paper_2410_19993_amd.surrogate as sgm
@@ -208,16 +213,32 @@ def test_training_beats_ideal_currents():
     dt = osg.targets(It, Gt, Vt)
     net = sgm.Surrogate(channels=16, seed=1, lr=3e-3)
     Gd, Vd, rd, dd = _t(Gt), _t(Vt), _t(rt), _t(dt)
-    log("case surrogate training: 384 samples of 16 x 16, 400 steps of 32")
+    log("case surrogate training: 384 samples of 16 x 16, 600 steps of 32")
     g = torch.Generator().manual_seed(5)
-    for step in range(400):
+    for step in range(600):
         idx = torch.randint(0, len(Gt), (32,), generator=g).cuda()
         net.train_step(Gd[idx].contiguous(), Vd[idx].contiguous(), rd[idx].contiguous(), dd[idx].contiguous(),
                        want_loss=False)
-    I_sg = net.predict(_t(Gh), _t(Vh), _t(rh)).cpu().numpy()
+    est = torch.empty((len(Gh), n), dtype=torch.float64, device="cuda")
+    I_sg = net.predict(_t(Gh), _t(Vh), _t(rh), est=est).cpu().numpy()
     I0 = osg.ideal_currents(Gh, Vh)
-    e_sg = float(np.mean(np.abs(I_sg - Ih) / np.abs(Ih)))
+    err = np.abs(I_sg - Ih) / np.abs(Ih)
+    e_sg = float(err.mean())
     e_0 = float(np.mean(np.abs(I0 - Ih) / np.abs(Ih)))
     log(f"  held-out mean relative error: surrogate {e_sg:.4f}, G^T V {e_0:.4f}")
     assert np.all(np.isfinite(I_sg))
     assert e_sg < 0.5 * e_0
+
+    worst_est = est.cpu().numpy().max(axis=1)
+    worst_err = err.max(axis=1)
+    tol = float(np.quantile(worst_est, 0.8))
+    hi = worst_est > tol
+    log(f"  flagged {hi.sum()} of {len(hi)}: mean worst error {worst_err[hi].mean():.4f} flagged, "
+        f"{worst_err[~hi].mean():.4f} not flagged")
+    assert hi.any() and (~hi).any()
+    assert worst_err[hi].mean() > worst_err[~hi].mean()
+    I_chk, flagged = net.predict_checked(_t(Gh), _t(Vh), _t(rh), tol=tol)
+    assert np.array_equal(flagged, hi)
+    I_chk = I_chk.cpu().numpy()
+    assert np.abs(I_chk[hi] - Ih[hi]).max() <= 1e-10 * np.abs(Ih[hi]).max()
+    assert np.array_equal(I_chk[~hi], I_sg[~hi])

@@ -68,11 +68,19 @@ def test_backward_matches_finite_differences():
     X = sg.features(G, V, np.array([2.0, 4.0]))
     delta = rng.normal(scale=0.1, size=(2, 5))
 
-    def loss(ps):
-        return sg.loss_and_grad(sg.forward(ps, X)[-1], delta)[0]
+    def loss(ps, k):
+        """Layers 0-2 follow the main loss alone; the last layer the main loss plus lam
+        times the estimate loss with its target frozen at the unperturbed error."""
+        Y = sg.forward(ps, X)[-1]
+        e = sg.readout(Y) - delta
+        s = Y[:, 1].mean(axis=1)
+        main = float(np.mean(e * e))
+        return main + (sg.LAM * float(np.mean((s - t_frozen) ** 2)) if k == 3 else 0.0)
 
     acts = sg.forward(params, X)
-    _, dY = sg.loss_and_grad(acts[-1], delta)
+    e0 = sg.readout(acts[-1]) - delta
+    t_frozen = (np.log(e0 * e0 + sg.EPS) - sg.MU) / sg.SIG
+    _, _, dY = sg.loss_and_grad(acts[-1], delta)
     grads = sg.backward(params, acts, dY)
     h = 1e-6
     for k in range(4):
@@ -82,9 +90,9 @@ def test_backward_matches_finite_differences():
             for ix in idx:
                 saved = arr[ix]
                 arr[ix] = saved + h
-                lp = loss(params)
+                lp = loss(params, k)
                 arr[ix] = saved - h
-                lm = loss(params)
+                lm = loss(params, k)
                 arr[ix] = saved
                 fd = (lp - lm) / (2 * h)
                 assert grads[k][part][ix] == pytest.approx(fd, rel=1e-5, abs=1e-10), (k, part, ix)
@@ -126,10 +134,21 @@ def test_targets_vanish_without_wire_resistance():
     assert np.all(sg.targets(real, G, V) < 0)
 
 
-def test_loss_gradient_of_the_readout():
-    """dLoss/dY spreads 2 e / (B n) evenly over the m rows of each column."""
-    Y = np.zeros((2, 1, 3, 4))
-    delta = np.arange(8.0).reshape(2, 4) / 10
-    loss, dY = sg.loss_and_grad(Y, delta)
+def test_loss_gradient_of_the_readouts():
+    """dLoss/dY spreads 2 e / (B n) evenly over the m rows of each column (channel 0)
+    and lam 2 (s - t) / (B n) (channel 1), t the normalised log of e^2 + eps; the
+    estimate loss is zero when s equals t, and the estimate is then |e|."""
+    Y = np.zeros((2, 2, 3, 4))
+    delta = np.arange(1.0, 9.0).reshape(2, 4) / 10
+    loss, est_loss, dY = sg.loss_and_grad(Y, delta)
     assert loss == pytest.approx(np.mean(delta ** 2))
     assert np.allclose(dY[:, 0].sum(axis=1), -2 * delta / 8)
+    t = (np.log(delta ** 2 + sg.EPS) - sg.MU) / sg.SIG
+    assert est_loss == pytest.approx(np.mean(t ** 2))
+    assert np.allclose(dY[:, 1].sum(axis=1), sg.LAM * 2 * (0 - t) / 8)
+    Y[:, 1] = t[:, None, :]
+    _, est_loss, dY = sg.loss_and_grad(Y, delta)
+    assert est_loss == pytest.approx(0.0, abs=1e-20) and np.allclose(dY[:, 1], 0.0)
+    assert np.allclose(sg.estimate(Y), np.sqrt(delta ** 2 + sg.EPS))     # yhat = 0 here
+    Y[:, 0] = -0.5
+    assert np.allclose(sg.estimate(Y), np.sqrt(delta ** 2 + sg.EPS) / 0.5)
