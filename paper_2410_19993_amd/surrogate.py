@@ -191,11 +191,12 @@ class Surrogate:
         return self.kappa
 
     def predict_checked(self, G, V, r, tol: float = 0.01, r_src: float = 50.0, r_sense: float = 50.0,
-                        lanes: int = 3):
+                        lanes: int = 3, precision: str = "fp64"):
         """Currents for every sample, from the surrogate where kappa times its error
         estimate is at most tol in every column (kappa = 1 until calibrate()), and from
-        the exact solver (float64, through PlanLanes, one plan set per segment resistance)
-        for the others.  Returns (I, flagged),
+        the exact solver (through PlanLanes, one plan set per segment resistance, in
+        `precision`: "fp64", or "fp32_ir" for float32 with float64 refinement) for the
+        others.  Returns (I, flagged),
         flagged a host bool array of the samples that were solved exactly.  The plans are
         kept for later calls until close()."""
         torch = _torch()
@@ -208,10 +209,11 @@ class Surrogate:
             rs = r.cpu().numpy()
             for lv in np.unique(rs[idx]):
                 sel = idx[rs[idx] == lv]
-                key = (float(lv), float(r_src), float(r_sense), int(lanes))
+                key = (float(lv), float(r_src), float(r_sense), int(lanes), precision)
                 pl = self._solvers.get(key)
                 if pl is None:
-                    pl = self._solvers[key] = PlanLanes(key[0], key[0], key[1], key[2], lanes=key[3], max_batch=1)
+                    pl = self._solvers[key] = PlanLanes(key[0], key[0], key[1], key[2], lanes=key[3], max_batch=1,
+                                                        precision=precision)
                 pl.currents([G[k] for k in sel], [V[k:k + 1] for k in sel], [out[k:k + 1] for k in sel])
                 pl.check()
         return out, flagged

@@ -242,3 +242,8 @@ def test_training_beats_ideal_currents_and_flags_its_errors():
     I_chk = I_chk.cpu().numpy()
     assert np.abs(I_chk[hi] - Ih[hi]).max() <= 1e-10 * np.abs(Ih[hi]).max()
     assert np.array_equal(I_chk[~hi], I_sg[~hi])
+    I_ir, flagged_ir = net.predict_checked(_t(Gh), _t(Vh), _t(rh), tol=tol, precision="fp32_ir")
+    I_ir = I_ir.cpu().numpy()
+    assert np.array_equal(flagged_ir, hi)
+    assert np.abs(I_ir[hi] - Ih[hi]).max() <= 1e-9 * np.abs(Ih[hi]).max()
+    net.close()
