@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import _lib
+from . import _check_tensor, _lib
 from .lanes import PlanLanes
 
 N_FEATURES = 7
@@ -118,9 +118,23 @@ class Surrogate:
         return _torch().cuda.current_stream().cuda_stream
 
     # -- steps ---------------------------------------------------------------------------
+    @staticmethod
+    def _check_inputs(G, V, r, delta=None):
+        """G [B][m][n], V [B][m], r [B] (and delta [B][n]): contiguous float64 device
+        tensors of exactly these shapes, checked before any kernel reads them."""
+        if getattr(G, "dim", lambda: 0)() != 3:
+            raise ValueError("G must be a [B][m][n] tensor")
+        B, m, n = (int(x) for x in G.shape)
+        _check_tensor("G", G, (B, m, n))
+        _check_tensor("V", V, (B, m))
+        _check_tensor("r", r, (B,))
+        if delta is not None:
+            _check_tensor("delta", delta, (B, n))
+        return B, m, n
+
     def forward(self, G, V, r):
         """Last map Y [B][2][m][n] for G [B][m][n], V [B][m], r [B] (float64 device tensors)."""
-        B, m, n = (int(x) for x in G.shape)
+        B, m, n = self._check_inputs(G, V, r)
         self._buffers(B, m, n)
         s = self._stream()
         _lib.xbar_sg_features(B, m, n, G, V, r, self.X, s)
@@ -133,9 +147,10 @@ class Surrogate:
 
     def train_step(self, G, V, r, delta, want_loss: bool = True):
         """One forward, backward and Adam step on a batch (delta [B][n] float64 device
-        tensor).  Returns (mean (yhat - delta)^2, mean (s - log(e^2 + eps))^2), which
-        waits for the step to finish, or None when want_loss is false."""
-        B, m, n = (int(x) for x in G.shape)
+        tensor).  Returns (mean (yhat - delta)^2, mean (s - t)^2), t the normalised log
+        squared error, which waits for the step to finish, or None when want_loss is
+        false."""
+        B, m, n = self._check_inputs(G, V, r, delta)
         self.forward(G, V, r)
         s = self._stream()
         _lib.xbar_sg_readout_loss(B, m, n, self.Y, delta, self.lam, self.gY, self.err2, s)
@@ -165,10 +180,13 @@ class Surrogate:
         """Surrogate currents I [B][n] float64 = (G^T V)_j (1 + yhat_j); when est (a
         [B][n] float64 tensor) is given, it receives the predicted relative errors."""
         torch = _torch()
-        B, m, n = (int(x) for x in G.shape)
-        self.forward(G, V, r)
+        B, m, n = self._check_inputs(G, V, r)
         if out is None:
             out = torch.empty((B, n), dtype=torch.float64, device="cuda")
+        _check_tensor("out", out, (B, n))
+        if est is not None:
+            _check_tensor("est", est, (B, n))
+        self.forward(G, V, r)
         _lib.xbar_sg_predict(B, m, n, self.Y, G, V, out, est, self._stream())
         return out
 

@@ -247,3 +247,29 @@ def test_training_beats_ideal_currents_and_flags_its_errors():
     assert np.array_equal(flagged_ir, hi)
     assert np.abs(I_ir[hi] - Ih[hi]).max() <= 1e-9 * np.abs(Ih[hi]).max()
     net.close()
+
+
+def test_surrogate_rejects_bad_inputs_before_launching():
+    """Wrong dtypes, shapes or layouts raise on the host: a float32 G of the right
+    shape would otherwise be read as float64, past its end."""
+    import torch
+
+    import paper_2410_19993_amd.surrogate as sgm
+    net = sgm.Surrogate(channels=4, seed=0)
+    B, m, n = 2, 5, 6
+    G = torch.full((B, m, n), 1e-5, dtype=torch.float64, device="cuda")
+    V = torch.zeros((B, m), dtype=torch.float64, device="cuda")
+    r = torch.full((B,), 2.0, dtype=torch.float64, device="cuda")
+    d = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+    log("case surrogate argument checks")
+    with pytest.raises(ValueError):
+        net.predict(G.float(), V, r)
+    with pytest.raises(ValueError):
+        net.predict(G, V[:, :4].contiguous(), r)
+    with pytest.raises(ValueError):
+        net.predict(G.transpose(1, 2), V, r)
+    with pytest.raises(ValueError):
+        net.train_step(G, V, r, d[:, :3].contiguous())
+    with pytest.raises(ValueError):
+        net.predict(G, V, r, est=torch.empty((B, n), dtype=torch.float32, device="cuda"))
+    assert net.predict(G, V, r).shape == (B, n)
