@@ -53,6 +53,7 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--depth", type=int, default=4, help="3 x 3 convolution layers")
     ap.add_argument("--seed", type=int, default=1005)
     ap.add_argument("--infer-batch", type=int, default=256)
     ap.add_argument("--tol", type=float, default=0.01, help="error-estimate threshold of the checked predictions")
@@ -80,7 +81,7 @@ def main():
         f"({args.maps / t_label:.0f} maps/s, {len(train) / t_label:.0f} solves/s)")
 
     # 2. training
-    net = sgm.Surrogate(channels=args.channels, seed=args.seed, lr=args.lr)
+    net = sgm.Surrogate(channels=args.channels, seed=args.seed, lr=args.lr, depth=args.depth)
     S = len(train)
     steps_per_epoch = S // args.batch
     total = steps_per_epoch * args.epochs
@@ -184,7 +185,8 @@ def main():
     result = {
         "metric": "surrogate_samples_per_s", "value": B / t_inf, "unit": "samples/s",
         "workload": f"{m}x{n} crossbars, r_wl = r_bl in [1, 5] ohm, r_src = r_sense = 50 ohm, synthetic",
-        "train_samples": S, "held_out_samples": len(held), "channels": args.channels, "epochs": args.epochs,
+        "train_samples": S, "held_out_samples": len(held), "channels": args.channels, "depth": args.depth,
+        "epochs": args.epochs,
         "batch": args.batch, "steps": total, "dtype": "f32 (network), f64 (labels, readout)",
         "label_solves_per_s": len(train) / t_label, "label_maps_per_s": args.maps / t_label,
         "train_s": t_train, "train_ms_per_step": 1e3 * t_train / max(total, 1),

@@ -17,9 +17,9 @@ Definitions (the GPU library implements the same definitions in float32):
   two line totals that set the drops at the line ends: 1e4 times the mean
   conductance of row i, and 1e4 times the column mean of G_i'j 2 V_i' (the
   ideal current of column j over 0.5 m V).
-* Network: four 3 x 3 convolutions with zero padding of one crosspoint,
-  7 -> C -> C -> C -> 2 channels, a bias per output channel, ReLU after the
-  first three.  conv(x)[o, y, x] = b[o] + sum_{c, dy, dx} w[o, c, dy, dx]
+* Network: 3 x 3 convolutions with zero padding of one crosspoint (four by
+  default), 7 -> C -> ... -> C -> 2 channels, a bias per output channel, ReLU
+  after all but the last.  conv(x)[o, y, x] = b[o] + sum_{c, dy, dx} w[o, c, dy, dx]
   x[c, y + dy - 1, x + dx - 1] (cross-correlation, as deep-learning
   convolutions are defined).
 * Column readouts: yhat_j = mean over rows i of the last layer's channel 0
@@ -105,23 +105,23 @@ def conv2d_grad_weight(x: np.ndarray, g: np.ndarray):
     return gw, g.sum(axis=(0, 2, 3))
 
 
-def init_params(channels: int = 32, seed: int = 0):
-    """He-initialised weights [(w, b)] of the four layers, float64."""
+def init_params(channels: int = 32, seed: int = 0, depth: int = 4):
+    """He-initialised weights [(w, b)] of the `depth` layers, float64."""
     rng = np.random.default_rng(seed)
-    dims = [N_FEATURES, channels, channels, channels, 2]
+    dims = [N_FEATURES] + [channels] * (depth - 1) + [2]
     out = []
-    for k in range(4):
+    for k in range(depth):
         fan_in = dims[k] * 9
         out.append((rng.normal(0.0, np.sqrt(2.0 / fan_in), (dims[k + 1], dims[k], 3, 3)), np.zeros(dims[k + 1])))
     return out
 
 
 def forward(params, X):
-    """Activations [X, a1, a2, a3, Y] (a_k after ReLU; Y the last map, [B][1][m][n])."""
+    """Activations [X, a1, ..., Y] (a_k after ReLU; Y the last map, [B][2][m][n])."""
     acts = [X]
     for k, (w, b) in enumerate(params):
         y = conv2d(acts[-1], w, b)
-        acts.append(np.maximum(y, 0.0) if k < 3 else y)
+        acts.append(np.maximum(y, 0.0) if k < len(params) - 1 else y)
     return acts
 
 
@@ -155,12 +155,13 @@ def loss_and_grad(Y: np.ndarray, delta: np.ndarray, lam: float = LAM, eps: float
 def backward(params, acts, dY):
     """Gradients [(dw, db)] of every layer given dLoss/dY; the estimate channel's
     gradient stops at the last layer (its input gradient uses channel 0 only)."""
-    grads = [None] * 4
+    last = len(params) - 1
+    grads = [None] * len(params)
     g = dY
-    for k in range(3, -1, -1):
+    for k in range(last, -1, -1):
         w, _ = params[k]
         grads[k] = conv2d_grad_weight(acts[k], g)
-        if k == 3:
+        if k == last:
             g = g.copy()
             g[:, 1] = 0.0
         if k > 0:

@@ -9,7 +9,8 @@ PlanLanes) produces the training targets and stays the reference for the error.
 Network: 7 features per crosspoint (log10 G + 5, 2 V_i, (r - 3) / 2, column and
 row position, and the row's mean conductance and the column's mean G 2 V, which set
 the drops across the source and sense resistors at the line ends), four 3 x 3
-convolutions 7 -> C -> C -> C -> 2 with ReLU after the first three.  The row means of
+convolutions 7 -> C -> ... -> C -> 2 (four layers by default, `depth`) with ReLU after
+all but the last.  The row means of
 the last map's two channels are the correction yhat_j and the error estimate s_j.
 Loss: mean squared error of yhat against delta, plus lam times the squared error of
 s against the normalised log((yhat - delta)^2 + eps), that target held constant; the
@@ -43,26 +44,29 @@ class Surrogate:
     that the untrained network predicts the ideal currents G^T V exactly."""
 
     def __init__(self, channels: int = 32, seed: int = 0, lr: float = 1e-3, betas=(0.9, 0.999),
-                 eps: float = 1e-8, zero_last: bool = True, lam: float = 0.1):
+                 eps: float = 1e-8, zero_last: bool = True, lam: float = 0.1, depth: int = 4):
         torch = _torch()
         if not 1 <= channels <= 32:
             raise ValueError("channels must be in [1, 32]")
+        if depth < 2:
+            raise ValueError("depth must be >= 2")
         self.C = int(channels)
-        self.dims = [N_FEATURES, self.C, self.C, self.C, 2]
+        self.L = int(depth)
+        self.dims = [N_FEATURES] + [self.C] * (self.L - 1) + [2]
         self.lr, self.betas, self.eps, self.lam = float(lr), tuple(betas), float(eps), float(lam)
         self.t = 0
         sizes = []
-        for k in range(4):
+        for k in range(self.L):
             sizes += [self.dims[k + 1] * self.dims[k] * 9, self.dims[k + 1]]
         self._sizes = sizes
         total = sum(sizes)
         rng = np.random.default_rng(seed)
         host = np.zeros(total, dtype=np.float32)
         off = 0
-        for k in range(4):
+        for k in range(self.L):
             nw = sizes[2 * k]
             w = rng.normal(0.0, np.sqrt(2.0 / (self.dims[k] * 9)), nw)
-            host[off:off + nw] = 0.0 if (zero_last and k == 3) else w
+            host[off:off + nw] = 0.0 if (zero_last and k == self.L - 1) else w
             off += nw + sizes[2 * k + 1]
         self.params = torch.from_numpy(host).cuda()
         self.grads = torch.zeros_like(self.params)
@@ -76,7 +80,7 @@ class Surrogate:
     # -- parameter views -----------------------------------------------------------------
     def _views(self, flat):
         out, off = [], 0
-        for k in range(4):
+        for k in range(self.L):
             nw, nb = self._sizes[2 * k], self._sizes[2 * k + 1]
             out.append((flat[off:off + nw], flat[off + nw:off + nw + nb]))
             off += nw + nb
@@ -89,15 +93,16 @@ class Surrogate:
     def state(self) -> dict:
         """Host copies of the weights and optimizer state (for checkpoints)."""
         return {"params": self.params.cpu().numpy(), "m1": self.m1.cpu().numpy(), "m2": self.m2.cpu().numpy(),
-                "t": self.t, "channels": self.C}
+                "t": self.t, "channels": self.C, "depth": self.L, "kappa": self.kappa}
 
     def load(self, state: dict) -> None:
         torch = _torch()
-        if int(state["channels"]) != self.C:
-            raise ValueError("checkpoint has a different width")
+        if int(state["channels"]) != self.C or int(state.get("depth", 4)) != self.L:
+            raise ValueError("checkpoint has a different width or depth")
         for name in ("params", "m1", "m2"):
             getattr(self, name).copy_(torch.from_numpy(np.asarray(state[name], dtype=np.float32)))
         self.t = int(state["t"])
+        self.kappa = float(state.get("kappa", 1.0))
 
     # -- buffers -------------------------------------------------------------------------
     def _buffers(self, B, m, n):
@@ -106,7 +111,7 @@ class Surrogate:
             return
         f = dict(dtype=torch.float32, device="cuda")
         self.X = torch.empty((B, N_FEATURES, m, n), **f)
-        self.acts = [torch.empty((B, self.C, m, n), **f) for _ in range(3)]
+        self.acts = [torch.empty((B, self.C, m, n), **f) for _ in range(self.L - 1)]
         self.Y = torch.empty((B, 2, m, n), **f)
         self.gY = torch.empty((B, 2, m, n), **f)
         self.ga = [torch.empty((B, self.C, m, n), **f) for _ in range(2)]
@@ -141,7 +146,7 @@ class Surrogate:
         x = self.X
         outs = self.acts + [self.Y]
         for k, (w, b) in enumerate(self._views(self.params)):
-            _lib.xbar_sg_conv_forward(B, m, n, self.dims[k], self.dims[k + 1], k < 3, x, w, b, outs[k], s)
+            _lib.xbar_sg_conv_forward(B, m, n, self.dims[k], self.dims[k + 1], k < self.L - 1, x, w, b, outs[k], s)
             x = outs[k]
         return self.Y[:B]
 
@@ -158,11 +163,12 @@ class Surrogate:
         gv = self._views(self.grads)
         wv = self._views(self.params)
         g_out = self.gY                             # dLoss / d(output of layer k)
-        for k in range(3, -1, -1):
-            mask = self.acts[k] if k < 3 else None   # ReLU output of layer k
+        last = self.L - 1
+        for k in range(last, -1, -1):
+            mask = self.acts[k] if k < last else None   # ReLU output of layer k
             C, O = self.dims[k], self.dims[k + 1]
             _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, mask, gv[k][0], gv[k][1], self.work, s)
-            if k == 3:
+            if k == last:
                 self.gY[:B, 1].zero_()              # the estimate trains the last layer only
             if k > 0:
                 g_in = self.ga[k % 2]

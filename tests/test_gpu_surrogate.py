@@ -150,10 +150,10 @@ def test_features_readout_predict_adam():
 
 
 def test_network_gradients_and_update_match_oracle():
-    """Surrogate.train_step: its gradients equal the oracle's backward pass at the
-    pre-step weights (norm-wise within 1e-3 per tensor: four float32 layers of at most
-    288-term sums, about 4 * 288 u = 7e-5, with a margin), and the new weights equal
-    the oracle's Adam step."""
+    """Surrogate.train_step on a five-layer network: its gradients equal the oracle's
+    backward pass at the pre-step weights (norm-wise within 1e-3 per tensor: five
+    float32 layers of at most 288-term sums, about 5 * 288 u = 9e-5, with a margin),
+    and the new weights equal the oracle's Adam step."""
     import torch
 
     import paper_2410_19993_amd.surrogate as sgm
@@ -163,9 +163,9 @@ def test_network_gradients_and_update_match_oracle():
     V = rng.uniform(0, 0.5, (B, m))
     r = rng.uniform(1, 5, B)
     delta = rng.normal(scale=0.05, size=(B, n))
-    net = sgm.Surrogate(channels=8, seed=3, lr=1e-3, zero_last=False)
+    net = sgm.Surrogate(channels=8, seed=3, lr=1e-3, zero_last=False, depth=5)
     params = [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for w, b in net.layers()]
-    log("case network gradients, channels 8, B=4 12x19")
+    log("case network gradients, channels 8, depth 5, B=4 12x19")
     loss = net.train_step(_t(G), _t(V), _t(r), _t(delta))
     X = osg.features(G, V, r)
     acts = osg.forward(params, _f32(X))
@@ -173,13 +173,13 @@ def test_network_gradients_and_update_match_oracle():
     assert loss[0] == pytest.approx(ref_loss, rel=1e-3) and loss[1] == pytest.approx(ref_est, rel=1e-3)
     grads = osg.backward(params, acts, dY)
     gv = net._views(net.grads)
-    for k in range(4):
+    for k in range(5):
         for part in range(2):
             got = gv[k][part].cpu().numpy().astype(np.float64).reshape(grads[k][part].shape)
             ref = grads[k][part]
             assert np.linalg.norm(got - ref) <= 1e-3 * np.linalg.norm(ref) + 1e-30, (k, part)
     new = [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for w, b in net.layers()]
-    for k in range(4):
+    for k in range(5):
         for part in range(2):
             g = gv[k][part].cpu().numpy().astype(np.float64).reshape(params[k][part].shape)
             p1, _, _ = osg.adam_step(params[k][part], g, 0.0, 0.0, 1, 1e-3)

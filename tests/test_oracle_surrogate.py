@@ -62,20 +62,20 @@ def test_conv_adjoints():
 
 def test_backward_matches_finite_differences():
     rng = np.random.default_rng(4)
-    params = sg.init_params(channels=3, seed=5)
+    params = sg.init_params(channels=3, seed=5, depth=5)
     G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (2, 4, 5)))
     V = rng.uniform(0, 0.5, (2, 4))
     X = sg.features(G, V, np.array([2.0, 4.0]))
     delta = rng.normal(scale=0.1, size=(2, 5))
 
     def loss(ps, k):
-        """Layers 0-2 follow the main loss alone; the last layer the main loss plus lam
+        """Layers 0-3 follow the main loss alone; the last layer the main loss plus lam
         times the estimate loss with its target frozen at the unperturbed error."""
         Y = sg.forward(ps, X)[-1]
         e = sg.readout(Y) - delta
         s = Y[:, 1].mean(axis=1)
         main = float(np.mean(e * e))
-        return main + (sg.LAM * float(np.mean((s - t_frozen) ** 2)) if k == 3 else 0.0)
+        return main + (sg.LAM * float(np.mean((s - t_frozen) ** 2)) if k == 4 else 0.0)
 
     acts = sg.forward(params, X)
     e0 = sg.readout(acts[-1]) - delta
@@ -83,7 +83,7 @@ def test_backward_matches_finite_differences():
     _, _, dY = sg.loss_and_grad(acts[-1], delta)
     grads = sg.backward(params, acts, dY)
     h = 1e-6
-    for k in range(4):
+    for k in range(5):
         for part in range(2):
             arr = params[k][part]
             idx = [tuple(rng.integers(0, s) for s in arr.shape) for _ in range(4)]
