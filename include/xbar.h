@@ -295,9 +295,12 @@ xbar_status xbar_sg_conv_forward(int32_t B, int32_t H, int32_t W, int32_t C, int
 
 /* Input gradient of a convolution: with g = gy, multiplied by [ymask > 0] when
  * ymask (the layer's ReLU output, same shape as gy) is not NULL,
- * gx[b][c][p][q] = sum_{o,dy,dx} w[o][c][dy][dx] g[b][o][p-dy+1][q-dx+1]. */
+ * gx[b][c][p][q] = sum_{o,dy,dx} w[o][c][dy][dx] g[b][o][p-dy+1][q-dx+1], multiplied
+ * by [xmask > 0] when xmask (the layer's input, the previous layer's ReLU output,
+ * same shape as gx) is not NULL: then gx is the gradient before that ReLU. */
 xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* gy,
-                                       const float* ymask, const float* w, float* gx, void* stream);
+                                       const float* ymask, const float* w, const float* xmask, float* gx,
+                                       void* stream);
 
 /* Weight and bias gradients, g masked as above: gw[o][c][dy][dx] = sum_{b,p,q}
  * g[b][o][p][q] x[b][c][p+dy-1][q+dx-1], gb[o] = sum g[b][o][p][q].  work:

@@ -90,7 +90,7 @@ def lib() -> ctypes.CDLL:
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.xbar_sg_features.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
         L.xbar_sg_conv_forward.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
-        L.xbar_sg_conv_backward_data.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_backward_data.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.xbar_sg_conv_backward_weight.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i64, vp]
         L.xbar_sg_workspace_floats.argtypes = [i32, i32]
         L.xbar_sg_workspace_floats.restype = i64
@@ -208,9 +208,10 @@ def xbar_sg_conv_forward(B, H, W, C, O, relu, x, w, b, y, stream=None) -> None:
                                                               _ptr(b), _ptr(y), _s(stream)))
 
 
-def xbar_sg_conv_backward_data(B, H, W, C, O, gy, ymask, w, gx, stream=None) -> None:
+def xbar_sg_conv_backward_data(B, H, W, C, O, gy, ymask, w, gx, xmask=None, stream=None) -> None:
     _check("xbar_sg_conv_backward_data", lib().xbar_sg_conv_backward_data(B, H, W, C, O, _ptr(gy), _ptr(ymask),
-                                                                          _ptr(w), _ptr(gx), _s(stream)))
+                                                                          _ptr(w), _ptr(xmask), _ptr(gx),
+                                                                          _s(stream)))
 
 
 def xbar_sg_conv_backward_weight(B, H, W, C, O, x, gy, ymask, gw, gb, work, stream=None) -> None:

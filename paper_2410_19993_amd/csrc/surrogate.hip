@@ -134,11 +134,16 @@ __global__ __launch_bounds__(256) void sg_conv_fwd_kernel(int H, int W, int C, i
 // Gradient of the layer's output g = gy (times [ymask > 0] when the layer has a
 // ReLU) with respect to its input:
 //     gx[b][c][p][q] = sum_{o, dy, dx} w[o][c][dy][dx] g[b][o][p - dy + 1][q - dx + 1].
-// As in the forward kernel, each thread takes two crosspoints 16 rows apart.
+// As in the forward kernel, each thread takes two crosspoints 16 rows apart.  With
+// xmask (the layer input, when it is a ReLU output) the result is written already
+// multiplied by [xmask > 0], the gradient before the previous layer's ReLU, so the
+// kernels that read it next need no mask.
 __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int C, int O,
                                                                const float* __restrict__ gy,
                                                                const float* __restrict__ ymask,
-                                                               const float* __restrict__ w, float* __restrict__ gx)
+                                                               const float* __restrict__ w,
+                                                               const float* __restrict__ xmask,
+                                                               float* __restrict__ gx)
 {
     __shared__ float ws[kMaxCh * kMaxCh * 9];
     for (int e = threadIdx.x; e < O * C * 9; e += 256) ws[e] = w[e];
@@ -190,12 +195,19 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int
             }
         }
     }
-    float* gb = gx + (int64_t)blockIdx.y * C * hw + (int64_t)p * W + q;
+    const int64_t xo = (int64_t)blockIdx.y * C * hw + (int64_t)p * W + q;
+    float* gb = gx + xo;
+    const float* xm = xmask ? xmask + xo : nullptr;
 #pragma unroll
     for (int c = 0; c < kMaxCh; ++c) {
         if (c < C) {
-            gb[c * hw] = acc[c];
-            if (two) gb[c * hw + 16 * (int64_t)W] = acc2[c];
+            float a = acc[c], a2 = acc2[c];
+            if (xm) {
+                if (!(xm[c * hw] > 0.0f)) a = 0.0f;
+                if (two && !(xm[c * hw + 16 * (int64_t)W] > 0.0f)) a2 = 0.0f;
+            }
+            gb[c * hw] = a;
+            if (two) gb[c * hw + 16 * (int64_t)W] = a2;
         }
     }
 }
@@ -209,6 +221,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int
 // the 3 x 3 window of x in registers, so each crosspoint costs three LDS reads of x
 // and one of g per output channel for 9 multiply-adds per output channel.
 constexpr int kXs = 18 * 18 + 1;        // LDS stride of a staged x channel (odd: spreads banks)
+constexpr int kGs = 257;                // LDS stride of a staged g channel (odd: spreads banks)
 constexpr int kOk = 4;                  // output channels per thread (256 / 32 groups of 8)
 
 __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, int W, int C, int O,
@@ -217,7 +230,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
                                                                  const float* __restrict__ ymask,
                                                                  float* __restrict__ part)
 {
-    __shared__ float gs[kMaxCh * 256];          // [o][16 x 16]
+    __shared__ float gs[kMaxCh * kGs];          // [o][16 x 16]
     __shared__ float xs[kMaxCh * kXs];          // [c][18 x 18]
     const int ne = O * C * 9;
     const int tw = (W + 15) / 16, th = (H + 15) / 16;
@@ -233,7 +246,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
         const int o = og + groups * k;
         const bool own = active && o < O;
         on[k] = own ? 1.0f : 0.0f;
-        orow[k] = (own ? o : 0) * 256;          // a valid row of gs either way
+        orow[k] = (own ? o : 0) * kGs;          // a valid row of gs either way
     }
     float acc[kOk][9];
 #pragma unroll
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
                 g = gy[off];
                 if (ymask && !(ymask[off] > 0.0f)) g = 0.0f;
             }
-            gs[e] = g;
+            gs[o * kGs + (e & 255)] = g;
         }
         for (int e = threadIdx.x; e < C * 324; e += 256) {
             const int cc = e / 324, k = e % 324;
@@ -291,7 +304,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
         }
         if (threadIdx.x < O) {
             float sb = 0.0f;
-            for (int e = 0; e < 256; ++e) sb += gs[threadIdx.x * 256 + e];
+            for (int e = 0; e < 256; ++e) sb += gs[threadIdx.x * kGs + e];
             accb += sb;
         }
     }
@@ -476,14 +489,16 @@ xbar_status xbar_sg_conv_forward(int32_t B, int32_t H, int32_t W, int32_t C, int
 }
 
 xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* gy,
-                                       const float* ymask, const float* w, float* gx, void* hip_stream)
+                                       const float* ymask, const float* w, const float* xmask, float* gx,
+                                       void* hip_stream)
 {
     if (!shape_ok(B, H, W) || !ch_ok(C, O) || !gy || !w || !gx) return XBAR_ERR_ARG;
     const int64_t hw = (int64_t)H * W, nx = (int64_t)B * C * hw * 4, ny = (int64_t)B * O * hw * 4;
-    if (overlap(gx, nx, gy, ny) || (ymask && overlap(gx, nx, ymask, ny)) || overlap(gx, nx, w, (int64_t)O * C * 36))
+    if (overlap(gx, nx, gy, ny) || (ymask && overlap(gx, nx, ymask, ny)) || overlap(gx, nx, w, (int64_t)O * C * 36) ||
+        (xmask && overlap(gx, nx, xmask, nx)))
         return XBAR_ERR_ARG;
     hipLaunchKernelGGL(sg_conv_bwd_data_kernel, tall_grid(B, H, W), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(hip_stream), H, W, C, O, gy, ymask, w, gx);
+                       reinterpret_cast<hipStream_t>(hip_stream), H, W, C, O, gy, ymask, w, xmask, gx);
     return launched();
 }
 

@@ -165,14 +165,15 @@ class Surrogate:
         g_out = self.gY                             # dLoss / d(output of layer k)
         last = self.L - 1
         for k in range(last, -1, -1):
-            mask = self.acts[k] if k < last else None   # ReLU output of layer k
+            # g_out is already the gradient before layer k's ReLU: the input gradient of
+            # layer k + 1 wrote it masked by [layer k's output > 0]
             C, O = self.dims[k], self.dims[k + 1]
-            _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, mask, gv[k][0], gv[k][1], self.work, s)
+            _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, None, gv[k][0], gv[k][1], self.work, s)
             if k == last:
                 self.gY[:B, 1].zero_()              # the estimate trains the last layer only
             if k > 0:
                 g_in = self.ga[k % 2]
-                _lib.xbar_sg_conv_backward_data(B, m, n, C, O, g_out, mask, wv[k][0], g_in, s)
+                _lib.xbar_sg_conv_backward_data(B, m, n, C, O, g_out, None, wv[k][0], g_in, xmask=ins[k], stream=s)
                 g_out = g_in
         self.t += 1
         _lib.xbar_sg_adam(self.params, self.grads, self.m1, self.m2, self.lr, self.betas[0], self.betas[1],

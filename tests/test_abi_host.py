@@ -142,7 +142,7 @@ def test_surrogate_calls_reject_bad_arguments():
     assert L.xbar_sg_conv_forward(0, 4, 4, 2, 2, 1, a, b, c, d, None) == E
     assert L.xbar_sg_conv_forward(1, 4, 0, 2, 2, 1, a, b, c, d, None) == E
     assert L.xbar_sg_conv_forward(1, 4, 4, 2, 2, 1, None, b, c, d, None) == E
-    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, None, None) == E
+    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, None, None, None) == E
     assert L.xbar_sg_features(1, 0, 4, a, b, c, d, None) == E
     assert L.xbar_sg_features(1, 4, 2049, a, b, c, d, None) == E
     assert L.xbar_sg_readout_loss(1, 4, 4, a, b, 0.1, None, d, None) == E
@@ -150,7 +150,9 @@ def test_surrogate_calls_reject_bad_arguments():
     assert L.xbar_sg_predict(1, 4, 4, a, b, c, None, None, None) == E
     # outputs overlapping inputs: y over x, gx over gy, I over Y
     assert L.xbar_sg_conv_forward(1, 4, 4, 2, 2, 1, a, b, c, ctypes.c_void_p(base + 16), None) == E
-    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, ctypes.c_void_p(base + 64), None) == E
+    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, None, ctypes.c_void_p(base + 64), None) == E
+    assert L.xbar_sg_conv_backward_data(1, 4, 4, 2, 2, a, None, b, ctypes.c_void_p(base + 3 * 65536 + 8), d,
+                                        None) == E                                # gx over xmask
     assert L.xbar_sg_predict(1, 4, 4, a, b, c, ctypes.c_void_p(base + 8), None, None) == E
     assert L.xbar_sg_predict(1, 4, 4, a, b, c, d, ctypes.c_void_p(base + 3 * 65536 + 8), None) == E  # est over I
     # weight gradient: workspace too small, gw over gb

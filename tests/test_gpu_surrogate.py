@@ -70,18 +70,23 @@ def test_conv_forward(B, H, W, C, O, relu):
 
 @pytest.mark.parametrize("B,H,W,C,O", CONV_CASES)
 @pytest.mark.parametrize("masked", [False, True])
-def test_conv_backward_data(B, H, W, C, O, masked):
+@pytest.mark.parametrize("xmasked", [False, True])
+def test_conv_backward_data(B, H, W, C, O, masked, xmasked):
     import torch
-    rng = np.random.default_rng(7 + B * 1000 + H * 10 + C + O + masked)
+    rng = np.random.default_rng(7 + B * 1000 + H * 10 + C + O + masked + 2 * xmasked)
     g, w = _rand(rng, B, O, H, W), _rand(rng, O, C, 3, 3)
     ymask = _f32(np.maximum(rng.normal(size=(B, O, H, W)), 0.0)) if masked else None
-    log(f"case conv backward data B={B} H={H} W={W} C={C} O={O} masked={masked}")
+    xmask = _f32(np.maximum(rng.normal(size=(B, C, H, W)), 0.0)) if xmasked else None
+    log(f"case conv backward data B={B} H={H} W={W} C={C} O={O} masked={masked} xmasked={xmasked}")
     gx = torch.empty((B, C, H, W), dtype=torch.float32, device="cuda")
     _lib().xbar_sg_conv_backward_data(B, H, W, C, O, _t(g, torch.float32),
-                                      None if ymask is None else _t(ymask, torch.float32), _t(w, torch.float32), gx)
+                                      None if ymask is None else _t(ymask, torch.float32), _t(w, torch.float32), gx,
+                                      xmask=None if xmask is None else _t(xmask, torch.float32))
     gm = g * (ymask > 0) if masked else g
     ref = osg.conv2d_grad_input(gm, w)
     absref = osg.conv2d_grad_input(np.abs(gm), np.abs(w))
+    if xmasked:
+        ref, absref = ref * (xmask > 0), absref * (xmask > 0)
     _assert_within(gx.cpu().numpy().astype(np.float64), ref, absref, O * 9, "conv backward data")
 
 
