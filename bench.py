@@ -114,8 +114,8 @@ def main():
     ap.add_argument("--no-shortcuts", action="store_true",
                     help="skip the currents-only and transfer-matrix legs")
     ap.add_argument("--no-tiles", action="store_true", help="skip the batched small-tile leg")
-    ap.add_argument("--tiles-large", action="store_true",
-                    help="also time the tiles workload's n_t >= 128 half through plans (several seconds)")
+    ap.add_argument("--no-tiles-large", action="store_true",
+                    help="skip the tiles workload's n_t >= 128 half (plan lanes, a few seconds)")
     ap.add_argument("--tile-lanes", type=int, default=3,
                     help="concurrent plans (stream + host thread each) for the n_t >= 128 tiles")
     args = ap.parse_args()
@@ -390,7 +390,7 @@ def main():
         result["transfer"] = run_transfer(args.steps)
     if not args.no_tiles:
         result["tiles"] = run_tiles(args.steps)
-    if args.tiles_large:
+    if not args.no_tiles_large:
         result["tiles_large"] = run_tiles_large(args.tile_lanes)
     if not args.no_fp32_ir:
         # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
