@@ -278,3 +278,52 @@ def test_surrogate_rejects_bad_inputs_before_launching():
     with pytest.raises(ValueError):
         net.predict(G, V, r, est=torch.empty((B, n), dtype=torch.float32, device="cuda"))
     assert net.predict(G, V, r).shape == (B, n)
+
+
+def test_checkpoint_round_trip():
+    """state() / load(): a restored network predicts the same bits and trains on to the
+    same weights as the original."""
+    import torch
+
+    import paper_2410_19993_amd.surrogate as sgm
+    rng = np.random.default_rng(51)
+    B, m, n = 4, 10, 12
+    G = _t(np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (B, m, n))))
+    V = _t(rng.uniform(0, 0.5, (B, m)))
+    r = _t(rng.uniform(1, 5, B))
+    d = _t(rng.normal(scale=0.05, size=(B, n)))
+    log("case surrogate checkpoint round trip")
+    a = sgm.Surrogate(channels=6, seed=2, lr=1e-3)
+    for _ in range(5):
+        a.train_step(G, V, r, d, want_loss=False)
+    a.kappa = 3.5
+    st = a.state()
+    b = sgm.Surrogate(channels=6, seed=99, lr=1e-3)
+    b.load(st)
+    assert b.t == a.t and b.kappa == 3.5
+    assert torch.equal(a.predict(G, V, r), b.predict(G, V, r))
+    a.train_step(G, V, r, d, want_loss=False)
+    b.train_step(G, V, r, d, want_loss=False)
+    assert torch.equal(a.params, b.params)
+    with pytest.raises(ValueError):
+        sgm.Surrogate(channels=5).load(st)
+
+
+def test_solver_dataset_labels_match_the_oracle():
+    """solver_dataset: every sample's currents equal the oracle's for its map, input
+    vector and segment resistance, and delta = (I - G^T V) / G^T V."""
+    import paper_2410_19993_amd.surrogate as sgm
+    log("case solver dataset: 3 maps x 2 vectors of 16 x 16")
+    ds = sgm.solver_dataset(3, 2, 16, 16, seed=7, r_levels=[1.5, 4.0])
+    G, r, V, I = (x.cpu().numpy() for x in (ds.G, ds.r, ds.V, ds.I))
+    assert G.shape == (3, 16, 16) and V.shape == (6, 16) and I.shape == (6, 16) and set(r) <= {1.5, 4.0}
+    for s in range(6):
+        k = s // 2
+        ref = oracle.solve(G[k], V[s:s + 1], r[k], r[k], 50.0, 50.0).currents[0]
+        assert rel_err_vec(I[s], ref) <= 1e-10
+    Gs = np.repeat(G, 2, axis=0)
+    assert np.allclose(ds.delta.cpu().numpy(), osg.targets(I, Gs, V), rtol=1e-12, atol=1e-15)
+
+
+def rel_err_vec(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
