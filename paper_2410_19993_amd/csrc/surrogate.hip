@@ -215,16 +215,17 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_data_kernel(int H, int W, int
 // Partial weight and bias gradients: workgroup k sums, over the 16 x 16 tiles
 // k, k + kParts, ..., gw[o][c][dy][dx] = sum g[b][o][p][q] x[b][c][p + dy - 1][q + dx - 1]
 // and gb[o] = sum g[b][o][p][q] into part[k][0 .. O C 9 + O).  The tile of g and
-// the tile of x with its one-crosspoint halo are staged in LDS.  With G = 256 / C
+// the tile of x with its one-crosspoint halo are staged in LDS.  With G = 512 / C
 // groups, thread t < G C owns input channel c = t % C and output channels
-// o = t / C + G k (k < 4), all nine taps of each: it walks the tile row by row with
+// o = t / C + G k (k < 2), all nine taps of each: it walks the tile row by row with
 // the 3 x 3 window of x in registers, so each crosspoint costs three LDS reads of x
 // and one of g per output channel for 9 multiply-adds per output channel.
 constexpr int kXs = 18 * 18 + 1;        // LDS stride of a staged x channel (odd: spreads banks)
 constexpr int kGs = 257;                // LDS stride of a staged g channel (odd: spreads banks)
-constexpr int kOk = 4;                  // output channels per thread (256 / 32 groups of 8)
+constexpr int kWgT = 512;               // threads of a weight-gradient workgroup
+constexpr int kOk = 2;                  // output channels per thread (512 / 32 = 16 groups of 2)
 
-__global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, int W, int C, int O,
+__global__ __launch_bounds__(kWgT) void sg_conv_bwd_weight_kernel(int B, int H, int W, int C, int O,
                                                                  const float* __restrict__ x,
                                                                  const float* __restrict__ gy,
                                                                  const float* __restrict__ ymask,
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
     const int tw = (W + 15) / 16, th = (H + 15) / 16;
     const int tiles = B * th * tw;
     const int64_t hw = (int64_t)H * W;
-    const int groups = 256 / C;
+    const int groups = kWgT / C;
     const int c = threadIdx.x % C, og = threadIdx.x / C;
     const bool active = og < groups;
     int orow[kOk];
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
         const int b = t / (th * tw), r = t % (th * tw);
         const int p0 = (r / tw) * 16, q0 = (r % tw) * 16;
         __syncthreads();                        // the previous tile's LDS reads are done
-        for (int e = threadIdx.x; e < O * 256; e += 256) {
+        for (int e = threadIdx.x; e < O * 256; e += kWgT) {
             const int o = e >> 8, p = p0 + ((e & 255) >> 4), q = q0 + (e & 15);
             float g = 0.0f;
             if (p < H && q < W) {
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(256) void sg_conv_bwd_weight_kernel(int B, int H, i
             }
             gs[o * kGs + (e & 255)] = g;
         }
-        for (int e = threadIdx.x; e < C * 324; e += 256) {
+        for (int e = threadIdx.x; e < C * 324; e += kWgT) {
             const int cc = e / 324, k = e % 324;
             const int p = p0 + k / 18 - 1, q = q0 + k % 18 - 1;
             xs[cc * kXs + k] = in_grid(p, q, H, W) ? x[((int64_t)b * C + cc) * hw + (int64_t)p * W + q] : 0.0f;
@@ -515,7 +516,7 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
     if (overlap(work, nw, gw, ne * 4) || overlap(work, nw, gb, O * 4) || overlap(gw, ne * 4, gb, O * 4))
         return XBAR_ERR_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(256), 0, s, B, H, W, C, O, x, gy, ymask, work);
+    hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(kWgT), 0, s, B, H, W, C, O, x, gy, ymask, work);
     if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
     hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 31) / 32), dim3(256), 0, s, nparts, ne, O, work, gw,
                        gb);
