@@ -7,12 +7,15 @@ forward/back substitution with every node voltage written to HBM, and the
 output currents.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
-                    [--no-shortcuts]
+                    [--no-shortcuts] [--no-tiles] [--no-tiles-large] [--tile-lanes 3]
 
 Besides the metric (float64, node voltages written) the line reports the
 float32 + float64-refinement leg and exact shortcuts that skip work the metric
 does: the same path without node voltages, the sweeps alone, and the output
 currents through the transfer matrix (one product per batch once T is built).
+It also reports the heterogeneous tiles workload (2048 crossbars of 32-256 rows
+and columns, 256 input vectors each): the crossbars with n <= 64 through the
+batched tile kernel, the others through concurrent plans.
 
 Prints one JSON line.  --gpus N > 1 is refused: the solver runs on one GPU.
 """
