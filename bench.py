@@ -7,7 +7,7 @@ forward/back substitution with every node voltage written to HBM, and the
 output currents.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
-                    [--no-shortcuts] [--no-tiles] [--no-tiles-large] [--tile-lanes 3]
+                    [--no-shortcuts] [--no-tiles] [--no-tiles-large] [--tile-lanes 4]
 
 Besides the metric (float64, node voltages written) the line reports the
 float32 + float64-refinement leg and exact shortcuts that skip work the metric
@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--no-tiles", action="store_true", help="skip the batched small-tile leg")
     ap.add_argument("--no-tiles-large", action="store_true",
                     help="skip the tiles workload's n_t >= 128 half (plan lanes, a few seconds)")
-    ap.add_argument("--tile-lanes", type=int, default=3,
+    ap.add_argument("--tile-lanes", type=int, default=4,
                     help="concurrent plans (stream + host thread each) for the n_t >= 128 tiles")
     args = ap.parse_args()
     if args.gpus != 1:

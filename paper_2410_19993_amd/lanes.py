@@ -8,13 +8,16 @@ A PlanLanes object runs `lanes` host threads, each with a HIP stream of its own
 and one plan per (m, n) shape, that take the crossbars in order of decreasing
 size until none is left.  Plans share no state, and each plan waits only on its
 own stream when its factorization reads the schedule state back, so the lanes'
-kernels overlap on the device.  All arithmetic runs in the library's kernels.
+kernels overlap on the device.  A plan clears its device-side error flags at
+every assembly, so each lane reads its plan's status after every crossbar it
+solves; `status` keeps one code per crossbar.  All arithmetic runs in the
+library's kernels.
 """
 from __future__ import annotations
 
 import threading
 
-from . import Plan, _check_tensor
+from . import Plan, XbarError, _check_tensor, _lib
 
 
 def _torch():
@@ -53,7 +56,10 @@ class PlanLanes:
     def currents(self, Gs, Vs, outs=None):
         """Gs[k] [m_k][n_k], Vs[k] [B_k][m_k] (B_k <= max_batch) float64 CUDA/HIP tensors
         written on the current stream; returns outs[k] [B_k][n_k], ready on the current
-        stream.  Raises the first error any lane met, after every lane has stopped."""
+        stream.  Raises the first error any lane met, after every lane has stopped.
+        Device-side failures of single crossbars (a conductance that is not finite and
+        positive, a pivot that is not) do not raise here: `status[k]` holds each
+        crossbar's code (XBAR_OK = 0) and check() raises for them."""
         torch = _torch()
         T = len(Gs)
         if len(Vs) != T or (outs is not None and len(outs) != T):
@@ -82,6 +88,7 @@ class PlanLanes:
         order = iter(sorted(range(T), key=lambda k: (-shapes[k][0] * shapes[k][1], k)))
         lock = threading.Lock()
         errors = []
+        self.status = [None] * T
 
         def work(lane):
             try:
@@ -98,6 +105,7 @@ class PlanLanes:
                     p.factor()
                     p.solve_batch(Vs[k], None)
                     p.currents(outs[k])
+                    self.status[k] = p.info()[0]        # before the next assembly clears it
             except BaseException as e:          # handed to the caller below
                 with lock:
                     errors.append(e)
@@ -116,11 +124,18 @@ class PlanLanes:
             raise errors[0]
         return outs
 
+    def failed(self) -> list:
+        """Indices of the crossbars of the last currents() call whose solve failed on
+        the device."""
+        return [k for k, st in enumerate(getattr(self, "status", [])) if st is not None and st != _lib.XBAR_OK]
+
     def check(self) -> None:
-        """Raise XbarError if any plan recorded a device-side failure."""
-        for lane in self._lanes:
-            for p in lane["plans"].values():
-                p.check()
+        """Raise XbarError if any crossbar of the last currents() call failed on the
+        device; the message names the crossbars."""
+        bad = self.failed()
+        if bad:
+            st = self.status[bad[0]]
+            raise XbarError(f"PlanLanes crossbars {bad[:8]}{' ...' if len(bad) > 8 else ''}", st)
 
     def close(self) -> None:
         for lane in self._lanes:

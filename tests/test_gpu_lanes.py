@@ -68,3 +68,37 @@ def test_lanes_reject_bad_arguments_before_launching():
         with pytest.raises(ValueError):
             pl.currents([G, G], [V[:4]])                            # lengths differ
         assert pl.currents([], []) == []
+
+
+def test_lanes_report_each_failed_crossbar():
+    """A plan clears its error flags at every assembly, so a failure must be read per
+    crossbar: a negative conductance in crossbars 1 and 4 (of six of one shape, so
+    later crossbars reuse the failed plans) is reported for exactly those, and the
+    others still match single plans."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    rng = np.random.default_rng(600)
+    m, n, B = 12, 80, 4
+    Gs, Vs = [], []
+    for k in range(6):
+        G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (m, n)))
+        if k in (1, 4):
+            G[3, 5] = -1e-5
+        Gs.append(torch.from_numpy(G).cuda())
+        Vs.append(torch.from_numpy(rng.uniform(0, 0.5, (B, m))).cuda())
+    log("case plan lanes with failing crossbars 1 and 4, 2 lanes")
+    with xb.PlanLanes(*R, lanes=2, max_batch=B) as pl:
+        outs = pl.currents(Gs, Vs)
+        assert pl.failed() == [1, 4]
+        with pytest.raises(xb.XbarError):
+            pl.check()
+        for k in (0, 2, 3, 5):
+            with xb.Plan(m, n, *R, "fp64", max_batch=B) as p:
+                p.assemble(Gs[k])
+                p.factor()
+                p.solve_batch(Vs[k], None)
+                assert np.array_equal(outs[k].cpu().numpy(), p.currents().cpu().numpy())
+        pl.currents([Gs[0]], [Vs[0]])
+        assert pl.failed() == []
+        pl.check()
