@@ -33,7 +33,11 @@ __device__ __forceinline__ bool in_grid(int p, int q, int H, int W) { return p >
 
 // X[b][0..6][i][j] = log10(G) + 5, 2 V_i, (r - 3) / 2, column and row position in
 // [-1, 1], and the line totals 1e4 mean_j' G[i][j'] (row i) and 1e4 mean_i' G[i'][j] 2 V_i'
-// (column j).  One workgroup per sample; the line totals go through LDS.
+// (column j).  kFeatParts workgroups per sample (blockIdx.y), each writing a
+// contiguous quarter of the rows; each forms all column totals and its rows'
+// totals in LDS.
+constexpr int kFeatParts = 4;
+
 __global__ __launch_bounds__(256) void sg_features_kernel(int m, int n, const double* __restrict__ G,
                                                           const double* __restrict__ V, const double* __restrict__ r,
                                                           float* __restrict__ X)
@@ -43,7 +47,9 @@ __global__ __launch_bounds__(256) void sg_features_kernel(int m, int n, const do
     const int64_t mn = (int64_t)m * n;
     const double* gb = G + (int64_t)b * mn;
     const double* vb = V + (int64_t)b * m;
-    for (int i = threadIdx.x; i < m; i += 256) {
+    const int per = (m + kFeatParts - 1) / kFeatParts;
+    const int i0 = blockIdx.y * per, i1 = min(m, i0 + per);
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
         double s = 0.0;
         for (int j = 0; j < n; ++j) s += gb[(int64_t)i * n + j];
         rows[i] = 1e4 * s / n;
@@ -56,7 +62,7 @@ __global__ __launch_bounds__(256) void sg_features_kernel(int m, int n, const do
     __syncthreads();
     float* xb = X + (int64_t)b * kFeatures * mn;
     const float rr = (float)((r[b] - 3.0) * 0.5);
-    for (int64_t e = threadIdx.x; e < mn; e += 256) {
+    for (int64_t e = (int64_t)i0 * n + threadIdx.x; e < (int64_t)i1 * n; e += 256) {
         const int i = (int)(e / n), j = (int)(e % n);
         xb[e] = (float)(log10(gb[e]) + 5.0);
         xb[mn + e] = (float)(2.0 * vb[i]);
@@ -320,24 +326,24 @@ __global__ __launch_bounds__(kWgT) void sg_conv_bwd_weight_kernel(int B, int H, 
     if (threadIdx.x < O) pw[ne + threadIdx.x] = accb;
 }
 
-// gw[e] = sum over the partials; e >= ne: gb.  Each workgroup takes 32 entries; lane
-// l of an entry adds the partials l, l + 8, ... in order, and the eight sums are then
-// added in lane order, so the result does not depend on scheduling.
+// gw[e] = sum over the partials; e >= ne: gb.  Each workgroup takes 16 entries; lane
+// l of an entry adds the partials l, l + 16, ... in order, and the sixteen sums are
+// then added in lane order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void sg_reduce_parts_kernel(int nparts, int ne, int O,
                                                               const float* __restrict__ part,
                                                               float* __restrict__ gw, float* __restrict__ gb)
 {
-    __shared__ float red[8][32];
-    const int le = threadIdx.x & 31, lp = threadIdx.x >> 5;
-    const int e = blockIdx.x * 32 + le;
+    __shared__ float red[16][16];
+    const int le = threadIdx.x & 15, lp = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + le;
     float s = 0.0f;
     if (e < ne + O)
-        for (int k = lp; k < nparts; k += 8) s += part[(int64_t)k * (ne + O) + e];
+        for (int k = lp; k < nparts; k += 16) s += part[(int64_t)k * (ne + O) + e];
     red[lp][le] = s;
     __syncthreads();
     if (lp == 0 && e < ne + O) {
         float t = red[0][le];
-        for (int k = 1; k < 8; ++k) t += red[k][le];
+        for (int k = 1; k < 16; ++k) t += red[k][le];
         if (e < ne) gw[e] = t;
         else gb[e - ne] = t;
     }
@@ -468,8 +474,8 @@ xbar_status xbar_sg_features(int32_t B, int32_t m, int32_t n, const double* G, c
     const int64_t total = (int64_t)B * m * n, nx = total * kFeatures * 4;
     if (overlap(X, nx, G, total * 8) || overlap(X, nx, V, (int64_t)B * m * 8) || overlap(X, nx, r, (int64_t)B * 8))
         return XBAR_ERR_ARG;
-    hipLaunchKernelGGL(sg_features_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream), m, n,
-                       G, V, r, X);
+    hipLaunchKernelGGL(sg_features_kernel, dim3(B, kFeatParts), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+                       m, n, G, V, r, X);
     return launched();
 }
 
@@ -518,7 +524,7 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(kWgT), 0, s, B, H, W, C, O, x, gy, ymask, work);
     if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
-    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 31) / 32), dim3(256), 0, s, nparts, ne, O, work, gw,
+    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 15) / 16), dim3(256), 0, s, nparts, ne, O, work, gw,
                        gb);
     return launched();
 }
