@@ -9,7 +9,7 @@ r_src = r_sense = 50 ohm, input vectors uniform on [0, 0.5] V; `vectors` input v
 per map.  The defaults give 200,000 training and 20,000 held-out samples.
 
 Steps, all on the GPU through the library:
-1. labels: exact float64 currents of every sample from the solver (PlanLanes, three
+1. labels: exact float64 currents of every sample from the solver (PlanLanes, four
    plans at a time), timed: that is the solver's throughput on new maps;
 2. training: Adam on the mean squared error of the predicted correction, timed per
    step (features, 4 convolutions, readout and loss, 7 gradient kernels, update);

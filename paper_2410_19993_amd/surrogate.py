@@ -216,7 +216,7 @@ class Surrogate:
         return self.kappa
 
     def predict_checked(self, G, V, r, tol: float = 0.01, r_src: float = 50.0, r_sense: float = 50.0,
-                        lanes: int = 3, precision: str = "fp64"):
+                        lanes: int = 4, precision: str = "fp64"):
         """Currents for every sample, from the surrogate where kappa times its error
         estimate is at most tol in every column (kappa = 1 until calibrate()), and from
         the exact solver (through PlanLanes, one plan set per segment resistance, in
@@ -271,7 +271,7 @@ class Dataset:
 
 
 def solver_dataset(maps: int, vectors: int, m: int, n: int, seed: int, r_levels=None, r_src: float = 50.0,
-                   r_sense: float = 50.0, lanes: int = 3) -> Dataset:
+                   r_sense: float = 50.0, lanes: int = 4) -> Dataset:
     """Training data from the exact solver: `maps` conductance maps (log-uniform on
     [1e-6, 1e-4] S), each with `vectors` input vectors (uniform on [0, 0.5] V) and one
     segment resistance r = r_wl = r_bl drawn from r_levels (default 1.0, 1.25, ..., 5.0
