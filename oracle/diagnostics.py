@@ -58,10 +58,17 @@ def power_balance(net: Netlist, V: np.ndarray, node_v: np.ndarray):
 
 
 def relative_error(I: np.ndarray, I_ref: np.ndarray, abs_floor: float = 1e-18) -> np.ndarray:
-    """Per input vector ||I - I_ref||_inf / ||I_ref||_inf ([B]); absolute when I_ref == 0."""
-    I = np.atleast_2d(I)
-    I_ref = np.atleast_2d(I_ref)
+    """Per input vector ||I - I_ref||_inf / ||I_ref||_inf over the columns ([B]).
+
+    For an input vector whose reference currents are all zero the comparison is
+    absolute: the error is 0 when every |I_j| <= abs_floor (amperes) and inf
+    otherwise, so any relative tolerance then demands currents within abs_floor.
+    """
+    I = np.atleast_2d(np.asarray(I, dtype=np.float64))
+    I_ref = np.atleast_2d(np.asarray(I_ref, dtype=np.float64))
+    if I.shape != I_ref.shape:
+        raise ValueError(f"shape mismatch {I.shape} vs {I_ref.shape}")
     num = np.max(np.abs(I - I_ref), axis=1)
     den = np.max(np.abs(I_ref), axis=1)
-    out = np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
-    return out
+    zero_ref = np.where(num <= abs_floor, 0.0, np.inf)
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), zero_ref)
