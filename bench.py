@@ -8,6 +8,9 @@ output currents.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
                     [--no-shortcuts] [--no-tiles] [--no-tiles-large] [--tile-lanes 4]
+                    [--no-r-sweep]
+    python bench.py --copy-probe GIB    # a plain device copy of GIB GiB, three times
+                                        # (calibrates the HBM traffic counters)
 
 Besides the metric (float64, node voltages written) the line reports the
 float32 + float64-refinement leg and exact shortcuts that skip work the metric
@@ -16,6 +19,11 @@ currents through the transfer matrix (one product per batch once T is built).
 It also reports the heterogeneous tiles workload (2048 crossbars of 32-256 rows
 and columns, 256 input vectors each): the crossbars with n <= 64 through the
 batched tile kernel, the others through concurrent plans.
+
+The CPU baseline has two parts: the oracle (one core) on a bounded slice,
+scaled to the workload, and LAPACK's banded Cholesky (dpbtrf / dpbtrs through
+SciPy) factored once with the input vectors split over worker processes on the
+host's cores, also on a bounded slice and scaled.
 
 Prints one JSON line.  --gpus N > 1 is refused: the solver runs on one GPU.
 """
@@ -83,6 +91,111 @@ def cpu_baseline(wl, rows=64, vectors=128):
             "seconds_measured": t_all + t_fact, "extrapolated_seconds": t_full}
 
 
+def host_description():
+    """CPU model, logical CPU count and BLAS thread setting of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+        blas = [{"api": d.get("internal_api"), "threads": d.get("num_threads")}
+                for d in threadpoolctl.threadpool_info() if d.get("user_api") == "blas"]
+    except Exception:
+        pass
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "blas": blas}
+
+
+def _lapack_worker(args):
+    """Worker process: attach the shared Cholesky factor and solve a chunk of vectors."""
+    name, shape, rhs = args
+    import threadpoolctl
+    from multiprocessing import shared_memory
+
+    import scipy.linalg as sl
+    with threadpoolctl.threadpool_limits(1):
+        shm = shared_memory.SharedMemory(name=name)
+        try:
+            c = np.ndarray(shape, dtype=np.float64, buffer=shm.buf)
+            t0 = time.perf_counter()
+            sl.cho_solve_banded((c, False), rhs, check_finite=False)
+            return time.perf_counter() - t0
+        finally:
+            shm.close()
+
+
+def lapack_baseline(wl, rows=64, per_worker=8, workers=None):
+    """LAPACK banded Cholesky on the host's cores: the nodal matrix of rows 0..rows-1
+    of the crossbar (the same half-bandwidth 2n as the full one) is factored once
+    (dpbtrf, all BLAS threads), then `workers` processes (one BLAS thread each) solve
+    `per_worker` input vectors each (dpbtrs) against the shared factor.  Factor and
+    per-vector solve cost are linear in the rows, so the full workload's time is
+    estimated as 8 x (factor) + ceil(B / workers) x 8 x (per-vector solve)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
+    import scipy.linalg as sl
+
+    import oracle
+    g = wl.geom
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    Gs = np.ascontiguousarray(wl.G[:rows])
+    net = oracle.build_netlist(Gs, g.r_wl, g.r_bl, g.r_src, g.r_sense)
+    ab, w = oracle.assemble_band(net)              # ab[r][c - r + w]
+    N = ab.shape[0]
+    au = np.zeros((w + 1, N))                      # LAPACK upper band: au[w + r - c][c]
+    for d in range(w + 1):
+        au[w - d, d:] = ab[:N - d, w + d]
+    del ab
+    t0 = time.perf_counter()
+    c = sl.cholesky_banded(au, lower=False, overwrite_ab=True, check_finite=False)
+    t_fact = time.perf_counter() - t0
+    shm = shared_memory.SharedMemory(create=True, size=c.nbytes)
+    try:
+        np.ndarray(c.shape, dtype=np.float64, buffer=shm.buf)[:] = c
+        del c, au
+        rhs = oracle.injections(net, wl.V[:per_worker * workers, :rows])
+        jobs = [(shm.name, (w + 1, N), np.ascontiguousarray(rhs[:, k * per_worker:(k + 1) * per_worker]))
+                for k in range(workers)]
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(workers) as pool:
+            pool.map(_lapack_worker, jobs[:1])              # start-up and first touch
+            t0 = time.perf_counter()
+            times = pool.map(_lapack_worker, jobs)
+            t_solve = time.perf_counter() - t0
+    finally:
+        shm.close()
+        shm.unlink()
+    per_vec = t_solve / per_worker                 # wall time per vector per worker, all busy
+    scale = wl.G.shape[0] / rows
+    t_full = scale * (t_fact + -(-wl.B // workers) * per_vec)
+    return {"value": wl.B / t_full, "unit": "solves/s", "cores": workers, "kind": "lapack_banded_cholesky",
+            "sample": (f"dpbtrf of rows 0-{rows - 1} ({N} unknowns, half-bandwidth {w}) in {t_fact:.2f} s, "
+                       f"then {workers} processes x {per_worker} vectors (dpbtrs, one BLAS thread each) in "
+                       f"{t_solve:.2f} s; scaled x{scale:g} in rows and to {wl.B} vectors"),
+            "factor_s_measured": t_fact, "solve_s_measured": t_solve,
+            "worker_s": [round(x, 3) for x in times], "extrapolated_seconds": t_full}
+
+
+def copy_probe(gib):
+    """A plain device copy of known size (torch's elementwise copy, three times), run
+    under the traffic counters to calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}))
+
+
 def kernel_source_hash(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
@@ -121,11 +234,18 @@ def main():
                     help="skip the tiles workload's n_t >= 128 half (plan lanes, a few seconds)")
     ap.add_argument("--tile-lanes", type=int, default=4,
                     help="concurrent plans (stream + host thread each) for the n_t >= 128 tiles")
+    ap.add_argument("--no-r-sweep", action="store_true",
+                    help="skip the float64 and float32+refinement steps at the other segment resistances")
+    ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the solver has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe is not None:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
 
@@ -146,15 +266,17 @@ def main():
     stream = torch.cuda.current_stream()
     gold = os.path.join(ROOT, "tests", "golden", f"c3_r{g.r_wl:g}_currents.npy")
 
-    def verify():
-        if args.no_verify or not os.path.exists(gold) or B != 4096:
+    def verify(path=None):
+        path = path or gold
+        if args.no_verify or not os.path.exists(path) or B != 4096:
             return None
-        ref = np.load(gold)
+        ref = np.load(path)
         Ih = I.cpu().numpy()[workloads.c3_subset()]
         return float((np.max(np.abs(Ih - ref), axis=1) / np.max(np.abs(ref), axis=1)).max())
 
-    def run(precision, steps, warmup, ir_tol=0.0, nodes=True):
-        plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B,
+    def run(precision, steps, warmup, ir_tol=0.0, nodes=True, geom=None, verify_fn=None):
+        gg = geom or g
+        plan = xb.Plan(m, n, gg.r_wl, gg.r_bl, gg.r_src, gg.r_sense, precision, max_batch=B,
                        ir_tol=ir_tol, stream=stream)
 
         def step():
@@ -179,7 +301,7 @@ def main():
         tm = plan.timing()
         st, info = plan.info()
         plan.check()
-        err = verify()
+        err = (verify_fn or verify)()
         plan.close()
         log(f"{precision}{'' if nodes else ' currents only'}: {steps} steps in {wall:.3f} s")
         return wall * 1e3 / steps, tm, info, err
@@ -398,19 +520,67 @@ def main():
     if not args.no_fp32_ir:
         # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
         # refinement stops once its error estimate is below 1e-10 (the error actually
-        # reached, measured against the oracle, is reported beside it).
+        # reached, measured against the oracle, is reported beside it, and a result above
+        # 1e-9 marks the leg invalid).
         ms32, tm32, info32, err32 = run("fp32_ir", args.steps, args.warmup, ir_tol=IR_TOL)
+        k_ir = per(tm32.ir_sweep_ms, tm32.ir_sweep_launches)
+        k_res = per(tm32.residual_ms, tm32.residual_launches)
+        ir_flops = 2.0 * n * n * B * (2 * m - 1)        # one float32 sweep: forward m, back m - 1 products
+        res_bytes = 8.0 * B * m * n + 4.0 * B * m * n   # reads U (float64), writes R (float32)
+        ok32 = err32 is not None and err32 <= 1e-9
         result["fp32_ir"] = {
             "value": B / (ms32 * 1e-3), "unit": "solves/s", "ms_per_step": ms32, "dtype": "f32+f64",
+            "valid": ok32 if err32 is not None else None,
             "sweeps": int(info32.ir_iters), "ir_tol": IR_TOL, "max_rel_err_vs_oracle": err32,
             "phases_ms": {"condense": per(tm32.condense_ms, tm32.condense_launches),
                           "factor": per(tm32.factor_ms, tm32.factor_launches),
                           "refined_solve": per(tm32.sweep_ms, tm32.sweep_launches),
-                          "recover": per(tm32.recover_ms, tm32.recover_launches)},
+                          "recover": per(tm32.recover_ms, tm32.recover_launches),
+                          "float32_sweep_each": k_ir, "float64_residual_each": k_res},
+            "roofline": {"bound": "mfma", "kernel": "sweep_kernel<float,8,true,false>",
+                         "achieved": ir_flops / (k_ir * 1e-3) / 1e12 if k_ir > 0 else None,
+                         "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                         "frac": ir_flops / (k_ir * 1e-3) / PEAK_FP32_MFMA if k_ir > 0 else None,
+                         "flops_per_launch": ir_flops, "avg_launch_ms": k_ir},
+            "residual_roofline": {"bound": "hbm", "kernel": "residual_kernel",
+                                  "achieved": res_bytes / (k_res * 1e-3) / 1e9 if k_res > 0 else None,
+                                  "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                  "frac": res_bytes / (k_res * 1e-3) / PEAK_HBM if k_res > 0 else None,
+                                  "bytes_per_launch": res_bytes},
             "speedup_vs_fp64": ms64 / ms32}
+        if not ok32 and err32 is not None:
+            log(f"fp32_ir: error {err32:.3e} above 1e-9: leg marked invalid")
+    if not args.no_r_sweep and B == 4096:
+        # the other segment resistances of the 512 x 512 workload (same G and V): both
+        # precisions, fewer steps, each with its error against the stored oracle currents
+        sweep = {}
+        for rr in workloads.C3_R:
+            if rr == g.r_wl:
+                continue
+            wr = workloads.c3(r=rr, batch=B)
+            path = os.path.join(ROOT, "tests", "golden", f"c3_r{rr:g}_currents.npy")
+            entry = {}
+            for prec, tol in (("fp64", 0.0), ("fp32_ir", IR_TOL)):
+                if prec == "fp32_ir" and args.no_fp32_ir:
+                    continue
+                msr, tmr, infor, errr = run(prec, max(2, args.steps // 4), 1, ir_tol=tol, geom=wr.geom,
+                                            verify_fn=lambda p=path: verify(p))
+                entry[prec] = {"value": B / (msr * 1e-3), "ms_per_step": msr, "max_rel_err_vs_oracle": errr,
+                               "sweeps": int(infor.ir_iters) if prec != "fp64" else None,
+                               "factor_ms": per(tmr.factor_ms, tmr.factor_launches),
+                               "sweep_ms": per(tmr.sweep_ms, tmr.sweep_launches)}
+            sweep[f"r{rr:g}"] = entry
+        result["r_sweep"] = sweep
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
-        result["cpu_baseline"] = cpu_baseline(wl)
+        cb = cpu_baseline(wl)
+        cb.update(host_description())
+        log("timing LAPACK banded Cholesky over the host's cores on a bounded sample ...")
+        try:
+            cb["lapack_all_cores"] = lapack_baseline(wl)
+        except Exception as e:                     # reported, not fatal: the oracle figure stands
+            cb["lapack_all_cores"] = {"error": repr(e)}
+        result["cpu_baseline"] = cb
     print(json.dumps(result))
 
 

@@ -84,6 +84,18 @@ typedef struct {
     int64_t workspace_bytes;    /* device memory held by the plan                             */
     int32_t block;              /* padded block size used for the row blocks                  */
     int32_t reserved;
+    double min_pivot;           /* smallest pivot the last factorization met (Sec. II.C: the
+                                   LU's pivots): the smallest diagonal entry of any block
+                                   pivot for Newton-Schulz, the smallest scalar pivot for the
+                                   Gauss-Jordan elimination; +inf before a factorization.
+                                   Not positive => XBAR_ERR_NOT_SPD.                           */
+    double max_backward_err;    /* largest normwise backward error ||b - A v||_inf /
+                                   (||A||_inf ||v||_inf + ||b||_inf) over the last batch's
+                                   node voltages v for the nodal system A v = b of Sec. II.A
+                                   (Eqs. 5-7), when xbar_set_diagnostics is on and the batch
+                                   wrote node voltages; -1 when not measured                  */
+    int32_t factor_slots_used;  /* Newton-Schulz launches the last factorization needed       */
+    int32_t factor_slots_launched; /* launches it queued (the asynchronous budget)           */
 } xbar_info;
 
 /*
@@ -96,7 +108,10 @@ typedef struct {
  *                of its vectors, the error estimate |d| min(1, |d| / |d_prev|)
  *                (d: the latest correction of the bit-line voltages, max norm)
  *                is <= ir_tol times the largest bit-line voltage; 0 selects
- *                1e-12.  Must be finite, 0 <= ir_tol < 1.  Ignored for FP64.
+ *                1e-12.  This bounds the forward error of the solution (the
+ *                estimate of a contracting iteration), not its backward error;
+ *                xbar_set_diagnostics measures the latter after the solve.
+ *                Must be finite, 0 <= ir_tol < 1.  Ignored for FP64.
  *   ir_max_iter  IR modes: refinement steps allowed, 1..100 (0 selects 10).
  *   hip_stream   hipStream_t the plan's work is queued on (NULL = null stream).
  *                The plan also creates one stream of its own (default priority,
@@ -119,11 +134,12 @@ xbar_status xbar_assemble(xbar_plan plan, const double* G);
 /*
  * LU-decompose the assembled system once per conductance map (Sec. II.C):
  * a block LU over the m row blocks.  Requires a prior xbar_assemble
- * (otherwise XBAR_ERR_STATE).  A block pivot that is not positive sets
- * XBAR_ERR_NOT_SPD on the device.  The Newton-Schulz inversion of the pivot
- * blocks runs its two independent chains on the plan stream and the plan's
- * own second stream, and reads its schedule state back to the host, so the
- * call synchronises the plan stream (it cannot be captured into a graph).
+ * (otherwise XBAR_ERR_STATE).  A pivot that is not positive sets
+ * XBAR_ERR_NOT_SPD on the device (see xbar_info.min_pivot).  In the default
+ * method (XBAR_FACTOR_AUTO) the call is asynchronous and reads nothing back,
+ * so it can be captured into a HIP graph with the other calls: the plan's own
+ * second stream is forked from and joined back to the plan stream by events
+ * within the call.  See xbar_set_factor_method for the other methods.
  */
 xbar_status xbar_factor(xbar_plan plan);
 
@@ -220,17 +236,43 @@ xbar_status xbar_get_info(xbar_plan plan, xbar_info* info);
 
 /*
  * How xbar_factor inverts the pivot blocks of the block LU.
- *   XBAR_FACTOR_AUTO (default): Newton-Schulz iteration on the matrix cores;
- *       if any block misses its tolerance the factorization is redone with
- *       Gauss-Jordan elimination.  xbar_factor then waits for the device to
- *       decide (it synchronises the plan's stream).
+ *   XBAR_FACTOR_AUTO (default): Newton-Schulz iteration on the matrix cores, on
+ *       a schedule driven by the device with a fixed launch budget derived from
+ *       the geometry (one two-step round per row, a cold start for each chain,
+ *       and a margin); launches past a schedule's end do nothing.  Asynchronous
+ *       and capturable.  A block that misses its tolerance, or a budget that
+ *       runs out, sets XBAR_ERR_NO_CONVERGENCE on the device; the caller may
+ *       then refactor with XBAR_FACTOR_CHECKED or XBAR_FACTOR_GJ.
  *   XBAR_FACTOR_GJ: blocked Gauss-Jordan elimination only (asynchronous).
- *   XBAR_FACTOR_NS: Newton-Schulz only (asynchronous); a block that misses
- *       its tolerance sets XBAR_ERR_NO_CONVERGENCE on the device.
+ *   XBAR_FACTOR_NS: Newton-Schulz; the call reads the schedule states back and
+ *       launches until every row has finished (it synchronises the plan's
+ *       stream); a block that misses its tolerance sets XBAR_ERR_NO_CONVERGENCE.
+ *   XBAR_FACTOR_CHECKED: as XBAR_FACTOR_NS, but a missed tolerance makes the
+ *       call redo the factorization by Gauss-Jordan elimination.
  * Host-only; takes effect at the next xbar_factor.
  */
-typedef enum { XBAR_FACTOR_AUTO = 0, XBAR_FACTOR_GJ = 1, XBAR_FACTOR_NS = 2 } xbar_factor_method;
+typedef enum { XBAR_FACTOR_AUTO = 0, XBAR_FACTOR_GJ = 1, XBAR_FACTOR_NS = 2, XBAR_FACTOR_CHECKED = 3 } xbar_factor_method;
 xbar_status xbar_set_factor_method(xbar_plan plan, xbar_factor_method method);
+
+/*
+ * Solution diagnostics (host-only switch, off by default).  When on, every
+ * xbar_solve_batch that writes node voltages also measures their normwise
+ * backward error for the nodal system of Sec. II.A (one extra pass over the
+ * node voltages, queued on the plan stream), reported as
+ * xbar_info.max_backward_err.  Returns XBAR_ERR_ARG for a NULL plan.
+ */
+xbar_status xbar_set_diagnostics(xbar_plan plan, int32_t enable);
+
+/*
+ * Test hook, not for use in production: from the next xbar_assemble on,
+ * subtract `shift` siemens from every diagonal entry of the condensed bit-line
+ * blocks E_i before the factorization (0 switches it off).  Only the
+ * factorization sees the shift; with a shift above the blocks' diagonal the
+ * factor meets pivots that are not positive and reports XBAR_ERR_NOT_SPD, so
+ * that path can be exercised with valid conductances.  XBAR_ERR_ARG for a NULL
+ * plan or a shift that is not finite.
+ */
+xbar_status xbar_debug_shift_pivots(xbar_plan plan, double shift);
 
 /*
  * Phase timing, measured with HIP events recorded on the plan's stream
@@ -238,14 +280,18 @@ xbar_status xbar_set_factor_method(xbar_plan plan, xbar_factor_method method);
  * per xbar_assemble (condense), per xbar_factor (all its kernels), per
  * xbar_solve_batch (its substitution sweeps; in FP64 mode that is exactly
  * one kernel, the sweep with the word-line recovery fused) and per
- * word-line recovery launch of the IR modes.  Times are accumulated
- * milliseconds; *_launches count the intervals.
+ * word-line recovery launch of the IR modes; inside the IR modes' solve,
+ * also one interval per float32 sweep launch and per float64 residual
+ * launch.  Times are accumulated milliseconds; *_launches count the
+ * intervals.  Do not enable while capturing a graph.
  */
 typedef struct {
     double condense_ms;   int64_t condense_launches;   /* xbar_assemble                 */
     double factor_ms;     int64_t factor_launches;     /* xbar_factor (all its kernels) */
     double sweep_ms;      int64_t sweep_launches;      /* substitution sweeps           */
     double recover_ms;    int64_t recover_launches;    /* word-line recovery + output   */
+    double ir_sweep_ms;   int64_t ir_sweep_launches;   /* IR modes: each float32 sweep  */
+    double residual_ms;   int64_t residual_launches;   /* IR modes: each float64 residual */
 } xbar_timing;
 
 /* Enable (1) or disable (0) per-kernel timing.  Host-only; never fails on a valid plan. */

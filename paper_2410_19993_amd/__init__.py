@@ -89,6 +89,16 @@ class Plan:
         _lib.xbar_transfer_apply(self._plan, T, V, B, out)
         return out
 
+    def set_diagnostics(self, enable: bool = True) -> None:
+        """Measure the backward error of every batch solved with node voltages
+        (xbar_set_diagnostics); read it from info()[1].max_backward_err."""
+        _lib.xbar_set_diagnostics(self._plan, enable)
+
+    def debug_shift_pivots(self, shift: float) -> None:
+        """Test hook (xbar_debug_shift_pivots): subtract `shift` S from the diagonal of
+        every condensed block at the next assemble."""
+        _lib.xbar_debug_shift_pivots(self._plan, shift)
+
     def set_timing(self, enable: bool = True) -> None:
         _lib.xbar_set_timing(self._plan, enable)
 

@@ -32,7 +32,9 @@ PRECISIONS = {"fp64": XBAR_FP64, "fp32_ir": XBAR_FP32_IR, "bf16_ir": XBAR_BF16_I
 XBAR_FACTOR_AUTO = 0
 XBAR_FACTOR_GJ = 1
 XBAR_FACTOR_NS = 2
-FACTOR_METHODS = {"auto": XBAR_FACTOR_AUTO, "gj": XBAR_FACTOR_GJ, "ns": XBAR_FACTOR_NS}
+XBAR_FACTOR_CHECKED = 3
+FACTOR_METHODS = {"auto": XBAR_FACTOR_AUTO, "gj": XBAR_FACTOR_GJ, "ns": XBAR_FACTOR_NS,
+                  "checked": XBAR_FACTOR_CHECKED}
 
 
 class Geometry(ctypes.Structure):
@@ -45,14 +47,18 @@ class Info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("last_batch", ctypes.c_int32),
                 ("ir_iters", ctypes.c_int32), ("device_error", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("min_pivot", ctypes.c_double),
+                ("max_backward_err", ctypes.c_double), ("factor_slots_used", ctypes.c_int32),
+                ("factor_slots_launched", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
     _fields_ = [("condense_ms", ctypes.c_double), ("condense_launches", ctypes.c_int64),
                 ("factor_ms", ctypes.c_double), ("factor_launches", ctypes.c_int64),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
-                ("recover_ms", ctypes.c_double), ("recover_launches", ctypes.c_int64)]
+                ("recover_ms", ctypes.c_double), ("recover_launches", ctypes.c_int64),
+                ("ir_sweep_ms", ctypes.c_double), ("ir_sweep_launches", ctypes.c_int64),
+                ("residual_ms", ctypes.c_double), ("residual_launches", ctypes.c_int64)]
 
 
 class XbarError(RuntimeError):
@@ -85,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.xbar_destroy.argtypes = [vp]
         L.xbar_set_timing.argtypes = [vp, ctypes.c_int32]
         L.xbar_set_factor_method.argtypes = [vp, ctypes.c_int]
+        L.xbar_set_diagnostics.argtypes = [vp, ctypes.c_int32]
+        L.xbar_debug_shift_pivots.argtypes = [vp, ctypes.c_double]
         L.xbar_get_timing.argtypes = [vp, ctypes.POINTER(Timing), ctypes.c_int32]
         L.xbar_status_string.argtypes = [ctypes.c_int]
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -100,7 +108,8 @@ def lib() -> ctypes.CDLL:
         L.xbar_status_string.restype = ctypes.c_char_p
         for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
-                  "xbar_get_timing", "xbar_set_factor_method", "xbar_transfer",
+                  "xbar_get_timing", "xbar_set_factor_method", "xbar_set_diagnostics",
+                  "xbar_debug_shift_pivots", "xbar_transfer",
                   "xbar_transfer_apply", "xbar_tiles_currents", "xbar_sg_features", "xbar_sg_conv_forward",
                   "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_readout_loss",
                   "xbar_sg_adam", "xbar_sg_predict"):
@@ -177,6 +186,14 @@ def xbar_get_info(plan) -> tuple[int, Info]:
 
 def xbar_set_factor_method(plan, method: int) -> None:
     _check("xbar_set_factor_method", lib().xbar_set_factor_method(plan, int(method)))
+
+
+def xbar_set_diagnostics(plan, enable: bool) -> None:
+    _check("xbar_set_diagnostics", lib().xbar_set_diagnostics(plan, 1 if enable else 0))
+
+
+def xbar_debug_shift_pivots(plan, shift: float) -> None:
+    _check("xbar_debug_shift_pivots", lib().xbar_debug_shift_pivots(plan, float(shift)))
 
 
 def xbar_set_timing(plan, enable: bool) -> None:

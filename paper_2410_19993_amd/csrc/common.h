@@ -119,7 +119,28 @@ __device__ __forceinline__ void lds_barrier()
 // Device error flags (sticky, cleared by assemble).  kNsFail is internal: a
 // Newton-Schulz inverse that missed its tolerance (the factor then reruns
 // with Gauss-Jordan elimination).
-enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNsFail = 4, kNumFlags = 8 };
+enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNsFail = 4, kNsSlotsUsed = 5,
+             kNumFlags = 8 };
+
+// Plan diagnostics (64-bit words, reset by assembly and, for the backward error,
+// by each solve that measures it): the smallest pivot the factor met, as an
+// order-preserving key (pivot_key), and the bit pattern of the largest normwise
+// backward error of a solved batch (a non-negative double, so its bits order
+// like its value; NaN above everything).
+enum : int { kDiagMinPivot = 0, kDiagBackErr = 1, kNumDiag = 4 };
+
+// Key whose unsigned order is the order of the doubles (NaN below everything).
+__host__ __device__ inline unsigned long long pivot_key(double x)
+{
+    if (x != x) return 0ull;
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+constexpr unsigned long long kPivotKeyInf = 0xFFF0000000000000ull;   // pivot_key(+inf)
+
+// Fold a wave's candidate pivots (+inf where a lane has none) into the plan's
+// smallest pivot; a pivot that is not positive (or NaN) raises kErrPivot.
+__device__ inline void record_min_pivot(double v, unsigned long long* diag, int* flags);
 
 constexpr int kNsMaxIter = 6;      // Newton-Schulz steps allowed per chain row
 constexpr int kNsMaxIterTwist = 10;
@@ -155,6 +176,18 @@ struct NSState {
     int slots;    // slot count at which the schedule finished (kNsFinished), else 0
 };
 
+__device__ inline void record_min_pivot(double v, unsigned long long* diag, int* flags)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off);
+        v = (o < v || o != o) ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && !(v == __builtin_inf())) {
+        if (!(v > 0.0)) atomicOr(flags + kErrPivot, 1);
+        atomicMin(diag + kDiagMinPivot, pivot_key(v));
+    }
+}
+
 struct NSArgs {
     int m, n, n_p;
     double g2;
@@ -163,6 +196,7 @@ struct NSArgs {
     NSState* state;          // [2 parities][3 schedules: top chain, bottom chain, twist]
     double* part;            // [2 chains][(n_p/32)^2] per-workgroup max |I - X P| of the current step
     int* flags;
+    unsigned long long* diag;   // [kNumDiag] plan diagnostics
     int max_iter;
 };
 
@@ -194,6 +228,7 @@ struct GJArgs {
     void* H;             // [m][n_p][n_p] FRG: E_i on entry, pivot inverse H_i on exit
     GJJob job[2];        // top and bottom chains (one job for the twist row)
     int* flags;
+    unsigned long long* diag;   // [kNumDiag] plan diagnostics
 };
 
 struct SweepArgs {
@@ -251,6 +286,16 @@ struct RecoverArgs {
     double* node_v;      // [B][2mn]
 };
 
+// Normwise backward error of node voltages (diagnostics.hip).
+struct BackErrArgs {
+    int m, n, B;
+    double g_wl, g_bl, g_src, g_sense;
+    const double* G;          // [m][n]
+    const double* V;          // [B][m]
+    const double* node_v;     // [B][2mn], paper order
+    unsigned long long* diag; // [kNumDiag]: kDiagBackErr receives the batch maximum
+};
+
 }  // namespace xbk
 
 // Host-side launchers (defined in the .hip files, called by the C ABI layer).
@@ -258,7 +303,11 @@ hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_
 hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s);
 hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int chain, int first, int count, hipStream_t s);
+hipError_t xbk_launch_ns_finish(const xbk::NSArgs& a, int launched0, int launched1, int launched2, hipStream_t s);
 hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s);
+hipError_t xbk_launch_backward_error(const xbk::BackErrArgs& a, hipStream_t s);
+hipError_t xbk_launch_shift_diag(void* E, bool fp32, int m, int n, int n_p, double shift, hipStream_t s);
+hipError_t xbk_launch_reset_diag(unsigned long long* diag, int which, hipStream_t s);

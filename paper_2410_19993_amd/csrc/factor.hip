@@ -121,9 +121,11 @@ __device__ inline void store_acc(const typename Frag<T>::acc_t (&acc)[4], T* M, 
 // column go through double-buffered LDS, one barrier per pivot, and every
 // thread updates its 16 entries without branches.  A pivot that is not
 // positive and finite raises kErrPivot.
+// `valid` pivots of the tile lie inside the n x n block (the rest are the
+// identity padding); the smallest of them is folded into the plan's diagnostics.
 template <typename T>
 __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* Pout, int* flags,
-                            int w, int l)
+                            unsigned long long* diag, int valid, int w, int l)
 {
     using v4 = typename std::conditional<sizeof(T) == 8, d4_t, f4_t>::type;
     T* sP = lds;                         // [64][kLd] staging of the tile
@@ -140,6 +142,7 @@ __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* 
 #pragma unroll
     for (int c = 0; c < 16; ++c) a[c] = sP[r * kLd + c0 + c];
     bool bad = false;
+    double dmin = __builtin_inf();
     for (int p = 0; p < kTile; ++p) {
         T* rb = rowb + (p & 1) * kTile;
         T* cb = colb + (p & 1) * kTile;
@@ -163,6 +166,7 @@ __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* 
         const T d = rb[p];
         const T cr = cb[r];
         bad |= !(d > (T)0) || !isfinite(d);
+        if (p < valid) dmin = ((double)d < dmin || d != d) ? (double)d : dmin;
         const T inv = (T)1 / d;
         const bool is_p = (r == p);
         const T f = cr * inv;
@@ -176,6 +180,7 @@ __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* 
         }
     }
     if (bad) atomicOr(flags + kErrPivot, 1);
+    if (threadIdx.x == 0 && valid > 0) atomicMin(diag + kDiagMinPivot, pivot_key(dmin));
 #pragma unroll
     for (int c = 0; c < 16; ++c) Pout[cpr<T>(r, c0 + c, kTile)] = a[c];
 }
@@ -220,7 +225,8 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
             acc[C][v] = form_elem<T>(E, Ha, Hb, frg<T>(rr, cc, a.n_p), a.g2, rr, cc, a.n);
         }
     store_acc<T>(acc, reinterpret_cast<T*>(job.S[0]), a.n_p, 64 * I, 64 * J, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, w, l);
+    if (I == 0 && J == 0)
+        invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, a.diag, min(a.n, kTile), w, l);
 }
 
 // Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
@@ -288,7 +294,8 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
 
     if (k != nb - 1) {
         store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-        if (I == k + 1 && J == k + 1) invert_tile<T>(acc, sA, Pout, a.flags, w, l);
+        if (I == k + 1 && J == k + 1)
+            invert_tile<T>(acc, sA, Pout, a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l);
         return;
     }
     // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
@@ -310,7 +317,7 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
             acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
         }
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, sA, Pout, a.flags, w, l);
+    if (I == 0 && J == 0) invert_tile<T>(acc, sA, Pout, a.flags, a.diag, min(a.n, kTile), w, l);
 }
 
 template <typename T>

@@ -117,6 +117,7 @@ __device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const
     const T* Hb = hslot<T>(a, job.dep_b);
     T* S = reinterpret_cast<T*>(ch.S);
     T* X = reinterpret_cast<T*>(ch.X[xb]);
+    double dmin = __builtin_inf();
     for (int64_t e = e0; e < nn; e += stride) {
         int r, c;
         frg_rc<T>(e, n_p, r, c);
@@ -133,11 +134,15 @@ __device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const
             } else {
                 x = (r == c) ? (T)1 / s : (T)0;
             }
-            if (r == c) ch.dprev[r] = (double)s;
+            if (r == c) {
+                ch.dprev[r] = (double)s;
+                dmin = ((double)s < dmin || s != s) ? (double)s : dmin;
+            }
         }
         S[e] = s;
         X[e] = x;
     }
+    record_min_pivot(dmin, a.diag, a.flags);
 }
 
 // A-operand fragment of FRG tile (tr, tk) of an n_p x n_p block (kt = n_p / 16).
@@ -382,6 +387,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
     T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
     const bool form = (fin || last) && next_row >= 0;
     T* S = reinterpret_cast<T*>(ch.S);
+    double dmin = __builtin_inf();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t o = base + frg_slot<T>(l, v);
@@ -398,6 +404,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
                 if (row == col) {
                     xv += (T)1 / sv - (T)(1.0 / dp);
                     ch.dprev[row] = (double)sv;
+                    dmin = ((double)sv < dmin || sv != sv) ? (double)sv : dmin;
                 }
             }
             S[o] = sv;
@@ -406,6 +413,8 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
             Xout[o] = x;
         }
     }
+    // the diagonal of the next pivot block: only waves on a diagonal tile hold it
+    if (form && TR + (w >> 1) == TC + (w & 1)) record_min_pivot(dmin, a.diag, a.flags);
     return fin;
 }
 
@@ -479,6 +488,24 @@ __global__ void ns_init_kernel(NSArgs a)
     a.state[2] = NSState{kt, kNsForm, 0, 0, 0};
 }
 
+// After a schedule's launch budget: the slots the schedules used (kNsSlotsUsed),
+// and kErrConv when a row missed its tolerance (kNsFail) or a schedule had not
+// finished within its budget.
+__global__ void ns_finish_kernel(NSArgs a, int l0, int l1, int l2)
+{
+    if (threadIdx.x != 0) return;
+    const int launched[3] = {l0, l1, l2};
+    int used = 0;
+    bool open = false;
+    for (int c = 0; c < 3; ++c) {
+        const NSState s = a.state[3 * (launched[c] & 1) + c];
+        if (s.phase != kNsFinished) open = true;
+        used += s.slots;
+    }
+    a.flags[kNsSlotsUsed] = used;
+    if (open || a.flags[kNsFail]) a.flags[kErrConv] = 1;
+}
+
 template <typename T, int NT>
 hipError_t launch_slots_nt(const NSArgs& a, int chain, int first, int count, hipStream_t s)
 {
@@ -520,4 +547,10 @@ hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int chain, int f
     if (chain < 0 || chain > 2) return hipErrorInvalidValue;
     return fp32 ? xbk::launch_slots<float>(a, chain, first, count, s)
                 : xbk::launch_slots<double>(a, chain, first, count, s);
+}
+
+hipError_t xbk_launch_ns_finish(const xbk::NSArgs& a, int launched0, int launched1, int launched2, hipStream_t s)
+{
+    hipLaunchKernelGGL(xbk::ns_finish_kernel, dim3(1), dim3(64), 0, s, a, launched0, launched1, launched2);
+    return hipGetLastError();
 }

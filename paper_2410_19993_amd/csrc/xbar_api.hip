@@ -28,6 +28,7 @@ struct Buffers {
     void* Z = nullptr;        // [nslab][m][16][n_p]
     double* Iout = nullptr;   // [max_batch][n]
     int* flags = nullptr;     // [kNumFlags]
+    unsigned long long* diag = nullptr;   // [kNumDiag]: smallest pivot key, largest backward error bits
     double* sink = nullptr;   // [128]: target of the sweep's masked-off node-voltage stores
     // Newton-Schulz factor: per chain S, X[2], Q ([n_p][n_p]) and dprev ([n_p])
     void* ns_S[2] = {nullptr, nullptr};
@@ -123,10 +124,16 @@ struct xbar_plan_s {
     bool timing = false;
     int32_t factor_method = XBAR_FACTOR_AUTO;
     int64_t gj_fallbacks = 0;
-    int ns_slots_hint[3] = {0, 0, 0};   // slots each Newton-Schulz schedule last needed
+    int ns_slots_hint[3] = {0, 0, 0};   // slots each Newton-Schulz schedule last needed (checked mode)
+    int ns_launched[3] = {0, 0, 0};     // slots the last Newton-Schulz factorization launched
+    int ns_used_host = 0;               // slots used, when the factorization read its states back
+    bool ns_async = false;              // the last factorization ran the asynchronous schedule
+    double pivot_shift = 0.0;           // test hook: subtracted from diag(E_i) at assembly
+    bool diagnostics = false;           // measure the backward error of solved batches
+    bool backerr_valid = false;         // the last solve measured it
     hipStream_t side = nullptr;         // second stream: the bottom chain of the factor
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    PhaseTimer t_condense, t_factor, t_sweep, t_recover;
+    PhaseTimer t_condense, t_factor, t_sweep, t_recover, t_ir_sweep, t_residual;
     bool fp32() const { return prec != XBAR_FP64; }
     size_t elem() const { return fp32() ? sizeof(float) : sizeof(double); }
 };
@@ -149,7 +156,7 @@ void free_all(xbar_plan p)
 {
     Buffers& d = p->d;
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
-                   d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags, d.sink,
+                   d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags, d.diag, d.sink,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
                    d.ns_Q[0], d.ns_Q[1], d.ns_Qt[0], d.ns_Qt[1], d.ns_P2[0], d.ns_P2[1],
                    d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
@@ -179,6 +186,16 @@ void destroy_side(xbar_plan p)
 }
 
 xbk::CondenseArgs condense_args(xbar_plan p, const double* G);
+
+// Condensation of the rows (A1 + A2) into the plan's E blocks, then the test
+// hook's diagonal shift when one is set.
+hipError_t condense(xbar_plan p, const double* G)
+{
+    hipError_t e = xbk_launch_condense(condense_args(p, G), p->fp32(), p->stream);
+    if (e == hipSuccess && p->pivot_shift != 0.0)
+        e = xbk_launch_shift_diag(p->d.H, p->fp32(), p->g.m, p->g.n, p->n_p, p->pivot_shift, p->stream);
+    return e;
+}
 
 }  // namespace
 
@@ -255,6 +272,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     A(&d.Z, (int64_t)p->nslab_max * m * 16 * n_p * es);
     A((void**)&d.Iout, (int64_t)max_batch * n * 8);
     A((void**)&d.flags, xbk::kNumFlags * sizeof(int));
+    A((void**)&d.diag, xbk::kNumDiag * sizeof(unsigned long long));
     A((void**)&d.sink, 128 * sizeof(double));
     for (int c = 0; c < 2; ++c) {
         A(&d.ns_S[c], n_p * n_p * es);
@@ -283,7 +301,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         return st;
     }
     hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, p->stream, d.flags);
-    if (hipGetLastError() != hipSuccess ||
+    if (hipGetLastError() != hipSuccess || xbk_launch_reset_diag(d.diag, 3, p->stream) != hipSuccess ||
         hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -302,9 +320,10 @@ xbar_status xbar_assemble(xbar_plan p, const double* G)
     if (p == nullptr || G == nullptr) return XBAR_ERR_ARG;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
     hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, p->stream, p->d.flags);
-    const xbk::CondenseArgs a = condense_args(p, G);
+    if (xbk_launch_reset_diag(p->d.diag, 3, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    p->backerr_valid = false;
     if (p->timing && !p->t_condense.begin(p->stream)) return XBAR_ERR_DEVICE;
-    if (xbk_launch_condense(a, p->fp32(), p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+    if (condense(p, G) != hipSuccess) return XBAR_ERR_DEVICE;
     if (p->timing && !p->t_condense.end(p->stream)) return XBAR_ERR_DEVICE;
     p->state = kAssembled;
     return XBAR_OK;
@@ -353,14 +372,11 @@ hipError_t launch_gj(xbar_plan p)
         }
     }
     a.flags = p->d.flags;
+    a.diag = p->d.diag;
     return xbk_launch_factor(a, p->fp32(), p->stream);
 }
 
-// Newton-Schulz factor on its device-driven schedule: launch the slots the last
-// factorization needed (or an estimate), read the two chain states back, and
-// launch more until both chains have finished.  *failed: a block missed its
-// tolerance, or the schedule hit its cap.
-hipError_t run_ns(xbar_plan p, bool* failed)
+xbk::NSArgs ns_args(xbar_plan p)
 {
     xbk::NSArgs a{};
     a.m = p->g.m;
@@ -381,13 +397,45 @@ hipError_t run_ns(xbar_plan p, bool* failed)
     a.state = p->d.ns_state;
     a.part = p->d.ns_part;
     a.flags = p->d.flags;
+    a.diag = p->d.diag;
     a.max_iter = xbk::kNsMaxIter;
+    return a;
+}
+
+// Launch budget of a Newton-Schulz schedule that is not read back: the form
+// launch, the cold start of its first row (up to kNsMaxIter + 4 steps), one round
+// (three launches; float32: one step, two launches) for every later row, and a
+// margin of extra rounds for rows that need more than one.  Launches past the
+// schedule's end only carry its final state over.
+int ns_budget(xbar_plan p, int c)
+{
+    const int m = p->g.m, kt = m / 2;
+    const int rows = c == 0 ? kt : c == 1 ? std::max(0, m - 1 - kt) : 1;
+    if (rows == 0) return 0;
+    const bool f64 = !p->fp32();
+    const int per_round = f64 ? 3 : 2, steps_per_round = f64 ? 2 : 1;
+    const int cold = (xbk::kNsMaxIter + 4 + steps_per_round - 1) / steps_per_round;
+    const int margin = c == 2 ? 2 : std::max(6, (rows + 7) / 8);
+    return 1 + per_round * (cold + rows - 1 + margin);
+}
+
+// Newton-Schulz factor on its device-driven schedule.  The two chains run on the
+// plan stream and the side stream (so that one chain's launches fill the matrix
+// cores while the other's start up or write out); schedule 2 (the twist) runs on
+// the plan stream once both have finished.
+//  - asynchronous (checked == false): each schedule gets its launch budget and
+//    nothing is read back, so the call can be captured into a graph; a finishing
+//    kernel raises kErrConv when a row missed its tolerance or a schedule ran out
+//    of launches.
+//  - checked: launch the slots the last factorization needed (or an estimate),
+//    read the states back, and launch more until every schedule has finished;
+//    *failed reports a missed tolerance or the cap.
+hipError_t run_ns(xbar_plan p, bool checked, bool* failed)
+{
+    const xbk::NSArgs a = ns_args(p);
+    *failed = false;
     hipError_t e = xbk_launch_ns_init(a, p->stream);
     if (e != hipSuccess) return e;
-    // Schedules 0 and 1 (the two chains) run on the plan stream and the side stream,
-    // so that one chain's launches fill the matrix cores while the other's start up
-    // or write out; schedule 2 (the twist) runs on the plan stream once both have
-    // finished.
     const int m = p->g.m, kt = m / 2;
     const int rows[3] = {kt, std::max(0, m - 1 - kt), 1};
     hipStream_t on[3] = {p->stream, p->side, p->stream};
@@ -396,10 +444,13 @@ hipError_t run_ns(xbar_plan p, bool* failed)
     for (int c = 0; c < 3; ++c) {
         const int steps = (c == 0 || c == 1) ? xbk::kNsMaxIter : xbk::kNsMaxIter + 4;
         cap[c] = rows[c] * (1 + 2 * (steps + 4)) + 4;
-        batch[c] = rows[c] == 0                ? 0
-                   : p->ns_slots_hint[c] > 0 ? p->ns_slots_hint[c]
-                   : c == 2                  ? 2 * steps + 2
-                                             : rows[c] * 5 + 8;
+        if (!checked)
+            batch[c] = ns_budget(p, c);
+        else
+            batch[c] = rows[c] == 0                ? 0
+                       : p->ns_slots_hint[c] > 0 ? p->ns_slots_hint[c]
+                       : c == 2                  ? 2 * steps + 2
+                                                 : rows[c] * 5 + 8;
     }
     xbk::NSState st[6];
     int fail = 0;
@@ -430,6 +481,13 @@ hipError_t run_ns(xbar_plan p, bool* failed)
                                             hipSuccess)
                         return e;
             for (int c = c0; c <= c1; ++c) launched[c] += batch[c];
+            if (!checked) {
+                if (phase == 0 &&
+                    ((e = hipEventRecord(p->ev_join, p->side)) != hipSuccess ||
+                     (e = hipStreamWaitEvent(p->stream, p->ev_join, 0)) != hipSuccess))
+                    return e;
+                break;
+            }
             if ((e = sync_states()) != hipSuccess) return e;
             bool done = true, over = false;
             for (int c = c0; c <= c1; ++c) {
@@ -446,12 +504,19 @@ hipError_t run_ns(xbar_plan p, bool* failed)
             }
             if (over) {
                 *failed = true;
+                for (int c = 0; c < 3; ++c) p->ns_launched[c] = launched[c];
                 return hipSuccess;
             }
             if (done) break;
         }
     }
-    for (int c = 0; c < 3; ++c) p->ns_slots_hint[c] = state_of(c).slots;
+    for (int c = 0; c < 3; ++c) p->ns_launched[c] = launched[c];
+    if (!checked) return xbk_launch_ns_finish(a, launched[0], launched[1], launched[2], p->stream);
+    p->ns_used_host = 0;
+    for (int c = 0; c < 3; ++c) {
+        p->ns_slots_hint[c] = state_of(c).slots;
+        p->ns_used_host += state_of(c).slots;
+    }
     *failed = fail != 0;
     return hipSuccess;
 }
@@ -569,7 +634,8 @@ extern "C" {
 xbar_status xbar_set_factor_method(xbar_plan p, xbar_factor_method method)
 {
     if (p == nullptr) return XBAR_ERR_ARG;
-    if (method != XBAR_FACTOR_AUTO && method != XBAR_FACTOR_GJ && method != XBAR_FACTOR_NS)
+    if (method != XBAR_FACTOR_AUTO && method != XBAR_FACTOR_GJ && method != XBAR_FACTOR_NS &&
+        method != XBAR_FACTOR_CHECKED)
         return XBAR_ERR_ARG;
     p->factor_method = method;
     return XBAR_OK;
@@ -582,17 +648,21 @@ xbar_status xbar_factor(xbar_plan p)
     if (!set_device(p)) return XBAR_ERR_DEVICE;
     if (p->timing && !p->t_factor.begin(p->stream)) return XBAR_ERR_DEVICE;
     if (p->factor_method == XBAR_FACTOR_GJ) {
+        p->ns_async = false;
+        p->ns_used_host = 0;
+        for (int& c : p->ns_launched) c = 0;
         if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
     } else {
+        const bool checked = p->factor_method != XBAR_FACTOR_AUTO;
+        p->ns_async = !checked;
         bool failed = false;
-        if (run_ns(p, &failed) != hipSuccess) return XBAR_ERR_DEVICE;
-        if (failed && p->factor_method == XBAR_FACTOR_AUTO) {
+        if (run_ns(p, checked, &failed) != hipSuccess) return XBAR_ERR_DEVICE;
+        if (failed && p->factor_method == XBAR_FACTOR_CHECKED) {
             // Redo the factorization by Gauss-Jordan elimination: rebuild E from the
             // plan's copy of G (the Newton-Schulz pass consumed part of it).
             hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
                                (int)xbk::kNsFail);
-            if (xbk_launch_condense(condense_args(p, p->d.Gc), p->fp32(), p->stream) != hipSuccess)
-                return XBAR_ERR_DEVICE;
+            if (condense(p, p->d.Gc) != hipSuccess) return XBAR_ERR_DEVICE;
             if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
             p->gj_fallbacks++;
             for (int& h : p->ns_slots_hint) h = 0;
@@ -679,9 +749,13 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
             s.Uout = p->d.U[(it + 1) & 1];
             if (it > 0) {
                 r.U = p->d.U[it & 1];
+                if (p->timing && !p->t_residual.begin(p->stream)) return XBAR_ERR_DEVICE;
                 if (xbk_launch_residual(r, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+                if (p->timing && !p->t_residual.end(p->stream)) return XBAR_ERR_DEVICE;
             }
+            if (p->timing && !p->t_ir_sweep.begin(p->stream)) return XBAR_ERR_DEVICE;
             if (xbk_launch_sweep_ir(s, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
+            if (p->timing && !p->t_ir_sweep.end(p->stream)) return XBAR_ERR_DEVICE;
         }
     }
     if (p->timing && !p->t_sweep.end(p->stream)) return XBAR_ERR_DEVICE;
@@ -705,6 +779,25 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         if (p->timing && !p->t_recover.begin(p->stream)) return XBAR_ERR_DEVICE;
         if (xbk_launch_recover(r, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
         if (p->timing && !p->t_recover.end(p->stream)) return XBAR_ERR_DEVICE;
+    }
+    p->backerr_valid = false;
+    if (p->diagnostics && node_v != nullptr) {
+        xbk::BackErrArgs be{};
+        be.m = p->g.m;
+        be.n = p->g.n;
+        be.B = B;
+        be.g_wl = 1.0 / p->g.r_wl;
+        be.g_bl = 1.0 / p->g.r_bl;
+        be.g_src = 1.0 / p->g.r_src;
+        be.g_sense = 1.0 / p->g.r_sense;
+        be.G = p->d.Gc;
+        be.V = V;
+        be.node_v = node_v;
+        be.diag = p->d.diag;
+        if (xbk_launch_reset_diag(p->d.diag, 2, p->stream) != hipSuccess ||
+            xbk_launch_backward_error(be, p->stream) != hipSuccess)
+            return XBAR_ERR_DEVICE;
+        p->backerr_valid = true;
     }
     p->state = kSolved;
     p->last_B = B;
@@ -769,8 +862,10 @@ xbar_status xbar_get_info(xbar_plan p, xbar_info* info)
 {
     if (p == nullptr || info == nullptr) return XBAR_ERR_ARG;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
-    int flags[xbk::kNumFlags] = {0, 0, 0, 0};
-    if (hipMemcpyAsync(flags, p->d.flags, sizeof(flags), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
+    int flags[xbk::kNumFlags] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long diag[xbk::kNumDiag] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(flags, p->d.flags, sizeof(flags), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipMemcpyAsync(diag, p->d.diag, sizeof(diag), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
         return XBAR_ERR_DEVICE;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
     std::memset(info, 0, sizeof(*info));
@@ -779,12 +874,37 @@ xbar_status xbar_get_info(xbar_plan p, xbar_info* info)
     info->ir_iters = flags[xbk::kIrIters];
     info->workspace_bytes = p->bytes;
     info->block = p->n_p;
+    // smallest pivot: decode the order-preserving key (+inf: no factorization yet)
+    const unsigned long long k = diag[xbk::kDiagMinPivot];
+    unsigned long long bits;
+    if (k == 0ull) bits = 0x7FF8000000000000ull;
+    else if (k >> 63) bits = k & 0x7FFFFFFFFFFFFFFFull;
+    else bits = ~k;
+    std::memcpy(&info->min_pivot, &bits, sizeof(double));
+    if (p->backerr_valid) std::memcpy(&info->max_backward_err, &diag[xbk::kDiagBackErr], sizeof(double));
+    else info->max_backward_err = -1.0;
+    info->factor_slots_used = p->ns_async ? flags[xbk::kNsSlotsUsed] : p->ns_used_host;
+    info->factor_slots_launched = p->ns_launched[0] + p->ns_launched[1] + p->ns_launched[2];
     xbar_status st = XBAR_OK;
     if (flags[xbk::kErrInput]) st = XBAR_ERR_INPUT;
     else if (flags[xbk::kErrPivot]) st = XBAR_ERR_NOT_SPD;
     else if (flags[xbk::kErrConv]) st = XBAR_ERR_NO_CONVERGENCE;
     info->device_error = (int32_t)st;
     return st;
+}
+
+xbar_status xbar_set_diagnostics(xbar_plan p, int32_t enable)
+{
+    if (p == nullptr) return XBAR_ERR_ARG;
+    p->diagnostics = enable != 0;
+    return XBAR_OK;
+}
+
+xbar_status xbar_debug_shift_pivots(xbar_plan p, double shift)
+{
+    if (p == nullptr || !std::isfinite(shift)) return XBAR_ERR_ARG;
+    p->pivot_shift = shift;
+    return XBAR_OK;
 }
 
 xbar_status xbar_set_timing(xbar_plan p, int32_t enable)
@@ -798,7 +918,7 @@ xbar_status xbar_get_timing(xbar_plan p, xbar_timing* out, int32_t reset)
 {
     if (p == nullptr || out == nullptr) return XBAR_ERR_ARG;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
-    PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover};
+    PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover, &p->t_ir_sweep, &p->t_residual};
     for (PhaseTimer* t : all)
         if (!t->flush()) return XBAR_ERR_DEVICE;
     out->condense_ms = p->t_condense.ms;
@@ -809,6 +929,10 @@ xbar_status xbar_get_timing(xbar_plan p, xbar_timing* out, int32_t reset)
     out->sweep_launches = p->t_sweep.launches;
     out->recover_ms = p->t_recover.ms;
     out->recover_launches = p->t_recover.launches;
+    out->ir_sweep_ms = p->t_ir_sweep.ms;
+    out->ir_sweep_launches = p->t_ir_sweep.launches;
+    out->residual_ms = p->t_residual.ms;
+    out->residual_launches = p->t_residual.launches;
     if (reset)
         for (PhaseTimer* t : all) {
             t->ms = 0.0;
@@ -822,7 +946,7 @@ xbar_status xbar_destroy(xbar_plan p)
     if (p == nullptr) return XBAR_OK;
     (void)set_device(p);
     (void)hipStreamSynchronize(p->stream);
-    PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover};
+    PhaseTimer* all[] = {&p->t_condense, &p->t_factor, &p->t_sweep, &p->t_recover, &p->t_ir_sweep, &p->t_residual};
     for (PhaseTimer* t : all) t->destroy();
     if (p->side) (void)hipStreamSynchronize(p->side);
     destroy_side(p);

@@ -72,7 +72,10 @@ class Surrogate:
         self.grads = torch.zeros_like(self.params)
         self.m1 = torch.zeros_like(self.params)
         self.m2 = torch.zeros_like(self.params)
-        self.work = torch.empty(_lib.xbar_sg_workspace_floats(self.C, self.C), dtype=torch.float32, device="cuda")
+        # the weight gradient's partial sums: the largest need over the layers (the first
+        # maps 7 features to C channels, which needs more than C -> C when C < 7)
+        ws = max(_lib.xbar_sg_workspace_floats(self.dims[k], self.dims[k + 1]) for k in range(self.L))
+        self.work = torch.empty(ws, dtype=torch.float32, device="cuda")
         self._buf_shape = None
         self._solvers = {}
         self.kappa = 1.0
@@ -210,9 +213,23 @@ class Surrogate:
             G, V, r, _, I = data.batch(idx)
             est = torch.empty((len(idx), n), dtype=torch.float64, device="cuda")
             Ip = self.predict(G, V, r, est=est)
-            worst = ((Ip - I).abs() / I.abs()).max(dim=1).values
-            ratios.append((worst / est.max(dim=1).values).cpu().numpy())
-        self.kappa = float(np.quantile(np.concatenate(ratios), quantile))
+            # columns with no exact current (an all-zero input vector) carry no relative
+            # error; samples without any such column, or with a non-finite estimate, are
+            # left out of the quantile
+            live = I.abs() > 0
+            rel = torch.where(live, (Ip - I).abs() / torch.where(live, I.abs(), torch.ones_like(I)),
+                              torch.zeros_like(I))
+            worst = rel.max(dim=1).values
+            emax = est.max(dim=1).values
+            ok = live.any(dim=1) & torch.isfinite(worst) & torch.isfinite(emax) & (emax > 0)
+            ratios.append((worst[ok] / emax[ok]).cpu().numpy())
+        ratios = np.concatenate(ratios)
+        if ratios.size == 0:
+            raise ValueError("calibration set has no sample with a nonzero exact current and a finite estimate")
+        kappa = float(np.quantile(ratios, quantile))
+        if not np.isfinite(kappa) or kappa <= 0:
+            raise ValueError(f"calibration gave a kappa that is not finite and positive: {kappa}")
+        self.kappa = kappa
         return self.kappa
 
     def predict_checked(self, G, V, r, tol: float = 0.01, r_src: float = 50.0, r_sense: float = 50.0,
@@ -228,7 +245,13 @@ class Surrogate:
         B, m, n = (int(x) for x in G.shape)
         est = torch.empty((B, n), dtype=torch.float64, device="cuda")
         out = self.predict(G, V, r, est=est)
-        flagged = (self.kappa * est.max(dim=1).values > tol).cpu().numpy()
+        # a sample is trusted only when its scaled estimate is a number <= tol in every
+        # column and its currents are finite; samples whose conductances are not finite
+        # and positive, or whose inputs are not finite, go to the exact solver, which
+        # reports them (XBAR_ERR_INPUT) instead of returning surrogate values
+        trusted = (self.kappa * est.max(dim=1).values <= tol) & torch.isfinite(out).all(dim=1)
+        valid = (torch.isfinite(G) & (G > 0)).flatten(1).all(dim=1) & torch.isfinite(V).all(dim=1)
+        flagged = (~(trusted & valid)).cpu().numpy()
         idx = np.nonzero(flagged)[0]
         if len(idx):
             rs = r.cpu().numpy()

@@ -5,6 +5,8 @@ seeded workloads of ``workloads/``; nothing is read from the GPU library.
 
     python tests/golden/make_golden.py c2          # 128x128, all 1024 input vectors
     python tests/golden/make_golden.py c3          # 512x512, seeded 256-vector subset, r in {1, 2.5, 5}
+    python tests/golden/make_golden.py c4          # heterogeneous tiles: the first tile of each of
+                                                   # the 16 (m_t, n_t) classes, all 256 vectors
 
 Outputs (float64 .npy/.npz next to this file):
 
@@ -12,6 +14,9 @@ Outputs (float64 .npy/.npz next to this file):
 * ``c3_r{r}_currents.npy``       [256][512]   rows = workloads.c3_subset()
 * ``c3_r{r}_nodes.npz``          node voltages of the first 8 subset vectors at
                                  4096 seeded node indices (``idx``, ``v``)
+* ``c4_class_currents.npz``      per (m_t, n_t) class: the index of the class's first tile
+                                 in workloads.c4() (``t{m}x{n}``) and its currents
+                                 [256][n_t] (``I{m}x{n}``)
 * ``manifest.json``              oracle diagnostics and timings per file
 """
 from __future__ import annotations
@@ -67,10 +72,32 @@ def make_c3(rs=workloads.C3_R):
         del res
 
 
+def make_c4():
+    g = workloads.C4_GEOM
+    r = (g["r_wl"], g["r_bl"], g["r_src"], g["r_sense"])
+    first = {}
+    for t in workloads.c4():
+        first.setdefault(t.G.shape, t)
+    out, info = {}, {}
+    for (m, n), t in sorted(first.items()):
+        t0 = time.time()
+        res = oracle.solve(t.G, t.V, *r)
+        out[f"t{m}x{n}"] = np.array(t.index)
+        out[f"I{m}x{n}"] = res.currents
+        info[f"{m}x{n}"] = {"tile": t.index, "seconds": time.time() - t0, "residual_inf_A": res.residual_inf,
+                           "min_pivot": res.min_pivot}
+        print(f"c4 {m}x{n} tile {t.index}: {time.time() - t0:.1f} s", flush=True)
+    np.savez(os.path.join(HERE, "c4_class_currents.npz"), **out)
+    _manifest_update("c4_class_currents.npz", {"workload": "c4 (seed 1004), first tile of each class",
+                                               "vectors": 256, "refine": 2, "classes": info})
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c2", "c3"]
+    which = sys.argv[1:] or ["c2", "c3", "c4"]
     if "c2" in which:
         make_c2()
     if "c3" in which:
-        rs = [float(x) for x in which[which.index("c3") + 1:]] or list(workloads.C3_R)
+        rs = [float(x) for x in which[which.index("c3") + 1:] if x[0].isdigit()] or list(workloads.C3_R)
         make_c3(rs)
+    if "c4" in which:
+        make_c4()

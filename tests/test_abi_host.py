@@ -8,8 +8,9 @@ import pytest
 
 from paper_2410_19993_amd import _lib
 
-EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_destroy", "xbar_factor", "xbar_get_info",
-            "xbar_get_timing", "xbar_set_factor_method", "xbar_set_timing", "xbar_sg_adam",
+EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_debug_shift_pivots", "xbar_destroy",
+            "xbar_factor", "xbar_get_info", "xbar_get_timing", "xbar_set_diagnostics", "xbar_set_factor_method",
+            "xbar_set_timing", "xbar_sg_adam",
             "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_conv_forward",
             "xbar_sg_features", "xbar_sg_predict", "xbar_sg_readout_loss", "xbar_sg_workspace_floats",
             "xbar_solve_batch", "xbar_status_string", "xbar_tiles_currents", "xbar_transfer",
@@ -93,6 +94,19 @@ def test_null_plan_calls():
     assert L.xbar_set_timing(None, 1) == _lib.XBAR_ERR_ARG
     assert L.xbar_set_factor_method(None, 0) == _lib.XBAR_ERR_ARG
     assert L.xbar_get_timing(None, ctypes.byref(_lib.Timing()), 0) == _lib.XBAR_ERR_ARG
+    assert L.xbar_set_diagnostics(None, 1) == _lib.XBAR_ERR_ARG
+    assert L.xbar_debug_shift_pivots(None, 1.0) == _lib.XBAR_ERR_ARG
+
+
+def test_info_struct_matches_the_header():
+    """The binding's xbar_info mirrors the header's field order and types."""
+    import re
+    text = open(_lib.HEADER).read()
+    body = text[text.index("typedef struct {\n    int32_t state;"):]
+    body = body[:body.index("} xbar_info;")]
+    fields = re.findall(r"^\s*(int32_t|int64_t|double)\s+(\w+);", body, re.M)
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    assert [(n, ctype[t]) for t, n in fields] == list(_lib.Info._fields_)
 
 
 @pytest.mark.skipif(_gpu_visible(), reason="checks the GPU-less path")

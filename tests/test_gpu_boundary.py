@@ -1,0 +1,209 @@
+"""The plan boundary's diagnostics and factor methods on a GPU (include/xbar.h).
+
+* min_pivot: the smallest pivot the factorization met (Sec. II.C).  A 1 x 1
+  crossbar condenses to the single pivot q - G^2 / t (App. of the stamps:
+  t = G + g_src, q = G + g_sense), which both inversion methods must report;
+  on any crossbar the pivots are diagonals of Schur complements of an SPD
+  matrix, so 0 < min_pivot <= the smallest bit-line self conductance q_ij.
+* A forced non-SPD pivot (the shift hook) must give XBAR_ERR_NOT_SPD with every
+  kernel exiting normally, and the plan must work again once the hook is off.
+* max_backward_err: the normwise backward error of the returned node voltages,
+  compared with the oracle's evaluation of the same quantity on the same
+  voltages (KCL residual from the resistor list, ||A||_inf from the oracle's band
+  matrix, ||b||_inf from its injections), on a solution left unrefined on
+  purpose so that the residual stands far above rounding.
+* The default factor is asynchronous: assemble + factor + solve_batch captured
+  into one HIP graph and replayed must give the eager bits.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import diagnostics as dg
+from paper_2410_19993_amd import _lib
+from tests.gpu_util import TOL_FP64, gpu_solve, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve_with(wl, precision="fp64", method="auto", diagnostics=False, shift=0.0, **kw):
+    import torch
+
+    import paper_2410_19993_amd as xb
+    g = wl.geom
+    m, n = wl.G.shape
+    B = wl.V.shape[0]
+    G = torch.from_numpy(np.ascontiguousarray(wl.G)).cuda()
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).cuda()
+    nv = torch.empty((B, 2 * m * n), dtype=torch.float64, device="cuda")
+    with xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B,
+                 factor_method=method, **kw) as p:
+        p.set_diagnostics(diagnostics)
+        if shift:
+            p.debug_shift_pivots(shift)
+        p.assemble(G)
+        p.factor()
+        p.solve_batch(V, nv)
+        I = p.currents()
+        st, info = p.info()
+    return I.cpu().numpy(), nv.cpu().numpy(), st, info
+
+
+@pytest.mark.parametrize("method", ["auto", "gj", "checked"])
+def test_min_pivot_single_cell_closed_form(method):
+    G, rs, rt = 3e-5, 40.0, 60.0
+    wl = workloads.random_crossbar(1, 1, 2, 3, r_wl=1.0, r_bl=1.0, r_src=rs, r_sense=rt)
+    wl.G[:] = G
+    _, _, st, info = _solve_with(wl, method=method)
+    t, q = G + 1.0 / rs, G + 1.0 / rt
+    want = q - G * G / t
+    log(f"  {method}: min_pivot {info.min_pivot!r} against {want!r}")
+    assert st == 0
+    assert abs(info.min_pivot - want) <= 4e-16 * want
+
+
+@pytest.mark.parametrize("method", ["auto", "gj"])
+@pytest.mark.parametrize("m,n", [(16, 16), (33, 70), (9, 300)])
+def test_min_pivot_bounded_by_bitline_diagonal(m, n, method):
+    wl = workloads.random_crossbar(m, n, 4, 31 + m, r_wl=2.0, r_bl=3.0, r_src=50.0, r_sense=50.0)
+    _, _, st, info = _solve_with(wl, method=method)
+    gb, gt = 1.0 / wl.geom.r_bl, 1.0 / wl.geom.r_sense
+    i = np.arange(m)[:, None]
+    q = wl.G + np.where(i > 0, gb, 0.0) + np.where(i < m - 1, gb, gt)
+    log(f"  {method} {m}x{n}: min_pivot {info.min_pivot:.6e}, min q {q.min():.6e}")
+    assert st == 0
+    assert 0.0 < info.min_pivot <= q.min() * (1 + 1e-14)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("method", ["auto", "gj", "ns", "checked"])
+def test_forced_non_spd_pivot_is_reported(method, precision):
+    """The shift hook subtracts 10 S from every diagonal entry of the condensed blocks
+    (far above their ~1 S diagonal): the factor must flag XBAR_ERR_NOT_SPD and report a
+    negative min_pivot, every kernel must still exit (the calls return), and the same
+    plan must solve normally once the hook is switched off."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    wl = workloads.random_crossbar(12, 40, 8, 41, r_wl=1.0, r_bl=1.0)
+    log(f"case forced non-SPD {method} {precision}")
+    g = wl.geom
+    G = torch.from_numpy(wl.G).cuda()
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).cuda()
+    with xb.Plan(12, 40, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=8, factor_method=method) as p:
+        p.debug_shift_pivots(10.0)
+        p.assemble(G)
+        p.factor()
+        p.solve_batch(V)
+        st, info = p.info()
+        log(f"  status {st}, min_pivot {info.min_pivot:.3e}")
+        assert st == _lib.XBAR_ERR_NOT_SPD and info.device_error == _lib.XBAR_ERR_NOT_SPD
+        assert info.min_pivot < 0.0
+        p.debug_shift_pivots(0.0)
+        p.assemble(G)
+        p.factor()
+        p.solve_batch(V)
+        I = p.currents().cpu().numpy()
+        st2, info2 = p.info()
+    ref = oracle.solve_workload(wl)
+    assert st2 == 0 and info2.min_pivot > 0.0
+    assert rel_err(I, ref.currents).max() <= 1e-9
+
+
+def _oracle_backward_error(wl, node_v):
+    g = wl.geom
+    net = oracle.build_netlist(wl.G, g.r_wl, g.r_bl, g.r_src, g.r_sense)
+    ab, _ = oracle.assemble_band(net)
+    a_inf = np.abs(ab).sum(axis=1).max()
+    b = oracle.injections(net, wl.V)                      # [N][B]
+    r = dg.kcl_imbalance(net, wl.V, node_v)               # [B][N] = b - A v
+    den = a_inf * np.abs(node_v).max(axis=1) + np.abs(b).max(axis=0)
+    return np.abs(r).max(axis=1) / den
+
+
+def test_backward_error_matches_oracle_on_unrefined_solution():
+    """The bfloat16 trial with a single correction sweep leaves node voltages whose
+    residual stands far above float64 rounding, so the GPU's and the oracle's
+    evaluations of the backward error must agree closely."""
+    wl = workloads.random_crossbar(20, 48, 16, 43, r_wl=2.5, r_bl=2.5)
+    I, nv, st, info = _solve_with(wl, precision="bf16_ir", diagnostics=True, ir_tol=1e-15, ir_max_iter=1)
+    eta = _oracle_backward_error(wl, nv)
+    log(f"  status {st}; GPU max backward error {info.max_backward_err:.9e}, oracle {eta.max():.9e}")
+    assert eta.max() > 1e-9                                   # far above rounding
+    assert abs(info.max_backward_err - eta.max()) <= 1e-8 * eta.max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_backward_error_of_converged_solutions_is_at_rounding(precision):
+    wl = workloads.c1()
+    I, nv, st, info = _solve_with(wl, precision=precision, diagnostics=True)
+    eta = _oracle_backward_error(wl, nv)
+    log(f"  {precision}: GPU max backward error {info.max_backward_err:.3e}, oracle {eta.max():.3e}")
+    assert st == 0
+    assert 0.0 <= info.max_backward_err <= 1e-15 and eta.max() <= 1e-15
+
+
+def test_backward_error_not_measured_without_node_voltages_or_switch():
+    wl = workloads.c1()
+    _, _, st, info = _solve_with(wl)
+    assert st == 0 and info.max_backward_err == -1.0
+
+
+@pytest.mark.parametrize("wl_name", ["c1", "c2"])
+def test_async_factor_budget_covers_the_schedule(wl_name):
+    wl = getattr(workloads, wl_name)()
+    I, _, st, info = _solve_with(wl)
+    ref_I = gpu_solve(wl.G, wl.V, wl.geom, node_voltages=False, factor_method="checked")[0]
+    log(f"  {wl_name}: Newton-Schulz launches used {info.factor_slots_used} of {info.factor_slots_launched}")
+    assert st == 0
+    assert 0 < info.factor_slots_used <= info.factor_slots_launched
+    # the asynchronous budget and the read-back schedule run the same rounds: same bits
+    assert np.array_equal(I, ref_I)
+
+
+def test_graph_capture_of_assemble_factor_solve_replays_eager_bits():
+    import torch
+
+    import paper_2410_19993_amd as xb
+    wl = workloads.random_crossbar(40, 96, 32, 47, r_wl=2.5, r_bl=2.5)
+    m, n = wl.G.shape
+    B = wl.V.shape[0]
+    G = torch.from_numpy(wl.G).cuda()
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).cuda()
+    nv = torch.empty((B, 2 * m * n), dtype=torch.float64, device="cuda")
+    I = torch.empty((B, n), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    with xb.Plan(m, n, 2.5, 2.5, 50.0, 50.0, "fp64", max_batch=B, stream=s) as p:
+        with torch.cuda.stream(s):
+            p.assemble(G)
+            p.factor()
+            p.solve_batch(V, nv)
+            p.currents(I)
+        s.synchronize()
+        I_eager, nv_eager = I.clone(), nv.clone()
+        st, _ = p.info()
+        assert st == 0
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            p.assemble(G)
+            p.factor()
+            p.solve_batch(V, nv)
+            p.currents(I)
+        for rep in range(3):
+            I.zero_()
+            nv.fill_(-1.0)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            log(f"  replay {rep}: currents equal {torch.equal(I, I_eager)}")
+            assert torch.equal(I, I_eager) and torch.equal(nv, nv_eager)
+            # eager work on the same plan between replays
+            with torch.cuda.stream(s):
+                p.assemble(G * 1.01)
+                p.factor()
+            s.synchronize()
+        st, _ = p.info()
+        assert st == 0
+    ref = oracle.solve_workload(wl)
+    assert rel_err(I_eager.cpu().numpy(), ref.currents).max() <= TOL_FP64

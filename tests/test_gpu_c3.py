@@ -22,18 +22,18 @@ from tests.gpu_util import GOLDEN, TOL_FP64, TOL_IR, log, rel_err
 pytestmark = pytest.mark.gpu
 
 
-def _solve_c3(r, precision):
+def _solve_c3(r, precision, ir_tol=0.0):
     import torch
 
     import paper_2410_19993_amd as xb
     wl = workloads.c3(r=r)
     g = wl.geom
     m, n, B = wl.G.shape[0], wl.G.shape[1], wl.B
-    log(f"case c3 r={r} {precision}: m={m} n={n} B={B}")
+    log(f"case c3 r={r} {precision} ir_tol={ir_tol}: m={m} n={n} B={B}")
     G = torch.from_numpy(wl.G).cuda()
     V = torch.from_numpy(np.ascontiguousarray(wl.V)).cuda()
     nv = torch.empty((B, 2 * m * n), dtype=torch.float64, device="cuda")
-    with xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B) as p:
+    with xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, precision, max_batch=B, ir_tol=ir_tol) as p:
         p.assemble(G)
         p.factor()
         p.solve_batch(V, nv)
@@ -79,8 +79,15 @@ def test_c3_fp64(r):
     _check(wl, V, nv, I, TOL_FP64)
 
 
-def test_c3_fp32_ir():
-    wl, V, nv, I, st, info = _solve_c3(2.5, "fp32_ir")
+# the benchmark's refinement tolerance (its float32 + refinement leg targets 1e-9)
+BENCH_IR_TOL = 1e-10
+
+
+@pytest.mark.parametrize("r", [1.0, 2.5, 5.0])
+def test_c3_fp32_ir(r):
+    """float32 factor + float64 refinement in the benchmark's configuration (ir_tol 1e-10)
+    at every segment resistance of the 512 x 512 workload."""
+    wl, V, nv, I, st, info = _solve_c3(r, "fp32_ir", ir_tol=BENCH_IR_TOL)
     assert st == 0
     log(f"  refinement sweeps {info.ir_iters}")
     _check(wl, V, nv, I, TOL_IR)

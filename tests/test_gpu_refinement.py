@@ -70,17 +70,24 @@ def test_zero_inputs_converge_at_once():
     assert np.all(I == 0) and np.all(nv == 0)
 
 
-@pytest.mark.parametrize("wl_name", ["c1", "ragged64"])
+@pytest.mark.parametrize("wl_name", ["c1", "ragged64", "c2"])
 def test_bf16_trial_reports_its_outcome(wl_name):
     """The bfloat16 trial (the float32 factor's inverse blocks rounded to bfloat16):
     with kappa * u_bf16 well above one the refinement cannot be expected to contract.
     Whatever it does, the library must either meet the refinement tolerance (and then
     agree with the oracle) or say that it did not (XBAR_ERR_NO_CONVERGENCE), never
     return wrong currents as converged."""
-    wl = workloads.c1() if wl_name == "c1" else workloads.random_crossbar(64, 64, 16, 19)
-    I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, "bf16_ir", ir_max_iter=20)
-    ref = oracle.solve_workload(wl)
-    e = rel_err(I, ref.currents)
+    if wl_name == "c2":
+        # 128 x 128, 1024 vectors, against the stored oracle currents
+        wl = workloads.c2()
+        ref_I = np.load(os.path.join(GOLDEN, "c2_currents.npy"))
+        I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, "bf16_ir", node_voltages=False, ir_max_iter=30,
+                                      ir_tol=1e-10)
+    else:
+        wl = workloads.c1() if wl_name == "c1" else workloads.random_crossbar(64, 64, 16, 19)
+        I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, "bf16_ir", ir_max_iter=20)
+        ref_I = oracle.solve_workload(wl).currents
+    e = rel_err(I, ref_I)
     log(f"  bf16 trial {wl_name}: status {st}, sweeps {info.ir_iters}, max current rel err {e.max():.3e}")
     assert st in (0, 5)
     if st == 0:
