@@ -136,10 +136,11 @@ xbar_status xbar_assemble(xbar_plan plan, const double* G);
  * a block LU over the m row blocks.  Requires a prior xbar_assemble
  * (otherwise XBAR_ERR_STATE).  A pivot that is not positive sets
  * XBAR_ERR_NOT_SPD on the device (see xbar_info.min_pivot).  In the default
- * method (XBAR_FACTOR_AUTO) the call is asynchronous and reads nothing back,
- * so it can be captured into a HIP graph with the other calls: the plan's own
- * second stream is forked from and joined back to the plan stream by events
- * within the call.  See xbar_set_factor_method for the other methods.
+ * method (XBAR_FACTOR_AUTO) every factorization of a plan after its first is
+ * asynchronous and reads nothing back, so it can be captured into a HIP graph
+ * with the other calls: the plan's own second stream is forked from and joined
+ * back to the plan stream by events within the call.  See
+ * xbar_set_factor_method for the details and the other methods.
  */
 xbar_status xbar_factor(xbar_plan plan);
 
@@ -237,12 +238,17 @@ xbar_status xbar_get_info(xbar_plan plan, xbar_info* info);
 /*
  * How xbar_factor inverts the pivot blocks of the block LU.
  *   XBAR_FACTOR_AUTO (default): Newton-Schulz iteration on the matrix cores, on
- *       a schedule driven by the device with a fixed launch budget derived from
- *       the geometry (one two-step round per row, a cold start for each chain,
- *       and a margin); launches past a schedule's end do nothing.  Asynchronous
- *       and capturable.  A block that misses its tolerance, or a budget that
- *       runs out, sets XBAR_ERR_NO_CONVERGENCE on the device; the caller may
- *       then refactor with XBAR_FACTOR_CHECKED or XBAR_FACTOR_GJ.
+ *       a schedule driven by the device.  The first factorization of a plan
+ *       reads the schedule back (it synchronises the plan's stream) and so
+ *       learns how many launches each of its three schedules needs; later ones
+ *       are asynchronous and capturable: each schedule gets that many launches
+ *       plus a margin of extra rounds (launches past a schedule's end do
+ *       nothing), and nothing is read back.  xbar_get_info refreshes the
+ *       counts from the device.  A block that misses its tolerance, or a budget
+ *       that runs out, sets XBAR_ERR_NO_CONVERGENCE on the device (after a
+ *       budget ran out the next factorization reads back again); the caller may
+ *       then refactor, or use XBAR_FACTOR_CHECKED or XBAR_FACTOR_GJ.  To capture
+ *       a plan's factorization into a graph, factor it once eagerly first.
  *   XBAR_FACTOR_GJ: blocked Gauss-Jordan elimination only (asynchronous).
  *   XBAR_FACTOR_NS: Newton-Schulz; the call reads the schedule states back and
  *       launches until every row has finished (it synchronises the plan's
@@ -358,6 +364,7 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
 
 /* Floats of workspace xbar_sg_conv_backward_weight needs (-1 for bad C, O). */
 int64_t xbar_sg_workspace_floats(int32_t C, int32_t O);
+
 
 /* Column readouts and loss of the last map Y [B][2][m][n] (float32):
  * yhat_j = mean_i Y[b][0][i][j] (the correction), s_j = mean_i Y[b][1][i][j] (the

@@ -119,7 +119,9 @@ __device__ __forceinline__ void lds_barrier()
 // Device error flags (sticky, cleared by assemble).  kNsFail is internal: a
 // Newton-Schulz inverse that missed its tolerance (the factor then reruns
 // with Gauss-Jordan elimination).
-enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNsFail = 4, kNsSlotsUsed = 5,
+// kNsUsed + c: launches Newton-Schulz schedule c needed in the last asynchronous
+// factorization (0 if it did not finish within its budget).
+enum : int { kErrInput = 0, kErrPivot = 1, kErrConv = 2, kIrIters = 3, kNsFail = 4, kNsUsed = 5,
              kNumFlags = 8 };
 
 // Plan diagnostics (64-bit words, reset by assembly and, for the backward error,

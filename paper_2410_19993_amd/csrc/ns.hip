@@ -488,21 +488,20 @@ __global__ void ns_init_kernel(NSArgs a)
     a.state[2] = NSState{kt, kNsForm, 0, 0, 0};
 }
 
-// After a schedule's launch budget: the slots the schedules used (kNsSlotsUsed),
-// and kErrConv when a row missed its tolerance (kNsFail) or a schedule had not
-// finished within its budget.
+// After the schedules' launch budgets: the launches each schedule needed
+// (kNsUsed + c, 0 for one that had not finished), and kErrConv when a row missed
+// its tolerance (kNsFail) or a schedule had not finished within its budget.
 __global__ void ns_finish_kernel(NSArgs a, int l0, int l1, int l2)
 {
     if (threadIdx.x != 0) return;
     const int launched[3] = {l0, l1, l2};
-    int used = 0;
     bool open = false;
     for (int c = 0; c < 3; ++c) {
         const NSState s = a.state[3 * (launched[c] & 1) + c];
-        if (s.phase != kNsFinished) open = true;
-        used += s.slots;
+        const bool fin = s.phase == kNsFinished;
+        open |= !fin;
+        a.flags[kNsUsed + c] = fin ? s.slots : 0;
     }
-    a.flags[kNsSlotsUsed] = used;
     if (open || a.flags[kNsFail]) a.flags[kErrConv] = 1;
 }
 

@@ -1,5 +1,6 @@
 // C ABI of the crossbar solver: plan lifetime, host-side validation,
 // workspace sizing and the call-order state machine (include/xbar.h).
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -127,6 +128,7 @@ struct xbar_plan_s {
     int ns_slots_hint[3] = {0, 0, 0};   // slots each Newton-Schulz schedule last needed (checked mode)
     int ns_launched[3] = {0, 0, 0};     // slots the last Newton-Schulz factorization launched
     int ns_used_host = 0;               // slots used, when the factorization read its states back
+    bool ns_hint_valid = false;         // ns_slots_hint holds what the last factorization needed
     bool ns_async = false;              // the last factorization ran the asynchronous schedule
     double pivot_shift = 0.0;           // test hook: subtracted from diag(E_i) at assembly
     bool diagnostics = false;           // measure the backward error of solved batches
@@ -402,21 +404,22 @@ xbk::NSArgs ns_args(xbar_plan p)
     return a;
 }
 
-// Launch budget of a Newton-Schulz schedule that is not read back: the form
-// launch, the cold start of its first row (up to kNsMaxIter + 4 steps), one round
-// (three launches; float32: one step, two launches) for every later row, and a
-// margin of extra rounds for rows that need more than one.  Launches past the
-// schedule's end only carry its final state over.
+// Launch budget of a Newton-Schulz schedule that is not read back: the launches
+// it needed the last time they were read back (ns_slots_hint), plus a margin of
+// extra rounds (three launches each in float64, one two-launch step in float32)
+// for a conductance map whose rows need more.  The margin grows with the rounds
+// beyond one per row that the schedule needed then (k): rows that need one or two
+// rounds make the count vary from map to map by about sqrt(k) rounds.  Launches
+// past a schedule's end only carry its final state over.
 int ns_budget(xbar_plan p, int c)
 {
     const int m = p->g.m, kt = m / 2;
     const int rows = c == 0 ? kt : c == 1 ? std::max(0, m - 1 - kt) : 1;
     if (rows == 0) return 0;
-    const bool f64 = !p->fp32();
-    const int per_round = f64 ? 3 : 2, steps_per_round = f64 ? 2 : 1;
-    const int cold = (xbk::kNsMaxIter + 4 + steps_per_round - 1) / steps_per_round;
-    const int margin = c == 2 ? 2 : std::max(6, (rows + 7) / 8);
-    return 1 + per_round * (cold + rows - 1 + margin);
+    const int per_round = p->fp32() ? 2 : 3;
+    const double k = std::max(0.0, (p->ns_slots_hint[c] - 1) / (double)per_round - rows);
+    const int margin = 4 + (int)std::ceil(0.5 * k + 4.0 * std::sqrt(k));
+    return p->ns_slots_hint[c] + per_round * margin;
 }
 
 // Newton-Schulz factor on its device-driven schedule.  The two chains run on the
@@ -518,6 +521,7 @@ hipError_t run_ns(xbar_plan p, bool checked, bool* failed)
         p->ns_used_host += state_of(c).slots;
     }
     *failed = fail != 0;
+    p->ns_hint_valid = true;
     return hipSuccess;
 }
 
@@ -653,7 +657,9 @@ xbar_status xbar_factor(xbar_plan p)
         for (int& c : p->ns_launched) c = 0;
         if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
     } else {
-        const bool checked = p->factor_method != XBAR_FACTOR_AUTO;
+        // AUTO reads the schedule back (and learns its launch counts) until it has
+        // counts from an earlier factorization of this plan; then it runs asynchronously
+        const bool checked = p->factor_method != XBAR_FACTOR_AUTO || !p->ns_hint_valid;
         p->ns_async = !checked;
         bool failed = false;
         if (run_ns(p, checked, &failed) != hipSuccess) return XBAR_ERR_DEVICE;
@@ -666,6 +672,7 @@ xbar_status xbar_factor(xbar_plan p)
             if (launch_gj(p) != hipSuccess) return XBAR_ERR_DEVICE;
             p->gj_fallbacks++;
             for (int& h : p->ns_slots_hint) h = 0;
+            p->ns_hint_valid = false;
         } else if (failed) {
             // Newton-Schulz only: report the miss through the sticky flags
             hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, p->stream, p->d.flags,
@@ -883,7 +890,22 @@ xbar_status xbar_get_info(xbar_plan p, xbar_info* info)
     std::memcpy(&info->min_pivot, &bits, sizeof(double));
     if (p->backerr_valid) std::memcpy(&info->max_backward_err, &diag[xbk::kDiagBackErr], sizeof(double));
     else info->max_backward_err = -1.0;
-    info->factor_slots_used = p->ns_async ? flags[xbk::kNsSlotsUsed] : p->ns_used_host;
+    if (p->ns_async) {
+        // what the asynchronous factorization needed becomes the next one's budget base
+        info->factor_slots_used = flags[xbk::kNsUsed] + flags[xbk::kNsUsed + 1] + flags[xbk::kNsUsed + 2];
+        bool all = true;
+        for (int c = 0; c < 3; ++c) {
+            const int rows = c == 0 ? p->g.m / 2 : c == 1 ? std::max(0, p->g.m - 1 - p->g.m / 2) : 1;
+            all &= rows == 0 || flags[xbk::kNsUsed + c] > 0;
+        }
+        if (all) {
+            for (int c = 0; c < 3; ++c) p->ns_slots_hint[c] = flags[xbk::kNsUsed + c];
+        } else {
+            p->ns_hint_valid = false;       // a budget ran out: the next factorization re-learns
+        }
+    } else {
+        info->factor_slots_used = p->ns_used_host;
+    }
     info->factor_slots_launched = p->ns_launched[0] + p->ns_launched[1] + p->ns_launched[2];
     xbar_status st = XBAR_OK;
     if (flags[xbk::kErrInput]) st = XBAR_ERR_INPUT;

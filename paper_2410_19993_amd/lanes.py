@@ -49,7 +49,10 @@ class PlanLanes:
     def _plan(self, lane, m, n):
         p = lane["plans"].get((m, n))
         if p is None:
-            p = Plan(m, n, *self.r, precision=self.precision, max_batch=self.max_batch, stream=lane["stream"])
+            # each crossbar of a lane is a new conductance map on the same plan: the factor
+            # reads its schedule back and falls back to Gauss-Jordan if it must
+            p = Plan(m, n, *self.r, precision=self.precision, max_batch=self.max_batch, stream=lane["stream"],
+                     factor_method="checked")
             lane["plans"][(m, n)] = p
         return p
 

@@ -150,16 +150,40 @@ def test_backward_error_not_measured_without_node_voltages_or_switch():
     assert st == 0 and info.max_backward_err == -1.0
 
 
+@pytest.mark.parametrize("r", [1.0, 2.5, 5.0])
 @pytest.mark.parametrize("wl_name", ["c1", "c2"])
-def test_async_factor_budget_covers_the_schedule(wl_name):
+def test_async_factor_learns_its_budget(wl_name, r):
+    """The default factor reads its schedule back the first time (learning how many
+    launches each schedule needs) and runs asynchronously after that, within the
+    learned count plus a margin: same bits as the read-back factorization, also on a
+    second conductance map."""
+    import torch
+
+    import paper_2410_19993_amd as xb
     wl = getattr(workloads, wl_name)()
-    I, _, st, info = _solve_with(wl)
-    ref_I = gpu_solve(wl.G, wl.V, wl.geom, node_voltages=False, factor_method="checked")[0]
-    log(f"  {wl_name}: Newton-Schulz launches used {info.factor_slots_used} of {info.factor_slots_launched}")
-    assert st == 0
-    assert 0 < info.factor_slots_used <= info.factor_slots_launched
-    # the asynchronous budget and the read-back schedule run the same rounds: same bits
-    assert np.array_equal(I, ref_I)
+    m, n = wl.G.shape
+    B = wl.V.shape[0]
+    G = torch.from_numpy(wl.G).cuda()
+    G2 = torch.from_numpy(np.ascontiguousarray(wl.G[::-1])).cuda()      # another map: rows reversed
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).cuda()
+    with xb.Plan(m, n, r, r, 50.0, 50.0, "fp64", max_batch=B) as p:
+        out = []
+        for k, Gk in enumerate((G, G, G2)):
+            p.assemble(Gk)
+            p.factor()
+            p.solve_batch(V)
+            out.append(p.currents().cpu().numpy())
+            st, info = p.info()
+            log(f"  {wl_name} r={r} factorization {k}: status {st}, Newton-Schulz launches used "
+                f"{info.factor_slots_used} of {info.factor_slots_launched}")
+            assert st == 0
+            assert 0 < info.factor_slots_used <= info.factor_slots_launched
+        with xb.Plan(m, n, r, r, 50.0, 50.0, "fp64", max_batch=B, factor_method="checked") as q:
+            q.assemble(G2)
+            q.factor()
+            q.solve_batch(V)
+            ref2 = q.currents().cpu().numpy()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[2], ref2)
 
 
 def test_graph_capture_of_assemble_factor_solve_replays_eager_bits():
