@@ -365,6 +365,21 @@ xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_
 /* Floats of workspace xbar_sg_conv_backward_weight needs (-1 for bad C, O). */
 int64_t xbar_sg_workspace_floats(int32_t C, int32_t O);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc): xbar_sg_conv_backward_weight without the
+ * workspace argument.  The partial sums go to a device array inside the library,
+ * sized for the largest channel counts, xbar_sg_workspace_floats(32, 32) floats
+ * (about 19 MB), which each GPU the library runs on holds from the first call on
+ * that GPU until the process ends; the call allocates nothing (no hipMalloc, no
+ * library allocation).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (concurrent streams, other host threads) race and must be
+ * serialised by the caller.  Same result, bit for bit, as
+ * xbar_sg_conv_backward_weight on the same inputs.  XBAR_ERR_ARG as that call
+ * (sizes, NULL pointers, gw overlapping gb); XBAR_ERR_DEVICE when the array's
+ * address cannot be obtained on the current device or a launch fails. */
+xbar_status xbar_sg_conv_backward_weight_noalloc(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O,
+                                                 const float* x, const float* gy, const float* ymask, float* gw,
+                                                 float* gb, void* stream);
 
 /* Column readouts and loss of the last map Y [B][2][m][n] (float32):
  * yhat_j = mean_i Y[b][0][i][j] (the correction), s_j = mean_i Y[b][1][i][j] (the

@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         L.xbar_sg_conv_forward.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
         L.xbar_sg_conv_backward_data.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.xbar_sg_conv_backward_weight.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.xbar_sg_conv_backward_weight_noalloc.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.xbar_sg_workspace_floats.argtypes = [i32, i32]
         L.xbar_sg_workspace_floats.restype = i64
         L.xbar_sg_readout_loss.argtypes = [i32, i32, i32, vp, vp, f64, vp, vp, vp]
@@ -111,7 +112,8 @@ def lib() -> ctypes.CDLL:
                   "xbar_get_timing", "xbar_set_factor_method", "xbar_set_diagnostics",
                   "xbar_debug_shift_pivots", "xbar_transfer",
                   "xbar_transfer_apply", "xbar_tiles_currents", "xbar_sg_features", "xbar_sg_conv_forward",
-                  "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_readout_loss",
+                  "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight",
+                  "xbar_sg_conv_backward_weight_noalloc", "xbar_sg_readout_loss",
                   "xbar_sg_adam", "xbar_sg_predict"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -235,6 +237,12 @@ def xbar_sg_conv_backward_weight(B, H, W, C, O, x, gy, ymask, gw, gb, work, stre
     _check("xbar_sg_conv_backward_weight",
            lib().xbar_sg_conv_backward_weight(B, H, W, C, O, _ptr(x), _ptr(gy), _ptr(ymask), _ptr(gw), _ptr(gb),
                                               _ptr(work), int(work.numel()), _s(stream)))
+
+
+def xbar_sg_conv_backward_weight_noalloc(B, H, W, C, O, x, gy, ymask, gw, gb, stream=None) -> None:
+    _check("xbar_sg_conv_backward_weight_noalloc",
+           lib().xbar_sg_conv_backward_weight_noalloc(B, H, W, C, O, _ptr(x), _ptr(gy), _ptr(ymask), _ptr(gw),
+                                                      _ptr(gb), _s(stream)))
 
 
 def xbar_sg_workspace_floats(C, O) -> int:

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "xbar.h"
 
@@ -459,6 +460,63 @@ dim3 tall_grid(int B, int H, int W) { return dim3(((H + 31) / 32) * ((W + 15) / 
 
 }  // namespace
 
+namespace {
+
+// The weight gradient's two launches: per-workgroup partial sums into `work`, then
+// their fixed-order reduction into gw and gb.
+xbar_status bwd_weight_launch(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
+                              const float* gy, const float* ymask, float* gw, float* gb, float* work, int nparts,
+                              hipStream_t s)
+{
+    const int ne = O * C * 9;
+    hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(kWgT), 0, s, B, H, W, C, O, x, gy, ymask, work);
+    if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
+    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 15) / 16), dim3(256), 0, s, nparts, ne, O, work, gw,
+                       gb);
+    return launched();
+}
+
+int bwd_weight_parts(int32_t B, int32_t H, int32_t W)
+{
+    const int64_t tiles = (int64_t)B * ((H + 15) / 16) * ((W + 15) / 16);
+    return (int)(tiles < kParts ? tiles : kParts);
+}
+
+// Workspace of the allocation-free weight gradient: the partial sums for the largest
+// channel counts, a file-scope device array.  Each GPU the library runs on holds its
+// own copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in), looked up once per device.
+constexpr int64_t kSgScratchFloats = (int64_t)kParts * (XBAR_SG_MAX_CHANNELS * XBAR_SG_MAX_CHANNELS * 9 +
+                                                         XBAR_SG_MAX_CHANNELS);
+}  // namespace
+
+static __device__ __align__(256) float scratch[kSgScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float* scratch_at[kMaxDevices] = {};
+
+float* scratch_ptr()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_at[dev] == nullptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_at[dev] = static_cast<float*>(p);
+    }
+    return scratch_at[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 int64_t xbar_sg_workspace_floats(int32_t C, int32_t O)
@@ -509,24 +567,35 @@ xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t 
     return launched();
 }
 
+
 xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
                                          const float* gy, const float* ymask, float* gw, float* gb, float* work,
                                          int64_t work_floats, void* hip_stream)
 {
     if (!shape_ok(B, H, W) || !ch_ok(C, O) || !x || !gy || !gw || !gb || !work) return XBAR_ERR_ARG;
     const int ne = O * C * 9;
-    const int64_t tiles = (int64_t)B * ((H + 15) / 16) * ((W + 15) / 16);
-    const int nparts = (int)(tiles < kParts ? tiles : kParts);
+    const int nparts = bwd_weight_parts(B, H, W);
     if (work_floats < (int64_t)nparts * (ne + O)) return XBAR_ERR_ARG;
     const int64_t nw = (int64_t)nparts * (ne + O) * 4;
     if (overlap(work, nw, gw, ne * 4) || overlap(work, nw, gb, O * 4) || overlap(gw, ne * 4, gb, O * 4))
         return XBAR_ERR_ARG;
-    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    hipLaunchKernelGGL(sg_conv_bwd_weight_kernel, dim3(nparts), dim3(kWgT), 0, s, B, H, W, C, O, x, gy, ymask, work);
-    if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
-    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 15) / 16), dim3(256), 0, s, nparts, ne, O, work, gw,
-                       gb);
-    return launched();
+    return bwd_weight_launch(B, H, W, C, O, x, gy, ymask, gw, gb, work, nparts,
+                             reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+xbar_status xbar_sg_conv_backward_weight_noalloc(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O,
+                                                 const float* x, const float* gy, const float* ymask, float* gw,
+                                                 float* gb, void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !x || !gy || !gw || !gb) return XBAR_ERR_ARG;
+    const int ne = O * C * 9;
+    const int nparts = bwd_weight_parts(B, H, W);
+    if ((int64_t)nparts * (ne + O) > kSgScratchFloats) return XBAR_ERR_ARG;
+    if (overlap(gw, ne * 4, gb, O * 4)) return XBAR_ERR_ARG;
+    float* ws = scratch_ptr();
+    if (ws == nullptr) return XBAR_ERR_DEVICE;
+    return bwd_weight_launch(B, H, W, C, O, x, gy, ymask, gw, gb, ws, nparts,
+                             reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 xbar_status xbar_sg_readout_loss(int32_t B, int32_t m, int32_t n, const float* Y, const double* delta, double lam,

@@ -11,7 +11,8 @@ from paper_2410_19993_amd import _lib
 EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_debug_shift_pivots", "xbar_destroy",
             "xbar_factor", "xbar_get_info", "xbar_get_timing", "xbar_set_diagnostics", "xbar_set_factor_method",
             "xbar_set_timing", "xbar_sg_adam",
-            "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_conv_forward",
+            "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_conv_backward_weight_noalloc",
+            "xbar_sg_conv_forward",
             "xbar_sg_features", "xbar_sg_predict", "xbar_sg_readout_loss", "xbar_sg_workspace_floats",
             "xbar_solve_batch", "xbar_status_string", "xbar_tiles_currents", "xbar_transfer",
             "xbar_transfer_apply"]
@@ -175,6 +176,12 @@ def test_surrogate_calls_reject_bad_arguments():
                                           1, None) == E
     assert L.xbar_sg_conv_backward_weight(1, 4, 4, 2, 2, a, b, None, c, ctypes.c_void_p(base + 2 * 65536 + 8),
                                           ctypes.c_void_p(base + 4 * 65536 * 8), ws, None) == E
+    # allocation-free weight gradient: the same host checks, and gw over gb
+    assert L.xbar_sg_conv_backward_weight_noalloc(1, 4, 4, 33, 2, a, b, None, c, d, None) == E
+    assert L.xbar_sg_conv_backward_weight_noalloc(0, 4, 4, 2, 2, a, b, None, c, d, None) == E
+    assert L.xbar_sg_conv_backward_weight_noalloc(1, 4, 4, 2, 2, None, b, None, c, d, None) == E
+    assert L.xbar_sg_conv_backward_weight_noalloc(1, 4, 4, 2, 2, a, b, None, c, ctypes.c_void_p(base + 2 * 65536 + 8),
+                                                  None) == E
     # Adam: step 0, lr <= 0, beta outside [0, 1)
     assert L.xbar_sg_adam(4, a, b, c, d, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E
     assert L.xbar_sg_adam(4, a, b, c, d, 0.0, 0.9, 0.999, 1e-8, 1, None) == E
