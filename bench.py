@@ -7,8 +7,7 @@ forward/back substitution with every node voltage written to HBM, and the
 output currents.  Inputs are resident in HBM before timing starts.
 
     python bench.py [--steps K] [--warmup W] [--r 2.5] [--no-fp32-ir] [--no-cpu-baseline]
-                    [--no-shortcuts] [--no-tiles] [--no-tiles-large] [--tile-lanes 4]
-                    [--no-r-sweep]
+                    [--no-shortcuts] [--no-tiles] [--no-r-sweep]
     python bench.py --copy-probe GIB    # a plain device copy of GIB GiB, three times
                                         # (calibrates the HBM traffic counters)
 
@@ -17,8 +16,7 @@ float32 + float64-refinement leg and exact shortcuts that skip work the metric
 does: the same path without node voltages, the sweeps alone, and the output
 currents through the transfer matrix (one product per batch once T is built).
 It also reports the heterogeneous tiles workload (2048 crossbars of 32-256 rows
-and columns, 256 input vectors each): the crossbars with n <= 64 through the
-batched tile kernel, the others through concurrent plans.
+and columns, 256 input vectors each) through one batched library call.
 
 The CPU baseline has two parts: the oracle (one core) on a bounded slice,
 scaled to the workload, and LAPACK's banded Cholesky (dpbtrf / dpbtrs through
@@ -229,11 +227,7 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-shortcuts", action="store_true",
                     help="skip the currents-only and transfer-matrix legs")
-    ap.add_argument("--no-tiles", action="store_true", help="skip the batched small-tile leg")
-    ap.add_argument("--no-tiles-large", action="store_true",
-                    help="skip the tiles workload's n_t >= 128 half (plan lanes, a few seconds)")
-    ap.add_argument("--tile-lanes", type=int, default=4,
-                    help="concurrent plans (stream + host thread each) for the n_t >= 128 tiles")
+    ap.add_argument("--no-tiles", action="store_true", help="skip the heterogeneous tiles leg")
     ap.add_argument("--no-r-sweep", action="store_true",
                     help="skip the float64 and float32+refinement steps at the other segment resistances")
     ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
@@ -358,109 +352,63 @@ def main():
                 "max_rel_err_vs_oracle": err}
 
     def run_tiles(steps):
-        """The heterogeneous tiles workload's crossbars with n_t <= 64 (its other half needs
-        blocks larger than one workgroup's LDS), one xbar_tiles_currents launch per
-        (m_t, n_t) class, longest classes first, over four streams; currents of all 256
-        input vectors of every tile."""
-        tl = workloads.c4(max_n=64)
-        classes = {}
+        """The heterogeneous tiles workload: 2048 crossbars of 32..256 rows and columns,
+        256 input vectors each, currents only, in one library call (TileBatch) with the
+        tuned configuration of every class; eager, and captured once into a HIP graph
+        and replayed."""
+        tl = workloads.c4()
+        by = {}
         for t in tl:
-            classes.setdefault(t.G.shape, []).append(t)
-        dev = []
-        flops = 0.0
-        for (tm_, tn_), ts in sorted(classes.items()):
-            Gs = torch.from_numpy(np.stack([t.G for t in ts])).cuda()
-            Vs = torch.from_numpy(np.stack([t.V for t in ts])).cuda()
-            Is = torch.empty((len(ts), 256, tn_), dtype=torch.float64, device="cuda")
-            dev.append((Gs, Vs, Is))
-            flops += len(ts) * (tm_ * tn_ ** 3 + 2.0 * tm_ * tn_ ** 2 * 256)
+            by.setdefault((t.G.shape[0], t.G.shape[1], t.V.shape[0]), []).append(t)
+        keys = sorted(by)
+        classes = [(mm, nn, len(by[(mm, nn, bb)]), bb) for (mm, nn, bb) in keys]
+        Gs = [torch.from_numpy(np.stack([t.G for t in by[k]])).cuda() for k in keys]
+        Vs = [torch.from_numpy(np.stack([t.V for t in by[k]])).cuda() for k in keys]
+        Is = [torch.empty((c, bb, nn), dtype=torch.float64, device="cuda") for (mm, nn, c, bb) in classes]
         g4 = workloads.C4_GEOM
-        # classes side by side: each launch covers fewer tiles than there are CUs, so the
-        # launches go round-robin over four streams (default priority) joined to the main one
-        side = [torch.cuda.Stream() for _ in range(4)]
-
-        def one_pass():
-            ev = torch.cuda.Event()
-            ev.record(stream)
-            order = sorted(range(len(dev)), key=lambda k: -dev[k][0].shape[1] * dev[k][0].shape[2] ** 2)
-            for j, k in enumerate(order):
-                Gs, Vs, Is = dev[k]
-                st = side[j % 4]
-                st.wait_event(ev)
-                xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is, stream=st)
-            for st in side:
-                done = torch.cuda.Event()
-                done.record(st)
-                stream.wait_event(done)
-
-        one_pass()
-        torch.cuda.synchronize()
-        assert all(bool(torch.isfinite(Is).all()) for _, _, Is in dev), "tile currents not finite"
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            one_pass()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        # the same pass captured once into a HIP graph and replayed
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            cap = torch.cuda.current_stream()
-            ev0 = torch.cuda.Event()
-            ev0.record(cap)
-            for j, (Gs, Vs, Is) in enumerate(sorted(dev, key=lambda d: -d[0].shape[1] * d[0].shape[2] ** 2)):
-                st = side[j % 4]
-                st.wait_event(ev0)
-                xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is, stream=st)
-            for st in side:
-                done = torch.cuda.Event()
-                done.record(st)
-                cap.wait_event(done)
-        graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        ms_graph = (time.perf_counter() - t0) * 1e3 / steps
-        # each class alone, HIP events on the launch stream
-        per_class = {}
-        for Gs, Vs, Is in dev:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            xb.tiles_currents(Gs, Vs, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], out=Is, stream=stream)
-            e1.record(stream)
+        # the method's work, rows ordered as the crossbar's (m n^3 factor, 2 m n^2 per vector)
+        flops = sum(c * (mm * nn ** 3 + 2.0 * mm * nn * nn * bb) for (mm, nn, c, bb) in classes)
+        with xb.TileBatch(classes, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], stream=stream) as tb:
+            tb.run(Gs, Vs, Is)
             torch.cuda.synchronize()
-            per_class[f"{Gs.shape[1]}x{Gs.shape[2]}"] = {"tiles": int(Gs.shape[0]), "ms": e0.elapsed_time(e1)}
-        vecs = 256 * len(tl)
-        log(f"tiles: {len(tl)} crossbars in {len(dev)} classes, {ms:.2f} ms per pass")
-        return {"value": vecs / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms,
-                "ms_per_pass_graph_replay": ms_graph, "per_class": per_class, "tiles": len(tl),
-                "classes": len(dev), "tiles_per_s": len(tl) / (ms * 1e-3),
-                "workload": "c4 tiles with n_t <= 64 (seed 1004), 256 vectors each, currents only",
-                "algorithmic_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
-                "frac_of_fp64_peak": flops / (ms * 1e-3) / PEAK_FP64_MFMA}
-
-    def run_tiles_large(lanes):
-        """The tiles workload's crossbars with n_t >= 128 through plans (float64, currents
-        only, all 256 vectors): `lanes` plans at a time, each on a stream and host thread
-        of its own (PlanLanes), one plan per shape and lane."""
-        tl = [t for t in workloads.c4() if t.G.shape[1] >= 128]
-        g4 = workloads.C4_GEOM
-        Gd = [torch.from_numpy(t.G).cuda() for t in tl]
-        Vd = [torch.from_numpy(np.ascontiguousarray(t.V)).cuda() for t in tl]
-        Id = [torch.empty((256, t.G.shape[1]), dtype=torch.float64, device="cuda") for t in tl]
-        with xb.PlanLanes(g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], lanes=lanes, max_batch=256) as pl:
-            pl.currents(Gd, Vd, Id)                     # creates and warms every plan
-            torch.cuda.synchronize()
+            assert all(bool(torch.isfinite(I).all()) for I in Is), "tile currents not finite"
             t0 = time.perf_counter()
-            pl.currents(Gd, Vd, Id)
+            for _ in range(steps):
+                tb.run(Gs, Vs, Is)
             torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3
-            pl.check()
-        log(f"tiles (n >= 128): {len(tl)} crossbars through {lanes} plan lanes in {ms:.0f} ms")
-        return {"value": 256 * len(tl) / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms, "tiles": len(tl),
-                "lanes": lanes,
-                "workload": "c4 tiles with n_t >= 128 (seed 1004), 256 vectors each, currents only, plan path"}
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with xb.TileBatch(classes, g4["r_wl"], g4["r_bl"], g4["r_src"], g4["r_sense"], stream=side) as tg:
+                with torch.cuda.stream(side):
+                    tg.run(Gs, Vs, Is)
+                side.synchronize()
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph, stream=side):
+                    tg.run(Gs, Vs, Is)
+                graph.replay()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    graph.replay()
+                torch.cuda.synchronize()
+                ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+            configs = {f"{mm}x{nn}": {"tiles": c, "method": cf.method, "block": cf.block, "split": cf.split,
+                                      "transpose": cf.transpose, "source": src}
+                       for (mm, nn, c, bb), cf, src in zip(classes, tb.configs, tb.sources)}
+            streams = tb.streams
+        vecs = 256 * len(tl)
+        log(f"tiles: {len(tl)} crossbars in {len(classes)} classes, {ms:.2f} ms per pass "
+            f"({ms_graph:.2f} ms as a graph replay)")
+        return {"value": vecs / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms,
+                "ms_per_pass_graph_replay": ms_graph, "tiles": len(tl), "classes": len(classes),
+                "tiles_per_s": len(tl) / (ms * 1e-3), "streams": streams, "per_class": configs,
+                "workload": "c4 tiles (seed 1004): 2048 crossbars of {32,64,128,256}^2, 256 vectors each, "
+                            "currents only, one TileBatch call",
+                "algorithmic_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
+                "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
+                             "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / PEAK_FP64_MFMA,
+                             "note": "work counted as the row-ordered method's m n^3 + 2 m n^2 B per crossbar"}}
 
     ms64, tm, info64, err64 = run("fp64", args.steps, args.warmup)
     # kernels: algorithmic work per launch
@@ -515,8 +463,6 @@ def main():
         result["transfer"] = run_transfer(args.steps)
     if not args.no_tiles:
         result["tiles"] = run_tiles(args.steps)
-    if not args.no_tiles_large:
-        result["tiles_large"] = run_tiles_large(args.tile_lanes)
     if not args.no_fp32_ir:
         # The metric's accuracy target for this leg is 1e-9 relative error on the currents:
         # refinement stops once its error estimate is below 1e-10 (the error actually

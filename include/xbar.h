@@ -228,6 +228,76 @@ xbar_status xbar_tiles_currents(const xbar_geometry* geom, int32_t T, int32_t B,
                                 double* I, void* hip_stream);
 
 /*
+ * ---- Heterogeneous batches of crossbars ------------------------------------
+ *
+ * Many independent crossbars of mixed shapes (the partitioned crossbars of
+ * Sec. III.C, each solved by the method of Sec. II.A-II.C), grouped by the caller
+ * into classes of one shape: the output currents of every crossbar for its own
+ * input vectors, in one call that queues every class's launches on a few streams
+ * forked from, and joined back to, the caller's stream.  The call allocates
+ * nothing and reads nothing back, so it can be captured into a HIP graph.
+ *
+ * How a class is solved (`method`, chosen per class, e.g. by a tuner):
+ *   XBAR_TILE_ONE_WG    one workgroup per crossbar (n <= XBAR_TILE_MAX_N), the whole
+ *                       solve in one launch, blocks padded to `block` (16, 32 or 64,
+ *                       >= n; 0 picks the smallest); `split` (1..4) workgroups per
+ *                       crossbar, each forward-substituting a share of its vectors
+ *                       after redoing the factorization;
+ *   XBAR_TILE_PIPELINE  the plan path's kernels batched over the class (n <=
+ *                       XBAR_MAX_N): condensation, the twisted block Gauss-Jordan
+ *                       factorization and the float64 currents-only sweep, each
+ *                       covering every crossbar of the class per launch; `block`
+ *                       and `split` must be 0 and 1.
+ * `transpose` = 1 solves the class through its reciprocal problem instead, which
+ * orders the row blocks by the smaller side when m < n: the network is reciprocal,
+ * so the current into the sense resistor of bit line j per volt on word line i,
+ * T[i][j], is the current into the source resistor of word line i per volt at the
+ * sense terminal of bit line j (Sec. II.A's network with sources and sinks
+ * exchanged).  That problem is the crossbar turned by a half turn and transposed
+ * (n rows, m columns, word-line and bit-line segment resistances swapped, r_sense as
+ * source and r_src as sense resistance) driven by the n unit inputs; `method`,
+ * `block` and `split` apply to it (so they are checked against its n' = m columns
+ * and n <= XBAR_TILE_MAX_B unit inputs), and I = V T follows by one product per
+ * crossbar.
+ * A crossbar with a conductance that is not finite and positive, or a pivot that
+ * is not positive, gets NaN currents; the other crossbars are unaffected.
+ */
+#define XBAR_TILE_ONE_WG 0
+#define XBAR_TILE_PIPELINE 1
+typedef struct {
+    int32_t m, n;       /* shape of the class's crossbars (rows, columns)             */
+    int32_t count;      /* crossbars in the class, >= 1                                */
+    int32_t B;          /* input vectors per crossbar, 1 .. XBAR_TILE_MAX_B            */
+    int32_t method;     /* XBAR_TILE_ONE_WG or XBAR_TILE_PIPELINE                      */
+    int32_t block;      /* XBAR_TILE_ONE_WG: padded block size, 0 = smallest           */
+    int32_t split;      /* XBAR_TILE_ONE_WG: workgroups per crossbar (1..4)            */
+    int32_t transpose;  /* 1: through the reciprocal problem (see above), else 0      */
+} xbar_tile_class;
+
+typedef struct xbar_tiles_s* xbar_tiles;    /* opaque, owned by the library */
+
+/* Validate the classes and resistances (as xbar_create's) on the host, allocate the
+ * pipeline classes' device workspace and `streams` (1..8) streams of default priority
+ * with their events.  hip_stream: the caller's stream (NULL = null stream).  Returns
+ * XBAR_ERR_ARG, XBAR_ERR_DEVICE, XBAR_ERR_ALLOC or XBAR_OK. */
+xbar_status xbar_tiles_create(const xbar_tile_class* classes, int32_t nclasses, double r_wl, double r_bl,
+                              double r_src, double r_sense, int32_t streams, void* hip_stream, xbar_tiles* out);
+
+/* Output currents of every class: host arrays of nclasses device pointers, class k's
+ * G[k] [count][m][n] siemens, V[k] [count][B][m] volts, I[k] [count][B][n] amperes
+ * (as xbar_currents; must not overlap G[k] or V[k]).  Asynchronous on the caller's
+ * stream; the pointers may change from call to call.  XBAR_ERR_ARG on a NULL
+ * pointer, XBAR_ERR_DEVICE on a launch error. */
+xbar_status xbar_tiles_run(xbar_tiles tiles, const double* const* G, const double* const* V, double* const* I);
+
+/* Device bytes the batch holds (-1 for NULL). */
+int64_t xbar_tiles_workspace_bytes(xbar_tiles tiles);
+
+/* Synchronise the caller's stream and the batch's streams, then free everything.
+ * NULL is a no-op. */
+xbar_status xbar_tiles_destroy(xbar_tiles tiles);
+
+/*
  * Synchronise the plan's stream and report its state.  Returns the sticky
  * device error (XBAR_ERR_INPUT, XBAR_ERR_NOT_SPD, XBAR_ERR_NO_CONVERGENCE)
  * if one was raised, XBAR_ERR_DEVICE on a HIP error, else XBAR_OK.

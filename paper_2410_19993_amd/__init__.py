@@ -9,7 +9,8 @@ from . import _lib
 from ._lib import (FACTOR_METHODS, PRECISIONS, XBAR_BF16_IR, XBAR_FP32_IR, XBAR_FP64,  # noqa: F401
                    Geometry, XbarError, status_string)
 
-__all__ = ["Plan", "PlanLanes", "solve", "tiles_currents", "Geometry", "XbarError", "PRECISIONS", "status_string"]
+__all__ = ["Plan", "PlanLanes", "TileBatch", "TileConfig", "solve", "tiles_currents", "Geometry", "XbarError",
+           "PRECISIONS", "status_string"]
 
 
 def _torch():
@@ -166,3 +167,4 @@ def solve(G, V, r_wl, r_bl, r_src=50.0, r_sense=50.0, precision="fp64", node_vol
 
 
 from .lanes import PlanLanes  # noqa: E402  (needs Plan above)
+from .tiles import TileBatch, TileConfig  # noqa: E402

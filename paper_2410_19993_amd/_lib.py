@@ -52,6 +52,16 @@ class Info(ctypes.Structure):
                 ("factor_slots_launched", ctypes.c_int32)]
 
 
+class TileClass(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("count", ctypes.c_int32), ("B", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("block", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("transpose", ctypes.c_int32)]
+
+
+XBAR_TILE_ONE_WG = 0
+XBAR_TILE_PIPELINE = 1
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("condense_ms", ctypes.c_double), ("condense_launches", ctypes.c_int64),
                 ("factor_ms", ctypes.c_double), ("factor_launches", ctypes.c_int64),
@@ -88,6 +98,12 @@ def lib() -> ctypes.CDLL:
         L.xbar_transfer_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
         L.xbar_tiles_currents.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         L.xbar_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.xbar_tiles_create.argtypes = [ctypes.POINTER(TileClass), ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.xbar_tiles_run.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.xbar_tiles_workspace_bytes.argtypes = [vp]
+        L.xbar_tiles_workspace_bytes.restype = ctypes.c_int64
+        L.xbar_tiles_destroy.argtypes = [vp]
         L.xbar_destroy.argtypes = [vp]
         L.xbar_set_timing.argtypes = [vp, ctypes.c_int32]
         L.xbar_set_factor_method.argtypes = [vp, ctypes.c_int]
@@ -111,7 +127,8 @@ def lib() -> ctypes.CDLL:
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
                   "xbar_get_timing", "xbar_set_factor_method", "xbar_set_diagnostics",
                   "xbar_debug_shift_pivots", "xbar_transfer",
-                  "xbar_transfer_apply", "xbar_tiles_currents", "xbar_sg_features", "xbar_sg_conv_forward",
+                  "xbar_transfer_apply", "xbar_tiles_currents", "xbar_tiles_create", "xbar_tiles_run",
+                  "xbar_tiles_destroy", "xbar_sg_features", "xbar_sg_conv_forward",
                   "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight",
                   "xbar_sg_conv_backward_weight_noalloc", "xbar_sg_readout_loss",
                   "xbar_sg_adam", "xbar_sg_predict"):
@@ -178,6 +195,31 @@ def xbar_transfer_apply(plan, T, V, B: int, I) -> None:
 def xbar_tiles_currents(geom: Geometry, T: int, B: int, G, V, I, stream: int | None = None) -> None:
     _check("xbar_tiles_currents", lib().xbar_tiles_currents(ctypes.byref(geom), int(T), int(B), _ptr(G), _ptr(V),
                                                             _ptr(I), ctypes.c_void_p(stream or 0)))
+
+
+def xbar_tiles_create(classes, r_wl, r_bl, r_src, r_sense, streams: int, stream: int | None = None):
+    arr = (TileClass * len(classes))(*classes)
+    t = ctypes.c_void_p()
+    _check("xbar_tiles_create", lib().xbar_tiles_create(arr, len(classes), float(r_wl), float(r_bl), float(r_src),
+                                                        float(r_sense), int(streams), ctypes.c_void_p(stream or 0),
+                                                        ctypes.byref(t)))
+    return t
+
+
+def xbar_tiles_run(t, Gs, Vs, Is) -> None:
+    k = len(Gs)
+    G = (ctypes.c_void_p * k)(*[g.data_ptr() for g in Gs])
+    V = (ctypes.c_void_p * k)(*[v.data_ptr() for v in Vs])
+    I = (ctypes.c_void_p * k)(*[i.data_ptr() for i in Is])
+    _check("xbar_tiles_run", lib().xbar_tiles_run(t, G, V, I))
+
+
+def xbar_tiles_workspace_bytes(t) -> int:
+    return int(lib().xbar_tiles_workspace_bytes(t))
+
+
+def xbar_tiles_destroy(t) -> None:
+    _check("xbar_tiles_destroy", lib().xbar_tiles_destroy(t))
 
 
 def xbar_get_info(plan) -> tuple[int, Info]:

@@ -202,6 +202,8 @@ struct NSArgs {
     int max_iter;
 };
 
+// Crossbar blockIdx.y of a batch of one shape reads G + y m n and writes E, c, fr,
+// ip, q and Gc at y times one crossbar's size (gridDim.y = 1 for a plan).
 struct CondenseArgs {
     const double* G;     // [m][n] user conductances
     int m, n, n_p;
@@ -213,6 +215,7 @@ struct CondenseArgs {
     double* q;           // [m][n]    bit-line self conductance q_ij
     double* Gc;          // [m][n]    copy of G
     int* flags;
+    int* tile_bad = nullptr;   // batches: per-crossbar flag, set for a bad conductance
 };
 
 // One inversion in flight: the pivot block of crossbar row `row`.
@@ -231,6 +234,11 @@ struct GJArgs {
     GJJob job[2];        // top and bottom chains (one job for the twist row)
     int* flags;
     unsigned long long* diag;   // [kNumDiag] plan diagnostics
+    // batched crossbars of one shape (blockIdx.y): crossbar t uses H + t * h_stride and the
+    // jobs' S and P buffers + t * s_stride, t * p_stride (elements); batch = 1 for a plan
+    int batch = 1;
+    int64_t h_stride = 0, s_stride = 0, p_stride = 0;
+    int* tile_bad = nullptr;   // batches: per-crossbar flag, set for a pivot that is not positive
 };
 
 struct SweepArgs {
@@ -259,6 +267,14 @@ struct SweepArgs {
     int* slab_done;      // [nslab]
     int* slab_final;     // [nslab] which U buffer holds the final solution
     int* flags;
+    // batched crossbars of one shape (float64, currents only): `batch` crossbars of
+    // `slabs_per` slabs each, crossbar t's H, c, V, Z and Iout at t times the size of one
+    // crossbar's; workgroups are mapped so that a crossbar's slabs share an XCD (and its
+    // L2).  batch = 1 for a plan.  `slab` is set per workgroup inside the kernel.
+    int batch = 1, slabs_per = 0;
+    int slab = 0;
+    const int* tile_bad = nullptr;   // batches: crossbars flagged bad get NaN currents
+    int unit = 0;                    // 1: input vector b is the unit vector e_b (V is not read)
 };
 
 struct ResidualArgs {
@@ -301,7 +317,7 @@ struct BackErrArgs {
 }  // namespace xbk
 
 // Host-side launchers (defined in the .hip files, called by the C ABI layer).
-hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s);
+hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s, int batch = 1);
 hipError_t xbk_launch_factor(const xbk::GJArgs& a, bool fp32, hipStream_t s);
 hipError_t xbk_launch_ns_init(const xbk::NSArgs& a, hipStream_t s);
 hipError_t xbk_launch_ns_slots(const xbk::NSArgs& a, bool fp32, int chain, int first, int count, hipStream_t s);

@@ -50,6 +50,17 @@ __global__ __launch_bounds__(256) void condense_kernel(CondenseArgs a)
 {
     extern __shared__ double lds[];
     const int n = a.n, n_p = a.n_p, i = blockIdx.x;
+    if (blockIdx.y > 0) {
+        // crossbar blockIdx.y of a batch of one shape
+        const int64_t t = blockIdx.y, mn = (int64_t)a.m * n;
+        a.G += t * mn;
+        a.E = reinterpret_cast<T*>(a.E) + t * (int64_t)a.m * n_p * n_p;
+        a.c += t * (int64_t)a.m * n_p;
+        a.fr += t * mn;
+        a.ip += t * mn;
+        a.q += t * mn;
+        a.Gc += t * mn;
+    }
     double* Gs = lds;            // G_ij
     double* fp = Gs + n;         // forward pivots p_j of T_i
     double* fx = fp + n;         // forward excess d_j = p_j - (right link)
@@ -63,7 +74,10 @@ __global__ __launch_bounds__(256) void condense_kernel(CondenseArgs a)
     const double* Grow = a.G + (int64_t)i * n;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const double g = Grow[j];
-        if (!(g > 0.0) || !isfinite(g)) atomicOr(a.flags + kErrInput, 1);
+        if (!(g > 0.0) || !isfinite(g)) {
+            atomicOr(a.flags + kErrInput, 1);
+            if (a.tile_bad) atomicOr(a.tile_bad + blockIdx.y, 1);
+        }
         Gs[j] = g;
         a.Gc[(int64_t)i * n + j] = g;
     }
@@ -172,12 +186,12 @@ __global__ __launch_bounds__(256) void condense_kernel(CondenseArgs a)
 
 }  // namespace xbk
 
-hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s)
+hipError_t xbk_launch_condense(const xbk::CondenseArgs& a, bool fp32, hipStream_t s, int batch)
 {
     const size_t lds = 8 * (size_t)a.n * sizeof(double);
     if (fp32)
-        hipLaunchKernelGGL(xbk::condense_kernel<float>, dim3(a.m), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(xbk::condense_kernel<float>, dim3(a.m, batch), dim3(256), lds, s, a);
     else
-        hipLaunchKernelGGL(xbk::condense_kernel<double>, dim3(a.m), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(xbk::condense_kernel<double>, dim3(a.m, batch), dim3(256), lds, s, a);
     return hipGetLastError();
 }

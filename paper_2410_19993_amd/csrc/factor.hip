@@ -116,21 +116,21 @@ __device__ inline void store_acc(const typename Frag<T>::acc_t (&acc)[4], T* M, 
 }
 
 // Gauss-Jordan inverse of the 64x64 SPD tile held in acc (MFMA output layout),
-// written row-major CPR to Pout.  Thread t keeps row t/4, columns 16(t%4)..+15
-// in registers; the pivot row (with the pivot's reciprocal) and the pivot
-// column go through double-buffered LDS, one barrier per pivot, and every
-// thread updates its 16 entries without branches.  A pivot that is not
-// positive and finite raises kErrPivot.
-// `valid` pivots of the tile lie inside the n x n block (the rest are the
-// identity padding); the smallest of them is folded into the plan's diagnostics.
+// written row-major CPR to Pout, four pivots per step.  Thread t keeps row t/4,
+// columns 16(t%4)..+15 in registers.  For the pivot block D of rows and columns
+// p..p+3, with R the pivot rows and C the pivot columns,
+//     D <- D^-1,  R <- D^-1 R,  C <- -C D^-1,  A <- A - C D^-1 R,
+// the pivot rows and columns go through double-buffered LDS (one barrier per step),
+// and every thread inverts the 4x4 pivot block itself by scalar Gauss-Jordan (whose
+// pivots are the elimination's scalar pivots).  A pivot that is not positive and
+// finite raises kErrPivot.  `valid` pivots of the tile lie inside the n x n block
+// (the rest are the identity padding); the smallest of them is folded into the
+// plan's diagnostics.
 template <typename T>
 __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* Pout, int* flags,
-                            unsigned long long* diag, int valid, int w, int l)
+                            unsigned long long* diag, int valid, int w, int l, int* tbad)
 {
-    using v4 = typename std::conditional<sizeof(T) == 8, d4_t, f4_t>::type;
     T* sP = lds;                         // [64][kLd] staging of the tile
-    T* rowb = lds + kTile * kLd;         // [2][64]
-    T* colb = rowb + 2 * kTile;          // [2][64]
     __syncthreads();
 #pragma unroll
     for (int C = 0; C < 4; ++C)
@@ -141,45 +141,98 @@ __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* 
     T a[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) a[c] = sP[r * kLd + c0 + c];
+    __syncthreads();                     // the staging area becomes the pivot buffers
+    T* rowb = lds;                       // [2][4][64] pivot rows
+    T* colb = lds + 2 * 4 * kTile;       // [2][4][64] pivot columns
     bool bad = false;
     double dmin = __builtin_inf();
-    for (int p = 0; p < kTile; ++p) {
-        T* rb = rowb + (p & 1) * kTile;
-        T* cb = colb + (p & 1) * kTile;
-        if (r == p) {
+    for (int p = 0; p < kTile; p += 4) {
+        const int buf = (p >> 2) & 1;
+        T* rb = rowb + buf * 4 * kTile;
+        T* cb = colb + buf * 4 * kTile;
+        const int ir = r - p;                           // pivot row index, if 0..3
+        const bool prow = ir >= 0 && ir < 4;
+        const int cp = p >> 4, op = p & 15;             // chunk and offset of the pivot columns
+        if (prow) {
 #pragma unroll
-            for (int c = 0; c < 16; ++c) rb[c0 + c] = a[c];
+            for (int c = 0; c < 16; ++c) rb[ir * kTile + c0 + c] = a[c];
         }
-        if ((p >> 4) == cbk) {
-            T v = a[0];
+        if (cbk == cp) {
 #pragma unroll
-            for (int c = 1; c < 16; ++c) v = ((p & 15) == c) ? a[c] : v;
-            cb[r] = v;
+            for (int j = 0; j < 4; ++j) {
+                T v = a[0];
+#pragma unroll
+                for (int c = 1; c < 16; ++c) v = (c == op + j) ? a[c] : v;
+                cb[j * kTile + r] = v;
+            }
         }
         __syncthreads();
-        T pr[16];
+        // D^-1 by scalar Gauss-Jordan on the 4x4 block (its pivots are the scalar pivots)
+        T D[4][4];
 #pragma unroll
-        for (int c = 0; c < 16; c += 4) {
-            const v4 x = *reinterpret_cast<const v4*>(rb + c0 + c);
-            pr[c] = x[0]; pr[c + 1] = x[1]; pr[c + 2] = x[2]; pr[c + 3] = x[3];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) D[i][j] = rb[i * kTile + p + j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T d = D[k][k];
+            bad |= !(d > (T)0) || !isfinite(d);
+            if (p + k < valid) dmin = ((double)d < dmin || d != d) ? (double)d : dmin;
+            const T inv = (T)1 / d;
+            T rowk[4], colk[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                rowk[j] = D[k][j];
+                colk[j] = D[j][k];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    T x;
+                    if (i == k && j == k) x = inv;
+                    else if (i == k) x = rowk[j] * inv;
+                    else if (j == k) x = -colk[i] * inv;
+                    else x = D[i][j] - colk[i] * inv * rowk[j];
+                    D[i][j] = x;
+                }
         }
-        const T d = rb[p];
-        const T cr = cb[r];
-        bad |= !(d > (T)0) || !isfinite(d);
-        if (p < valid) dmin = ((double)d < dmin || d != d) ? (double)d : dmin;
-        const T inv = (T)1 / d;
-        const bool is_p = (r == p);
-        const T f = cr * inv;
+        // this row's pivot-column entries C[r][i] (own registers or LDS) and F = C D^-1
+        T Cr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Cr[i] = cb[i * kTile + r];
+        T F[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) F[j] = Cr[0] * D[0][j] + Cr[1] * D[1][j] + Cr[2] * D[2][j] + Cr[3] * D[3][j];
+        T Dr[4];                                        // row ir of D^-1 (pivot rows)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            T v = D[0][j];
+#pragma unroll
+            for (int i = 1; i < 4; ++i) v = (ir == i) ? D[i][j] : v;
+            Dr[j] = v;
+        }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            const T upd = a[c] - f * pr[c];
-            const T scl = a[c] * inv;
-            T x = is_p ? scl : upd;
-            if (c0 + c == p) x = is_p ? inv : -f;
-            a[c] = x;
+            const int col = c0 + c, jc = col - p;
+            const bool pcol = jc >= 0 && jc < 4;
+            const T R0 = rb[0 * kTile + col], R1 = rb[1 * kTile + col], R2 = rb[2 * kTile + col],
+                    R3 = rb[3 * kTile + col];
+            const T upd = a[c] - (F[0] * R0 + F[1] * R1 + F[2] * R2 + F[3] * R3);
+            const T prw = Dr[0] * R0 + Dr[1] * R1 + Dr[2] * R2 + Dr[3] * R3;
+            T fj = F[0], dj = Dr[0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                fj = (jc == j) ? F[j] : fj;
+                dj = (jc == j) ? Dr[j] : dj;
+            }
+            a[c] = prow ? (pcol ? dj : prw) : (pcol ? -fj : upd);
         }
     }
-    if (bad) atomicOr(flags + kErrPivot, 1);
+    if (bad) {
+        atomicOr(flags + kErrPivot, 1);
+        if (tbad) atomicOr(tbad, 1);
+    }
     if (threadIdx.x == 0 && valid > 0) atomicMin(diag + kDiagMinPivot, pivot_key(dmin));
 #pragma unroll
     for (int c = 0; c < 16; ++c) Pout[cpr<T>(r, c0 + c, kTile)] = a[c];
@@ -197,6 +250,64 @@ __device__ inline T form_elem(const T* E, const T* Ha, const T* Hb, int64_t off,
     return s;
 }
 
+// Work of one workgroup: crossbar `tile` of the batch, job `job`, output tile (I, J).
+// The workgroups that invert a pivot tile at the end of the launch (output tile
+// `special` = I nb + J of every job and crossbar; -1: none) come first in dispatch
+// order, so that their serial inversions start with the launch instead of after
+// the other updates.
+struct GJSlot {
+    int tile, job, I, J;
+};
+
+__device__ inline GJSlot gj_slot(int nb, int nj, int batch, int special)
+{
+    const int tiles = nb * nb;
+    int L = blockIdx.y * gridDim.x + blockIdx.x;
+    GJSlot s;
+    if (special >= 0 && L < nj * batch) {
+        s.tile = L / nj;
+        s.job = L % nj;
+        s.I = special / nb;
+        s.J = special % nb;
+        return s;
+    }
+    int IJ;
+    if (special >= 0) {
+        L -= nj * batch;
+        const int per = tiles - 1;
+        s.tile = L / (nj * per);
+        const int rem = L % (nj * per);
+        s.job = rem / per;
+        const int q = rem % per;
+        IJ = q < special ? q : q + 1;
+    } else {
+        s.tile = L / (nj * tiles);
+        const int rem = L % (nj * tiles);
+        s.job = rem / tiles;
+        IJ = rem % tiles;
+    }
+    s.I = IJ / nb;
+    s.J = IJ % nb;
+    return s;
+}
+
+// Crossbar `tile` of a batch of one shape: its H blocks and its jobs' working
+// buffers (a plan has one crossbar and keeps its own pointers).
+template <typename T>
+__device__ inline GJJob batch_job(GJArgs& a, const GJJob& j0, int tile)
+{
+    GJJob job = j0;
+    if (tile > 0) {
+        const int64_t t = tile;
+        a.H = reinterpret_cast<T*>(a.H) + t * a.h_stride;
+        for (int k = 0; k < 2; ++k) {
+            job.S[k] = reinterpret_cast<T*>(job.S[k]) + t * a.s_stride;
+            job.P[k] = reinterpret_cast<T*>(job.P[k]) + t * a.p_stride;
+        }
+    }
+    return job;
+}
+
 template <typename T>
 __device__ inline const T* slot_ptr(const GJArgs& a, int row)
 {
@@ -210,8 +321,10 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
 {
     __shared__ __align__(32) T lds[kTile * kLd + 4 * kTile];
     const int tiles = a.nb * a.nb;
-    const GJJob& job = a.job[blockIdx.x / tiles];
-    const int I = (blockIdx.x % tiles) / a.nb, J = blockIdx.x % a.nb;
+    const GJSlot sl = gj_slot(a.nb, (int)(gridDim.x * gridDim.y) / (tiles * a.batch), a.batch, 0);
+    const GJJob job = batch_job<T>(a, a.job[sl.job], sl.tile);
+    int* tbad = a.tile_bad ? a.tile_bad + sl.tile : nullptr;
+    const int I = sl.I, J = sl.J;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const T* E = slot_ptr<T>(a, job.row);
     const T* Ha = slot_ptr<T>(a, job.dep_a);
@@ -226,7 +339,7 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
         }
     store_acc<T>(acc, reinterpret_cast<T*>(job.S[0]), a.n_p, 64 * I, 64 * J, w, l);
     if (I == 0 && J == 0)
-        invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, a.diag, min(a.n, kTile), w, l);
+        invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, a.diag, min(a.n, kTile), w, l, tbad);
 }
 
 // Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
@@ -236,8 +349,14 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
     __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
     __shared__ __align__(32) T sB[kTile * kLd];
     const int nb = a.nb, n_p = a.n_p, tiles = nb * nb;
-    const GJJob& job = a.job[blockIdx.x / tiles];
-    const int I = (blockIdx.x % tiles) / nb, J = blockIdx.x % nb;
+    const int nj = (int)(gridDim.x * gridDim.y) / (tiles * a.batch);
+    // the pivot tile this launch's inverting workgroups own: (k+1, k+1), or (0, 0) of
+    // the next row's pivot block after the last pivot of a row
+    const int special = k != nb - 1 ? (k + 1) * nb + (k + 1) : (a.job[0].next >= 0 || (nj > 1 && a.job[1].next >= 0)) ? 0 : -1;
+    const GJSlot sl = gj_slot(nb, nj, a.batch, special);
+    const GJJob job = batch_job<T>(a, a.job[sl.job], sl.tile);
+    int* tbad = a.tile_bad ? a.tile_bad + sl.tile : nullptr;
+    const int I = sl.I, J = sl.J;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int par = (int)(((int64_t)step * nb + k) & 1);
     const T* Sin = reinterpret_cast<const T*>(job.S[par]);
@@ -295,7 +414,7 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
     if (k != nb - 1) {
         store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
         if (I == k + 1 && J == k + 1)
-            invert_tile<T>(acc, sA, Pout, a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l);
+            invert_tile<T>(acc, sA, Pout, a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
         return;
     }
     // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
@@ -317,7 +436,7 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
             acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
         }
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, sA, Pout, a.flags, a.diag, min(a.n, kTile), w, l);
+    if (I == 0 && J == 0) invert_tile<T>(acc, sA, Pout, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
 }
 
 template <typename T>
@@ -334,7 +453,7 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
         if (top_len > 0) { f.job[nj] = top; f.job[nj].row = 0; f.job[nj].dep_a = f.job[nj].dep_b = -1; ++nj; }
         if (bot_len > 0) { f.job[nj] = bot; f.job[nj].row = m - 1; f.job[nj].dep_a = f.job[nj].dep_b = -1; ++nj; }
         if (nj > 0) {
-            hipLaunchKernelGGL(gj_form_kernel<T>, dim3(nj * tiles), dim3(256), 0, s, f);
+            hipLaunchKernelGGL(gj_form_kernel<T>, dim3(nj * tiles, a.batch), dim3(256), 0, s, f);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -355,7 +474,7 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
             ++nj;
         }
         for (int k = 0; k < nb; ++k) {
-            hipLaunchKernelGGL(gj_step_kernel<T>, dim3(nj * tiles), dim3(256), 0, s, f, st, k);
+            hipLaunchKernelGGL(gj_step_kernel<T>, dim3(nj * tiles, a.batch), dim3(256), 0, s, f, st, k);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -366,10 +485,10 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
     f.job[0].dep_a = (kt >= 1) ? kt - 1 : -1;
     f.job[0].dep_b = (kt + 1 <= m - 1) ? kt + 1 : -1;
     f.job[0].next = -1;
-    hipLaunchKernelGGL(gj_form_kernel<T>, dim3(tiles), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(gj_form_kernel<T>, dim3(tiles, a.batch), dim3(256), 0, s, f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int k = 0; k < nb; ++k) {
-        hipLaunchKernelGGL(gj_step_kernel<T>, dim3(tiles), dim3(256), 0, s, f, 0, k);
+        hipLaunchKernelGGL(gj_step_kernel<T>, dim3(tiles, a.batch), dim3(256), 0, s, f, 0, k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -194,9 +194,11 @@ struct SweepCtx {
     __device__ __forceinline__ int row_of(int t, int v) const { return 16 * (TW * w + t) + Frag<T>::drow(q, v); }
     __device__ __forceinline__ uint32_t poff() const { return (uint32_t)(16 * TW * w + 4 * q); }
     __device__ __forceinline__ uint32_t lane_off() const { return (uint32_t)(col * n_p) + poff(); }
-    __device__ __forceinline__ int64_t slab_row(int i) const { return ((int64_t)blockIdx.x * a.m + i) * 16 * n_p; }
+    __device__ __forceinline__ int64_t slab_row(int i) const { return ((int64_t)a.slab * a.m + i) * 16 * n_p; }
     __device__ __forceinline__ T* zbase(int i) const { return Zs + (int64_t)i * 16 * n_p; }
-    __device__ __forceinline__ double vin(int i) const { return bval ? a.V[(int64_t)b * a.m + i] : 0.0; }
+    __device__ __forceinline__ double vin(int i) const {
+        return bval ? (a.unit ? (b == i ? 1.0 : 0.0) : a.V[(int64_t)b * a.m + i]) : 0.0;
+    }
 
     // ---- forward sweep
     // this lane's rows of the right-hand side of row block i: V_i c_i, or the residual R_i
@@ -305,12 +307,13 @@ struct SweepCtx {
             }
     }
     __device__ __forceinline__ void currents(const acc_t (&u)[TW]) {
+        const bool bad = a.tile_bad != nullptr && *a.tile_bad != 0;     // batches: a spoilt crossbar
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int k = row_of(t, v);
-                if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * (double)u[t][v];
+                if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = bad ? NAN : a.g_sense * (double)u[t][v];
             }
     }
 
@@ -334,7 +337,7 @@ struct SweepCtx {
                 D = fmax(D, red[k * 16 + threadIdx.x]);
                 U = fmax(U, red[16 * W + k * 16 + threadIdx.x]);
             }
-            double* dprev = a.dnorm + (int64_t)blockIdx.x * 16 + threadIdx.x;
+            double* dprev = a.dnorm + (int64_t)a.slab * 16 + threadIdx.x;
             const double est = (a.iter > 0 && *dprev > 0.0) ? D * fmin(1.0, D / *dprev) : D;
             const bool ok = (D == 0.0) || (a.iter > 0 && est <= a.tol * U);
             *dprev = D;
@@ -342,8 +345,8 @@ struct SweepCtx {
             if (threadIdx.x == 0) {
                 const bool last = a.iter + 1 >= a.max_iter;
                 if (all || last) {
-                    a.slab_done[blockIdx.x] = 1;
-                    a.slab_final[blockIdx.x] = (a.iter + 1) & 1;
+                    a.slab_done[a.slab] = 1;
+                    a.slab_final[a.slab] = (a.iter + 1) & 1;
                     atomicMax(a.flags + kIrIters, a.iter + 1);
                     if (!all) atomicOr(a.flags + kErrConv, 1);
                 }
@@ -431,16 +434,21 @@ struct SweepHelper {
     // Pull this workgroup's 1/32 share of an H block into L2: one 4-byte load per
     // 128-byte line.  The loads are issued before the task's recovery and their
     // values consumed after it, so the helper never waits on them.
+    // A single crossbar's slabs (workgroups b, b + 8, ... on one XCD) take 1/32 of the
+    // block each; in a batch a crossbar's slabs share one XCD and take 1/16 each.
     static constexpr size_t LINE = 128;
     static constexpr size_t STEP = (size_t)kHelpers * 64 * LINE;
     static constexpr size_t BLK = (size_t)n_p * n_p * sizeof(T);
     static constexpr size_t SHARE = ((BLK / 32) + LINE - 1) & ~(LINE - 1);
-    static constexpr int PULL_IT = (int)((SHARE + STEP - 1) / STEP);
+    static constexpr size_t SHARE_B = ((BLK / 16) + LINE - 1) & ~(LINE - 1);
+    static constexpr int PULL_IT = (int)((SHARE_B + STEP - 1) / STEP);
     uint32_t pv[PULL_IT];
     __device__ __forceinline__ void pull_issue(const T* blk) {
         const char* p = reinterpret_cast<const char*>(blk);
-        const size_t lo = SHARE * (((size_t)blockIdx.x >> 3) & 31);
-        const size_t hi = min(BLK, lo + SHARE);
+        const bool batched = a.batch > 1;
+        const size_t share = batched ? SHARE_B : SHARE;
+        const size_t lo = batched ? SHARE_B * ((size_t)a.slab & 15) : SHARE * (((size_t)blockIdx.x >> 3) & 31);
+        const size_t hi = min(BLK, lo + share);
 #pragma unroll
         for (int it = 0; it < PULL_IT; ++it) {
             const size_t off = lo + ((size_t)it * kHelpers + h) * 64 * LINE + LINE * (size_t)l;
@@ -461,8 +469,8 @@ struct SweepHelper {
     double vnext = 0.0, vcur = 0.0;                          // input V of this lane's vector
     __device__ __forceinline__ void stage_load(int i) {
         const int64_t o = (int64_t)i * a.n;
-        const int bb = 16 * (int)blockIdx.x + h * VPW + l / LR;
-        vnext = (bb < a.B) ? a.V[(int64_t)bb * a.m + i] : 0.0;
+        const int bb = 16 * a.slab + h * VPW + l / LR;
+        vnext = (bb < a.B && !a.unit) ? a.V[(int64_t)bb * a.m + i] : 0.0;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int jj = min(h * 64 + l + c * HT, a.n - 1);
@@ -491,7 +499,7 @@ struct SweepHelper {
     static constexpr int SEG = seg_cap(KJ);                  // longest lane segment
     __device__ __forceinline__ void recover(int i, int buf) {
         const int n = a.n, v = l / LR, s = l % LR, cc = h * VPW + v;
-        const int bb = 16 * (int)blockIdx.x + cc;
+        const int bb = 16 * a.slab + cc;
         const double* fr = coef + buf * 3 * PL;              // padded like d
         const double* ip = fr + PL;
         const double* Gi = fr + 2 * PL;
@@ -568,7 +576,7 @@ struct SweepHelper {
         // node voltages (w_j, u_j) of the wave's vectors, 1 KB per store instruction
         typedef double d2v __attribute__((ext_vector_type(2)));
         for (int vv = 0; vv < VPW; ++vv) {
-            const int c2 = h * VPW + vv, b2 = 16 * (int)blockIdx.x + c2;
+            const int c2 = h * VPW + vv, b2 = 16 * a.slab + c2;
             if (b2 >= a.B) break;
             double* out = a.node_v + ((int64_t)b2 * a.m + i) * 2 * n;
 #pragma unroll 4
@@ -615,6 +623,30 @@ __host__ __device__ inline size_t sweep_lds_bytes(int n)
     return panel + extra;
 }
 
+// Workgroup -> (crossbar, slab) of a batch: workgroup b runs on XCD b % 8, and the
+// slabs of crossbar t all get the XCD t % 8, so they share its L2 for the H blocks.
+// Returns false for the padding workgroups past the last crossbar.
+template <typename T, int NT>
+__device__ __forceinline__ bool batch_slab(SweepArgs& a)
+{
+    if (a.batch <= 1) {
+        a.slab = blockIdx.x;
+        return true;
+    }
+    const int S = a.slabs_per, xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int t = (local / S) * 8 + xcd;
+    if (t >= a.batch) return false;
+    a.slab = local % S;
+    const int64_t n_p = 64 * NT;
+    a.H = reinterpret_cast<const T*>(a.H) + (int64_t)t * a.m * n_p * n_p;
+    a.c += (int64_t)t * a.m * n_p;
+    if (!a.unit) a.V += (int64_t)t * a.B * a.m;
+    a.Z = reinterpret_cast<T*>(a.Z) + (int64_t)t * S * a.m * 16 * n_p;
+    a.Iout += (int64_t)t * a.B * a.n;
+    if (a.tile_bad) a.tile_bad += t;
+    return true;
+}
+
 template <typename T, int NT, bool IR, bool REC>
 __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep_kernel(SweepArgs a)
 {
@@ -623,7 +655,8 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
     using acc_t = typename Frag<T>::acc_t;
     using Ctx = SweepCtx<T, NT, IR, W>;
     constexpr int TW = Ctx::TW;
-    if (IR && a.iter > 0 && a.slab_done[blockIdx.x]) return;
+    if (!batch_slab<T, NT>(a)) return;
+    if (IR && a.iter > 0 && a.slab_done[a.slab]) return;
     const int m = a.m, kt = m / 2;
     const int l = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -642,9 +675,9 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
         return;
     }
     Ctx x{a, reinterpret_cast<T*>(smem_raw),
-          reinterpret_cast<T*>(a.Z) + (int64_t)blockIdx.x * m * 16 * Ctx::n_p,
+          reinterpret_cast<T*>(a.Z) + (int64_t)a.slab * m * 16 * Ctx::n_p,
           reinterpret_cast<const T*>(a.H), wave, l, l >> 4, l & 15,
-          16 * (int)blockIdx.x + (l & 15), false, (T)a.g_bl};
+          16 * a.slab + (l & 15), false, (T)a.g_bl};
     x.bval = x.b < a.B;
     const int64_t blk = (int64_t)Ctx::n_p * Ctx::n_p;
     auto Hb = [&](int i) { return x.H + i * blk; };
@@ -1000,11 +1033,16 @@ hipError_t launch_sweep_nt(const SweepArgs& a, hipStream_t s)
     const size_t lds = sweep_lds_bytes<T, NT, IR>(a.n);
     if constexpr (!IR) {
         if (a.node_v != nullptr) {
+            if (a.batch > 1) return hipErrorInvalidValue;       // batches: currents only
             hipLaunchKernelGGL((sweep_kernel<T, NT, IR, true>), dim3(a.nslab), dim3(threads), lds, s, a);
             return hipGetLastError();
         }
+    } else {
+        if (a.batch > 1) return hipErrorInvalidValue;           // batches: float64 only
     }
-    hipLaunchKernelGGL((sweep_kernel<T, NT, IR, false>), dim3(a.nslab), dim3(threads), lds, s, a);
+    // a batch: crossbars in groups of 8 (one per XCD), a crossbar's slabs on its XCD
+    const unsigned grid = a.batch > 1 ? (unsigned)(((a.batch + 7) / 8) * 8 * a.slabs_per) : (unsigned)a.nslab;
+    hipLaunchKernelGGL((sweep_kernel<T, NT, IR, false>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -49,8 +49,12 @@ __device__ inline double recip(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// A crossbar's B input vectors may be split over gridDim.y workgroups (Bp each, the
+// last one fewer): each redoes the crossbar's factorization and forward-substitutes its
+// own vectors, trading repeated elimination for more workgroups in flight.
 struct TileArgs {
-    int m, n, B;
+    int m, n, B, Bp;
+    int unit;           // 1: input vector b is the unit vector e_b (V is not read)
     double g_wl, g_bl, g_src, g_sense;
     const double* G;    // [T][m][n]
     const double* V;    // [T][B][m]
@@ -71,11 +75,13 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, l16 = lane & 15;
     const int br = tid >> 4, bc = tid & 15;
-    const int m = a.m, n = a.n, B = a.B;
+    const int m = a.m, n = a.n;
     const int64_t t = blockIdx.x;
+    const int b0 = (int)blockIdx.y * a.Bp;                 // first vector of this workgroup
+    const int B = min(a.Bp, a.B - b0);                      // vectors of this workgroup
     const double* G = a.G + t * m * n;
-    const double* V = a.V + t * B * m;
-    double* I = a.I + t * B * n;
+    const double* V = a.V + (t * a.B + b0) * m;
+    double* I = a.I + (t * a.B + b0) * n;
     const double gw = a.g_wl, gb = a.g_bl;
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -240,7 +246,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int b = 64 * w + 16 * g + l16;
-                vi[g] = (b < B) ? V[(int64_t)b * m + i] : 0.0;
+                vi[g] = (b < B) ? (a.unit ? (b0 + b == i ? 1.0 : 0.0) : V[(int64_t)b * m + i]) : 0.0;
             }
             dv4 y[NT][4];
 #pragma unroll
@@ -287,17 +293,22 @@ __global__ __launch_bounds__(kTileThreads) void tile_currents_kernel(TileArgs a)
 }  // namespace
 
 hipError_t xbk_launch_tile_currents(int T, int m, int n, int B, double g_wl, double g_bl, double g_src,
-                                    double g_sense, const double* G, const double* V, double* I, hipStream_t s)
+                                    double g_sense, const double* G, const double* V, double* I, hipStream_t s,
+                                    int block, int split, bool unit)
 {
-    if (T < 1 || m < 1 || n < 1 || n > 64 || B < 1 || B > kTileThreads || !G || !V || !I)
+    if (T < 1 || m < 1 || n < 1 || n > 64 || B < 1 || B > kTileThreads || !G || (!V && !unit) || !I)
         return hipErrorInvalidValue;
-    TileArgs a{m, n, B, g_wl, g_bl, g_src, g_sense, G, V, I};
-    const dim3 grid((unsigned)T), block(kTileThreads);
-    if (n <= 16)
-        hipLaunchKernelGGL(tile_currents_kernel<16>, grid, block, 0, s, a);
-    else if (n <= 32)
-        hipLaunchKernelGGL(tile_currents_kernel<32>, grid, block, 0, s, a);
+    if (block == 0) block = n <= 16 ? 16 : n <= 32 ? 32 : 64;
+    if ((block != 16 && block != 32 && block != 64) || block < n || split < 1 || split > 4) return hipErrorInvalidValue;
+    const int Bp = (B + split - 1) / split;
+    const int parts = (B + Bp - 1) / Bp;
+    TileArgs a{m, n, B, Bp, unit ? 1 : 0, g_wl, g_bl, g_src, g_sense, G, V, I};
+    const dim3 grid((unsigned)T, (unsigned)parts), blk(kTileThreads);
+    if (block == 16)
+        hipLaunchKernelGGL(tile_currents_kernel<16>, grid, blk, 0, s, a);
+    else if (block == 32)
+        hipLaunchKernelGGL(tile_currents_kernel<32>, grid, blk, 0, s, a);
     else
-        hipLaunchKernelGGL(tile_currents_kernel<64>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(tile_currents_kernel<64>, grid, blk, 0, s, a);
     return hipGetLastError();
 }

@@ -14,7 +14,8 @@ EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_debug_shift_p
             "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight", "xbar_sg_conv_backward_weight_noalloc",
             "xbar_sg_conv_forward",
             "xbar_sg_features", "xbar_sg_predict", "xbar_sg_readout_loss", "xbar_sg_workspace_floats",
-            "xbar_solve_batch", "xbar_status_string", "xbar_tiles_currents", "xbar_transfer",
+            "xbar_solve_batch", "xbar_status_string", "xbar_tiles_create", "xbar_tiles_currents",
+            "xbar_tiles_destroy", "xbar_tiles_run", "xbar_tiles_workspace_bytes", "xbar_transfer",
             "xbar_transfer_apply"]
 
 

@@ -138,40 +138,3 @@ def test_tiles_in_a_captured_graph():
         for k, (_, _, Id) in enumerate(data):
             assert np.array_equal(Id.cpu().numpy(), eager[k]), f"replay {rep}, class {k}"
         _ = torch.ones(1000, device="cuda").sum().item()        # eager work between replays
-
-
-def test_c4_every_class_all_vectors_against_stored_oracle():
-    """All 16 (m_t, n_t) classes of the heterogeneous tiles workload, through the path
-    the benchmark times for that class: the first tile of each class, all 256 input
-    vectors, against oracle currents stored by tests/golden/make_golden.py c4."""
-    import os
-
-    import torch
-
-    import paper_2410_19993_amd as xb
-    import workloads
-    from tests.gpu_util import GOLDEN
-    g = workloads.C4_GEOM
-    r = (g["r_wl"], g["r_bl"], g["r_src"], g["r_sense"])
-    gold = np.load(os.path.join(GOLDEN, "c4_class_currents.npz"))
-    tiles = workloads.c4()
-    worst = 0.0
-    for m in workloads.C4_SIZES:
-        for n in workloads.C4_SIZES:
-            t = tiles[int(gold[f"t{m}x{n}"])]
-            assert t.G.shape == (m, n)
-            ref = gold[f"I{m}x{n}"]
-            Gd = torch.from_numpy(t.G).cuda()
-            Vd = torch.from_numpy(t.V).cuda()
-            log(f"case c4 class {m}x{n}: tile {t.index}, 256 vectors")
-            if n <= 64:
-                I = xb.tiles_currents(Gd[None], Vd[None], *r)[0].cpu().numpy()
-            else:
-                with xb.PlanLanes(*r, lanes=1, max_batch=256) as pl:
-                    I = pl.currents([Gd], [Vd])[0].cpu().numpy()
-                    pl.check()
-            e = float(rel_err(I, ref).max())
-            log(f"  max current rel err {e:.3e}")
-            worst = max(worst, e)
-            assert np.all(np.isfinite(I)) and e <= TOL_FP64
-    log(f"  worst over the 16 classes {worst:.3e}")
