@@ -155,7 +155,7 @@ struct NSChain {
     void* Q;
     void* Qt;
     void* P2;
-    double* dprev;       // [n_p] diagonal of the previous pivot block of this chain
+    double* dprev;       // [2][n_p] diagonal of the pivot block of chain row i at [i & 1]
 };
 
 struct NSJob {

@@ -6,8 +6,12 @@
 // consecutive pivots of a chain differ little, so the inverse is reached in a
 // few steps of the quadratically convergent Newton-Schulz iteration
 //     Q_k = I - X_k P,      X_{k+1} = X_k + Q_k X_k      (I - X_{k+1} P = Q_k^2)
-// started from the previous row's inverse with its diagonal corrected,
-//     X_0 = H_prev + diag(P)^{-1} - diag(P_prev)^{-1},
+// started from the previous row's inverse corrected to first order in the change
+// of the pivot block, with the previous inverse taken as its diagonal there,
+//     X_0 = H_prev + diag(P)^{-1} - diag(P_prev)^{-1} - D offdiag(P - P_prev) D,
+//     D = diag(P_prev)^{-1}
+// (elementwise: for the 512 x 512 workload it takes max |I - X_0 P| from about
+// 6e-6 to 5e-9 at 2.5-ohm segments and from 1.5e-5 to 2.4e-8 at 5 ohm),
 // or from diag(P)^{-1} at a chain start and for the twist block.  Two steps are
 // taken together as a round of three launches,
 //     Q = I - X P;    Q^2 and Y = X + Q X;    X'' = Y + Q^2 Y = (I + Q^2)(I + Q) X,
@@ -130,12 +134,12 @@ __device__ __forceinline__ void ns_form(const NSArgs& a, const NSJob& job, const
             if (Hb) s -= (T)a.g2 * Hb[e];
             if (job.warm) {
                 x = Ha[e];
-                if (r == c) x += (T)1 / s - (T)(1.0 / ch.dprev[r]);
+                if (r == c) x += (T)1 / s - (T)(1.0 / ch.dprev[(job.dep_a & 1) * n_p + r]);
             } else {
                 x = (r == c) ? (T)1 / s : (T)0;
             }
             if (r == c) {
-                ch.dprev[r] = (double)s;
+                ch.dprev[(job.row & 1) * n_p + r] = (double)s;
                 dmin = ((double)s < dmin || s != s) ? (double)s : dmin;
             }
         }
@@ -358,20 +362,26 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
     // the epilogue's operands (this tile of Y, of the next row's E block and the
     // previous pivot diagonal) and the round's max |P2| partials are requested
     // before the product, so that their latency hides behind it
-    T yin[4], en[4];
-    double dp = 1.0;
+    T yin[4], en[4], sold[4];
+    double dpr = 1.0, dpc[4] = {1.0, 1.0, 1.0, 1.0};
     double mx = 0.0;
     for (int k = threadIdx.x; k < tiles; k += 256) {
         const double o = a.part[(int64_t)chain * tiles + k];
         mx = (o > mx || o != o) ? o : mx;
     }
     const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)max(next_row, 0) * n_p * n_p;
+    const T* Sp = reinterpret_cast<const T*>(ch.S);                    // this row's pivot block
+    const double* dprev = ch.dprev + (job.row & 1) * n_p;              // and its diagonal
+    const int col0 = 16 * (TC + (w & 1));
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         yin[v] = Y[base + frg_slot<T>(l, v)];
         en[v] = next_row >= 0 ? En[base + frg_slot<T>(l, v)] : (T)0;
+        sold[v] = next_row >= 0 ? Sp[base + frg_slot<T>(l, v)] : (T)0;
+        const int col = col0 + Frag<T>::kidx(l >> 4, v);
+        if (next_row >= 0 && col < a.n) dpc[v] = dprev[col];
     }
-    if (next_row >= 0 && row < a.n) dp = ch.dprev[row];
+    if (next_row >= 0 && row < a.n) dpr = dprev[row];
     for (int off = 32; off > 0; off >>= 1) {
         const double o = __shfl_xor(mx, off);
         mx = (o > mx || o != o) ? o : mx;
@@ -394,7 +404,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
         const T x = yin[v] + sum[v];
         if (fin || last) Hr[o] = x;
         if (form) {
-            const int col = 16 * (TC + (w & 1)) + Frag<T>::kidx(l >> 4, v);
+            const int col = col0 + Frag<T>::kidx(l >> 4, v);
             T sv, xv;
             if (row >= a.n || col >= a.n) {
                 sv = xv = (row == col) ? (T)1 : (T)0;
@@ -402,9 +412,11 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
                 sv = en[v] - (T)a.g2 * x;
                 xv = x;
                 if (row == col) {
-                    xv += (T)1 / sv - (T)(1.0 / dp);
-                    ch.dprev[row] = (double)sv;
+                    xv += (T)1 / sv - (T)(1.0 / dpr);
+                    ch.dprev[(next_row & 1) * n_p + row] = (double)sv;
                     dmin = ((double)sv < dmin || sv != sv) ? (double)sv : dmin;
+                } else {
+                    xv -= (T)((double)(sv - sold[v]) / (dpr * dpc[v]));
                 }
             }
             S[o] = sv;

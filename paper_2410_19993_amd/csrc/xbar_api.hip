@@ -31,7 +31,7 @@ struct Buffers {
     int* flags = nullptr;     // [kNumFlags]
     unsigned long long* diag = nullptr;   // [kNumDiag]: smallest pivot key, largest backward error bits
     double* sink = nullptr;   // [128]: target of the sweep's masked-off node-voltage stores
-    // Newton-Schulz factor: per chain S, X[2], Q ([n_p][n_p]) and dprev ([n_p])
+    // Newton-Schulz factor: per chain S, X[2], Q ([n_p][n_p]) and dprev ([2][n_p])
     void* ns_S[2] = {nullptr, nullptr};
     void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* ns_Q[2] = {nullptr, nullptr};
@@ -283,7 +283,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         A(&d.ns_Q[c], n_p * n_p * es);
         A(&d.ns_Qt[c], n_p * n_p * es);
         A(&d.ns_P2[c], n_p * n_p * es);
-        A((void**)&d.ns_dprev[c], n_p * 8);
+        A((void**)&d.ns_dprev[c], 2 * n_p * 8);
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
     A((void**)&d.ns_state, 6 * sizeof(xbk::NSState));
