@@ -451,6 +451,21 @@ xbar_status xbar_sg_conv_backward_weight_noalloc(int32_t B, int32_t H, int32_t W
                                                  const float* x, const float* gy, const float* ymask, float* gw,
                                                  float* gb, void* stream);
 
+/* The same three convolutions on the bfloat16 matrix cores: each call has the
+ * arguments, layouts and checks of its float32 counterpart above, and computes the
+ * same sums with every operand rounded to bfloat16 (8-bit significand, nearest, ties
+ * to even; activations, gradients and weights stay float32 in memory) and the
+ * products accumulated in float32.  The input-gradient masks and the workspace are as
+ * for the float32 calls (xbar_sg_workspace_floats). */
+xbar_status xbar_sg_conv_forward_bf16(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, int32_t relu,
+                                      const float* x, const float* w, const float* bias, float* y, void* stream);
+xbar_status xbar_sg_conv_backward_data_bf16(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* gy,
+                                            const float* ymask, const float* w, const float* xmask, float* gx,
+                                            void* stream);
+xbar_status xbar_sg_conv_backward_weight_bf16(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
+                                              const float* gy, const float* ymask, float* gw, float* gb, float* work,
+                                              int64_t work_floats, void* stream);
+
 /* Column readouts and loss of the last map Y [B][2][m][n] (float32):
  * yhat_j = mean_i Y[b][0][i][j] (the correction), s_j = mean_i Y[b][1][i][j] (the
  * error estimate), e = yhat - delta (delta [B][n] float64), and the normalised log

@@ -117,6 +117,9 @@ def lib() -> ctypes.CDLL:
         L.xbar_sg_conv_backward_data.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.xbar_sg_conv_backward_weight.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i64, vp]
         L.xbar_sg_conv_backward_weight_noalloc.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_forward_bf16.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_backward_data_bf16.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.xbar_sg_conv_backward_weight_bf16.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, i64, vp]
         L.xbar_sg_workspace_floats.argtypes = [i32, i32]
         L.xbar_sg_workspace_floats.restype = i64
         L.xbar_sg_readout_loss.argtypes = [i32, i32, i32, vp, vp, f64, vp, vp, vp]
@@ -130,7 +133,8 @@ def lib() -> ctypes.CDLL:
                   "xbar_transfer_apply", "xbar_tiles_currents", "xbar_tiles_create", "xbar_tiles_run",
                   "xbar_tiles_destroy", "xbar_sg_features", "xbar_sg_conv_forward",
                   "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight",
-                  "xbar_sg_conv_backward_weight_noalloc", "xbar_sg_readout_loss",
+                  "xbar_sg_conv_backward_weight_noalloc", "xbar_sg_conv_forward_bf16",
+                  "xbar_sg_conv_backward_data_bf16", "xbar_sg_conv_backward_weight_bf16", "xbar_sg_readout_loss",
                   "xbar_sg_adam", "xbar_sg_predict"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -264,21 +268,25 @@ def xbar_sg_features(B, m, n, G, V, r, X, stream=None) -> None:
     _check("xbar_sg_features", lib().xbar_sg_features(B, m, n, _ptr(G), _ptr(V), _ptr(r), _ptr(X), _s(stream)))
 
 
-def xbar_sg_conv_forward(B, H, W, C, O, relu, x, w, b, y, stream=None) -> None:
-    _check("xbar_sg_conv_forward", lib().xbar_sg_conv_forward(B, H, W, C, O, int(bool(relu)), _ptr(x), _ptr(w),
-                                                              _ptr(b), _ptr(y), _s(stream)))
+def _sfx(bf16: bool) -> str:
+    return "_bf16" if bf16 else ""
 
 
-def xbar_sg_conv_backward_data(B, H, W, C, O, gy, ymask, w, gx, xmask=None, stream=None) -> None:
-    _check("xbar_sg_conv_backward_data", lib().xbar_sg_conv_backward_data(B, H, W, C, O, _ptr(gy), _ptr(ymask),
-                                                                          _ptr(w), _ptr(xmask), _ptr(gx),
-                                                                          _s(stream)))
+def xbar_sg_conv_forward(B, H, W, C, O, relu, x, w, b, y, stream=None, bf16=False) -> None:
+    name = "xbar_sg_conv_forward" + _sfx(bf16)
+    _check(name, getattr(lib(), name)(B, H, W, C, O, int(bool(relu)), _ptr(x), _ptr(w), _ptr(b), _ptr(y), _s(stream)))
 
 
-def xbar_sg_conv_backward_weight(B, H, W, C, O, x, gy, ymask, gw, gb, work, stream=None) -> None:
-    _check("xbar_sg_conv_backward_weight",
-           lib().xbar_sg_conv_backward_weight(B, H, W, C, O, _ptr(x), _ptr(gy), _ptr(ymask), _ptr(gw), _ptr(gb),
-                                              _ptr(work), int(work.numel()), _s(stream)))
+def xbar_sg_conv_backward_data(B, H, W, C, O, gy, ymask, w, gx, xmask=None, stream=None, bf16=False) -> None:
+    name = "xbar_sg_conv_backward_data" + _sfx(bf16)
+    _check(name, getattr(lib(), name)(B, H, W, C, O, _ptr(gy), _ptr(ymask), _ptr(w), _ptr(xmask), _ptr(gx),
+                                      _s(stream)))
+
+
+def xbar_sg_conv_backward_weight(B, H, W, C, O, x, gy, ymask, gw, gb, work, stream=None, bf16=False) -> None:
+    name = "xbar_sg_conv_backward_weight" + _sfx(bf16)
+    _check(name, getattr(lib(), name)(B, H, W, C, O, _ptr(x), _ptr(gy), _ptr(ymask), _ptr(gw), _ptr(gb),
+                                      _ptr(work), int(work.numel()), _s(stream)))
 
 
 def xbar_sg_conv_backward_weight_noalloc(B, H, W, C, O, x, gy, ymask, gw, gb, stream=None) -> None:

@@ -19,6 +19,14 @@
 
 #include "xbar.h"
 
+// bfloat16 matrix-core convolutions (surrogate_mfma.hip)
+hipError_t xbk_sg_conv_forward_bf16(int B, int H, int W, int C, int O, int relu, const float* x, const float* w,
+                                    const float* bias, float* y, hipStream_t s);
+hipError_t xbk_sg_conv_backward_data_bf16(int B, int H, int W, int C, int O, const float* gy, const float* ymask,
+                                          const float* w, const float* xmask, float* gx, hipStream_t s);
+hipError_t xbk_sg_conv_backward_weight_bf16(int B, int H, int W, int C, int O, const float* x, const float* gy,
+                                            const float* ymask, float* part, int nparts, hipStream_t s);
+
 namespace {
 
 constexpr int kMaxCh = XBAR_SG_MAX_CHANNELS;
@@ -567,6 +575,54 @@ xbar_status xbar_sg_conv_backward_data(int32_t B, int32_t H, int32_t W, int32_t 
     return launched();
 }
 
+
+xbar_status xbar_sg_conv_forward_bf16(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, int32_t relu,
+                                      const float* x, const float* w, const float* bias, float* y, void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !x || !w || !bias || !y) return XBAR_ERR_ARG;
+    const int64_t hw = (int64_t)H * W;
+    if (overlap(y, (int64_t)B * O * hw * 4, x, (int64_t)B * C * hw * 4) ||
+        overlap(y, (int64_t)B * O * hw * 4, w, (int64_t)O * C * 36) || overlap(y, (int64_t)B * O * hw * 4, bias, O * 4))
+        return XBAR_ERR_ARG;
+    if (xbk_sg_conv_forward_bf16(B, H, W, C, O, relu, x, w, bias, y, reinterpret_cast<hipStream_t>(hip_stream)) !=
+        hipSuccess)
+        return XBAR_ERR_DEVICE;
+    return launched();
+}
+
+xbar_status xbar_sg_conv_backward_data_bf16(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* gy,
+                                            const float* ymask, const float* w, const float* xmask, float* gx,
+                                            void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !gy || !w || !gx) return XBAR_ERR_ARG;
+    const int64_t hw = (int64_t)H * W, nx = (int64_t)B * C * hw * 4, ny = (int64_t)B * O * hw * 4;
+    if (overlap(gx, nx, gy, ny) || (ymask && overlap(gx, nx, ymask, ny)) || overlap(gx, nx, w, (int64_t)O * C * 36) ||
+        (xmask && overlap(gx, nx, xmask, nx)))
+        return XBAR_ERR_ARG;
+    if (xbk_sg_conv_backward_data_bf16(B, H, W, C, O, gy, ymask, w, xmask, gx,
+                                       reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+        return XBAR_ERR_DEVICE;
+    return launched();
+}
+
+xbar_status xbar_sg_conv_backward_weight_bf16(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
+                                              const float* gy, const float* ymask, float* gw, float* gb, float* work,
+                                              int64_t work_floats, void* hip_stream)
+{
+    if (!shape_ok(B, H, W) || !ch_ok(C, O) || !x || !gy || !gw || !gb || !work) return XBAR_ERR_ARG;
+    const int ne = O * C * 9;
+    const int nparts = bwd_weight_parts(B, H, W);
+    if (work_floats < (int64_t)nparts * (ne + O)) return XBAR_ERR_ARG;
+    const int64_t nw = (int64_t)nparts * (ne + O) * 4;
+    if (overlap(work, nw, gw, ne * 4) || overlap(work, nw, gb, O * 4) || overlap(gw, ne * 4, gb, O * 4))
+        return XBAR_ERR_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (xbk_sg_conv_backward_weight_bf16(B, H, W, C, O, x, gy, ymask, work, nparts, s) != hipSuccess)
+        return XBAR_ERR_DEVICE;
+    hipLaunchKernelGGL(sg_reduce_parts_kernel, dim3((ne + O + 15) / 16), dim3(256), 0, s, nparts, ne, O, work, gw,
+                       gb);
+    return launched();
+}
 
 xbar_status xbar_sg_conv_backward_weight(int32_t B, int32_t H, int32_t W, int32_t C, int32_t O, const float* x,
                                          const float* gy, const float* ymask, float* gw, float* gb, float* work,

@@ -44,12 +44,19 @@ class Surrogate:
     that the untrained network predicts the ideal currents G^T V exactly."""
 
     def __init__(self, channels: int = 32, seed: int = 0, lr: float = 1e-3, betas=(0.9, 0.999),
-                 eps: float = 1e-8, zero_last: bool = True, lam: float = 0.1, depth: int = 4):
+                 eps: float = 1e-8, zero_last: bool = True, lam: float = 0.1, depth: int = 4,
+                 precision: str = "bf16"):
         torch = _torch()
         if not 1 <= channels <= 32:
             raise ValueError("channels must be in [1, 32]")
         if depth < 2:
             raise ValueError("depth must be >= 2")
+        if precision not in ("bf16", "fp32"):
+            raise ValueError("precision must be 'bf16' (matrix cores) or 'fp32' (vector ALUs)")
+        # the convolutions' arithmetic: bfloat16 operands with float32 accumulation on the
+        # matrix cores, or float32 throughout; weights, activations and Adam stay float32
+        self.precision = precision
+        self._bf16 = precision == "bf16"
         self.C = int(channels)
         self.L = int(depth)
         self.dims = [N_FEATURES] + [self.C] * (self.L - 1) + [2]
@@ -96,7 +103,7 @@ class Surrogate:
     def state(self) -> dict:
         """Host copies of the weights and optimizer state (for checkpoints)."""
         return {"params": self.params.cpu().numpy(), "m1": self.m1.cpu().numpy(), "m2": self.m2.cpu().numpy(),
-                "t": self.t, "channels": self.C, "depth": self.L, "kappa": self.kappa}
+                "t": self.t, "channels": self.C, "depth": self.L, "kappa": self.kappa, "precision": self.precision}
 
     def load(self, state: dict) -> None:
         torch = _torch()
@@ -149,7 +156,8 @@ class Surrogate:
         x = self.X
         outs = self.acts + [self.Y]
         for k, (w, b) in enumerate(self._views(self.params)):
-            _lib.xbar_sg_conv_forward(B, m, n, self.dims[k], self.dims[k + 1], k < self.L - 1, x, w, b, outs[k], s)
+            _lib.xbar_sg_conv_forward(B, m, n, self.dims[k], self.dims[k + 1], k < self.L - 1, x, w, b, outs[k], s,
+                                      bf16=self._bf16)
             x = outs[k]
         return self.Y[:B]
 
@@ -171,12 +179,14 @@ class Surrogate:
             # g_out is already the gradient before layer k's ReLU: the input gradient of
             # layer k + 1 wrote it masked by [layer k's output > 0]
             C, O = self.dims[k], self.dims[k + 1]
-            _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, None, gv[k][0], gv[k][1], self.work, s)
+            _lib.xbar_sg_conv_backward_weight(B, m, n, C, O, ins[k], g_out, None, gv[k][0], gv[k][1], self.work, s,
+                                              bf16=self._bf16)
             if k == last:
                 self.gY[:B, 1].zero_()              # the estimate trains the last layer only
             if k > 0:
                 g_in = self.ga[k % 2]
-                _lib.xbar_sg_conv_backward_data(B, m, n, C, O, g_out, None, wv[k][0], g_in, xmask=ins[k], stream=s)
+                _lib.xbar_sg_conv_backward_data(B, m, n, C, O, g_out, None, wv[k][0], g_in, xmask=ins[k], stream=s,
+                                                bf16=self._bf16)
                 g_out = g_in
         self.t += 1
         _lib.xbar_sg_adam(self.params, self.grads, self.m1, self.m2, self.lr, self.betas[0], self.betas[1],

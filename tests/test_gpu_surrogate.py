@@ -179,7 +179,7 @@ def test_network_gradients_and_update_match_oracle():
     V = rng.uniform(0, 0.5, (B, m))
     r = rng.uniform(1, 5, B)
     delta = rng.normal(scale=0.05, size=(B, n))
-    net = sgm.Surrogate(channels=8, seed=3, lr=1e-3, zero_last=False, depth=5)
+    net = sgm.Surrogate(channels=8, seed=3, lr=1e-3, zero_last=False, depth=5, precision="fp32")
     params = [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for w, b in net.layers()]
     log("case network gradients element by element, channels 8, depth 5, B=4 12x19")
     loss = net.train_step(_t(G), _t(V), _t(r), _t(delta))
@@ -416,7 +416,7 @@ def test_train_step_with_few_channels_on_many_tiles():
     V = rng.uniform(0, 0.5, (B, m))
     r = rng.uniform(1, 5, B)
     delta = rng.normal(scale=0.05, size=(B, n))
-    net = sgm.Surrogate(channels=3, seed=4, zero_last=False)
+    net = sgm.Surrogate(channels=3, seed=4, zero_last=False, precision="fp32")
     params = [(w.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for w, b in net.layers()]
     log("case train_step channels 3 on 640 tiles")
     net.train_step(_t(G), _t(V), _t(r), _t(delta))
