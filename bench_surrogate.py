@@ -2,6 +2,7 @@
 
     python bench_surrogate.py [--maps 12500] [--held-out-maps 1250] [--vectors 16]
                               [--epochs 6] [--batch 32] [--lr 1e-3] [--channels 32]
+                              [--precision bf16|fp32]
 
 Workload (seeded, synthetic): conductance maps log-uniform on [1e-6, 1e-4] S, the
 segment resistance r = r_wl = r_bl drawn from {1.0, 1.25, ..., 5.0} ohm per map,
@@ -21,7 +22,11 @@ Steps, all on the GPU through the library:
    the errors of the rest;
 4. inference: surrogate currents for batches of held-out samples, timed;
 5. checked predictions: the surrogate, with every flagged sample re-solved exactly,
-   over the first 2048 held-out samples, timed.
+   over the first 2048 held-out samples, timed;
+6. convolution rates: each layer's forward, input-gradient and weight-gradient
+   convolution at the training batch, timed with HIP events on the launch stream, as
+   TFLOP/s (2 flops per multiply-add of the 3 x 3 convolution) against the dense peak of
+   the arithmetic they run on (bfloat16 matrix cores 2500, float32 vector 157.3).
 One JSON line goes to stdout at the end; progress goes to stderr.
 """
 from __future__ import annotations
@@ -58,6 +63,9 @@ def main():
     ap.add_argument("--infer-batch", type=int, default=256)
     ap.add_argument("--tol", type=float, default=0.01, help="error-estimate threshold of the checked predictions")
     ap.add_argument("--cal-maps", type=int, default=256, help="maps of the calibration set of the error estimate")
+    ap.add_argument("--precision", choices=("bf16", "fp32"), default="bf16",
+                    help="convolution arithmetic: bfloat16 matrix cores or float32 vector units")
+    ap.add_argument("--rates-only", action="store_true", help="only the convolution rates (step 6)")
     args = ap.parse_args()
 
     import torch
@@ -67,6 +75,9 @@ def main():
     _lib.lib()
     assert torch.cuda.is_available(), "no GPU visible"
     m = n = args.size
+    if args.rates_only:
+        print(json.dumps({"conv_rates": conv_rates(args, m, n)}), flush=True)
+        return
 
     # 1. labels from the exact solver
     torch.cuda.synchronize()
@@ -81,7 +92,8 @@ def main():
         f"({args.maps / t_label:.0f} maps/s, {len(train) / t_label:.0f} solves/s)")
 
     # 2. training
-    net = sgm.Surrogate(channels=args.channels, seed=args.seed, lr=args.lr, depth=args.depth)
+    net = sgm.Surrogate(channels=args.channels, seed=args.seed, lr=args.lr, depth=args.depth,
+                        precision=args.precision)
     S = len(train)
     steps_per_epoch = S // args.batch
     total = steps_per_epoch * args.epochs
@@ -187,16 +199,93 @@ def main():
         "workload": f"{m}x{n} crossbars, r_wl = r_bl in [1, 5] ohm, r_src = r_sense = 50 ohm, synthetic",
         "train_samples": S, "held_out_samples": len(held), "channels": args.channels, "depth": args.depth,
         "epochs": args.epochs,
-        "batch": args.batch, "steps": total, "dtype": "f32 (network), f64 (labels, readout)",
+        "batch": args.batch, "steps": total,
+        "dtype": ("bf16 operands, f32 accumulate (convolutions)" if args.precision == "bf16" else
+                  "f32 (convolutions)") + "; f32 (features, Adam), f64 (labels, readout)",
+        "precision": args.precision,
         "label_solves_per_s": len(train) / t_label, "label_maps_per_s": args.maps / t_label,
         "train_s": t_train, "train_ms_per_step": 1e3 * t_train / max(total, 1),
         "train_samples_per_s": total * args.batch / t_train,
         "infer_ms_per_batch": 1e3 * t_inf, "infer_batch": B,
         "speedup_vs_solver_new_maps": (B / t_inf) / (args.maps / t_label),
         "error_surrogate": acc_sg, "error_ideal_GtV": acc_0, "error_estimate": estimate, "loss_curve": losses[-10:],
+        "conv_rates": conv_rates(args, m, n),
     }
     print(json.dumps(result), flush=True)
     net.close()
+
+
+def conv_rates(args, m, n, reps: int = 50):
+    """Per-launch time and rate of each convolution kind, summed over the network's layers
+    at the training batch, with random operands of the layers' shapes."""
+    import torch
+
+    from paper_2410_19993_amd import _lib
+    from paper_2410_19993_amd.surrogate import N_FEATURES
+    bf = args.precision == "bf16"
+    peak = 2500.0 if bf else 157.3
+    B, L, Cw = args.batch, args.depth, args.channels
+    dims = [N_FEATURES] + [Cw] * (L - 1) + [2]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    rnd = lambda *sh: torch.randn(*sh, generator=gen, device="cuda", dtype=torch.float32)
+    s = torch.cuda.Stream()
+    sp = s.cuda_stream
+    work = torch.empty(max(_lib.xbar_sg_workspace_floats(dims[k], dims[k + 1]) for k in range(L)),
+                       dtype=torch.float32, device="cuda")
+    calls = {"forward": [], "input_gradient": [], "weight_gradient": []}
+    flops = 0.0
+    for k in range(L):
+        C, O = dims[k], dims[k + 1]
+        x, y, gy, gx = rnd(B, C, m, n), rnd(B, O, m, n), rnd(B, O, m, n), rnd(B, C, m, n)
+        w, b, gw, gb = rnd(O, C, 3, 3), rnd(O), rnd(O, C, 3, 3), rnd(O)
+        relu = k < L - 1
+        calls["forward"].append(lambda C=C, O=O, x=x, w=w, b=b, y=y, relu=relu: _lib.xbar_sg_conv_forward(
+            B, m, n, C, O, relu, x, w, b, y, sp, bf16=bf))
+        if k > 0:
+            # as in training: the output gradient arrives already masked by the ReLU, the
+            # input gradient is masked by the layer input's ReLU
+            calls["input_gradient"].append(lambda C=C, O=O, gy=gy, w=w, gx=gx, x=x: _lib.xbar_sg_conv_backward_data(
+                B, m, n, C, O, gy, None, w, gx, xmask=x, stream=sp, bf16=bf))
+        calls["weight_gradient"].append(lambda C=C, O=O, x=x, gy=gy, gw=gw, gb=gb: _lib.xbar_sg_conv_backward_weight(
+            B, m, n, C, O, x, gy, None, gw, gb, work, sp, bf16=bf))
+    out = {"peak_tflops": peak, "arithmetic": "bf16 matrix cores" if bf else "f32 vector", "batch": B}
+    torch.cuda.synchronize()
+    for kind, fs in calls.items():
+        layer_flops = [2.0 * B * m * n * 9 * dims[k] * dims[k + 1] for k in range(L)]
+        if kind == "input_gradient":
+            layer_flops = layer_flops[1:]
+        with torch.cuda.stream(s):
+            for f in fs:
+                f()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record(s)
+            for _ in range(reps):
+                for f in fs:
+                    f()
+            t1.record(s)
+        t1.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        tf = sum(layer_flops) / (ms * 1e-3) / 1e12
+        out[kind] = {"ms_per_pass": ms, "launches_per_pass": len(fs), "tflops": tf, "frac": tf / peak}
+        log(f"conv {kind}: {len(fs)} layers in {ms:.3f} ms, {tf:.1f} TFLOP/s, {tf / peak:.3f} of {peak} peak")
+    # reference: a plain device copy of one hidden activation tensor (B x C x m x n float32),
+    # the traffic of a layer that reads and writes one such tensor
+    src, dst = rnd(B, Cw, m, n), torch.empty((B, Cw, m, n), dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(s):
+        dst.copy_(src)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(s)
+        for _ in range(reps):
+            dst.copy_(src)
+        t1.record(s)
+    t1.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    nbytes = 2 * src.numel() * 4
+    out["copy_reference"] = {"bytes": nbytes, "ms": ms, "gbps": nbytes / (ms * 1e-3) / 1e9}
+    log(f"plain copy of a {tuple(src.shape)} float32 tensor: {ms * 1e3:.1f} us, {nbytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+    work = None
+    return out
 
 
 if __name__ == "__main__":

@@ -346,8 +346,19 @@ __global__ __launch_bounds__(256) void sg_reduce_parts_kernel(int nparts, int ne
     const int le = threadIdx.x & 15, lp = threadIdx.x >> 4;
     const int e = blockIdx.x * 16 + le;
     float s = 0.0f;
-    if (e < ne + O)
-        for (int k = lp; k < nparts; k += 16) s += part[(int64_t)k * (ne + O) + e];
+    if (e < ne + O) {
+        // eight partials in flight at a time, added in the same order as one at a time
+        const int64_t stride = ne + O;
+        int k = lp;
+        for (; k + 7 * 16 < nparts; k += 8 * 16) {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = part[(int64_t)(k + 16 * i) * stride + e];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s += v[i];
+        }
+        for (; k < nparts; k += 16) s += part[(int64_t)k * stride + e];
+    }
     red[lp][le] = s;
     __syncthreads();
     if (lp == 0 && e < ne + O) {
