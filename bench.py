@@ -215,6 +215,65 @@ def measured_traffic(workload, record=TRAFFIC_FILE, sources=KERNEL_SOURCES):
     return rec.get("bytes_per_launch")
 
 
+def run_bf16(steps, r=2.5):
+    """The bfloat16 factor with the classical float64 refinement and with the GMRES
+    refinement around it, each timed per step (assemble, factor, solve, currents) with its
+    status, refinement steps and error against stored oracle currents, on two workloads:
+    128 x 128 with 1024 input vectors (2.5-ohm segments), and the 512 x 512 crossbar with
+    32 of its stored-oracle input vectors (segment resistance r)."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    import workloads
+    cases = []
+    wl = workloads.c2()
+    path = os.path.join(ROOT, "tests", "golden", "c2_currents.npy")
+    cases.append(("c2_128x128_b1024_r2.5", wl.G, np.ascontiguousarray(wl.V), wl.geom,
+                  np.load(path) if os.path.exists(path) else None))
+    w3 = workloads.c3(r=r)
+    sub = workloads.c3_subset()[:32]
+    path = os.path.join(ROOT, "tests", "golden", f"c3_r{r:g}_currents.npy")
+    cases.append((f"c3_512x512_b32_r{r:g}", w3.G, np.ascontiguousarray(w3.V[sub]), w3.geom,
+                  np.load(path)[:32] if os.path.exists(path) else None))
+    out = {"ir_tol": 1e-12, "ir_max_iter": 30}
+    for name, Gh, Vh, g, ref in cases:
+        m, n = Gh.shape
+        B = Vh.shape[0]
+        G = torch.from_numpy(Gh).cuda()
+        V = torch.from_numpy(Vh).cuda()
+        I = torch.empty((B, n), dtype=torch.float64, device="cuda")
+        entry = {}
+        for prec in ("bf16_ir", "bf16_gmres"):
+            plan = xb.Plan(m, n, g.r_wl, g.r_bl, g.r_src, g.r_sense, prec, max_batch=B, ir_tol=1e-12,
+                           ir_max_iter=30)
+
+            def step():
+                plan.assemble(G)
+                plan.factor()
+                plan.solve_batch(V)
+                plan.currents(I)
+
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            st, info = plan.info()
+            err = None
+            if ref is not None:
+                Ih = I.cpu().numpy()
+                err = float((np.max(np.abs(Ih - ref), axis=1) / np.max(np.abs(ref), axis=1)).max())
+            plan.close()
+            entry[prec] = {"status": xb.status_string(st), "refinement_steps": int(info.ir_iters),
+                           "ms_per_step": ms, "solves_per_s": B / (ms * 1e-3), "max_rel_err_vs_oracle": err}
+            log(f"bf16 {name} {prec}: {xb.status_string(st)}, {info.ir_iters} refinement steps, {ms:.2f} ms/step, "
+                f"max rel err {err}")
+        out[name] = entry
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +289,8 @@ def main():
     ap.add_argument("--no-tiles", action="store_true", help="skip the heterogeneous tiles leg")
     ap.add_argument("--no-r-sweep", action="store_true",
                     help="skip the float64 and float32+refinement steps at the other segment resistances")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the bfloat16-factor legs (classical and GMRES refinement)")
     ap.add_argument("--copy-probe", type=float, default=None, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -522,6 +583,8 @@ def main():
                                "sweep_ms": per(tmr.sweep_ms, tmr.sweep_launches)}
             sweep[f"r{rr:g}"] = entry
         result["r_sweep"] = sweep
+    if not args.no_bf16:
+        result["bf16"] = run_bf16(max(2, args.steps))
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         cb = cpu_baseline(wl)

@@ -55,11 +55,23 @@ typedef enum {
 typedef enum {
     XBAR_FP64 = 0,      /* factor and substitution in float64 (the paper's method)         */
     XBAR_FP32_IR = 1,   /* factor and substitution in float32 on MFMA, refined in float64  */
-    XBAR_BF16_IR = 2    /* trial: as XBAR_FP32_IR, with the factor's inverse blocks rounded
+    XBAR_BF16_IR = 2,   /* trial: as XBAR_FP32_IR, with the factor's inverse blocks rounded
                            to bfloat16 values (8-bit significand, ties to even) before the
                            float32 sweeps; measures whether a bfloat16-accurate factor still
                            drives the float64 refinement (else XBAR_ERR_NO_CONVERGENCE) */
+    XBAR_BF16_GMRES_IR = 3 /* the XBAR_BF16_IR factor used as the preconditioner of a
+                           restarted flexible GMRES in float64 (GMRES-based iterative
+                           refinement, Carson and Higham): u_0 = M^-1 V c, then per outer
+                           step the float64 residual, XBAR_GMRES_RESTART Arnoldi steps on
+                           A M^-1 (M^-1: one float32 sweep of the factor; classical
+                           Gram-Schmidt applied twice), the least-squares solution, and the
+                           correction d.  A slab of input vectors stops when every vector's
+                           max |d| <= ir_tol max |u|; ir_max_iter counts outer steps, and
+                           ir_iters reports them.  Needs 2 XBAR_GMRES_RESTART + 4 float64
+                           panels of ceil(max_batch / 16) m 16 n_p values.              */
 } xbar_precision;
+
+#define XBAR_GMRES_RESTART 8
 
 typedef struct {
     int32_t m;          /* word lines (rows),   1 <= m                                  */

@@ -6,7 +6,7 @@ and the HIP stream.  All arithmetic runs in the library's HIP kernels.
 from __future__ import annotations
 
 from . import _lib
-from ._lib import (FACTOR_METHODS, PRECISIONS, XBAR_BF16_IR, XBAR_FP32_IR, XBAR_FP64,  # noqa: F401
+from ._lib import (FACTOR_METHODS, PRECISIONS, XBAR_BF16_GMRES_IR, XBAR_BF16_IR, XBAR_FP32_IR, XBAR_FP64,  # noqa: F401
                    Geometry, XbarError, status_string)
 
 __all__ = ["Plan", "PlanLanes", "TileBatch", "TileConfig", "solve", "tiles_currents", "Geometry", "XbarError",

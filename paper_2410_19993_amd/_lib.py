@@ -27,7 +27,8 @@ XBAR_ERR_INPUT = 7
 XBAR_FP64 = 0
 XBAR_FP32_IR = 1
 XBAR_BF16_IR = 2
-PRECISIONS = {"fp64": XBAR_FP64, "fp32_ir": XBAR_FP32_IR, "bf16_ir": XBAR_BF16_IR}
+XBAR_BF16_GMRES_IR = 3
+PRECISIONS = {"fp64": XBAR_FP64, "fp32_ir": XBAR_FP32_IR, "bf16_ir": XBAR_BF16_IR, "bf16_gmres": XBAR_BF16_GMRES_IR}
 
 XBAR_FACTOR_AUTO = 0
 XBAR_FACTOR_GJ = 1

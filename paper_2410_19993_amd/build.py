@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libxbar.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["xbar_api.hip", "condense.hip", "factor.hip", "ns.hip", "sweep.hip", "transfer.hip", "tiles.hip",
-           "surrogate.hip", "surrogate_mfma.hip", "diagnostics.hip", "tiles_plan.hip"]
+           "surrogate.hip", "surrogate_mfma.hip", "diagnostics.hip", "tiles_plan.hip", "gmres.hip"]
 ARCH = os.environ.get("XBAR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

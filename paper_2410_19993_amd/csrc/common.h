@@ -267,6 +267,8 @@ struct SweepArgs {
     int* slab_done;      // [nslab]
     int* slab_final;     // [nslab] which U buffer holds the final solution
     int* flags;
+    // tol < 0: the sweep only applies the factor (Uout = Uin + M^-1 R); it keeps no
+    // convergence state (dnorm, slab_done, slab_final and flags are not written)
     // batched crossbars of one shape (float64, currents only): `batch` crossbars of
     // `slabs_per` slabs each, crossbar t's H, c, V, Z and Iout at t times the size of one
     // crossbar's; workgroups are mapped so that a crossbar's slabs share an XCD (and its
@@ -289,6 +291,22 @@ struct ResidualArgs {
     const double* U;     // [nslab][m][16][n_p] current solution (float positions)
     void* R;             // [nslab][m][16][n_p] float residual
     const int* slab_done;
+    // Krylov refinement: Rd != nullptr writes the float64 result there instead of the
+    // float R; matvec = 1 writes the product A u of the condensed matrix (V not read)
+    // instead of the residual V c - A u
+    double* Rd = nullptr;
+    int matvec = 0;
+};
+
+// Krylov refinement (gmres.hip): restart length and the panel geometry its batched
+// vector kernels share.  A panel holds P = nslab m 16 n_p float64 values; reductions
+// run over nchunk chunks of rows_per_chunk rows.
+constexpr int kGmRestart = 8;              // XBAR_GMRES_RESTART
+struct GmPanel {
+    int m, n_p, nslab, nchunk, rows_per_chunk;
+    int64_t P;
+    int* slab_done;      // [nslab] converged slabs (skipped by every kernel)
+    int* slab_final;     // [nslab] set to 0 (the solution buffer) when a slab stops
 };
 
 struct RecoverArgs {
@@ -326,6 +344,21 @@ hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s);
+// Krylov refinement kernels (gmres.hip); X_i = X + i P
+hipError_t xbk_gm_dots(const xbk::GmPanel& g, const double* X, int nv, const double* w, double* part, double* out,
+                       int ld_out, bool add, bool sqrt_out, hipStream_t s);
+hipError_t xbk_gm_axpy(const xbk::GmPanel& g, const double* X, int nv, const double* coef, int ld_coef, double* w,
+                       hipStream_t s);
+hipError_t xbk_gm_scale(const xbk::GmPanel& g, const double* w, const double* sc, double* v, float* Rf,
+                        hipStream_t s);
+hipError_t xbk_gm_lsq(const xbk::GmPanel& g, const double* Hs, const double* beta, double* y, hipStream_t s);
+hipError_t xbk_gm_update(const xbk::GmPanel& g, const double* Z, const double* y, double* u, double* part, int B,
+                         double tol, int it, bool last, int* flags, hipStream_t s);
+hipError_t xbk_gm_currents(const xbk::GmPanel& g, int B, int n, double g_sense, const double* u, double* Iout,
+                           hipStream_t s);
+hipError_t xbk_gm_fill(double* x, int64_t count, double v, hipStream_t s);
+hipError_t xbk_gm_add(const xbk::GmPanel& g, int nv, const double* src, int ld_src, double* dst, int ld_dst,
+                      hipStream_t s);
 hipError_t xbk_launch_backward_error(const xbk::BackErrArgs& a, hipStream_t s);
 hipError_t xbk_launch_shift_diag(void* E, bool fp32, int m, int n, int n_p, double shift, hipStream_t s);
 hipError_t xbk_launch_reset_diag(unsigned long long* diag, int which, hipStream_t s);

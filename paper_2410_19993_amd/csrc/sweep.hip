@@ -759,7 +759,7 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
             x.put_panel(acc);
         }
     }
-    if (IR) x.decide(extra);
+    if (IR && a.tol >= 0.0) x.decide(extra);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,6 +894,7 @@ __device__ __forceinline__ void residual_walk(const ResidualArgs& a, unsigned ch
     const int64_t rs = 16 * (int64_t)n_p;
     const double* U = a.U + ((int64_t)slab * m * 16 + colg) * n_p;
     float* R = reinterpret_cast<float*>(a.R) + ((int64_t)slab * m * 16 + colg) * n_p;
+    double* Rd = a.Rd ? a.Rd + ((int64_t)slab * m * 16 + colg) * n_p : nullptr;
     double* w = wb + c * PL;
     const double* const src[5] = {a.fr, a.ip, a.Gc, a.c, a.q};
     const int ld[5] = {n, n, n, n_p, n};
@@ -916,7 +917,7 @@ __device__ __forceinline__ void residual_walk(const ResidualArgs& a, unsigned ch
             rw_load_row(U + (i + 1) * rs, n, s, un);
             rc.load(src, ld, i + 1, n);
         }
-        const double vb = b < a.B ? a.V[(int64_t)b * m + i] : 0.0;
+        const double vb = (b < a.B && !a.matvec) ? a.V[(int64_t)b * m + i] : 0.0;
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;
@@ -926,17 +927,28 @@ __device__ __forceinline__ void residual_walk(const ResidualArgs& a, unsigned ch
         tridiag_solve_masked<kRwLanes, kRwSeg, FULL>(w, cf, cf + PL, a.g_wl, n, s, lg, spare);
         wave_lds_fence();
         float* Ri = R + i * rs;
+        double* Rdi = Rd ? Rd + i * rs : nullptr;
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;
             if (FULL || j < n) {
                 const int pj = padj(j, lg);
-                const double r = cf[3 * PL + pj] * vb - (cf[4 * PL + pj] * uc[k] - cf[2 * PL + pj] * w[pj]) +
-                                 a.g_bl * (up[k] + un[k]);
-                Ri[j] = (float)r;
+                // A u = E_i u_i - g_bl (u_{i-1} + u_{i+1}); the residual is V c - A u
+                const double eu = cf[4 * PL + pj] * uc[k] - cf[2 * PL + pj] * w[pj];
+                const double r = a.matvec ? eu - a.g_bl * (up[k] + un[k])
+                                          : cf[3 * PL + pj] * vb - eu + a.g_bl * (up[k] + un[k]);
+                if (Rdi)
+                    Rdi[j] = r;
+                else
+                    Ri[j] = (float)r;
             }
         }
-        for (int j = n + s; j < n_p; j += kRwLanes) Ri[j] = 0.0f;      // padding stays zero
+        for (int j = n + s; j < n_p; j += kRwLanes) {                 // padding stays zero
+            if (Rdi)
+                Rdi[j] = 0.0;
+            else
+                Ri[j] = 0.0f;
+        }
         if (i + 1 < m) rc.store(cb + ((i + 1) & 1) * 5 * PL, PL, n, lg);
         __syncthreads();
 #pragma unroll

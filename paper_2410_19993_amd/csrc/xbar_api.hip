@@ -48,6 +48,17 @@ struct Buffers {
     int* slab_final = nullptr;               // [nslab]
     double* Vunit = nullptr;                 // [tr_rows][m]: unit inputs of xbar_transfer (plans
                                              // without the block form only)
+    // Krylov refinement (XBAR_BF16_GMRES_IR): Arnoldi basis v_0..v_k and preconditioned
+    // directions z_0..z_{k-1} (panels), a zero panel, reduction partials, the Hessenberg
+    // matrices [k+1][k][Bp], beta [Bp], y [k][Bp] and Gram-Schmidt coefficients [k+1][Bp]
+    double* gm_V = nullptr;
+    double* gm_Z = nullptr;
+    double* gm_zero = nullptr;
+    double* gm_part = nullptr;
+    double* gm_H = nullptr;
+    double* gm_beta = nullptr;
+    double* gm_y = nullptr;
+    double* gm_coef = nullptr;
 };
 
 __global__ void clear_slabs_kernel(int* done, double* dnorm, int nslab)
@@ -162,7 +173,8 @@ void free_all(xbar_plan p)
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
                    d.ns_Q[0], d.ns_Q[1], d.ns_Qt[0], d.ns_Qt[1], d.ns_P2[0], d.ns_P2[1],
                    d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
-                   d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final, d.Vunit};
+                   d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final, d.Vunit,
+                   d.gm_V, d.gm_Z, d.gm_zero, d.gm_part, d.gm_H, d.gm_beta, d.gm_y, d.gm_coef};
     for (void* x : all)
         if (x) (void)hipFree(x);
     d = Buffers{};
@@ -227,7 +239,8 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     if (g.m < 1 || g.n < 1 || g.n > XBAR_MAX_N) return XBAR_ERR_ARG;
     if (!finite_pos(g.r_wl) || !finite_pos(g.r_bl) || !finite_pos(g.r_src) || !finite_pos(g.r_sense))
         return XBAR_ERR_ARG;
-    if (prec != XBAR_FP64 && prec != XBAR_FP32_IR && prec != XBAR_BF16_IR) return XBAR_ERR_ARG;
+    if (prec != XBAR_FP64 && prec != XBAR_FP32_IR && prec != XBAR_BF16_IR && prec != XBAR_BF16_GMRES_IR)
+        return XBAR_ERR_ARG;
     if (max_batch < 1) return XBAR_ERR_ARG;
     if (!(std::isfinite(ir_tol) && ir_tol >= 0.0 && ir_tol < 1.0)) return XBAR_ERR_ARG;
     if (ir_max_iter < 0 || ir_max_iter > 100) return XBAR_ERR_ARG;
@@ -296,6 +309,19 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
         A((void**)&d.dnorm, (int64_t)p->nslab_max * 16 * 8);
         A((void**)&d.slab_done, (int64_t)p->nslab_max * 4);
         A((void**)&d.slab_final, (int64_t)p->nslab_max * 4);
+        if (prec == XBAR_BF16_GMRES_IR) {
+            constexpr int K = xbk::kGmRestart;
+            const int64_t Bp = 16 * (int64_t)p->nslab_max;
+            A((void**)&d.gm_V, (K + 1) * panel * 8);
+            A((void**)&d.gm_Z, K * panel * 8);
+            A((void**)&d.gm_zero, panel * 8);
+            A((void**)&d.gm_part, (int64_t)m * (K + 1) * Bp * 8);     // at most m chunks
+            A((void**)&d.gm_H, (int64_t)(K + 1) * K * Bp * 8);
+            A((void**)&d.gm_beta, Bp * 8);
+            A((void**)&d.gm_y, K * Bp * 8);
+            A((void**)&d.gm_coef, (K + 1) * Bp * 8);
+            if (st == XBAR_OK && xbk_gm_fill(d.gm_zero, panel, 0.0, p->stream) != hipSuccess) st = XBAR_ERR_DEVICE;
+        }
     }
     if (st != XBAR_OK) {
         free_all(p);
@@ -679,7 +705,7 @@ xbar_status xbar_factor(xbar_plan p)
                                (int)xbk::kErrConv);
         }
     }
-    if (p->prec == XBAR_BF16_IR) {
+    if (p->prec == XBAR_BF16_IR || p->prec == XBAR_BF16_GMRES_IR) {
         // the trial's factor: the float32 inverse blocks at bfloat16 precision
         const int64_t count = (int64_t)p->g.m * p->n_p * p->n_p;
         hipLaunchKernelGGL(round_bf16_kernel, dim3(2048), dim3(256), 0, p->stream, reinterpret_cast<float*>(p->d.H),
@@ -688,6 +714,83 @@ xbar_status xbar_factor(xbar_plan p)
     }
     if (p->timing && !p->t_factor.end(p->stream)) return XBAR_ERR_DEVICE;
     p->state = kFactored;
+    return XBAR_OK;
+}
+
+// Restarted flexible GMRES refinement of the condensed system (the kernels and the
+// method are described in gmres.hip): u_0 = M^-1 V c, then up to ir_max_iter outer
+// steps of k = kGmRestart Arnoldi steps each, with classical Gram-Schmidt applied
+// twice; every launch is queued without a host read-back.
+static_assert(xbk::kGmRestart == XBAR_GMRES_RESTART, "restart length of the header");
+
+xbar_status gmres_solve(xbar_plan p, xbk::SweepArgs s, xbk::ResidualArgs r, int B)
+{
+    Buffers& d = p->d;
+    constexpr int K = xbk::kGmRestart;
+    const int nslab = (B + 15) / 16, Bp = 16 * nslab, m = p->g.m;
+    xbk::GmPanel g{};
+    g.m = m;
+    g.n_p = p->n_p;
+    g.nslab = nslab;
+    const int want = std::max(1, 1024 / nslab);
+    g.nchunk = std::min(m, want);
+    g.rows_per_chunk = (m + g.nchunk - 1) / g.nchunk;
+    g.nchunk = (m + g.rows_per_chunk - 1) / g.rows_per_chunk;
+    g.P = (int64_t)nslab * m * 16 * p->n_p;
+    g.slab_done = d.slab_done;
+    g.slab_final = d.slab_final;
+    const int64_t P = g.P;
+    auto ok = [](hipError_t e) { return e == hipSuccess; };
+    auto sweep = [&](int iter, const double* uin, double* uout) {
+        s.iter = iter;
+        s.Uin = uin;
+        s.Uout = uout;
+        if (p->timing && !p->t_ir_sweep.begin(p->stream)) return false;
+        if (!ok(xbk_launch_sweep_ir(s, p->stream))) return false;
+        return !p->timing || p->t_ir_sweep.end(p->stream);
+    };
+    auto resid = [&](const double* u, double* out, int matvec) {
+        r.U = u;
+        r.Rd = out;
+        r.matvec = matvec;
+        if (p->timing && !p->t_residual.begin(p->stream)) return false;
+        if (!ok(xbk_launch_residual(r, p->stream))) return false;
+        return !p->timing || p->t_residual.end(p->stream);
+    };
+    s.max_iter = 1 << 20;
+    s.tol = -1.0;                        // the sweeps only apply the factor
+    s.R = d.R;
+    double* U = d.U[0];
+    if (!sweep(0, d.gm_zero, U)) return XBAR_ERR_DEVICE;
+    for (int it = 0; it < p->ir_max_iter; ++it) {
+        double* V0 = d.gm_V;
+        if (!resid(U, V0, 0)) return XBAR_ERR_DEVICE;
+        if (!ok(xbk_gm_dots(g, V0, 1, V0, d.gm_part, d.gm_beta, Bp, false, true, p->stream)) ||
+            !ok(xbk_gm_scale(g, V0, d.gm_beta, V0, reinterpret_cast<float*>(d.R), p->stream)) ||
+            !ok(xbk_gm_fill(d.gm_H, (int64_t)(K + 1) * K * Bp, 0.0, p->stream)))
+            return XBAR_ERR_DEVICE;
+        for (int j = 0; j < K; ++j) {
+            double* Zj = d.gm_Z + j * P;
+            double* W = d.gm_V + (j + 1) * P;
+            double* Hcol = d.gm_H + (int64_t)j * Bp;             // H[i][j] at Hcol + i K Bp
+            if (!sweep(1, d.gm_zero, Zj) || !resid(Zj, W, 1)) return XBAR_ERR_DEVICE;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (!ok(xbk_gm_dots(g, d.gm_V, j + 1, W, d.gm_part, d.gm_coef, Bp, false, false, p->stream)) ||
+                    !ok(xbk_gm_axpy(g, d.gm_V, j + 1, d.gm_coef, Bp, W, p->stream)) ||
+                    !ok(xbk_gm_add(g, j + 1, d.gm_coef, Bp, Hcol, K * Bp, p->stream)))
+                    return XBAR_ERR_DEVICE;
+            }
+            double* hsub = Hcol + (int64_t)(j + 1) * K * Bp;
+            if (!ok(xbk_gm_dots(g, W, 1, W, d.gm_part, hsub, Bp, false, true, p->stream)) ||
+                !ok(xbk_gm_scale(g, W, hsub, W, j + 1 < K ? reinterpret_cast<float*>(d.R) : nullptr, p->stream)))
+                return XBAR_ERR_DEVICE;
+        }
+        if (!ok(xbk_gm_lsq(g, d.gm_H, d.gm_beta, d.gm_y, p->stream)) ||
+            !ok(xbk_gm_update(g, d.gm_Z, d.gm_y, U, d.gm_part, B, p->ir_tol, it, it + 1 == p->ir_max_iter,
+                              d.flags, p->stream)))
+            return XBAR_ERR_DEVICE;
+    }
+    if (!ok(xbk_gm_currents(g, B, p->g.n, 1.0 / p->g.r_sense, U, d.Iout, p->stream))) return XBAR_ERR_DEVICE;
     return XBAR_OK;
 }
 
@@ -750,6 +853,11 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         r.Gc = p->d.Gc;
         r.R = p->d.R;
         r.slab_done = p->d.slab_done;
+        if (p->prec == XBAR_BF16_GMRES_IR) {
+            const xbar_status gs = gmres_solve(p, s, r, B);
+            if (gs != XBAR_OK) return gs;
+            s.max_iter = 0;                  // the loop below is the classical refinement
+        }
         for (int it = 0; it < s.max_iter; ++it) {
             s.iter = it;
             s.Uin = p->d.U[it & 1];

@@ -68,7 +68,7 @@ def test_create_rejects_bad_geometry(field, value):
 
 
 @pytest.mark.parametrize("prec,max_batch,tol,iters", [
-    (7, 8, 0.0, 0), (-1, 8, 0.0, 0), (3, 8, 0.0, 0), (0, 0, 0.0, 0), (0, -5, 0.0, 0),
+    (7, 8, 0.0, 0), (-1, 8, 0.0, 0), (4, 8, 0.0, 0), (0, 0, 0.0, 0), (0, -5, 0.0, 0),
     (0, 8, -1.0, 0), (0, 8, math.nan, 0), (0, 8, 1.5, 0), (0, 8, 0.0, -1), (0, 8, 0.0, 1000)])
 def test_create_rejects_bad_options(prec, max_batch, tol, iters):
     st, plan = _create(_lib.Geometry(**GOOD), prec, max_batch, tol, iters)
