@@ -277,6 +277,11 @@ struct SweepArgs {
     int slab = 0;
     const int* tile_bad = nullptr;   // batches: crossbars flagged bad get NaN currents
     int unit = 0;                    // 1: input vector b is the unit vector e_b (V is not read)
+    // 1: reciprocal ordering (a plan of an m' x n' crossbar with n' > m', solved as its
+    // n' x m' reciprocal): the inputs V [B][n] drive the bit-line terminations of row
+    // m-1, so the right-hand side is g_sense V[b][n-1-k] at row m-1 and zero elsewhere,
+    // and the word lines have no sources
+    int term = 0;
 };
 
 struct ResidualArgs {
@@ -296,6 +301,8 @@ struct ResidualArgs {
     // instead of the residual V c - A u
     double* Rd = nullptr;
     int matvec = 0;
+    int term = 0;        // reciprocal ordering (see SweepArgs::term); V is [B][n]
+    double g_sense = 0.0;
 };
 
 // Krylov refinement (gmres.hip): restart length and the panel geometry its batched
@@ -320,6 +327,7 @@ struct RecoverArgs {
     const double* Gc;
     double g_wl;
     double* node_v;      // [B][2mn]
+    int term = 0;        // reciprocal ordering: no word-line sources
 };
 
 // Normwise backward error of node voltages (diagnostics.hip).
@@ -330,6 +338,7 @@ struct BackErrArgs {
     const double* V;          // [B][m]
     const double* node_v;     // [B][2mn], paper order
     unsigned long long* diag; // [kNumDiag]: kDiagBackErr receives the batch maximum
+    int rev = 0;              // G is the reciprocal crossbar's [n][m]: G[i][j] at (n-1-j) m + m-1-i
 };
 
 }  // namespace xbk
@@ -344,6 +353,7 @@ hipError_t xbk_launch_sweep(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_recover(const xbk::RecoverArgs& a, hipStream_t s);
 hipError_t xbk_launch_sweep_ir(const xbk::SweepArgs& a, hipStream_t s);
 hipError_t xbk_launch_residual(const xbk::ResidualArgs& a, hipStream_t s);
+int xbk_backward_error_max_n();     // widest crossbar the backward-error kernel measures
 // Krylov refinement kernels (gmres.hip); X_i = X + i P
 hipError_t xbk_gm_dots(const xbk::GmPanel& g, const double* X, int nv, const double* w, double* part, double* out,
                        int ld_out, bool add, bool sqrt_out, hipStream_t s);

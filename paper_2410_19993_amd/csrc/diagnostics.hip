@@ -16,6 +16,10 @@
 //
 // shift_diag_kernel: subtracts a shift from every diagonal entry of the condensed
 // blocks E_i (a test hook that makes the factor meet non-positive pivots).
+//
+// For a plan in reciprocal ordering the kernel runs on the crossbar as given (m, n,
+// resistances, V and node voltages in its order), reading its conductances from the
+// reciprocal crossbar's array.
 #include <algorithm>
 
 #include "common.h"
@@ -51,7 +55,7 @@ __global__ __launch_bounds__(kBeThreads) void backward_error_kernel(BackErrArgs 
                     const d2v x = *reinterpret_cast<const d2v*>(v + 2 * ((int64_t)i * n + j));
                     w0[c] = x[0];
                     u0[c] = x[1];
-                    G0[c] = a.G[(int64_t)i * n + j];
+                    G0[c] = a.rev ? a.G[(int64_t)(n - 1 - j) * m + (m - 1 - i)] : a.G[(int64_t)i * n + j];
                     wr[j] = x[0];
                     keep(vmax, fabs(x[0]));
                     keep(vmax, fabs(x[1]));
@@ -160,3 +164,5 @@ hipError_t xbk_launch_reset_diag(unsigned long long* diag, int which, hipStream_
     hipLaunchKernelGGL(xbk::reset_diag_kernel, dim3(1), dim3(64), 0, s, diag, which);
     return hipGetLastError();
 }
+
+int xbk_backward_error_max_n() { return xbk::kBeCols * xbk::kBeThreads; }

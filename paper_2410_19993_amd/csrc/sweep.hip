@@ -210,6 +210,16 @@ struct SweepCtx {
             for (int t = 0; t < TW; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) f[t][v] = row_of(t, v) < a.n ? Ri[o + 16 * t + v] : (T)0;
+        } else if (a.term) {
+            // reciprocal ordering: g_sense V[b][n-1-k] at the last row only
+            const double* Vb = a.V + (int64_t)b * a.n;
+#pragma unroll
+            for (int t = 0; t < TW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int k = row_of(t, v);
+                    f[t][v] = (T)((bval && i == a.m - 1 && k < a.n) ? a.g_sense * Vb[a.n - 1 - k] : 0.0);
+                }
         } else {
             const double vb = vin(i);
             const double* ci = a.c + (int64_t)i * n_p;         // zero on the padding
@@ -470,7 +480,7 @@ struct SweepHelper {
     __device__ __forceinline__ void stage_load(int i) {
         const int64_t o = (int64_t)i * a.n;
         const int bb = 16 * a.slab + h * VPW + l / LR;
-        vnext = (bb < a.B && !a.unit) ? a.V[(int64_t)bb * a.m + i] : 0.0;
+        vnext = (bb < a.B && !a.unit && !a.term) ? a.V[(int64_t)bb * a.m + i] : 0.0;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int jj = min(h * 64 + l + c * HT, a.n - 1);
@@ -917,7 +927,9 @@ __device__ __forceinline__ void residual_walk(const ResidualArgs& a, unsigned ch
             rw_load_row(U + (i + 1) * rs, n, s, un);
             rc.load(src, ld, i + 1, n);
         }
-        const double vb = (b < a.B && !a.matvec) ? a.V[(int64_t)b * m + i] : 0.0;
+        const double vb = (b < a.B && !a.matvec && !a.term) ? a.V[(int64_t)b * m + i] : 0.0;
+        // reciprocal ordering: the terminations' right-hand side at the last row
+        const double* Vt = (a.term && !a.matvec && b < a.B && i == m - 1) ? a.V + (int64_t)b * n : nullptr;
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;
@@ -935,8 +947,8 @@ __device__ __forceinline__ void residual_walk(const ResidualArgs& a, unsigned ch
                 const int pj = padj(j, lg);
                 // A u = E_i u_i - g_bl (u_{i-1} + u_{i+1}); the residual is V c - A u
                 const double eu = cf[4 * PL + pj] * uc[k] - cf[2 * PL + pj] * w[pj];
-                const double r = a.matvec ? eu - a.g_bl * (up[k] + un[k])
-                                          : cf[3 * PL + pj] * vb - eu + a.g_bl * (up[k] + un[k]);
+                const double rhs = Vt ? a.g_sense * Vt[n - 1 - j] : cf[3 * PL + pj] * vb;
+                const double r = a.matvec ? eu - a.g_bl * (up[k] + un[k]) : rhs - eu + a.g_bl * (up[k] + un[k]);
                 if (Rdi)
                     Rdi[j] = r;
                 else
@@ -1005,7 +1017,7 @@ __device__ __forceinline__ void recover_walk(const RecoverArgs& a, unsigned char
             rw_load_row(U + (i + 1) * rs, n, s, un);
             rc.load(src, ld, i + 1, n);
         }
-        const double vb = bval ? a.V[(int64_t)b * m + i] : 0.0;
+        const double vb = (bval && !a.term) ? a.V[(int64_t)b * m + i] : 0.0;
 #pragma unroll
         for (int k = 0; k < kRwJ; ++k) {
             const int j = s + kRwLanes * k;

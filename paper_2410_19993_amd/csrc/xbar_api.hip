@@ -59,6 +59,11 @@ struct Buffers {
     double* gm_beta = nullptr;
     double* gm_y = nullptr;
     double* gm_coef = nullptr;
+    // reciprocal ordering: the reciprocal crossbar's conductances [m][n] and its node
+    // voltages [max_batch][2mn] (always recovered: the given crossbar's currents are the
+    // reciprocal's first word-line nodes)
+    double* Grev = nullptr;
+    double* nv_rev = nullptr;
 };
 
 __global__ void clear_slabs_kernel(int* done, double* dnorm, int nslab)
@@ -120,7 +125,13 @@ struct PhaseTimer {
 };
 
 struct xbar_plan_s {
+    // g: the crossbar the solver works on; og: the crossbar as given.  They differ in
+    // reciprocal ordering (og.n > og.m): then g is og rotated by 180 degrees and
+    // transposed (g.m = og.n, g.n = og.m, word and bit lines exchanged, r_src and
+    // r_sense exchanged), so that the row blocks have the smaller size og.m.
     xbar_geometry g{};
+    xbar_geometry og{};
+    bool rev = false;
     xbar_precision prec = XBAR_FP64;
     int32_t max_batch = 0;
     double ir_tol = 0;
@@ -174,7 +185,8 @@ void free_all(xbar_plan p)
                    d.ns_Q[0], d.ns_Q[1], d.ns_Qt[0], d.ns_Qt[1], d.ns_P2[0], d.ns_P2[1],
                    d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
                    d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final, d.Vunit,
-                   d.gm_V, d.gm_Z, d.gm_zero, d.gm_part, d.gm_H, d.gm_beta, d.gm_y, d.gm_coef};
+                   d.gm_V, d.gm_Z, d.gm_zero, d.gm_part, d.gm_H, d.gm_beta, d.gm_y, d.gm_coef,
+                   d.Grev, d.nv_rev};
     for (void* x : all)
         if (x) (void)hipFree(x);
     d = Buffers{};
@@ -187,7 +199,46 @@ bool set_device(xbar_plan p) { return hipSetDevice(p->device) == hipSuccess; }
 // unit inputs and hold a staging buffer for them.
 bool transfer_blocks_fit(xbar_plan p)
 {
-    return p->prec == XBAR_FP64 && (int64_t)p->nslab_max * 16 >= p->n_p;
+    return !p->rev && p->prec == XBAR_FP64 && (int64_t)p->nslab_max * 16 >= p->n_p;
+}
+
+// Reciprocal crossbar of the given m x n one (n > m): Gr [n][m], Gr[i][j] = G[m-1-j][n-1-i].
+__global__ void rev_conductances_kernel(const double* __restrict__ G, int m, int n, double* __restrict__ Gr)
+{
+    const int64_t total = (int64_t)m * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / m, j = e - i * m;
+        Gr[e] = G[(m - 1 - j) * (int64_t)n + (n - 1 - i)];
+    }
+}
+
+// Outputs of the given crossbar (m x n, n > m) from the reciprocal's node voltages
+// nr [B][2 n m]: column j's current flows through the sense resistor at BL(m-1, j),
+// which is the reciprocal's source resistor at its WL(n-1-j, 0); node WL(i, j) of the
+// given crossbar is the reciprocal's BL(n-1-j, m-1-i) and BL(i, j) its WL(n-1-j, m-1-i).
+// I [B][n]; node_v [B][2mn] (paper order) when not null.
+__global__ void rev_outputs_kernel(const double* __restrict__ nr, int B, int m, int n, double g_sense,
+                                   double* __restrict__ I, double* __restrict__ node_v)
+{
+    const int64_t per = (int64_t)m * n;
+    const int64_t total = (int64_t)B * per;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / per, r = e - b * per;
+        const int i = (int)(r / n), j = (int)(r - (int64_t)i * n);
+        const int64_t rr = (int64_t)(n - 1 - j) * m + (m - 1 - i);          // reciprocal's (row, column)
+        const double* x = nr + b * 2 * per;
+        if (node_v) {
+            node_v[b * 2 * per + 2 * r] = x[2 * rr + 1];
+            node_v[b * 2 * per + 2 * r + 1] = x[2 * rr];
+        }
+        if (i == m - 1) I[b * n + j] = g_sense * x[2 * rr];       // reciprocal WL(n-1-j, 0)
+    }
+}
+
+unsigned grid_for(int64_t count)
+{
+    const int64_t blocks = (count + 255) / 256;
+    return (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
 }
 
 void destroy_side(xbar_plan p)
@@ -235,10 +286,22 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
 {
     if (out == nullptr || geom == nullptr) return XBAR_ERR_ARG;
     *out = nullptr;
-    const xbar_geometry g = *geom;
-    if (g.m < 1 || g.n < 1 || g.n > XBAR_MAX_N) return XBAR_ERR_ARG;
-    if (!finite_pos(g.r_wl) || !finite_pos(g.r_bl) || !finite_pos(g.r_src) || !finite_pos(g.r_sense))
+    const xbar_geometry og = *geom;
+    if (og.m < 1 || og.n < 1 || std::min(og.m, og.n) > XBAR_MAX_N) return XBAR_ERR_ARG;
+    if (!finite_pos(og.r_wl) || !finite_pos(og.r_bl) || !finite_pos(og.r_src) || !finite_pos(og.r_sense))
         return XBAR_ERR_ARG;
+    // row blocks of the smaller side: a crossbar with more columns than rows is solved
+    // as its reciprocal (rotated by 180 degrees and transposed)
+    const bool rev = og.n > og.m;
+    xbar_geometry g = og;
+    if (rev) {
+        g.m = og.n;
+        g.n = og.m;
+        g.r_wl = og.r_bl;
+        g.r_bl = og.r_wl;
+        g.r_src = og.r_sense;
+        g.r_sense = og.r_src;
+    }
     if (prec != XBAR_FP64 && prec != XBAR_FP32_IR && prec != XBAR_BF16_IR && prec != XBAR_BF16_GMRES_IR)
         return XBAR_ERR_ARG;
     if (max_batch < 1) return XBAR_ERR_ARG;
@@ -256,6 +319,8 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     xbar_plan p = new (std::nothrow) xbar_plan_s;
     if (!p) return XBAR_ERR_ALLOC;
     p->g = g;
+    p->og = og;
+    p->rev = rev;
     p->prec = prec;
     p->max_batch = max_batch;
     p->ir_tol = (ir_tol == 0.0) ? 1e-12 : ir_tol;
@@ -265,7 +330,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     p->n_p = 64 * ((g.n + 63) / 64);
     p->nb = p->n_p / 64;
     p->nslab_max = (max_batch + 15) / 16;
-    p->tr_rows = max_batch < g.m ? max_batch : g.m;
+    p->tr_rows = max_batch < og.m ? max_batch : og.m;
 
     const int64_t m = g.m, n = g.n, n_p = p->n_p, es = (int64_t)p->elem();
     Buffers& d = p->d;
@@ -285,7 +350,7 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
             A(&d.P[c][k], 64 * 64 * es);
         }
     A(&d.Z, (int64_t)p->nslab_max * m * 16 * n_p * es);
-    A((void**)&d.Iout, (int64_t)max_batch * n * 8);
+    A((void**)&d.Iout, (int64_t)max_batch * og.n * 8);
     A((void**)&d.flags, xbk::kNumFlags * sizeof(int));
     A((void**)&d.diag, xbk::kNumDiag * sizeof(unsigned long long));
     A((void**)&d.sink, 128 * sizeof(double));
@@ -300,7 +365,11 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t 
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
     A((void**)&d.ns_state, 6 * sizeof(xbk::NSState));
-    if (!transfer_blocks_fit(p)) A((void**)&d.Vunit, (int64_t)p->tr_rows * m * 8);
+    if (!transfer_blocks_fit(p)) A((void**)&d.Vunit, (int64_t)p->tr_rows * og.m * 8);
+    if (rev) {
+        A((void**)&d.Grev, m * n * 8);
+        A((void**)&d.nv_rev, (int64_t)max_batch * 2 * m * n * 8);
+    }
     if (prec != XBAR_FP64) {
         const int64_t panel = (int64_t)p->nslab_max * m * 16 * n_p;
         A((void**)&d.U[0], panel * 8);
@@ -351,6 +420,12 @@ xbar_status xbar_assemble(xbar_plan p, const double* G)
     if (xbk_launch_reset_diag(p->d.diag, 3, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
     p->backerr_valid = false;
     if (p->timing && !p->t_condense.begin(p->stream)) return XBAR_ERR_DEVICE;
+    if (p->rev) {
+        hipLaunchKernelGGL(rev_conductances_kernel, dim3(grid_for((int64_t)p->og.m * p->og.n)), dim3(256), 0,
+                           p->stream, G, p->og.m, p->og.n, p->d.Grev);
+        if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
+        G = p->d.Grev;
+    }
     if (condense(p, G) != hipSuccess) return XBAR_ERR_DEVICE;
     if (p->timing && !p->t_condense.end(p->stream)) return XBAR_ERR_DEVICE;
     p->state = kAssembled;
@@ -587,7 +662,7 @@ bool overlaps(const void* a, int64_t a_bytes, const void* b, int64_t b_bytes)
 // T from the m unit input vectors, solved with the plan's factorization (any plan).
 xbar_status transfer_by_unit_solves(xbar_plan p, double* T)
 {
-    const int m = p->g.m, n = p->g.n;
+    const int m = p->og.m, n = p->og.n;                  // the crossbar as given
     const bool timing = p->timing;
     p->timing = false;                     // the unit solves are not counted as sweeps
     xbar_status st = XBAR_OK;
@@ -817,7 +892,11 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
     s.flags = p->d.flags;
     s.sink = p->d.sink;
     const bool ir = p->prec != XBAR_FP64;
-    s.node_v = ir ? nullptr : node_v;     // float64: recovery fused into the back sweep
+    // reciprocal ordering: the inputs drive the terminations, and the node voltages are
+    // always recovered (into the plan's buffer) for the given crossbar's currents
+    double* nv_solve = p->rev ? p->d.nv_rev : node_v;
+    s.term = p->rev ? 1 : 0;
+    s.node_v = ir ? nullptr : nv_solve;   // float64: recovery fused into the back sweep
     s.Gc = p->d.Gc;
     s.fr = p->d.fr;
     s.ip = p->d.ip;
@@ -853,6 +932,8 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         r.Gc = p->d.Gc;
         r.R = p->d.R;
         r.slab_done = p->d.slab_done;
+        r.term = s.term;
+        r.g_sense = 1.0 / p->g.r_sense;
         if (p->prec == XBAR_BF16_GMRES_IR) {
             const xbar_status gs = gmres_solve(p, s, r, B);
             if (gs != XBAR_OK) return gs;
@@ -874,7 +955,7 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         }
     }
     if (p->timing && !p->t_sweep.end(p->stream)) return XBAR_ERR_DEVICE;
-    if (node_v != nullptr && ir) {
+    if (nv_solve != nullptr && ir) {
         xbk::RecoverArgs r{};
         r.m = p->g.m;
         r.n = p->g.n;
@@ -890,21 +971,31 @@ xbar_status xbar_solve_batch(xbar_plan p, const double* V, int32_t B, double* no
         r.fr = p->d.fr;
         r.ip = p->d.ip;
         r.Gc = p->d.Gc;
-        r.node_v = node_v;
+        r.node_v = nv_solve;
+        r.term = s.term;
         if (p->timing && !p->t_recover.begin(p->stream)) return XBAR_ERR_DEVICE;
         if (xbk_launch_recover(r, p->stream) != hipSuccess) return XBAR_ERR_DEVICE;
         if (p->timing && !p->t_recover.end(p->stream)) return XBAR_ERR_DEVICE;
     }
+    if (p->rev) {
+        // the given crossbar's currents (and node voltages) from the reciprocal's
+        hipLaunchKernelGGL(rev_outputs_kernel, dim3(grid_for((int64_t)B * p->og.m * p->og.n)), dim3(256), 0,
+                           p->stream, p->d.nv_rev, B, p->og.m, p->og.n, 1.0 / p->og.r_sense, p->d.Iout, node_v);
+        if (hipGetLastError() != hipSuccess) return XBAR_ERR_DEVICE;
+    }
     p->backerr_valid = false;
-    if (p->diagnostics && node_v != nullptr) {
+    if (p->diagnostics && node_v != nullptr && p->og.n <= xbk_backward_error_max_n()) {
+        // on the crossbar as given (reciprocal ordering: its conductances read through
+        // the reciprocal's array)
         xbk::BackErrArgs be{};
-        be.m = p->g.m;
-        be.n = p->g.n;
+        be.m = p->og.m;
+        be.n = p->og.n;
         be.B = B;
-        be.g_wl = 1.0 / p->g.r_wl;
-        be.g_bl = 1.0 / p->g.r_bl;
-        be.g_src = 1.0 / p->g.r_src;
-        be.g_sense = 1.0 / p->g.r_sense;
+        be.g_wl = 1.0 / p->og.r_wl;
+        be.g_bl = 1.0 / p->og.r_bl;
+        be.g_src = 1.0 / p->og.r_src;
+        be.g_sense = 1.0 / p->og.r_sense;
+        be.rev = p->rev ? 1 : 0;
         be.G = p->d.Gc;
         be.V = V;
         be.node_v = node_v;
@@ -924,7 +1015,7 @@ xbar_status xbar_currents(xbar_plan p, double* I)
     if (p == nullptr || I == nullptr) return XBAR_ERR_ARG;
     if (p->state != kSolved) return XBAR_ERR_STATE;
     if (!set_device(p)) return XBAR_ERR_DEVICE;
-    const size_t bytes = (size_t)p->last_B * p->g.n * sizeof(double);
+    const size_t bytes = (size_t)p->last_B * p->og.n * sizeof(double);
     if (hipMemcpyAsync(I, p->d.Iout, bytes, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
         return XBAR_ERR_DEVICE;
     return XBAR_OK;
@@ -945,7 +1036,7 @@ xbar_status xbar_transfer(xbar_plan p, double* T)
 xbar_status xbar_transfer_apply(xbar_plan p, const double* T, const double* V, int32_t B, double* I)
 {
     if (p == nullptr || T == nullptr || V == nullptr || I == nullptr || B < 1) return XBAR_ERR_ARG;
-    const int64_t m = p->g.m, n = p->g.n;
+    const int64_t m = p->og.m, n = p->og.n;
     const int64_t i_bytes = (int64_t)B * n * 8;
     if (overlaps(I, i_bytes, V, (int64_t)B * m * 8) || overlaps(I, i_bytes, T, m * n * 8))
         return XBAR_ERR_ARG;

@@ -7,6 +7,7 @@ seeded workloads of ``workloads/``; nothing is read from the GPU library.
     python tests/golden/make_golden.py c3          # 512x512, seeded 256-vector subset, r in {1, 2.5, 5}
     python tests/golden/make_golden.py c4          # heterogeneous tiles: the first tile of each of
                                                    # the 16 (m_t, n_t) classes, all 256 vectors
+    python tests/golden/make_golden.py rev         # a 32 x 700 crossbar (more columns than rows)
 
 Outputs (float64 .npy/.npz next to this file):
 
@@ -17,6 +18,9 @@ Outputs (float64 .npy/.npz next to this file):
 * ``c4_class_currents.npz``      per (m_t, n_t) class: the index of the class's first tile
                                  in workloads.c4() (``t{m}x{n}``) and its currents
                                  [256][n_t] (``I{m}x{n}``)
+* ``rev_32x700_b3.npz``           a 32 x 700 crossbar (workloads.random_crossbar(32, 700, 3, 41),
+                                 2.5-ohm segments): currents [3][700] (``I``) and node
+                                 voltages [3][44800] (``v``)
 * ``manifest.json``              oracle diagnostics and timings per file
 """
 from __future__ import annotations
@@ -92,8 +96,18 @@ def make_c4():
                                                "vectors": 256, "refine": 2, "classes": info})
 
 
+def make_rev():
+    wl = workloads.random_crossbar(32, 700, 3, 41)
+    t = time.time()
+    res = oracle.solve_workload(wl)
+    np.savez(os.path.join(HERE, "rev_32x700_b3.npz"), I=res.currents, v=res.node_v)
+    _manifest_update("rev_32x700_b3.npz", {
+        "workload": wl.name, "refine": 2, "seconds": time.time() - t, "residual_inf_A": res.residual_inf,
+        "corrections": res.correction_norms, "min_pivot": res.min_pivot})
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c2", "c3", "c4"]
+    which = sys.argv[1:] or ["c2", "c3", "c4", "rev"]
     if "c2" in which:
         make_c2()
     if "c3" in which:
@@ -101,3 +115,5 @@ if __name__ == "__main__":
         make_c3(rs)
     if "c4" in which:
         make_c4()
+    if "rev" in which:
+        make_rev()

@@ -58,11 +58,20 @@ GOOD = dict(m=4, n=4, r_wl=1.0, r_bl=1.0, r_src=50.0, r_sense=50.0)
 
 
 @pytest.mark.parametrize("field,value", [
-    ("m", 0), ("n", 0), ("m", -3), ("n", 513), ("r_wl", 0.0), ("r_bl", -1.0),
+    ("m", 0), ("n", 0), ("m", -3), ("r_wl", 0.0), ("r_bl", -1.0),
     ("r_src", math.inf), ("r_sense", math.nan), ("r_wl", math.nan)])
 def test_create_rejects_bad_geometry(field, value):
     kw = dict(GOOD)
     kw[field] = value
+    st, plan = _create(_lib.Geometry(**kw))
+    assert st == _lib.XBAR_ERR_ARG and not plan.value
+
+
+@pytest.mark.parametrize("m,n", [(513, 513), (600, 1000), (1000, 600)])
+def test_create_rejects_both_sides_above_the_block_limit(m, n):
+    """Row blocks take the smaller side, which must be <= XBAR_MAX_N (512); one side
+    alone may be longer (reciprocal ordering when the columns are)."""
+    kw = dict(GOOD, m=m, n=n)
     st, plan = _create(_lib.Geometry(**kw))
     assert st == _lib.XBAR_ERR_ARG and not plan.value
 

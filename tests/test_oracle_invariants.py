@@ -91,6 +91,30 @@ def test_reciprocity():
     np.testing.assert_allclose(E, E.T, rtol=1e-10, atol=0)
 
 
+@pytest.mark.parametrize("m,n", [(4, 7), (1, 5), (3, 3), (6, 2)])
+def test_turned_crossbar_is_the_reciprocal_two_port(m, n):
+    """The crossbar turned by 180 degrees and transposed (G'[i][j] = G[m-1-j][n-1-i], word
+    and bit lines exchanged, so r_wl' = r_bl, r_bl' = r_wl, and the source and sense
+    resistors exchanged) carries, by reciprocity of the passive network, the transfer
+    T'[n-1-j][m-1-i] = T[i][j] between the same pair of terminals.  This is the relabelling
+    that lets a wide crossbar be solved with row blocks of its smaller side."""
+    rng = np.random.default_rng(100 + 10 * m + n)
+    G = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (m, n)))
+    r_wl, r_bl, r_src, r_sense = 2.0, 3.5, 40.0, 60.0
+    T = oracle.solve(G, np.eye(m), r_wl, r_bl, r_src, r_sense).currents
+    Gt = np.empty((n, m))
+    for i in range(n):
+        for j in range(m):
+            Gt[i, j] = G[m - 1 - j, n - 1 - i]
+    Tt = oracle.solve(Gt, np.eye(n), r_bl, r_wl, r_sense, r_src).currents
+    for i in range(m):
+        for j in range(n):
+            assert abs(Tt[n - 1 - j, m - 1 - i] - T[i, j]) <= 1e-12 * abs(T[i, j])
+    # a wrong relabelling (resistances not exchanged) breaks it
+    Tw = oracle.solve(Gt, np.eye(n), r_wl, r_bl, r_src, r_sense).currents
+    assert max(abs(Tw[n - 1 - j, m - 1 - i] - T[i, j]) / T[i, j] for i in range(m) for j in range(n)) > 1e-6
+
+
 @pytest.mark.parametrize("m,n,r", CASES)
 def test_transfer_matrix_superposition(m, n, r):
     """Linear network: each vector's currents are its voltages times the currents per unit
