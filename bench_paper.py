@@ -15,6 +15,10 @@ Three tables, printed as markdown (and one JSON line per measurement on stderr):
 3. Batch processing (Sec. III.D): n x n crossbars with batches of 1, 2, 10, 100 and
    1000 input vectors: decomposition time (assemble + factor) against solve time
    (substitution + currents), from HIP events on the plan stream.
+4. Block ordering (Sec. III.B, bandwidth): m x n and n x m pairs (32 x 256, 128 x 512,
+   32 x 700) with row blocks along the word lines ("rows") and of the smaller side
+   ("smaller": a wide crossbar solved as its reciprocal), one input vector with node
+   voltages, the block size each plan used, and which one the default ("auto") picks.
 
 Inputs are seeded and synthetic: G log-uniform on [1e-6, 1e-4] S, V uniform on
 [0, 0.5] V, and the paper's model of 5-ohm wire segments, with the source and
@@ -149,6 +153,36 @@ def main():
             sol = (tm.sweep_ms + tm.recover_ms) / args.reps
             log({"table": "batch", "n": n, "B": B, "decomposition_ms": dec, "solve_ms": sol})
             print(f"| {n} x {n} | {B} | {dec:.3f} | {sol:.3f} | {100 * sol / (dec + sol):.0f}% |")
+
+    # 4. block ordering of wide and tall crossbars
+    print("\n## Block ordering, one input vector with node voltages (ms, mean of %d)\n" % args.reps)
+    print("| m x n | ordering | block | ms | auto picks |")
+    print("|---|---|---:|---:|---|")
+    pairs = [(32, 256), (256, 32), (128, 512), (512, 128), (32, 700), (700, 32)]
+    if args.quick:
+        pairs = pairs[:2]
+    for (m, n) in pairs:
+        G, V = inputs(m, n, 1, 13 * m + n)
+        Gd, Vd = torch.from_numpy(G).to(dev), torch.from_numpy(V).to(dev)
+        nv = torch.empty((1, 2 * m * n), dtype=torch.float64, device=dev)
+        orders = ["rows", "smaller"] if n > m and n <= 512 else (["smaller"] if n > m else ["rows"])
+        with xb.Plan(m, n, R, R, R, R, "fp64", max_batch=1) as p:
+            auto_block = p.info()[1].block
+        for order in orders:
+            with xb.Plan(m, n, R, R, R, R, "fp64", max_batch=1, ordering=order) as p:
+                run_plan(p, Gd, Vd, nv)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(args.reps):
+                    t0 = time.perf_counter()
+                    run_plan(p, Gd, Vd, nv)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                p.check()
+                block = p.info()[1].block
+            ms = 1e3 * float(np.mean(ts))
+            log({"table": "ordering", "m": m, "n": n, "ordering": order, "block": block, "ms": ms})
+            print(f"| {m} x {n} | {order} | {block} | {ms:.2f} | {'yes' if block == auto_block else ''} |")
 
 
 if __name__ == "__main__":

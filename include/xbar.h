@@ -135,6 +135,31 @@ xbar_status xbar_create(const xbar_geometry* geom, xbar_precision p, int32_t max
                         double ir_tol, int32_t ir_max_iter, void* hip_stream, xbar_plan* out);
 
 /*
+ * Order of the block rows (Sec. III.B: the matrix bandwidth follows the side the
+ * nodes are numbered along).  ROWS: one row block per word line, of size n (the
+ * ordering of Sec. II.B; needs n <= XBAR_MAX_N).  SMALLER: row blocks of size
+ * min(m, n); when n > m the plan solves the reciprocal crossbar, turned by 180
+ * degrees and transposed (word and bit lines exchanged, r_src and r_sense
+ * exchanged), whose inputs drive its bit-line terminations; currents, node voltages
+ * (in the given crossbar's order), the transfer matrix and the backward error are
+ * those of the crossbar as given.  That plan always recovers the node voltages (the
+ * given crossbar's currents come from them) and holds a buffer of max_batch 2 m n
+ * doubles for them.  AUTO: ROWS when n <= m; when n > m, SMALLER if n > XBAR_MAX_N,
+ * else whichever of the two a cost model of the factor, measured on gfx950, finds
+ * faster (the shorter chain of row blocks wins unless the blocks are large).
+ */
+typedef enum { XBAR_ORDER_AUTO = 0, XBAR_ORDER_ROWS = 1, XBAR_ORDER_SMALLER = 2 } xbar_ordering;
+
+/*
+ * xbar_create with an ordering (xbar_create is this with XBAR_ORDER_AUTO).  Returns
+ * XBAR_ERR_ARG also for an unknown ordering and for ROWS with n > XBAR_MAX_N.
+ * xbar_get_info's block field reports the padded row-block size the plan uses.
+ */
+xbar_status xbar_create_ordered(const xbar_geometry* geom, xbar_precision p, int32_t max_batch,
+                                double ir_tol, int32_t ir_max_iter, void* hip_stream, int32_t ordering,
+                                xbar_plan* out);
+
+/*
  * Assemble the nodal equations (Sec. II.A-II.B, Eqs. 1-7) for the device
  * conductances G: device pointer, [m][n] row-major, siemens, each finite and
  * > 0 (a value that is not sets XBAR_ERR_INPUT on the device).  The library

@@ -33,7 +33,8 @@ class Plan:
 
     def __init__(self, m: int, n: int, r_wl: float, r_bl: float, r_src: float = 50.0,
                  r_sense: float = 50.0, precision: str = "fp64", max_batch: int = 1024,
-                 ir_tol: float = 0.0, ir_max_iter: int = 0, stream=None, factor_method: str = "auto"):
+                 ir_tol: float = 0.0, ir_max_iter: int = 0, stream=None, factor_method: str = "auto",
+                 ordering: str = "auto"):
         torch = _torch()
         self.m, self.n = int(m), int(n)
         self.max_batch = int(max_batch)
@@ -41,7 +42,7 @@ class Plan:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.precision = precision
         self._plan = _lib.xbar_create(self.geom, PRECISIONS[precision], self.max_batch, ir_tol,
-                                      ir_max_iter, self.stream.cuda_stream)
+                                      ir_max_iter, self.stream.cuda_stream, _lib.ORDERINGS[ordering])
         self._B = 0
         _lib.xbar_set_factor_method(self._plan, FACTOR_METHODS[factor_method])
 

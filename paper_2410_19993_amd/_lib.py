@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         vp = ctypes.c_void_p
         L.xbar_create.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int, ctypes.c_int32,
                                   ctypes.c_double, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        L.xbar_create_ordered.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int, ctypes.c_int32,
+                                          ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(vp)]
         L.xbar_assemble.argtypes = [vp, vp]
         L.xbar_factor.argtypes = [vp]
         L.xbar_solve_batch.argtypes = [vp, vp, ctypes.c_int32, vp]
@@ -127,7 +129,7 @@ def lib() -> ctypes.CDLL:
         L.xbar_sg_adam.argtypes = [i64, vp, vp, vp, vp, f64, f64, f64, f64, i32, vp]
         L.xbar_sg_predict.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.xbar_status_string.restype = ctypes.c_char_p
-        for f in ("xbar_create", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
+        for f in ("xbar_create", "xbar_create_ordered", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
                   "xbar_get_timing", "xbar_set_factor_method", "xbar_set_diagnostics",
                   "xbar_debug_shift_pivots", "xbar_transfer",
@@ -164,12 +166,16 @@ def _check(call, st):
         raise XbarError(call, st)
 
 
+ORDERINGS = {"auto": 0, "rows": 1, "smaller": 2}
+
+
 def xbar_create(geom: Geometry, precision: int, max_batch: int, ir_tol: float = 0.0,
-                ir_max_iter: int = 0, stream: int | None = None) -> ctypes.c_void_p:
+                ir_max_iter: int = 0, stream: int | None = None, ordering: int = 0) -> ctypes.c_void_p:
     plan = ctypes.c_void_p()
-    st = lib().xbar_create(ctypes.byref(geom), int(precision), int(max_batch), float(ir_tol),
-                           int(ir_max_iter), ctypes.c_void_p(stream or 0), ctypes.byref(plan))
-    _check("xbar_create", st)
+    st = lib().xbar_create_ordered(ctypes.byref(geom), int(precision), int(max_batch), float(ir_tol),
+                                   int(ir_max_iter), ctypes.c_void_p(stream or 0), int(ordering),
+                                   ctypes.byref(plan))
+    _check("xbar_create_ordered", st)
     return plan
 
 

@@ -197,6 +197,27 @@ bool set_device(xbar_plan p) { return hipSetDevice(p->device) == hipSuccess; }
 // The block form of xbar_transfer keeps m FRG blocks of n_p x n_p in the sweep workspace
 // (float64 plans whose max_batch, rounded up to 16, is at least n_p); other plans solve
 // unit inputs and hold a staging buffer for them.
+// Cost model of the choice between the two orderings of an m x n crossbar with n > m.
+// A simulation (assembly, factor, solve) walks the chain of row blocks in sequence,
+// at about t(n_p) microseconds per row for the padded block size n_p; measured on
+// gfx950 (float64, one to 256 input vectors) the cost is nearly flat up to n_p = 128
+// and grows beyond: t = 14, 15, 22, 30, 42, 55, 67, 80 for n_p = 64 .. 512.  Rows:
+// m t(pad(n)); reciprocal: n t(pad(m)).  With it, among the wide shapes up to 256 x 512
+// the reciprocal wins at 128 x 512 and 256 x 512 and loses at every smaller or narrower
+// one, as the measurements did.
+double row_us(int n)
+{
+    const int n_p = 64 * ((n + 63) / 64);
+    static const double t[9] = {0.0, 14.0, 15.0, 22.0, 30.0, 42.0, 55.0, 67.0, 80.0};   // n_p = 64 k
+    return t[n_p / 64];
+}
+
+bool reciprocal_is_faster(int m, int n)
+{
+    if (n > XBAR_MAX_N) return true;
+    return (double)n * row_us(m) < (double)m * row_us(n);
+}
+
 bool transfer_blocks_fit(xbar_plan p)
 {
     return !p->rev && p->prec == XBAR_FP64 && (int64_t)p->nslab_max * 16 >= p->n_p;
@@ -284,15 +305,26 @@ const char* xbar_status_string(xbar_status s)
 xbar_status xbar_create(const xbar_geometry* geom, xbar_precision prec, int32_t max_batch,
                         double ir_tol, int32_t ir_max_iter, void* hip_stream, xbar_plan* out)
 {
+    return xbar_create_ordered(geom, prec, max_batch, ir_tol, ir_max_iter, hip_stream, XBAR_ORDER_AUTO, out);
+}
+
+xbar_status xbar_create_ordered(const xbar_geometry* geom, xbar_precision prec, int32_t max_batch,
+                                double ir_tol, int32_t ir_max_iter, void* hip_stream, int32_t ordering,
+                                xbar_plan* out)
+{
     if (out == nullptr || geom == nullptr) return XBAR_ERR_ARG;
     *out = nullptr;
     const xbar_geometry og = *geom;
     if (og.m < 1 || og.n < 1 || std::min(og.m, og.n) > XBAR_MAX_N) return XBAR_ERR_ARG;
     if (!finite_pos(og.r_wl) || !finite_pos(og.r_bl) || !finite_pos(og.r_src) || !finite_pos(og.r_sense))
         return XBAR_ERR_ARG;
-    // row blocks of the smaller side: a crossbar with more columns than rows is solved
-    // as its reciprocal (rotated by 180 degrees and transposed)
-    const bool rev = og.n > og.m;
+    if (ordering != XBAR_ORDER_AUTO && ordering != XBAR_ORDER_ROWS && ordering != XBAR_ORDER_SMALLER)
+        return XBAR_ERR_ARG;
+    if (ordering == XBAR_ORDER_ROWS && og.n > XBAR_MAX_N) return XBAR_ERR_ARG;
+    // reciprocal ordering: the crossbar turned by 180 degrees and transposed, so that the
+    // row blocks take the smaller side m
+    const bool rev = og.n > og.m && (ordering == XBAR_ORDER_SMALLER ||
+                                     (ordering == XBAR_ORDER_AUTO && reciprocal_is_faster(og.m, og.n)));
     xbar_geometry g = og;
     if (rev) {
         g.m = og.n;

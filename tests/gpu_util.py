@@ -20,7 +20,7 @@ def log(*a):
 
 
 def gpu_solve(G, V, geom, precision="fp64", node_voltages=True, max_batch=None, ir_tol=0.0,
-              ir_max_iter=0, factor_method="auto"):
+              ir_max_iter=0, factor_method="auto", ordering="auto"):
     """Solve on cuda:0 through the C ABI; returns (currents, node_v or None, info)."""
     import torch
 
@@ -31,7 +31,7 @@ def gpu_solve(G, V, geom, precision="fp64", node_voltages=True, max_batch=None, 
     Vd = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64)).cuda()
     with xb.Plan(m, n, geom.r_wl, geom.r_bl, geom.r_src, geom.r_sense, precision,
                  max_batch=max_batch or B, ir_tol=ir_tol, ir_max_iter=ir_max_iter,
-                 factor_method=factor_method) as p:
+                 factor_method=factor_method, ordering=ordering) as p:
         p.assemble(Gd)
         p.factor()
         nv = torch.empty((B, 2 * m * n), dtype=torch.float64, device="cuda") if node_voltages else None

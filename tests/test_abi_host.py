@@ -8,7 +8,7 @@ import pytest
 
 from paper_2410_19993_amd import _lib
 
-EXPECTED = ["xbar_assemble", "xbar_create", "xbar_currents", "xbar_debug_shift_pivots", "xbar_destroy",
+EXPECTED = ["xbar_assemble", "xbar_create", "xbar_create_ordered", "xbar_currents", "xbar_debug_shift_pivots", "xbar_destroy",
             "xbar_factor", "xbar_get_info", "xbar_get_timing", "xbar_set_diagnostics", "xbar_set_factor_method",
             "xbar_set_timing", "xbar_sg_adam",
             "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_data_bf16", "xbar_sg_conv_backward_weight",
@@ -64,6 +64,15 @@ def test_create_rejects_bad_geometry(field, value):
     kw = dict(GOOD)
     kw[field] = value
     st, plan = _create(_lib.Geometry(**kw))
+    assert st == _lib.XBAR_ERR_ARG and not plan.value
+
+
+@pytest.mark.parametrize("m,n,ordering", [(4, 4, 3), (4, 4, -1), (4, 600, 1)])
+def test_create_ordered_rejects_bad_orderings(m, n, ordering):
+    """Unknown orderings, and row blocks along the word lines when n > XBAR_MAX_N."""
+    geom = _lib.Geometry(**dict(GOOD, m=m, n=n))
+    plan = ctypes.c_void_p()
+    st = _lib.lib().xbar_create_ordered(ctypes.byref(geom), 0, 8, 0.0, 0, None, ordering, ctypes.byref(plan))
     assert st == _lib.XBAR_ERR_ARG and not plan.value
 
 

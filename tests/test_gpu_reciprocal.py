@@ -29,7 +29,7 @@ def test_32x700_against_stored_oracle(precision):
     wl = workloads.random_crossbar(32, 700, 3, 41)
     ref = np.load(os.path.join(GOLDEN, "rev_32x700_b3.npz"))
     log(f"case reciprocal 32x700 {precision}")
-    I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, precision, ir_max_iter=20)
+    I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, precision, ir_max_iter=20)      # n > 512: reciprocal
     e, ev = rel_err(I, ref["I"]), node_rel_err(nv, ref["v"])
     log(f"  status {st}, block {info.block}, steps {info.ir_iters}, current rel err {e.max():.3e}, "
         f"node {ev.max():.3e}")
@@ -55,8 +55,8 @@ def test_700x32_against_oracle(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_wide_shapes_against_oracle(m, n, B, seed, r_wl, r_bl, precision):
     wl = workloads.random_crossbar(m, n, B, seed, r_wl=r_wl, r_bl=r_bl, r_src=30.0, r_sense=70.0)
-    log(f"case wide {m}x{n} B={B} {precision} r_wl={r_wl} r_bl={r_bl}")
-    I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, precision)
+    log(f"case wide {m}x{n} B={B} {precision} r_wl={r_wl} r_bl={r_bl}, row blocks of the smaller side")
+    I, nv, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, precision, ordering="smaller")
     ref = oracle.solve_workload(wl)
     e, ev = rel_err(I, ref.currents), node_rel_err(nv, ref.node_v)
     log(f"  status {st}, block {info.block}, current rel err {e.max():.3e}, node {ev.max():.3e}")
@@ -71,7 +71,7 @@ def test_wide_transfer_matrix_and_apply():
     wl = workloads.random_crossbar(6, 50, 7, 49, r_wl=2.0, r_bl=3.0)
     T_ref = oracle.solve(wl.G, np.eye(6), 2.0, 3.0, 50.0, 50.0).currents
     log("case wide 6x50 transfer matrix")
-    with xb.Plan(6, 50, 2.0, 3.0, 50.0, 50.0, "fp64", max_batch=7) as p:
+    with xb.Plan(6, 50, 2.0, 3.0, 50.0, 50.0, "fp64", max_batch=7, ordering="smaller") as p:
         p.assemble(torch.from_numpy(wl.G).cuda())
         p.factor()
         T = p.transfer().cpu().numpy()
@@ -106,7 +106,8 @@ def test_wide_backward_error_on_the_crossbar_as_given():
     import paper_2410_19993_amd as xb
     wl = workloads.random_crossbar(12, 90, 5, 50, r_wl=2.5, r_bl=4.0, r_src=20.0, r_sense=80.0)
     log("case wide 12x90 backward error")
-    with xb.Plan(12, 90, 2.5, 4.0, 20.0, 80.0, "bf16_ir", max_batch=5, ir_tol=1e-15, ir_max_iter=1) as p:
+    with xb.Plan(12, 90, 2.5, 4.0, 20.0, 80.0, "bf16_ir", max_batch=5, ir_tol=1e-15, ir_max_iter=1,
+                 ordering="smaller") as p:
         p.set_diagnostics(True)
         p.assemble(torch.from_numpy(wl.G).cuda())
         p.factor()
@@ -120,11 +121,13 @@ def test_wide_backward_error_on_the_crossbar_as_given():
 
 
 def test_both_orderings_of_a_pair_use_the_smaller_block():
-    """32 x 256 and 256 x 32 solve on row blocks of 32 (padded 64): the same path."""
-    for (m, n) in ((32, 256), (256, 32)):
+    """32 x 256 and 256 x 32 with row blocks of the smaller side solve on blocks of 32
+    (padded 64): the same path; 32 x 256 ordered by rows uses blocks of 256."""
+    for (m, n, order, block) in ((32, 256, "smaller", 64), (256, 32, "smaller", 64), (32, 256, "rows", 256),
+                                 (256, 32, "rows", 64)):
         wl = workloads.random_crossbar(m, n, 16, 51 + m)
-        log(f"case pair {m}x{n}")
-        I, _, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, "fp64", node_voltages=False)
+        log(f"case pair {m}x{n} ordering {order}")
+        I, _, (st, info) = gpu_solve(wl.G, wl.V, wl.geom, "fp64", node_voltages=False, ordering=order)
         e = rel_err(I, oracle.solve_workload(wl).currents)
         log(f"  block {info.block}, rel err {e.max():.3e}")
-        assert st == 0 and info.block == 64 and e.max() <= TOL_FP64
+        assert st == 0 and info.block == block and e.max() <= TOL_FP64
