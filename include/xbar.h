@@ -529,6 +529,24 @@ xbar_status xbar_sg_adam(int64_t count, float* p, const float* g, float* m1, flo
 xbar_status xbar_sg_predict(int32_t B, int32_t m, int32_t n, const float* Y, const double* G, const double* V,
                             double* I, double* est, void* stream);
 
+/* Training targets delta [S][n] = (I - I0) / I0 elementwise (I: exact currents, I0 = G^T V,
+ * both [S][n] float64 device arrays). */
+xbar_status xbar_sg_targets(int32_t S, int32_t n, const double* I, const double* I0, double* delta, void* stream);
+
+/* Calibration ratios ratio [B] of predictions Ip [B][n] with error estimates est [B][n]
+ * against exact currents I [B][n]: max_j |Ip - I| / |I| over the columns with I != 0,
+ * divided by max_j est; NaN for a sample with no such column, a maximum that is not
+ * finite, or a non-positive estimate maximum.  The caller's quantile of the finite
+ * ratios is the scale kappa of the estimate (split-conformal calibration). */
+xbar_status xbar_sg_calib_ratios(int32_t B, int32_t n, const double* Ip, const double* I, const double* est,
+                                 double* ratio, void* stream);
+
+/* Routing of checked predictions: flag [B] int32 = 1 (solve exactly) unless
+ * kappa max_j est[b][j] <= tol, every I[b][j] is finite, every G[b] entry is finite and
+ * positive and every V[b] entry is finite; else 0.  G [B][m][n], V [B][m], I, est [B][n]. */
+xbar_status xbar_sg_route(int32_t B, int32_t m, int32_t n, const double* G, const double* V, const double* I,
+                          const double* est, double kappa, double tol, int32_t* flag, void* stream);
+
 /* Static, NUL-terminated name of a status code. */
 const char* xbar_status_string(xbar_status s);
 

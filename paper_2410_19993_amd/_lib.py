@@ -128,6 +128,9 @@ def lib() -> ctypes.CDLL:
         L.xbar_sg_readout_loss.argtypes = [i32, i32, i32, vp, vp, f64, vp, vp, vp]
         L.xbar_sg_adam.argtypes = [i64, vp, vp, vp, vp, f64, f64, f64, f64, i32, vp]
         L.xbar_sg_predict.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.xbar_sg_targets.argtypes = [i32, i32, vp, vp, vp, vp]
+        L.xbar_sg_calib_ratios.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+        L.xbar_sg_route.argtypes = [i32, i32, i32, vp, vp, vp, vp, f64, f64, vp, vp]
         L.xbar_status_string.restype = ctypes.c_char_p
         for f in ("xbar_create", "xbar_create_ordered", "xbar_assemble", "xbar_factor", "xbar_solve_batch",
                   "xbar_currents", "xbar_get_info", "xbar_destroy", "xbar_set_timing",
@@ -138,7 +141,7 @@ def lib() -> ctypes.CDLL:
                   "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_weight",
                   "xbar_sg_conv_backward_weight_noalloc", "xbar_sg_conv_forward_bf16",
                   "xbar_sg_conv_backward_data_bf16", "xbar_sg_conv_backward_weight_bf16", "xbar_sg_readout_loss",
-                  "xbar_sg_adam", "xbar_sg_predict"):
+                  "xbar_sg_adam", "xbar_sg_predict", "xbar_sg_targets", "xbar_sg_calib_ratios", "xbar_sg_route"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -319,3 +322,17 @@ def xbar_sg_adam(p, g, m1, m2, lr, b1, b2, eps, t, stream=None) -> None:
 def xbar_sg_predict(B, m, n, Y, G, V, I, est=None, stream=None) -> None:
     _check("xbar_sg_predict", lib().xbar_sg_predict(B, m, n, _ptr(Y), _ptr(G), _ptr(V), _ptr(I), _ptr(est),
                                                     _s(stream)))
+
+
+def xbar_sg_targets(S, n, I, I0, delta, stream=None) -> None:
+    _check("xbar_sg_targets", lib().xbar_sg_targets(S, n, _ptr(I), _ptr(I0), _ptr(delta), _s(stream)))
+
+
+def xbar_sg_calib_ratios(B, n, Ip, I, est, ratio, stream=None) -> None:
+    _check("xbar_sg_calib_ratios", lib().xbar_sg_calib_ratios(B, n, _ptr(Ip), _ptr(I), _ptr(est), _ptr(ratio),
+                                                              _s(stream)))
+
+
+def xbar_sg_route(B, m, n, G, V, I, est, kappa, tol, flag, stream=None) -> None:
+    _check("xbar_sg_route", lib().xbar_sg_route(B, m, n, _ptr(G), _ptr(V), _ptr(I), _ptr(est), float(kappa),
+                                                float(tol), _ptr(flag), _s(stream)))

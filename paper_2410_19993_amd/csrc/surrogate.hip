@@ -434,6 +434,86 @@ __global__ void sg_adam_kernel(int64_t count, float* __restrict__ p, const float
     p[e] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
+// Training targets: delta[e] = (I[e] - I0[e]) / I0[e] over B n entries.
+__global__ void sg_targets_kernel(int64_t count, const double* __restrict__ I, const double* __restrict__ I0,
+                                  double* __restrict__ delta)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        delta[e] = (I[e] - I0[e]) / I0[e];
+}
+
+// Fixed-order maximum over a workgroup of 256 (NaN above everything).
+__device__ double wg_max(double v, double* red)
+{
+    auto mx = [](double a, double b) { return (a != a || b != b) ? __builtin_nan("") : fmax(a, b); };
+    for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return mx(mx(red[0], red[1]), mx(red[2], red[3]));
+}
+
+// Calibration ratio of sample b (one workgroup): the largest relative current error of
+// the prediction Ip over the columns with a nonzero exact current I, divided by the
+// largest error estimate; NaN when no column has I != 0, when either maximum is not
+// finite, or when the estimate's maximum is not positive (such samples do not enter
+// the quantile).
+__global__ __launch_bounds__(256) void sg_calib_ratio_kernel(int n, const double* __restrict__ Ip,
+                                                             const double* __restrict__ I,
+                                                             const double* __restrict__ est,
+                                                             double* __restrict__ ratio)
+{
+    __shared__ double red[4];
+    const int64_t o = (int64_t)blockIdx.x * n;
+    double worst = 0.0, emax = 0.0, live = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double x = I[o + j];
+        if (x != 0.0) {
+            const double r = fabs(Ip[o + j] - x) / fabs(x);
+            worst = (r != r) ? r : fmax(worst, r);
+            live = 1.0;
+        }
+        const double e = est[o + j];
+        emax = (e != e) ? e : fmax(emax, e);
+    }
+    worst = wg_max(worst, red);
+    emax = wg_max(emax, red);
+    live = wg_max(live, red);
+    if (threadIdx.x == 0) {
+        const bool ok = live > 0.0 && isfinite(worst) && isfinite(emax) && emax > 0.0;
+        ratio[blockIdx.x] = ok ? worst / emax : __builtin_nan("");
+    }
+}
+
+// Routing of checked predictions (one workgroup per sample): flag[b] = 1 (solve it
+// exactly) unless kappa times the largest error estimate is a number <= tol, every
+// predicted current is finite, every conductance is finite and positive and every
+// input is finite.
+__global__ __launch_bounds__(256) void sg_route_kernel(int m, int n, const double* __restrict__ G,
+                                                       const double* __restrict__ V, const double* __restrict__ I,
+                                                       const double* __restrict__ est, double kappa, double tol,
+                                                       int* __restrict__ flag)
+{
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    double bad = 0.0, emax = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        const double e = est[(int64_t)b * n + j];
+        emax = (e != e) ? e : fmax(emax, e);
+        if (!isfinite(I[(int64_t)b * n + j])) bad = 1.0;
+    }
+    const int64_t mn = (int64_t)m * n;
+    for (int64_t k = threadIdx.x; k < mn; k += 256) {
+        const double g = G[(int64_t)b * mn + k];
+        if (!(isfinite(g) && g > 0.0)) bad = 1.0;
+    }
+    for (int i = threadIdx.x; i < m; i += 256)
+        if (!isfinite(V[(int64_t)b * m + i])) bad = 1.0;
+    bad = wg_max(bad, red);
+    emax = wg_max(emax, red);
+    if (threadIdx.x == 0) flag[b] = (bad > 0.0 || !(kappa * emax <= tol)) ? 1 : 0;
+}
+
 // I[b][j] = (sum_i G[b][i][j] V[b][i]) (1 + yhat_j), yhat_j = mean_i Y[b][0][i][j];
 // est[b][j] = exp((sigma mean_i Y[b][1][i][j] + mu) / 2) / |1 + yhat_j|, the predicted
 // relative current error (skipped when est is null).
@@ -702,6 +782,42 @@ xbar_status xbar_sg_predict(int32_t B, int32_t m, int32_t n, const float* Y, con
         return XBAR_ERR_ARG;
     hipLaunchKernelGGL(sg_predict_kernel, dim3((n + 255) / 256, B), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(hip_stream), B, m, n, Y, G, V, I, est);
+    return launched();
+}
+
+xbar_status xbar_sg_targets(int32_t S, int32_t n, const double* I, const double* I0, double* delta,
+                            void* hip_stream)
+{
+    if (S < 1 || n < 1 || !I || !I0 || !delta) return XBAR_ERR_ARG;
+    const int64_t nb = (int64_t)S * n * 8;
+    if (overlap(delta, nb, I, nb) || overlap(delta, nb, I0, nb)) return XBAR_ERR_ARG;
+    const int64_t count = (int64_t)S * n;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(sg_targets_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(hip_stream), count, I, I0, delta);
+    return launched();
+}
+
+xbar_status xbar_sg_calib_ratios(int32_t B, int32_t n, const double* Ip, const double* I, const double* est,
+                                 double* ratio, void* hip_stream)
+{
+    if (B < 1 || B > 65535 || n < 1 || !Ip || !I || !est || !ratio) return XBAR_ERR_ARG;
+    const int64_t nb = (int64_t)B * n * 8;
+    if (overlap(ratio, (int64_t)B * 8, Ip, nb) || overlap(ratio, (int64_t)B * 8, I, nb) ||
+        overlap(ratio, (int64_t)B * 8, est, nb))
+        return XBAR_ERR_ARG;
+    hipLaunchKernelGGL(sg_calib_ratio_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream), n,
+                       Ip, I, est, ratio);
+    return launched();
+}
+
+xbar_status xbar_sg_route(int32_t B, int32_t m, int32_t n, const double* G, const double* V, const double* I,
+                          const double* est, double kappa, double tol, int32_t* flag, void* hip_stream)
+{
+    if (!shape_ok(B, m, n) || !G || !V || !I || !est || !flag) return XBAR_ERR_ARG;
+    if (!(kappa >= 0.0) || !(tol >= 0.0)) return XBAR_ERR_ARG;
+    hipLaunchKernelGGL(sg_route_kernel, dim3(B), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream), m, n, G, V,
+                       I, est, kappa, tol, flag);
     return launched();
 }
 

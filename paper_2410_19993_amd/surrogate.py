@@ -223,16 +223,12 @@ class Surrogate:
             G, V, r, _, I = data.batch(idx)
             est = torch.empty((len(idx), n), dtype=torch.float64, device="cuda")
             Ip = self.predict(G, V, r, est=est)
-            # columns with no exact current (an all-zero input vector) carry no relative
-            # error; samples without any such column, or with a non-finite estimate, are
-            # left out of the quantile
-            live = I.abs() > 0
-            rel = torch.where(live, (Ip - I).abs() / torch.where(live, I.abs(), torch.ones_like(I)),
-                              torch.zeros_like(I))
-            worst = rel.max(dim=1).values
-            emax = est.max(dim=1).values
-            ok = live.any(dim=1) & torch.isfinite(worst) & torch.isfinite(emax) & (emax > 0)
-            ratios.append((worst[ok] / emax[ok]).cpu().numpy())
+            # per sample, the worst relative error over the columns with a nonzero exact
+            # current divided by the largest estimate (NaN: left out of the quantile)
+            ratio = torch.empty(len(idx), dtype=torch.float64, device="cuda")
+            _lib.xbar_sg_calib_ratios(len(idx), n, Ip, I, est, ratio, self._stream())
+            x = ratio.cpu().numpy()
+            ratios.append(x[np.isfinite(x)])
         ratios = np.concatenate(ratios)
         if ratios.size == 0:
             raise ValueError("calibration set has no sample with a nonzero exact current and a finite estimate")
@@ -259,9 +255,9 @@ class Surrogate:
         # column and its currents are finite; samples whose conductances are not finite
         # and positive, or whose inputs are not finite, go to the exact solver, which
         # reports them (XBAR_ERR_INPUT) instead of returning surrogate values
-        trusted = (self.kappa * est.max(dim=1).values <= tol) & torch.isfinite(out).all(dim=1)
-        valid = (torch.isfinite(G) & (G > 0)).flatten(1).all(dim=1) & torch.isfinite(V).all(dim=1)
-        flagged = (~(trusted & valid)).cpu().numpy()
+        flag = torch.empty(B, dtype=torch.int32, device="cuda")
+        _lib.xbar_sg_route(B, m, n, G, V, out, est, self.kappa, tol, flag, self._stream())
+        flagged = flag.cpu().numpy().astype(bool)
         idx = np.nonzero(flagged)[0]
         if len(idx):
             rs = r.cpu().numpy()
@@ -341,4 +337,6 @@ def targets_of(ds: Dataset):
         idx = torch.arange(a, min(S, a + step), device="cuda")
         Gb = ds.G[idx // ds.vectors].contiguous()
         _lib.xbar_sg_predict(len(idx), m, n, zero, Gb, ds.V[idx].contiguous(), I0[a:a + len(idx)], None, st)
-    return (ds.I - I0) / I0, I0
+    delta = torch.empty_like(I0)
+    _lib.xbar_sg_targets(S, n, ds.I, I0, delta, st)
+    return delta, I0

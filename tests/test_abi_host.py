@@ -8,16 +8,16 @@ import pytest
 
 from paper_2410_19993_amd import _lib
 
-EXPECTED = ["xbar_assemble", "xbar_create", "xbar_create_ordered", "xbar_currents", "xbar_debug_shift_pivots", "xbar_destroy",
-            "xbar_factor", "xbar_get_info", "xbar_get_timing", "xbar_set_diagnostics", "xbar_set_factor_method",
-            "xbar_set_timing", "xbar_sg_adam",
-            "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_data_bf16", "xbar_sg_conv_backward_weight",
-            "xbar_sg_conv_backward_weight_bf16", "xbar_sg_conv_backward_weight_noalloc",
-            "xbar_sg_conv_forward", "xbar_sg_conv_forward_bf16",
-            "xbar_sg_features", "xbar_sg_predict", "xbar_sg_readout_loss", "xbar_sg_workspace_floats",
-            "xbar_solve_batch", "xbar_status_string", "xbar_tiles_create", "xbar_tiles_currents",
-            "xbar_tiles_destroy", "xbar_tiles_run", "xbar_tiles_workspace_bytes", "xbar_transfer",
-            "xbar_transfer_apply"]
+EXPECTED = ["xbar_assemble", "xbar_create", "xbar_create_ordered", "xbar_currents",
+            "xbar_debug_shift_pivots", "xbar_destroy", "xbar_factor", "xbar_get_info", "xbar_get_timing",
+            "xbar_set_diagnostics", "xbar_set_factor_method", "xbar_set_timing", "xbar_sg_adam",
+            "xbar_sg_calib_ratios", "xbar_sg_conv_backward_data", "xbar_sg_conv_backward_data_bf16",
+            "xbar_sg_conv_backward_weight", "xbar_sg_conv_backward_weight_bf16",
+            "xbar_sg_conv_backward_weight_noalloc", "xbar_sg_conv_forward", "xbar_sg_conv_forward_bf16",
+            "xbar_sg_features", "xbar_sg_predict", "xbar_sg_readout_loss", "xbar_sg_route",
+            "xbar_sg_targets", "xbar_sg_workspace_floats", "xbar_solve_batch", "xbar_status_string",
+            "xbar_tiles_create", "xbar_tiles_currents", "xbar_tiles_destroy", "xbar_tiles_run",
+            "xbar_tiles_workspace_bytes", "xbar_transfer", "xbar_transfer_apply"]
 
 
 def _gpu_visible():

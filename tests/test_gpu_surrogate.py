@@ -427,3 +427,60 @@ def test_train_step_with_few_channels_on_many_tiles():
     got = net._views(net.grads)[0][0].cpu().numpy().astype(np.float64).reshape(ref.shape)
     assert np.all(np.isfinite(got))
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def test_targets_calibration_ratios_and_routing_kernels():
+    """xbar_sg_targets, xbar_sg_calib_ratios and xbar_sg_route against numpy on crafted
+    inputs: zero exact currents (left out), NaN and zero estimates, a non-finite
+    prediction, a negative conductance and a NaN input."""
+    import torch
+
+    from paper_2410_19993_amd import _lib
+    rng = np.random.default_rng(91)
+    B, m, n = 7, 5, 6
+    I = rng.uniform(1e-6, 1e-4, (B, n))
+    I[2, :] = 0.0                                # no live column: NaN ratio
+    I[3, 1] = 0.0                                # one dead column
+    I0 = I * rng.uniform(1.2, 2.0, (B, n))
+    Ip = I * (1 + rng.normal(scale=1e-3, size=(B, n)))
+    est = rng.uniform(1e-4, 5e-3, (B, n))
+    est[4, 2] = np.nan                           # NaN estimate: NaN ratio
+    est[5, :] = 0.0                              # zero estimate: NaN ratio
+    Ip[6, 3] = np.inf                            # non-finite prediction
+    G = rng.uniform(1e-6, 1e-4, (B, m, n))
+    G[1, 2, 3] = -1e-5                           # bad conductance
+    V = rng.uniform(0, 0.5, (B, m))
+    V[0, 4] = np.nan                             # bad input
+    t = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+    Id, I0d, Ipd, ed = t(I), t(I0), t(Ip), t(est)
+
+    delta = torch.empty((B, n), dtype=torch.float64, device="cuda")
+    _lib.xbar_sg_targets(B, n, Id, I0d, delta)
+    with np.errstate(invalid="ignore"):                      # 0 / 0 in the dead row, NaN on both sides
+        np.testing.assert_array_equal(delta.cpu().numpy(), (I - I0) / I0)
+
+    ratio = torch.empty(B, dtype=torch.float64, device="cuda")
+    _lib.xbar_sg_calib_ratios(B, n, Ipd, Id, ed, ratio)
+    got = ratio.cpu().numpy()
+    for b in range(B):
+        live = I[b] != 0
+        if not live.any() or not np.all(np.isfinite(est[b])) or est[b].max() <= 0:
+            assert np.isnan(got[b]), b
+            continue
+        worst = (np.abs(Ip[b] - I[b])[live] / np.abs(I[b])[live]).max()
+        if not np.isfinite(worst):
+            assert np.isnan(got[b]), b
+            continue
+        assert got[b] == worst / est[b].max(), b
+
+    flag = torch.empty(B, dtype=torch.int32, device="cuda")
+    kappa, tol = 2.0, 0.0098
+    _lib.xbar_sg_route(B, m, n, t(G), t(V), Ipd, ed, kappa, tol, flag)
+    want = []
+    for b in range(B):
+        ok = (np.all(np.isfinite(est[b])) and kappa * est[b].max() <= tol and np.all(np.isfinite(Ip[b])) and
+              np.all(np.isfinite(G[b])) and np.all(G[b] > 0) and np.all(np.isfinite(V[b])))
+        want.append(0 if ok else 1)
+    log(f"case surrogate host kernels: flags {flag.cpu().numpy().tolist()}, want {want}")
+    assert flag.cpu().numpy().tolist() == want
+    assert 0 in want and want[0] == 1 and want[1] == 1 and want[6] == 1
