@@ -458,12 +458,14 @@ def main():
                                       "transpose": cf.transpose, "source": src}
                        for (mm, nn, c, bb), cf, src in zip(classes, tb.configs, tb.sources)}
             streams = tb.streams
+            ws_bytes = tb.workspace_bytes
         vecs = 256 * len(tl)
         log(f"tiles: {len(tl)} crossbars in {len(classes)} classes, {ms:.2f} ms per pass "
             f"({ms_graph:.2f} ms as a graph replay)")
         return {"value": vecs / (ms * 1e-3), "unit": "solves/s", "ms_per_pass": ms,
                 "ms_per_pass_graph_replay": ms_graph, "tiles": len(tl), "classes": len(classes),
-                "tiles_per_s": len(tl) / (ms * 1e-3), "streams": streams, "per_class": configs,
+                "tiles_per_s": len(tl) / (ms * 1e-3), "streams": streams, "workspace_bytes": ws_bytes,
+                "per_class": configs,
                 "workload": "c4 tiles (seed 1004): 2048 crossbars of {32,64,128,256}^2, 256 vectors each, "
                             "currents only, one TileBatch call",
                 "algorithmic_flops": flops, "tflops": flops / (ms * 1e-3) / 1e12,
