@@ -131,3 +131,19 @@ def test_both_orderings_of_a_pair_use_the_smaller_block():
         e = rel_err(I, oracle.solve_workload(wl).currents)
         log(f"  block {info.block}, rel err {e.max():.3e}")
         assert st == 0 and info.block == block and e.max() <= TOL_FP64
+
+
+@pytest.mark.parametrize("m,n,block", [(32, 256, 256), (128, 512, 128), (256, 512, 256), (64, 512, 512),
+                                       (32, 700, 64), (300, 40, 64)])
+def test_auto_ordering_follows_the_measured_cost_model(m, n, block):
+    """The default ordering keeps rows where the chain of row blocks would grow more
+    than the blocks shrink (32 x 256, 64 x 512), turns 128 x 512 and 256 x 512, and must
+    turn past 512 columns; tall crossbars are already on their smaller side."""
+    import torch
+
+    import paper_2410_19993_amd as xb
+    log(f"case auto ordering {m}x{n}")
+    with xb.Plan(m, n, 2.5, 2.5, 50.0, 50.0, "fp64", max_batch=1) as p:
+        st, info = p.info()
+    log(f"  block {info.block}")
+    assert info.block == block
