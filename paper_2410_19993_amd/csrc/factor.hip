@@ -255,25 +255,65 @@ __device__ inline T form_elem(const T* E, const T* Ha, const T* Hb, int64_t off,
 // `special` = I nb + J of every job and crossbar; -1: none) come first in dispatch
 // order, so that their serial inversions start with the launch instead of after
 // the other updates.
+// With eight jobs or more (batches), job g = tile nj + job runs on XCD g % 8:
+// workgroups are dispatched round-robin over the 8 XCDs by linear index, and each
+// XCD takes its jobs one after another, all of a job's workgroups together, so the
+// pivot-row and pivot-column tiles that every workgroup of a job reads are fetched
+// into that XCD's L2 once.  The grid then holds 8 ceil(jobs / 8) jobs' workgroups
+// (gj_grid); those of the missing jobs exit at once.  A single crossbar's one or
+// two jobs are spread over the whole grid instead.
 struct GJSlot {
     int tile, job, I, J;
+    bool valid;
 };
+
+inline dim3 gj_grid(int nj, int tiles, int batch)
+{
+    const int jobs = nj * batch;
+    if (jobs >= 8) return dim3((unsigned)(8 * ((jobs + 7) / 8) * tiles));
+    return dim3((unsigned)(nj * tiles), (unsigned)batch);
+}
 
 __device__ inline GJSlot gj_slot(int nb, int nj, int batch, int special)
 {
-    const int tiles = nb * nb;
-    int L = blockIdx.y * gridDim.x + blockIdx.x;
+    const int tiles = nb * nb, jobs = nj * batch;
     GJSlot s;
-    if (special >= 0 && L < nj * batch) {
+    s.valid = true;
+    int IJ;
+    if (jobs >= 8) {
+        const int L = blockIdx.x, xcd = L & 7, local = L >> 3;
+        const int per_xcd = (jobs + 7) / 8;
+        int jl;
+        if (special < 0) {
+            jl = local / tiles;
+            IJ = local % tiles;
+        } else if (local < per_xcd) {
+            jl = local;
+            IJ = special;
+        } else {
+            const int r = local - per_xcd, per = tiles - 1;
+            jl = r / per;
+            const int q = r % per;
+            IJ = q < special ? q : q + 1;
+        }
+        const int g = 8 * jl + xcd;
+        s.valid = g < jobs;
+        s.tile = g / nj;
+        s.job = g % nj;
+        s.I = IJ / nb;
+        s.J = IJ % nb;
+        return s;
+    }
+    int L = blockIdx.y * gridDim.x + blockIdx.x;
+    if (special >= 0 && L < jobs) {
         s.tile = L / nj;
         s.job = L % nj;
         s.I = special / nb;
         s.J = special % nb;
         return s;
     }
-    int IJ;
     if (special >= 0) {
-        L -= nj * batch;
+        L -= jobs;
         const int per = tiles - 1;
         s.tile = L / (nj * per);
         const int rem = L % (nj * per);
@@ -291,44 +331,51 @@ __device__ inline GJSlot gj_slot(int nb, int nj, int batch, int special)
     return s;
 }
 
-// Crossbar `tile` of a batch of one shape: its H blocks and its jobs' working
-// buffers (a plan has one crossbar and keeps its own pointers).
+// Job `j` of the launch for crossbar `tile` of a batch of one shape: the job's
+// working buffers offset to that crossbar (a plan has one crossbar and keeps its own
+// pointers), and in *H the crossbar's H blocks.  The job is chosen field by field
+// and the arguments are never written, so that they stay in the kernel-argument
+// segment: a runtime index into them, or a write, makes the compiler copy the whole
+// argument block to per-lane scratch memory in every thread.
 template <typename T>
-__device__ inline GJJob batch_job(GJArgs& a, const GJJob& j0, int tile)
+__device__ inline GJJob batch_job(const GJArgs& a, int j, int tile, T** H)
 {
-    GJJob job = j0;
-    if (tile > 0) {
-        const int64_t t = tile;
-        a.H = reinterpret_cast<T*>(a.H) + t * a.h_stride;
-        for (int k = 0; k < 2; ++k) {
-            job.S[k] = reinterpret_cast<T*>(job.S[k]) + t * a.s_stride;
-            job.P[k] = reinterpret_cast<T*>(job.P[k]) + t * a.p_stride;
-        }
+    GJJob job;
+    job.row = j ? a.job[1].row : a.job[0].row;
+    job.next = j ? a.job[1].next : a.job[0].next;
+    job.dep_a = j ? a.job[1].dep_a : a.job[0].dep_a;
+    job.dep_b = j ? a.job[1].dep_b : a.job[0].dep_b;
+    const int64_t t = tile;
+    for (int k = 0; k < 2; ++k) {
+        job.S[k] = reinterpret_cast<T*>(j ? a.job[1].S[k] : a.job[0].S[k]) + t * a.s_stride;
+        job.P[k] = reinterpret_cast<T*>(j ? a.job[1].P[k] : a.job[0].P[k]) + t * a.p_stride;
     }
+    *H = reinterpret_cast<T*>(a.H) + t * a.h_stride;
     return job;
 }
 
 template <typename T>
-__device__ inline const T* slot_ptr(const GJArgs& a, int row)
+__device__ inline const T* slot_ptr(const T* H, int n_p, int row)
 {
-    return row < 0 ? nullptr : reinterpret_cast<const T*>(a.H) + (int64_t)row * a.n_p * a.n_p;
+    return row < 0 ? nullptr : H + (int64_t)row * n_p * n_p;
 }
 
 // Form the first pivot block of each job (chain start or twist) into its S[0] and
 // invert its pivot tile (0,0) into its P[0].
 template <typename T>
-__global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
+__global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a, int nj)
 {
     __shared__ __align__(32) T lds[kTile * kLd + 4 * kTile];
-    const int tiles = a.nb * a.nb;
-    const GJSlot sl = gj_slot(a.nb, (int)(gridDim.x * gridDim.y) / (tiles * a.batch), a.batch, 0);
-    const GJJob job = batch_job<T>(a, a.job[sl.job], sl.tile);
+    const GJSlot sl = gj_slot(a.nb, nj, a.batch, 0);
+    if (!sl.valid) return;
+    T* H;
+    const GJJob job = batch_job<T>(a, sl.job, sl.tile, &H);
     int* tbad = a.tile_bad ? a.tile_bad + sl.tile : nullptr;
     const int I = sl.I, J = sl.J;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const T* E = slot_ptr<T>(a, job.row);
-    const T* Ha = slot_ptr<T>(a, job.dep_a);
-    const T* Hb = slot_ptr<T>(a, job.dep_b);
+    const T* E = slot_ptr<T>(H, a.n_p, job.row);
+    const T* Ha = slot_ptr<T>(H, a.n_p, job.dep_a);
+    const T* Hb = slot_ptr<T>(H, a.n_p, job.dep_b);
     typename Frag<T>::acc_t acc[4];
 #pragma unroll
     for (int C = 0; C < 4; ++C)
@@ -342,27 +389,66 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a)
         invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, a.diag, min(a.n, kTile), w, l, tbad);
 }
 
+// Output tile (I, J) of pivot block k, held in acc: stored into the next working
+// copy, and the pivot tile (k+1, k+1) inverted; after the last pivot block, stored as
+// H_row[I][J] over E_row, then the chain's next pivot block E_next - g^2 H_row formed
+// (tile (0, 0) inverted).  lds: the workgroup's operand area, free when called.
+template <typename T>
+__device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const GJArgs& a, const GJJob& job, T* H,
+                                      T* Sout, T* Pout, int* tbad, int I, int J, int k, T* lds, int w, int l)
+{
+    const int nb = a.nb, n_p = a.n_p, r0 = 64 * I, c0 = 64 * J;
+    if (k != nb - 1) {
+        store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
+        if (I == k + 1 && J == k + 1)
+            invert_tile<T>(acc, lds, Pout, a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
+        return;
+    }
+    // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
+    // chain's next pivot block E_next - g^2 H_row.
+    T* Hr = H + (int64_t)job.row * n_p * n_p;
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            Hr[frg<T>(r0 + out_row<T>(w, l, v), c0 + 16 * C + (l & 15), n_p)] = acc[C][v];
+    if (job.next < 0) return;
+    const T* En = H + (int64_t)job.next * n_p * n_p;
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = r0 + out_row<T>(w, l, v), cc = c0 + 16 * C + (l & 15);
+            const T e = En[frg<T>(rr, cc, n_p)];
+            acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
+        }
+    store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
+    if (I == 0 && J == 0) invert_tile<T>(acc, lds, Pout, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
+}
+
 // Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
 template <typename T>
-__global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
+__global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int nj, int step, int k)
 {
     __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
     __shared__ __align__(32) T sB[kTile * kLd];
-    const int nb = a.nb, n_p = a.n_p, tiles = nb * nb;
-    const int nj = (int)(gridDim.x * gridDim.y) / (tiles * a.batch);
+    const int nb = a.nb, n_p = a.n_p;
     // the pivot tile this launch's inverting workgroups own: (k+1, k+1), or (0, 0) of
     // the next row's pivot block after the last pivot of a row
     const int special = k != nb - 1 ? (k + 1) * nb + (k + 1) : (a.job[0].next >= 0 || (nj > 1 && a.job[1].next >= 0)) ? 0 : -1;
     const GJSlot sl = gj_slot(nb, nj, a.batch, special);
-    const GJJob job = batch_job<T>(a, a.job[sl.job], sl.tile);
+    if (!sl.valid) return;
+    T* H;
+    const GJJob job = batch_job<T>(a, sl.job, sl.tile, &H);
     int* tbad = a.tile_bad ? a.tile_bad + sl.tile : nullptr;
     const int I = sl.I, J = sl.J;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int par = (int)(((int64_t)step * nb + k) & 1);
-    const T* Sin = reinterpret_cast<const T*>(job.S[par]);
-    T* Sout = reinterpret_cast<T*>(job.S[par ^ 1]);
-    const T* Pin = reinterpret_cast<const T*>(job.P[par]);
-    T* Pout = reinterpret_cast<T*>(job.P[par ^ 1]);
+    // (selects, not a runtime index, which would put the pointer pairs in scratch)
+    const T* Sin = reinterpret_cast<const T*>(par ? job.S[1] : job.S[0]);
+    T* Sout = reinterpret_cast<T*>(par ? job.S[0] : job.S[1]);
+    const T* Pin = reinterpret_cast<const T*>(par ? job.P[1] : job.P[0]);
+    T* Pout = reinterpret_cast<T*>(par ? job.P[0] : job.P[1]);
     using acc_t = typename Frag<T>::acc_t;
     acc_t acc[4];
 #pragma unroll
@@ -411,32 +497,120 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int step, int k)
         load_acc<T>(acc, Pin, kTile, 0, 0, w, l);       // P^{-1}
     }
 
-    if (k != nb - 1) {
-        store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-        if (I == k + 1 && J == k + 1)
-            invert_tile<T>(acc, sA, Pout, a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
-        return;
+    gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sA, w, l);
+}
+
+// Column workgroups of a batch (eight jobs or more, nb >= 3): one workgroup per
+// column block J of every job, job g on XCD g % 8 as in gj_slot, the column that
+// holds the tile inverted at the end (`scol`, -1: none) first in dispatch order.
+__device__ inline GJSlot gj_col_slot(int nb, int nj, int batch, int scol)
+{
+    const int jobs = nj * batch;
+    const int L = blockIdx.x, xcd = L & 7, local = L >> 3;
+    const int per_xcd = (jobs + 7) / 8;
+    int jl, J;
+    if (scol < 0) {
+        jl = local / nb;
+        J = local % nb;
+    } else if (local < per_xcd) {
+        jl = local;
+        J = scol;
+    } else {
+        const int r = local - per_xcd, per = nb - 1;
+        jl = r / per;
+        const int q = r % per;
+        J = q < scol ? q : q + 1;
     }
-    // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
-    // chain's next pivot block E_next - g^2 H_row.
-    T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
+    const int g = 8 * jl + xcd;
+    GJSlot s;
+    s.valid = g < jobs;
+    s.tile = g / nj;
+    s.job = g % nj;
+    s.I = 0;
+    s.J = J;
+    return s;
+}
+
+inline dim3 gj_col_grid(int nj, int nb, int batch)
+{
+    return dim3((unsigned)(8 * ((nj * batch + 7) / 8) * nb));
+}
+
+// Pivot block k of the current row of every job, one column block J per workgroup:
+// X = P^{-1} S[k][J] (P^{-1} itself for J = k) is formed once and becomes tile (k, J);
+// every other tile of the column is S[I][J] - S[I][k] X (-S[I][k] P^{-1} for J = k).
+// The same products as gj_step_kernel's, in the same order, so the same bits; the
+// column's three other workgroups there each form X again.  The tile to invert at
+// the end of the launch is the column's last.
+template <typename T>
+__global__ __launch_bounds__(256) void gj_col_kernel(GJArgs a, int nj, int step, int k)
+{
+    __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
+    __shared__ __align__(32) T sB[kTile * kLd];
+    const int nb = a.nb, n_p = a.n_p;
+    const bool last = k == nb - 1;
+    const int scol = !last ? k + 1 : (a.job[0].next >= 0 || (nj > 1 && a.job[1].next >= 0)) ? 0 : -1;
+    const GJSlot sl = gj_col_slot(nb, nj, a.batch, scol);
+    if (!sl.valid) return;
+    T* H;
+    const GJJob job = batch_job<T>(a, sl.job, sl.tile, &H);
+    int* tbad = a.tile_bad ? a.tile_bad + sl.tile : nullptr;
+    const int J = sl.J;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int par = (int)(((int64_t)step * nb + k) & 1);
+    const T* Sin = reinterpret_cast<const T*>(par ? job.S[1] : job.S[0]);
+    T* Sout = reinterpret_cast<T*>(par ? job.S[0] : job.S[1]);
+    const T* Pin = reinterpret_cast<const T*>(par ? job.P[1] : job.P[0]);
+    T* Pout = reinterpret_cast<T*>(par ? job.P[0] : job.P[1]);
+    using acc_t = typename Frag<T>::acc_t;
+    const int c0 = 64 * J, pk = 64 * k;
+    // the row of this column whose tile is inverted at the end (-1: none)
+    const int srow = J == scol ? (last ? 0 : k + 1) : -1;
+
+    acc_t x[4];
+    if (J != k) {
+        T v0[kPer], v1[kPer];
+        fetch_tile<T>(v0, Pin, kTile, 0, 0);
+        fetch_tile<T>(v1, Sin, n_p, pk, c0);
+        put_A<T>(sA, v0, (T)1);
+        put_B<T>(sB, v1);
+        __syncthreads();
+#pragma unroll
+        for (int C = 0; C < 4; ++C) x[C] = acc_t{0, 0, 0, 0};
+        tile_mma<T>(x, sA, sB, w, l);                   // X = P^{-1} S[k][J]
+        __syncthreads();
+    } else {
+        load_acc<T>(x, Pin, kTile, 0, 0, w, l);         // X = P^{-1}
+    }
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            Hr[frg<T>(r0 + out_row<T>(w, l, v), c0 + 16 * C + (l & 15), n_p)] = acc[C][v];
-    if (job.next < 0) return;
-    const T* En = reinterpret_cast<const T*>(a.H) + (int64_t)job.next * n_p * n_p;
-#pragma unroll
-    for (int C = 0; C < 4; ++C)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int rr = r0 + out_row<T>(w, l, v), cc = c0 + 16 * C + (l & 15);
-            const T e = En[frg<T>(rr, cc, n_p)];
-            acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
+        for (int v = 0; v < 4; ++v) {                   // X becomes the B operand of the column
+            const int kk = out_row<T>(w, l, v);
+            sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = x[C][v];
         }
-    store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, sA, Pout, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
+    gj_finish_tile<T>(x, a, job, H, Sout, Pout, tbad, k, J, k, sA, w, l);
+
+    auto update = [&](int I) {
+        T v2[kPer];
+        acc_t acc[4];
+        fetch_tile<T>(v2, Sin, n_p, 64 * I, pk);
+        if (J != k) {
+            load_acc<T>(acc, Sin, n_p, 64 * I, c0, w, l);
+        } else {
+#pragma unroll
+            for (int C = 0; C < 4; ++C) acc[C] = acc_t{0, 0, 0, 0};
+        }
+        __syncthreads();                                 // sA free, X in sB visible
+        put_A<T>(sA, v2, (T)-1);
+        __syncthreads();
+        tile_mma<T>(acc, sA, sB, w, l);                  // S[I][J] - S[I][k] X
+        gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sA, w, l);
+    };
+    // the rows other than k, the inverted tile's row last
+    for (int I = 0; I < nb; ++I)
+        if (I != k && I != srow) update(I);
+    if (srow >= 0) update(srow);
 }
 
 template <typename T>
@@ -453,7 +627,7 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
         if (top_len > 0) { f.job[nj] = top; f.job[nj].row = 0; f.job[nj].dep_a = f.job[nj].dep_b = -1; ++nj; }
         if (bot_len > 0) { f.job[nj] = bot; f.job[nj].row = m - 1; f.job[nj].dep_a = f.job[nj].dep_b = -1; ++nj; }
         if (nj > 0) {
-            hipLaunchKernelGGL(gj_form_kernel<T>, dim3(nj * tiles, a.batch), dim3(256), 0, s, f);
+            hipLaunchKernelGGL(gj_form_kernel<T>, gj_grid(nj, tiles, a.batch), dim3(256), 0, s, f, nj);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -473,8 +647,12 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
             f.job[nj].next = (m - 2 - st > kt) ? m - 2 - st : -1;
             ++nj;
         }
+        const bool cols = nj * a.batch >= 8 && nb >= 3;
         for (int k = 0; k < nb; ++k) {
-            hipLaunchKernelGGL(gj_step_kernel<T>, dim3(nj * tiles, a.batch), dim3(256), 0, s, f, st, k);
+            if (cols)
+                hipLaunchKernelGGL(gj_col_kernel<T>, gj_col_grid(nj, nb, a.batch), dim3(256), 0, s, f, nj, st, k);
+            else
+                hipLaunchKernelGGL(gj_step_kernel<T>, gj_grid(nj, tiles, a.batch), dim3(256), 0, s, f, nj, st, k);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -485,10 +663,13 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
     f.job[0].dep_a = (kt >= 1) ? kt - 1 : -1;
     f.job[0].dep_b = (kt + 1 <= m - 1) ? kt + 1 : -1;
     f.job[0].next = -1;
-    hipLaunchKernelGGL(gj_form_kernel<T>, dim3(tiles, a.batch), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(gj_form_kernel<T>, gj_grid(1, tiles, a.batch), dim3(256), 0, s, f, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int k = 0; k < nb; ++k) {
-        hipLaunchKernelGGL(gj_step_kernel<T>, dim3(tiles, a.batch), dim3(256), 0, s, f, 0, k);
+        if (a.batch >= 8 && nb >= 3)
+            hipLaunchKernelGGL(gj_col_kernel<T>, gj_col_grid(1, nb, a.batch), dim3(256), 0, s, f, 1, 0, k);
+        else
+            hipLaunchKernelGGL(gj_step_kernel<T>, gj_grid(1, tiles, a.batch), dim3(256), 0, s, f, 1, 0, k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -69,6 +69,23 @@ def test_pipeline_classes_against_oracle():
     log(f"  max current rel err {_check(classes, data, out):.3e}")
 
 
+@pytest.mark.parametrize("m,n", [(6, 130), (9, 260)])
+def test_column_factor_matches_tile_factor_bits(m, n):
+    """Nine crossbars with three or more 64-column blocks (eighteen or nine jobs per
+    launch) are factored with one workgroup per column block of each job; a crossbar
+    alone (one or two jobs) with one workgroup per tile.  Both form the same products
+    in the same order, and the batched sweep runs the same arithmetic per vector, so
+    every crossbar's currents agree bit for bit; the batch also meets the oracle."""
+    from paper_2410_19993_amd.tiles import TileConfig
+    G, V = _class(m, n, 9, 24, seed=350 + n)
+    log(f"case column factor {m}x{n}, 9 crossbars")
+    out, _ = _run([(m, n, 9, 24)], [(G, V)], configs=[TileConfig("pipeline")], streams=1)
+    for t in range(9):
+        one, _ = _run([(m, n, 1, 24)], [(G[t:t + 1], V[t:t + 1])], configs=[TileConfig("pipeline")], streams=1)
+        assert np.array_equal(out[0][t], one[0][0]), t
+    log(f"  bitwise equal; max current rel err {_check([(m, n, 9, 24)], [(G, V)], out):.3e}")
+
+
 @pytest.mark.parametrize("method", ["one_wg", "pipeline"])
 def test_reciprocal_classes_against_oracle(method):
     """Classes solved through their reciprocal problem (the turned, transposed crossbar
