@@ -37,6 +37,14 @@ __device__ inline int out_row(int w, int l, int v)
     return 16 * w + Frag<T>::drow(l >> 4, v);
 }
 
+// Orders one wave's own LDS accesses (the wave's lanes exchange values through LDS).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // acc[C] += A(rows 16w.., 64) * B(64, cols 16C..); sA row-major CPR, sB = B^T (CPR on k).
 template <typename T>
 __device__ inline void tile_mma(typename Frag<T>::acc_t (&acc)[4], const T* sA, const T* sB, int w, int l)
@@ -405,22 +413,47 @@ __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const G
         return;
     }
     // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
-    // chain's next pivot block E_next - g^2 H_row.
-    T* Hr = H + (int64_t)job.row * n_p * n_p;
+    // chain's next pivot block E_next - g^2 H_row.  H and E are fragment-tiled, and
+    // each wave holds four whole 16x16 fragment tiles of the output tile (its rows
+    // 16w..16w+15), so they pass through the wave's own quarter of the LDS area:
+    // every global access is then a contiguous 16 bytes per lane, where element-wise
+    // accesses touch all sixteen cache lines of a fragment tile per instruction.
+    lds_barrier();                       // the area is free: the product that read it is done
+    T* st = lds + w * 1024;
+    const int64_t tb = ((int64_t)((r0 >> 4) + w) * (n_p >> 4) + (c0 >> 4)) * 256;
+    const bool form = job.next >= 0;
+    T e[4][4];
+    if (form) {
+        const T* En = H + (int64_t)job.next * n_p * n_p + tb;
+#pragma unroll
+        for (int C = 0; C < 4; ++C)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) e[C][t] = En[C * 256 + frg_slot<T>(l, t)];
+    }
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            Hr[frg<T>(r0 + out_row<T>(w, l, v), c0 + 16 * C + (l & 15), n_p)] = acc[C][v];
-    if (job.next < 0) return;
-    const T* En = H + (int64_t)job.next * n_p * n_p;
+        for (int v = 0; v < 4; ++v) st[C * 256 + frg<T>(Frag<T>::drow(l >> 4, v), l & 15, 16)] = acc[C][v];
+    wave_lds_sync();
+    T* Hr = H + (int64_t)job.row * n_p * n_p + tb;
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Hr[C * 256 + frg_slot<T>(l, t)] = st[C * 256 + frg_slot<T>(l, t)];
+    if (!form) return;
+    wave_lds_sync();
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) st[C * 256 + frg_slot<T>(l, t)] = e[C][t];
+    wave_lds_sync();
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = r0 + out_row<T>(w, l, v), cc = c0 + 16 * C + (l & 15);
-            const T e = En[frg<T>(rr, cc, n_p)];
-            acc[C][v] = (rr < a.n && cc < a.n) ? e - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
+            const T ev = st[C * 256 + frg<T>(Frag<T>::drow(l >> 4, v), l & 15, 16)];
+            acc[C][v] = (rr < a.n && cc < a.n) ? ev - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
         }
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
     if (I == 0 && J == 0) invert_tile<T>(acc, lds, Pout, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
@@ -543,7 +576,7 @@ inline dim3 gj_col_grid(int nj, int nb, int batch)
 // column's three other workgroups there each form X again.  The tile to invert at
 // the end of the launch is the column's last.
 template <typename T>
-__global__ __launch_bounds__(256) void gj_col_kernel(GJArgs a, int nj, int step, int k)
+__global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int step, int k)
 {
     __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
     __shared__ __align__(32) T sB[kTile * kLd];
@@ -567,20 +600,47 @@ __global__ __launch_bounds__(256) void gj_col_kernel(GJArgs a, int nj, int step,
     // the row of this column whose tile is inverted at the end (-1: none)
     const int srow = J == scol ? (last ? 0 : k + 1) : -1;
 
+    // the rows other than k in increasing order, the inverted tile's row last
+    const int s1 = srow < 0 ? k : min(k, srow), s2 = srow < 0 ? nb : max(k, srow);
+    const int rows = nb - 1;
+    auto row_at = [&](int t) {
+        if (srow >= 0 && t == rows - 1) return srow;
+        int I = t;
+        if (I >= s1) ++I;
+        if (I >= s2) ++I;
+        return I;
+    };
+    // operands of a row's update: S[I][k], and S[I][J] (0 for J = k)
+    auto fetch_row = [&](int I, T (&v)[kPer], acc_t (&acc)[4]) {
+        fetch_tile<T>(v, Sin, n_p, 64 * I, pk);
+        if (J != k) {
+            load_acc<T>(acc, Sin, n_p, 64 * I, c0, w, l);
+        } else {
+#pragma unroll
+            for (int C = 0; C < 4; ++C) acc[C] = acc_t{0, 0, 0, 0};
+        }
+    };
+    // Each row's operands are requested one update ahead, so that their latency
+    // hides behind the previous product; the barriers order LDS only, and no thread
+    // reads another's global writes within the launch.
     acc_t x[4];
+    T vc[kPer];
+    acc_t ac[4];
     if (J != k) {
         T v0[kPer], v1[kPer];
         fetch_tile<T>(v0, Pin, kTile, 0, 0);
         fetch_tile<T>(v1, Sin, n_p, pk, c0);
+        fetch_row(row_at(0), vc, ac);
         put_A<T>(sA, v0, (T)1);
         put_B<T>(sB, v1);
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int C = 0; C < 4; ++C) x[C] = acc_t{0, 0, 0, 0};
         tile_mma<T>(x, sA, sB, w, l);                   // X = P^{-1} S[k][J]
-        __syncthreads();
+        lds_barrier();
     } else {
         load_acc<T>(x, Pin, kTile, 0, 0, w, l);         // X = P^{-1}
+        fetch_row(row_at(0), vc, ac);
     }
 #pragma unroll
     for (int C = 0; C < 4; ++C)
@@ -591,26 +651,23 @@ __global__ __launch_bounds__(256) void gj_col_kernel(GJArgs a, int nj, int step,
         }
     gj_finish_tile<T>(x, a, job, H, Sout, Pout, tbad, k, J, k, sA, w, l);
 
-    auto update = [&](int I) {
-        T v2[kPer];
-        acc_t acc[4];
-        fetch_tile<T>(v2, Sin, n_p, 64 * I, pk);
-        if (J != k) {
-            load_acc<T>(acc, Sin, n_p, 64 * I, c0, w, l);
-        } else {
+    for (int t = 0; t < rows; ++t) {
+        const int I = row_at(t);
+        T vn[kPer];
+        acc_t an[4];
+        if (t + 1 < rows) fetch_row(row_at(t + 1), vn, an);
+        lds_barrier();                                   // sA free, X in sB visible
+        put_A<T>(sA, vc, (T)-1);
+        lds_barrier();
+        tile_mma<T>(ac, sA, sB, w, l);                   // S[I][J] - S[I][k] X
+        gj_finish_tile<T>(ac, a, job, H, Sout, Pout, tbad, I, J, k, sA, w, l);
+        if (t + 1 < rows) {
 #pragma unroll
-            for (int C = 0; C < 4; ++C) acc[C] = acc_t{0, 0, 0, 0};
+            for (int e = 0; e < kPer; ++e) vc[e] = vn[e];
+#pragma unroll
+            for (int C = 0; C < 4; ++C) ac[C] = an[C];
         }
-        __syncthreads();                                 // sA free, X in sB visible
-        put_A<T>(sA, v2, (T)-1);
-        __syncthreads();
-        tile_mma<T>(acc, sA, sB, w, l);                  // S[I][J] - S[I][k] X
-        gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sA, w, l);
-    };
-    // the rows other than k, the inverted tile's row last
-    for (int I = 0; I < nb; ++I)
-        if (I != k && I != srow) update(I);
-    if (srow >= 0) update(srow);
+    }
 }
 
 template <typename T>
