@@ -104,6 +104,13 @@ __host__ __device__ inline void frg_rc(int64_t e, int n_p, int& r, int& c) {
     c = 16 * (int)(tile % kt) + Frag<T>::kidx(l >> 4, t);
 }
 
+// Maximum that keeps NaN: fmax drops a NaN as soon as a number follows it, which
+// would let a non-finite correction or estimate pass a convergence or routing test.
+__device__ __forceinline__ double nan_max(double a, double b)
+{
+    return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
+}
+
 // Workgroup barrier that orders LDS only.  __syncthreads() also waits for
 // every outstanding global load and store of the wave; kernels whose threads
 // never read each other's global writes within a launch use this instead, so

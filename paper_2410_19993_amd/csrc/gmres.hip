@@ -36,10 +36,10 @@ __device__ __forceinline__ double sum16(double v)
 }
 __device__ __forceinline__ double max16(double v)
 {
-    v = fmax(v, __shfl_xor(v, 1, 16));
-    v = fmax(v, __shfl_xor(v, 2, 16));
-    v = fmax(v, __shfl_xor(v, 4, 16));
-    v = fmax(v, __shfl_xor(v, 8, 16));
+    v = nan_max(v, __shfl_xor(v, 1, 16));
+    v = nan_max(v, __shfl_xor(v, 2, 16));
+    v = nan_max(v, __shfl_xor(v, 4, 16));
+    v = nan_max(v, __shfl_xor(v, 8, 16));
     return v;
 }
 
@@ -190,8 +190,8 @@ __global__ __launch_bounds__(256) void gm_update_kernel(GmPanel g, const double*
             for (int k = 0; k < kGmRestart; ++k) d += yy[k] * Z[(int64_t)k * g.P + base + j];
             const double x = u[base + j] + d;
             u[base + j] = x;
-            dmax = fmax(dmax, fabs(d));
-            umax = fmax(umax, fabs(x));
+            dmax = nan_max(dmax, fabs(d));
+            umax = nan_max(umax, fabs(x));
         }
     }
     dmax = max16(dmax);
@@ -216,8 +216,8 @@ __global__ __launch_bounds__(256) void gm_converge_kernel(GmPanel g, int B, cons
         if (b >= B) break;
         double dm = 0.0, um = 0.0;
         for (int c = 0; c < g.nchunk; ++c) {
-            dm = fmax(dm, part[((int64_t)c * kGmMaxNv + 0) * Bp + b]);
-            um = fmax(um, part[((int64_t)c * kGmMaxNv + 1) * Bp + b]);
+            dm = nan_max(dm, part[((int64_t)c * kGmMaxNv + 0) * Bp + b]);
+            um = nan_max(um, part[((int64_t)c * kGmMaxNv + 1) * Bp + b]);
         }
         if (!std::isfinite(dm) || !std::isfinite(um)) bad = true;
         if (!(dm <= tol * um)) all = false;

@@ -443,14 +443,19 @@ __global__ void sg_targets_kernel(int64_t count, const double* __restrict__ I, c
 }
 
 // Fixed-order maximum over a workgroup of 256 (NaN above everything).
+// Maximum that keeps NaN (fmax drops a NaN as soon as a number follows it).
+__device__ inline double nan_max(double a, double b)
+{
+    return (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
+}
+
 __device__ double wg_max(double v, double* red)
 {
-    auto mx = [](double a, double b) { return (a != a || b != b) ? __builtin_nan("") : fmax(a, b); };
-    for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off));
+    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off));
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    return mx(mx(red[0], red[1]), mx(red[2], red[3]));
+    return nan_max(nan_max(red[0], red[1]), nan_max(red[2], red[3]));
 }
 
 // Calibration ratio of sample b (one workgroup): the largest relative current error of
@@ -470,11 +475,10 @@ __global__ __launch_bounds__(256) void sg_calib_ratio_kernel(int n, const double
         const double x = I[o + j];
         if (x != 0.0) {
             const double r = fabs(Ip[o + j] - x) / fabs(x);
-            worst = (r != r) ? r : fmax(worst, r);
+            worst = nan_max(worst, r);
             live = 1.0;
         }
-        const double e = est[o + j];
-        emax = (e != e) ? e : fmax(emax, e);
+        emax = nan_max(emax, est[o + j]);
     }
     worst = wg_max(worst, red);
     emax = wg_max(emax, red);
@@ -498,8 +502,7 @@ __global__ __launch_bounds__(256) void sg_route_kernel(int m, int n, const doubl
     const int b = blockIdx.x;
     double bad = 0.0, emax = 0.0;
     for (int j = threadIdx.x; j < n; j += 256) {
-        const double e = est[(int64_t)b * n + j];
-        emax = (e != e) ? e : fmax(emax, e);
+        emax = nan_max(emax, est[(int64_t)b * n + j]);
         if (!isfinite(I[(int64_t)b * n + j])) bad = 1.0;
     }
     const int64_t mn = (int64_t)m * n;

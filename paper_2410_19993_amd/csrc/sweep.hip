@@ -308,8 +308,8 @@ struct SweepCtx {
                 const double d = (double)u[t][v];
                 const double x = up[t][v] + d;
                 uo[o + 16 * t + v] = x;
-                dmax = fmax(dmax, fabs(d));
-                umax = fmax(umax, fabs(x));
+                dmax = nan_max(dmax, fabs(d));
+                umax = nan_max(umax, fabs(x));
                 if (i == a.m - 1) {
                     const int k = row_of(t, v);
                     if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * x;
@@ -332,8 +332,8 @@ struct SweepCtx {
     __device__ __forceinline__ void decide(double* red) {
         double dm = dmax, um = umax;
         for (int off = 16; off < 64; off <<= 1) {
-            dm = fmax(dm, __shfl_xor(dm, off));
-            um = fmax(um, __shfl_xor(um, off));
+            dm = nan_max(dm, __shfl_xor(dm, off));
+            um = nan_max(um, __shfl_xor(um, off));
         }
         lds_barrier();
         if (l < 16) {
@@ -344,8 +344,8 @@ struct SweepCtx {
         if (threadIdx.x < 16) {
             double D = 0.0, U = 0.0;
             for (int k = 0; k < W; ++k) {
-                D = fmax(D, red[k * 16 + threadIdx.x]);
-                U = fmax(U, red[16 * W + k * 16 + threadIdx.x]);
+                D = nan_max(D, red[k * 16 + threadIdx.x]);
+                U = nan_max(U, red[16 * W + k * 16 + threadIdx.x]);
             }
             double* dprev = a.dnorm + (int64_t)a.slab * 16 + threadIdx.x;
             const double est = (a.iter > 0 && *dprev > 0.0) ? D * fmin(1.0, D / *dprev) : D;

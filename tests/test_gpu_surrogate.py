@@ -484,3 +484,30 @@ def test_targets_calibration_ratios_and_routing_kernels():
     log(f"case surrogate host kernels: flags {flag.cpu().numpy().tolist()}, want {want}")
     assert flag.cpu().numpy().tolist() == want
     assert 0 in want and want[0] == 1 and want[1] == 1 and want[6] == 1
+
+
+def test_routing_and_calibration_keep_a_nan_in_an_early_column():
+    """With more columns than threads each thread folds several columns: a NaN estimate
+    or error in column 0 must survive the finite columns 256 and later (a plain fmax
+    would drop it): the sample goes to the solver and its calibration ratio is NaN."""
+    import torch
+
+    from paper_2410_19993_amd import _lib
+    rng = np.random.default_rng(93)
+    B, m, n = 3, 4, 300
+    I = rng.uniform(1e-6, 1e-4, (B, n))
+    Ip = I * (1 + rng.normal(scale=1e-4, size=(B, n)))
+    est = rng.uniform(1e-5, 1e-4, (B, n))
+    est[0, 0] = np.nan                           # estimate NaN in the thread's first column
+    Ip[1, 0] = np.nan                            # prediction NaN in the thread's first column
+    G = rng.uniform(1e-6, 1e-4, (B, m, n))
+    V = rng.uniform(0, 0.5, (B, m))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ratio = torch.empty(B, dtype=torch.float64, device="cuda")
+    _lib.xbar_sg_calib_ratios(B, n, t(Ip), t(I), t(est), ratio)
+    got = ratio.cpu().numpy()
+    log(f"case NaN in column 0 of {n}: ratios {got.tolist()}")
+    assert np.isnan(got[0]) and np.isnan(got[1]) and np.isfinite(got[2])
+    flag = torch.empty(B, dtype=torch.int32, device="cuda")
+    _lib.xbar_sg_route(B, m, n, t(G), t(V), t(Ip), t(est), 2.0, 0.01, flag)
+    assert flag.cpu().numpy().tolist() == [1, 1, 0]
