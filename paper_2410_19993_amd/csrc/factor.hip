@@ -66,6 +66,44 @@ __device__ inline void tile_mma(typename Frag<T>::acc_t (&acc)[4], const T* sA, 
     }
 }
 
+// A-operand fragments of a 64x64 tile straight from memory into registers: rows
+// r0 + 16w + (l & 15), columns c0 + 16K + 4(l >> 4) + t of chunk K.  The memory
+// layout (row-major, columns permuted inside each 16-chunk) puts a lane's four values
+// of a chunk next to each other, as in an LDS-staged A tile.
+template <typename T>
+__device__ inline void fetch_afrag(T (&av)[4][4], const T* __restrict__ M, int ld, int r0, int c0, int w, int l)
+{
+    const T* p = M + (int64_t)(r0 + 16 * w + (l & 15)) * ld + c0 + 4 * (l >> 4);
+#pragma unroll
+    for (int K = 0; K < 4; ++K)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[K][t] = p[16 * K + t];
+}
+
+// acc[C] += s A(rows 16w.., 64) * B(64, cols 16C..) with A's fragments in registers
+// (fetch_afrag) and B as for tile_mma: the same products in the same order as
+// tile_mma on an A tile staged with the scale s.
+template <typename T>
+__device__ inline void tile_mma_r(typename Frag<T>::acc_t (&acc)[4], const T (&av)[4][4], T s, const T* sB, int w,
+                                  int l)
+{
+    const int q = l >> 4, r = l & 15;
+#pragma unroll
+    for (int K = 0; K < 4; ++K) {
+        T bv[4][4];
+#pragma unroll
+        for (int C = 0; C < 4; ++C)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[C][t] = sB[(16 * C + r) * kLd + 16 * K + 4 * q + t];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const T x = s * av[K][t];
+#pragma unroll
+            for (int C = 0; C < 4; ++C) acc[C] = Frag<T>::mma(x, bv[C][t], acc[C]);
+        }
+    }
+}
+
 // Operand staging is split into a fetch (global -> registers, 16 values per
 // thread, row-contiguous across a wave) and a put (registers -> LDS), so that a
 // workgroup can issue every global load of a launch before waiting on any.
@@ -461,10 +499,11 @@ __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const G
 
 // Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
 template <typename T>
-__global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int nj, int step, int k)
+__global__ __launch_bounds__(256, 3) void gj_step_kernel(GJArgs a, int nj, int step, int k)
 {
-    __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
-    __shared__ __align__(32) T sB[kTile * kLd];
+    // B operands; the A operands go from memory straight into registers.  Also the
+    // area of the pivot-tile inversion and of the staged output tiles.
+    __shared__ __align__(32) T sB[kTile * kLd + 4 * kTile];
     const int nb = a.nb, n_p = a.n_p;
     // the pivot tile this launch's inverting workgroups own: (k+1, k+1), or (0, 0) of
     // the next row's pivot block after the last pivot of a row
@@ -488,19 +527,19 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int nj, int step
     for (int C = 0; C < 4; ++C) acc[C] = acc_t{0, 0, 0, 0};
 
     const int r0 = 64 * I, c0 = 64 * J, pk = 64 * k;
-    T v0[kPer], v1[kPer], v2[kPer];
+    T av[4][4], vb[kPer];
     if (I != k && J != k) {
-        fetch_tile<T>(v0, Pin, kTile, 0, 0);
-        fetch_tile<T>(v1, Sin, n_p, pk, c0);
-        fetch_tile<T>(v2, Sin, n_p, r0, pk);
+        T a2[4][4];
+        fetch_afrag<T>(av, Pin, kTile, 0, 0, w, l);
+        fetch_tile<T>(vb, Sin, n_p, pk, c0);
+        fetch_afrag<T>(a2, Sin, n_p, r0, pk, w, l);
         load_acc<T>(acc, Sin, n_p, r0, c0, w, l);
-        put_A<T>(sA, v0, (T)1);
-        put_B<T>(sB, v1);
+        put_B<T>(sB, vb);
         __syncthreads();
         acc_t x[4];
 #pragma unroll
         for (int C = 0; C < 4; ++C) x[C] = acc_t{0, 0, 0, 0};
-        tile_mma<T>(x, sA, sB, w, l);                   // X = P^{-1} S[k][J]
+        tile_mma_r<T>(x, av, (T)1, sB, w, l);           // X = P^{-1} S[k][J]
         __syncthreads();
 #pragma unroll
         for (int C = 0; C < 4; ++C)
@@ -509,28 +548,25 @@ __global__ __launch_bounds__(256) void gj_step_kernel(GJArgs a, int nj, int step
                 const int kk = out_row<T>(w, l, v);
                 sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = x[C][v];
             }
-        put_A<T>(sA, v2, (T)-1);
         __syncthreads();
-        tile_mma<T>(acc, sA, sB, w, l);                 // S[I][J] - S[I][k] X
+        tile_mma_r<T>(acc, a2, (T)-1, sB, w, l);        // S[I][J] - S[I][k] X
     } else if (I == k && J != k) {
-        fetch_tile<T>(v0, Pin, kTile, 0, 0);
-        fetch_tile<T>(v1, Sin, n_p, pk, c0);
-        put_A<T>(sA, v0, (T)1);
-        put_B<T>(sB, v1);
+        fetch_afrag<T>(av, Pin, kTile, 0, 0, w, l);
+        fetch_tile<T>(vb, Sin, n_p, pk, c0);
+        put_B<T>(sB, vb);
         __syncthreads();
-        tile_mma<T>(acc, sA, sB, w, l);                 // P^{-1} S[k][J]
+        tile_mma_r<T>(acc, av, (T)1, sB, w, l);         // P^{-1} S[k][J]
     } else if (I != k && J == k) {
-        fetch_tile<T>(v2, Sin, n_p, r0, pk);
-        fetch_tile<T>(v0, Pin, kTile, 0, 0);
-        put_A<T>(sA, v2, (T)-1);
-        put_B<T>(sB, v0);
+        fetch_afrag<T>(av, Sin, n_p, r0, pk, w, l);
+        fetch_tile<T>(vb, Pin, kTile, 0, 0);
+        put_B<T>(sB, vb);
         __syncthreads();
-        tile_mma<T>(acc, sA, sB, w, l);                 // -S[I][k] P^{-1}
+        tile_mma_r<T>(acc, av, (T)-1, sB, w, l);        // -S[I][k] P^{-1}
     } else {
         load_acc<T>(acc, Pin, kTile, 0, 0, w, l);       // P^{-1}
     }
 
-    gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sA, w, l);
+    gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sB, w, l);
 }
 
 // Column workgroups of a batch (eight jobs or more, nb >= 3): one workgroup per
