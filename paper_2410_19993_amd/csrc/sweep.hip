@@ -187,6 +187,7 @@ struct SweepCtx {
     bool bval;
     T g;
     double dmax = 0.0, umax = 0.0;           // refinement: largest correction and solution entry
+    double dbad = 0.0;                       // 0, or NaN once a correction entry was not finite
 
     // Lane (q, col) of wave w holds rows row_of(t, v) of tile t, item v.  In panel
     // (CPR) order those rows sit at poff + 16 t + v, so every panel access is a
@@ -308,8 +309,9 @@ struct SweepCtx {
                 const double d = (double)u[t][v];
                 const double x = up[t][v] + d;
                 uo[o + 16 * t + v] = x;
-                dmax = nan_max(dmax, fabs(d));
-                umax = nan_max(umax, fabs(x));
+                dmax = fmax(dmax, fabs(d));
+                dbad += d * 0.0;             // one instruction; fmax alone would drop a NaN
+                umax = fmax(umax, fabs(x));
                 if (i == a.m - 1) {
                     const int k = row_of(t, v);
                     if (bval && k < a.n) a.Iout[(int64_t)b * a.n + k] = a.g_sense * x;
@@ -330,7 +332,7 @@ struct SweepCtx {
     // Refinement bookkeeping for the slab: per input vector, stop when the error left after
     // this correction, estimated as |d| * min(1, |d| / |d_prev|), is <= tol * |u|.
     __device__ __forceinline__ void decide(double* red) {
-        double dm = dmax, um = umax;
+        double dm = dmax + dbad, um = umax;
         for (int off = 16; off < 64; off <<= 1) {
             dm = nan_max(dm, __shfl_xor(dm, off));
             um = nan_max(um, __shfl_xor(um, off));
