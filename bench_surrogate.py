@@ -1,17 +1,19 @@
 """Learned current surrogate on 128 x 128 crossbars: data, training, accuracy, speed.
 
-    python bench_surrogate.py [--maps 12500] [--held-out-maps 1250] [--vectors 16]
+    python bench_surrogate.py [--maps 200000] [--held-out-maps 20000] [--vectors 1]
                               [--epochs 20] [--batch 32] [--lr 1e-3] [--channels 32]
                               [--precision bf16|fp32]
 
 Workload (seeded, synthetic): conductance maps log-uniform on [1e-6, 1e-4] S, the
 segment resistance r = r_wl = r_bl drawn from {1.0, 1.25, ..., 5.0} ohm per map,
 r_src = r_sense = 50 ohm, input vectors uniform on [0, 0.5] V; `vectors` input vectors
-per map.  The defaults give 200,000 training and 20,000 held-out samples.
+per map.  The defaults give 200,000 training and 20,000 held-out samples, each with a
+conductance map of its own.
 
 Steps, all on the GPU through the library:
-1. labels: exact float64 currents of every sample from the solver (PlanLanes, four
-   plans at a time), timed: that is the solver's throughput on new maps;
+1. labels: exact float64 currents of every sample from the solver (the batched tile
+   pipeline over the maps of each resistance level, 1024 maps per call), timed: that
+   is the solver's throughput on new maps;
 2. training: Adam on the mean squared error of the predicted correction, timed per
    step (features, 4 convolutions, readout and loss, 7 gradient kernels, update);
 3. held-out accuracy: relative current error of the surrogate and of G^T V against the
@@ -50,9 +52,9 @@ def log(msg):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--maps", type=int, default=12500)
-    ap.add_argument("--held-out-maps", type=int, default=1250)
-    ap.add_argument("--vectors", type=int, default=16)
+    ap.add_argument("--maps", type=int, default=200000)
+    ap.add_argument("--held-out-maps", type=int, default=20000)
+    ap.add_argument("--vectors", type=int, default=1)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=32)
@@ -62,7 +64,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1005)
     ap.add_argument("--infer-batch", type=int, default=256)
     ap.add_argument("--tol", type=float, default=0.01, help="error-estimate threshold of the checked predictions")
-    ap.add_argument("--cal-maps", type=int, default=256, help="maps of the calibration set of the error estimate")
+    ap.add_argument("--cal-maps", type=int, default=4096, help="maps of the calibration set of the error estimate")
     ap.add_argument("--precision", choices=("bf16", "fp32"), default="bf16",
                     help="convolution arithmetic: bfloat16 matrix cores or float32 vector units")
     ap.add_argument("--rates-only", action="store_true", help="only the convolution rates (step 6)")

@@ -300,25 +300,51 @@ class Dataset:
 
 
 def solver_dataset(maps: int, vectors: int, m: int, n: int, seed: int, r_levels=None, r_src: float = 50.0,
-                   r_sense: float = 50.0, lanes: int = 4) -> Dataset:
+                   r_sense: float = 50.0, lanes: int = 4, method: str = "tiles", chunk: int = 1024) -> Dataset:
     """Training data from the exact solver: `maps` conductance maps (log-uniform on
     [1e-6, 1e-4] S), each with `vectors` input vectors (uniform on [0, 0.5] V) and one
     segment resistance r = r_wl = r_bl drawn from r_levels (default 1.0, 1.25, ..., 5.0
-    ohm), solved with PlanLanes (one plan set per resistance level)."""
+    ohm).  The maps of one resistance level are solved together: with method "tiles"
+    through TileBatch's batched pipeline (condensation, block factor and sweep over up
+    to `chunk` maps per call), with "lanes" through PlanLanes (one plan per map on
+    `lanes` host threads)."""
+    from .tiles import TileBatch, TileConfig
     torch = _torch()
+    if method not in ("tiles", "lanes"):
+        raise ValueError(f"method must be 'tiles' or 'lanes', not {method!r}")
     levels = np.arange(1.0, 5.0001, 0.25) if r_levels is None else np.asarray(r_levels, dtype=np.float64)
     rng = np.random.default_rng(seed)
-    Gm = np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (maps, m, n)))
+    # the maps in draws of about 1 GiB of host memory (the same stream as one draw)
+    Gd = torch.empty((maps, m, n), dtype=torch.float64, device="cuda")
+    step = max(1, (1 << 27) // (m * n))
+    for a in range(0, maps, step):
+        b = min(maps, a + step)
+        Gd[a:b].copy_(torch.from_numpy(np.exp(rng.uniform(np.log(1e-6), np.log(1e-4), (b - a, m, n)))))
     Vm = rng.uniform(0.0, 0.5, (maps, vectors, m))
     rm = levels[rng.integers(0, len(levels), maps)]
-    Gd = torch.from_numpy(Gm).cuda()
     Vd = torch.from_numpy(Vm).cuda()
     Id = torch.empty((maps, vectors, n), dtype=torch.float64, device="cuda")
     for lv in np.unique(rm):
         idx = np.nonzero(rm == lv)[0]
-        with PlanLanes(lv, lv, r_src, r_sense, lanes=lanes, max_batch=vectors) as pl:
-            pl.currents([Gd[k] for k in idx], [Vd[k] for k in idx], [Id[k] for k in idx])
-            pl.check()
+        if method == "lanes":
+            with PlanLanes(lv, lv, r_src, r_sense, lanes=lanes, max_batch=vectors) as pl:
+                pl.currents([Gd[k] for k in idx], [Vd[k] for k in idx], [Id[k] for k in idx])
+                pl.check()
+            continue
+        batches = {}
+        try:
+            for a in range(0, len(idx), chunk):
+                sel = torch.from_numpy(idx[a:a + chunk]).cuda()
+                count = int(sel.numel())
+                if count not in batches:
+                    batches[count] = TileBatch([(m, n, count, vectors)], lv, lv, r_src, r_sense,
+                                               configs=[TileConfig("pipeline")], streams=1)
+                Id[sel] = batches[count].run([Gd[sel].contiguous()], [Vd[sel].contiguous()])[0]
+        finally:
+            for tb in batches.values():
+                tb.close()
+    if not bool(torch.isfinite(Id).all()):
+        raise RuntimeError("solver_dataset: a label is not finite (a map the solver rejected)")
     return Dataset(Gd, torch.from_numpy(rm).cuda(), Vd.reshape(maps * vectors, m), Id.reshape(maps * vectors, n),
                    vectors)
 

@@ -329,19 +329,23 @@ def test_checkpoint_round_trip():
         sgm.Surrogate(channels=5).load(st)
 
 
-def test_solver_dataset_labels_match_the_oracle():
+@pytest.mark.parametrize("method,maps,vectors,chunk", [("lanes", 3, 2, 1024), ("tiles", 3, 2, 1024),
+                                                       ("tiles", 11, 1, 4)])
+def test_solver_dataset_labels_match_the_oracle(method, maps, vectors, chunk):
     """solver_dataset: every sample's currents equal the oracle's for its map, input
-    vector and segment resistance, and delta = (I - G^T V) / G^T V."""
+    vector and segment resistance, and delta = (I - G^T V) / G^T V; through PlanLanes
+    and through the batched tile pipeline (11 maps in calls of at most 4: ragged)."""
     import paper_2410_19993_amd.surrogate as sgm
-    log("case solver dataset: 3 maps x 2 vectors of 16 x 16")
-    ds = sgm.solver_dataset(3, 2, 16, 16, seed=7, r_levels=[1.5, 4.0])
+    log(f"case solver dataset ({method}): {maps} maps x {vectors} vectors of 16 x 16, chunks of {chunk}")
+    ds = sgm.solver_dataset(maps, vectors, 16, 16, seed=7, r_levels=[1.5, 4.0], method=method, chunk=chunk)
     G, r, V, I = (x.cpu().numpy() for x in (ds.G, ds.r, ds.V, ds.I))
-    assert G.shape == (3, 16, 16) and V.shape == (6, 16) and I.shape == (6, 16) and set(r) <= {1.5, 4.0}
-    for s in range(6):
-        k = s // 2
+    S = maps * vectors
+    assert G.shape == (maps, 16, 16) and V.shape == (S, 16) and I.shape == (S, 16) and set(r) <= {1.5, 4.0}
+    for s in range(S):
+        k = s // vectors
         ref = oracle.solve(G[k], V[s:s + 1], r[k], r[k], 50.0, 50.0).currents[0]
         assert rel_err_vec(I[s], ref) <= 1e-10
-    Gs = np.repeat(G, 2, axis=0)
+    Gs = np.repeat(G, vectors, axis=0)
     assert np.allclose(ds.delta.cpu().numpy(), osg.targets(I, Gs, V), rtol=1e-12, atol=1e-15)
 
 
