@@ -242,12 +242,14 @@ class Surrogate:
                         lanes: int = 4, precision: str = "fp64"):
         """Currents for every sample, from the surrogate where kappa times its error
         estimate is at most tol in every column (kappa = 1 until calibrate()), and from
-        the exact solver (through PlanLanes, one plan set per segment resistance, in
-        `precision`: "fp64", or "fp32_ir" for float32 with float64 refinement) for the
-        others.  Returns (I, flagged),
-        flagged a host bool array of the samples that were solved exactly.  The plans are
-        kept for later calls until close()."""
+        the exact solver for the others, grouped by segment resistance: in float64
+        (`precision` "fp64") through the batched tile pipeline, the group padded to a
+        power of two (at least 32) by repeating its last map; with "fp32_ir" (float32
+        with float64 refinement) through PlanLanes, one plan per map on `lanes` host
+        threads.  Returns (I, flagged), flagged a host bool array of the samples that
+        were solved exactly.  The solvers are kept for later calls until close()."""
         torch = _torch()
+        from .tiles import TileBatch, TileConfig
         B, m, n = (int(x) for x in G.shape)
         est = torch.empty((B, n), dtype=torch.float64, device="cuda")
         out = self.predict(G, V, r, est=est)
@@ -263,6 +265,24 @@ class Surrogate:
             rs = r.cpu().numpy()
             for lv in np.unique(rs[idx]):
                 sel = idx[rs[idx] == lv]
+                if precision == "fp64":
+                    cnt = len(sel)
+                    bucket = max(32, 1 << (cnt - 1).bit_length())
+                    key = ("tiles", float(lv), float(r_src), float(r_sense), m, n, bucket)
+                    tb = self._solvers.get(key)
+                    if tb is None:
+                        tb = self._solvers[key] = TileBatch([(m, n, bucket, 1)], lv, lv, r_src, r_sense,
+                                                            configs=[TileConfig("pipeline")], streams=1)
+                    st = torch.from_numpy(np.concatenate([sel, np.full(bucket - cnt, sel[-1])])).cuda()
+                    Ib = tb.run([G[st].contiguous()], [V[st].unsqueeze(1).contiguous()])[0][:cnt, 0]
+                    # the pipeline gives a crossbar with a bad conductance (or pivot) NaN
+                    # currents where a plan reports the input; a NaN input gives NaN
+                    # currents either way
+                    bad = ~torch.isfinite(Ib).all(dim=1) & torch.isfinite(V[st[:cnt]]).all(dim=1)
+                    if bool(bad.any()):
+                        raise _lib.XbarError("predict_checked", _lib.XBAR_ERR_INPUT)
+                    out[st[:cnt]] = Ib
+                    continue
                 key = (float(lv), float(r_src), float(r_sense), int(lanes), precision)
                 pl = self._solvers.get(key)
                 if pl is None:
@@ -273,7 +293,8 @@ class Surrogate:
         return out, flagged
 
     def close(self) -> None:
-        """Free the plans predict_checked keeps (one PlanLanes per segment resistance)."""
+        """Free the solvers predict_checked keeps (per segment resistance: tile batches
+        and plan lanes)."""
         for pl in self._solvers.values():
             pl.close()
         self._solvers.clear()
