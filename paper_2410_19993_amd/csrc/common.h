@@ -232,6 +232,9 @@ struct GJJob {
     int dep_a, dep_b;    // rows whose inverses enter the pivot block (-1: none)
     void* S[2];          // working copies of the pivot block, [n_p][n_p] CPR each
     void* P[2];          // inverted 64x64 pivot tiles, CPR each
+    void* W = nullptr;   // batches: [2][nb][64][64] CPR, the chain's last inverse of each pivot
+                         // tile and the tile itself (warm starts of the next row's inverses),
+                         // or null (elimination only)
 };
 
 struct GJArgs {
@@ -244,7 +247,7 @@ struct GJArgs {
     // batched crossbars of one shape (blockIdx.y): crossbar t uses H + t * h_stride and the
     // jobs' S and P buffers + t * s_stride, t * p_stride (elements); batch = 1 for a plan
     int batch = 1;
-    int64_t h_stride = 0, s_stride = 0, p_stride = 0;
+    int64_t h_stride = 0, s_stride = 0, p_stride = 0, w_stride = 0;
     int* tile_bad = nullptr;   // batches: per-crossbar flag, set for a pivot that is not positive
 };
 

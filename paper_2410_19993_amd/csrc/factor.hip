@@ -174,7 +174,7 @@ __device__ inline void store_acc(const typename Frag<T>::acc_t (&acc)[4], T* M, 
 // plan's diagnostics.
 template <typename T>
 __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* Pout, int* flags,
-                            unsigned long long* diag, int valid, int w, int l, int* tbad)
+                            unsigned long long* diag, int valid, int w, int l, int* tbad, T* Pout2 = nullptr)
 {
     T* sP = lds;                         // [64][kLd] staging of the tile
     __syncthreads();
@@ -282,6 +282,140 @@ __device__ void invert_tile(const typename Frag<T>::acc_t (&acc)[4], T* lds, T* 
     if (threadIdx.x == 0 && valid > 0) atomicMin(diag + kDiagMinPivot, pivot_key(dmin));
 #pragma unroll
     for (int c = 0; c < 16; ++c) Pout[cpr<T>(r, c0 + c, kTile)] = a[c];
+    if (Pout2) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Pout2[cpr<T>(r, c0 + c, kTile)] = a[c];
+    }
+}
+
+// A 64x64 tile held in the accumulator layout (row out_row(w, l, v), column 16C + (l & 15))
+// into an operand area: as the A operand (row-major, columns in chunk order) or as the
+// B operand (stored transposed, rows in chunk order).
+template <typename T>
+__device__ inline void acc_to_A(T* sA, const typename Frag<T>::acc_t (&x)[4], int w, int l)
+{
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sA[out_row<T>(w, l, v) * kLd + 16 * C + Frag<T>::slot(l & 15)] = x[C][v];
+}
+
+template <typename T>
+__device__ inline void acc_to_B(T* sB, const typename Frag<T>::acc_t (&x)[4], int w, int l)
+{
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = out_row<T>(w, l, v);
+            sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = x[C][v];
+        }
+}
+
+constexpr double kTileNsDone = 1e-9;    // largest |Q^2| entry accepted
+
+// Inverse of the pivot tile P (in acc) by one Newton-Schulz round on the matrix cores,
+// from the chain's inverse Wk of the same tile one row earlier, corrected to first
+// order in the change of the tile with that inverse taken as its diagonal (Pk: the
+// tile one row earlier; consecutive rows' pivot tiles differ little, as the pivot
+// blocks do):
+//     X0 = Wk + diag(P)^-1 - diag(Pk)^-1 - D offdiag(P - Pk) D,   D = diag(Pk)^-1,
+//     Q = I - X0 P,   P2 = Q Q,   Y = X0 + Q X0,   X = Y + P2 Y,   I - X P = Q^4.
+// Accepted when every |P2| entry is <= 1e-9, so ||Q^2||_inf <= 64e-9 and
+// ||I - X P||_inf <= 4.1e-15 (on the 256 x 256 tiles of the tiles workload the
+// corrected start leaves |Q| <= 9e-9, so |Q^2| <= 1e-15 and X ends at rounding level;
+// uncorrected it would leave |Q^2| near 3e-8, and the test would fail every tile):
+// X goes to Pout and Wk, P to Pk, and the call returns true.  Otherwise (NaN included)
+// it writes nothing and returns false, and the caller eliminates.  Four 64 x 64 x 64
+// products against the 16 dependent elimination steps; no pivot is examined on this
+// path.  sA, sB: the workgroup's two operand areas.
+template <typename T>
+__device__ bool ns_tile_inverse(const typename Frag<T>::acc_t (&P)[4], T* Wk, T* Pk, T* sA, T* sB, T* Pout, int w,
+                                int l)
+{
+    using acc_t = typename Frag<T>::acc_t;
+    __shared__ double wmx[4];
+    acc_t y[4], q[4], p2[4];
+    {
+        acc_t pp[4];
+        T dpr[4], dpc[4];
+        load_acc<T>(y, Wk, kTile, 0, 0, w, l);
+        load_acc<T>(pp, Pk, kTile, 0, 0, w, l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = out_row<T>(w, l, v);
+            dpr[v] = Pk[cpr<T>(rr, rr, kTile)];
+        }
+#pragma unroll
+        for (int C = 0; C < 4; ++C) {
+            const int cc = 16 * C + (l & 15);
+            dpc[C] = Pk[cpr<T>(cc, cc, kTile)];
+        }
+#pragma unroll
+        for (int C = 0; C < 4; ++C)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (out_row<T>(w, l, v) == 16 * C + (l & 15))
+                    y[C][v] += (T)1 / P[C][v] - (T)1 / dpr[v];
+                else
+                    y[C][v] -= (P[C][v] - pp[C][v]) / (dpr[v] * dpc[C]);
+            }
+    }
+    __syncthreads();                                    // the operand areas are free
+    acc_to_A<T>(sA, y, w, l);
+    acc_to_B<T>(sB, P, w, l);
+    __syncthreads();
+#pragma unroll
+    for (int C = 0; C < 4; ++C) q[C] = acc_t{0, 0, 0, 0};
+    tile_mma<T>(q, sA, sB, w, l);                       // X0 P
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[C][v] = (T)(out_row<T>(w, l, v) == 16 * C + (l & 15) ? 1 : 0) - q[C][v];
+    __syncthreads();
+    acc_to_A<T>(sA, q, w, l);
+    acc_to_B<T>(sB, q, w, l);
+    __syncthreads();
+#pragma unroll
+    for (int C = 0; C < 4; ++C) p2[C] = acc_t{0, 0, 0, 0};
+    tile_mma<T>(p2, sA, sB, w, l);                      // Q Q
+    double mx = 0.0;
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) mx = nan_max(mx, fabs((double)p2[C][v]));
+    for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
+    if (l == 0) wmx[w] = mx;
+    __syncthreads();                                    // Q in sB read; wmx written
+    acc_to_B<T>(sB, y, w, l);
+    __syncthreads();
+    tile_mma<T>(y, sA, sB, w, l);                       // Y = X0 + Q X0
+    const double nu = nan_max(nan_max(wmx[0], wmx[1]), nan_max(wmx[2], wmx[3]));
+    if (!(nu <= kTileNsDone)) return false;             // the same answer in every wave
+    __syncthreads();
+    acc_to_A<T>(sA, p2, w, l);
+    acc_to_B<T>(sB, y, w, l);
+    __syncthreads();
+    tile_mma<T>(y, sA, sB, w, l);                       // X = Y + P2 Y
+    store_acc<T>(y, Pout, kTile, 0, 0, w, l);
+    store_acc<T>(y, Wk, kTile, 0, 0, w, l);             // Wk and Pk were read into registers
+    store_acc<T>(P, Pk, kTile, 0, 0, w, l);
+    return true;
+}
+
+// The pivot tile in acc inverted into Pout: by the Newton-Schulz round when `warm`
+// (the warm-start slots hold the chain's inverse of this tile and the tile one row
+// earlier) and it is accepted, else by elimination; either way the slots then hold
+// this row's inverse and tile.  W: the slots of the tile (inverse; the tile nb tiles
+// on), or null.
+template <typename T>
+__device__ void invert_pivot(const typename Frag<T>::acc_t (&acc)[4], T* sA, T* sB, T* Pout, T* W, int nb,
+                             bool warm, int* flags, unsigned long long* diag, int valid, int w, int l, int* tbad)
+{
+    T* const Pk = W ? W + (int64_t)nb * kTile * kTile : nullptr;
+    if (warm && W != nullptr && ns_tile_inverse<T>(acc, W, Pk, sA, sB, Pout, w, l)) return;
+    invert_tile<T>(acc, sA, Pout, flags, diag, valid, w, l, tbad, W);
+    if (Pk) store_acc<T>(acc, Pk, kTile, 0, 0, w, l);
 }
 
 // Pivot block of a row: E_row - g^2 (H_a + H_b) on the n x n part (a, b < 0: absent),
@@ -396,6 +530,8 @@ __device__ inline GJJob batch_job(const GJArgs& a, int j, int tile, T** H)
         job.S[k] = reinterpret_cast<T*>(j ? a.job[1].S[k] : a.job[0].S[k]) + t * a.s_stride;
         job.P[k] = reinterpret_cast<T*>(j ? a.job[1].P[k] : a.job[0].P[k]) + t * a.p_stride;
     }
+    T* W = reinterpret_cast<T*>(j ? a.job[1].W : a.job[0].W);
+    job.W = W ? W + t * a.w_stride : nullptr;
     *H = reinterpret_cast<T*>(a.H) + t * a.h_stride;
     return job;
 }
@@ -431,23 +567,32 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a, int nj)
             acc[C][v] = form_elem<T>(E, Ha, Hb, frg<T>(rr, cc, a.n_p), a.g2, rr, cc, a.n);
         }
     store_acc<T>(acc, reinterpret_cast<T*>(job.S[0]), a.n_p, 64 * I, 64 * J, w, l);
-    if (I == 0 && J == 0)
-        invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, a.diag, min(a.n, kTile), w, l, tbad);
+    if (I == 0 && J == 0) {
+        T* const W = reinterpret_cast<T*>(job.W);
+        invert_tile<T>(acc, lds, reinterpret_cast<T*>(job.P[0]), a.flags, a.diag, min(a.n, kTile), w, l, tbad, W);
+        if (W) store_acc<T>(acc, W + (int64_t)a.nb * kTile * kTile, kTile, 0, 0, w, l);   // the tile itself
+    }
 }
 
 // Output tile (I, J) of pivot block k, held in acc: stored into the next working
 // copy, and the pivot tile (k+1, k+1) inverted; after the last pivot block, stored as
 // H_row[I][J] over E_row, then the chain's next pivot block E_next - g^2 H_row formed
 // (tile (0, 0) inverted).  lds: the workgroup's operand area, free when called.
-template <typename T>
+template <typename T, bool INV = true>
 __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const GJArgs& a, const GJJob& job, T* H,
-                                      T* Sout, T* Pout, int* tbad, int I, int J, int k, T* lds, int w, int l)
+                                      T* Sout, T* Pout, int* tbad, int I, int J, int k, T* lds, T* lds2, int w, int l)
 {
     const int nb = a.nb, n_p = a.n_p, r0 = 64 * I, c0 = 64 * J;
+    T* const W = reinterpret_cast<T*>(job.W);
     if (k != nb - 1) {
         store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-        if (I == k + 1 && J == k + 1)
-            invert_tile<T>(acc, lds, Pout, a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
+        if (INV && I == k + 1 && J == k + 1) {
+            // a warm start exists once the chain is past its first row (the twist row
+            // has two neighbours and no such inverse)
+            const bool warm = job.dep_b < 0 && job.row != 0 && job.row != a.m - 1;
+            invert_pivot<T>(acc, lds, lds2, Pout, W ? W + (int64_t)(k + 1) * kTile * kTile : nullptr, nb, warm,
+                            a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
+        }
         return;
     }
     // Last pivot block: acc holds H_row[I][J]; store it over E_row, then form the
@@ -494,15 +639,18 @@ __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const G
             acc[C][v] = (rr < a.n && cc < a.n) ? ev - (T)a.g2 * acc[C][v] : (T)(rr == cc ? 1 : 0);
         }
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
-    if (I == 0 && J == 0) invert_tile<T>(acc, lds, Pout, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
+    // tile 0 of the next row's pivot block, from this row's inverse of its tile 0
+    if (INV && I == 0 && J == 0)
+        invert_pivot<T>(acc, lds, lds2, Pout, W, nb, true, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
 }
 
 // Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
 template <typename T>
-__global__ __launch_bounds__(256, 3) void gj_step_kernel(GJArgs a, int nj, int step, int k)
+__global__ __launch_bounds__(256, 2) void gj_step_kernel(GJArgs a, int nj, int step, int k)
 {
-    // B operands; the A operands go from memory straight into registers.  Also the
-    // area of the pivot-tile inversion and of the staged output tiles.
+    // B operands (the A operands go from memory straight into registers); both areas
+    // also serve the pivot-tile inversion, sA the staged output tiles.
+    __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
     __shared__ __align__(32) T sB[kTile * kLd + 4 * kTile];
     const int nb = a.nb, n_p = a.n_p;
     // the pivot tile this launch's inverting workgroups own: (k+1, k+1), or (0, 0) of
@@ -566,7 +714,7 @@ __global__ __launch_bounds__(256, 3) void gj_step_kernel(GJArgs a, int nj, int s
         load_acc<T>(acc, Pin, kTile, 0, 0, w, l);       // P^{-1}
     }
 
-    gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sB, w, l);
+    gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sA, sB, w, l);
 }
 
 // Column workgroups of a batch (eight jobs or more, nb >= 3): one workgroup per
@@ -656,17 +804,13 @@ __global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int st
             for (int C = 0; C < 4; ++C) acc[C] = acc_t{0, 0, 0, 0};
         }
     };
-    // Each row's operands are requested one update ahead, so that their latency
-    // hides behind the previous product; the barriers order LDS only, and no thread
-    // reads another's global writes within the launch.
+    // The barriers order LDS only: no thread reads another's global writes within the
+    // launch.
     acc_t x[4];
-    T vc[kPer];
-    acc_t ac[4];
     if (J != k) {
         T v0[kPer], v1[kPer];
         fetch_tile<T>(v0, Pin, kTile, 0, 0);
         fetch_tile<T>(v1, Sin, n_p, pk, c0);
-        fetch_row(row_at(0), vc, ac);
         put_A<T>(sA, v0, (T)1);
         put_B<T>(sB, v1);
         lds_barrier();
@@ -676,7 +820,6 @@ __global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int st
         lds_barrier();
     } else {
         load_acc<T>(x, Pin, kTile, 0, 0, w, l);         // X = P^{-1}
-        fetch_row(row_at(0), vc, ac);
     }
 #pragma unroll
     for (int C = 0; C < 4; ++C)
@@ -685,26 +828,31 @@ __global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int st
             const int kk = out_row<T>(w, l, v);
             sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = x[C][v];
         }
-    gj_finish_tile<T>(x, a, job, H, Sout, Pout, tbad, k, J, k, sA, w, l);
+    gj_finish_tile<T, false>(x, a, job, H, Sout, Pout, tbad, k, J, k, sA, sB, w, l);   // row k: never inverted
 
-    for (int t = 0; t < rows; ++t) {
-        const int I = row_at(t);
-        T vn[kPer];
-        acc_t an[4];
-        if (t + 1 < rows) fetch_row(row_at(t + 1), vn, an);
+    // the other rows, the inverted tile's row after them
+    auto update = [&](int I, acc_t (&ac)[4]) {
+        T vc[kPer];
+        fetch_row(I, vc, ac);
         lds_barrier();                                   // sA free, X in sB visible
         put_A<T>(sA, vc, (T)-1);
         lds_barrier();
         tile_mma<T>(ac, sA, sB, w, l);                   // S[I][J] - S[I][k] X
-        gj_finish_tile<T>(ac, a, job, H, Sout, Pout, tbad, I, J, k, sA, w, l);
-        if (t + 1 < rows) {
-#pragma unroll
-            for (int e = 0; e < kPer; ++e) vc[e] = vn[e];
-#pragma unroll
-            for (int C = 0; C < 4; ++C) ac[C] = an[C];
-        }
+    };
+    const int plain = srow >= 0 ? rows - 1 : rows;
+    for (int t = 0; t < plain; ++t) {
+        const int I = row_at(t);
+        acc_t ac[4];
+        update(I, ac);
+        gj_finish_tile<T, false>(ac, a, job, H, Sout, Pout, tbad, I, J, k, sA, sB, w, l);
+    }
+    if (srow >= 0) {
+        acc_t ac[4];
+        update(srow, ac);
+        gj_finish_tile<T>(ac, a, job, H, Sout, Pout, tbad, srow, J, k, sA, sB, w, l);
     }
 }
+
 
 template <typename T>
 hipError_t launch_factor(GJArgs a, hipStream_t s)

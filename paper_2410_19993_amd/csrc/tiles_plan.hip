@@ -54,6 +54,7 @@ struct PipeBuffers {
     double* Gc = nullptr;
     void* S[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [chain][parity][T][n_p][n_p]
     void* P[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [chain][parity][T][64][64]
+    void* W[2] = {nullptr, nullptr};   // [chain][T][2][nb][64][64] last inverse of each pivot tile, the tile
     void* Z = nullptr;           // [T][slabs][m][16][n_p] forward results
     int* flags = nullptr;        // [kNumFlags]
     unsigned long long* diag = nullptr;
@@ -137,8 +138,8 @@ void tiles_free(xbar_tiles t)
 {
     for (PipeBuffers& b : t->pipe) {
         void* all[] = {b.H, b.c, b.fr, b.ip, b.q, b.Gc, b.S[0][0], b.S[0][1], b.S[1][0], b.S[1][1],
-                       b.P[0][0], b.P[0][1], b.P[1][0], b.P[1][1], b.Z, b.flags, b.diag, b.sink, b.bad,
-                       b.Gt, b.Tt};
+                       b.P[0][0], b.P[0][1], b.P[1][0], b.P[1][1], b.W[0], b.W[1], b.Z, b.flags, b.diag, b.sink,
+                       b.bad, b.Gt, b.Tt};
         for (void* x : all)
             if (x) (void)hipFree(x);
         b = PipeBuffers{};
@@ -199,6 +200,7 @@ hipError_t run_pipe(xbar_tiles t, int k, const Inner& in, const double* G, const
             ga.job[ch].S[q] = b.S[ch][q];
             ga.job[ch].P[q] = b.P[ch][q];
         }
+        ga.job[ch].W = b.W[ch];      // warm starts of the pivot-tile inverses
     }
     ga.flags = b.flags;
     ga.diag = b.diag;
@@ -206,6 +208,7 @@ hipError_t run_pipe(xbar_tiles t, int k, const Inner& in, const double* G, const
     ga.h_stride = (int64_t)m * n_p * n_p;
     ga.s_stride = (int64_t)n_p * n_p;
     ga.p_stride = (int64_t)xbk::kTile * xbk::kTile;
+    ga.w_stride = (int64_t)2 * b.nb * xbk::kTile * xbk::kTile;
     ga.tile_bad = b.bad;
     if ((e = xbk_launch_factor(ga, false, s)) != hipSuccess) return e;
     xbk::SweepArgs sa{};
@@ -339,11 +342,13 @@ xbar_status xbar_tiles_create(const xbar_tile_class* classes, int32_t nclasses, 
         A((void**)&b.ip, T * m * n * 8);
         A((void**)&b.q, T * m * n * 8);
         A((void**)&b.Gc, T * m * n * 8);
-        for (int ch = 0; ch < 2; ++ch)
+        for (int ch = 0; ch < 2; ++ch) {
             for (int q = 0; q < 2; ++q) {
                 A(&b.S[ch][q], T * n_p * n_p * 8);
                 A(&b.P[ch][q], T * xbk::kTile * xbk::kTile * 8);
             }
+            A(&b.W[ch], T * 2 * b.nb * xbk::kTile * xbk::kTile * 8);
+        }
         A(&b.Z, T * b.slabs * m * 16 * n_p * 8);
         A((void**)&b.flags, xbk::kNumFlags * sizeof(int));
         A((void**)&b.diag, xbk::kNumDiag * sizeof(unsigned long long));
