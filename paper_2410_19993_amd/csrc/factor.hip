@@ -403,19 +403,23 @@ __device__ bool ns_tile_inverse(const typename Frag<T>::acc_t (&P)[4], T* Wk, T*
     return true;
 }
 
-// The pivot tile in acc inverted into Pout: by the Newton-Schulz round when `warm`
-// (the warm-start slots hold the chain's inverse of this tile and the tile one row
-// earlier) and it is accepted, else by elimination; either way the slots then hold
-// this row's inverse and tile.  W: the slots of the tile (inverse; the tile nb tiles
-// on), or null.
-template <typename T>
+// The pivot tile in acc inverted into Pout.  NS (a batch with warm-start slots): by the
+// Newton-Schulz round when `warm` (the slots hold the chain's inverse of this tile and
+// the tile one row earlier) and it is accepted, else by elimination; either way the
+// slots then hold this row's inverse and tile.  W: the slots of the tile (inverse; the
+// tile nb tiles on).  Without NS: elimination only, W unused.
+template <typename T, bool NS>
 __device__ void invert_pivot(const typename Frag<T>::acc_t (&acc)[4], T* sA, T* sB, T* Pout, T* W, int nb,
                              bool warm, int* flags, unsigned long long* diag, int valid, int w, int l, int* tbad)
 {
-    T* const Pk = W ? W + (int64_t)nb * kTile * kTile : nullptr;
-    if (warm && W != nullptr && ns_tile_inverse<T>(acc, W, Pk, sA, sB, Pout, w, l)) return;
-    invert_tile<T>(acc, sA, Pout, flags, diag, valid, w, l, tbad, W);
-    if (Pk) store_acc<T>(acc, Pk, kTile, 0, 0, w, l);
+    if constexpr (NS) {
+        T* const Pk = W + (int64_t)nb * kTile * kTile;
+        if (warm && ns_tile_inverse<T>(acc, W, Pk, sA, sB, Pout, w, l)) return;
+        invert_tile<T>(acc, sA, Pout, flags, diag, valid, w, l, tbad, W);
+        store_acc<T>(acc, Pk, kTile, 0, 0, w, l);
+    } else {
+        invert_tile<T>(acc, sA, Pout, flags, diag, valid, w, l, tbad);
+    }
 }
 
 // Pivot block of a row: E_row - g^2 (H_a + H_b) on the n x n part (a, b < 0: absent),
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(256) void gj_form_kernel(GJArgs a, int nj)
 // copy, and the pivot tile (k+1, k+1) inverted; after the last pivot block, stored as
 // H_row[I][J] over E_row, then the chain's next pivot block E_next - g^2 H_row formed
 // (tile (0, 0) inverted).  lds: the workgroup's operand area, free when called.
-template <typename T, bool INV = true>
+template <typename T, bool NS, bool INV = true>
 __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const GJArgs& a, const GJJob& job, T* H,
                                       T* Sout, T* Pout, int* tbad, int I, int J, int k, T* lds, T* lds2, int w, int l)
 {
@@ -590,8 +594,8 @@ __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const G
             // a warm start exists once the chain is past its first row (the twist row
             // has two neighbours and no such inverse)
             const bool warm = job.dep_b < 0 && job.row != 0 && job.row != a.m - 1;
-            invert_pivot<T>(acc, lds, lds2, Pout, W ? W + (int64_t)(k + 1) * kTile * kTile : nullptr, nb, warm,
-                            a.flags, a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
+            invert_pivot<T, NS>(acc, lds, lds2, Pout, W ? W + (int64_t)(k + 1) * kTile * kTile : nullptr, nb, warm, a.flags,
+                                a.diag, max(0, min(a.n - kTile * (k + 1), kTile)), w, l, tbad);
         }
         return;
     }
@@ -641,17 +645,19 @@ __device__ inline void gj_finish_tile(typename Frag<T>::acc_t (&acc)[4], const G
     store_acc<T>(acc, Sout, n_p, r0, c0, w, l);
     // tile 0 of the next row's pivot block, from this row's inverse of its tile 0
     if (INV && I == 0 && J == 0)
-        invert_pivot<T>(acc, lds, lds2, Pout, W, nb, true, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
+        invert_pivot<T, NS>(acc, lds, lds2, Pout, W, nb, true, a.flags, a.diag, min(a.n, kTile), w, l, tbad);
 }
 
 // Pivot block k of the current row of every job; parity = (step*nb + k) & 1.
-template <typename T>
-__global__ __launch_bounds__(256, 2) void gj_step_kernel(GJArgs a, int nj, int step, int k)
+template <typename T, bool NS>
+__global__ __launch_bounds__(256, NS ? 2 : 3) void gj_step_kernel(GJArgs a, int nj, int step, int k)
 {
-    // B operands (the A operands go from memory straight into registers); both areas
-    // also serve the pivot-tile inversion, sA the staged output tiles.
-    __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
+    // B operands (the A operands go from memory straight into registers), also the
+    // area of the pivot-tile inversion and of the staged output tiles; the
+    // Newton-Schulz round (NS) needs a second area.
     __shared__ __align__(32) T sB[kTile * kLd + 4 * kTile];
+    __shared__ __align__(32) T sA[NS ? kTile * kLd + 4 * kTile : 1];
+    T* const area = NS ? sA : sB;
     const int nb = a.nb, n_p = a.n_p;
     // the pivot tile this launch's inverting workgroups own: (k+1, k+1), or (0, 0) of
     // the next row's pivot block after the last pivot of a row
@@ -714,7 +720,7 @@ __global__ __launch_bounds__(256, 2) void gj_step_kernel(GJArgs a, int nj, int s
         load_acc<T>(acc, Pin, kTile, 0, 0, w, l);       // P^{-1}
     }
 
-    gj_finish_tile<T>(acc, a, job, H, Sout, Pout, tbad, I, J, k, sA, sB, w, l);
+    gj_finish_tile<T, NS>(acc, a, job, H, Sout, Pout, tbad, I, J, k, area, sB, w, l);
 }
 
 // Column workgroups of a batch (eight jobs or more, nb >= 3): one workgroup per
@@ -759,7 +765,7 @@ inline dim3 gj_col_grid(int nj, int nb, int batch)
 // The same products as gj_step_kernel's, in the same order, so the same bits; the
 // column's three other workgroups there each form X again.  The tile to invert at
 // the end of the launch is the column's last.
-template <typename T>
+template <typename T, bool NS>
 __global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int step, int k)
 {
     __shared__ __align__(32) T sA[kTile * kLd + 4 * kTile];
@@ -828,7 +834,7 @@ __global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int st
             const int kk = out_row<T>(w, l, v);
             sB[(16 * C + (l & 15)) * kLd + (kk & ~15) + Frag<T>::slot(kk & 15)] = x[C][v];
         }
-    gj_finish_tile<T, false>(x, a, job, H, Sout, Pout, tbad, k, J, k, sA, sB, w, l);   // row k: never inverted
+    gj_finish_tile<T, NS, false>(x, a, job, H, Sout, Pout, tbad, k, J, k, sA, sB, w, l);   // row k: never inverted
 
     // the other rows, the inverted tile's row after them
     auto update = [&](int I, acc_t (&ac)[4]) {
@@ -844,15 +850,32 @@ __global__ __launch_bounds__(256, 2) void gj_col_kernel(GJArgs a, int nj, int st
         const int I = row_at(t);
         acc_t ac[4];
         update(I, ac);
-        gj_finish_tile<T, false>(ac, a, job, H, Sout, Pout, tbad, I, J, k, sA, sB, w, l);
+        gj_finish_tile<T, NS, false>(ac, a, job, H, Sout, Pout, tbad, I, J, k, sA, sB, w, l);
     }
     if (srow >= 0) {
         acc_t ac[4];
         update(srow, ac);
-        gj_finish_tile<T>(ac, a, job, H, Sout, Pout, tbad, srow, J, k, sA, sB, w, l);
+        gj_finish_tile<T, NS>(ac, a, job, H, Sout, Pout, tbad, srow, J, k, sA, sB, w, l);
     }
 }
 
+
+// One pivot-block launch: column or tile workgroups, with the Newton-Schulz pivot tiles
+// when the jobs carry warm-start slots.
+template <typename T>
+void launch_step(const GJArgs& f, int nj, int st, int k, bool cols, hipStream_t s)
+{
+    const int nb = f.nb, tiles = nb * nb;
+    const bool ns = f.job[0].W != nullptr;
+    if (cols && ns)
+        hipLaunchKernelGGL((gj_col_kernel<T, true>), gj_col_grid(nj, nb, f.batch), dim3(256), 0, s, f, nj, st, k);
+    else if (cols)
+        hipLaunchKernelGGL((gj_col_kernel<T, false>), gj_col_grid(nj, nb, f.batch), dim3(256), 0, s, f, nj, st, k);
+    else if (ns)
+        hipLaunchKernelGGL((gj_step_kernel<T, true>), gj_grid(nj, tiles, f.batch), dim3(256), 0, s, f, nj, st, k);
+    else
+        hipLaunchKernelGGL((gj_step_kernel<T, false>), gj_grid(nj, tiles, f.batch), dim3(256), 0, s, f, nj, st, k);
+}
 
 template <typename T>
 hipError_t launch_factor(GJArgs a, hipStream_t s)
@@ -890,10 +913,7 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
         }
         const bool cols = nj * a.batch >= 8 && nb >= 3;
         for (int k = 0; k < nb; ++k) {
-            if (cols)
-                hipLaunchKernelGGL(gj_col_kernel<T>, gj_col_grid(nj, nb, a.batch), dim3(256), 0, s, f, nj, st, k);
-            else
-                hipLaunchKernelGGL(gj_step_kernel<T>, gj_grid(nj, tiles, a.batch), dim3(256), 0, s, f, nj, st, k);
+            launch_step<T>(f, nj, st, k, cols, s);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -907,10 +927,7 @@ hipError_t launch_factor(GJArgs a, hipStream_t s)
     hipLaunchKernelGGL(gj_form_kernel<T>, gj_grid(1, tiles, a.batch), dim3(256), 0, s, f, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int k = 0; k < nb; ++k) {
-        if (a.batch >= 8 && nb >= 3)
-            hipLaunchKernelGGL(gj_col_kernel<T>, gj_col_grid(1, nb, a.batch), dim3(256), 0, s, f, 1, 0, k);
-        else
-            hipLaunchKernelGGL(gj_step_kernel<T>, gj_grid(1, tiles, a.batch), dim3(256), 0, s, f, 1, 0, k);
+        launch_step<T>(f, 1, 0, k, a.batch >= 8 && nb >= 3, s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

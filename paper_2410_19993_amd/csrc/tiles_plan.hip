@@ -67,6 +67,8 @@ struct PipeBuffers {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+constexpr int64_t kNsPivotJobs = 512;    // largest batch (jobs per launch) with warm-started pivot tiles
+
 // Gt[t][j'][i'] = G[t][m-1-i'][n-1-j']: the crossbar turned by a half turn and transposed
 __global__ void rotate_transpose_kernel(const double* __restrict__ G, double* __restrict__ Gt, int T, int m, int n)
 {
@@ -347,7 +349,12 @@ xbar_status xbar_tiles_create(const xbar_tile_class* classes, int32_t nclasses, 
                 A(&b.S[ch][q], T * n_p * n_p * 8);
                 A(&b.P[ch][q], T * xbk::kTile * xbk::kTile * 8);
             }
-            A(&b.W[ch], T * 2 * b.nb * xbk::kTile * xbk::kTile * 8);
+            // Newton-Schulz pivot tiles pay where a launch waits on its pivot inversions:
+            // up to kNsPivotJobs jobs (a launch has one inversion per job).  Larger
+            // batches fill the chip with updates, and the round's four products cost
+            // more than the elimination (1024 maps of 128 x 128: 8.6k against 9.8k
+            // maps/s); without slots every pivot tile is eliminated.
+            if (2 * T <= kNsPivotJobs) A(&b.W[ch], T * 2 * b.nb * xbk::kTile * xbk::kTile * 8);
         }
         A(&b.Z, T * b.slabs * m * 16 * n_p * 8);
         A((void**)&b.flags, xbk::kNumFlags * sizeof(int));

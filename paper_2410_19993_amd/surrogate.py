@@ -23,6 +23,8 @@ exceeds a tolerance.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 
 from . import _check_tensor, _lib
@@ -345,6 +347,8 @@ def solver_dataset(maps: int, vectors: int, m: int, n: int, seed: int, r_levels=
     rm = levels[rng.integers(0, len(levels), maps)]
     Vd = torch.from_numpy(Vm).cuda()
     Id = torch.empty((maps, vectors, n), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for lv in np.unique(rm):
         idx = np.nonzero(rm == lv)[0]
         if method == "lanes":
@@ -364,10 +368,14 @@ def solver_dataset(maps: int, vectors: int, m: int, n: int, seed: int, r_levels=
         finally:
             for tb in batches.values():
                 tb.close()
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
     if not bool(torch.isfinite(Id).all()):
         raise RuntimeError("solver_dataset: a label is not finite (a map the solver rejected)")
-    return Dataset(Gd, torch.from_numpy(rm).cuda(), Vd.reshape(maps * vectors, m), Id.reshape(maps * vectors, n),
-                   vectors)
+    ds = Dataset(Gd, torch.from_numpy(rm).cuda(), Vd.reshape(maps * vectors, m), Id.reshape(maps * vectors, n),
+                 vectors)
+    ds.solve_seconds = solve_s           # the solver's share: the maps are drawn on the host before
+    return ds
 
 
 def targets_of(ds: Dataset):

@@ -86,6 +86,25 @@ def test_column_factor_matches_tile_factor_bits(m, n):
     log(f"  bitwise equal; max current rel err {_check([(m, n, 9, 24)], [(G, V)], out):.3e}")
 
 
+@pytest.mark.parametrize("m,n", [(6, 130), (7, 100)])
+def test_large_batch_eliminates_every_pivot_tile(m, n):
+    """Above 256 crossbars a class's pivot tiles are all eliminated (no Newton-Schulz
+    slots): 300 crossbars with three (column workgroups) or two (tile workgroups)
+    64-column blocks; sampled crossbars across the batch meet the oracle."""
+    from paper_2410_19993_amd.tiles import TileConfig
+    T, B = 300, 4
+    G, V = _class(m, n, T, B, seed=371 + n)
+    log(f"case large batch: {T} crossbars of {m}x{n}")
+    out, _ = _run([(m, n, T, B)], [(G, V)], configs=[TileConfig("pipeline")], streams=1)
+    assert np.all(np.isfinite(out[0]))
+    worst = 0.0
+    for t in (0, 1, 7, 8, 150, 298, 299):
+        ref = oracle.solve(G[t], V[t], *R).currents
+        worst = max(worst, float(rel_err(out[0][t], ref).max()))
+    log(f"  sampled max current rel err {worst:.3e}")
+    assert worst <= TOL_FP64
+
+
 @pytest.mark.parametrize("method", ["one_wg", "pipeline"])
 def test_reciprocal_classes_against_oracle(method):
     """Classes solved through their reciprocal problem (the turned, transposed crossbar
