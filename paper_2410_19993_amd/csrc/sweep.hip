@@ -59,12 +59,20 @@ __device__ __forceinline__ typename Vec4<T>::type load_frag(const T* __restrict_
 // and the last DP chunks of Hi are followed by the first DP of Hnext, so the
 // next row's loads are in flight during the barriers and bookkeeping between
 // products.
-template <typename T> struct SweepRing { static constexpr int value = 2; };
+constexpr int kRing = 2;        // chunk-sets of H in flight per wave
 
-template <typename T, int NT, int TW>
+// Matrix-core waves per workgroup: 8 for even n_p / 64 (n_p / 128 row tiles each);
+// for odd n_p / 64 either n_p / 64 waves of 4 tiles or (n_p = 320) 4 waves of 5
+// tiles, whichever keeps the accumulators and the H ring without spills next to
+// the helper waves.
+template <int NT> struct SweepWaves { static constexpr int value = (NT % 2 == 0) ? 8 : (NT == 5 ? 4 : NT); };
+// The refinement sweeps keep two panels, so that a row's panel update needs one
+// barrier: the panel written is the one the product before the previous barrier read.
+template <bool IR> struct SweepPanels { static constexpr int value = IR ? 2 : 1; };
+
+template <typename T, int NT, int TW, int DP>
 struct HRing {
     using v4 = typename Vec4<T>::type;
-    static constexpr int DP = SweepRing<T>::value;
     v4 r[DP][TW];
     __device__ __forceinline__ void prime(const T* __restrict__ Hi, int w, int l) {
 #pragma unroll
@@ -81,8 +89,8 @@ struct NoHook {
 // hook(K) runs after the products of chunk K have been issued (K is a
 // compile-time constant once the loop is unrolled), so that independent
 // work can fill the matrix-core loop.
-template <typename T, int NT, int TW, typename Hook>
-__device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW], HRing<T, NT, TW>& ring,
+template <typename T, int NT, int TW, int DP, typename Hook>
+__device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW], HRing<T, NT, TW, DP>& ring,
                                               const T* __restrict__ Hi, const T* __restrict__ Hnext,
                                               const T* ybuf, int ldy, int w, int l, const Hook& hook)
 {
@@ -90,7 +98,6 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
     using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT;
     constexpr int KC = n_p / 16;
-    constexpr int DP = SweepRing<T>::value;
     static_assert(KC % DP == 0, "chunk count must be a multiple of the ring depth");
     const int q = l >> 4, r = l & 15;
 #pragma unroll
@@ -101,6 +108,10 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
         for (int d = 0; d < DP; ++d) {
             const int K = K0 + d;
             const v4 bv = *reinterpret_cast<const v4*>(ybuf + r * ldy + 16 * K + 4 * q);
+            // chunk K + DP: of this block, or of the next one (one load site, a selected
+            // block pointer: the float64 waves need the registers this saves)
+            const T* Hl = K + DP < KC ? Hi : Hnext;
+            const int cn = K + DP < KC ? K + DP : K + DP - KC;
             if constexpr (sizeof(T) == 4) {
                 // float32: tile by tile, the tile's products and then the load of its
                 // chunk K + DP, with a scheduling fence after every second tile, so that
@@ -110,8 +121,7 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
                 for (int t = 0; t < TW; ++t) {
 #pragma unroll
                     for (int s = 0; s < 4; ++s) acc[t] = Frag<T>::mma(ring.r[d][t][s], bv[s], acc[t]);
-                    ring.r[d][t] = K + DP < KC ? load_frag<T>(Hi, KC, TW * w + t, K + DP, l)
-                                               : load_frag<T>(Hnext, KC, TW * w + t, K + DP - KC, l);
+                    ring.r[d][t] = load_frag<T>(Hl, KC, TW * w + t, cn, l);
                     if (t & 1) __builtin_amdgcn_sched_barrier(0);
                 }
             } else {
@@ -119,13 +129,8 @@ __device__ __forceinline__ void panel_product(typename Frag<T>::acc_t (&acc)[TW]
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
                     for (int t = 0; t < TW; ++t) acc[t] = Frag<T>::mma(ring.r[d][t][s], bv[s], acc[t]);
-                if (K + DP < KC) {
 #pragma unroll
-                    for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hi, KC, TW * w + t, K + DP, l);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hnext, KC, TW * w + t, K + DP - KC, l);
-                }
+                for (int t = 0; t < TW; ++t) ring.r[d][t] = load_frag<T>(Hl, KC, TW * w + t, cn, l);
             }
             hook(K);
         }
@@ -179,6 +184,7 @@ struct SweepCtx {
     static constexpr int n_p = 64 * NT;
     static constexpr int ldy = n_p + 4;
     static constexpr int TW = 4 * NT / W;    // row tiles per wave
+    static constexpr bool DB = SweepPanels<IR>::value == 2;
     const SweepArgs& a;
     T* ybuf;          // [16][ldy] right-hand side / solution panel
     T* Zs;
@@ -188,6 +194,7 @@ struct SweepCtx {
     T g;
     double dmax = 0.0, umax = 0.0;           // refinement: largest correction and solution entry
     double dbad = 0.0;                       // 0, or NaN once a correction entry was not finite
+    T* yalt = nullptr;                       // two panels: the one the next update writes
 
     // Lane (q, col) of wave w holds rows row_of(t, v) of tile t, item v.  In panel
     // (CPR) order those rows sit at poff + 16 t + v, so every panel access is a
@@ -202,7 +209,10 @@ struct SweepCtx {
     }
 
     // ---- forward sweep
-    // this lane's rows of the right-hand side of row block i: V_i c_i, or the residual R_i
+    // this lane's rows of the right-hand side of row block i: V_i c_i, or the residual R_i.
+    // LAST = false: i is known not to be the last row (the loads inside the chains,
+    // which overlap a product and must not add to its registers).
+    template <bool LAST = true>
     __device__ __forceinline__ void load_rhs(int i, T (&f)[TW][4]) const {
         if (IR && a.iter > 0) {
             const T* Ri = reinterpret_cast<const T*>(a.R) + slab_row(i);
@@ -212,15 +222,23 @@ struct SweepCtx {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) f[t][v] = row_of(t, v) < a.n ? Ri[o + 16 * t + v] : (T)0;
         } else if (a.term) {
-            // reciprocal ordering: g_sense V[b][n-1-k] at the last row only
-            const double* Vb = a.V + (int64_t)b * a.n;
+            // reciprocal ordering: g_sense V[b][n-1-k] at the last row only (clamped
+            // indices keep every load in bounds)
+            const double* Vb = a.V + (int64_t)(bval ? b : 0) * a.n + (a.n - 1);
 #pragma unroll
             for (int t = 0; t < TW; ++t)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int k = row_of(t, v);
-                    f[t][v] = (T)((bval && i == a.m - 1 && k < a.n) ? a.g_sense * Vb[a.n - 1 - k] : 0.0);
-                }
+                for (int v = 0; v < 4; ++v) f[t][v] = (T)0;
+            if (LAST && i == a.m - 1) {
+#pragma unroll
+                for (int t = 0; t < TW; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int k = row_of(t, v);
+                        const double x = Vb[-min(k, a.n - 1)];
+                        f[t][v] = (T)((bval && k < a.n) ? a.g_sense * x : 0.0);
+                    }
+            }
         } else {
             const double vb = vin(i);
             const double* ci = a.c + (int64_t)i * n_p;         // zero on the padding
@@ -233,7 +251,10 @@ struct SweepCtx {
     // panel <- f + g * zacc (+ g * the forward results of rows zrow_a, zrow_b: the twist)
     __device__ __forceinline__ void set_panel(const T (&f)[TW][4], const acc_t (&zacc)[TW], bool with_acc,
                                               int zrow_a, int zrow_b) {
-        lds_barrier();
+        // one panel: wait until every wave has read it; two: the other one was last
+        // read by the product before the previous barrier
+        if (!DB) lds_barrier();
+        T* dst = DB ? yalt : ybuf;
         const uint32_t o = lane_off(), lo = (uint32_t)(col * ldy) + poff();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
@@ -243,9 +264,13 @@ struct SweepCtx {
                 if (with_acc) y += g * zacc[t][v];
                 if (zrow_a >= 0) y += g * zbase(zrow_a)[o + 16 * t + v];
                 if (zrow_b >= 0) y += g * zbase(zrow_b)[o + 16 * t + v];
-                ybuf[lo + 16 * t + v] = y;
+                dst[lo + 16 * t + v] = y;
             }
         lds_barrier();
+        if (DB) {
+            yalt = ybuf;
+            ybuf = dst;
+        }
     }
     // z_i is read back only in the back sweep: streamed past L2 so that it does not
     // displace the H blocks the workgroups share
@@ -285,13 +310,18 @@ struct SweepCtx {
     }
     // panel <- u
     __device__ __forceinline__ void put_panel(const acc_t (&u)[TW]) {
-        lds_barrier();
+        if (!DB) lds_barrier();
+        T* dst = DB ? yalt : ybuf;
         const uint32_t lo = (uint32_t)(col * ldy) + poff();
 #pragma unroll
         for (int t = 0; t < TW; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ybuf[lo + 16 * t + v] = u[t][v];
+            for (int v = 0; v < 4; ++v) dst[lo + 16 * t + v] = u[t][v];
         lds_barrier();
+        if (DB) {
+            yalt = ybuf;
+            ybuf = dst;
+        }
     }
     // Row i of the back sweep is final in u: emit the currents of row m-1, or (when
     // refining) add the correction to the float64 solution.
@@ -367,12 +397,48 @@ struct SweepCtx {
     }
 };
 
-// Matrix-core waves per workgroup: 8 for even n_p / 64 (n_p / 128 row tiles each);
-// for odd n_p / 64 either n_p / 64 waves of 4 tiles or (n_p = 320) 4 waves of 5
-// tiles, whichever keeps the accumulators and the H ring without spills next to
-// the helper waves.
-template <int NT> struct SweepWaves { static constexpr int value = (NT % 2 == 0) ? 8 : (NT == 5 ? 4 : NT); };
 constexpr int kHelpers = 4;      // helper waves of the float64 sweep (one per SIMD)
+// The refinement sweeps recover no word lines and have no helper waves: their
+// matrix-core waves pull the H blocks into L2 themselves (measured faster than
+// helpers doing it, at two waves per SIMD instead of three).
+template <bool IR> struct SweepHelpers { static constexpr int value = IR ? 0 : kHelpers; };
+
+// Pull this workgroup's share of an H block into L2 with WAVES waves: one 4-byte
+// load per 128-byte line.  The loads are issued before the work they overlap and
+// their values consumed after it, so no wave waits on them.  A single crossbar's
+// slabs (workgroups b, b + 8, ... on one XCD) take 1/32 of the block each; in a
+// batch a crossbar's slabs share one XCD and take 1/16 each.
+template <typename T, int NT, int WAVES>
+struct L2Pull {
+    static constexpr size_t LINE = 128;
+    static constexpr size_t STEP = (size_t)WAVES * 64 * LINE;
+    static constexpr size_t BLK = (size_t)(64 * NT) * (64 * NT) * sizeof(T);
+    static constexpr size_t SHARE = ((BLK / 32) + LINE - 1) & ~(LINE - 1);
+    static constexpr size_t SHARE_B = ((BLK / 16) + LINE - 1) & ~(LINE - 1);
+    static constexpr int IT = (int)((SHARE_B + STEP - 1) / STEP);
+    uint32_t pv[IT];
+    uint32_t keep = 0;                        // xor of the pulled words (kept live)
+    __device__ __forceinline__ void issue(const SweepArgs& a, const T* blk, int wv, int l) {
+        const char* p = reinterpret_cast<const char*>(blk);
+        const bool batched = a.batch > 1;
+        const size_t share = batched ? SHARE_B : SHARE;
+        const size_t lo = batched ? SHARE_B * ((size_t)a.slab & 15) : SHARE * (((size_t)blockIdx.x >> 3) & 31);
+        const size_t hi = min(BLK, lo + share);
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const size_t off = lo + ((size_t)it * WAVES + wv) * 64 * LINE + LINE * (size_t)l;
+            pv[it] = (blk != nullptr && off < hi) ? *reinterpret_cast<const uint32_t*>(p + off) : 0u;
+        }
+    }
+    __device__ __forceinline__ void consume() {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) keep ^= pv[it];
+    }
+    // a store that never happens but keeps the loads
+    __device__ __forceinline__ void retire(const SweepArgs& a, int l) const {
+        if (keep == 0x9e3779b9u) a.sink[l] = (double)keep;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Schedule of the float64 sweep as pairs of workgroup barriers (a panel update
@@ -441,36 +507,7 @@ struct SweepHelper {
     const T* ybuf;
     double* wv;                               // [16][PL] word-line buffers
     int h, l, lg, PL;
-    uint32_t keep = 0;                        // xor of the prefetched words (kept live)
-
-    // Pull this workgroup's 1/32 share of an H block into L2: one 4-byte load per
-    // 128-byte line.  The loads are issued before the task's recovery and their
-    // values consumed after it, so the helper never waits on them.
-    // A single crossbar's slabs (workgroups b, b + 8, ... on one XCD) take 1/32 of the
-    // block each; in a batch a crossbar's slabs share one XCD and take 1/16 each.
-    static constexpr size_t LINE = 128;
-    static constexpr size_t STEP = (size_t)kHelpers * 64 * LINE;
-    static constexpr size_t BLK = (size_t)n_p * n_p * sizeof(T);
-    static constexpr size_t SHARE = ((BLK / 32) + LINE - 1) & ~(LINE - 1);
-    static constexpr size_t SHARE_B = ((BLK / 16) + LINE - 1) & ~(LINE - 1);
-    static constexpr int PULL_IT = (int)((SHARE_B + STEP - 1) / STEP);
-    uint32_t pv[PULL_IT];
-    __device__ __forceinline__ void pull_issue(const T* blk) {
-        const char* p = reinterpret_cast<const char*>(blk);
-        const bool batched = a.batch > 1;
-        const size_t share = batched ? SHARE_B : SHARE;
-        const size_t lo = batched ? SHARE_B * ((size_t)a.slab & 15) : SHARE * (((size_t)blockIdx.x >> 3) & 31);
-        const size_t hi = min(BLK, lo + share);
-#pragma unroll
-        for (int it = 0; it < PULL_IT; ++it) {
-            const size_t off = lo + ((size_t)it * kHelpers + h) * 64 * LINE + LINE * (size_t)l;
-            pv[it] = (blk != nullptr && off < hi) ? *reinterpret_cast<const uint32_t*>(p + off) : 0u;
-        }
-    }
-    __device__ __forceinline__ void pull_consume() {
-#pragma unroll
-        for (int it = 0; it < PULL_IT; ++it) keep ^= pv[it];
-    }
+    L2Pull<T, NT, kHelpers> pull;             // this workgroup's share of the next H block
     // Row coefficients of T_i (fr, ip) and the devices G of the row recovered after the
     // next barrier pair: requested at the start of a task, written to the free half of
     // the double-buffered LDS copy at its end, published by the next barrier pair.
@@ -613,13 +650,13 @@ struct SweepHelper {
             // during the product after pair p: the block of the next product
             int nb = sp.product_after(p + 1);
             if (nb < 0 && p + 2 < np) nb = sp.product_after(p + 2);
-            pull_issue(nb >= 0 ? H + (int64_t)nb * n_p * n_p : nullptr);
+            pull.issue(a, nb >= 0 ? H + (int64_t)nb * n_p * n_p : nullptr, h, l);
             const int r = sp.recover_after(p);
             if (rec && r >= 0) recover(r, p & 1);
-            pull_consume();
+            pull.consume();
             if (rn >= 0) stage_store((p + 1) & 1);
         }
-        if (keep == 0x9e3779b9u) a.sink[l] = (double)keep;   // keeps the prefetch loads
+        pull.retire(a, l);
     }
 };
 
@@ -629,7 +666,7 @@ template <typename T, int NT, bool IR>
 __host__ __device__ inline size_t sweep_lds_bytes(int n)
 {
     constexpr int W = SweepWaves<NT>::value;
-    const size_t panel = 16 * (size_t)(64 * NT + 4) * sizeof(T);
+    const size_t panel = SweepPanels<IR>::value * 16 * (size_t)(64 * NT + 4) * sizeof(T);
     const size_t extra = IR ? 2 * 16 * W * sizeof(double)
                             : (16 + 2 * 3) * (size_t)padded_len(n, SweepHelper<T, NT>::LR) * sizeof(double);
     return panel + extra;
@@ -660,9 +697,11 @@ __device__ __forceinline__ bool batch_slab(SweepArgs& a)
 }
 
 template <typename T, int NT, bool IR, bool REC>
-__global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(64 * (SweepWaves<NT>::value + SweepHelpers<IR>::value)) void sweep_kernel(SweepArgs a)
 {
     constexpr int W = SweepWaves<NT>::value;
+    constexpr int NH = SweepHelpers<IR>::value;
+    constexpr int DP = kRing;
     extern __shared__ __align__(32) unsigned char smem_raw[];
     using acc_t = typename Frag<T>::acc_t;
     using Ctx = SweepCtx<T, NT, IR, W>;
@@ -672,41 +711,51 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
     const int m = a.m, kt = m / 2;
     const int l = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    double* extra = reinterpret_cast<double*>(smem_raw + 16 * Ctx::ldy * sizeof(T));
-    if (wave >= W) {
-        // helper waves; in the refinement sweeps (no word-line recovery here) they only
-        // pull the H blocks into L2, and own no LDS
-        const int PL = padded_len(a.n, SweepHelper<T, NT>::LR);
-        SweepHelper<T, NT> hp{a, reinterpret_cast<const T*>(smem_raw), extra, wave - W, l,
-                               seg_lg(a.n, SweepHelper<T, NT>::LR), PL};
-        hp.coef = extra + 16 * PL;
-        // the helpers' latency-bound work gets issue priority over the matrix-core
-        // waves, which have independent work queued behind every instruction
-        __builtin_amdgcn_s_setprio(3);
-        hp.run(REC && !IR, IR || REC);
-        return;
+    double* extra = reinterpret_cast<double*>(smem_raw + SweepPanels<IR>::value * 16 * Ctx::ldy * sizeof(T));
+    if constexpr (NH > 0) {
+        if (wave >= W) {
+            // helper waves (float64 sweep): word-line recovery and the H pulls
+            const int PL = padded_len(a.n, SweepHelper<T, NT>::LR);
+            SweepHelper<T, NT> hp{a, reinterpret_cast<const T*>(smem_raw), extra, wave - W, l,
+                                   seg_lg(a.n, SweepHelper<T, NT>::LR), PL};
+            hp.coef = extra + 16 * PL;
+            // the helpers' latency-bound work gets issue priority over the matrix-core
+            // waves, which have independent work queued behind every instruction
+            __builtin_amdgcn_s_setprio(3);
+            hp.run(REC, REC);
+            return;
+        }
     }
     Ctx x{a, reinterpret_cast<T*>(smem_raw),
           reinterpret_cast<T*>(a.Z) + (int64_t)a.slab * m * 16 * Ctx::n_p,
           reinterpret_cast<const T*>(a.H), wave, l, l >> 4, l & 15,
           16 * a.slab + (l & 15), false, (T)a.g_bl};
     x.bval = x.b < a.B;
+    if constexpr (Ctx::DB) x.yalt = x.ybuf + 16 * Ctx::ldy;
     const int64_t blk = (int64_t)Ctx::n_p * Ctx::n_p;
     auto Hb = [&](int i) { return x.H + i * blk; };
     acc_t acc[TW];
     T f[TW][4];
     const NoHook none{};
     // H blocks in sweep order: 0..kt-1, m-1..kt+1, kt, kt-1..0, kt+1..m-1
-    HRing<T, NT, TW> ring;
+    HRing<T, NT, TW, DP> ring;
     ring.prime(Hb(kt > 0 ? 0 : (m - 1 > kt ? m - 1 : kt)), x.w, l);
+    // the product of row i; block nx follows it.  Without helper waves, the share of
+    // block nx is pulled into L2 during the product.
+    L2Pull<T, NT, W> pull;
+    auto product = [&](acc_t (&out)[TW], int i, int nx) {
+        if constexpr (NH == 0) pull.issue(a, Hb(nx), x.w, l);
+        panel_product<T, NT, TW>(out, ring, Hb(i), Hb(nx), x.ybuf, Ctx::ldy, x.w, l, none);
+        if constexpr (NH == 0) pull.consume();
+    };
     // forward, top chain
     if (kt > 0) {
         x.load_rhs(0, f);
         x.set_panel(f, acc, false, -1, -1);
         for (int i = 0; i < kt; ++i) {
-            if (i + 1 < kt) x.load_rhs(i + 1, f);
+            if (i + 1 < kt) x.template load_rhs<false>(i + 1, f);
             const int nx = i + 1 < kt ? i + 1 : (m - 1 > kt ? m - 1 : kt);
-            panel_product<T, NT, TW>(acc, ring, Hb(i), Hb(nx), x.ybuf, Ctx::ldy, x.w, l, none);
+            product(acc, i, nx);
             x.store_z(i, acc);
             if (i + 1 < kt) x.set_panel(f, acc, true, -1, -1);
         }
@@ -716,8 +765,8 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
         x.load_rhs(m - 1, f);
         x.set_panel(f, acc, false, -1, -1);
         for (int i = m - 1; i > kt; --i) {
-            if (i - 1 > kt) x.load_rhs(i - 1, f);
-            panel_product<T, NT, TW>(acc, ring, Hb(i), Hb(i - 1 > kt ? i - 1 : kt), x.ybuf, Ctx::ldy, x.w, l, none);
+            if (i - 1 > kt) x.template load_rhs<false>(i - 1, f);
+            product(acc, i, i - 1 > kt ? i - 1 : kt);
             x.store_z(i, acc);
             if (i - 1 > kt) x.set_panel(f, acc, true, -1, -1);
         }
@@ -730,7 +779,7 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
     x.set_panel(f, acc, false, kt > 0 ? kt - 1 : -1, kt + 1 < m ? kt + 1 : -1);
     x.load_u(kt, up);
     const int after_twist = (UP && kt > 0) ? kt - 1 : (kt + 1 < m ? kt + 1 : kt);
-    panel_product<T, NT, TW>(acc, ring, Hb(kt), Hb(after_twist), x.ybuf, Ctx::ldy, x.w, l, none);
+    product(acc, kt, after_twist);
     if (UP) x.store_z(kt, acc);     // the downward back sweep restarts from this row
     x.settle(kt, acc, up);
     x.put_panel(acc);
@@ -741,9 +790,8 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
             if (IR) x.load_z(i, zp);    // refinement sweeps: no helpers, request z before the product
             x.load_u(i, up);
             acc_t u[TW];
-            panel_product<T, NT, TW>(u, ring, Hb(i), Hb(i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i)), x.ybuf,
-                                     Ctx::ldy, x.w, l, none);
-            if (!IR) x.load_z(i, zp);   // float64 sweep: the helpers have pulled z_i into L2
+            product(u, i, i > 0 ? i - 1 : (kt + 1 < m ? kt + 1 : i));
+            if (!IR) x.load_z(i, zp);   // float64 sweep: after the product (no registers to spare in it)
             x.back_step(zp, u);
             x.settle(i, u, up);
             x.put_panel(u);
@@ -764,7 +812,7 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
             T zp[TW][4];
             if (IR) x.load_z(i, zp);
             x.load_u(i, up);
-            panel_product<T, NT, TW>(acc, ring, Hb(i), Hb(i + 1 < m ? i + 1 : i), x.ybuf, Ctx::ldy, x.w, l, none);
+            product(acc, i, i + 1 < m ? i + 1 : i);
             if (!IR) x.load_z(i, zp);
             x.back_step(zp, acc);
             x.settle(i, acc, up);
@@ -772,6 +820,7 @@ __global__ __launch_bounds__(64 * (SweepWaves<NT>::value + kHelpers)) void sweep
         }
     }
     if (IR && a.tol >= 0.0) x.decide(extra);
+    if constexpr (NH == 0) pull.retire(a, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,7 +1104,7 @@ __global__ __launch_bounds__(256) void recover_kernel(RecoverArgs a)
 template <typename T, int NT, bool IR>
 hipError_t launch_sweep_nt(const SweepArgs& a, hipStream_t s)
 {
-    constexpr int threads = 64 * (SweepWaves<NT>::value + kHelpers);
+    constexpr int threads = 64 * (SweepWaves<NT>::value + SweepHelpers<IR>::value);
     const size_t lds = sweep_lds_bytes<T, NT, IR>(a.n);
     if constexpr (!IR) {
         if (a.node_v != nullptr) {
