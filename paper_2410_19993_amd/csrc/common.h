@@ -160,8 +160,6 @@ struct NSChain {
     void* S;
     void* X[2];
     void* Q;
-    void* Qt;
-    void* P2;
     double* dprev;       // [2][n_p] diagonal of the pivot block of chain row i at [i & 1]
 };
 
@@ -173,10 +171,10 @@ struct NSJob {
 
 // Device-driven schedules of the Newton-Schulz factor (top chain, bottom chain,
 // twist).  Each launch ("slot") of a schedule reads its state, does its phase
-// (form the pivot block and the first iterate, or one of the three launches of
-// a two-step round) and writes the next state into the other parity, so no
+// (form the pivot block and the first iterate, or one of the launches of a round
+// or step) and writes the next state into the other parity, so no
 // launch is spent on a row that has already converged.
-enum : int { kNsForm = 0, kNsResid = 1, kNsDouble = 2, kNsUpdate = 3, kNsFinished = 4 };
+enum : int { kNsForm = 0, kNsResid = 1, kNsQx = 2, kNsUpdate = 3, kNsFinished = 4 };
 struct NSState {
     int row;      // crossbar row being inverted
     int phase;    // kNs*

@@ -12,21 +12,22 @@
 //     D = diag(P_prev)^{-1}
 // (elementwise: for the 512 x 512 workload it takes max |I - X_0 P| from about
 // 6e-6 to 5e-9 at 2.5-ohm segments and from 1.5e-5 to 2.4e-8 at 5 ohm),
-// or from diag(P)^{-1} at a chain start and for the twist block.  Two steps are
-// taken together as a round of three launches,
-//     Q = I - X P;    Q^2 and Y = X + Q X;    X'' = Y + Q^2 Y = (I + Q^2)(I + Q) X,
-// whose residual is I - X'' P = Q^4 (the middle launch holds two products that
-// share their first operand), so a round costs four n_p^3 products and three
-// launches instead of four.  All products run on the matrix cores, spread over
-// all the GPU's workgroups; no small serial inversion sits on the critical path.
+// or from diag(P)^{-1} at a chain start and for the twist block.  float64 rows
+// take the third-order step as a round of three launches,
+//     Q = I - X P;    Y = Q X;    X'' = X + Y + Q Y = (I + Q + Q^2) X,
+// whose residual is I - X'' P = Q^3: three n_p^3 products in three launches (two
+// quadratic steps, with residual Q^4, cost four).  All products run on the matrix
+// cores, spread over all the GPU's workgroups; no small serial inversion sits on
+// the critical path.
 //
-// The largest |Q^2| entry of a round is reduced on the device (per-workgroup
-// partials, combined by every workgroup of the round's last launch).  When it is
-// <= 1e-9, ||Q^2||_inf <= n_p 1e-9 and the round leaves
-// ||I - X'' P||_inf <= (n_p 1e-9)^2 <= 2.7e-13 for n_p <= 512 (in practice
-// float64 rounding: consecutive pivots of a chain start the iteration at about
-// |Q| = 4e-6, so one round ends at rounding level).  The float32 factor of the
-// refinement mode stops at 1e-4 and relies on the refinement.  The result is
+// The largest |Q| entry of a round is reduced on the device (per-workgroup
+// partials of the residual launch, combined by every workgroup of the round's
+// last launch).  When it is <= 1.25e-7, ||Q||_inf <= n_p 1.25e-7 and the round
+// leaves ||I - X'' P||_inf <= (n_p 1.25e-7)^3 <= 2.7e-13 for n_p <= 512 (in
+// practice float64 rounding: the warm start begins a chain's rows at about
+// |Q| = 5e-9 to 2.4e-8, so one round ends at rounding level).  The float32 factor
+// of the refinement mode takes single quadratic steps, stops at 1e-4 and relies on
+// the refinement.  The result is
 // written over E_i.  A row still above the threshold after its last round raises
 // kNsFail, and the host then refactors with Gauss-Jordan elimination
 // (factor.hip).
@@ -44,26 +45,25 @@
 // factorization needed, reads the states back, and launches more until every
 // schedule has finished.
 //
-// Every block here (E_i, H_i, S, X, Q, Q^T, Q^2) is stored fragment-tiled (FRG),
-// and a product C = A B^T is formed with the A slot of the matrix cores fed from
-// tile rows of B and the B slot from tile rows of A, so that operand loads and
-// output stores are all contiguous 16-byte accesses.  Since S is symmetric,
-// X S^T = X S; Q X and Q^2 Y are formed as Q X^T and Q^2 Y^T, equal up to
-// rounding because the iteration keeps X and Y symmetric (X Q^T = Q X when X and
-// P are symmetric, so (I + Q) X and every iterate are); Q Q is formed from the
-// transpose that the residual launch stores next to Q.
+// Every block here (E_i, H_i, S, X, Q, Y) is stored fragment-tiled (FRG), and a
+// product C = A B^T is formed with the A slot of the matrix cores fed from tile
+// rows of B and the B slot from tile rows of A, so that operand loads and output
+// stores are all contiguous 16-byte accesses.  Since S is symmetric, X S^T = X S;
+// Q X and Q Y are formed as Q X^T and Q Y^T, equal up to rounding because the
+// iteration keeps X and Y symmetric (Q X = X - X P X is symmetric when X and P
+// are, and so is every iterate).
 #include <algorithm>
 
 #include "common.h"
 
 namespace xbk {
 
-constexpr double kNsDone = 1e-9;       // float64: see the bound above
+constexpr double kNsDone = 1.25e-7;    // float64: largest |Q| of a round, see the bound above
 constexpr double kNsDoneF32 = 1e-4;    // float32: at float rounding after the update
 
-// float64 rows take rounds of two steps (three launches); the float32 factor of
-// the refinement mode, whose loose tolerance a warm-started row meets after one
-// step, takes single steps (residual launch, update launch).
+// float64 rows take third-order rounds (three launches); the float32 factor of the
+// refinement mode, whose loose tolerance a warm-started row meets after one
+// quadratic step, takes single steps (residual launch, update launch).
 template <typename T>
 constexpr bool ns_rounds() { return sizeof(T) == 8; }
 
@@ -265,10 +265,10 @@ __device__ __forceinline__ void ns_tile_max(const NSArgs& a, int chain, int tile
     }
 }
 
-// Residual launch of a round:  Q = I - X S, its transpose, and the workgroup's max |Q|.
+// Residual launch:  Q = I - X S and the workgroup's max |Q|.
 template <typename T, int NT>
 __device__ __forceinline__ void ns_resid(const NSArgs& a, const NSChain& ch, int xb, int chain, int tile, T* red,
-                                         T* trn, double* wmax)
+                                         double* wmax)
 {
     using acc_t = typename Frag<T>::acc_t;
     constexpr int kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
@@ -280,69 +280,42 @@ __device__ __forceinline__ void ns_resid(const NSArgs& a, const NSChain& ch, int
     const acc_t sum = ns_reduce<T>(acc[0], red, w, l);
     const int tr = TR + (w >> 1), tc = TC + (w & 1);
     T* Q = reinterpret_cast<T*>(ch.Q);
-    T* Qt = reinterpret_cast<T*>(ch.Qt);
     T val[4];
-    T* tw = trn + w * 16 * 17;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int c = Frag<T>::kidx(q, v);
         val[v] = (T)(tr == tc && r == c ? 1 : 0) - sum[v];
         Q[((int64_t)tr * kt + tc) * 256 + frg_slot<T>(l, v)] = val[v];
-        tw[r * 17 + c] = val[v];
     }
-    if constexpr (!ns_rounds<T>()) {
-        ns_tile_max<T>(a, chain, tile, tiles, val, wmax, w, l);
-        return;
-    }
-    // the transposed tile through the wave's LDS scratch
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-        Qt[((int64_t)tc * kt + tr) * 256 + frg_slot<T>(l, v)] = tw[Frag<T>::kidx(q, v) * 17 + r];
     ns_tile_max<T>(a, chain, tile, tiles, val, wmax, w, l);
 }
 
-// Middle launch of a round:  P2 = Q Q and Y = X + Q X (into the other iterate
-// buffer), and the workgroup's max |P2|.
+// Middle launch of a round:  Y = Q X into the other iterate buffer.  It leaves the
+// residual launch's max |Q| partials in place for the last launch.
 template <typename T, int NT>
-__device__ __forceinline__ void ns_double(const NSArgs& a, const NSChain& ch, int xb, int chain, int tile, T* red,
-                                          double* wmax)
+__device__ __forceinline__ void ns_qx(const NSArgs& a, const NSChain& ch, int xb, int tile, T* red)
 {
     using acc_t = typename Frag<T>::acc_t;
-    constexpr int kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
+    constexpr int kt = 4 * NT, tdim = 2 * NT;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
     const T* X = reinterpret_cast<const T*>(ch.X[xb]);
     const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
-    T xin[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) xin[v] = X[base + frg_slot<T>(l, v)];
-    // Q Q = Q (Q^T)^T and Q X = Q X^T (X is symmetric)
-    const T* const Bm[2] = {reinterpret_cast<const T*>(ch.Qt), X};
-    acc_t acc[2][2][2];
-    ns_core<T, NT, 2>(reinterpret_cast<const T*>(ch.Q), Bm, TR, TC, w, l, acc);
-    const acc_t p2 = ns_reduce<T>(acc[0], red, w, l);
-    __syncthreads();
-    const acc_t qx = ns_reduce<T>(acc[1], red, w, l);
-    T* P2 = reinterpret_cast<T*>(ch.P2);
+    // Q X = Q X^T (X is symmetric)
+    const T* const Bm[1] = {X};
+    acc_t acc[1][2][2];
+    ns_core<T, NT, 1>(reinterpret_cast<const T*>(ch.Q), Bm, TR, TC, w, l, acc);
+    const acc_t qx = ns_reduce<T>(acc[0], red, w, l);
     T* Y = reinterpret_cast<T*>(ch.X[xb ^ 1]);
-    T val[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int64_t o = base + frg_slot<T>(l, v);
-        val[v] = p2[v];
-        P2[o] = p2[v];
-        Y[o] = xin[v] + qx[v];
-    }
-    ns_tile_max<T>(a, chain, tile, tiles, val, wmax, w, l);
+    for (int v = 0; v < 4; ++v) Y[base + frg_slot<T>(l, v)] = qx[v];
 }
 
-// Last launch of a round:  X'' = Y + P2 Y, whose residual is Q^4 (or, for single
-// steps, X' = X + Q X with residual Q^2: Am = Q, Y = X).  When the round converged
-// (the largest |entry| of P2, or of Q, read from the previous launch's partials,
-// is <= the tolerance) or was the last allowed, the result is H_row; the launch
+// Last launch of a round:  X'' = X + Y + Q Y with Y = Q X (Xadd = X), whose
+// residual is Q^3 (or, for single steps, X' = X + Q X with residual Q^2: Y = X,
+// Xadd = nullptr).  When the round converged (the largest |entry| of Q, read from
+// the residual launch's partials, is <= the tolerance) or was the last allowed,
+// the result is H_row; the launch
 // that finishes a row also forms the chain's next pivot block E_next - g^2 H and
 // first iterate H + diag(S)^-1 - diag(S_prev)^-1, element by element from its
 // tile of H (E_next is read before being overwritten by H_next, many launches
@@ -350,8 +323,8 @@ __device__ __forceinline__ void ns_double(const NSArgs& a, const NSChain& ch, in
 // workgroup).
 template <typename T, int NT>
 __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, const NSChain& ch, const T* Am,
-                                          const T* Y, T* Xout, int chain, int tile, bool last, int next_row, T* red,
-                                          double* wmax)
+                                          const T* Y, const T* Xadd, T* Xout, int chain, int tile, bool last,
+                                          int next_row, T* red, double* wmax)
 {
     using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT, kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
@@ -359,10 +332,10 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
     const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
     const int64_t base = ((int64_t)(TR + (w >> 1)) * kt + TC + (w & 1)) * 256;
     const int row = 16 * (TR + (w >> 1)) + (l & 15);
-    // the epilogue's operands (this tile of Y, of the next row's E block and the
-    // previous pivot diagonal) and the round's max |P2| partials are requested
+    // the epilogue's operands (this tile of Y and X, of the next row's E block and
+    // the previous pivot diagonal) and the round's max |Q| partials are requested
     // before the product, so that their latency hides behind it
-    T yin[4], en[4], sold[4];
+    T yin[4], xin[4], en[4], sold[4];
     double dpr = 1.0, dpc[4] = {1.0, 1.0, 1.0, 1.0};
     double mx = 0.0;
     for (int k = threadIdx.x; k < tiles; k += 256) {
@@ -376,6 +349,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         yin[v] = Y[base + frg_slot<T>(l, v)];
+        xin[v] = Xadd ? Xadd[base + frg_slot<T>(l, v)] : (T)0;
         en[v] = next_row >= 0 ? En[base + frg_slot<T>(l, v)] : (T)0;
         sold[v] = next_row >= 0 ? Sp[base + frg_slot<T>(l, v)] : (T)0;
         const int col = col0 + Frag<T>::kidx(l >> 4, v);
@@ -401,7 +375,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t o = base + frg_slot<T>(l, v);
-        const T x = yin[v] + sum[v];
+        const T x = (Xadd ? xin[v] + yin[v] : yin[v]) + sum[v];
         if (fin || last) Hr[o] = x;
         if (form) {
             const int col = col0 + Frag<T>::kidx(l >> 4, v);
@@ -438,7 +412,6 @@ __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int chain, int s
 {
     constexpr int tdim = 2 * NT;
     __shared__ __align__(16) T red[4 * 4 * 4 * 64];       // product partials [wave][output tile][item][lane]
-    __shared__ __align__(16) T trn[4 * 16 * 17];          // per-wave transpose scratch
     __shared__ double wmax[4];
     // XCD-aware tile map: workgroups are dispatched round-robin over the 8 XCDs
     // (each with its own L2), so workgroup b runs on XCD b % 8.  Each XCD owns a
@@ -463,23 +436,24 @@ __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int chain, int s
             ns_form<T>(a, job, ch, s.xb, (int64_t)tile * 256 + threadIdx.x, (int64_t)tiles * 256);
             ns = NSState{s.row, kNsResid, 0, s.xb, 0};
         } else if (s.phase == kNsResid) {
-            ns_resid<T, NT>(a, ch, s.xb, job.chain, tile, red, trn, wmax);
-            ns = NSState{s.row, ns_rounds<T>() ? kNsDouble : kNsUpdate, s.it, s.xb, 0};
-        } else if (s.phase == kNsDouble) {
-            ns_double<T, NT>(a, ch, s.xb, job.chain, tile, red, wmax);
+            ns_resid<T, NT>(a, ch, s.xb, job.chain, tile, red, wmax);
+            ns = NSState{s.row, ns_rounds<T>() ? kNsQx : kNsUpdate, s.it, s.xb, 0};
+        } else if (s.phase == kNsQx) {
+            ns_qx<T, NT>(a, ch, s.xb, tile, red);
             ns = NSState{s.row, kNsUpdate, s.it, s.xb, 0};
         } else {
-            // a round: X[xb] <- Y + P2 Y with Y in X[xb^1]; a single step: X[xb^1] <- X + Q X
+            // a round: X[xb] <- X + Y + Q Y with Y = Q X in X[xb^1] (in place: each
+            // workgroup reads only its own tile of X); a single step: X[xb^1] <- X + Q X
             constexpr int steps = ns_rounds<T>() ? 2 : 1;
             T* const X0 = reinterpret_cast<T*>(ch.X[s.xb]);
             T* const X1 = reinterpret_cast<T*>(ch.X[s.xb ^ 1]);
-            const T* Am = reinterpret_cast<const T*>(ns_rounds<T>() ? ch.P2 : ch.Q);
+            const T* Am = reinterpret_cast<const T*>(ch.Q);
             const int xo = ns_rounds<T>() ? s.xb : s.xb ^ 1;
             const int maxit = job.warm ? a.max_iter : a.max_iter + 4;
             const bool last = s.it + steps >= maxit;
             const int next_row = ns_fused_next(m, chain, s.row);
-            const bool fin = ns_update<T, NT>(a, job, ch, Am, ns_rounds<T>() ? X1 : X0, ns_rounds<T>() ? X0 : X1,
-                                              job.chain, tile, last, next_row, red, wmax);
+            const bool fin = ns_update<T, NT>(a, job, ch, Am, ns_rounds<T>() ? X1 : X0, ns_rounds<T>() ? X0 : nullptr,
+                                              ns_rounds<T>() ? X0 : X1, job.chain, tile, last, next_row, red, wmax);
             if (fin || last) {
                 if (!fin && tile == 0 && threadIdx.x == 0) atomicOr(a.flags + kNsFail, 1);
                 ns = ns_advance(m, chain, s.row, slot, xo);

@@ -35,8 +35,6 @@ struct Buffers {
     void* ns_S[2] = {nullptr, nullptr};
     void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* ns_Q[2] = {nullptr, nullptr};
-    void* ns_Qt[2] = {nullptr, nullptr};
-    void* ns_P2[2] = {nullptr, nullptr};
     double* ns_dprev[2] = {nullptr, nullptr};
     double* ns_part = nullptr;               // [2][(n_p/32)^2]
     xbk::NSState* ns_state = nullptr;        // [2 parities][3 schedules] schedule state
@@ -182,7 +180,7 @@ void free_all(xbar_plan p)
     void* all[] = {d.H, d.c, d.fr, d.ip, d.q, d.Gc, d.S[0][0], d.S[0][1], d.S[1][0], d.S[1][1],
                    d.P[0][0], d.P[0][1], d.P[1][0], d.P[1][1], d.Z, d.Iout, d.flags, d.diag, d.sink,
                    d.ns_S[0], d.ns_S[1], d.ns_X[0][0], d.ns_X[0][1], d.ns_X[1][0], d.ns_X[1][1],
-                   d.ns_Q[0], d.ns_Q[1], d.ns_Qt[0], d.ns_Qt[1], d.ns_P2[0], d.ns_P2[1],
+                   d.ns_Q[0], d.ns_Q[1],
                    d.ns_dprev[0], d.ns_dprev[1], d.ns_part, d.ns_state,
                    d.U[0], d.U[1], d.R, d.dnorm, d.slab_done, d.slab_final, d.Vunit,
                    d.gm_V, d.gm_Z, d.gm_zero, d.gm_part, d.gm_H, d.gm_beta, d.gm_y, d.gm_coef,
@@ -391,8 +389,6 @@ xbar_status xbar_create_ordered(const xbar_geometry* geom, xbar_precision prec, 
         A(&d.ns_X[c][0], n_p * n_p * es);
         A(&d.ns_X[c][1], n_p * n_p * es);
         A(&d.ns_Q[c], n_p * n_p * es);
-        A(&d.ns_Qt[c], n_p * n_p * es);
-        A(&d.ns_P2[c], n_p * n_p * es);
         A((void**)&d.ns_dprev[c], 2 * n_p * 8);
     }
     A((void**)&d.ns_part, 2 * (n_p / 32) * (n_p / 32) * 8);
@@ -525,8 +521,6 @@ xbk::NSArgs ns_args(xbar_plan p)
         a.ch[c].X[0] = p->d.ns_X[c][0];
         a.ch[c].X[1] = p->d.ns_X[c][1];
         a.ch[c].Q = p->d.ns_Q[c];
-        a.ch[c].Qt = p->d.ns_Qt[c];
-        a.ch[c].P2 = p->d.ns_P2[c];
         a.ch[c].dprev = p->d.ns_dprev[c];
     }
     a.state = p->d.ns_state;
