@@ -312,34 +312,34 @@ __device__ inline void acc_to_B(T* sB, const typename Frag<T>::acc_t (&x)[4], in
         }
 }
 
-constexpr double kTileNsDone = 1e-9;    // largest |Q^2| entry accepted
+constexpr double kTileNsDone = 2.5e-7;  // largest |Q| entry accepted
 
-// Inverse of the pivot tile P (in acc) by one Newton-Schulz round on the matrix cores,
-// from the chain's inverse Wk of the same tile one row earlier, corrected to first
-// order in the change of the tile with that inverse taken as its diagonal (Pk: the
-// tile one row earlier; consecutive rows' pivot tiles differ little, as the pivot
-// blocks do):
+// Inverse of the pivot tile P (in acc) by one third-order Newton-Schulz round on the
+// matrix cores, from the chain's inverse Wk of the same tile one row earlier,
+// corrected to first order in the change of the tile with that inverse taken as its
+// diagonal (Pk: the tile one row earlier; consecutive rows' pivot tiles differ
+// little, as the pivot blocks do):
 //     X0 = Wk + diag(P)^-1 - diag(Pk)^-1 - D offdiag(P - Pk) D,   D = diag(Pk)^-1,
-//     Q = I - X0 P,   P2 = Q Q,   Y = X0 + Q X0,   X = Y + P2 Y,   I - X P = Q^4.
-// Accepted when every |P2| entry is <= 1e-9, so ||Q^2||_inf <= 64e-9 and
+//     Q = I - X0 P,   Y = Q X0,   X = X0 + Y + Q Y,   I - X P = Q^3.
+// Accepted when every |Q| entry is <= 2.5e-7, so ||Q||_inf <= 1.6e-5 and
 // ||I - X P||_inf <= 4.1e-15 (on the 256 x 256 tiles of the tiles workload the
-// corrected start leaves |Q| <= 9e-9, so |Q^2| <= 1e-15 and X ends at rounding level;
-// uncorrected it would leave |Q^2| near 3e-8, and the test would fail every tile):
-// X goes to Pout and Wk, P to Pk, and the call returns true.  Otherwise (NaN included)
-// it writes nothing and returns false, and the caller eliminates.  Four 64 x 64 x 64
-// products against the 16 dependent elimination steps; no pivot is examined on this
-// path.  sA, sB: the workgroup's two operand areas.
+// corrected start leaves |Q| <= 9e-9, so X ends at rounding level; uncorrected it
+// would leave |Q| near 2e-4, and the test would fail every tile): X goes to Pout and
+// Wk, P to Pk, and the call returns true.  Otherwise (NaN included) it writes nothing
+// and returns false after the first product, and the caller eliminates.  Three
+// 64 x 64 x 64 products against the 16 dependent elimination steps; no pivot is
+// examined on this path.  sA, sB: the workgroup's two operand areas.
 template <typename T>
 __device__ bool ns_tile_inverse(const typename Frag<T>::acc_t (&P)[4], T* Wk, T* Pk, T* sA, T* sB, T* Pout, int w,
                                 int l)
 {
     using acc_t = typename Frag<T>::acc_t;
     __shared__ double wmx[4];
-    acc_t y[4], q[4], p2[4];
+    acc_t x[4], q[4], t[4];
     {
         acc_t pp[4];
         T dpr[4], dpc[4];
-        load_acc<T>(y, Wk, kTile, 0, 0, w, l);
+        load_acc<T>(x, Wk, kTile, 0, 0, w, l);
         load_acc<T>(pp, Pk, kTile, 0, 0, w, l);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -356,49 +356,47 @@ __device__ bool ns_tile_inverse(const typename Frag<T>::acc_t (&P)[4], T* Wk, T*
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (out_row<T>(w, l, v) == 16 * C + (l & 15))
-                    y[C][v] += (T)1 / P[C][v] - (T)1 / dpr[v];
+                    x[C][v] += (T)1 / P[C][v] - (T)1 / dpr[v];
                 else
-                    y[C][v] -= (P[C][v] - pp[C][v]) / (dpr[v] * dpc[C]);
+                    x[C][v] -= (P[C][v] - pp[C][v]) / (dpr[v] * dpc[C]);
             }
     }
     __syncthreads();                                    // the operand areas are free
-    acc_to_A<T>(sA, y, w, l);
+    acc_to_A<T>(sA, x, w, l);
     acc_to_B<T>(sB, P, w, l);
     __syncthreads();
 #pragma unroll
     for (int C = 0; C < 4; ++C) q[C] = acc_t{0, 0, 0, 0};
     tile_mma<T>(q, sA, sB, w, l);                       // X0 P
-#pragma unroll
-    for (int C = 0; C < 4; ++C)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) q[C][v] = (T)(out_row<T>(w, l, v) == 16 * C + (l & 15) ? 1 : 0) - q[C][v];
-    __syncthreads();
-    acc_to_A<T>(sA, q, w, l);
-    acc_to_B<T>(sB, q, w, l);
-    __syncthreads();
-#pragma unroll
-    for (int C = 0; C < 4; ++C) p2[C] = acc_t{0, 0, 0, 0};
-    tile_mma<T>(p2, sA, sB, w, l);                      // Q Q
     double mx = 0.0;
 #pragma unroll
     for (int C = 0; C < 4; ++C)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) mx = nan_max(mx, fabs((double)p2[C][v]));
+        for (int v = 0; v < 4; ++v) {
+            q[C][v] = (T)(out_row<T>(w, l, v) == 16 * C + (l & 15) ? 1 : 0) - q[C][v];
+            mx = nan_max(mx, fabs((double)q[C][v]));
+        }
     for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
     if (l == 0) wmx[w] = mx;
-    __syncthreads();                                    // Q in sB read; wmx written
-    acc_to_B<T>(sB, y, w, l);
-    __syncthreads();
-    tile_mma<T>(y, sA, sB, w, l);                       // Y = X0 + Q X0
+    __syncthreads();                                    // X0 and P read; wmx written
     const double nu = nan_max(nan_max(wmx[0], wmx[1]), nan_max(wmx[2], wmx[3]));
     if (!(nu <= kTileNsDone)) return false;             // the same answer in every wave
+    acc_to_A<T>(sA, q, w, l);
+    acc_to_B<T>(sB, x, w, l);
     __syncthreads();
-    acc_to_A<T>(sA, p2, w, l);
-    acc_to_B<T>(sB, y, w, l);
+#pragma unroll
+    for (int C = 0; C < 4; ++C) t[C] = acc_t{0, 0, 0, 0};
+    tile_mma<T>(t, sA, sB, w, l);                       // Y = Q X0
+    __syncthreads();                                    // X0 in sB read
+    acc_to_B<T>(sB, t, w, l);
+#pragma unroll
+    for (int C = 0; C < 4; ++C)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[C][v] += t[C][v];
     __syncthreads();
-    tile_mma<T>(y, sA, sB, w, l);                       // X = Y + P2 Y
-    store_acc<T>(y, Pout, kTile, 0, 0, w, l);
-    store_acc<T>(y, Wk, kTile, 0, 0, w, l);             // Wk and Pk were read into registers
+    tile_mma<T>(x, sA, sB, w, l);                       // X = X0 + Y + Q Y
+    store_acc<T>(x, Pout, kTile, 0, 0, w, l);
+    store_acc<T>(x, Wk, kTile, 0, 0, w, l);             // Wk and Pk were read into registers
     store_acc<T>(P, Pk, kTile, 0, 0, w, l);
     return true;
 }
