@@ -165,6 +165,26 @@ __device__ __forceinline__ typename V4<T>::type load_frag(const T* __restrict__ 
     }
 }
 
+// The first operand chunk of a product (this wave's first K chunk of tile rows TR,
+// TR + 1 of A and TC, TC + 1 of B), when it was requested ahead (valid).
+template <typename T>
+struct NSFirst {
+    typename V4<T>::type a[2], b[2];
+    bool valid = false;
+};
+
+template <typename T, int NT>
+__device__ __forceinline__ void ns_first(const T* __restrict__ Am, const T* __restrict__ Bm, int TR, int TC, int w,
+                                         int l, NSFirst<T>& f)
+{
+    constexpr int kt = 4 * NT;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        f.a[i] = load_frag<T>(Am, kt, TR + i, w * NT, l);
+        f.b[i] = load_frag<T>(Bm, kt, TC + i, w * NT, l);
+    }
+}
+
 // Products of a Newton-Schulz round on a 32x32 output tile per workgroup.
 // The four waves split K = n_p into quarters (NT = n_p / 64 chunks of 16
 // each), every wave accumulating all four 16x16 output tiles (of one or two
@@ -173,7 +193,7 @@ __device__ __forceinline__ typename V4<T>::type load_frag(const T* __restrict__ 
 // row TC of B are read.
 template <typename T, int NT, int NB>
 __device__ __forceinline__ void ns_core(const T* __restrict__ Am, const T* const (&Bm)[NB], int TR, int TC, int w,
-                                        int l, typename Frag<T>::acc_t (&acc)[NB][2][2])
+                                        int l, typename Frag<T>::acc_t (&acc)[NB][2][2], const NSFirst<T>& first)
 {
     using v4 = typename V4<T>::type;
     using acc_t = typename Frag<T>::acc_t;
@@ -186,11 +206,19 @@ __device__ __forceinline__ void ns_core(const T* __restrict__ Am, const T* const
             for (int j = 0; j < 2; ++j) acc[p][i][j] = acc_t{0, 0, 0, 0};
     const int K0 = w * NT;
     v4 ac[2], bc[NB][2];
+    if (ns_rounds<T>() && NB == 1 && first.valid) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        ac[i] = load_frag<T>(Am, kt, TR + i, K0, l);
+        for (int i = 0; i < 2; ++i) {
+            ac[i] = first.a[i];
+            bc[0][i] = first.b[i];
+        }
+    } else {
 #pragma unroll
-        for (int p = 0; p < NB; ++p) bc[p][i] = load_frag<T>(Bm[p], kt, TC + i, K0, l);
+        for (int i = 0; i < 2; ++i) {
+            ac[i] = load_frag<T>(Am, kt, TR + i, K0, l);
+#pragma unroll
+            for (int p = 0; p < NB; ++p) bc[p][i] = load_frag<T>(Bm[p], kt, TC + i, K0, l);
+        }
     }
 #pragma unroll
     for (int K = 0; K < NT; ++K) {
@@ -268,7 +296,7 @@ __device__ __forceinline__ void ns_tile_max(const NSArgs& a, int chain, int tile
 // Residual launch:  Q = I - X S and the workgroup's max |Q|.
 template <typename T, int NT>
 __device__ __forceinline__ void ns_resid(const NSArgs& a, const NSChain& ch, int xb, int chain, int tile, T* red,
-                                         double* wmax)
+                                         double* wmax, const NSFirst<T>& first)
 {
     using acc_t = typename Frag<T>::acc_t;
     constexpr int kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
@@ -276,7 +304,7 @@ __device__ __forceinline__ void ns_resid(const NSArgs& a, const NSChain& ch, int
     const int TR = 2 * (tile / tdim), TC = 2 * (tile % tdim);
     const T* const Bm[1] = {reinterpret_cast<const T*>(ch.S)};
     acc_t acc[1][2][2];
-    ns_core<T, NT, 1>(reinterpret_cast<const T*>(ch.X[xb]), Bm, TR, TC, w, l, acc);
+    ns_core<T, NT, 1>(reinterpret_cast<const T*>(ch.X[xb]), Bm, TR, TC, w, l, acc, first);
     const acc_t sum = ns_reduce<T>(acc[0], red, w, l);
     const int tr = TR + (w >> 1), tc = TC + (w & 1);
     T* Q = reinterpret_cast<T*>(ch.Q);
@@ -293,7 +321,8 @@ __device__ __forceinline__ void ns_resid(const NSArgs& a, const NSChain& ch, int
 // Middle launch of a round:  Y = Q X into the other iterate buffer.  It leaves the
 // residual launch's max |Q| partials in place for the last launch.
 template <typename T, int NT>
-__device__ __forceinline__ void ns_qx(const NSArgs& a, const NSChain& ch, int xb, int tile, T* red)
+__device__ __forceinline__ void ns_qx(const NSArgs& a, const NSChain& ch, int xb, int tile, T* red,
+                                      const NSFirst<T>& first)
 {
     using acc_t = typename Frag<T>::acc_t;
     constexpr int kt = 4 * NT, tdim = 2 * NT;
@@ -304,7 +333,7 @@ __device__ __forceinline__ void ns_qx(const NSArgs& a, const NSChain& ch, int xb
     // Q X = Q X^T (X is symmetric)
     const T* const Bm[1] = {X};
     acc_t acc[1][2][2];
-    ns_core<T, NT, 1>(reinterpret_cast<const T*>(ch.Q), Bm, TR, TC, w, l, acc);
+    ns_core<T, NT, 1>(reinterpret_cast<const T*>(ch.Q), Bm, TR, TC, w, l, acc, first);
     const acc_t qx = ns_reduce<T>(acc[0], red, w, l);
     T* Y = reinterpret_cast<T*>(ch.X[xb ^ 1]);
 #pragma unroll
@@ -324,7 +353,7 @@ __device__ __forceinline__ void ns_qx(const NSArgs& a, const NSChain& ch, int xb
 template <typename T, int NT>
 __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, const NSChain& ch, const T* Am,
                                           const T* Y, const T* Xadd, T* Xout, int chain, int tile, bool last,
-                                          int next_row, T* red, double* wmax)
+                                          int next_row, T* red, double* wmax, const NSFirst<T>& first)
 {
     using acc_t = typename Frag<T>::acc_t;
     constexpr int n_p = 64 * NT, kt = 4 * NT, tdim = 2 * NT, tiles = tdim * tdim;
@@ -363,7 +392,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
     if (l == 0) wmax[w] = mx;
     const T* const Bm[1] = {Y};
     acc_t acc[1][2][2];
-    ns_core<T, NT, 1>(Am, Bm, TR, TC, w, l, acc);
+    ns_core<T, NT, 1>(Am, Bm, TR, TC, w, l, acc, first);
     const acc_t sum = ns_reduce<T>(acc[0], red, w, l);      // its barrier also publishes wmax
     double nu = wmax[0];
     for (int k = 1; k < 4; ++k) nu = (wmax[k] > nu || wmax[k] != wmax[k]) ? wmax[k] : nu;
@@ -426,7 +455,24 @@ __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int chain, int s
     const NSState* cur = a.state + 3 * (slot & 1);
     NSState* nxt = a.state + 3 * ((slot + 1) & 1);
     const int m = a.m;
+    // float64 rounds keep the iterate in X[0], and a schedule's launches take its
+    // phases in a fixed order (a form, then residual, Q X and update launches in
+    // turn) until it finishes.  So this slot's first operand chunk is requested
+    // before its state has arrived; a state that disagrees (a finished schedule)
+    // leaves it unused.  (The float32 steps' short launches measured slower with it.)
+    NSFirst<T> first;
+    int guess = -1;
+    if constexpr (ns_rounds<T>()) {
+        if (slot > 0) {
+            guess = kNsResid + (slot - 1) % 3;
+            const NSChain& cg = a.ch[chain == 1 ? 1 : 0];
+            const T* Ag = reinterpret_cast<const T*>(guess == kNsResid ? cg.X[0] : cg.Q);
+            const T* Bg = reinterpret_cast<const T*>(guess == kNsResid ? cg.S : cg.X[guess == kNsQx ? 0 : 1]);
+            ns_first<T, NT>(Ag, Bg, 2 * (tile / tdim), 2 * (tile % tdim), threadIdx.x >> 6, threadIdx.x & 63, first);
+        }
+    }
     const NSState s = cur[chain];
+    first.valid = s.phase == guess && s.xb == 0;
     NSState ns = s;
     if (s.phase != kNsFinished) {
         const NSJob job = ns_job(m, chain, s.row);
@@ -436,10 +482,10 @@ __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int chain, int s
             ns_form<T>(a, job, ch, s.xb, (int64_t)tile * 256 + threadIdx.x, (int64_t)tiles * 256);
             ns = NSState{s.row, kNsResid, 0, s.xb, 0};
         } else if (s.phase == kNsResid) {
-            ns_resid<T, NT>(a, ch, s.xb, job.chain, tile, red, wmax);
+            ns_resid<T, NT>(a, ch, s.xb, job.chain, tile, red, wmax, first);
             ns = NSState{s.row, ns_rounds<T>() ? kNsQx : kNsUpdate, s.it, s.xb, 0};
         } else if (s.phase == kNsQx) {
-            ns_qx<T, NT>(a, ch, s.xb, tile, red);
+            ns_qx<T, NT>(a, ch, s.xb, tile, red, first);
             ns = NSState{s.row, kNsUpdate, s.it, s.xb, 0};
         } else {
             // a round: X[xb] <- X + Y + Q Y with Y = Q X in X[xb^1] (in place: each
@@ -453,7 +499,8 @@ __global__ __launch_bounds__(256) void ns_slot_kernel(NSArgs a, int chain, int s
             const bool last = s.it + steps >= maxit;
             const int next_row = ns_fused_next(m, chain, s.row);
             const bool fin = ns_update<T, NT>(a, job, ch, Am, ns_rounds<T>() ? X1 : X0, ns_rounds<T>() ? X0 : nullptr,
-                                              ns_rounds<T>() ? X0 : X1, job.chain, tile, last, next_row, red, wmax);
+                                              ns_rounds<T>() ? X0 : X1, job.chain, tile, last, next_row, red, wmax,
+                                              first);
             if (fin || last) {
                 if (!fin && tile == 0 && threadIdx.x == 0) atomicOr(a.flags + kNsFail, 1);
                 ns = ns_advance(m, chain, s.row, slot, xo);
