@@ -1,7 +1,7 @@
 """Learned current surrogate on 128 x 128 crossbars: data, training, accuracy, speed.
 
     python bench_surrogate.py [--maps 200000] [--held-out-maps 20000] [--vectors 1]
-                              [--epochs 80] [--batch 32] [--lr 1e-3] [--channels 32]
+                              [--epochs 160] [--batch 32] [--lr 1e-3] [--channels 32]
                               [--precision bf16|fp32]
 
 Workload (seeded, synthetic): conductance maps log-uniform on [1e-6, 1e-4] S, the
@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--held-out-maps", type=int, default=20000)
     ap.add_argument("--vectors", type=int, default=1)
     ap.add_argument("--size", type=int, default=128)
-    ap.add_argument("--epochs", type=int, default=80)
+    ap.add_argument("--epochs", type=int, default=160)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--channels", type=int, default=32)
