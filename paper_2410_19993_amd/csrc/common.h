@@ -259,7 +259,7 @@ struct SweepArgs {
     double* Iout;        // [B][n]
     // word-line recovery fused into the float64 back sweep (node_v == nullptr: skipped)
     double* node_v;      // [B][2mn]
-    double* sink;        // [128] scratch target of masked-off node-voltage stores
+    double* sink;        // [128] target of the L2 pulls' keep-alive store (taken only by chance)
     const double* Gc;    // [m][n]
     const double* fr;    // [m][n]
     const double* ip;    // [m][n]

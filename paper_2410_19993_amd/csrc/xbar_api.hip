@@ -30,7 +30,7 @@ struct Buffers {
     double* Iout = nullptr;   // [max_batch][n]
     int* flags = nullptr;     // [kNumFlags]
     unsigned long long* diag = nullptr;   // [kNumDiag]: smallest pivot key, largest backward error bits
-    double* sink = nullptr;   // [128]: target of the sweep's masked-off node-voltage stores
+    double* sink = nullptr;   // [128]: target of the sweep's L2-pull keep-alive store
     // Newton-Schulz factor: per chain S, X[2], Q ([n_p][n_p]) and dprev ([2][n_p])
     void* ns_S[2] = {nullptr, nullptr};
     void* ns_X[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
