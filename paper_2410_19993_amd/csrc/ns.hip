@@ -22,10 +22,10 @@
 //
 // The largest |Q| entry of a round is reduced on the device (per-workgroup
 // partials of the residual launch, combined by every workgroup of the round's
-// last launch).  When it is <= 1.25e-7, ||Q||_inf <= n_p 1.25e-7 and the round
-// leaves ||I - X'' P||_inf <= (n_p 1.25e-7)^3 <= 2.7e-13 for n_p <= 512 (in
-// practice float64 rounding: the warm start begins a chain's rows at about
-// |Q| = 5e-9 to 2.4e-8, so one round ends at rounding level).  The float32 factor
+// last launch).  When it is <= 6.4e-5 / n_p, ||Q||_inf <= 6.4e-5 and the round
+// leaves ||I - X'' P||_inf <= 2.7e-13 (in practice float64 rounding: at 512 x 512
+// the warm start begins a chain's rows at about |Q| = 5e-9 to 2.4e-8, so one round
+// ends at rounding level).  The float32 factor
 // of the refinement mode takes single quadratic steps, stops at 1e-4 and relies on
 // the refinement.  The result is
 // written over E_i.  A row still above the threshold after its last round raises
@@ -58,7 +58,9 @@
 
 namespace xbk {
 
-constexpr double kNsDone = 1.25e-7;    // float64: largest |Q| of a round, see the bound above
+// float64: largest |Q| of a round, so that (n_p |Q|)^3 <= 2.6e-13 (see the bound above)
+template <int NT>
+constexpr double ns_done() { return 6.4e-5 / (64.0 * NT); }
 constexpr double kNsDoneF32 = 1e-4;    // float32: at float rounding after the update
 
 // float64 rows take third-order rounds (three launches); the float32 factor of the
@@ -396,7 +398,7 @@ __device__ __forceinline__ bool ns_update(const NSArgs& a, const NSJob& job, con
     const acc_t sum = ns_reduce<T>(acc[0], red, w, l);      // its barrier also publishes wmax
     double nu = wmax[0];
     for (int k = 1; k < 4; ++k) nu = (wmax[k] > nu || wmax[k] != wmax[k]) ? wmax[k] : nu;
-    const bool fin = nu <= (sizeof(T) == 8 ? kNsDone : kNsDoneF32);   // false for NaN
+    const bool fin = nu <= (sizeof(T) == 8 ? ns_done<NT>() : kNsDoneF32);   // false for NaN
     T* Hr = reinterpret_cast<T*>(a.H) + (int64_t)job.row * n_p * n_p;
     const bool form = (fin || last) && next_row >= 0;
     T* S = reinterpret_cast<T*>(ch.S);
