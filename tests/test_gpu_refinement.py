@@ -36,7 +36,9 @@ def test_c1_fp32_ir():
 @pytest.mark.parametrize("method", ["auto", "gj"])
 @pytest.mark.parametrize("m,n,B,seed", [(1, 1, 1, 1), (3, 70, 17, 5), (65, 64, 33, 6),
                                         (7, 129, 15, 7), (4, 512, 2, 9), (40, 96, 20, 3),
-                                        (9, 300, 20, 17), (6, 420, 18, 18)])
+                                        (9, 300, 20, 17), (6, 420, 18, 18),
+                                        # every block count of the refinement sweep: n_p = 256, 384
+                                        (5, 250, 9, 21), (8, 380, 12, 22)])
 def test_ragged_fp32_ir(m, n, B, seed, method):
     wl = workloads.random_crossbar(m, n, B, seed, r_wl=1.5, r_bl=3.0, r_src=40.0, r_sense=60.0)
     _check(wl, factor_method=method)
