@@ -41,7 +41,7 @@ def test_c1_full(method):
 @pytest.mark.parametrize("m,n,B,seed", [
     (1, 1, 1, 1), (1, 7, 3, 2), (9, 1, 5, 3), (2, 2, 16, 4), (3, 70, 17, 5), (65, 64, 33, 6),
     (7, 129, 15, 7), (10, 200, 20, 8), (4, 512, 2, 9), (33, 40, 48, 10), (9, 300, 20, 17),
-    (6, 420, 18, 18)])
+    (6, 420, 18, 18), (5, 380, 12, 23)])
 def test_ragged_shapes(m, n, B, seed, method):
     """Sizes that are not multiples of the 64-wide blocks or 16-vector slabs, with either
     way of inverting the pivot blocks (Gauss-Jordan, Newton-Schulz)."""
